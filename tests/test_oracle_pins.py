@@ -1,0 +1,319 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Every check compares the oracle with something other than itself: numbers
+the paper prints (tests/golden/), closed forms, invariants, special cases
+that reduce to a library routine, or brute force on tiny inputs.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import Oracle, OracleParams, box_tridiag, line_units, prolong, restrict, setup_maps, visit_order
+from oracle import lfa
+from paper_1807_02137_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def table2():
+    rows = np.loadtxt(os.path.join(GOLDEN, "table2_gsline_rates.txt"), comments="#")
+    return rows[:, 2], rows[:, 3:7]
+
+
+# ---------------------------------------------------------------- LFA (Sec. 3.3, Sec. 4)
+def test_lfa_table2_gsline():
+    """eq. gslinelfa on the frozen coefficients of Table 2 gives the printed rates."""
+    mu, coef = table2()
+    got = np.array([lfa.rate_gsline(c) for c in coef])
+    err = np.abs(got - mu)
+    assert err.max() <= 1e-3
+    assert (err <= 1e-4).sum() >= 8
+
+
+def test_lfa_isotropic_closed_forms():
+    """Constant coefficients: the supremum over the closed high-frequency set is 1/2 for
+    lexicographic GS and 1/sqrt(5) for column-line GS (textbook values)."""
+    assert abs(lfa.rate_gslex((1, 1, 1, 1), n=1024, strict=False) - 0.5) < 1e-6
+    assert abs(lfa.rate_gsline((1, 1, 1, 1), n=1024, strict=False) - 1 / np.sqrt(5)) < 1e-6
+
+
+def test_lfa_decoupled_pair_rate_one():
+    """Lagging a decoupled pair ({A, B} or {C, D}) gives exactly 1 (Sec. 4.1, box cases)."""
+    _, coef = table2()
+    for c in coef:
+        assert abs(lfa.rate_lag(c, "AB") - 1.0) < 1e-12
+        assert abs(lfa.rate_lag(c, "CD") - 1.0) < 1e-12
+
+
+def test_lfa_lag_smallest_is_best():
+    """Lagging only the smallest coefficient beats every other lag set (Fig. 2 claim)."""
+    import itertools
+    _, coef = table2()
+    best = 0
+    for c in coef:
+        sets = ["".join(s) for k in (1, 2, 3) for s in itertools.combinations("ABCD", k)]
+        rates = {s: lfa.rate_lag(c, s) for s in sets}
+        smallest = "ABCD"[int(np.argmin(c))]
+        if rates[smallest] <= min(rates.values()) + 1e-12:
+            best += 1
+        else:
+            assert rates[smallest] <= 1.03 * min(rates.values())
+    assert best >= 8
+
+
+def test_iteration_counts_printed():
+    """Sweeps for a 90 % reduction (Sec. 4.1, Sec. 4.3) and 0.7705^4."""
+    for mu, n in [(0.9997, 7675), (0.7705, 9), (0.9863, 167), (0.7324, 8), (0.4789, 4), (0.9990, 2302)]:
+        assert lfa.iterations_for(mu) == n
+    assert round(0.7705 ** 4, 4) == 0.3524
+
+
+# ---------------------------------------------------------------- transfers (Sec. 3.1)
+def test_full_weighting_stencil():
+    """Restriction of a unit impulse reproduces 1/16 [1 2 1; 2 4 2; 1 2 1] (1-based 2i)."""
+    f = np.zeros((16, 16))
+    f[7, 9] = 1.0       # 0-based fine (7, 9) = 1-based (8, 10) = (2i, 2j) for i=4, j=5
+    c = restrict(f)
+    # coarse (1-based i=4, j=5) = 0-based (3, 4) takes weight 4/16
+    assert abs(c[3, 4] - 4 / 16) < 1e-15
+    f2 = np.zeros((16, 16)); f2[6, 8] = 1.0   # 1-based (7, 9) = (2i-1, 2j-1)
+    assert abs(restrict(f2)[3, 4] - 1 / 16) < 1e-15
+    f3 = np.zeros((16, 16)); f3[7, 8] = 1.0   # (2i, 2j-1)
+    assert abs(restrict(f3)[3, 4] - 2 / 16) < 1e-15
+
+
+def test_restriction_boundary_rule():
+    """Last coarse index: 1/2 [fine n-1 + fine n] in each direction (Sec. 3.1)."""
+    rng = np.random.default_rng(1)
+    f = rng.normal(size=(8, 8))
+    c = restrict(f)
+    # 0-based coarse (3, 3): rows 6, 7 and columns 6, 7 with weights 1/2 x 1/2
+    assert abs(c[3, 3] - 0.25 * (f[6, 6] + f[6, 7] + f[7, 6] + f[7, 7])) < 1e-14
+    # interior row, last column: rows 2I..2I+2 (1/4,1/2,1/4) x columns 6, 7 (1/2, 1/2)
+    I = 1
+    want = sum(wr * 0.5 * (f[2 * I + a, 6] + f[2 * I + a, 7]) for a, wr in enumerate((0.25, 0.5, 0.25)))
+    assert abs(c[I, 3] - want) < 1e-14
+
+
+def test_transfers_constants_and_linear():
+    c = np.full((8, 6), 3.25)
+    assert np.allclose(restrict(np.full((16, 12), 3.25)), 3.25, atol=1e-15)
+    assert np.allclose(prolong(c), 3.25, atol=1e-15)
+    # bilinear interpolation reproduces data linear in the fine index away from fine index 0
+    I, J = np.meshgrid(np.arange(8), np.arange(6), indexing="ij")
+    lin = 0.7 * I - 1.3 * J + 2.0
+    f = prolong(lin)
+    fi, fj = np.meshgrid(np.arange(16), np.arange(12), indexing="ij")
+    want = 0.7 * (fi - 1) / 2 - 1.3 * (fj - 1) / 2 + 2.0
+    assert np.allclose(f[1:, 1:], want[1:, 1:], atol=1e-13)
+    # injection at odd fine indices (1-based even)
+    assert np.allclose(f[1::2, 1::2], lin, atol=1e-15)
+
+
+# ---------------------------------------------------------------- setup maps (Sec. 2.2, Sec. 5)
+def test_setup_closed_forms():
+    n = m = 32
+    img = np.zeros((n, m), np.float32)
+    mk = np.array([[8.5, 8.5], [8.5, 20.5], [20.5, 20.5], [20.5, 8.5]])
+    p = OracleParams(levels=1)
+    out = setup_maps(img, mk, p)
+    h0 = 1.0 / 32
+    assert np.allclose(out["g"], 1.0)                       # flat image: no edges
+    assert abs(out["A1"] - 12.0 * 12.0 * h0 * h0) < 1e-15   # square polygon area
+    # d vanishes at a marker cell centre and is below 1 near markers
+    assert out["d"][8, 8] == 0.0 and out["d"].max() <= 1.0
+    # signed distance to the square boundary: inside centre cell (14, 14) is 6 px from every edge
+    assert abs(out["phi0"][14, 14] - min(6.0, p.M)) < 1e-12
+    assert abs(out["phi0"][8, 14] - 0.0) < 1e-12            # on the top edge
+    assert abs(out["phi0"][6, 14] - (-2.0)) < 1e-12         # 2 px outside
+
+
+def test_edge_detector_closed_form():
+    """A linear ramp z = a * (j + 1/2) has |grad(G*z)| = a / h0 away from the borders."""
+    n = m = 32
+    a = 0.01
+    img = np.tile(a * (np.arange(m) + 0.5), (n, 1)).astype(np.float64)
+    out = setup_maps(img, np.array([[10.5, 10.5], [10.5, 20.5], [20.5, 15.5]]), OracleParams(levels=1))
+    grad = a * 32
+    assert abs(out["g"][16, 16] - 1.0 / (1.0 + grad ** 2)) < 1e-12
+
+
+# ---------------------------------------------------------------- operator (eq. abcdrc, eq. abcd)
+def _tiny(seed=5, n=16, m=16, **kw):
+    inst = synth.tiny_instance(seed, n, m)
+    return inst, Oracle(inst.image, inst.markers, OracleParams(levels=1, **kw))
+
+
+def test_conservation_identity():
+    """sum_ij N(phi)_ij / delta(phi_ij) = -sum_ij fit_ij for any phi (flux form, Neumann)."""
+    inst, o = _tiny()
+    rng = np.random.default_rng(3)
+    for _ in range(3):
+        phi = rng.uniform(-4, 4, (16, 16))
+        o.set("phi", phi)
+        N = o.operator(0)
+        delta = 1.0 / (np.pi * (1.0 + phi ** 2))
+        lhs = (N / delta).sum()
+        rhs = -o.get("fit").sum()
+        assert abs(lhs - rhs) <= 1e-9 * max(1.0, abs(rhs))
+
+
+def test_operator_constant_phi():
+    """N(c) = -f: the curvature part vanishes on a constant level set."""
+    inst, o = _tiny()
+    o.set("phi", np.full((16, 16), 1.5))
+    N = o.operator(0)
+    delta = 1.0 / (np.pi * (1.0 + 1.5 ** 2))
+    assert np.allclose(N, -delta * o.get("fit"), rtol=0, atol=1e-13)
+
+
+def test_operator_circle_curvature():
+    """On the distance function of a circle, N/delta + fit = mu * w * (curvature 1/R)."""
+    n = 128
+    img = np.zeros((n, n), np.float32)
+    o = Oracle(img, np.array([[60.5, 60.5], [60.5, 70.5], [70.5, 65.5]]),
+               OracleParams(levels=1, eps_tv_px=1e-6, M=1e9))
+    i, j = np.meshgrid(np.arange(n) + 0.5, np.arange(n) + 0.5, indexing="ij")
+    R = 30.0
+    phi = R - np.sqrt((i - 64.0) ** 2 + (j - 64.0) ** 2)
+    o.set("phi", phi)
+    o.set("w", np.ones((n, n)))
+    N = o.operator(0)
+    delta = 1.0 / (np.pi * (1.0 + phi ** 2))
+    curv = N / delta + o.get("fit")
+    h0 = 1.0 / n
+    # on the circle r = R the level lines have curvature 1 / (R h0) in domain units
+    ring = np.abs(np.sqrt((i - 64.0) ** 2 + (j - 64.0) ** 2) - R) < 0.5
+    want = -0.5 / (R * h0)          # div(grad phi/|grad phi|) < 0 for a phi decreasing outward
+    assert abs(np.median(curv[ring]) - want) < 0.05 * abs(want)
+
+
+def test_face_symmetry():
+    """A face coefficient over delta is shared by the two cells: A_ij/delta_ij = B_i+1,j/delta_i+1,j."""
+    inst, o = _tiny()
+    rng = np.random.default_rng(4)
+    phi = rng.uniform(-4, 4, (16, 16))
+    o.set("phi", phi)
+    o.freeze(0)
+    d = 1.0 / (np.pi * (1.0 + phi ** 2))
+    A, B, C, D = (o.get(k) / d for k in "ABCD")
+    assert np.allclose(A[:-1, :], B[1:, :], rtol=1e-14, atol=0)
+    assert np.allclose(C[:, :-1], D[:, 1:], rtol=1e-14, atol=0)
+    assert np.all(A[-1, :] == 0) and np.all(B[0, :] == 0) and np.all(C[:, -1] == 0) and np.all(D[:, 0] == 0)
+
+
+# ---------------------------------------------------------------- runs (Sec. 4.3, Fig. 3, Fig. 4)
+def test_box_tridiag_unconstrained_matches_linalg():
+    rng = np.random.default_rng(6)
+    for L in (1, 2, 5, 17):
+        lo, up = rng.uniform(0, 1, L), rng.uniform(0, 1, L)
+        lo[0] = 0; up[-1] = 0
+        di = -(lo + up + rng.uniform(0.1, 1, L))
+        rh = rng.normal(size=L)
+        T = np.diag(di) + np.diag(lo[1:], -1) + np.diag(up[:-1], 1)
+        x = box_tridiag(lo, di, up, rh, np.full(L, -1e9), np.full(L, 1e9))
+        assert np.allclose(x, np.linalg.solve(T, rh), rtol=1e-12, atol=1e-12)
+
+
+def test_box_tridiag_matches_projected_gauss_seidel():
+    """With active bounds the run solve is the projected fixed point (brute force PGS)."""
+    rng = np.random.default_rng(7)
+    for trial in range(20):
+        L = int(rng.integers(2, 12))
+        lo, up = rng.uniform(0, 1, L), rng.uniform(0, 1, L)
+        lo[0] = 0; up[-1] = 0
+        di = -(lo + up + rng.uniform(0.05, 0.5, L))
+        rh = rng.normal(scale=2.0, size=L)
+        bl, bh = np.full(L, -1.0), np.full(L, 1.0)
+        x = box_tridiag(lo, di, up, rh, bl, bh)
+        y = np.zeros(L)
+        for _ in range(20000):
+            for k in range(L):
+                s = rh[k] - (lo[k] * y[k - 1] if k > 0 else 0) - (up[k] * y[k + 1] if k < L - 1 else 0)
+                y[k] = min(max(s / di[k], bl[k]), bh[k])
+        assert np.allclose(x, y, atol=1e-10), trial
+
+
+def test_fig3_units():
+    """Fig. 3: stars at row 2, cols 2-4 and row 4, col 3 (1-based): row 2 has one run of
+    three pixels, the single star of row 4 is grouped with its right neighbour."""
+    lab = np.zeros((5, 5), np.uint8)
+    lab[1, 1:4] = 1
+    lab[3, 2] = 1
+    u1 = line_units(lab[1], 0)
+    assert list(u1) == [0, 1, 1, 1, 4]
+    u3 = line_units(lab[3], 0)
+    assert list(u3) == [0, 1, 2, 2, 4]
+    # a single star at the end of a line has no next pixel and stays alone
+    end = np.array([0, 0, 0, 0, 1], np.uint8)
+    assert list(line_units(end, 0)) == [0, 1, 2, 3, 4]
+
+
+def test_fig4_visit_orders():
+    """Fig. 4: the labels of the four sweeps on a 5 x 5 grid (x = column, y = row from the bottom)."""
+    n = 5
+    want = {0: lambda x, y: x + (5 - y) * 5, 1: lambda x, y: 6 - x + (y - 1) * 5,
+            2: lambda x, y: 6 - y + (x - 1) * 5, 3: lambda x, y: y + (6 - x - 1) * 5}
+    for s in range(4):
+        order = visit_order(s, n, n, 0)
+        rank = np.empty(n * n, int)
+        rank[order] = np.arange(1, n * n + 1)
+        for i in range(n):
+            for j in range(n):
+                x, y = j + 1, n - i
+                assert rank[i * n + j] == want[s](x, y), (s, i, j)
+
+
+def test_four_class_order_is_a_permutation():
+    for s in range(4):
+        o = visit_order(s, 12, 8, 1)
+        assert sorted(o) == list(range(96))
+
+
+# ---------------------------------------------------------------- smoother and FAS
+def test_smoother_fixed_point_is_projected_solution():
+    """Iterating Hybrid Smoother 2 alone drives the projected residual to rounding level:
+    its fixed points solve the box-constrained problem (runs included)."""
+    inst, o = _tiny(seed=11, n=24, m=24)
+    r0 = o.res_norm()
+    for _ in range(60):
+        o.smooth(5, 0)
+    # frozen c1, c2: the smoother alone never refreshes them
+    assert o.res_norm() <= 1e-10 * r0
+
+
+def test_fas_converges_and_residual_decreases():
+    for seed in (1000, 1001, 1002, 1003):
+        inst = synth.config1(seed)
+        o = Oracle(inst.image, inst.markers, OracleParams(levels=6))
+        k, hist = o.solve(1e-6, 40)
+        assert k > 0, seed
+        assert np.all(np.diff(hist) <= 0), (seed, hist)
+
+
+def test_fas_fixed_point_agrees_with_time_marching():
+    """The multigrid fixed point is a fixed point of projected time-marching of the same system."""
+    inst = synth.tiny_instance(21, 16, 16)
+    o = Oracle(inst.image, inst.markers, OracleParams(levels=3))
+    k, hist = o.solve(1e-12, 60)
+    assert k > 0
+    phi_mg = o.get("phi")
+    rel = o.timemarch(2000, cfl=0.2, crefresh=50, tol=0.0)
+    assert rel <= 1e-10
+    assert np.abs(o.get("phi") - phi_mg).max() <= 1e-8
+
+
+def test_selectivity_gate_config1():
+    """Calibration gate of the selection weight: the segmentation of config-1 inputs picks
+    the marked object (IoU >= 0.9 on at least 90 % of seeds)."""
+    good = 0
+    seeds = list(range(1000, 1010))
+    for seed in seeds:
+        inst = synth.config1(seed)
+        o = Oracle(inst.image, inst.markers, OracleParams(levels=6))
+        o.solve(1e-6, 40)
+        mask = o.get("phi") > 0
+        iou = (mask & inst.target).sum() / max((mask | inst.target).sum(), 1)
+        good += iou >= 0.9
+    assert good >= 9
