@@ -1,0 +1,163 @@
+/*
+ * mgseg.h -- C ABI of libmgseg: FAS multigrid with the jump-aware Hybrid
+ * Smoother 2 for the selective level-set segmentation models of
+ * Roberts, Chen & Irion, "A Multigrid Algorithm with Non-Standard Smoother
+ * for Two Selective Models in Variational Segmentation" (arXiv 1807.02137).
+ *
+ * Problem (Sec. 2.2): given an image z on the grid and a marker set S of
+ * points on or near the object of interest, find the level-set function phi
+ * whose positive set is the selected object, by solving the discrete
+ * Euler-Lagrange equations of the Spencer-Chen model (eq. scel) or the
+ * Rada-Chen model (eq. rcel, discretised in eq. rcabcd / abcdrc) with the FAS
+ * V-cycle of the Algorithm-1 box driven by Hybrid Smoother 2 (Sec. 4.3;
+ * "Algorithm 3" of Sec. 4).
+ *
+ * Conventions for every entry point:
+ *  - All arrays are row-major, element (i, j) at ptr[i * pitch + j], with
+ *    i the row (0..n-1) and j the column (0..m-1); pitches are in elements.
+ *  - "_dev" pointers are device (HBM) pointers of the current HIP device;
+ *    "_host" pointers are host memory.  The caller owns every pointer it
+ *    passes in; the library copies what it needs before returning.
+ *  - All work is enqueued on the stream given at setup.  Calls that return
+ *    host values (vcycle, solve, get_stats, the debug getters) synchronise
+ *    that stream before returning.
+ *  - No entry point aborts or throws: each returns an mgseg_status.  On an
+ *    argument error the context is left unchanged.
+ *  - One host thread may use a context at a time; distinct contexts may be
+ *    used concurrently on distinct streams.
+ */
+#ifndef MGSEG_H
+#define MGSEG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mgseg_ctx mgseg_ctx;
+
+typedef enum {
+    MGSEG_OK = 0,
+    MGSEG_E_ARG = 1,            /* invalid argument (null pointer, bad value)        */
+    MGSEG_E_SHAPE = 2,          /* n, m not divisible by 2^(levels-1), or too small  */
+    MGSEG_E_NOMEM = 3,          /* device allocation failed                          */
+    MGSEG_E_HIP = 4,            /* a HIP runtime call failed                         */
+    MGSEG_E_NONFINITE = 5,      /* a residual norm became NaN/Inf                    */
+    MGSEG_E_NOT_CONVERGED = 6,  /* solve hit max_cycles; outputs are still valid     */
+    MGSEG_E_STATE = 7           /* call not valid in the context's current state     */
+} mgseg_status;
+
+typedef enum { MGSEG_SPENCER_CHEN = 0, MGSEG_RADA_CHEN = 1 } mgseg_model;
+
+/* Model and solver parameters.  Defaults (mgseg_params_default) follow the
+ * paper where it fixes a value (Sec. 5: mu = 1/2, nu = 1, eps = 1, V-cycle)
+ * and the project's stated readings elsewhere. */
+typedef struct {
+    uint32_t struct_size;   /* must be sizeof(mgseg_params)                          */
+    int32_t model;          /* mgseg_model                                           */
+    double mu;              /* curvature weight (eq. scfunc / rcfunc)                */
+    double lambda1, lambda2;/* fitting weights, for intensities in [0, 1]            */
+    double theta;           /* Spencer-Chen selection weight (eq. scfunc)            */
+    double nu;              /* Rada-Chen area weight (eq. rcfunc)                    */
+    double eps;             /* smoothed Heaviside width, in phi units (Sec. 2)       */
+    double eps_tv_px;       /* |grad phi| regularisation, phi units per pixel        */
+    double beta;            /* edge detector g(s) = 1/(1 + beta s) (Sec. 2.2)        */
+    double sigma_g;         /* pre-blur of z for the edge detector, pixels           */
+    double sigma_d;         /* width of the marker distance function, domain units   */
+    double Sigma;           /* jump threshold on the coefficient ratio (Sec. 5.2)    */
+    double M;               /* bound |phi| <= M                                      */
+    int32_t nu1, nu2;       /* pre/post smoothing: Hybrid-2 outer iterations         */
+    int32_t levels;         /* grids including the finest; 0 = as many as fit        */
+    int32_t coarse_iters;   /* outer iterations on the coarsest grid                 */
+    int32_t mixed_precision;/* 1: FP32 cycles + FP64 finest defect correction        */
+    int32_t scaled;         /* 1: each equation row divided by delta_eps(psi_ij)     */
+} mgseg_params;
+
+typedef struct {
+    double c1, c2;          /* region means (eq. c1c2)                               */
+    double rel_res;         /* |r~_k| / |r~_0| on the finest grid                    */
+    double res;             /* |r~_k| (FP64, projected residual)                     */
+    double res0;            /* |r~_0|                                                */
+    double eta;             /* paper's relative change |phi_k - phi_k-1|/|phi_k-1|   */
+    int32_t cycles;         /* V-cycles done since setup / last set_phi0             */
+    int32_t levels;
+    double frac_fg;         /* fraction of pixels with phi > 0                       */
+} mgseg_stats;
+
+/* Fills *p with the defaults. */
+void mgseg_params_default(mgseg_params *p);
+
+/* Human-readable text for a status code (static storage). */
+const char *mgseg_strerror(mgseg_status s);
+
+/*
+ * Sets up one image (Sec. 2.2, Sec. 5): edge detector g from the
+ * pre-blurred image, marker distance function d, the curvature weight w
+ * (g for Spencer-Chen, d g for Rada-Chen), the initial level set (signed
+ * distance to the boundary of the marker polygon, Sec. 5), the polygon area
+ * A1, the coarse-grid static maps (full-weighting restriction, Sec. 3.1),
+ * the initial c1, c2 (eq. c1c2) and the initial residual norm.
+ *   image_dev        : n x m float, values in [0, 1], row pitch `pitch`.
+ *   markers_host     : k (row, col) pairs of floats in pixel coordinates;
+ *                      the centre of cell (i, j) is (i + 0.5, j + 0.5).
+ *   stream           : a hipStream_t (0 = default stream), passed as void*.
+ * Errors: MGSEG_E_ARG (null pointers, k < 1, pitch < m, bad struct_size),
+ * MGSEG_E_SHAPE (n or m not divisible by 2^(levels-1)), MGSEG_E_NOMEM.
+ */
+mgseg_status mgseg_setup(const float *image_dev, int n, int m, int pitch,
+                         const float *markers_host, int k, const mgseg_params *p,
+                         void *stream, mgseg_ctx **out);
+
+/* Replaces the finest phi (warm start), clamped to [-M, M]; recomputes c1,
+ * c2 and the reference residual norm; resets the cycle counter. */
+mgseg_status mgseg_set_phi0(mgseg_ctx *c, const float *phi_dev, int pitch);
+
+/* One FAS V-cycle (Algorithm-1 box, gamma = 1) followed by the c1, c2
+ * refresh (Sec. 5); returns |r~|/|r~_0| after the refresh. */
+mgseg_status mgseg_vcycle(mgseg_ctx *c, double *rel_res_out);
+
+/* V-cycles until |r~|/|r~_0| <= tol or max_cycles (then
+ * MGSEG_E_NOT_CONVERGED with valid outputs). */
+mgseg_status mgseg_solve(mgseg_ctx *c, double tol, int max_cycles, int *cycles_out,
+                         double *rel_res_out);
+
+/* Finest phi in FP64 (n x m, pitch in elements). */
+mgseg_status mgseg_get_phi(mgseg_ctx *c, double *phi_dev, int pitch);
+
+/* Segmentation mask: 1 where phi > 0, else 0 (Sec. 2.1). */
+mgseg_status mgseg_get_mask(mgseg_ctx *c, uint8_t *mask_dev, int pitch);
+
+mgseg_status mgseg_get_stats(mgseg_ctx *c, mgseg_stats *s);
+
+/* Releases every device buffer of the context (NULL is a no-op). */
+void mgseg_destroy(mgseg_ctx *c);
+
+/* ------------------------------------------------------------------------
+ * Single steps, for tests and profiling.  They operate on one level of an
+ * existing context; host buffers are n_l x m_l, dense (pitch m_l).
+ * Fields: 0 z, 1 d, 2 w, 3 fit, 4 phi, 5 F, 6 lo, 7 hi, 8 g (level 0 only),
+ *         9 phi64 (level 0, double), 10 labels (uint8, bit s = starred in
+ *         sweep s of the current freeze).
+ * ---------------------------------------------------------------------- */
+mgseg_status mgseg_level_shape(mgseg_ctx *c, int level, int *n, int *m, double *h);
+mgseg_status mgseg_debug_get(mgseg_ctx *c, int level, int field, void *host);
+mgseg_status mgseg_debug_set(mgseg_ctx *c, int level, int field, const void *host);
+/* scalars: out[0] c1, out[1] c2, out[2] A1, out[3] res0, out[4] h0 */
+mgseg_status mgseg_debug_scalars(mgseg_ctx *c, double *out5);
+mgseg_status mgseg_debug_set_c(mgseg_ctx *c, double c1, double c2);
+/* op: 0 freeze (coefficients, labels and psi at the current phi),
+ *     1..4 one sweep A..D of Hybrid Smoother 2 with the current freeze,
+ *     5 `arg` outer iterations (freeze + 4 sweeps),
+ *     6 the coarsest-grid solve on this level,
+ *     7 the V-cycle from this level down (F of this level as set),
+ *     8 residual r = F - N(phi), projected (result in field F of the next
+ *       debug_get with field 11 = residual),
+ *     9 c1, c2 refresh from the finest phi and fit maps of every level. */
+mgseg_status mgseg_debug_op(mgseg_ctx *c, int level, int op, int arg);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MGSEG_H */

@@ -1,0 +1,744 @@
+// mgseg.hip -- libmgseg host driver and C ABI (see include/mgseg.h).
+#include <hip/hip_runtime.h>
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/mgseg.h"
+#include "mgseg_kernels.h"
+
+#define MAXLEV 16
+
+namespace {
+
+// device scalar slots (doubles)
+enum {
+    DS_C1 = 0, DS_C2 = 1,
+    DS_AREA_FRZ = 2,          // area term of the current freeze
+    DS_AREA_EVAL = 3,         // area term for operator evaluations
+    DS_AREA64 = 4,            // area term at the FP64 finest phi
+    DS_RES = 5,               // last residual norm
+    DS_COUNT = 8
+};
+
+struct Level {
+    int n = 0, m = 0, prm = 0, pcm = 0;
+    double h = 0.0;
+    float *z = nullptr, *d = nullptr, *w = nullptr, *fit = nullptr, *F = nullptr;
+    float *P[3] = {nullptr, nullptr, nullptr};
+    float *psi = nullptr, *phic = nullptr, *r = nullptr, *lo = nullptr, *hi = nullptr;
+    float *w_cm = nullptr, *fit_cm = nullptr, *F_cm = nullptr, *lo_cm = nullptr, *hi_cm = nullptr;
+    float *T[3] = {nullptr, nullptr, nullptr};
+    float *psi_cm = nullptr;
+    uint8_t *lab = nullptr, *lab_cm = nullptr;
+    bool has_F = false;
+};
+
+}  // namespace
+
+struct mgseg_ctx {
+    mgseg_params p;
+    hipStream_t s = nullptr;
+    int L = 0, n = 0, m = 0;
+    double h0 = 0.0, A1 = 0.0, res0 = 0.0, res = 0.0, eta = 0.0, rel = 0.0;
+    int cycles = 0;
+    Level lev[MAXLEV];
+    double *phi64 = nullptr, *w64 = nullptr, *d64 = nullptr, *g64 = nullptr, *prev64 = nullptr;
+    double *dsc = nullptr;          // device scalars
+    double *part = nullptr;         // reduction partials
+    int part_n = 0;
+    float *scr = nullptr;           // run scratch
+    long long scr_field = 0;
+    double *hull_d = nullptr, *mk_d = nullptr;
+    int hv = 0, k = 0;
+    std::vector<void *> allocs;
+    hipError_t err = hipSuccess;
+    bool oom = false;
+};
+
+namespace {
+
+const int RED_BLOCKS = 1024;
+
+template <typename T>
+T *dalloc(mgseg_ctx *c, size_t count)
+{
+    void *p = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc(&p, count * sizeof(T));
+    if (e != hipSuccess) { c->oom = true; (void)hipGetLastError(); return nullptr; }
+    c->allocs.push_back(p);
+    (void)hipMemsetAsync(p, 0, count * sizeof(T), c->s);
+    return (T *)p;
+}
+
+inline int pad64(int x) { return (x + 63) / 64 * 64; }
+
+inline void chk(mgseg_ctx *c)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess && c->err == hipSuccess) c->err = e;
+}
+
+inline dim3 grid2(int n, int m, int bx = 256) { return dim3((m + bx - 1) / bx, n); }
+
+// ---- host convex hull (Andrew's monotone chain), CCW, no collinear points
+int host_hull(const std::vector<double> &pts, std::vector<double> &hull)
+{
+    std::vector<std::pair<double, double>> P;
+    for (size_t t = 0; t + 1 < pts.size(); t += 2) P.push_back({pts[t], pts[t + 1]});
+    std::sort(P.begin(), P.end());
+    P.erase(std::unique(P.begin(), P.end()), P.end());
+    hull.clear();
+    if (P.size() <= 2) {
+        for (auto &q : P) { hull.push_back(q.first); hull.push_back(q.second); }
+        return (int)P.size();
+    }
+    auto cr = [](const std::pair<double, double> &o, const std::pair<double, double> &a,
+                 const std::pair<double, double> &b) {
+        return (a.first - o.first) * (b.second - o.second) - (a.second - o.second) * (b.first - o.first);
+    };
+    std::vector<std::pair<double, double>> H(2 * P.size());
+    size_t k = 0;
+    for (size_t i = 0; i < P.size(); i++) {
+        while (k >= 2 && cr(H[k - 2], H[k - 1], P[i]) <= 0) k--;
+        H[k++] = P[i];
+    }
+    for (size_t i = P.size() - 1, t = k + 1; i-- > 0;) {
+        while (k >= t && cr(H[k - 2], H[k - 1], P[i]) <= 0) k--;
+        H[k++] = P[i];
+    }
+    H.resize(k - 1);
+    for (auto &q : H) { hull.push_back(q.first); hull.push_back(q.second); }
+    return (int)H.size();
+}
+
+double host_area(const std::vector<double> &h, int hv)
+{
+    if (hv < 3) return 0.0;
+    double s = 0.0;
+    for (int t = 0; t < hv; t++) {
+        int u = (t + 1) % hv;
+        s += h[2 * t] * h[2 * u + 1] - h[2 * u] * h[2 * t + 1];
+    }
+    return 0.5 * std::fabs(s);
+}
+
+float lev_e2(const mgseg_ctx *c, int l)
+{
+    double e = c->p.eps_tv_px * (double)(1 << l);
+    return (float)(e * e);
+}
+
+// --------------------------------------------------------------------------
+void transpose_f(mgseg_ctx *c, const float *in, int pin, float *out, int pout, int n, int m)
+{
+    dim3 g((m + TILE - 1) / TILE, (n + TILE - 1) / TILE), b(TILE, 8);
+    hipLaunchKernelGGL(k_transpose<float>, g, b, 0, c->s, in, pin, out, pout, n, m);
+}
+void transpose_u8(mgseg_ctx *c, const uint8_t *in, int pin, uint8_t *out, int pout, int n, int m)
+{
+    dim3 g((m + TILE - 1) / TILE, (n + TILE - 1) / TILE), b(TILE, 8);
+    hipLaunchKernelGGL(k_transpose<uint8_t>, g, b, 0, c->s, in, pin, out, pout, n, m);
+}
+
+// area term 2 nu (h^2 sum H(phi) - A1) of level l at phi (row-major) -> slot
+void area_term(mgseg_ctx *c, int l, const float *phi, int pp, int slot)
+{
+    Level &L = c->lev[l];
+    int nb = std::min(RED_BLOCKS, std::max(1, (L.n * L.m + 255) / 256));
+    hipLaunchKernelGGL(k_sums<float>, dim3(nb), dim3(256), 0, c->s, phi, pp, (const float *)nullptr, 0, L.n, L.m,
+                       c->p.eps, c->part);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, c->s, c->part, nb, 0, (double)L.n * L.m, L.h * L.h, c->A1,
+                       c->p.nu, c->dsc + slot);
+}
+
+void update_fit(mgseg_ctx *c)
+{
+    for (int l = 0; l < c->L; l++) {
+        Level &L = c->lev[l];
+        hipLaunchKernelGGL(k_fit, grid2(L.n, L.m), dim3(256), 0, c->s, L.z, L.d, L.prm, L.n, L.m, c->dsc + DS_C1,
+                           (float)c->p.lambda1, (float)c->p.lambda2, (float)c->p.theta, c->p.model, L.fit);
+        transpose_f(c, L.fit, L.prm, L.fit_cm, L.pcm, L.n, L.m);
+    }
+}
+
+// c1, c2 (eq. c1c2) from the FP64 finest phi
+void update_c(mgseg_ctx *c)
+{
+    Level &L = c->lev[0];
+    int nb = std::min(RED_BLOCKS, std::max(1, (c->n * c->m + 255) / 256));
+    hipLaunchKernelGGL(k_sums<double>, dim3(nb), dim3(256), 0, c->s, c->phi64, c->m, L.z, L.prm, c->n, c->m,
+                       c->p.eps, c->part);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, c->s, c->part, nb, 1, (double)c->n * c->m, 0.0, 0.0, 0.0,
+                       c->dsc + DS_C1);
+    update_fit(c);
+}
+
+// FP64 finest residual: norm into DS_RES; phi32 <- fl32(phi64); F~ if mixed
+void res64(mgseg_ctx *c, bool write_Ft)
+{
+    Level &L = c->lev[0];
+    if (c->p.model == 1) {
+        int nb = std::min(RED_BLOCKS, std::max(1, (c->n * c->m + 255) / 256));
+        hipLaunchKernelGGL(k_sums<double>, dim3(nb), dim3(256), 0, c->s, c->phi64, c->m, (const float *)nullptr, 0,
+                           c->n, c->m, c->p.eps, c->part);
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, c->s, c->part, nb, 0, (double)c->n * c->m,
+                           L.h * L.h, c->A1, c->p.nu, c->dsc + DS_AREA64);
+    }
+    Res64Args A;
+    A.phi64 = c->phi64; A.w64 = c->w64; A.d64 = c->d64;
+    A.z32 = L.z; A.w32 = L.w; A.fit32 = L.fit; A.p32 = L.prm;
+    A.c12 = c->dsc + DS_C1; A.area = c->p.model == 1 ? c->dsc + DS_AREA64 : nullptr;
+    A.kap = c->p.mu / L.h; A.e2 = lev_e2(c, 0); A.eps = c->p.eps;
+    A.l1 = c->p.lambda1; A.l2 = c->p.lambda2; A.theta = c->p.theta; A.M = c->p.M;
+    A.model = c->p.model; A.scaled = c->p.scaled; A.n = c->n; A.m = c->m;
+    A.phi32 = L.P[0]; A.Ft = write_Ft ? L.F : nullptr;
+    A.partial = c->part;
+    dim3 g = grid2(c->n, c->m);
+    hipLaunchKernelGGL(k_res64, g, dim3(256), 0, c->s, A);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, c->s, c->part, (int)(g.x * g.y), 2, 0.0, 0.0, 0.0, 0.0,
+                       c->dsc + DS_RES);
+    if (write_Ft) {
+        transpose_f(c, L.F, L.prm, L.F_cm, L.pcm, L.n, L.m);
+        L.has_F = true;
+    }
+}
+
+// --------------------------------------------------------------------------
+// one directional sweep on level l: s = 0 (A), 1 (B) row-major, 2 (C), 3 (D)
+// column-major; phi_old -> phi_new in the layout of the sweep
+void launch_sweep(mgseg_ctx *c, int l, int s, const float *phi_old, float *phi_new)
+{
+    Level &L = c->lev[l];
+    bool cm = s >= 2;
+    LineArgs A;
+    A.phi_old = phi_old; A.phi_new = phi_new;
+    A.psi = cm ? L.psi_cm : L.psi;
+    A.w = cm ? L.w_cm : L.w;
+    A.fit = cm ? L.fit_cm : L.fit;
+    A.F = L.has_F ? (cm ? L.F_cm : L.F) : nullptr;
+    A.lab = cm ? L.lab_cm : L.lab;
+    A.lo = l > 0 ? (cm ? L.lo_cm : L.lo) : nullptr;
+    A.hi = l > 0 ? (cm ? L.hi_cm : L.hi) : nullptr;
+    A.scr = c->scr; A.scr_field = c->scr_field;
+    A.area = c->p.model == 1 ? c->dsc + DS_AREA_FRZ : nullptr;
+    A.pitch = cm ? L.pcm : L.prm;
+    A.lpitch = A.pitch;
+    A.nl = cm ? L.m : L.n;
+    A.ml = cm ? L.n : L.m;
+    A.kap = (float)(c->p.mu / L.h); A.e2 = lev_e2(c, l); A.M = (float)c->p.M; A.eps = (float)c->p.eps;
+    A.bit = s; A.scaled = c->p.scaled;
+    bool rev = (s == 1 || s == 3);
+    int bands = (A.nl + 3) / 4;
+    int ml = A.ml;
+    if (ml > 8192) {   // one workgroup holds a whole line: 1024 threads x 8 cells
+        if (c->err == hipSuccess) c->err = hipErrorInvalidValue;
+        return;
+    }
+#define MG_SWEEP(NT, K)                                                                                  \
+    do {                                                                                                 \
+        if (rev) hipLaunchKernelGGL((k_sweep<NT, K, true>), dim3(bands), dim3(NT), 0, c->s, A);       \
+        else hipLaunchKernelGGL((k_sweep<NT, K, false>), dim3(bands), dim3(NT), 0, c->s, A);          \
+    } while (0)
+    if (ml <= 64) MG_SWEEP(64, 1);
+    else if (ml <= 128) MG_SWEEP(64, 2);
+    else if (ml <= 256) MG_SWEEP(64, 4);
+    else if (ml <= 512) MG_SWEEP(64, 8);
+    else if (ml <= 1024) MG_SWEEP(128, 8);
+    else if (ml <= 2048) MG_SWEEP(256, 8);
+    else if (ml <= 4096) MG_SWEEP(512, 8);
+    else MG_SWEEP(1024, 8);
+#undef MG_SWEEP
+    chk(c);
+}
+
+// freeze at the current phi (in P[0]): psi copies, labels, area term
+void freeze(mgseg_ctx *c, int l)
+{
+    Level &L = c->lev[l];
+    (void)hipMemcpyAsync(L.psi, L.P[0], sizeof(float) * (size_t)L.n * L.prm, hipMemcpyDeviceToDevice, c->s);
+    transpose_f(c, L.psi, L.prm, L.psi_cm, L.pcm, L.n, L.m);
+    hipLaunchKernelGGL(k_labels, grid2(L.n, L.m), dim3(256), 0, c->s, L.psi, L.w, L.prm, L.n, L.m, lev_e2(c, l),
+                       (float)c->p.Sigma, L.lab, L.prm);
+    transpose_u8(c, L.lab, L.prm, L.lab_cm, L.pcm, L.n, L.m);
+    if (c->p.model == 1) area_term(c, l, L.psi, L.prm, DS_AREA_FRZ);
+    chk(c);
+}
+
+// one outer iteration of Hybrid Smoother 2: freeze, sweeps A, B, C, D
+void outer(mgseg_ctx *c, int l)
+{
+    Level &L = c->lev[l];
+    freeze(c, l);
+    launch_sweep(c, l, 0, L.P[0], L.P[1]);
+    launch_sweep(c, l, 1, L.P[1], L.P[2]);
+    transpose_f(c, L.P[2], L.prm, L.T[1], L.pcm, L.n, L.m);
+    launch_sweep(c, l, 2, L.T[1], L.T[2]);
+    launch_sweep(c, l, 3, L.T[2], L.T[1]);
+    transpose_f(c, L.T[1], L.pcm, L.P[0], L.prm, L.m, L.n);
+    chk(c);
+}
+
+void smooth(mgseg_ctx *c, int l, int iters)
+{
+    for (int it = 0; it < iters; it++) outer(c, l);
+}
+
+void coarsest(mgseg_ctx *c, int l)
+{
+    Level &L = c->lev[l];
+    if (L.n * L.m == 1) {
+        ScalarArgs S;
+        S.phi = L.P[0]; S.F = L.F; S.fit = L.fit; S.lo = l > 0 ? L.lo : nullptr; S.hi = l > 0 ? L.hi : nullptr;
+        S.h2 = L.h * L.h; S.A1 = c->A1; S.nu = c->p.nu; S.eps = c->p.eps; S.M = c->p.M;
+        S.model = c->p.model; S.scaled = c->p.scaled;
+        hipLaunchKernelGGL(k_scalar_solve, dim3(1), dim3(64), 0, c->s, S);
+        chk(c);
+        return;
+    }
+    smooth(c, l, c->p.coarse_iters);
+}
+
+void residual(mgseg_ctx *c, int l, float *r, double *partial)
+{
+    Level &L = c->lev[l];
+    if (c->p.model == 1) area_term(c, l, L.P[0], L.prm, DS_AREA_EVAL);
+    hipLaunchKernelGGL(k_residual, grid2(L.n, L.m), dim3(256), 0, c->s, L.P[0], L.w, L.fit,
+                       L.has_F ? L.F : nullptr, l > 0 ? L.lo : nullptr, l > 0 ? L.hi : nullptr, L.prm, L.n, L.m,
+                       (float)(c->p.mu / L.h), lev_e2(c, l), (float)c->p.eps,
+                       c->p.model == 1 ? c->dsc + DS_AREA_EVAL : nullptr, c->p.scaled, (float)c->p.M, r, partial);
+    chk(c);
+}
+
+// FAS V-cycle (Algorithm-1 box, gamma = 1) from level l0 down and back
+void vcycle_from(mgseg_ctx *c, int l0)
+{
+    for (int l = l0; l < c->L - 1; l++) {
+        Level &L = c->lev[l], &Lc = c->lev[l + 1];
+        smooth(c, l, c->p.nu1);
+        residual(c, l, L.r, nullptr);
+        dim3 gc = grid2(Lc.n, Lc.m);
+        hipLaunchKernelGGL(k_restrict, gc, dim3(256), 0, c->s, L.P[0], L.prm, Lc.phic, Lc.prm, Lc.n, Lc.m);
+        hipLaunchKernelGGL(k_restrict, gc, dim3(256), 0, c->s, L.r, L.prm, Lc.r, Lc.prm, Lc.n, Lc.m);
+        hipLaunchKernelGGL(k_coarse_bounds, gc, dim3(256), 0, c->s, L.P[0], l > 0 ? L.lo : nullptr,
+                           l > 0 ? L.hi : nullptr, L.prm, L.n, L.m, Lc.phic, Lc.lo, Lc.hi, Lc.prm, Lc.n, Lc.m,
+                           (float)c->p.M);
+        transpose_f(c, Lc.lo, Lc.prm, Lc.lo_cm, Lc.pcm, Lc.n, Lc.m);
+        transpose_f(c, Lc.hi, Lc.prm, Lc.hi_cm, Lc.pcm, Lc.n, Lc.m);
+        if (c->p.model == 1) area_term(c, l + 1, Lc.phic, Lc.prm, DS_AREA_EVAL);
+        hipLaunchKernelGGL(k_coarse_rhs, gc, dim3(256), 0, c->s, Lc.phic, Lc.w, Lc.fit, Lc.r, Lc.prm, Lc.n, Lc.m,
+                           (float)(c->p.mu / Lc.h), lev_e2(c, l + 1), (float)c->p.eps,
+                           c->p.model == 1 ? c->dsc + DS_AREA_EVAL : nullptr, c->p.scaled, Lc.F, Lc.P[0]);
+        transpose_f(c, Lc.F, Lc.prm, Lc.F_cm, Lc.pcm, Lc.n, Lc.m);
+        Lc.has_F = true;
+        chk(c);
+    }
+    coarsest(c, c->L - 1);
+    for (int l = c->L - 2; l >= l0; l--) {
+        Level &L = c->lev[l], &Lc = c->lev[l + 1];
+        hipLaunchKernelGGL(k_prolong_correct, grid2(L.n, L.m), dim3(256), 0, c->s, L.P[0], l > 0 ? L.lo : nullptr,
+                           l > 0 ? L.hi : nullptr, L.prm, L.n, L.m, Lc.P[0], Lc.phic, Lc.prm, (float)c->p.M);
+        smooth(c, l, c->p.nu2);
+        chk(c);
+    }
+}
+
+mgseg_status sync_status(mgseg_ctx *c)
+{
+    hipError_t e = hipStreamSynchronize(c->s);
+    if (e != hipSuccess && c->err == hipSuccess) c->err = e;
+    if (c->err != hipSuccess) return MGSEG_E_HIP;
+    return MGSEG_OK;
+}
+
+double read_scalar(mgseg_ctx *c, int slot)
+{
+    double v = 0.0;
+    (void)hipMemcpyAsync(&v, c->dsc + slot, sizeof(double), hipMemcpyDeviceToHost, c->s);
+    (void)hipStreamSynchronize(c->s);
+    return v;
+}
+
+// refresh c1, c2, then the FP64 residual (norm, phi32, F~)
+mgseg_status refresh_and_residual(mgseg_ctx *c)
+{
+    update_c(c);
+    res64(c, c->p.mixed_precision != 0);
+    if (!c->p.mixed_precision) c->lev[0].has_F = false;
+    return MGSEG_OK;
+}
+
+mgseg_status one_cycle(mgseg_ctx *c, double *rel_out)
+{
+    Level &L0 = c->lev[0];
+    size_t N = (size_t)c->n * c->m;
+    (void)hipMemcpyAsync(c->prev64, c->phi64, sizeof(double) * N, hipMemcpyDeviceToDevice, c->s);
+    vcycle_from(c, 0);
+    dim3 g = grid2(c->n, c->m);
+    if (c->p.mixed_precision)
+        hipLaunchKernelGGL(k_defect_update, g, dim3(256), 0, c->s, c->phi64, L0.P[0], L0.prm, c->n, c->m, c->p.M);
+    else
+        hipLaunchKernelGGL(k_copy32to64, g, dim3(256), 0, c->s, L0.P[0], L0.prm, c->phi64, c->n, c->m);
+    refresh_and_residual(c);
+    int nb = std::min(RED_BLOCKS, std::max(1, (int)((N + 255) / 256)));
+    hipLaunchKernelGGL(k_eta, dim3(nb), dim3(256), 0, c->s, c->phi64, c->prev64, (long long)N, c->part + 4 * RED_BLOCKS);
+    chk(c);
+    std::vector<double> eh(2 * nb);
+    double res = 0.0;
+    (void)hipMemcpyAsync(&res, c->dsc + DS_RES, sizeof(double), hipMemcpyDeviceToHost, c->s);
+    (void)hipMemcpyAsync(eh.data(), c->part + 4 * RED_BLOCKS, sizeof(double) * 2 * nb, hipMemcpyDeviceToHost, c->s);
+    mgseg_status st = sync_status(c);
+    if (st != MGSEG_OK) return st;
+    double d2 = 0.0, p2 = 0.0;
+    for (int b = 0; b < nb; b++) { d2 += eh[2 * b]; p2 += eh[2 * b + 1]; }
+    c->eta = p2 > 0.0 ? std::sqrt(d2 / p2) : 0.0;
+    c->res = res;
+    c->cycles++;
+    c->rel = c->res0 > 0.0 ? res / c->res0 : 0.0;
+    if (rel_out) *rel_out = c->rel;
+    if (!std::isfinite(res)) return MGSEG_E_NONFINITE;
+    return MGSEG_OK;
+}
+
+}  // namespace
+
+// ==========================================================================
+extern "C" {
+
+void mgseg_params_default(mgseg_params *p)
+{
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->struct_size = sizeof(mgseg_params);
+    p->model = MGSEG_SPENCER_CHEN;
+    p->mu = 0.5; p->lambda1 = 6.5025; p->lambda2 = 6.5025; p->theta = 4.0; p->nu = 1.0;
+    p->eps = 1.0; p->eps_tv_px = 1.0; p->beta = 1.0; p->sigma_g = 1.0; p->sigma_d = 0.1;
+    p->Sigma = 2.0; p->M = 4.0; p->nu1 = 2; p->nu2 = 2; p->levels = 0; p->coarse_iters = 100;
+    p->mixed_precision = 1; p->scaled = 0;
+}
+
+const char *mgseg_strerror(mgseg_status s)
+{
+    switch (s) {
+    case MGSEG_OK: return "ok";
+    case MGSEG_E_ARG: return "invalid argument";
+    case MGSEG_E_SHAPE: return "image shape not divisible by 2^(levels-1)";
+    case MGSEG_E_NOMEM: return "device allocation failed";
+    case MGSEG_E_HIP: return "HIP runtime error";
+    case MGSEG_E_NONFINITE: return "non-finite residual";
+    case MGSEG_E_NOT_CONVERGED: return "not converged within max_cycles";
+    case MGSEG_E_STATE: return "invalid state";
+    }
+    return "unknown status";
+}
+
+void mgseg_destroy(mgseg_ctx *c)
+{
+    if (!c) return;
+    if (c->s) (void)hipStreamSynchronize(c->s);
+    for (void *p : c->allocs) (void)hipFree(p);
+    delete c;
+}
+
+mgseg_status mgseg_setup(const float *image_dev, int n, int m, int pitch, const float *markers_host, int k,
+                         const mgseg_params *p, void *stream, mgseg_ctx **out)
+{
+    if (!out) return MGSEG_E_ARG;
+    *out = nullptr;
+    if (!image_dev || !markers_host || !p || k < 1 || k > 64 || n < 1 || m < 1 || pitch < m) return MGSEG_E_ARG;
+    if (p->struct_size != sizeof(mgseg_params)) return MGSEG_E_ARG;
+    if (p->nu1 < 0 || p->nu2 < 0 || p->coarse_iters < 0 || !(p->M > 0.0) || !(p->eps > 0.0) || p->levels < 0 ||
+        p->levels > MAXLEV)
+        return MGSEG_E_ARG;
+    for (int t = 0; t < 2 * k; t++)
+        if (!std::isfinite(markers_host[t])) return MGSEG_E_ARG;
+    int Lv = p->levels;
+    if (Lv == 0) {
+        Lv = 1;
+        while (Lv < MAXLEV && n % (1 << Lv) == 0 && m % (1 << Lv) == 0 && std::min(n, m) >> Lv >= 4) Lv++;
+    }
+    int div = 1 << (Lv - 1);
+    if (n % div || m % div) return MGSEG_E_SHAPE;
+    if (n > 8192 || m > 8192) return MGSEG_E_SHAPE;
+
+    mgseg_ctx *c = new (std::nothrow) mgseg_ctx();
+    if (!c) return MGSEG_E_NOMEM;
+    c->p = *p; c->p.levels = Lv;
+    c->s = (hipStream_t)stream;
+    c->L = Lv; c->n = n; c->m = m;
+    c->h0 = 1.0 / std::sqrt((double)n * (double)m);
+    size_t N = (size_t)n * m;
+    for (int l = 0; l < Lv; l++) {
+        Level &L = c->lev[l];
+        L.n = n >> l; L.m = m >> l; L.h = c->h0 * (double)(1 << l);
+        L.prm = pad64(L.m); L.pcm = pad64(L.n);
+        size_t Nr = (size_t)L.n * L.prm, Nc = (size_t)L.m * L.pcm;
+        L.z = dalloc<float>(c, Nr); L.d = dalloc<float>(c, Nr); L.w = dalloc<float>(c, Nr);
+        L.fit = dalloc<float>(c, Nr); L.F = dalloc<float>(c, Nr);
+        for (int t = 0; t < 3; t++) { L.P[t] = dalloc<float>(c, Nr); L.T[t] = dalloc<float>(c, Nc); }
+        L.psi = dalloc<float>(c, Nr); L.psi_cm = dalloc<float>(c, Nc);
+        L.phic = dalloc<float>(c, Nr); L.r = dalloc<float>(c, Nr);
+        L.lo = dalloc<float>(c, Nr); L.hi = dalloc<float>(c, Nr);
+        L.w_cm = dalloc<float>(c, Nc); L.fit_cm = dalloc<float>(c, Nc); L.F_cm = dalloc<float>(c, Nc);
+        L.lo_cm = dalloc<float>(c, Nc); L.hi_cm = dalloc<float>(c, Nc);
+        L.lab = dalloc<uint8_t>(c, Nr); L.lab_cm = dalloc<uint8_t>(c, Nc);
+    }
+    c->phi64 = dalloc<double>(c, N); c->w64 = dalloc<double>(c, N); c->d64 = dalloc<double>(c, N);
+    c->g64 = dalloc<double>(c, N); c->prev64 = dalloc<double>(c, N);
+    c->dsc = dalloc<double>(c, DS_COUNT);
+    c->part_n = 8 * RED_BLOCKS + (int)((N + 255) / 256) + n + 16;
+    c->part = dalloc<double>(c, (size_t)c->part_n);
+    c->scr_field = (long long)N;
+    c->scr = dalloc<float>(c, (size_t)2 * SF_COUNT * N);
+    double *zb = dalloc<double>(c, N), *t64 = dalloc<double>(c, N);
+    c->mk_d = dalloc<double>(c, 2 * (size_t)k);
+    c->hull_d = dalloc<double>(c, 2 * (size_t)k + 2);
+    if (c->oom) { mgseg_destroy(c); return MGSEG_E_NOMEM; }
+
+    // markers and their convex hull
+    std::vector<double> mk(2 * (size_t)k), hull;
+    for (int t = 0; t < 2 * k; t++) mk[t] = markers_host[t];
+    c->k = k;
+    c->hv = host_hull(mk, hull);
+    c->A1 = host_area(hull, c->hv) * c->h0 * c->h0;
+    (void)hipMemcpyAsync(c->mk_d, mk.data(), sizeof(double) * mk.size(), hipMemcpyHostToDevice, c->s);
+    if (!hull.empty())
+        (void)hipMemcpyAsync(c->hull_d, hull.data(), sizeof(double) * hull.size(), hipMemcpyHostToDevice, c->s);
+    // Gaussian kernel
+    int R = (int)std::ceil(4.0 * p->sigma_g);
+    std::vector<double> ker(2 * R + 1);
+    double ks = 0.0;
+    for (int t = -R; t <= R; t++) {
+        double v = p->sigma_g > 0 ? std::exp(-(double)(t * t) / (2.0 * p->sigma_g * p->sigma_g)) : (t == 0);
+        ker[t + R] = v; ks += v;
+    }
+    for (auto &v : ker) v /= ks;
+    double *ker_d = dalloc<double>(c, ker.size());
+    if (c->oom) { mgseg_destroy(c); return MGSEG_E_NOMEM; }
+    (void)hipMemcpyAsync(ker_d, ker.data(), sizeof(double) * ker.size(), hipMemcpyHostToDevice, c->s);
+
+    Level &L0 = c->lev[0];
+    dim3 g = grid2(n, m);
+    hipLaunchKernelGGL(k_blur_rows, g, dim3(256), 0, c->s, image_dev, pitch, t64, n, m, ker_d, R);
+    hipLaunchKernelGGL(k_blur_cols, g, dim3(256), 0, c->s, t64, zb, n, m, ker_d, R);
+    SetupArgs S;
+    S.zb = zb; S.z = image_dev; S.pz = pitch; S.mk = c->mk_d; S.k = k; S.hull = c->hull_d; S.hv = c->hv;
+    S.h0 = c->h0; S.beta = p->beta; S.sigma_d = p->sigma_d; S.M = p->M; S.model = p->model; S.n = n; S.m = m;
+    S.g64 = c->g64; S.d64 = c->d64; S.w64 = c->w64; S.phi64 = c->phi64;
+    S.w32 = L0.w; S.d32 = L0.d; S.z32 = L0.z; S.phi32 = L0.P[0]; S.p32 = L0.prm;
+    hipLaunchKernelGGL(k_setup_maps, g, dim3(256), 0, c->s, S);
+    for (int l = 1; l < Lv; l++) {
+        Level &Lf = c->lev[l - 1], &Lc = c->lev[l];
+        dim3 gc = grid2(Lc.n, Lc.m);
+        hipLaunchKernelGGL(k_restrict, gc, dim3(256), 0, c->s, Lf.z, Lf.prm, Lc.z, Lc.prm, Lc.n, Lc.m);
+        hipLaunchKernelGGL(k_restrict, gc, dim3(256), 0, c->s, Lf.d, Lf.prm, Lc.d, Lc.prm, Lc.n, Lc.m);
+        hipLaunchKernelGGL(k_restrict, gc, dim3(256), 0, c->s, Lf.w, Lf.prm, Lc.w, Lc.prm, Lc.n, Lc.m);
+    }
+    for (int l = 0; l < Lv; l++) {
+        Level &L = c->lev[l];
+        transpose_f(c, L.w, L.prm, L.w_cm, L.pcm, L.n, L.m);
+    }
+    chk(c);
+    refresh_and_residual(c);
+    mgseg_status st = sync_status(c);
+    if (st != MGSEG_OK) { mgseg_destroy(c); return st; }
+    c->res0 = read_scalar(c, DS_RES);
+    c->res = c->res0;
+    c->rel = 1.0;
+    *out = c;
+    return MGSEG_OK;
+}
+
+mgseg_status mgseg_set_phi0(mgseg_ctx *c, const float *phi_dev, int pitch)
+{
+    if (!c || !phi_dev || pitch < c->m) return MGSEG_E_ARG;
+    Level &L0 = c->lev[0];
+    hipLaunchKernelGGL(k_set_phi0, grid2(c->n, c->m), dim3(256), 0, c->s, phi_dev, pitch, c->p.M, c->phi64,
+                       L0.P[0], L0.prm, c->n, c->m);
+    refresh_and_residual(c);
+    mgseg_status st = sync_status(c);
+    if (st != MGSEG_OK) return st;
+    c->res0 = read_scalar(c, DS_RES);
+    c->res = c->res0; c->rel = 1.0; c->cycles = 0;
+    return MGSEG_OK;
+}
+
+mgseg_status mgseg_vcycle(mgseg_ctx *c, double *rel_res_out)
+{
+    if (!c) return MGSEG_E_ARG;
+    return one_cycle(c, rel_res_out);
+}
+
+mgseg_status mgseg_solve(mgseg_ctx *c, double tol, int max_cycles, int *cycles_out, double *rel_res_out)
+{
+    if (!c || !(tol > 0.0) || max_cycles < 0) return MGSEG_E_ARG;
+    int done = 0;
+    double rel = c->rel;
+    mgseg_status st = MGSEG_OK;
+    while (done < max_cycles && !(rel <= tol)) {
+        st = one_cycle(c, &rel);
+        done++;
+        if (st != MGSEG_OK) break;
+    }
+    if (cycles_out) *cycles_out = done;
+    if (rel_res_out) *rel_res_out = rel;
+    if (st != MGSEG_OK) return st;
+    return rel <= tol ? MGSEG_OK : MGSEG_E_NOT_CONVERGED;
+}
+
+mgseg_status mgseg_get_phi(mgseg_ctx *c, double *phi_dev, int pitch)
+{
+    if (!c || !phi_dev || pitch < c->m) return MGSEG_E_ARG;
+    hipLaunchKernelGGL(k_out_phi, grid2(c->n, c->m), dim3(256), 0, c->s, c->phi64, c->n, c->m, phi_dev, pitch);
+    chk(c);
+    return sync_status(c);
+}
+
+mgseg_status mgseg_get_mask(mgseg_ctx *c, uint8_t *mask_dev, int pitch)
+{
+    if (!c || !mask_dev || pitch < c->m) return MGSEG_E_ARG;
+    hipLaunchKernelGGL(k_out_mask, grid2(c->n, c->m), dim3(256), 0, c->s, c->phi64, c->n, c->m, mask_dev, pitch);
+    chk(c);
+    return sync_status(c);
+}
+
+mgseg_status mgseg_get_stats(mgseg_ctx *c, mgseg_stats *s)
+{
+    if (!c || !s) return MGSEG_E_ARG;
+    double c12[2] = {0, 0};
+    (void)hipMemcpyAsync(c12, c->dsc + DS_C1, sizeof(c12), hipMemcpyDeviceToHost, c->s);
+    mgseg_status st = sync_status(c);
+    if (st != MGSEG_OK) return st;
+    std::vector<double> ph((size_t)c->n * c->m);
+    (void)hipMemcpy(ph.data(), c->phi64, sizeof(double) * ph.size(), hipMemcpyDeviceToHost);
+    size_t fg = 0;
+    for (double v : ph) fg += v > 0.0;
+    s->c1 = c12[0]; s->c2 = c12[1]; s->rel_res = c->rel; s->res = c->res; s->res0 = c->res0;
+    s->eta = c->eta; s->cycles = c->cycles; s->levels = c->L;
+    s->frac_fg = ph.empty() ? 0.0 : (double)fg / (double)ph.size();
+    return MGSEG_OK;
+}
+
+mgseg_status mgseg_level_shape(mgseg_ctx *c, int level, int *n, int *m, double *h)
+{
+    if (!c || level < 0 || level >= c->L) return MGSEG_E_ARG;
+    if (n) *n = c->lev[level].n;
+    if (m) *m = c->lev[level].m;
+    if (h) *h = c->lev[level].h;
+    return MGSEG_OK;
+}
+
+static float *field_ptr(mgseg_ctx *c, int l, int field)
+{
+    Level &L = c->lev[l];
+    switch (field) {
+    case 0: return L.z; case 1: return L.d; case 2: return L.w; case 3: return L.fit;
+    case 4: return L.P[0]; case 5: return L.F; case 6: return L.lo; case 7: return L.hi;
+    case 11: return L.r;
+    default: return nullptr;
+    }
+}
+
+mgseg_status mgseg_debug_get(mgseg_ctx *c, int l, int field, void *host)
+{
+    if (!c || !host || l < 0 || l >= c->L) return MGSEG_E_ARG;
+    Level &L = c->lev[l];
+    mgseg_status st = sync_status(c);
+    if (st != MGSEG_OK) return st;
+    hipError_t e = hipSuccess;
+    if (field == 8 || field == 9) {
+        if (l != 0) return MGSEG_E_ARG;
+        e = hipMemcpy(host, field == 8 ? c->g64 : c->phi64, sizeof(double) * (size_t)c->n * c->m,
+                      hipMemcpyDeviceToHost);
+    } else if (field == 10) {
+        e = hipMemcpy2D(host, L.m, L.lab, L.prm, L.m, L.n, hipMemcpyDeviceToHost);
+    } else {
+        float *f = field_ptr(c, l, field);
+        if (!f) return MGSEG_E_ARG;
+        e = hipMemcpy2D(host, sizeof(float) * L.m, f, sizeof(float) * L.prm, sizeof(float) * L.m, L.n,
+                        hipMemcpyDeviceToHost);
+    }
+    return e == hipSuccess ? MGSEG_OK : MGSEG_E_HIP;
+}
+
+mgseg_status mgseg_debug_set(mgseg_ctx *c, int l, int field, const void *host)
+{
+    if (!c || !host || l < 0 || l >= c->L) return MGSEG_E_ARG;
+    Level &L = c->lev[l];
+    mgseg_status st = sync_status(c);
+    if (st != MGSEG_OK) return st;
+    hipError_t e = hipSuccess;
+    if (field == 9) {
+        if (l != 0) return MGSEG_E_ARG;
+        e = hipMemcpy(c->phi64, host, sizeof(double) * (size_t)c->n * c->m, hipMemcpyHostToDevice);
+    } else if (field == 10) {
+        e = hipMemcpy2D(L.lab, L.prm, host, L.m, L.m, L.n, hipMemcpyHostToDevice);
+        transpose_u8(c, L.lab, L.prm, L.lab_cm, L.pcm, L.n, L.m);
+    } else {
+        float *f = field_ptr(c, l, field);
+        if (!f || field == 8 || field == 11) return MGSEG_E_ARG;
+        e = hipMemcpy2D(f, sizeof(float) * L.prm, host, sizeof(float) * L.m, sizeof(float) * L.m, L.n,
+                        hipMemcpyHostToDevice);
+        if (field == 2) transpose_f(c, L.w, L.prm, L.w_cm, L.pcm, L.n, L.m);
+        if (field == 3) transpose_f(c, L.fit, L.prm, L.fit_cm, L.pcm, L.n, L.m);
+        if (field == 5) { transpose_f(c, L.F, L.prm, L.F_cm, L.pcm, L.n, L.m); L.has_F = true; }
+        if (field == 6) transpose_f(c, L.lo, L.prm, L.lo_cm, L.pcm, L.n, L.m);
+        if (field == 7) transpose_f(c, L.hi, L.prm, L.hi_cm, L.pcm, L.n, L.m);
+    }
+    if (e != hipSuccess) return MGSEG_E_HIP;
+    chk(c);
+    return sync_status(c);
+}
+
+mgseg_status mgseg_debug_scalars(mgseg_ctx *c, double *out5)
+{
+    if (!c || !out5) return MGSEG_E_ARG;
+    double c12[2];
+    (void)hipMemcpyAsync(c12, c->dsc + DS_C1, sizeof(c12), hipMemcpyDeviceToHost, c->s);
+    mgseg_status st = sync_status(c);
+    if (st != MGSEG_OK) return st;
+    out5[0] = c12[0]; out5[1] = c12[1]; out5[2] = c->A1; out5[3] = c->res0; out5[4] = c->h0;
+    return MGSEG_OK;
+}
+
+mgseg_status mgseg_debug_set_c(mgseg_ctx *c, double c1, double c2)
+{
+    if (!c) return MGSEG_E_ARG;
+    double c12[2] = {c1, c2};
+    (void)hipMemcpyAsync(c->dsc + DS_C1, c12, sizeof(c12), hipMemcpyHostToDevice, c->s);
+    update_fit(c);
+    chk(c);
+    return sync_status(c);
+}
+
+mgseg_status mgseg_debug_op(mgseg_ctx *c, int l, int op, int arg)
+{
+    if (!c || l < 0 || l >= c->L) return MGSEG_E_ARG;
+    Level &L = c->lev[l];
+    switch (op) {
+    case 0: freeze(c, l); break;
+    case 1: case 2:
+        launch_sweep(c, l, op - 1, L.P[0], L.P[1]);
+        (void)hipMemcpyAsync(L.P[0], L.P[1], sizeof(float) * (size_t)L.n * L.prm, hipMemcpyDeviceToDevice, c->s);
+        break;
+    case 3: case 4:
+        transpose_f(c, L.P[0], L.prm, L.T[1], L.pcm, L.n, L.m);
+        launch_sweep(c, l, op - 1, L.T[1], L.T[2]);
+        transpose_f(c, L.T[2], L.pcm, L.P[0], L.prm, L.m, L.n);
+        break;
+    case 5: smooth(c, l, arg); break;
+    case 6: coarsest(c, l); break;
+    case 7: vcycle_from(c, l); break;
+    case 8: residual(c, l, L.r, nullptr); break;
+    case 9: update_c(c); break;
+    default: return MGSEG_E_ARG;
+    }
+    chk(c);
+    return sync_status(c);
+}
+
+}  // extern "C"

@@ -1,0 +1,554 @@
+// mgseg_kernels.h -- grid kernels of libmgseg other than the line sweep.
+#pragma once
+#include "mgseg_device.h"
+
+#define TILE 32
+
+// ==========================================================================
+// Setup maps (Sec. 2.2).  Level-0 maps are computed in FP64.
+// Gaussian pre-blur of z (separable, half-sample mirror), then
+// g = 1/(1 + beta |grad|^2) with central differences in domain units.
+__global__ void k_blur_rows(const float *z, int pz, double *out, int n, int m, const double *ker, int R)
+{
+    int j = blockIdx.x * blockDim.x + threadIdx.x, i = blockIdx.y;
+    if (j >= m || i >= n) return;
+    double s = 0.0;
+    for (int t = -R; t <= R; t++) {
+        int jj = j + t;
+        while (jj < 0 || jj >= m) jj = (jj < 0) ? -jj - 1 : 2 * m - jj - 1;
+        s += ker[t + R] * (double)z[(long long)i * pz + jj];
+    }
+    out[(long long)i * m + j] = s;
+}
+__global__ void k_blur_cols(const double *in, double *out, int n, int m, const double *ker, int R)
+{
+    int j = blockIdx.x * blockDim.x + threadIdx.x, i = blockIdx.y;
+    if (j >= m || i >= n) return;
+    double s = 0.0;
+    for (int t = -R; t <= R; t++) {
+        int ii = i + t;
+        while (ii < 0 || ii >= n) ii = (ii < 0) ? -ii - 1 : 2 * n - ii - 1;
+        s += ker[t + R] * in[(long long)ii * m + j];
+    }
+    out[(long long)i * m + j] = s;
+}
+
+struct SetupArgs {
+    const double *zb;       // blurred image (dense n x m)
+    const float *z; int pz;
+    const double *mk; int k;        // markers (row, col) pixel coords
+    const double *hull; int hv;     // convex hull vertices
+    double h0, beta, sigma_d, M;
+    int model, n, m;
+    double *g64, *d64, *w64, *phi64;   // dense n x m
+    float *w32, *d32, *z32, *phi32; int p32;
+};
+
+__device__ double seg_dist64(double px, double py, double ax, double ay, double bx, double by)
+{
+    double vx = bx - ax, vy = by - ay, wx = px - ax, wy = py - ay;
+    double L2 = vx * vx + vy * vy;
+    double t = L2 > 0.0 ? (wx * vx + wy * vy) / L2 : 0.0;
+    t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+    double dx = px - (ax + t * vx), dy = py - (ay + t * vy);
+    return sqrt(dx * dx + dy * dy);
+}
+
+// signed distance (pixels) to the marker-polygon boundary, + inside (Sec. 5)
+__device__ double hull_sd(const double *hull, int hv, double pr, double pc)
+{
+    if (hv == 0) return -1e30;
+    if (hv == 1) return -sqrt((pr - hull[0]) * (pr - hull[0]) + (pc - hull[1]) * (pc - hull[1]));
+    double dmin = 1e300;
+    bool inside = hv >= 3;
+    for (int t = 0; t < hv; t++) {
+        const double *a = hull + 2 * t, *b = hull + 2 * ((t + 1) % hv);
+        double dd = seg_dist64(pr, pc, a[0], a[1], b[0], b[1]);
+        dmin = fmin(dmin, dd);
+        double cr = (b[0] - a[0]) * (pc - a[1]) - (b[1] - a[1]) * (pr - a[0]);
+        if (cr < 0.0) inside = false;
+        if (hv == 2) break;
+    }
+    return inside ? dmin : -dmin;
+}
+
+__global__ void k_setup_maps(SetupArgs S)
+{
+    int j = blockIdx.x * blockDim.x + threadIdx.x, i = blockIdx.y;
+    if (j >= S.m || i >= S.n) return;
+    const int n = S.n, m = S.m;
+    long long q = (long long)i * m + j;
+    int jp = mg_mirror(j + 1, m), jm = mg_mirror(j - 1, m), ip = mg_mirror(i + 1, n), im = mg_mirror(i - 1, n);
+    double gx = (S.zb[(long long)i * m + jp] - S.zb[(long long)i * m + jm]) / (2.0 * S.h0);
+    double gy = (S.zb[(long long)ip * m + j] - S.zb[(long long)im * m + j]) / (2.0 * S.h0);
+    double g = 1.0 / (1.0 + S.beta * (gx * gx + gy * gy));
+    double prod = 1.0;
+    for (int t = 0; t < S.k; t++) {
+        double dy = (S.mk[2 * t] - (i + 0.5)) * S.h0;
+        double dx = (S.mk[2 * t + 1] - (j + 0.5)) * S.h0;
+        prod *= 1.0 - exp(-(dx * dx + dy * dy) / (2.0 * S.sigma_d * S.sigma_d));
+    }
+    double w = (S.model == 1) ? prod * g : g;
+    double ph = hull_sd(S.hull, S.hv, i + 0.5, j + 0.5);
+    ph = ph < -S.M ? -S.M : (ph > S.M ? S.M : ph);
+    S.g64[q] = g; S.d64[q] = prod; S.w64[q] = w; S.phi64[q] = ph;
+    long long q32 = (long long)i * S.p32 + j;
+    S.w32[q32] = (float)w; S.d32[q32] = (float)prod;
+    S.z32[q32] = S.z[(long long)i * S.pz + j];
+    S.phi32[q32] = (float)ph;
+}
+
+// ==========================================================================
+// Transfers (Sec. 3.1).  Full weighting, 0-based: coarse I takes fine
+// 2I, 2I+1, 2I+2 with 1/4, 1/2, 1/4, the last coarse index fine 2I, 2I+1 with
+// 1/2, 1/2 (the paper's boundary rule); tensor product in 2-D.
+__device__ __forceinline__ float fw_row(const float *row, int J, int mc)
+{
+    if (J < mc - 1) return 0.25f * row[2 * J] + 0.5f * row[2 * J + 1] + 0.25f * row[2 * J + 2];
+    return 0.5f * row[2 * J] + 0.5f * row[2 * J + 1];
+}
+__global__ void k_restrict(const float *f, int pf, float *c, int pc, int nc, int mc)
+{
+    int J = blockIdx.x * blockDim.x + threadIdx.x, I = blockIdx.y;
+    if (J >= mc || I >= nc) return;
+    const float *r0 = f + (long long)(2 * I) * pf, *r1 = r0 + pf;
+    float v;
+    if (I < nc - 1) {
+        const float *r2 = r1 + pf;
+        v = 0.25f * fw_row(r0, J, mc) + 0.5f * fw_row(r1, J, mc) + 0.25f * fw_row(r2, J, mc);
+    } else {
+        v = 0.5f * fw_row(r0, J, mc) + 0.5f * fw_row(r1, J, mc);
+    }
+    c[(long long)I * pc + J] = v;
+}
+
+// coarse bounds of the box reading: the coarse unknown may move only as far as
+// every fine cell its interpolated correction reaches can follow inside that
+// cell's own bounds: lo_c = phic + max(lo_f - phi_f), hi_c = phic + min(hi_f - phi_f)
+// over fine (2I..2I+2) x (2J..2J+2).  flo / fhi null: -M / M.
+__global__ void k_coarse_bounds(const float *phi, const float *flo, const float *fhi, int pf, int n, int m,
+                                const float *phic, float *clo, float *chi, int pc, int nc, int mc, float M)
+{
+    int J = blockIdx.x * blockDim.x + threadIdx.x, I = blockIdx.y;
+    if (J >= mc || I >= nc) return;
+    float dl = -MG_BIG, dh = MG_BIG;
+    for (int i = 2 * I; i <= 2 * I + 2 && i < n; i++)
+        for (int j = 2 * J; j <= 2 * J + 2 && j < m; j++) {
+            long long q = (long long)i * pf + j;
+            float p = phi[q];
+            float lo = flo ? flo[q] : -M, hi = fhi ? fhi[q] : M;
+            dl = fmaxf(dl, lo - p);
+            dh = fminf(dh, hi - p);
+        }
+    float pcv = phic[(long long)I * pc + J];
+    clo[(long long)I * pc + J] = pcv + dl;
+    chi[(long long)I * pc + J] = pcv + dh;
+}
+
+// bilinear interpolation (Sec. 3.1), 0-based: fine 2I+1 <- coarse I, fine 2I
+// (I >= 1) <- mean of coarse I-1, I, fine 0 <- coarse 0; tensor product.
+// Correction: phi <- clip(phi + P(phi^c - phic), lo, hi).
+__device__ __forceinline__ void pl_idx(int f, int &a, int &b, float &wa)
+{
+    if (f & 1) { a = b = f >> 1; wa = 1.0f; }
+    else if (f == 0) { a = b = 0; wa = 1.0f; }
+    else { a = (f >> 1) - 1; b = f >> 1; wa = 0.5f; }
+}
+__global__ void k_prolong_correct(float *phi, const float *lo, const float *hi, int pf, int n, int m,
+                                  const float *phis, const float *phic, int pc, float M)
+{
+    int j = blockIdx.x * blockDim.x + threadIdx.x, i = blockIdx.y;
+    if (j >= m || i >= n) return;
+    int ia, ib, ja, jb;
+    float wi, wj;
+    pl_idx(i, ia, ib, wi);
+    pl_idx(j, ja, jb, wj);
+    auto e = [&](int I, int J) { long long q = (long long)I * pc + J; return phis[q] - phic[q]; };
+    float ea = wj * e(ia, ja) + (1.0f - wj) * e(ia, jb);
+    float eb = wj * e(ib, ja) + (1.0f - wj) * e(ib, jb);
+    float corr = wi * ea + (1.0f - wi) * eb;
+    long long q = (long long)i * pf + j;
+    float l = lo ? lo[q] : -M, h = hi ? hi[q] : M;
+    phi[q] = mg_clip(phi[q] + corr, l, h);
+}
+
+// ==========================================================================
+// transposes (32 x 32 tiles through LDS)
+template <typename T>
+__global__ void k_transpose(const T *in, int pin, T *out, int pout, int n, int m)
+{
+    // in: n x m (row pitch pin) -> out: m x n (row pitch pout)
+    __shared__ T tile[TILE][TILE + 1];
+    int bx = blockIdx.x * TILE, by = blockIdx.y * TILE;
+    for (int y = threadIdx.y; y < TILE; y += blockDim.y) {
+        int i = by + y, j = bx + threadIdx.x;
+        if (i < n && j < m) tile[y][threadIdx.x] = in[(long long)i * pin + j];
+    }
+    __syncthreads();
+    for (int y = threadIdx.y; y < TILE; y += blockDim.y) {
+        int j = bx + y, i = by + threadIdx.x;
+        if (i < n && j < m) out[(long long)j * pout + i] = tile[threadIdx.x][y];
+    }
+}
+
+// ==========================================================================
+// Freeze (start of every outer iteration, Sec. 3.2 "-I"): labels of the
+// jump set (Sec. 4.1 Definition; threshold Sigma of Sec. 5.2) with the
+// smallest coefficient (Sec. 4.2), on the four face values of each cell
+// (the common factor mu delta / h^2 cancels in both tests).  Interior faces
+// only; a zero interior value counts as an infinite ratio; ties take the
+// first of A, B, C, D.  Bit s of the label byte = starred in sweep s.
+__device__ __forceinline__ uint8_t cell_label(const float *psi, const float *w, int p, int n, int m, int i, int j,
+                                              float e2, float Sigma)
+{
+    int im = mg_mirror(i - 1, n), ip = mg_mirror(i + 1, n), jm = mg_mirror(j - 1, m), jp = mg_mirror(j + 1, m);
+    auto P = [&](int a, int b) { return psi[(long long)a * p + b]; };
+    auto W = [&](int a, int b) { return w[(long long)a * p + b]; };
+    float G[4];
+    bool in[4] = {i + 1 < n, i > 0, j + 1 < m, j > 0};
+    // A: face (i+1/2, j); B: (i-1/2, j); C: (i, j+1/2); D: (i, j-1/2)
+    G[0] = in[0] ? mg_face(P(i, j), P(i + 1, j), P(i, jp), P(i + 1, jp), P(i, jm), P(i + 1, jm), W(i, j), W(i + 1, j), e2) : 0.0f;
+    G[1] = in[1] ? mg_face(P(i - 1, j), P(i, j), P(i - 1, jp), P(i, jp), P(i - 1, jm), P(i, jm), W(i - 1, j), W(i, j), e2) : 0.0f;
+    G[2] = in[2] ? mg_face(P(i, j), P(i, j + 1), P(ip, j), P(ip, j + 1), P(im, j), P(im, j + 1), W(i, j), W(i, j + 1), e2) : 0.0f;
+    G[3] = in[3] ? mg_face(P(i, j - 1), P(i, j), P(ip, j - 1), P(ip, j), P(im, j - 1), P(im, j), W(i, j - 1), W(i, j), e2) : 0.0f;
+    int cnt = 0, amin = -1;
+    float gmin = 0.0f, gmax = 0.0f;
+    for (int s = 0; s < 4; s++) {
+        if (!in[s]) continue;
+        if (cnt == 0 || G[s] < gmin) { gmin = G[s]; amin = s; }
+        if (cnt == 0 || G[s] > gmax) gmax = G[s];
+        cnt++;
+    }
+    return (cnt >= 2 && gmax > Sigma * gmin) ? (uint8_t)(1u << amin) : (uint8_t)0;
+}
+
+__global__ void k_labels(const float *psi, const float *w, int p, int n, int m, float e2, float Sigma,
+                         uint8_t *lab, int lp)
+{
+    int j = blockIdx.x * blockDim.x + threadIdx.x, i = blockIdx.y;
+    if (j >= m || i >= n) return;
+    lab[(long long)i * lp + j] = cell_label(psi, w, p, n, m, i, j, e2, Sigma);
+}
+
+// ==========================================================================
+// operator N(phi) at one cell (eq. abcd, all coefficients at phi) in FP32
+__device__ __forceinline__ float cell_N(const float *phi, const float *w, const float *fit, int p, int n, int m,
+                                        int i, int j, float kap, float e2, float eps, float area, int scaled)
+{
+    int im = mg_mirror(i - 1, n), ip = mg_mirror(i + 1, n), jm = mg_mirror(j - 1, m), jp = mg_mirror(j + 1, m);
+    auto P = [&](int a, int b) { return phi[(long long)a * p + b]; };
+    auto W = [&](int a, int b) { return w[(long long)a * p + b]; };
+    float p0 = P(i, j);
+    float dl = scaled ? 1.0f : mg_delta(p0, eps);
+    float s = kap * dl;
+    float v = -dl * (fit[(long long)i * p + j] + area);
+    if (i + 1 < n) v += s * mg_face(p0, P(i + 1, j), P(i, jp), P(i + 1, jp), P(i, jm), P(i + 1, jm), W(i, j), W(i + 1, j), e2) * (P(i + 1, j) - p0);
+    if (i > 0) v += s * mg_face(P(i - 1, j), p0, P(i - 1, jp), P(i, jp), P(i - 1, jm), P(i, jm), W(i - 1, j), W(i, j), e2) * (P(i - 1, j) - p0);
+    if (j + 1 < m) v += s * mg_face(p0, P(i, j + 1), P(ip, j), P(ip, j + 1), P(im, j), P(im, j + 1), W(i, j), W(i, j + 1), e2) * (P(i, j + 1) - p0);
+    if (j > 0) v += s * mg_face(P(i, j - 1), p0, P(ip, j - 1), P(ip, j), P(im, j - 1), P(im, j), W(i, j - 1), W(i, j), e2) * (P(i, j - 1) - p0);
+    return v;
+}
+
+// residual r = F - N(phi), projected on the box (zero where the correction
+// -r/S would leave [lo, hi]); optional per-block partial sums of r^2.
+__global__ void k_residual(const float *phi, const float *w, const float *fit, const float *F, const float *lo,
+                           const float *hi, int p, int n, int m, float kap, float e2, float eps,
+                           const double *area, int scaled, float M, float *r, double *partial)
+{
+    __shared__ double red[256];
+    int j = blockIdx.x * blockDim.x + threadIdx.x, i = blockIdx.y;
+    int tid = threadIdx.x;
+    double acc = 0.0;
+    if (j < m && i < n) {
+        float ar = area ? (float)(*area) : 0.0f;
+        long long q = (long long)i * p + j;
+        float v = (F ? F[q] : 0.0f) - cell_N(phi, w, fit, p, n, m, i, j, kap, e2, eps, ar, scaled);
+        float ph = phi[q], l = lo ? lo[q] : -M, h = hi ? hi[q] : M;
+        if ((ph >= h && v < 0.0f) || (ph <= l && v > 0.0f)) v = 0.0f;
+        if (r) r[q] = v;
+        acc = (double)v * (double)v;
+    }
+    if (partial) {
+        red[tid] = acc;
+        __syncthreads();
+        for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+            if (tid < s) red[tid] += red[tid + s];
+            __syncthreads();
+        }
+        if (tid == 0) partial[(long long)blockIdx.y * gridDim.x + blockIdx.x] = red[0];
+    }
+}
+
+// coarse right-hand side F_c = N_c(phi_c) + r_c (Algorithm-1 box)
+__global__ void k_coarse_rhs(const float *phic, const float *w, const float *fit, const float *rc, int p, int n,
+                             int m, float kap, float e2, float eps, const double *area, int scaled, float *F,
+                             float *phi_init)
+{
+    int j = blockIdx.x * blockDim.x + threadIdx.x, i = blockIdx.y;
+    if (j >= m || i >= n) return;
+    float ar = area ? (float)(*area) : 0.0f;
+    long long q = (long long)i * p + j;
+    F[q] = cell_N(phic, w, fit, p, n, m, i, j, kap, e2, eps, ar, scaled) + rc[q];
+    phi_init[q] = phic[q];
+}
+
+// fit map with the current c1, c2 (Spencer-Chen adds theta d)
+__global__ void k_fit(const float *z, const float *d, int p, int n, int m, const double *c12, float l1, float l2,
+                      float theta, int model, float *fit)
+{
+    int j = blockIdx.x * blockDim.x + threadIdx.x, i = blockIdx.y;
+    if (j >= m || i >= n) return;
+    long long q = (long long)i * p + j;
+    float c1 = (float)c12[0], c2 = (float)c12[1];
+    float a = z[q] - c1, b = z[q] - c2;
+    float v = l1 * a * a - l2 * b * b;
+    if (model == 0) v += theta * d[q];
+    fit[q] = v;
+}
+
+// ==========================================================================
+// deterministic FP64 sums over a level: sum H(phi), sum H(phi) z, sum z
+template <typename T>
+__global__ void k_sums(const T *phi, int pp, const float *z, int pz, int n, int m, double eps, double *partial)
+{
+    __shared__ double r0[256], r1[256], r2[256];
+    int tid = threadIdx.x;
+    long long N = (long long)n * m;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    for (long long t = (long long)blockIdx.x * blockDim.x + tid; t < N; t += (long long)gridDim.x * blockDim.x) {
+        int i = (int)(t / m), j = (int)(t % m);
+        double H = mg_heav64((double)phi[(long long)i * pp + j], eps);
+        double zz = z ? (double)z[(long long)i * pz + j] : 0.0;
+        a0 += H; a1 += H * zz; a2 += zz;
+    }
+    r0[tid] = a0; r1[tid] = a1; r2[tid] = a2;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (tid < s) { r0[tid] += r0[tid + s]; r1[tid] += r1[tid + s]; r2[tid] += r2[tid + s]; }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        partial[3 * blockIdx.x] = r0[0];
+        partial[3 * blockIdx.x + 1] = r1[0];
+        partial[3 * blockIdx.x + 2] = r2[0];
+    }
+}
+
+// finalize: mode 0 -> area term 2 nu (h^2 sum H - A1) into out[0];
+//           mode 1 -> c1, c2 (eq. c1c2) into out[0], out[1];
+//           mode 2 -> sqrt(sum of partial r^2) into out[0] (partials of stride 1)
+__global__ void k_finalize(const double *partial, int nb, int mode, double N, double h2, double A1, double nu,
+                           double *out)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (mode == 2) {
+        double s = 0.0;
+        for (int b = 0; b < nb; b++) s += partial[b];
+        out[0] = sqrt(s);
+        return;
+    }
+    double sH = 0.0, sHz = 0.0, sz = 0.0;
+    for (int b = 0; b < nb; b++) { sH += partial[3 * b]; sHz += partial[3 * b + 1]; sz += partial[3 * b + 2]; }
+    if (mode == 0) {
+        out[0] = 2.0 * nu * (h2 * sH - A1);
+    } else {
+        out[0] = sH > 0.0 ? sHz / sH : 0.0;
+        out[1] = (N - sH) > 0.0 ? (sz - sHz) / (N - sH) : 0.0;
+    }
+}
+
+// ==========================================================================
+// FP64 residual on the finest grid (defect-correction loop): r64 = -N64(phi64)
+// (F = 0 there), the projected norm, phi32 = fl32(phi64) and the FP32 right-hand
+// side F~ = N32(phi32) + fl32(r64) of the next FP32 cycle.
+struct Res64Args {
+    const double *phi64, *w64, *d64;       // dense n x m
+    const float *z32, *w32, *fit32; int p32;
+    const double *c12, *area;              // area may be null
+    double kap, e2, eps, l1, l2, theta, M;
+    int model, scaled, n, m;
+    float *phi32, *Ft;                     // outputs (p32); Ft may be null
+    double *partial;
+};
+
+__device__ double cell_N64(const Res64Args &A, int i, int j, double c1, double c2, double area)
+{
+    const int n = A.n, m = A.m;
+    int im = mg_mirror(i - 1, n), ip = mg_mirror(i + 1, n), jm = mg_mirror(j - 1, m), jp = mg_mirror(j + 1, m);
+    auto P = [&](int a, int b) { return A.phi64[(long long)a * m + b]; };
+    auto W = [&](int a, int b) { return A.w64[(long long)a * m + b]; };
+    double p0 = P(i, j);
+    double dl = A.scaled ? 1.0 : mg_delta64(p0, A.eps);
+    double s = A.kap * dl;
+    double z = (double)A.z32[(long long)i * A.p32 + j];
+    double fa = z - c1, fb = z - c2;
+    double fit = A.l1 * fa * fa - A.l2 * fb * fb;
+    if (A.model == 0) fit += A.theta * A.d64[(long long)i * m + j];
+    double v = -dl * (fit + area);
+    if (i + 1 < n) v += s * mg_face64(p0, P(i + 1, j), P(i, jp), P(i + 1, jp), P(i, jm), P(i + 1, jm), W(i, j), W(i + 1, j), A.e2) * (P(i + 1, j) - p0);
+    if (i > 0) v += s * mg_face64(P(i - 1, j), p0, P(i - 1, jp), P(i, jp), P(i - 1, jm), P(i, jm), W(i - 1, j), W(i, j), A.e2) * (P(i - 1, j) - p0);
+    if (j + 1 < m) v += s * mg_face64(p0, P(i, j + 1), P(ip, j), P(ip, j + 1), P(im, j), P(im, j + 1), W(i, j), W(i, j + 1), A.e2) * (P(i, j + 1) - p0);
+    if (j > 0) v += s * mg_face64(P(i, j - 1), p0, P(ip, j - 1), P(ip, j), P(im, j - 1), P(im, j), W(i, j - 1), W(i, j), A.e2) * (P(i, j - 1) - p0);
+    return v;
+}
+
+__device__ float cell_N32_of64(const Res64Args &A, int i, int j, float area)
+{
+    const int n = A.n, m = A.m;
+    int im = mg_mirror(i - 1, n), ip = mg_mirror(i + 1, n), jm = mg_mirror(j - 1, m), jp = mg_mirror(j + 1, m);
+    auto P = [&](int a, int b) { return (float)A.phi64[(long long)a * m + b]; };
+    auto W = [&](int a, int b) { return A.w32[(long long)a * A.p32 + b]; };
+    float p0 = P(i, j);
+    float dl = A.scaled ? 1.0f : mg_delta(p0, (float)A.eps);
+    float s = (float)A.kap * dl;
+    float e2 = (float)A.e2;
+    float v = -dl * (A.fit32[(long long)i * A.p32 + j] + area);
+    if (i + 1 < n) v += s * mg_face(p0, P(i + 1, j), P(i, jp), P(i + 1, jp), P(i, jm), P(i + 1, jm), W(i, j), W(i + 1, j), e2) * (P(i + 1, j) - p0);
+    if (i > 0) v += s * mg_face(P(i - 1, j), p0, P(i - 1, jp), P(i, jp), P(i - 1, jm), P(i, jm), W(i - 1, j), W(i, j), e2) * (P(i - 1, j) - p0);
+    if (j + 1 < m) v += s * mg_face(p0, P(i, j + 1), P(ip, j), P(ip, j + 1), P(im, j), P(im, j + 1), W(i, j), W(i, j + 1), e2) * (P(i, j + 1) - p0);
+    if (j > 0) v += s * mg_face(P(i, j - 1), p0, P(ip, j - 1), P(ip, j), P(im, j - 1), P(im, j), W(i, j - 1), W(i, j), e2) * (P(i, j - 1) - p0);
+    return v;
+}
+
+__global__ void k_res64(Res64Args A)
+{
+    __shared__ double red[256];
+    int j = blockIdx.x * blockDim.x + threadIdx.x, i = blockIdx.y, tid = threadIdx.x;
+    double acc = 0.0;
+    if (j < A.m && i < A.n) {
+        double c1 = A.c12[0], c2 = A.c12[1];
+        double area = A.area ? *A.area : 0.0;
+        double N = cell_N64(A, i, j, c1, c2, area);
+        double r = -N;
+        double ph = A.phi64[(long long)i * A.m + j];
+        double rp = r;
+        if ((ph >= A.M && rp < 0.0) || (ph <= -A.M && rp > 0.0)) rp = 0.0;
+        acc = rp * rp;
+        long long q = (long long)i * A.p32 + j;
+        A.phi32[q] = (float)ph;
+        if (A.Ft) A.Ft[q] = cell_N32_of64(A, i, j, (float)area) + (float)r;
+    }
+    red[tid] = acc;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (tid < s) red[tid] += red[tid + s];
+        __syncthreads();
+    }
+    if (tid == 0) A.partial[(long long)blockIdx.y * gridDim.x + blockIdx.x] = red[0];
+}
+
+// phi64 <- clip(phi64 + (phi32_new - fl32(phi64)), -M, M); a cell that the
+// FP32 cycle left exactly at a bound is put exactly at that bound, so that the
+// projection of the FP64 residual sees it there.
+__global__ void k_defect_update(double *phi64, const float *phi32, int p32, int n, int m, double M)
+{
+    int j = blockIdx.x * blockDim.x + threadIdx.x, i = blockIdx.y;
+    if (j >= m || i >= n) return;
+    long long q = (long long)i * m + j;
+    double v = phi64[q];
+    float p = phi32[(long long)i * p32 + j];
+    v += (double)p - (double)(float)v;
+    if ((double)p >= M) v = M;
+    if ((double)p <= -M) v = -M;
+    phi64[q] = v < -M ? -M : (v > M ? M : v);
+}
+
+// phi64 <- phi32 (pure FP32 mode keeps the finest state in FP32)
+__global__ void k_copy32to64(const float *phi32, int p32, double *phi64, int n, int m)
+{
+    int j = blockIdx.x * blockDim.x + threadIdx.x, i = blockIdx.y;
+    if (j >= m || i >= n) return;
+    phi64[(long long)i * m + j] = (double)phi32[(long long)i * p32 + j];
+}
+
+__global__ void k_set_phi0(const float *src, int ps, double M, double *phi64, float *phi32, int p32, int n, int m)
+{
+    int j = blockIdx.x * blockDim.x + threadIdx.x, i = blockIdx.y;
+    if (j >= m || i >= n) return;
+    double v = (double)src[(long long)i * ps + j];
+    v = v < -M ? -M : (v > M ? M : v);
+    phi64[(long long)i * m + j] = v;
+    phi32[(long long)i * p32 + j] = (float)v;
+}
+
+__global__ void k_out_phi(const double *phi64, int n, int m, double *out, int po)
+{
+    int j = blockIdx.x * blockDim.x + threadIdx.x, i = blockIdx.y;
+    if (j >= m || i >= n) return;
+    out[(long long)i * po + j] = phi64[(long long)i * m + j];
+}
+__global__ void k_out_mask(const double *phi64, int n, int m, uint8_t *out, int po)
+{
+    int j = blockIdx.x * blockDim.x + threadIdx.x, i = blockIdx.y;
+    if (j >= m || i >= n) return;
+    out[(long long)i * po + j] = phi64[(long long)i * m + j] > 0.0 ? 1 : 0;
+}
+
+// relative change of the paper's stopping rule: sum (phi - prev)^2, sum prev^2
+__global__ void k_eta(const double *phi64, const double *prev, long long N, double *partial)
+{
+    __shared__ double r0[256], r1[256];
+    int tid = threadIdx.x;
+    double a0 = 0.0, a1 = 0.0;
+    for (long long t = (long long)blockIdx.x * blockDim.x + tid; t < N; t += (long long)gridDim.x * blockDim.x) {
+        double d = phi64[t] - prev[t];
+        a0 += d * d; a1 += prev[t] * prev[t];
+    }
+    r0[tid] = a0; r1[tid] = a1;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (tid < s) { r0[tid] += r0[tid + s]; r1[tid] += r1[tid + s]; }
+        __syncthreads();
+    }
+    if (tid == 0) { partial[2 * blockIdx.x] = r0[0]; partial[2 * blockIdx.x + 1] = r1[0]; }
+}
+
+// ==========================================================================
+// 1x1 coarsest grid: N = -delta(phi)(fit + s(phi)) has no stencil (S = 0);
+// the box-constrained scalar equation N(phi) = F is solved directly: among
+// its solutions (interior roots, or a bound where the residual pushes
+// outward) the one nearest the current value (FP64, one thread).
+struct ScalarArgs {
+    float *phi; const float *F, *fit, *lo, *hi;
+    double h2, A1, nu, eps, M;
+    int model, scaled;
+};
+__device__ double scalar_r(const ScalarArgs &S, double phi)
+{
+    double s = 0.0;
+    if (S.model == 1) s = 2.0 * S.nu * (S.h2 * mg_heav64(phi, S.eps) - S.A1);
+    double dl = S.scaled ? 1.0 : mg_delta64(phi, S.eps);
+    double N = -dl * ((double)S.fit[0] + s);
+    return (double)S.F[0] - N;
+}
+__global__ void k_scalar_solve(ScalarArgs S)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double lo = S.lo ? (double)S.lo[0] : -S.M, hi = S.hi ? (double)S.hi[0] : S.M;
+    double cur = (double)S.phi[0], best = cur, bestd = 1e300;
+    const int NS = 4096;
+    if (scalar_r(S, lo) >= 0.0) { best = lo; bestd = fabs(cur - lo); }
+    if (scalar_r(S, hi) <= 0.0 && fabs(hi - cur) < bestd) { best = hi; bestd = fabs(hi - cur); }
+    double a = lo, ra = scalar_r(S, a);
+    for (int t = 1; t <= NS && hi > lo; t++) {
+        double b = lo + (hi - lo) * t / NS, rb = scalar_r(S, b);
+        double root = 0.0;
+        bool found = false;
+        if (ra == 0.0) { root = a; found = true; }
+        else if (rb != 0.0 && ((ra < 0.0) != (rb < 0.0))) {
+            double x0 = a, x1 = b, r0 = ra;
+            for (int it = 0; it < 200; it++) {
+                double mid = 0.5 * (x0 + x1);
+                if (mid <= x0 || mid >= x1) break;
+                double rm = scalar_r(S, mid);
+                if (rm == 0.0) { x0 = x1 = mid; break; }
+                if ((rm < 0.0) == (r0 < 0.0)) { x0 = mid; r0 = rm; } else x1 = mid;
+            }
+            root = 0.5 * (x0 + x1); found = true;
+        }
+        if (found && fabs(root - cur) < bestd) { bestd = fabs(root - cur); best = root; }
+        a = b; ra = rb;
+    }
+    if (ra == 0.0 && fabs(a - cur) < bestd) best = a;
+    S.phi[0] = (float)best;
+}

@@ -1,0 +1,222 @@
+"""Python binding of libmgseg (argument marshalling only).
+
+Every step of the solver runs in the library's HIP kernels; PyTorch supplies
+device memory and the stream.  The binding fails loudly when the built
+library is missing: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, fields
+
+import numpy as np
+import torch
+
+from . import build as _build
+
+FIELD = {"z": 0, "d": 1, "w": 2, "fit": 3, "phi": 4, "F": 5, "lo": 6, "hi": 7, "g": 8, "phi64": 9,
+         "labels": 10, "r": 11}
+OP = {"freeze": 0, "sweep_A": 1, "sweep_B": 2, "sweep_C": 3, "sweep_D": 4, "smooth": 5, "coarsest": 6,
+      "vcycle_from": 7, "residual": 8, "update_c": 9}
+
+STATUS = {0: "ok", 1: "invalid argument", 2: "shape", 3: "out of device memory", 4: "HIP error",
+          5: "non-finite residual", 6: "not converged", 7: "invalid state"}
+
+
+class MgsegError(RuntimeError):
+    def __init__(self, code, where):
+        super().__init__(f"{where}: {STATUS.get(code, code)} ({code})")
+        self.code = code
+
+
+class _Params(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("model", C.c_int32), ("mu", C.c_double),
+                ("lambda1", C.c_double), ("lambda2", C.c_double), ("theta", C.c_double),
+                ("nu", C.c_double), ("eps", C.c_double), ("eps_tv_px", C.c_double),
+                ("beta", C.c_double), ("sigma_g", C.c_double), ("sigma_d", C.c_double),
+                ("Sigma", C.c_double), ("M", C.c_double), ("nu1", C.c_int32), ("nu2", C.c_int32),
+                ("levels", C.c_int32), ("coarse_iters", C.c_int32), ("mixed_precision", C.c_int32),
+                ("scaled", C.c_int32)]
+
+
+class _Stats(C.Structure):
+    _fields_ = [("c1", C.c_double), ("c2", C.c_double), ("rel_res", C.c_double), ("res", C.c_double),
+                ("res0", C.c_double), ("eta", C.c_double), ("cycles", C.c_int32), ("levels", C.c_int32),
+                ("frac_fg", C.c_double)]
+
+
+@dataclass
+class Params:
+    model: int = 0
+    mu: float = 0.5
+    lambda1: float = 6.5025
+    lambda2: float = 6.5025
+    theta: float = 4.0
+    nu: float = 1.0
+    eps: float = 1.0
+    eps_tv_px: float = 1.0
+    beta: float = 1.0
+    sigma_g: float = 1.0
+    sigma_d: float = 0.1
+    Sigma: float = 2.0
+    M: float = 4.0
+    nu1: int = 2
+    nu2: int = 2
+    levels: int = 0
+    coarse_iters: int = 100
+    mixed_precision: int = 1
+    scaled: int = 0
+
+    def to_c(self) -> _Params:
+        p = _Params()
+        p.struct_size = C.sizeof(_Params)
+        for f in fields(self):
+            setattr(p, f.name, getattr(self, f.name))
+        return p
+
+
+_lib = None
+
+
+def lib():
+    """Load the built library (after torch, so that one HIP runtime serves both)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB):
+            raise RuntimeError(f"libmgseg not built ({_build.LIB}); run __graft_entry__.build()")
+        L = C.CDLL(_build.LIB)
+        vp, dp, ip = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int)
+        L.mgseg_params_default.argtypes = [C.POINTER(_Params)]
+        L.mgseg_strerror.restype = C.c_char_p
+        L.mgseg_strerror.argtypes = [C.c_int]
+        L.mgseg_setup.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_float), C.c_int,
+                                  C.POINTER(_Params), vp, C.POINTER(vp)]
+        L.mgseg_set_phi0.argtypes = [vp, vp, C.c_int]
+        L.mgseg_vcycle.argtypes = [vp, dp]
+        L.mgseg_solve.argtypes = [vp, C.c_double, C.c_int, ip, dp]
+        L.mgseg_get_phi.argtypes = [vp, vp, C.c_int]
+        L.mgseg_get_mask.argtypes = [vp, vp, C.c_int]
+        L.mgseg_get_stats.argtypes = [vp, C.POINTER(_Stats)]
+        L.mgseg_destroy.argtypes = [vp]
+        L.mgseg_destroy.restype = None
+        L.mgseg_level_shape.argtypes = [vp, C.c_int, ip, ip, dp]
+        L.mgseg_debug_get.argtypes = [vp, C.c_int, C.c_int, vp]
+        L.mgseg_debug_set.argtypes = [vp, C.c_int, C.c_int, vp]
+        L.mgseg_debug_scalars.argtypes = [vp, dp]
+        L.mgseg_debug_set_c.argtypes = [vp, C.c_double, C.c_double]
+        L.mgseg_debug_op.argtypes = [vp, C.c_int, C.c_int, C.c_int]
+        for name in ("mgseg_setup", "mgseg_set_phi0", "mgseg_vcycle", "mgseg_solve", "mgseg_get_phi",
+                     "mgseg_get_mask", "mgseg_get_stats", "mgseg_level_shape", "mgseg_debug_get",
+                     "mgseg_debug_set", "mgseg_debug_scalars", "mgseg_debug_set_c", "mgseg_debug_op"):
+            getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(code, where):
+    if code != 0:
+        raise MgsegError(code, where)
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+class Solver:
+    """One image: setup, V-cycles, solve, results (all work on the GPU)."""
+
+    def __init__(self, image, markers, params: Params | None = None, stream=None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("mgseg needs a GPU (HIP device)")
+        self.L = lib()
+        self.params = params or Params()
+        img = torch.as_tensor(image, dtype=torch.float32)
+        if img.device.type != "cuda":
+            img = img.to("cuda")
+        img = img.contiguous()
+        self.n, self.m = img.shape
+        mk = np.ascontiguousarray(np.asarray(markers, np.float32).reshape(-1, 2))
+        self._p = self.params.to_c()
+        self.stream = stream or torch.cuda.current_stream()
+        ctx = C.c_void_p()
+        _check(self.L.mgseg_setup(C.c_void_p(img.data_ptr()), self.n, self.m, self.m,
+                                  mk.ctypes.data_as(C.POINTER(C.c_float)), len(mk), C.byref(self._p),
+                                  _stream_ptr(self.stream), C.byref(ctx)), "mgseg_setup")
+        self.ctx = ctx
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.L.mgseg_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def vcycle(self) -> float:
+        rel = C.c_double()
+        _check(self.L.mgseg_vcycle(self.ctx, C.byref(rel)), "mgseg_vcycle")
+        return rel.value
+
+    def solve(self, tol=1e-6, max_cycles=50, raise_on_nonconv=False):
+        cyc, rel = C.c_int(), C.c_double()
+        code = self.L.mgseg_solve(self.ctx, tol, max_cycles, C.byref(cyc), C.byref(rel))
+        if code not in (0, 6) or (code == 6 and raise_on_nonconv):
+            raise MgsegError(code, "mgseg_solve")
+        return cyc.value, rel.value, code == 0
+
+    def set_phi0(self, phi):
+        t = torch.as_tensor(phi, dtype=torch.float32, device="cuda").contiguous()
+        _check(self.L.mgseg_set_phi0(self.ctx, C.c_void_p(t.data_ptr()), self.m), "mgseg_set_phi0")
+
+    def phi(self) -> torch.Tensor:
+        out = torch.empty((self.n, self.m), dtype=torch.float64, device="cuda")
+        _check(self.L.mgseg_get_phi(self.ctx, C.c_void_p(out.data_ptr()), self.m), "mgseg_get_phi")
+        return out
+
+    def mask(self) -> torch.Tensor:
+        out = torch.empty((self.n, self.m), dtype=torch.uint8, device="cuda")
+        _check(self.L.mgseg_get_mask(self.ctx, C.c_void_p(out.data_ptr()), self.m), "mgseg_get_mask")
+        return out
+
+    def stats(self) -> dict:
+        s = _Stats()
+        _check(self.L.mgseg_get_stats(self.ctx, C.byref(s)), "mgseg_get_stats")
+        return {f[0]: getattr(s, f[0]) for f in _Stats._fields_}
+
+    # ---- single steps (tests, profiling)
+    def shape(self, level=0):
+        n, m, h = C.c_int(), C.c_int(), C.c_double()
+        _check(self.L.mgseg_level_shape(self.ctx, level, C.byref(n), C.byref(m), C.byref(h)), "level_shape")
+        return n.value, m.value, h.value
+
+    def get(self, name, level=0) -> np.ndarray:
+        n, m, _ = self.shape(level)
+        f = FIELD[name]
+        dt = np.float64 if f in (8, 9) else (np.uint8 if f == 10 else np.float32)
+        out = np.zeros((n, m), dt)
+        _check(self.L.mgseg_debug_get(self.ctx, level, f, out.ctypes.data_as(C.c_void_p)), f"get {name}")
+        return out
+
+    def set(self, name, arr, level=0):
+        n, m, _ = self.shape(level)
+        f = FIELD[name]
+        dt = np.float64 if f in (8, 9) else (np.uint8 if f == 10 else np.float32)
+        a = np.ascontiguousarray(np.asarray(arr).reshape(n, m), dt)
+        _check(self.L.mgseg_debug_set(self.ctx, level, f, a.ctypes.data_as(C.c_void_p)), f"set {name}")
+
+    def scalars(self) -> dict:
+        out = np.zeros(5)
+        _check(self.L.mgseg_debug_scalars(self.ctx, out.ctypes.data_as(C.POINTER(C.c_double))), "scalars")
+        return dict(c1=out[0], c2=out[1], A1=out[2], res0=out[3], h0=out[4])
+
+    def set_c(self, c1, c2):
+        _check(self.L.mgseg_debug_set_c(self.ctx, c1, c2), "set_c")
+
+    def op(self, name, level=0, arg=0):
+        _check(self.L.mgseg_debug_op(self.ctx, level, OP[name], arg), f"op {name}")

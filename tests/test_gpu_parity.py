@@ -1,0 +1,129 @@
+"""GPU parity against the FP64 CPU oracle (config-1 sized inputs).
+
+Every test drives the HIP library through its C ABI (Python ctypes binding)
+and the oracle on the same seeded synthetic input.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from oracle import Oracle, OracleParams  # noqa: E402
+from paper_1807_02137_amd import mgseg, synth  # noqa: E402
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def make(seed=1000, levels=6, **kw):
+    inst = synth.config1(seed)
+    s = mgseg.Solver(inst.image, inst.markers, mgseg.Params(levels=levels, **kw))
+    o = Oracle(inst.image, inst.markers, OracleParams(levels=levels, **kw))
+    return inst, s, o
+
+
+def test_setup_maps():
+    say("case setup_maps seed 1000")
+    inst, s, o = make()
+    g_gpu, g_or = s.get("g"), o.get("g")
+    assert np.abs(g_gpu - g_or).max() <= 1e-12 * max(1.0, np.abs(g_or).max())
+    assert np.abs(s.get("phi64") - o.get("phi")).max() <= 1e-12
+    for f in ("w", "d", "z"):
+        a, b = s.get(f), o.get(f)
+        assert np.abs(a - b).max() <= 1e-6 * max(1.0, np.abs(b).max()), f
+    for l in range(1, 6):
+        a, b = s.get("w", l), o.get("w", l)
+        assert np.abs(a - b).max() <= 1e-6 * max(1.0, np.abs(b).max()), l
+    sg, so = s.scalars(), o.scalars()
+    assert abs(sg["A1"] - so["A1"]) <= 1e-14
+    assert abs(sg["c1"] - so["c1"]) <= 1e-12 and abs(sg["c2"] - so["c2"]) <= 1e-12
+    assert abs(sg["res0"] - so["res0"]) <= 1e-9 * so["res0"]
+    s.close()
+
+
+def test_labels_match():
+    say("case labels seed 1000")
+    inst, s, o = make()
+    s.op("freeze", 0)
+    o.freeze(0)
+    lg, lo = s.get("labels"), o.labels()
+    mism = int((lg != lo).sum())
+    say("label mismatches", mism, "of", lg.size, "jump-set fraction", float((lo > 0).mean()))
+    assert mism <= 2
+    s.close()
+
+
+@pytest.mark.parametrize("sweep", [0, 1, 2, 3])
+def test_single_sweep(sweep):
+    say("case single sweep", "ABCD"[sweep])
+    inst, s, o = make()
+    # move away from the initial state: a few oracle outer iterations
+    o.smooth(2, 0)
+    phi = o.get("phi")
+    s.set("phi", phi.astype(np.float32))
+    o.set("phi", phi.astype(np.float32).astype(np.float64))
+    s.op("freeze", 0)
+    o.freeze(0)
+    s.set("labels", o.labels())
+    s.op(["sweep_A", "sweep_B", "sweep_C", "sweep_D"][sweep], 0)
+    o.sweep(sweep, 0)
+    d = np.abs(s.get("phi").astype(np.float64) - o.get("phi"))
+    say("max |dphi|", d.max(), "runs in sweep", int(((o.labels() >> sweep) & 1).sum()))
+    assert d.max() <= 2e-4
+    s.close()
+
+
+def test_residual_fp32():
+    say("case residual")
+    inst, s, o = make()
+    s.op("residual", 0)
+    rg, ro = s.get("r").astype(np.float64), o.residual(0, True)
+    scale = np.abs(ro).max()
+    say("max |dr|", np.abs(rg - ro).max(), "scale", scale)
+    assert np.abs(rg - ro).max() <= 1e-4 * scale
+    s.close()
+
+
+def test_vcycle_trajectory():
+    say("case vcycle trajectory seed 1000")
+    inst, s, o = make()
+    for k in range(3):
+        rg = s.vcycle()
+        ro, _ = o.vcycle()
+        pg, po = s.get("phi64"), o.get("phi")
+        flips = int(((pg > 0) != (po > 0)).sum())
+        say(f"cycle {k}: rel gpu {rg:.3e} oracle {ro:.3e} max|dphi| {np.abs(pg - po).max():.3e} flips {flips}")
+    assert flips <= 2
+    s.close()
+
+
+@pytest.mark.parametrize("seed", [1000, 1001, 1002])
+def test_solve_parity(seed):
+    say("case solve seed", seed)
+    inst, s, o = make(seed)
+    hg = []
+    for _ in range(40):
+        hg.append(s.vcycle())
+        if hg[-1] <= 1e-6:
+            break
+    cyc, rel, ok = len(hg), hg[-1], hg[-1] <= 1e-6
+    k, hist = o.solve(1e-6, 40)
+    say("gpu history", " ".join(f"{x:.1e}" for x in hg))
+    say("oracle history", " ".join(f"{x:.1e}" for x in hist))
+    pg, po = s.phi().cpu().numpy(), o.get("phi")
+    agree = (pg > 0) == (po > 0)
+    flips = int((~agree).sum())
+    dmax = float(np.abs(pg - po)[agree].max())
+    say(f"seed {seed}: gpu {cyc} cycles rel {rel:.2e}; oracle {k} cycles; flips {flips} max|dphi| {dmax:.3e}")
+    assert ok and k > 0
+    assert flips <= max(1, int(1e-4 * pg.size))
+    assert dmax <= 1e-4
+    s.close()
