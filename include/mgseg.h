@@ -63,7 +63,7 @@ typedef struct {
     double nu;              /* Rada-Chen area weight (eq. rcfunc)                    */
     double eps;             /* smoothed Heaviside width, in phi units (Sec. 2)       */
     double eps_tv_px;       /* |grad phi| regularisation, phi units per pixel        */
-    double beta;            /* edge detector g(s) = 1/(1 + beta s) (Sec. 2.2)        */
+    double beta;            /* edge detector g(s) = 1/(1 + beta s), s per pixel      */
     double sigma_g;         /* pre-blur of z for the edge detector, pixels           */
     double sigma_d;         /* width of the marker distance function, domain units   */
     double Sigma;           /* jump threshold on the coefficient ratio (Sec. 5.2)    */
@@ -156,6 +156,19 @@ mgseg_status mgseg_debug_set_c(mgseg_ctx *c, double c1, double c2);
  *       debug_get with field 11 = residual),
  *     9 c1, c2 refresh from the finest phi and fit maps of every level. */
 mgseg_status mgseg_debug_op(mgseg_ctx *c, int level, int op, int arg);
+
+/* ------------------------------------------------------------------------
+ * Kernel timing with HIP events recorded on the context's stream around each
+ * launch of one kernel class (kernel 0 = the finest-grid directional sweep
+ * of Hybrid Smoother 2).  mgseg_profile(enable = 1) clears earlier records
+ * and starts recording; enable = 0 stops.  mgseg_profile_read synchronises
+ * the stream and returns the summed elapsed time, the number of timed
+ * launches and the compulsory HBM bytes of one launch (cells x bytes per
+ * cell read and written once).
+ * ---------------------------------------------------------------------- */
+mgseg_status mgseg_profile(mgseg_ctx *c, int kernel, int enable);
+mgseg_status mgseg_profile_read(mgseg_ctx *c, int kernel, double *total_ms, int *count,
+                                double *bytes_per_launch);
 
 #ifdef __cplusplus
 }

@@ -48,7 +48,7 @@ class OracleParams:
     nu: float = 1.0
     eps: float = 1.0
     eps_tv_px: float = 1.0
-    beta: float = 1.0
+    beta: float = 16384.0
     sigma_g: float = 1.0
     sigma_d: float = 0.1
     Sigma: float = 2.0
@@ -60,7 +60,7 @@ class OracleParams:
     order: int = 1            # 0 paper lexicographic lines, 1 four-class line order
     smoother: int = 0         # 0 Hybrid Smoother 2, 1 GSLEX-I
     obstacle: int = 1         # 1 coarse corrections bounded by the fine slack
-    scaled: int = 0
+    scaled: int = 1           # 1 each row divided by delta_eps(psi_ij) > 0
 
     def to_c(self) -> _Params:
         p = _Params()

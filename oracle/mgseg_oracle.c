@@ -33,7 +33,7 @@ typedef struct {
     double mu, lambda1, lambda2, theta, nu;
     double eps;         /* smoothed-Heaviside width (Sec. 2, eps = 1)              */
     double eps_tv_px;   /* |grad phi| regularisation, in phi units per pixel       */
-    double beta;        /* edge detector g(s) = 1/(1 + beta s)   (Sec. 2.2)        */
+    double beta;        /* edge detector g(s) = 1/(1 + beta s), s per pixel (Sec. 2.2) */
     double sigma_g;     /* Gaussian pre-blur of z for g, in pixels                 */
     double sigma_d;     /* marker distance function width, domain units (Sec. 2.2) */
     double Sigma;       /* jump threshold: max/min coefficient ratio (Sec. 5.2)    */
@@ -246,8 +246,8 @@ static double hull_area(const double *hull, int hv)
 
 /* Static maps of the finest grid.
  *  g  : edge detector g = 1/(1 + beta |grad(G_sigma * z)|^2) (Sec. 2.2, with
- *       the Gaussian pre-blur of the image; gradient by central differences in
- *       domain units, mirror boundary);
+ *       the Gaussian pre-blur of the image; gradient by central differences per
+ *       pixel, mirror boundary, so that beta does not depend on the resolution);
  *  d  : marker distance function, the product over markers of
  *       1 - exp(-((x_k - x)^2 + (y_k - y)^2)/(2 sigma^2)) (Sec. 2.2);
  *  w  : weight inside the curvature term: g for Spencer-Chen (eq. scel),
@@ -283,8 +283,8 @@ void or_setup_maps(const double *z, int n, int m, const double *markers, int k,
         }
     for (int i = 0; i < n; i++)
         for (int j = 0; j < m; j++) {
-            double gx = (zb[(size_t)i * m + mirror(j + 1, m)] - zb[(size_t)i * m + mirror(j - 1, m)]) / (2.0 * h0);
-            double gy = (zb[(size_t)mirror(i + 1, n) * m + j] - zb[(size_t)mirror(i - 1, n) * m + j]) / (2.0 * h0);
+            double gx = (zb[(size_t)i * m + mirror(j + 1, m)] - zb[(size_t)i * m + mirror(j - 1, m)]) / 2.0;
+            double gy = (zb[(size_t)mirror(i + 1, n) * m + j] - zb[(size_t)mirror(i - 1, n) * m + j]) / 2.0;
             g[(size_t)i * m + j] = 1.0 / (1.0 + p->beta * (gx * gx + gy * gy));
         }
     double hull[128];
@@ -568,7 +568,8 @@ static int tridiag(int len, const double *lo0, const double *di0, const double *
  * bl_k <= x_k <= bh_k; a row may hold x_k at a bound only where its residual
  * pushes outward.  Active-set iteration: free cells solved exactly with held
  * cells as known values; free cells outside the box are held, held cells whose
- * residual turns inward are released; until the held set is stable.
+ * residual turns inward (beyond rounding) are released; until the held set is
+ * stable (at most 2 len + 4 passes).
  * Returns 0 on a zero pivot.  lo_0 and up_{len-1} are ignored. */
 int or_box_tridiag(int len, const double *lo, const double *di, const double *up, const double *rh,
                    const double *bl, const double *bh, double *x)
@@ -576,7 +577,7 @@ int or_box_tridiag(int len, const double *lo, const double *di, const double *up
     double *l2 = dalloc(len), *d2 = dalloc(len), *u2 = dalloc(len), *r2 = dalloc(len), *y = dalloc(len);
     int *held = (int *)calloc((size_t)len, sizeof(int)), *map = (int *)malloc(sizeof(int) * (size_t)(len + 1));
     int ok = 1;
-    for (int it = 0; ok && it < 4 * len + 8; it++) {
+    for (int it = 0; ok && it < 2 * len + 4; it++) {
         int nf = 0;
         for (int k = 0; k < len; k++) {
             if (held[k]) { x[k] = held[k] > 0 ? bh[k] : bl[k]; continue; }
@@ -605,10 +606,15 @@ int or_box_tridiag(int len, const double *lo, const double *di, const double *up
                 else if (x[k] < bl[k]) { held[k] = -1; changed = 1; }
             } else {
                 double v = di[k] * x[k] - rh[k];
-                if (k > 0) v += lo[k] * x[k - 1];
-                if (k < len - 1) v += up[k] * x[k + 1];
-                /* v = row value minus rhs; the point update moves x_k by -v / di_k */
-                if ((held[k] == 1 && v < 0.0) || (held[k] == -1 && v > 0.0)) { held[k] = 0; changed = 1; }
+                double mag = fabs(di[k] * x[k]) + fabs(rh[k]);
+                if (k > 0) { v += lo[k] * x[k - 1]; mag += fabs(lo[k] * x[k - 1]); }
+                if (k < len - 1) { v += up[k] * x[k + 1]; mag += fabs(up[k] * x[k + 1]); }
+                /* v = row value minus rhs; the point update moves x_k by -v / di_k.
+                 * A held cell is released only when its residual points inward
+                 * by more than rounding, so that the hold / release iteration
+                 * cannot alternate on a cell whose free value is the bound. */
+                double tau = 1e-12 * mag;
+                if ((held[k] == 1 && v < -tau) || (held[k] == -1 && v > tau)) { held[k] = 0; changed = 1; }
             }
         }
         if (!changed) break;
@@ -916,9 +922,9 @@ double or_res_norm(or_ctx *c)
 void or_params_default(or_params *p)
 {
     p->model = 0; p->mu = 0.5; p->lambda1 = 6.5025; p->lambda2 = 6.5025;
-    p->theta = 4.0; p->nu = 1.0; p->eps = 1.0; p->eps_tv_px = 1.0; p->beta = 1.0;
+    p->theta = 4.0; p->nu = 1.0; p->eps = 1.0; p->eps_tv_px = 1.0; p->beta = 16384.0;
     p->sigma_g = 1.0; p->sigma_d = 0.1; p->Sigma = 2.0; p->M = 4.0;
-    p->nu1 = 2; p->nu2 = 2; p->levels = 1; p->coarse_iters = 100; p->order = 1; p->smoother = 0; p->obstacle = 1; p->scaled = 0;
+    p->nu1 = 2; p->nu2 = 2; p->levels = 1; p->coarse_iters = 100; p->order = 1; p->smoother = 0; p->obstacle = 1; p->scaled = 1;
 }
 
 or_ctx *or_create(const double *z, int n, int m, const double *markers, int k, const or_params *p)

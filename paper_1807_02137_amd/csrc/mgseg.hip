@@ -57,6 +57,11 @@ struct mgseg_ctx {
     std::vector<void *> allocs;
     hipError_t err = hipSuccess;
     bool oom = false;
+    // event timing of the finest-grid sweep launches
+    bool prof_on = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used;
+    size_t ev_next = 0;
 };
 
 namespace {
@@ -126,6 +131,9 @@ double host_area(const std::vector<double> &h, int hv)
     }
     return 0.5 * std::fabs(s);
 }
+
+// the finest grid holds the FP32 deviation from the FP64 iterate
+inline bool dev0(const mgseg_ctx *c, int l) { return l == 0 && c->p.mixed_precision; }
 
 float lev_e2(const mgseg_ctx *c, int l)
 {
@@ -222,8 +230,9 @@ void launch_sweep(mgseg_ctx *c, int l, int s, const float *phi_old, float *phi_n
     A.fit = cm ? L.fit_cm : L.fit;
     A.F = L.has_F ? (cm ? L.F_cm : L.F) : nullptr;
     A.lab = cm ? L.lab_cm : L.lab;
-    A.lo = l > 0 ? (cm ? L.lo_cm : L.lo) : nullptr;
-    A.hi = l > 0 ? (cm ? L.hi_cm : L.hi) : nullptr;
+    const bool bnd = l > 0 || dev0(c, l);
+    A.lo = bnd ? (cm ? L.lo_cm : L.lo) : nullptr;
+    A.hi = bnd ? (cm ? L.hi_cm : L.hi) : nullptr;
     A.scr = c->scr; A.scr_field = c->scr_field;
     A.area = c->p.model == 1 ? c->dsc + DS_AREA_FRZ : nullptr;
     A.pitch = cm ? L.pcm : L.prm;
@@ -239,20 +248,40 @@ void launch_sweep(mgseg_ctx *c, int l, int s, const float *phi_old, float *phi_n
         if (c->err == hipSuccess) c->err = hipErrorInvalidValue;
         return;
     }
+    const size_t lds = sweep_lds_bytes(ml);
 #define MG_SWEEP(NT, K)                                                                                  \
     do {                                                                                                 \
-        if (rev) hipLaunchKernelGGL((k_sweep<NT, K, true>), dim3(bands), dim3(NT), 0, c->s, A);       \
-        else hipLaunchKernelGGL((k_sweep<NT, K, false>), dim3(bands), dim3(NT), 0, c->s, A);          \
+        if (rev) hipLaunchKernelGGL((k_sweep<NT, K, true>), dim3(bands), dim3(NT), lds, c->s, A);     \
+        else hipLaunchKernelGGL((k_sweep<NT, K, false>), dim3(bands), dim3(NT), lds, c->s, A);        \
     } while (0)
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    bool timed = c->prof_on && l == 0;
+    if (timed) {
+        while (c->ev_pool.size() < c->ev_next + 2) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) { timed = false; break; }
+            c->ev_pool.push_back(e);
+        }
+    }
+    if (timed) {
+        e0 = c->ev_pool[c->ev_next]; e1 = c->ev_pool[c->ev_next + 1];
+        c->ev_next += 2;
+        (void)hipEventRecord(e0, c->s);
+    }
+    // one thread per cell up to 1024-cell lines; longer lines take rounds
     if (ml <= 64) MG_SWEEP(64, 1);
-    else if (ml <= 128) MG_SWEEP(64, 2);
-    else if (ml <= 256) MG_SWEEP(64, 4);
-    else if (ml <= 512) MG_SWEEP(64, 8);
-    else if (ml <= 1024) MG_SWEEP(128, 8);
-    else if (ml <= 2048) MG_SWEEP(256, 8);
-    else if (ml <= 4096) MG_SWEEP(512, 8);
+    else if (ml <= 128) MG_SWEEP(128, 1);
+    else if (ml <= 256) MG_SWEEP(256, 1);
+    else if (ml <= 512) MG_SWEEP(512, 1);
+    else if (ml <= 1024) MG_SWEEP(1024, 1);
+    else if (ml <= 2048) MG_SWEEP(1024, 2);
+    else if (ml <= 4096) MG_SWEEP(1024, 4);
     else MG_SWEEP(1024, 8);
 #undef MG_SWEEP
+    if (timed) {
+        (void)hipEventRecord(e1, c->s);
+        c->ev_used.push_back({e0, e1});
+    }
     chk(c);
 }
 
@@ -260,7 +289,14 @@ void launch_sweep(mgseg_ctx *c, int l, int s, const float *phi_old, float *phi_n
 void freeze(mgseg_ctx *c, int l)
 {
     Level &L = c->lev[l];
-    (void)hipMemcpyAsync(L.psi, L.P[0], sizeof(float) * (size_t)L.n * L.prm, hipMemcpyDeviceToDevice, c->s);
+    if (dev0(c, l)) {
+        hipLaunchKernelGGL(k_freeze0, grid2(L.n, L.m), dim3(256), 0, c->s, c->phi64, L.P[0], L.w, L.prm, L.n, L.m,
+                           (float)(c->p.mu / L.h), lev_e2(c, l), (float)c->p.eps, c->p.scaled, L.psi, L.F);
+        transpose_f(c, L.F, L.prm, L.F_cm, L.pcm, L.n, L.m);
+        L.has_F = true;
+    } else {
+        (void)hipMemcpyAsync(L.psi, L.P[0], sizeof(float) * (size_t)L.n * L.prm, hipMemcpyDeviceToDevice, c->s);
+    }
     transpose_f(c, L.psi, L.prm, L.psi_cm, L.pcm, L.n, L.m);
     hipLaunchKernelGGL(k_labels, grid2(L.n, L.m), dim3(256), 0, c->s, L.psi, L.w, L.prm, L.n, L.m, lev_e2(c, l),
                        (float)c->p.Sigma, L.lab, L.prm);
@@ -300,12 +336,43 @@ void coarsest(mgseg_ctx *c, int l)
         chk(c);
         return;
     }
+    if (L.n <= 64 && L.m <= 64 && !dev0(c, l)) {
+        CoarseArgs C;
+        C.P0 = L.P[0]; C.P1 = L.P[1]; C.P2 = L.P[2]; C.T1 = L.T[1]; C.T2 = L.T[2];
+        C.psi = L.psi; C.psi_cm = L.psi_cm;
+        C.w = L.w; C.w_cm = L.w_cm; C.fit = L.fit; C.fit_cm = L.fit_cm;
+        C.F = L.has_F ? L.F : nullptr; C.F_cm = L.has_F ? L.F_cm : nullptr;
+        C.lo = l > 0 ? L.lo : nullptr; C.lo_cm = l > 0 ? L.lo_cm : nullptr;
+        C.hi = l > 0 ? L.hi : nullptr; C.hi_cm = l > 0 ? L.hi_cm : nullptr;
+        C.lab = L.lab; C.lab_cm = L.lab_cm; C.scr = c->scr; C.scr_field = c->scr_field;
+        C.area = c->p.model == 1 ? c->dsc + DS_AREA_FRZ : nullptr;
+        C.h2 = L.h * L.h; C.A1 = c->A1; C.nu = c->p.nu; C.eps = c->p.eps;
+        C.n = L.n; C.m = L.m; C.prm = L.prm; C.pcm = L.pcm; C.iters = c->p.coarse_iters; C.scaled = c->p.scaled;
+        C.kap = (float)(c->p.mu / L.h); C.e2 = lev_e2(c, l); C.M = (float)c->p.M; C.Sigma = (float)c->p.Sigma;
+        hipLaunchKernelGGL((k_coarse_smooth<64, 1>), dim3(1), dim3(64), 0, c->s, C);
+        chk(c);
+        return;
+    }
     smooth(c, l, c->p.coarse_iters);
 }
 
 void residual(mgseg_ctx *c, int l, float *r, double *partial)
 {
     Level &L = c->lev[l];
+    if (dev0(c, l)) {
+        if (c->p.model == 1) {     // area term at phi = b + d
+            int nb = std::min(RED_BLOCKS, std::max(1, (L.n * L.m + 255) / 256));
+            hipLaunchKernelGGL(k_sums_bd, dim3(nb), dim3(256), 0, c->s, c->phi64, L.P[0], L.prm, L.n, L.m, c->p.eps,
+                               c->part);
+            hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, c->s, c->part, nb, 0, (double)L.n * L.m, L.h * L.h,
+                               c->A1, c->p.nu, c->dsc + DS_AREA_EVAL);
+        }
+        hipLaunchKernelGGL(k_res0, grid2(L.n, L.m), dim3(256), 0, c->s, c->phi64, L.P[0], L.w, L.fit, L.prm, L.n, L.m,
+                           (float)(c->p.mu / L.h), lev_e2(c, l), (float)c->p.eps,
+                           c->p.model == 1 ? c->dsc + DS_AREA_EVAL : nullptr, c->p.scaled, c->p.M, r);
+        chk(c);
+        return;
+    }
     if (c->p.model == 1) area_term(c, l, L.P[0], L.prm, DS_AREA_EVAL);
     hipLaunchKernelGGL(k_residual, grid2(L.n, L.m), dim3(256), 0, c->s, L.P[0], L.w, L.fit,
                        L.has_F ? L.F : nullptr, l > 0 ? L.lo : nullptr, l > 0 ? L.hi : nullptr, L.prm, L.n, L.m,
@@ -322,11 +389,16 @@ void vcycle_from(mgseg_ctx *c, int l0)
         smooth(c, l, c->p.nu1);
         residual(c, l, L.r, nullptr);
         dim3 gc = grid2(Lc.n, Lc.m);
-        hipLaunchKernelGGL(k_restrict, gc, dim3(256), 0, c->s, L.P[0], L.prm, Lc.phic, Lc.prm, Lc.n, Lc.m);
         hipLaunchKernelGGL(k_restrict, gc, dim3(256), 0, c->s, L.r, L.prm, Lc.r, Lc.prm, Lc.n, Lc.m);
-        hipLaunchKernelGGL(k_coarse_bounds, gc, dim3(256), 0, c->s, L.P[0], l > 0 ? L.lo : nullptr,
-                           l > 0 ? L.hi : nullptr, L.prm, L.n, L.m, Lc.phic, Lc.lo, Lc.hi, Lc.prm, Lc.n, Lc.m,
-                           (float)c->p.M);
+        if (dev0(c, l)) {
+            hipLaunchKernelGGL(k_restrict0, gc, dim3(256), 0, c->s, c->phi64, L.P[0], L.prm, L.n, L.m, Lc.phic,
+                               Lc.lo, Lc.hi, Lc.prm, Lc.n, Lc.m, c->p.M);
+        } else {
+            hipLaunchKernelGGL(k_restrict, gc, dim3(256), 0, c->s, L.P[0], L.prm, Lc.phic, Lc.prm, Lc.n, Lc.m);
+            hipLaunchKernelGGL(k_coarse_bounds, gc, dim3(256), 0, c->s, L.P[0], l > 0 ? L.lo : nullptr,
+                               l > 0 ? L.hi : nullptr, L.prm, L.n, L.m, Lc.phic, Lc.lo, Lc.hi, Lc.prm, Lc.n, Lc.m,
+                               (float)c->p.M);
+        }
         transpose_f(c, Lc.lo, Lc.prm, Lc.lo_cm, Lc.pcm, Lc.n, Lc.m);
         transpose_f(c, Lc.hi, Lc.prm, Lc.hi_cm, Lc.pcm, Lc.n, Lc.m);
         if (c->p.model == 1) area_term(c, l + 1, Lc.phic, Lc.prm, DS_AREA_EVAL);
@@ -340,8 +412,9 @@ void vcycle_from(mgseg_ctx *c, int l0)
     coarsest(c, c->L - 1);
     for (int l = c->L - 2; l >= l0; l--) {
         Level &L = c->lev[l], &Lc = c->lev[l + 1];
-        hipLaunchKernelGGL(k_prolong_correct, grid2(L.n, L.m), dim3(256), 0, c->s, L.P[0], l > 0 ? L.lo : nullptr,
-                           l > 0 ? L.hi : nullptr, L.prm, L.n, L.m, Lc.P[0], Lc.phic, Lc.prm, (float)c->p.M);
+        const bool bnd = l > 0 || dev0(c, l);
+        hipLaunchKernelGGL(k_prolong_correct, grid2(L.n, L.m), dim3(256), 0, c->s, L.P[0], bnd ? L.lo : nullptr,
+                           bnd ? L.hi : nullptr, L.prm, L.n, L.m, Lc.P[0], Lc.phic, Lc.prm, (float)c->p.M);
         smooth(c, l, c->p.nu2);
         chk(c);
     }
@@ -367,8 +440,8 @@ double read_scalar(mgseg_ctx *c, int slot)
 mgseg_status refresh_and_residual(mgseg_ctx *c)
 {
     update_c(c);
-    res64(c, c->p.mixed_precision != 0);
-    if (!c->p.mixed_precision) c->lev[0].has_F = false;
+    res64(c, false);
+    c->lev[0].has_F = false;
     return MGSEG_OK;
 }
 
@@ -377,10 +450,17 @@ mgseg_status one_cycle(mgseg_ctx *c, double *rel_out)
     Level &L0 = c->lev[0];
     size_t N = (size_t)c->n * c->m;
     (void)hipMemcpyAsync(c->prev64, c->phi64, sizeof(double) * N, hipMemcpyDeviceToDevice, c->s);
-    vcycle_from(c, 0);
     dim3 g = grid2(c->n, c->m);
+    if (c->p.mixed_precision) {
+        hipLaunchKernelGGL(k_start0, g, dim3(256), 0, c->s, c->phi64, c->n, c->m, c->p.M, L0.P[0], L0.lo, L0.hi,
+                           L0.prm);
+        transpose_f(c, L0.lo, L0.prm, L0.lo_cm, L0.pcm, L0.n, L0.m);
+        transpose_f(c, L0.hi, L0.prm, L0.hi_cm, L0.pcm, L0.n, L0.m);
+    }
+    vcycle_from(c, 0);
     if (c->p.mixed_precision)
-        hipLaunchKernelGGL(k_defect_update, g, dim3(256), 0, c->s, c->phi64, L0.P[0], L0.prm, c->n, c->m, c->p.M);
+        hipLaunchKernelGGL(k_finish0, g, dim3(256), 0, c->s, c->phi64, L0.P[0], L0.lo, L0.hi, L0.prm, c->n, c->m,
+                           c->p.M);
     else
         hipLaunchKernelGGL(k_copy32to64, g, dim3(256), 0, c->s, L0.P[0], L0.prm, c->phi64, c->n, c->m);
     refresh_and_residual(c);
@@ -416,9 +496,9 @@ void mgseg_params_default(mgseg_params *p)
     p->struct_size = sizeof(mgseg_params);
     p->model = MGSEG_SPENCER_CHEN;
     p->mu = 0.5; p->lambda1 = 6.5025; p->lambda2 = 6.5025; p->theta = 4.0; p->nu = 1.0;
-    p->eps = 1.0; p->eps_tv_px = 1.0; p->beta = 1.0; p->sigma_g = 1.0; p->sigma_d = 0.1;
+    p->eps = 1.0; p->eps_tv_px = 1.0; p->beta = 16384.0; p->sigma_g = 1.0; p->sigma_d = 0.1;
     p->Sigma = 2.0; p->M = 4.0; p->nu1 = 2; p->nu2 = 2; p->levels = 0; p->coarse_iters = 100;
-    p->mixed_precision = 1; p->scaled = 0;
+    p->mixed_precision = 1; p->scaled = 1;
 }
 
 const char *mgseg_strerror(mgseg_status s)
@@ -440,6 +520,7 @@ void mgseg_destroy(mgseg_ctx *c)
 {
     if (!c) return;
     if (c->s) (void)hipStreamSynchronize(c->s);
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     for (void *p : c->allocs) (void)hipFree(p);
     delete c;
 }
@@ -739,6 +820,35 @@ mgseg_status mgseg_debug_op(mgseg_ctx *c, int l, int op, int arg)
     }
     chk(c);
     return sync_status(c);
+}
+
+mgseg_status mgseg_profile(mgseg_ctx *c, int kernel, int enable)
+{
+    if (!c || kernel != 0) return MGSEG_E_ARG;
+    mgseg_status st = sync_status(c);
+    if (st != MGSEG_OK) return st;
+    c->prof_on = enable != 0;
+    if (enable) { c->ev_used.clear(); c->ev_next = 0; }
+    return MGSEG_OK;
+}
+
+mgseg_status mgseg_profile_read(mgseg_ctx *c, int kernel, double *total_ms, int *count, double *bytes_per_launch)
+{
+    if (!c || kernel != 0) return MGSEG_E_ARG;
+    mgseg_status st = sync_status(c);
+    if (st != MGSEG_OK) return st;
+    double tot = 0.0;
+    for (auto &pr : c->ev_used) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, pr.first, pr.second) != hipSuccess) return MGSEG_E_HIP;
+        tot += ms;
+    }
+    if (total_ms) *total_ms = tot;
+    if (count) *count = (int)c->ev_used.size();
+    // compulsory bytes of one finest-grid sweep: read phi, psi, w, fit, F
+    // (4 B each) and the label byte, write phi (4 B) per cell
+    if (bytes_per_launch) *bytes_per_launch = (double)c->n * c->m * (c->lev[0].has_F ? 25.0 : 21.0);
+    return MGSEG_OK;
 }
 
 }  // extern "C"

@@ -7,7 +7,7 @@
 // ==========================================================================
 // Setup maps (Sec. 2.2).  Level-0 maps are computed in FP64.
 // Gaussian pre-blur of z (separable, half-sample mirror), then
-// g = 1/(1 + beta |grad|^2) with central differences in domain units.
+// g = 1/(1 + beta |grad|^2) with central differences per pixel.
 __global__ void k_blur_rows(const float *z, int pz, double *out, int n, int m, const double *ker, int R)
 {
     int j = blockIdx.x * blockDim.x + threadIdx.x, i = blockIdx.y;
@@ -79,8 +79,8 @@ __global__ void k_setup_maps(SetupArgs S)
     const int n = S.n, m = S.m;
     long long q = (long long)i * m + j;
     int jp = mg_mirror(j + 1, m), jm = mg_mirror(j - 1, m), ip = mg_mirror(i + 1, n), im = mg_mirror(i - 1, n);
-    double gx = (S.zb[(long long)i * m + jp] - S.zb[(long long)i * m + jm]) / (2.0 * S.h0);
-    double gy = (S.zb[(long long)ip * m + j] - S.zb[(long long)im * m + j]) / (2.0 * S.h0);
+    double gx = (S.zb[(long long)i * m + jp] - S.zb[(long long)i * m + jm]) / 2.0;
+    double gy = (S.zb[(long long)ip * m + j] - S.zb[(long long)im * m + j]) / 2.0;
     double g = 1.0 / (1.0 + S.beta * (gx * gx + gy * gy));
     double prod = 1.0;
     for (int t = 0; t < S.k; t++) {
@@ -551,4 +551,242 @@ __global__ void k_scalar_solve(ScalarArgs S)
     }
     if (ra == 0.0 && fabs(a - cur) < bestd) best = a;
     S.phi[0] = (float)best;
+}
+
+// ==========================================================================
+// Coarsest-grid solve in one workgroup: `iters` outer iterations of Hybrid
+// Smoother 2 (freeze + sweeps A, B, C, D), exactly the steps of the
+// multi-kernel path, with block barriers in place of kernel boundaries.
+struct CoarseArgs {
+    float *P0, *P1, *P2, *T1, *T2, *psi, *psi_cm;
+    const float *w, *w_cm, *fit, *fit_cm, *F, *F_cm, *lo, *lo_cm, *hi, *hi_cm;
+    uint8_t *lab, *lab_cm;
+    float *scr; long long scr_field;
+    double *area;                   // slot for the area term (Rada-Chen), may be null
+    double h2, A1, nu, eps;
+    int n, m, prm, pcm, iters, scaled;
+    float kap, e2, M, Sigma;
+};
+
+template <int NT>
+__device__ void block_transpose(const float *in, int pin, float *out, int pout, int n, int m)
+{
+    for (int t = threadIdx.x; t < n * m; t += NT) {
+        int i = t / m, j = t % m;
+        out[(long long)j * pout + i] = in[(long long)i * pin + j];
+    }
+}
+
+template <int NT, int K>
+__global__ void __launch_bounds__(NT) k_coarse_smooth(CoarseArgs C)
+{
+    __shared__ Ramp sh[NT / 64 > 0 ? NT / 64 : 1];
+    __shared__ double red[NT];
+    __shared__ float rb[SF_COUNT * NT * K];
+    __shared__ uint8_t sst[NT * K];
+    RunBuf RBr, RBc;
+    RBr.p = rb; RBr.fs = C.m; RBr.base = 0;
+    RBc.p = rb; RBc.fs = C.n; RBc.base = 0;
+    const int n = C.n, m = C.m, tid = threadIdx.x;
+    LineArgs R, T;
+    R.psi = C.psi; R.w = C.w; R.fit = C.fit; R.F = C.F; R.lab = C.lab; R.lo = C.lo; R.hi = C.hi;
+    R.scr = C.scr; R.scr_field = C.scr_field; R.area = C.area; R.pitch = C.prm; R.lpitch = C.prm;
+    R.nl = n; R.ml = m; R.kap = C.kap; R.e2 = C.e2; R.M = C.M; R.eps = (float)C.eps; R.scaled = C.scaled;
+    T = R;
+    T.psi = C.psi_cm; T.w = C.w_cm; T.fit = C.fit_cm; T.F = C.F_cm; T.lab = C.lab_cm; T.lo = C.lo_cm;
+    T.hi = C.hi_cm; T.pitch = C.pcm; T.lpitch = C.pcm; T.nl = m; T.ml = n;
+    for (int it = 0; it < C.iters; it++) {
+        // freeze
+        for (int t = tid; t < n * m; t += NT) {
+            int i = t / m, j = t % m;
+            float v = C.P0[(long long)i * C.prm + j];
+            C.psi[(long long)i * C.prm + j] = v;
+            C.psi_cm[(long long)j * C.pcm + i] = v;
+        }
+        __syncthreads();
+        double acc = 0.0;
+        for (int t = tid; t < n * m; t += NT) {
+            int i = t / m, j = t % m;
+            uint8_t b = cell_label(C.psi, C.w, C.prm, n, m, i, j, C.e2, C.Sigma);
+            C.lab[(long long)i * C.prm + j] = b;
+            C.lab_cm[(long long)j * C.pcm + i] = b;
+            acc += mg_heav64((double)C.psi[(long long)i * C.prm + j], C.eps);
+        }
+        if (C.area) {
+            red[tid] = acc;
+            __syncthreads();
+            if (tid == 0) {
+                double s = 0.0;
+                for (int k = 0; k < NT; k++) s += red[k];
+                *C.area = 2.0 * C.nu * (C.h2 * s - C.A1);
+            }
+        }
+        __syncthreads();
+        // sweeps A and B (rows)
+        R.phi_old = C.P0; R.phi_new = C.P1; R.bit = 0;
+        for (int b = 0; b < (n + 3) / 4; b++) sweep_band<NT, K, false>(R, b, RBr, RBr, sh, sst, true);
+        R.phi_old = C.P1; R.phi_new = C.P2; R.bit = 1;
+        for (int b = 0; b < (n + 3) / 4; b++) sweep_band<NT, K, true>(R, b, RBr, RBr, sh, sst, true);
+        block_transpose<NT>(C.P2, C.prm, C.T1, C.pcm, n, m);
+        __syncthreads();
+        // sweeps C and D (columns)
+        T.phi_old = C.T1; T.phi_new = C.T2; T.bit = 2;
+        for (int b = 0; b < (m + 3) / 4; b++) sweep_band<NT, K, false>(T, b, RBc, RBc, sh, sst, true);
+        T.phi_old = C.T2; T.phi_new = C.T1; T.bit = 3;
+        for (int b = 0; b < (m + 3) / 4; b++) sweep_band<NT, K, true>(T, b, RBc, RBc, sh, sst, true);
+        block_transpose<NT>(C.T1, C.pcm, C.P0, C.prm, m, n);
+        __syncthreads();
+    }
+}
+
+// ==========================================================================
+// Finest grid in the mixed-precision mode.  During a cycle the finest state
+// is phi = b + d with b the FP64 iterate at the start of the cycle and d a
+// small FP32 deviation: FP32 sweeps on d reach the FP64 fixed point because d
+// and the frozen equations' right-hand side are small where it matters.
+
+// coefficients of the frozen operator at cell (i, j) from psi = fl32(b + d),
+// with the same FP32 expressions as the line sweep (rm orientation:
+// A = cross +, B = cross -, C = in-line +, D = in-line -)
+__device__ __forceinline__ float psi_bd(const double *b, const float *d, int pd, int m, int i, int j)
+{
+    return (float)(b[(long long)i * m + j] + (double)d[(long long)i * pd + j]);
+}
+
+// psi = fl32(b + d) and F_eff = -(sum_nb coef b_nb - S b_p) in FP64, so that the
+// FP32 sweep of L_psi d - f = F_eff is the frozen equation L_psi (b + d) - f = 0.
+__global__ void k_freeze0(const double *b, const float *d, const float *w, int p, int n, int m, float kap,
+                          float e2, float eps, int scaled, float *psi, float *Feff)
+{
+    int j = blockIdx.x * blockDim.x + threadIdx.x, i = blockIdx.y;
+    if (j >= m || i >= n) return;
+    int im = mg_mirror(i - 1, n), ip = mg_mirror(i + 1, n), jm = mg_mirror(j - 1, m), jp = mg_mirror(j + 1, m);
+    auto P = [&](int a, int c) { return psi_bd(b, d, p, m, a, c); };
+    auto W = [&](int a, int c) { return w[(long long)a * p + c]; };
+    auto Bv = [&](int a, int c) { return b[(long long)a * m + c]; };
+    const float p0 = P(i, j);
+    float xp = 0.0f, xm = 0.0f, lp = 0.0f, lm = 0.0f;
+    if (i + 1 < n) xp = mg_face(p0, P(i + 1, j), P(i, jp), P(i + 1, jp), P(i, jm), P(i + 1, jm), W(i, j), W(i + 1, j), e2);
+    if (i > 0) xm = mg_face(P(i - 1, j), p0, P(i - 1, jp), P(i, jp), P(i - 1, jm), P(i, jm), W(i - 1, j), W(i, j), e2);
+    if (j + 1 < m) lp = mg_face(p0, P(i, j + 1), P(ip, j), P(ip, j + 1), P(im, j), P(im, j + 1), W(i, j), W(i, j + 1), e2);
+    if (j > 0) lm = mg_face(P(i, j - 1), p0, P(ip, j - 1), P(ip, j), P(im, j - 1), P(im, j), W(i, j - 1), W(i, j), e2);
+    const float dl = scaled ? 1.0f : mg_delta(p0, eps);
+    const float sc = kap * dl;
+    xp *= sc; xm *= sc; lp *= sc; lm *= sc;
+    const float S = xp + xm + lp + lm;
+    double acc = -(double)S * Bv(i, j);
+    if (i + 1 < n) acc += (double)xp * Bv(i + 1, j);
+    if (i > 0) acc += (double)xm * Bv(i - 1, j);
+    if (j + 1 < m) acc += (double)lp * Bv(i, j + 1);
+    if (j > 0) acc += (double)lm * Bv(i, j - 1);
+    long long q = (long long)i * p + j;
+    psi[q] = p0;
+    Feff[q] = (float)(-acc);
+}
+
+// cycle start: d = 0, bounds of d = [-M - b, M - b]
+__global__ void k_start0(const double *b, int n, int m, double M, float *d, float *lo, float *hi, int p)
+{
+    int j = blockIdx.x * blockDim.x + threadIdx.x, i = blockIdx.y;
+    if (j >= m || i >= n) return;
+    double v = b[(long long)i * m + j];
+    long long q = (long long)i * p + j;
+    d[q] = 0.0f;
+    lo[q] = (float)(-M - v);
+    hi[q] = (float)(M - v);
+}
+
+// cycle end: phi64 = clip(b + d); a deviation at its bound lands exactly on the bound
+__global__ void k_finish0(double *b, const float *d, const float *lo, const float *hi, int p, int n, int m, double M)
+{
+    int j = blockIdx.x * blockDim.x + threadIdx.x, i = blockIdx.y;
+    if (j >= m || i >= n) return;
+    long long q = (long long)i * p + j;
+    double v = b[(long long)i * m + j] + (double)d[q];
+    if (d[q] >= hi[q]) v = M;
+    if (d[q] <= lo[q]) v = -M;
+    b[(long long)i * m + j] = v < -M ? -M : (v > M ? M : v);
+}
+
+// residual of the finest grid at phi = b + d (coefficients at fl32(phi),
+// differences in FP64), projected on [-M, M]
+__global__ void k_res0(const double *b, const float *d, const float *w, const float *fit, int p, int n, int m,
+                       float kap, float e2, float eps, const double *area, int scaled, double M, float *r)
+{
+    int j = blockIdx.x * blockDim.x + threadIdx.x, i = blockIdx.y;
+    if (j >= m || i >= n) return;
+    int im = mg_mirror(i - 1, n), ip = mg_mirror(i + 1, n), jm = mg_mirror(j - 1, m), jp = mg_mirror(j + 1, m);
+    auto P = [&](int a, int c) { return psi_bd(b, d, p, m, a, c); };
+    auto PH = [&](int a, int c) { return b[(long long)a * m + c] + (double)d[(long long)a * p + c]; };
+    auto W = [&](int a, int c) { return w[(long long)a * p + c]; };
+    const float p0 = P(i, j);
+    const double ph0 = PH(i, j);
+    const float dl = scaled ? 1.0f : mg_delta(p0, eps);
+    const float sc = kap * dl;
+    const float ar = area ? (float)(*area) : 0.0f;
+    double v = -(double)(dl * (fit[(long long)i * p + j] + ar));
+    if (i + 1 < n) v += (double)(sc * mg_face(p0, P(i + 1, j), P(i, jp), P(i + 1, jp), P(i, jm), P(i + 1, jm), W(i, j), W(i + 1, j), e2)) * (PH(i + 1, j) - ph0);
+    if (i > 0) v += (double)(sc * mg_face(P(i - 1, j), p0, P(i - 1, jp), P(i, jp), P(i - 1, jm), P(i, jm), W(i - 1, j), W(i, j), e2)) * (PH(i - 1, j) - ph0);
+    if (j + 1 < m) v += (double)(sc * mg_face(p0, P(i, j + 1), P(ip, j), P(ip, j + 1), P(im, j), P(im, j + 1), W(i, j), W(i, j + 1), e2)) * (PH(i, j + 1) - ph0);
+    if (j > 0) v += (double)(sc * mg_face(P(i, j - 1), p0, P(ip, j - 1), P(ip, j), P(im, j - 1), P(im, j), W(i, j - 1), W(i, j), e2)) * (PH(i, j - 1) - ph0);
+    double rr = -v;
+    if ((ph0 >= M && rr < 0.0) || (ph0 <= -M && rr > 0.0)) rr = 0.0;
+    r[(long long)i * p + j] = (float)rr;
+}
+
+// full weighting of phi = b + d (FP64 sums), and the coarse bounds from the
+// finest cells' slack to [-M, M]
+__device__ __forceinline__ double fw_row_bd(const double *b, const float *d, int p, int m, int i, int J, int mc)
+{
+    auto V = [&](int j) { return b[(long long)i * m + j] + (double)d[(long long)i * p + j]; };
+    if (J < mc - 1) return 0.25 * V(2 * J) + 0.5 * V(2 * J + 1) + 0.25 * V(2 * J + 2);
+    return 0.5 * V(2 * J) + 0.5 * V(2 * J + 1);
+}
+__global__ void k_restrict0(const double *b, const float *d, int p, int n, int m, float *phic, float *clo, float *chi,
+                            int pc, int nc, int mc, double M)
+{
+    int J = blockIdx.x * blockDim.x + threadIdx.x, I = blockIdx.y;
+    if (J >= mc || I >= nc) return;
+    double v;
+    if (I < nc - 1)
+        v = 0.25 * fw_row_bd(b, d, p, m, 2 * I, J, mc) + 0.5 * fw_row_bd(b, d, p, m, 2 * I + 1, J, mc) +
+            0.25 * fw_row_bd(b, d, p, m, 2 * I + 2, J, mc);
+    else
+        v = 0.5 * fw_row_bd(b, d, p, m, 2 * I, J, mc) + 0.5 * fw_row_bd(b, d, p, m, 2 * I + 1, J, mc);
+    double dl = -1e300, dh = 1e300;
+    for (int i = 2 * I; i <= 2 * I + 2 && i < n; i++)
+        for (int j = 2 * J; j <= 2 * J + 2 && j < m; j++) {
+            double ph = b[(long long)i * m + j] + (double)d[(long long)i * p + j];
+            dl = fmax(dl, -M - ph);
+            dh = fmin(dh, M - ph);
+        }
+    long long q = (long long)I * pc + J;
+    float pcv = (float)v;
+    phic[q] = pcv;
+    clo[q] = (float)((double)pcv + dl);
+    chi[q] = (float)((double)pcv + dh);
+}
+
+// sum of H(b + d) over the finest grid (Rada-Chen area term in the mixed mode)
+__global__ void k_sums_bd(const double *b, const float *d, int p, int n, int m, double eps, double *partial)
+{
+    __shared__ double r0[256];
+    int tid = threadIdx.x;
+    long long N = (long long)n * m;
+    double a0 = 0.0;
+    for (long long t = (long long)blockIdx.x * blockDim.x + tid; t < N; t += (long long)gridDim.x * blockDim.x) {
+        int i = (int)(t / m), j = (int)(t % m);
+        a0 += mg_heav64(b[t] + (double)d[(long long)i * p + j], eps);
+    }
+    r0[tid] = a0;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (tid < s) r0[tid] += r0[tid + s];
+        __syncthreads();
+    }
+    if (tid == 0) {
+        partial[3 * blockIdx.x] = r0[0];
+        partial[3 * blockIdx.x + 1] = 0.0;
+        partial[3 * blockIdx.x + 2] = 0.0;
+    }
 }

@@ -56,7 +56,7 @@ class Params:
     nu: float = 1.0
     eps: float = 1.0
     eps_tv_px: float = 1.0
-    beta: float = 1.0
+    beta: float = 16384.0
     sigma_g: float = 1.0
     sigma_d: float = 0.1
     Sigma: float = 2.0
@@ -66,7 +66,7 @@ class Params:
     levels: int = 0
     coarse_iters: int = 100
     mixed_precision: int = 1
-    scaled: int = 0
+    scaled: int = 1
 
     def to_c(self) -> _Params:
         p = _Params()
@@ -106,9 +106,12 @@ def lib():
         L.mgseg_debug_scalars.argtypes = [vp, dp]
         L.mgseg_debug_set_c.argtypes = [vp, C.c_double, C.c_double]
         L.mgseg_debug_op.argtypes = [vp, C.c_int, C.c_int, C.c_int]
+        L.mgseg_profile.argtypes = [vp, C.c_int, C.c_int]
+        L.mgseg_profile_read.argtypes = [vp, C.c_int, dp, ip, dp]
         for name in ("mgseg_setup", "mgseg_set_phi0", "mgseg_vcycle", "mgseg_solve", "mgseg_get_phi",
                      "mgseg_get_mask", "mgseg_get_stats", "mgseg_level_shape", "mgseg_debug_get",
-                     "mgseg_debug_set", "mgseg_debug_scalars", "mgseg_debug_set_c", "mgseg_debug_op"):
+                     "mgseg_debug_set", "mgseg_debug_scalars", "mgseg_debug_set_c", "mgseg_debug_op",
+                     "mgseg_profile", "mgseg_profile_read"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -217,6 +220,15 @@ class Solver:
 
     def set_c(self, c1, c2):
         _check(self.L.mgseg_debug_set_c(self.ctx, c1, c2), "set_c")
+
+    def profile(self, enable=True, kernel=0):
+        _check(self.L.mgseg_profile(self.ctx, kernel, int(enable)), "profile")
+
+    def profile_read(self, kernel=0):
+        tot, cnt, by = C.c_double(), C.c_int(), C.c_double()
+        _check(self.L.mgseg_profile_read(self.ctx, kernel, C.byref(tot), C.byref(cnt), C.byref(by)),
+               "profile_read")
+        return tot.value, cnt.value, by.value
 
     def op(self, name, level=0, arg=0):
         _check(self.L.mgseg_debug_op(self.ctx, level, OP[name], arg), f"op {name}")

@@ -23,9 +23,11 @@ def say(*a):
     sys.stdout.flush()
 
 
-def make(seed=1000, levels=6, **kw):
+def make(seed=1000, levels=6, mixed=1, **kw):
+    """GPU solver and oracle on the same config-1 input.  Single-step tests use
+    mixed=0: the finest grid then holds phi itself in FP32."""
     inst = synth.config1(seed)
-    s = mgseg.Solver(inst.image, inst.markers, mgseg.Params(levels=levels, **kw))
+    s = mgseg.Solver(inst.image, inst.markers, mgseg.Params(levels=levels, mixed_precision=mixed, **kw))
     o = Oracle(inst.image, inst.markers, OracleParams(levels=levels, **kw))
     return inst, s, o
 
@@ -51,7 +53,7 @@ def test_setup_maps():
 
 def test_labels_match():
     say("case labels seed 1000")
-    inst, s, o = make()
+    inst, s, o = make(mixed=0)
     s.op("freeze", 0)
     o.freeze(0)
     lg, lo = s.get("labels"), o.labels()
@@ -64,7 +66,7 @@ def test_labels_match():
 @pytest.mark.parametrize("sweep", [0, 1, 2, 3])
 def test_single_sweep(sweep):
     say("case single sweep", "ABCD"[sweep])
-    inst, s, o = make()
+    inst, s, o = make(mixed=0)
     # move away from the initial state: a few oracle outer iterations
     o.smooth(2, 0)
     phi = o.get("phi")
@@ -83,7 +85,7 @@ def test_single_sweep(sweep):
 
 def test_residual_fp32():
     say("case residual")
-    inst, s, o = make()
+    inst, s, o = make(mixed=0)
     s.op("residual", 0)
     rg, ro = s.get("r").astype(np.float64), o.residual(0, True)
     scale = np.abs(ro).max()

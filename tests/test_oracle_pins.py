@@ -130,18 +130,23 @@ def test_setup_closed_forms():
 
 
 def test_edge_detector_closed_form():
-    """A linear ramp z = a * (j + 1/2) has |grad(G*z)| = a / h0 away from the borders."""
+    """A linear ramp z = a * (j + 1/2) has |grad(G*z)| = a per pixel away from the borders,
+    so g = 1 / (1 + beta a^2) with beta per squared pixel gradient."""
     n = m = 32
     a = 0.01
     img = np.tile(a * (np.arange(m) + 0.5), (n, 1)).astype(np.float64)
-    out = setup_maps(img, np.array([[10.5, 10.5], [10.5, 20.5], [20.5, 15.5]]), OracleParams(levels=1))
-    grad = a * 32
-    assert abs(out["g"][16, 16] - 1.0 / (1.0 + grad ** 2)) < 1e-12
+    p = OracleParams(levels=1)
+    out = setup_maps(img, np.array([[10.5, 10.5], [10.5, 20.5], [20.5, 15.5]]), p)
+    assert abs(out["g"][16, 16] - 1.0 / (1.0 + p.beta * a ** 2)) < 1e-12
+    # beta per pixel is the domain-unit beta scaled by h0^2: beta = 16384 at n = 128 is beta = 1
+    assert abs(p.beta / 128 ** 2 - 1.0) < 1e-15
 
 
 # ---------------------------------------------------------------- operator (eq. abcdrc, eq. abcd)
 def _tiny(seed=5, n=16, m=16, **kw):
+    """Unscaled rows (each row keeps its delta(phi) factor), as eq. abcd writes them."""
     inst = synth.tiny_instance(seed, n, m)
+    kw.setdefault("scaled", 0)
     return inst, Oracle(inst.image, inst.markers, OracleParams(levels=1, **kw))
 
 
@@ -173,7 +178,7 @@ def test_operator_circle_curvature():
     n = 128
     img = np.zeros((n, n), np.float32)
     o = Oracle(img, np.array([[60.5, 60.5], [60.5, 70.5], [70.5, 65.5]]),
-               OracleParams(levels=1, eps_tv_px=1e-6, M=1e9))
+               OracleParams(levels=1, eps_tv_px=1e-6, M=1e9, scaled=0))
     i, j = np.meshgrid(np.arange(n) + 0.5, np.arange(n) + 0.5, indexing="ij")
     R = 30.0
     phi = R - np.sqrt((i - 64.0) ** 2 + (j - 64.0) ** 2)
@@ -284,12 +289,14 @@ def test_smoother_fixed_point_is_projected_solution():
 
 
 def test_fas_converges_and_residual_decreases():
+    """The cycle converges; each c1, c2 refresh (Sec. 5) moves the discrete system, so the
+    history may rise while the region means settle, and decreases once they have."""
     for seed in (1000, 1001, 1002, 1003):
         inst = synth.config1(seed)
         o = Oracle(inst.image, inst.markers, OracleParams(levels=6))
         k, hist = o.solve(1e-6, 40)
-        assert k > 0, seed
-        assert np.all(np.diff(hist) <= 0), (seed, hist)
+        assert k > 0 and hist[-1] <= 1e-6, (seed, hist)
+        assert np.all(np.diff(hist[-3:]) < 0), (seed, hist)
 
 
 def test_fas_fixed_point_agrees_with_time_marching():
