@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/mgseg.h"
@@ -21,7 +22,8 @@ enum {
     DS_AREA_EVAL = 3,         // area term for operator evaluations
     DS_AREA64 = 4,            // area term at the FP64 finest phi
     DS_RES = 5,               // last residual norm
-    DS_COUNT = 8
+    DS_AREAB0 = 8,            // deviation form: area term at the base of level l is slot DS_AREAB0 + l
+    DS_COUNT = 8 + MAXLEV
 };
 
 struct Level {
@@ -30,6 +32,7 @@ struct Level {
     float *z = nullptr, *d = nullptr, *w = nullptr, *fit = nullptr, *F = nullptr;
     float *P[3] = {nullptr, nullptr, nullptr};
     float *psi = nullptr, *phic = nullptr, *r = nullptr, *lo = nullptr, *hi = nullptr;
+    float *G = nullptr;       // deviation form: the level's residual part of F (row-major)
     float *w_cm = nullptr, *fit_cm = nullptr, *F_cm = nullptr, *lo_cm = nullptr, *hi_cm = nullptr;
     float *T[3] = {nullptr, nullptr, nullptr};
     float *psi_cm = nullptr;
@@ -132,8 +135,8 @@ double host_area(const std::vector<double> &h, int hv)
     return 0.5 * std::fabs(s);
 }
 
-// the finest grid holds the FP32 deviation from the FP64 iterate
-inline bool dev0(const mgseg_ctx *c, int l) { return l == 0 && c->p.mixed_precision; }
+// mixed-precision mode: every level holds an FP32 deviation from a base
+inline bool devm(const mgseg_ctx *c) { return c->p.mixed_precision != 0; }
 
 float lev_e2(const mgseg_ctx *c, int l)
 {
@@ -186,8 +189,9 @@ void update_c(mgseg_ctx *c)
     update_fit(c);
 }
 
-// FP64 finest residual: norm into DS_RES; phi32 <- fl32(phi64); F~ if mixed
-void res64(mgseg_ctx *c, bool write_Ft)
+// FP64 finest residual: norm into DS_RES; FP32 mode: phi32 <- fl32(phi64);
+// deviation form: G of the finest grid <- fl32(r64)
+void res64(mgseg_ctx *c)
 {
     Level &L = c->lev[0];
     if (c->p.model == 1) {
@@ -204,16 +208,13 @@ void res64(mgseg_ctx *c, bool write_Ft)
     A.kap = c->p.mu / L.h; A.e2 = lev_e2(c, 0); A.eps = c->p.eps;
     A.l1 = c->p.lambda1; A.l2 = c->p.lambda2; A.theta = c->p.theta; A.M = c->p.M;
     A.model = c->p.model; A.scaled = c->p.scaled; A.n = c->n; A.m = c->m;
-    A.phi32 = L.P[0]; A.Ft = write_Ft ? L.F : nullptr;
+    A.phi32 = devm(c) ? nullptr : L.P[0];
+    A.G = devm(c) ? L.G : nullptr;
     A.partial = c->part;
     dim3 g = grid2(c->n, c->m);
     hipLaunchKernelGGL(k_res64, g, dim3(256), 0, c->s, A);
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, c->s, c->part, (int)(g.x * g.y), 2, 0.0, 0.0, 0.0, 0.0,
                        c->dsc + DS_RES);
-    if (write_Ft) {
-        transpose_f(c, L.F, L.prm, L.F_cm, L.pcm, L.n, L.m);
-        L.has_F = true;
-    }
 }
 
 // --------------------------------------------------------------------------
@@ -227,10 +228,10 @@ void launch_sweep(mgseg_ctx *c, int l, int s, const float *phi_old, float *phi_n
     A.phi_old = phi_old; A.phi_new = phi_new;
     A.psi = cm ? L.psi_cm : L.psi;
     A.w = cm ? L.w_cm : L.w;
-    A.fit = cm ? L.fit_cm : L.fit;
+    A.fit = devm(c) ? nullptr : (cm ? L.fit_cm : L.fit);
     A.F = L.has_F ? (cm ? L.F_cm : L.F) : nullptr;
     A.lab = cm ? L.lab_cm : L.lab;
-    const bool bnd = l > 0 || dev0(c, l);
+    const bool bnd = l > 0 || devm(c);
     A.lo = bnd ? (cm ? L.lo_cm : L.lo) : nullptr;
     A.hi = bnd ? (cm ? L.hi_cm : L.hi) : nullptr;
     A.scr = c->scr; A.scr_field = c->scr_field;
@@ -285,18 +286,67 @@ void launch_sweep(mgseg_ctx *c, int l, int s, const float *phi_old, float *phi_n
     chk(c);
 }
 
-// freeze at the current phi (in P[0]): psi copies, labels, area term
+int area_b_slot(int l) { return l == 0 ? DS_AREA64 : DS_AREAB0 + l; }
+
+// deviation-form arguments of level l; fn is called with DevArgs<double> on the
+// finest grid (base = the FP64 iterate) and DevArgs<float> below (base = phic)
+template <typename BT>
+DevArgs<BT> dev_args(mgseg_ctx *c, int l, const BT *b, int pb)
+{
+    Level &L = c->lev[l];
+    DevArgs<BT> A;
+    A.b = b; A.pb = pb;
+    A.e = L.P[0]; A.G = L.G; A.w = L.w; A.fit = L.fit; A.lo = L.lo; A.hi = L.hi;
+    A.psi = L.psi; A.T = L.F; A.r = L.r; A.lab = L.lab;
+    A.area_b = c->p.model == 1 ? c->dsc + area_b_slot(l) : nullptr;
+    A.area_u = nullptr;
+    A.p = L.prm; A.n = L.n; A.m = L.m; A.scaled = c->p.scaled;
+    A.kap = (float)(c->p.mu / L.h); A.e2 = lev_e2(c, l); A.eps = (float)c->p.eps; A.Sigma = (float)c->p.Sigma;
+    return A;
+}
+template <class Fn>
+void with_dev(mgseg_ctx *c, int l, Fn fn)
+{
+    if (l == 0) fn(dev_args<double>(c, 0, c->phi64, c->m));
+    else fn(dev_args<float>(c, l, c->lev[l].phic, c->lev[l].prm));
+}
+
+// area term at b + e of level l (deviation form) -> slot
+void dev_area(mgseg_ctx *c, int l, int slot)
+{
+    Level &L = c->lev[l];
+    int nb = std::min(RED_BLOCKS, std::max(1, (L.n * L.m + 255) / 256));
+    if (l == 0)
+        hipLaunchKernelGGL(k_sums_dev<double>, dim3(nb), dim3(256), 0, c->s, c->phi64, c->m, L.P[0], L.prm, L.n, L.m,
+                           c->p.eps, c->part);
+    else
+        hipLaunchKernelGGL(k_sums_dev<float>, dim3(nb), dim3(256), 0, c->s, L.phic, L.prm, L.P[0], L.prm, L.n, L.m,
+                           c->p.eps, c->part);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, c->s, c->part, nb, 0, (double)L.n * L.m, L.h * L.h, c->A1,
+                       c->p.nu, c->dsc + slot);
+}
+
+// freeze at the current state: psi, labels, area term; deviation form also
+// the frozen right-hand side T (in F)
 void freeze(mgseg_ctx *c, int l)
 {
     Level &L = c->lev[l];
-    if (dev0(c, l)) {
-        hipLaunchKernelGGL(k_freeze0, grid2(L.n, L.m), dim3(256), 0, c->s, c->phi64, L.P[0], L.w, L.prm, L.n, L.m,
-                           (float)(c->p.mu / L.h), lev_e2(c, l), (float)c->p.eps, c->p.scaled, L.psi, L.F);
+    if (devm(c)) {
+        const bool rc = c->p.model == 1;
+        if (rc) dev_area(c, l, DS_AREA_FRZ);
+        with_dev(c, l, [&](auto A) {
+            using BT = std::remove_const_t<std::remove_pointer_t<decltype(A.b)>>;
+            A.area_u = rc ? c->dsc + DS_AREA_FRZ : nullptr;
+            hipLaunchKernelGGL(k_freeze_dev<BT>, grid2(L.n, L.m), dim3(256), 0, c->s, A);
+        });
+        transpose_f(c, L.psi, L.prm, L.psi_cm, L.pcm, L.n, L.m);
         transpose_f(c, L.F, L.prm, L.F_cm, L.pcm, L.n, L.m);
+        transpose_u8(c, L.lab, L.prm, L.lab_cm, L.pcm, L.n, L.m);
         L.has_F = true;
-    } else {
-        (void)hipMemcpyAsync(L.psi, L.P[0], sizeof(float) * (size_t)L.n * L.prm, hipMemcpyDeviceToDevice, c->s);
+        chk(c);
+        return;
     }
+    (void)hipMemcpyAsync(L.psi, L.P[0], sizeof(float) * (size_t)L.n * L.prm, hipMemcpyDeviceToDevice, c->s);
     transpose_f(c, L.psi, L.prm, L.psi_cm, L.pcm, L.n, L.m);
     hipLaunchKernelGGL(k_labels, grid2(L.n, L.m), dim3(256), 0, c->s, L.psi, L.w, L.prm, L.n, L.m, lev_e2(c, l),
                        (float)c->p.Sigma, L.lab, L.prm);
@@ -327,29 +377,34 @@ void smooth(mgseg_ctx *c, int l, int iters)
 void coarsest(mgseg_ctx *c, int l)
 {
     Level &L = c->lev[l];
-    if (L.n * L.m == 1) {
+    const bool dev = devm(c);
+    if (L.n * L.m == 1 && !(dev && l == 0)) {
         ScalarArgs S;
-        S.phi = L.P[0]; S.F = L.F; S.fit = L.fit; S.lo = l > 0 ? L.lo : nullptr; S.hi = l > 0 ? L.hi : nullptr;
+        S.phi = L.P[0]; S.F = dev ? L.G : L.F; S.fit = L.fit;
+        S.lo = l > 0 ? L.lo : nullptr; S.hi = l > 0 ? L.hi : nullptr;
+        S.base = dev ? L.phic : nullptr;
         S.h2 = L.h * L.h; S.A1 = c->A1; S.nu = c->p.nu; S.eps = c->p.eps; S.M = c->p.M;
         S.model = c->p.model; S.scaled = c->p.scaled;
         hipLaunchKernelGGL(k_scalar_solve, dim3(1), dim3(64), 0, c->s, S);
         chk(c);
         return;
     }
-    if (L.n <= 64 && L.m <= 64 && !dev0(c, l)) {
+    if (L.n <= 64 && L.m <= 64 && l > 0) {
         CoarseArgs C;
         C.P0 = L.P[0]; C.P1 = L.P[1]; C.P2 = L.P[2]; C.T1 = L.T[1]; C.T2 = L.T[2];
         C.psi = L.psi; C.psi_cm = L.psi_cm;
         C.w = L.w; C.w_cm = L.w_cm; C.fit = L.fit; C.fit_cm = L.fit_cm;
-        C.F = L.has_F ? L.F : nullptr; C.F_cm = L.has_F ? L.F_cm : nullptr;
-        C.lo = l > 0 ? L.lo : nullptr; C.lo_cm = l > 0 ? L.lo_cm : nullptr;
-        C.hi = l > 0 ? L.hi : nullptr; C.hi_cm = l > 0 ? L.hi_cm : nullptr;
+        C.F = (dev || L.has_F) ? L.F : nullptr; C.F_cm = (dev || L.has_F) ? L.F_cm : nullptr;
+        C.base = dev ? L.phic : nullptr; C.G = dev ? L.G : nullptr;
+        C.area_b = dev && c->p.model == 1 ? c->dsc + area_b_slot(l) : nullptr;
+        C.lo = L.lo; C.lo_cm = L.lo_cm; C.hi = L.hi; C.hi_cm = L.hi_cm;
         C.lab = L.lab; C.lab_cm = L.lab_cm; C.scr = c->scr; C.scr_field = c->scr_field;
         C.area = c->p.model == 1 ? c->dsc + DS_AREA_FRZ : nullptr;
         C.h2 = L.h * L.h; C.A1 = c->A1; C.nu = c->p.nu; C.eps = c->p.eps;
         C.n = L.n; C.m = L.m; C.prm = L.prm; C.pcm = L.pcm; C.iters = c->p.coarse_iters; C.scaled = c->p.scaled;
         C.kap = (float)(c->p.mu / L.h); C.e2 = lev_e2(c, l); C.M = (float)c->p.M; C.Sigma = (float)c->p.Sigma;
         hipLaunchKernelGGL((k_coarse_smooth<64, 1>), dim3(1), dim3(64), 0, c->s, C);
+        if (dev) L.has_F = true;
         chk(c);
         return;
     }
@@ -359,17 +414,15 @@ void coarsest(mgseg_ctx *c, int l)
 void residual(mgseg_ctx *c, int l, float *r, double *partial)
 {
     Level &L = c->lev[l];
-    if (dev0(c, l)) {
-        if (c->p.model == 1) {     // area term at phi = b + d
-            int nb = std::min(RED_BLOCKS, std::max(1, (L.n * L.m + 255) / 256));
-            hipLaunchKernelGGL(k_sums_bd, dim3(nb), dim3(256), 0, c->s, c->phi64, L.P[0], L.prm, L.n, L.m, c->p.eps,
-                               c->part);
-            hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, c->s, c->part, nb, 0, (double)L.n * L.m, L.h * L.h,
-                               c->A1, c->p.nu, c->dsc + DS_AREA_EVAL);
-        }
-        hipLaunchKernelGGL(k_res0, grid2(L.n, L.m), dim3(256), 0, c->s, c->phi64, L.P[0], L.w, L.fit, L.prm, L.n, L.m,
-                           (float)(c->p.mu / L.h), lev_e2(c, l), (float)c->p.eps,
-                           c->p.model == 1 ? c->dsc + DS_AREA_EVAL : nullptr, c->p.scaled, c->p.M, r);
+    if (devm(c)) {
+        const bool rc = c->p.model == 1;
+        if (rc) dev_area(c, l, DS_AREA_EVAL);
+        with_dev(c, l, [&](auto A) {
+            using BT = std::remove_const_t<std::remove_pointer_t<decltype(A.b)>>;
+            A.area_u = rc ? c->dsc + DS_AREA_EVAL : nullptr;
+            A.r = r;
+            hipLaunchKernelGGL(k_res_dev<BT>, grid2(L.n, L.m), dim3(256), 0, c->s, A);
+        });
         chk(c);
         return;
     }
@@ -381,40 +434,50 @@ void residual(mgseg_ctx *c, int l, float *r, double *partial)
     chk(c);
 }
 
-// FAS V-cycle (Algorithm-1 box, gamma = 1) from level l0 down and back
+// FAS V-cycle (Algorithm-1 box, gamma = 1) from level l0 down and back.
+// Deviation form: the coarse base is the restricted state, the coarse
+// deviation starts at zero and G is the restricted residual; the FP32 mode
+// keeps full values with F_c = N_c(phic) + R r.
 void vcycle_from(mgseg_ctx *c, int l0)
 {
+    const bool dev = devm(c);
     for (int l = l0; l < c->L - 1; l++) {
         Level &L = c->lev[l], &Lc = c->lev[l + 1];
         smooth(c, l, c->p.nu1);
         residual(c, l, L.r, nullptr);
         dim3 gc = grid2(Lc.n, Lc.m);
-        hipLaunchKernelGGL(k_restrict, gc, dim3(256), 0, c->s, L.r, L.prm, Lc.r, Lc.prm, Lc.n, Lc.m);
-        if (dev0(c, l)) {
-            hipLaunchKernelGGL(k_restrict0, gc, dim3(256), 0, c->s, c->phi64, L.P[0], L.prm, L.n, L.m, Lc.phic,
-                               Lc.lo, Lc.hi, Lc.prm, Lc.n, Lc.m, c->p.M);
+        if (dev) {
+            hipLaunchKernelGGL(k_restrict, gc, dim3(256), 0, c->s, L.r, L.prm, Lc.G, Lc.prm, Lc.n, Lc.m);
+            with_dev(c, l, [&](auto A) {
+                using BT = std::remove_const_t<std::remove_pointer_t<decltype(A.b)>>;
+                hipLaunchKernelGGL(k_restrict_dev<BT>, gc, dim3(256), 0, c->s, A.b, A.pb, L.P[0], L.lo, L.hi, L.prm,
+                                   L.n, L.m, Lc.phic, Lc.P[0], Lc.lo, Lc.hi, Lc.prm, Lc.n, Lc.m);
+            });
+            if (c->p.model == 1) area_term(c, l + 1, Lc.phic, Lc.prm, DS_AREAB0 + l + 1);
         } else {
+            hipLaunchKernelGGL(k_restrict, gc, dim3(256), 0, c->s, L.r, L.prm, Lc.r, Lc.prm, Lc.n, Lc.m);
             hipLaunchKernelGGL(k_restrict, gc, dim3(256), 0, c->s, L.P[0], L.prm, Lc.phic, Lc.prm, Lc.n, Lc.m);
             hipLaunchKernelGGL(k_coarse_bounds, gc, dim3(256), 0, c->s, L.P[0], l > 0 ? L.lo : nullptr,
                                l > 0 ? L.hi : nullptr, L.prm, L.n, L.m, Lc.phic, Lc.lo, Lc.hi, Lc.prm, Lc.n, Lc.m,
                                (float)c->p.M);
+            if (c->p.model == 1) area_term(c, l + 1, Lc.phic, Lc.prm, DS_AREA_EVAL);
+            hipLaunchKernelGGL(k_coarse_rhs, gc, dim3(256), 0, c->s, Lc.phic, Lc.w, Lc.fit, Lc.r, Lc.prm, Lc.n, Lc.m,
+                               (float)(c->p.mu / Lc.h), lev_e2(c, l + 1), (float)c->p.eps,
+                               c->p.model == 1 ? c->dsc + DS_AREA_EVAL : nullptr, c->p.scaled, Lc.F, Lc.P[0]);
+            transpose_f(c, Lc.F, Lc.prm, Lc.F_cm, Lc.pcm, Lc.n, Lc.m);
+            Lc.has_F = true;
         }
         transpose_f(c, Lc.lo, Lc.prm, Lc.lo_cm, Lc.pcm, Lc.n, Lc.m);
         transpose_f(c, Lc.hi, Lc.prm, Lc.hi_cm, Lc.pcm, Lc.n, Lc.m);
-        if (c->p.model == 1) area_term(c, l + 1, Lc.phic, Lc.prm, DS_AREA_EVAL);
-        hipLaunchKernelGGL(k_coarse_rhs, gc, dim3(256), 0, c->s, Lc.phic, Lc.w, Lc.fit, Lc.r, Lc.prm, Lc.n, Lc.m,
-                           (float)(c->p.mu / Lc.h), lev_e2(c, l + 1), (float)c->p.eps,
-                           c->p.model == 1 ? c->dsc + DS_AREA_EVAL : nullptr, c->p.scaled, Lc.F, Lc.P[0]);
-        transpose_f(c, Lc.F, Lc.prm, Lc.F_cm, Lc.pcm, Lc.n, Lc.m);
-        Lc.has_F = true;
         chk(c);
     }
     coarsest(c, c->L - 1);
     for (int l = c->L - 2; l >= l0; l--) {
         Level &L = c->lev[l], &Lc = c->lev[l + 1];
-        const bool bnd = l > 0 || dev0(c, l);
+        const bool bnd = l > 0 || dev;
         hipLaunchKernelGGL(k_prolong_correct, grid2(L.n, L.m), dim3(256), 0, c->s, L.P[0], bnd ? L.lo : nullptr,
-                           bnd ? L.hi : nullptr, L.prm, L.n, L.m, Lc.P[0], Lc.phic, Lc.prm, (float)c->p.M);
+                           bnd ? L.hi : nullptr, L.prm, L.n, L.m, Lc.P[0], dev ? nullptr : Lc.phic, Lc.prm,
+                           (float)c->p.M);
         smooth(c, l, c->p.nu2);
         chk(c);
     }
@@ -440,7 +503,7 @@ double read_scalar(mgseg_ctx *c, int slot)
 mgseg_status refresh_and_residual(mgseg_ctx *c)
 {
     update_c(c);
-    res64(c, false);
+    res64(c);
     c->lev[0].has_F = false;
     return MGSEG_OK;
 }
@@ -562,7 +625,7 @@ mgseg_status mgseg_setup(const float *image_dev, int n, int m, int pitch, const 
         L.fit = dalloc<float>(c, Nr); L.F = dalloc<float>(c, Nr);
         for (int t = 0; t < 3; t++) { L.P[t] = dalloc<float>(c, Nr); L.T[t] = dalloc<float>(c, Nc); }
         L.psi = dalloc<float>(c, Nr); L.psi_cm = dalloc<float>(c, Nc);
-        L.phic = dalloc<float>(c, Nr); L.r = dalloc<float>(c, Nr);
+        L.phic = dalloc<float>(c, Nr); L.r = dalloc<float>(c, Nr); L.G = dalloc<float>(c, Nr);
         L.lo = dalloc<float>(c, Nr); L.hi = dalloc<float>(c, Nr);
         L.w_cm = dalloc<float>(c, Nc); L.fit_cm = dalloc<float>(c, Nc); L.F_cm = dalloc<float>(c, Nc);
         L.lo_cm = dalloc<float>(c, Nc); L.hi_cm = dalloc<float>(c, Nc);
@@ -845,9 +908,13 @@ mgseg_status mgseg_profile_read(mgseg_ctx *c, int kernel, double *total_ms, int 
     }
     if (total_ms) *total_ms = tot;
     if (count) *count = (int)c->ev_used.size();
-    // compulsory bytes of one finest-grid sweep: read phi, psi, w, fit, F
-    // (4 B each) and the label byte, write phi (4 B) per cell
-    if (bytes_per_launch) *bytes_per_launch = (double)c->n * c->m * (c->lev[0].has_F ? 25.0 : 21.0);
+    // compulsory bytes of one finest-grid sweep per cell: read phi, psi, w
+    // (4 B each), the label byte, F (4 B), fit (FP32 mode) or the bounds of
+    // the deviation (mixed mode, 8 B); write phi (4 B)
+    if (bytes_per_launch) {
+        double per = 4.0 * 3 + 1.0 + 4.0 + (devm(c) ? 8.0 + 4.0 : 4.0 + (c->lev[0].has_F ? 4.0 : 0.0));
+        *bytes_per_launch = (double)c->n * c->m * per;
+    }
     return MGSEG_OK;
 }
 

@@ -468,7 +468,7 @@ __device__ __forceinline__ void sweep_line(const LineArgs &A, int r, const RunBu
         const float sc = A.kap * dl;
         xp *= sc; xm *= sc; lp *= sc; lm *= sc;
         const float S = xp + xm + lp + lm;
-        const float f = dl * (A.fit[ro + q] + area);
+        const float f = A.fit ? dl * (A.fit[ro + q] + area) : 0.0f;   // null fit: f is part of F
         const float Fv = A.F ? A.F[ro + q] : 0.0f;
         const float Xu = REV ? xp : xm, Xd = REV ? xm : xp;
         const float Lp = REV ? lp : lm, Ls = REV ? lm : lp;

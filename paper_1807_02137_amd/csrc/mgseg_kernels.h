@@ -147,7 +147,8 @@ __global__ void k_coarse_bounds(const float *phi, const float *flo, const float 
 
 // bilinear interpolation (Sec. 3.1), 0-based: fine 2I+1 <- coarse I, fine 2I
 // (I >= 1) <- mean of coarse I-1, I, fine 0 <- coarse 0; tensor product.
-// Correction: phi <- clip(phi + P(phi^c - phic), lo, hi).
+// Correction: phi <- clip(phi + P(phi^c - phic), lo, hi); phic null: phi^c is
+// the correction itself (deviation form).
 __device__ __forceinline__ void pl_idx(int f, int &a, int &b, float &wa)
 {
     if (f & 1) { a = b = f >> 1; wa = 1.0f; }
@@ -163,7 +164,7 @@ __global__ void k_prolong_correct(float *phi, const float *lo, const float *hi, 
     float wi, wj;
     pl_idx(i, ia, ib, wi);
     pl_idx(j, ja, jb, wj);
-    auto e = [&](int I, int J) { long long q = (long long)I * pc + J; return phis[q] - phic[q]; };
+    auto e = [&](int I, int J) { long long q = (long long)I * pc + J; return phic ? phis[q] - phic[q] : phis[q]; };
     float ea = wj * e(ia, ja) + (1.0f - wj) * e(ia, jb);
     float eb = wj * e(ib, ja) + (1.0f - wj) * e(ib, jb);
     float corr = wi * ea + (1.0f - wi) * eb;
@@ -198,19 +199,24 @@ __global__ void k_transpose(const T *in, int pin, T *out, int pout, int n, int m
 // (the common factor mu delta / h^2 cancels in both tests).  Interior faces
 // only; a zero interior value counts as an infinite ratio; ties take the
 // first of A, B, C, D.  Bit s of the label byte = starred in sweep s.
-__device__ __forceinline__ uint8_t cell_label(const float *psi, const float *w, int p, int n, int m, int i, int j,
-                                              float e2, float Sigma)
+// raw face values w_face / |grad x|_eps of the faces A (i+1/2, j), B (i-1/2, j),
+// C (i, j+1/2), D (i, j-1/2) of cell (i, j), x read through X(i, j); zero on
+// boundary faces.  The arguments are those of the line sweep, so the values
+// are bit-identical to the sweep's.
+template <class X, class W>
+__device__ __forceinline__ void faces4(const X &P, const W &Wf, int n, int m, int i, int j, float e2, float (&g)[4])
 {
-    int im = mg_mirror(i - 1, n), ip = mg_mirror(i + 1, n), jm = mg_mirror(j - 1, m), jp = mg_mirror(j + 1, m);
-    auto P = [&](int a, int b) { return psi[(long long)a * p + b]; };
-    auto W = [&](int a, int b) { return w[(long long)a * p + b]; };
-    float G[4];
-    bool in[4] = {i + 1 < n, i > 0, j + 1 < m, j > 0};
-    // A: face (i+1/2, j); B: (i-1/2, j); C: (i, j+1/2); D: (i, j-1/2)
-    G[0] = in[0] ? mg_face(P(i, j), P(i + 1, j), P(i, jp), P(i + 1, jp), P(i, jm), P(i + 1, jm), W(i, j), W(i + 1, j), e2) : 0.0f;
-    G[1] = in[1] ? mg_face(P(i - 1, j), P(i, j), P(i - 1, jp), P(i, jp), P(i - 1, jm), P(i, jm), W(i - 1, j), W(i, j), e2) : 0.0f;
-    G[2] = in[2] ? mg_face(P(i, j), P(i, j + 1), P(ip, j), P(ip, j + 1), P(im, j), P(im, j + 1), W(i, j), W(i, j + 1), e2) : 0.0f;
-    G[3] = in[3] ? mg_face(P(i, j - 1), P(i, j), P(ip, j - 1), P(ip, j), P(im, j - 1), P(im, j), W(i, j - 1), W(i, j), e2) : 0.0f;
+    const int im = mg_mirror(i - 1, n), ip = mg_mirror(i + 1, n), jm = mg_mirror(j - 1, m), jp = mg_mirror(j + 1, m);
+    const float p0 = P(i, j);
+    g[0] = i + 1 < n ? mg_face(p0, P(i + 1, j), P(i, jp), P(i + 1, jp), P(i, jm), P(i + 1, jm), Wf(i, j), Wf(i + 1, j), e2) : 0.0f;
+    g[1] = i > 0 ? mg_face(P(i - 1, j), p0, P(i - 1, jp), P(i, jp), P(i - 1, jm), P(i, jm), Wf(i - 1, j), Wf(i, j), e2) : 0.0f;
+    g[2] = j + 1 < m ? mg_face(p0, P(i, j + 1), P(ip, j), P(ip, j + 1), P(im, j), P(im, j + 1), Wf(i, j), Wf(i, j + 1), e2) : 0.0f;
+    g[3] = j > 0 ? mg_face(P(i, j - 1), p0, P(ip, j - 1), P(ip, j), P(im, j - 1), P(im, j), Wf(i, j - 1), Wf(i, j), e2) : 0.0f;
+}
+
+__device__ __forceinline__ uint8_t label_of(const float (&G)[4], int n, int m, int i, int j, float Sigma)
+{
+    const bool in[4] = {i + 1 < n, i > 0, j + 1 < m, j > 0};
     int cnt = 0, amin = -1;
     float gmin = 0.0f, gmax = 0.0f;
     for (int s = 0; s < 4; s++) {
@@ -220,6 +226,16 @@ __device__ __forceinline__ uint8_t cell_label(const float *psi, const float *w, 
         cnt++;
     }
     return (cnt >= 2 && gmax > Sigma * gmin) ? (uint8_t)(1u << amin) : (uint8_t)0;
+}
+
+__device__ __forceinline__ uint8_t cell_label(const float *psi, const float *w, int p, int n, int m, int i, int j,
+                                              float e2, float Sigma)
+{
+    auto P = [&](int a, int b) { return psi[(long long)a * p + b]; };
+    auto W = [&](int a, int b) { return w[(long long)a * p + b]; };
+    float G[4];
+    faces4(P, W, n, m, i, j, e2, G);
+    return label_of(G, n, m, i, j, Sigma);
 }
 
 __global__ void k_labels(const float *psi, const float *w, int p, int n, int m, float e2, float Sigma,
@@ -359,15 +375,16 @@ __global__ void k_finalize(const double *partial, int nb, int mode, double N, do
 
 // ==========================================================================
 // FP64 residual on the finest grid (defect-correction loop): r64 = -N64(phi64)
-// (F = 0 there), the projected norm, phi32 = fl32(phi64) and the FP32 right-hand
-// side F~ = N32(phi32) + fl32(r64) of the next FP32 cycle.
+// (F = 0 there), its projected norm, and optionally phi32 = fl32(phi64) (the
+// FP32 mode's next iterate) and G = fl32(r64) unprojected (the deviation
+// form's finest right-hand side).
 struct Res64Args {
     const double *phi64, *w64, *d64;       // dense n x m
     const float *z32, *w32, *fit32; int p32;
     const double *c12, *area;              // area may be null
     double kap, e2, eps, l1, l2, theta, M;
     int model, scaled, n, m;
-    float *phi32, *Ft;                     // outputs (p32); Ft may be null
+    float *phi32, *G;                      // outputs (p32), each may be null
     double *partial;
 };
 
@@ -392,24 +409,6 @@ __device__ double cell_N64(const Res64Args &A, int i, int j, double c1, double c
     return v;
 }
 
-__device__ float cell_N32_of64(const Res64Args &A, int i, int j, float area)
-{
-    const int n = A.n, m = A.m;
-    int im = mg_mirror(i - 1, n), ip = mg_mirror(i + 1, n), jm = mg_mirror(j - 1, m), jp = mg_mirror(j + 1, m);
-    auto P = [&](int a, int b) { return (float)A.phi64[(long long)a * m + b]; };
-    auto W = [&](int a, int b) { return A.w32[(long long)a * A.p32 + b]; };
-    float p0 = P(i, j);
-    float dl = A.scaled ? 1.0f : mg_delta(p0, (float)A.eps);
-    float s = (float)A.kap * dl;
-    float e2 = (float)A.e2;
-    float v = -dl * (A.fit32[(long long)i * A.p32 + j] + area);
-    if (i + 1 < n) v += s * mg_face(p0, P(i + 1, j), P(i, jp), P(i + 1, jp), P(i, jm), P(i + 1, jm), W(i, j), W(i + 1, j), e2) * (P(i + 1, j) - p0);
-    if (i > 0) v += s * mg_face(P(i - 1, j), p0, P(i - 1, jp), P(i, jp), P(i - 1, jm), P(i, jm), W(i - 1, j), W(i, j), e2) * (P(i - 1, j) - p0);
-    if (j + 1 < m) v += s * mg_face(p0, P(i, j + 1), P(ip, j), P(ip, j + 1), P(im, j), P(im, j + 1), W(i, j), W(i, j + 1), e2) * (P(i, j + 1) - p0);
-    if (j > 0) v += s * mg_face(P(i, j - 1), p0, P(ip, j - 1), P(ip, j), P(im, j - 1), P(im, j), W(i, j - 1), W(i, j), e2) * (P(i, j - 1) - p0);
-    return v;
-}
-
 __global__ void k_res64(Res64Args A)
 {
     __shared__ double red[256];
@@ -425,8 +424,8 @@ __global__ void k_res64(Res64Args A)
         if ((ph >= A.M && rp < 0.0) || (ph <= -A.M && rp > 0.0)) rp = 0.0;
         acc = rp * rp;
         long long q = (long long)i * A.p32 + j;
-        A.phi32[q] = (float)ph;
-        if (A.Ft) A.Ft[q] = cell_N32_of64(A, i, j, (float)area) + (float)r;
+        if (A.phi32) A.phi32[q] = (float)ph;
+        if (A.G) A.G[q] = (float)r;
     }
     red[tid] = acc;
     __syncthreads();
@@ -437,23 +436,6 @@ __global__ void k_res64(Res64Args A)
     if (tid == 0) A.partial[(long long)blockIdx.y * gridDim.x + blockIdx.x] = red[0];
 }
 
-// phi64 <- clip(phi64 + (phi32_new - fl32(phi64)), -M, M); a cell that the
-// FP32 cycle left exactly at a bound is put exactly at that bound, so that the
-// projection of the FP64 residual sees it there.
-__global__ void k_defect_update(double *phi64, const float *phi32, int p32, int n, int m, double M)
-{
-    int j = blockIdx.x * blockDim.x + threadIdx.x, i = blockIdx.y;
-    if (j >= m || i >= n) return;
-    long long q = (long long)i * m + j;
-    double v = phi64[q];
-    float p = phi32[(long long)i * p32 + j];
-    v += (double)p - (double)(float)v;
-    if ((double)p >= M) v = M;
-    if ((double)p <= -M) v = -M;
-    phi64[q] = v < -M ? -M : (v > M ? M : v);
-}
-
-// phi64 <- phi32 (pure FP32 mode keeps the finest state in FP32)
 __global__ void k_copy32to64(const float *phi32, int p32, double *phi64, int n, int m)
 {
     int j = blockIdx.x * blockDim.x + threadIdx.x, i = blockIdx.y;
@@ -507,50 +489,246 @@ __global__ void k_eta(const double *phi64, const double *prev, long long N, doub
 // 1x1 coarsest grid: N = -delta(phi)(fit + s(phi)) has no stencil (S = 0);
 // the box-constrained scalar equation N(phi) = F is solved directly: among
 // its solutions (interior roots, or a bound where the residual pushes
-// outward) the one nearest the current value (FP64, one thread).
+// outward) the one nearest the current value (FP64, one thread).  In the
+// deviation form phi = b + e, F = N(b) + G, the bounds are those of e shifted
+// by b, and e = phi - b is stored.
 struct ScalarArgs {
     float *phi; const float *F, *fit, *lo, *hi;
+    const float *base;              // deviation form: base (phi then holds e); null otherwise
     double h2, A1, nu, eps, M;
     int model, scaled;
 };
-__device__ double scalar_r(const ScalarArgs &S, double phi)
+__device__ double scalar_N(const ScalarArgs &S, double phi)
 {
     double s = 0.0;
     if (S.model == 1) s = 2.0 * S.nu * (S.h2 * mg_heav64(phi, S.eps) - S.A1);
     double dl = S.scaled ? 1.0 : mg_delta64(phi, S.eps);
-    double N = -dl * ((double)S.fit[0] + s);
-    return (double)S.F[0] - N;
+    return -dl * ((double)S.fit[0] + s);
 }
 __global__ void k_scalar_solve(ScalarArgs S)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    double lo = S.lo ? (double)S.lo[0] : -S.M, hi = S.hi ? (double)S.hi[0] : S.M;
-    double cur = (double)S.phi[0], best = cur, bestd = 1e300;
+    const double b = S.base ? (double)S.base[0] : 0.0;
+    const double Fv = S.base ? (double)S.F[0] + scalar_N(S, b) : (double)S.F[0];
+    auto R = [&](double x) { return Fv - scalar_N(S, x); };
+    double lo = S.lo ? b + (double)S.lo[0] : -S.M, hi = S.hi ? b + (double)S.hi[0] : S.M;
+    double cur = b + (double)S.phi[0], best = cur, bestd = 1e300;
     const int NS = 4096;
-    if (scalar_r(S, lo) >= 0.0) { best = lo; bestd = fabs(cur - lo); }
-    if (scalar_r(S, hi) <= 0.0 && fabs(hi - cur) < bestd) { best = hi; bestd = fabs(hi - cur); }
-    double a = lo, ra = scalar_r(S, a);
+    if (R(lo) >= 0.0) { best = lo; bestd = fabs(cur - lo); }
+    if (R(hi) <= 0.0 && fabs(hi - cur) < bestd) { best = hi; bestd = fabs(hi - cur); }
+    double a = lo, ra = R(a);
     for (int t = 1; t <= NS && hi > lo; t++) {
-        double b = lo + (hi - lo) * t / NS, rb = scalar_r(S, b);
+        double bb = lo + (hi - lo) * t / NS, rb = R(bb);
         double root = 0.0;
         bool found = false;
         if (ra == 0.0) { root = a; found = true; }
         else if (rb != 0.0 && ((ra < 0.0) != (rb < 0.0))) {
-            double x0 = a, x1 = b, r0 = ra;
+            double x0 = a, x1 = bb, r0 = ra;
             for (int it = 0; it < 200; it++) {
                 double mid = 0.5 * (x0 + x1);
                 if (mid <= x0 || mid >= x1) break;
-                double rm = scalar_r(S, mid);
+                double rm = R(mid);
                 if (rm == 0.0) { x0 = x1 = mid; break; }
                 if ((rm < 0.0) == (r0 < 0.0)) { x0 = mid; r0 = rm; } else x1 = mid;
             }
             root = 0.5 * (x0 + x1); found = true;
         }
         if (found && fabs(root - cur) < bestd) { bestd = fabs(root - cur); best = root; }
-        a = b; ra = rb;
+        a = bb; ra = rb;
     }
     if (ra == 0.0 && fabs(a - cur) < bestd) best = a;
-    S.phi[0] = (float)best;
+    if (S.base) {
+        float e = (float)(best - b);
+        e = fminf(fmaxf(e, S.lo[0]), S.hi[0]);
+        S.phi[0] = e;
+    } else {
+        S.phi[0] = (float)best;
+    }
+}
+
+// ==========================================================================
+// Deviation form (mixed-precision mode).  On every level the state is
+// u = b + e: b a base held fixed while the cycle is on the level (the FP64
+// iterate on the finest grid, the restricted finer state on coarse grids) and
+// e an FP32 deviation that starts at zero.  Writing the level's right-hand
+// side as F = N_b(b) + G (G: the unprojected FP64 residual at b on the finest
+// grid, the restricted projected residual on coarse grids), the frozen
+// equation N_psi(b + e) = F reads, for e,
+//     L_psi e = G + [L_b b - f_b] - [L_psi b - f_psi] =: T,
+// with L_x y = sum over faces of a_f(x) (y_nb - y_p) and f_x = dl(x)(fit + s_x).
+// T is summed in FP64 from FP32 coefficients and base differences, so no
+// rounding of |b| enters and FP32 sweeps on e reach the FP64 fixed point.
+// Cycle start on the finest grid: e = 0 with bounds [-M - b, M - b]; coarse
+// grids: e = 0 with bounds from the finer grid's slack.
+
+// finest-grid cycle start: e = 0, bounds of e = [-M - b, M - b]
+__global__ void k_start0(const double *b, int n, int m, double M, float *e, float *lo, float *hi, int p)
+{
+    int j = blockIdx.x * blockDim.x + threadIdx.x, i = blockIdx.y;
+    if (j >= m || i >= n) return;
+    double v = b[(long long)i * m + j];
+    long long q = (long long)i * p + j;
+    e[q] = 0.0f;
+    lo[q] = (float)(-M - v);
+    hi[q] = (float)(M - v);
+}
+
+// finest-grid cycle end: phi64 = clip(b + e); a deviation at its bound lands
+// exactly on the bound
+__global__ void k_finish0(double *b, const float *e, const float *lo, const float *hi, int p, int n, int m, double M)
+{
+    int j = blockIdx.x * blockDim.x + threadIdx.x, i = blockIdx.y;
+    if (j >= m || i >= n) return;
+    long long q = (long long)i * p + j;
+    double v = b[(long long)i * m + j] + (double)e[q];
+    if (e[q] >= hi[q]) v = M;
+    if (e[q] <= lo[q]) v = -M;
+    b[(long long)i * m + j] = v < -M ? -M : (v > M ? M : v);
+}
+
+template <typename BT>
+struct DevArgs {
+    const BT *b; int pb;                       // base and its row pitch
+    const float *e, *G, *w, *fit, *lo, *hi;    // row pitch p
+    float *psi, *T, *r;                        // outputs (pitch p), null: not written
+    uint8_t *lab;                              // labels (pitch p), null: not written
+    const double *area_b, *area_u;             // Rada-Chen area terms at b and at b + e (null: 0)
+    int p, n, m, scaled;
+    float kap, e2, eps, Sigma;
+};
+
+// T at cell (i, j) with psi = fl32(b + e); with want_Le also L_psi e
+// (FP64 sums of FP32 coefficients); u0 = psi_ij; lab = the cell's label at psi.
+template <typename BT>
+__device__ __forceinline__ double dev_cell(const DevArgs<BT> &A, int i, int j, bool want_Le, double &Le, float &u0,
+                                           uint8_t &lab)
+{
+    const int n = A.n, m = A.m;
+    auto B64 = [&](int a, int c) { return (double)A.b[(long long)a * A.pb + c]; };
+    auto E64 = [&](int a, int c) { return (double)A.e[(long long)a * A.p + c]; };
+    auto Bf = [&](int a, int c) { return (float)A.b[(long long)a * A.pb + c]; };
+    auto Uf = [&](int a, int c) { return (float)(B64(a, c) + E64(a, c)); };
+    auto W = [&](int a, int c) { return A.w[(long long)a * A.p + c]; };
+    float gb[4], gu[4];
+    faces4(Bf, W, n, m, i, j, A.e2, gb);
+    faces4(Uf, W, n, m, i, j, A.e2, gu);
+    const float ub = Bf(i, j);
+    u0 = Uf(i, j);
+    const float dlb = A.scaled ? 1.0f : mg_delta(ub, A.eps), dlu = A.scaled ? 1.0f : mg_delta(u0, A.eps);
+    const float scb = A.kap * dlb, scu = A.kap * dlu;
+    const long long q = (long long)i * A.p + j;
+    const double b0 = B64(i, j), e0 = E64(i, j);
+    const bool in[4] = {i + 1 < n, i > 0, j + 1 < m, j > 0};
+    const int ni[4] = {i + 1, i - 1, i, i}, nj[4] = {j, j, j + 1, j - 1};
+    double t = (double)A.G[q];
+    Le = 0.0;
+#pragma unroll
+    for (int f = 0; f < 4; f++) {
+        if (!in[f]) continue;
+        const float ab = gb[f] * scb, au = gu[f] * scu;
+        t += ((double)ab - (double)au) * (B64(ni[f], nj[f]) - b0);
+        if (want_Le) Le += (double)au * (E64(ni[f], nj[f]) - e0);
+    }
+    const double fit = (double)A.fit[q];
+    const double sb = A.area_b ? *A.area_b : 0.0, su = A.area_u ? *A.area_u : 0.0;
+    t -= (double)dlb * (fit + sb) - (double)dlu * (fit + su);
+    lab = label_of(gu, n, m, i, j, A.Sigma);
+    return t;
+}
+
+// freeze in deviation form: psi = fl32(b + e), T, labels
+template <typename BT>
+__global__ void k_freeze_dev(DevArgs<BT> A)
+{
+    int j = blockIdx.x * blockDim.x + threadIdx.x, i = blockIdx.y;
+    if (j >= A.m || i >= A.n) return;
+    double Le;
+    float u0;
+    uint8_t lab;
+    const double t = dev_cell(A, i, j, false, Le, u0, lab);
+    const long long q = (long long)i * A.p + j;
+    A.psi[q] = u0;
+    A.T[q] = (float)t;
+    A.lab[q] = lab;
+}
+
+// residual in deviation form: r = F - N(b + e) = T(b + e) - L_{b+e} e, projected
+// on the bounds of e (zero where the correction would leave them)
+template <typename BT>
+__global__ void k_res_dev(DevArgs<BT> A)
+{
+    int j = blockIdx.x * blockDim.x + threadIdx.x, i = blockIdx.y;
+    if (j >= A.m || i >= A.n) return;
+    double Le;
+    float u0;
+    uint8_t lab;
+    const double t = dev_cell(A, i, j, true, Le, u0, lab);
+    const long long q = (long long)i * A.p + j;
+    double v = t - Le;
+    const float e = A.e[q];
+    if ((e >= A.hi[q] && v < 0.0) || (e <= A.lo[q] && v > 0.0)) v = 0.0;
+    A.r[q] = (float)v;
+}
+
+// restriction in deviation form: coarse base fl32(FW(b + e)) (FP64 sums),
+// coarse deviation 0, coarse bounds from the fine slack
+//   lo_c = max(lo - e), hi_c = min(hi - e) over fine (2I..2I+2) x (2J..2J+2).
+template <typename BT>
+__device__ __forceinline__ double fw_row_dev(const BT *b, int pb, const float *e, int p, int i, int J, int mc)
+{
+    auto V = [&](int j) { return (double)b[(long long)i * pb + j] + (double)e[(long long)i * p + j]; };
+    if (J < mc - 1) return 0.25 * V(2 * J) + 0.5 * V(2 * J + 1) + 0.25 * V(2 * J + 2);
+    return 0.5 * V(2 * J) + 0.5 * V(2 * J + 1);
+}
+template <typename BT>
+__global__ void k_restrict_dev(const BT *b, int pb, const float *e, const float *lo, const float *hi, int p, int n,
+                               int m, float *bc, float *ec, float *clo, float *chi, int pc, int nc, int mc)
+{
+    int J = blockIdx.x * blockDim.x + threadIdx.x, I = blockIdx.y;
+    if (J >= mc || I >= nc) return;
+    double v;
+    if (I < nc - 1)
+        v = 0.25 * fw_row_dev(b, pb, e, p, 2 * I, J, mc) + 0.5 * fw_row_dev(b, pb, e, p, 2 * I + 1, J, mc) +
+            0.25 * fw_row_dev(b, pb, e, p, 2 * I + 2, J, mc);
+    else
+        v = 0.5 * fw_row_dev(b, pb, e, p, 2 * I, J, mc) + 0.5 * fw_row_dev(b, pb, e, p, 2 * I + 1, J, mc);
+    float dl = -MG_BIG, dh = MG_BIG;
+    for (int i = 2 * I; i <= 2 * I + 2 && i < n; i++)
+        for (int j = 2 * J; j <= 2 * J + 2 && j < m; j++) {
+            long long q = (long long)i * p + j;
+            dl = fmaxf(dl, lo[q] - e[q]);
+            dh = fminf(dh, hi[q] - e[q]);
+        }
+    long long q = (long long)I * pc + J;
+    bc[q] = (float)v;
+    ec[q] = 0.0f;
+    clo[q] = dl;
+    chi[q] = dh;
+}
+
+// sum of H(b + e) over a level (area term of the Rada-Chen model)
+template <typename BT>
+__global__ void k_sums_dev(const BT *b, int pb, const float *e, int p, int n, int m, double eps, double *partial)
+{
+    __shared__ double r0[256];
+    int tid = threadIdx.x;
+    long long N = (long long)n * m;
+    double a0 = 0.0;
+    for (long long t = (long long)blockIdx.x * blockDim.x + tid; t < N; t += (long long)gridDim.x * blockDim.x) {
+        int i = (int)(t / m), j = (int)(t % m);
+        a0 += mg_heav64((double)b[(long long)i * pb + j] + (double)e[(long long)i * p + j], eps);
+    }
+    r0[tid] = a0;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (tid < s) r0[tid] += r0[tid + s];
+        __syncthreads();
+    }
+    if (tid == 0) {
+        partial[3 * blockIdx.x] = r0[0];
+        partial[3 * blockIdx.x + 1] = 0.0;
+        partial[3 * blockIdx.x + 2] = 0.0;
+    }
 }
 
 // ==========================================================================
@@ -559,7 +737,10 @@ __global__ void k_scalar_solve(ScalarArgs S)
 // multi-kernel path, with block barriers in place of kernel boundaries.
 struct CoarseArgs {
     float *P0, *P1, *P2, *T1, *T2, *psi, *psi_cm;
-    const float *w, *w_cm, *fit, *fit_cm, *F, *F_cm, *lo, *lo_cm, *hi, *hi_cm;
+    const float *w, *w_cm, *fit, *fit_cm, *lo, *lo_cm, *hi, *hi_cm;
+    float *F, *F_cm;                // FP32 mode: F (may be null); deviation form: T, written here
+    const float *base, *G;          // deviation form (P0 holds e); null base: FP32 mode
+    const double *area_b;           // deviation form, Rada-Chen: area term at the base
     uint8_t *lab, *lab_cm;
     float *scr; long long scr_field;
     double *area;                   // slot for the area term (Rada-Chen), may be null
@@ -595,33 +776,71 @@ __global__ void __launch_bounds__(NT) k_coarse_smooth(CoarseArgs C)
     T = R;
     T.psi = C.psi_cm; T.w = C.w_cm; T.fit = C.fit_cm; T.F = C.F_cm; T.lab = C.lab_cm; T.lo = C.lo_cm;
     T.hi = C.hi_cm; T.pitch = C.pcm; T.lpitch = C.pcm; T.nl = m; T.ml = n;
+    const bool dev = C.base != nullptr;
+    if (dev) { R.fit = nullptr; T.fit = nullptr; }
+    DevArgs<float> D;
+    D.b = C.base; D.pb = C.prm; D.e = C.P0; D.G = C.G; D.w = C.w; D.fit = C.fit; D.lo = C.lo; D.hi = C.hi;
+    D.psi = nullptr; D.T = nullptr; D.r = nullptr; D.lab = nullptr;
+    D.area_b = C.area_b; D.area_u = C.area;
+    D.p = C.prm; D.n = n; D.m = m; D.scaled = C.scaled;
+    D.kap = C.kap; D.e2 = C.e2; D.eps = (float)C.eps; D.Sigma = C.Sigma;
     for (int it = 0; it < C.iters; it++) {
         // freeze
-        for (int t = tid; t < n * m; t += NT) {
-            int i = t / m, j = t % m;
-            float v = C.P0[(long long)i * C.prm + j];
-            C.psi[(long long)i * C.prm + j] = v;
-            C.psi_cm[(long long)j * C.pcm + i] = v;
-        }
-        __syncthreads();
-        double acc = 0.0;
-        for (int t = tid; t < n * m; t += NT) {
-            int i = t / m, j = t % m;
-            uint8_t b = cell_label(C.psi, C.w, C.prm, n, m, i, j, C.e2, C.Sigma);
-            C.lab[(long long)i * C.prm + j] = b;
-            C.lab_cm[(long long)j * C.pcm + i] = b;
-            acc += mg_heav64((double)C.psi[(long long)i * C.prm + j], C.eps);
-        }
-        if (C.area) {
-            red[tid] = acc;
-            __syncthreads();
-            if (tid == 0) {
-                double s = 0.0;
-                for (int k = 0; k < NT; k++) s += red[k];
-                *C.area = 2.0 * C.nu * (C.h2 * s - C.A1);
+        if (dev) {
+            double acc = 0.0;
+            if (C.area) {
+                for (int t = tid; t < n * m; t += NT) {
+                    long long q = (long long)(t / m) * C.prm + t % m;
+                    acc += mg_heav64((double)C.base[q] + (double)C.P0[q], C.eps);
+                }
+                red[tid] = acc;
+                __syncthreads();
+                if (tid == 0) {
+                    double s = 0.0;
+                    for (int k = 0; k < NT; k++) s += red[k];
+                    *C.area = 2.0 * C.nu * (C.h2 * s - C.A1);
+                }
+                __syncthreads();
             }
+            for (int t = tid; t < n * m; t += NT) {
+                int i = t / m, j = t % m;
+                double Le;
+                float u0;
+                uint8_t b;
+                const double tv = dev_cell(D, i, j, false, Le, u0, b);
+                long long qr = (long long)i * C.prm + j, qc = (long long)j * C.pcm + i;
+                C.psi[qr] = u0; C.psi_cm[qc] = u0;
+                C.F[qr] = (float)tv; C.F_cm[qc] = (float)tv;
+                C.lab[qr] = b; C.lab_cm[qc] = b;
+            }
+            __syncthreads();
+        } else {
+            for (int t = tid; t < n * m; t += NT) {
+                int i = t / m, j = t % m;
+                float v = C.P0[(long long)i * C.prm + j];
+                C.psi[(long long)i * C.prm + j] = v;
+                C.psi_cm[(long long)j * C.pcm + i] = v;
+            }
+            __syncthreads();
+            double acc = 0.0;
+            for (int t = tid; t < n * m; t += NT) {
+                int i = t / m, j = t % m;
+                uint8_t b = cell_label(C.psi, C.w, C.prm, n, m, i, j, C.e2, C.Sigma);
+                C.lab[(long long)i * C.prm + j] = b;
+                C.lab_cm[(long long)j * C.pcm + i] = b;
+                acc += mg_heav64((double)C.psi[(long long)i * C.prm + j], C.eps);
+            }
+            if (C.area) {
+                red[tid] = acc;
+                __syncthreads();
+                if (tid == 0) {
+                    double s = 0.0;
+                    for (int k = 0; k < NT; k++) s += red[k];
+                    *C.area = 2.0 * C.nu * (C.h2 * s - C.A1);
+                }
+            }
+            __syncthreads();
         }
-        __syncthreads();
         // sweeps A and B (rows)
         R.phi_old = C.P0; R.phi_new = C.P1; R.bit = 0;
         for (int b = 0; b < (n + 3) / 4; b++) sweep_band<NT, K, false>(R, b, RBr, RBr, sh, sst, true);
@@ -639,154 +858,3 @@ __global__ void __launch_bounds__(NT) k_coarse_smooth(CoarseArgs C)
     }
 }
 
-// ==========================================================================
-// Finest grid in the mixed-precision mode.  During a cycle the finest state
-// is phi = b + d with b the FP64 iterate at the start of the cycle and d a
-// small FP32 deviation: FP32 sweeps on d reach the FP64 fixed point because d
-// and the frozen equations' right-hand side are small where it matters.
-
-// coefficients of the frozen operator at cell (i, j) from psi = fl32(b + d),
-// with the same FP32 expressions as the line sweep (rm orientation:
-// A = cross +, B = cross -, C = in-line +, D = in-line -)
-__device__ __forceinline__ float psi_bd(const double *b, const float *d, int pd, int m, int i, int j)
-{
-    return (float)(b[(long long)i * m + j] + (double)d[(long long)i * pd + j]);
-}
-
-// psi = fl32(b + d) and F_eff = -(sum_nb coef b_nb - S b_p) in FP64, so that the
-// FP32 sweep of L_psi d - f = F_eff is the frozen equation L_psi (b + d) - f = 0.
-__global__ void k_freeze0(const double *b, const float *d, const float *w, int p, int n, int m, float kap,
-                          float e2, float eps, int scaled, float *psi, float *Feff)
-{
-    int j = blockIdx.x * blockDim.x + threadIdx.x, i = blockIdx.y;
-    if (j >= m || i >= n) return;
-    int im = mg_mirror(i - 1, n), ip = mg_mirror(i + 1, n), jm = mg_mirror(j - 1, m), jp = mg_mirror(j + 1, m);
-    auto P = [&](int a, int c) { return psi_bd(b, d, p, m, a, c); };
-    auto W = [&](int a, int c) { return w[(long long)a * p + c]; };
-    auto Bv = [&](int a, int c) { return b[(long long)a * m + c]; };
-    const float p0 = P(i, j);
-    float xp = 0.0f, xm = 0.0f, lp = 0.0f, lm = 0.0f;
-    if (i + 1 < n) xp = mg_face(p0, P(i + 1, j), P(i, jp), P(i + 1, jp), P(i, jm), P(i + 1, jm), W(i, j), W(i + 1, j), e2);
-    if (i > 0) xm = mg_face(P(i - 1, j), p0, P(i - 1, jp), P(i, jp), P(i - 1, jm), P(i, jm), W(i - 1, j), W(i, j), e2);
-    if (j + 1 < m) lp = mg_face(p0, P(i, j + 1), P(ip, j), P(ip, j + 1), P(im, j), P(im, j + 1), W(i, j), W(i, j + 1), e2);
-    if (j > 0) lm = mg_face(P(i, j - 1), p0, P(ip, j - 1), P(ip, j), P(im, j - 1), P(im, j), W(i, j - 1), W(i, j), e2);
-    const float dl = scaled ? 1.0f : mg_delta(p0, eps);
-    const float sc = kap * dl;
-    xp *= sc; xm *= sc; lp *= sc; lm *= sc;
-    const float S = xp + xm + lp + lm;
-    double acc = -(double)S * Bv(i, j);
-    if (i + 1 < n) acc += (double)xp * Bv(i + 1, j);
-    if (i > 0) acc += (double)xm * Bv(i - 1, j);
-    if (j + 1 < m) acc += (double)lp * Bv(i, j + 1);
-    if (j > 0) acc += (double)lm * Bv(i, j - 1);
-    long long q = (long long)i * p + j;
-    psi[q] = p0;
-    Feff[q] = (float)(-acc);
-}
-
-// cycle start: d = 0, bounds of d = [-M - b, M - b]
-__global__ void k_start0(const double *b, int n, int m, double M, float *d, float *lo, float *hi, int p)
-{
-    int j = blockIdx.x * blockDim.x + threadIdx.x, i = blockIdx.y;
-    if (j >= m || i >= n) return;
-    double v = b[(long long)i * m + j];
-    long long q = (long long)i * p + j;
-    d[q] = 0.0f;
-    lo[q] = (float)(-M - v);
-    hi[q] = (float)(M - v);
-}
-
-// cycle end: phi64 = clip(b + d); a deviation at its bound lands exactly on the bound
-__global__ void k_finish0(double *b, const float *d, const float *lo, const float *hi, int p, int n, int m, double M)
-{
-    int j = blockIdx.x * blockDim.x + threadIdx.x, i = blockIdx.y;
-    if (j >= m || i >= n) return;
-    long long q = (long long)i * p + j;
-    double v = b[(long long)i * m + j] + (double)d[q];
-    if (d[q] >= hi[q]) v = M;
-    if (d[q] <= lo[q]) v = -M;
-    b[(long long)i * m + j] = v < -M ? -M : (v > M ? M : v);
-}
-
-// residual of the finest grid at phi = b + d (coefficients at fl32(phi),
-// differences in FP64), projected on [-M, M]
-__global__ void k_res0(const double *b, const float *d, const float *w, const float *fit, int p, int n, int m,
-                       float kap, float e2, float eps, const double *area, int scaled, double M, float *r)
-{
-    int j = blockIdx.x * blockDim.x + threadIdx.x, i = blockIdx.y;
-    if (j >= m || i >= n) return;
-    int im = mg_mirror(i - 1, n), ip = mg_mirror(i + 1, n), jm = mg_mirror(j - 1, m), jp = mg_mirror(j + 1, m);
-    auto P = [&](int a, int c) { return psi_bd(b, d, p, m, a, c); };
-    auto PH = [&](int a, int c) { return b[(long long)a * m + c] + (double)d[(long long)a * p + c]; };
-    auto W = [&](int a, int c) { return w[(long long)a * p + c]; };
-    const float p0 = P(i, j);
-    const double ph0 = PH(i, j);
-    const float dl = scaled ? 1.0f : mg_delta(p0, eps);
-    const float sc = kap * dl;
-    const float ar = area ? (float)(*area) : 0.0f;
-    double v = -(double)(dl * (fit[(long long)i * p + j] + ar));
-    if (i + 1 < n) v += (double)(sc * mg_face(p0, P(i + 1, j), P(i, jp), P(i + 1, jp), P(i, jm), P(i + 1, jm), W(i, j), W(i + 1, j), e2)) * (PH(i + 1, j) - ph0);
-    if (i > 0) v += (double)(sc * mg_face(P(i - 1, j), p0, P(i - 1, jp), P(i, jp), P(i - 1, jm), P(i, jm), W(i - 1, j), W(i, j), e2)) * (PH(i - 1, j) - ph0);
-    if (j + 1 < m) v += (double)(sc * mg_face(p0, P(i, j + 1), P(ip, j), P(ip, j + 1), P(im, j), P(im, j + 1), W(i, j), W(i, j + 1), e2)) * (PH(i, j + 1) - ph0);
-    if (j > 0) v += (double)(sc * mg_face(P(i, j - 1), p0, P(ip, j - 1), P(ip, j), P(im, j - 1), P(im, j), W(i, j - 1), W(i, j), e2)) * (PH(i, j - 1) - ph0);
-    double rr = -v;
-    if ((ph0 >= M && rr < 0.0) || (ph0 <= -M && rr > 0.0)) rr = 0.0;
-    r[(long long)i * p + j] = (float)rr;
-}
-
-// full weighting of phi = b + d (FP64 sums), and the coarse bounds from the
-// finest cells' slack to [-M, M]
-__device__ __forceinline__ double fw_row_bd(const double *b, const float *d, int p, int m, int i, int J, int mc)
-{
-    auto V = [&](int j) { return b[(long long)i * m + j] + (double)d[(long long)i * p + j]; };
-    if (J < mc - 1) return 0.25 * V(2 * J) + 0.5 * V(2 * J + 1) + 0.25 * V(2 * J + 2);
-    return 0.5 * V(2 * J) + 0.5 * V(2 * J + 1);
-}
-__global__ void k_restrict0(const double *b, const float *d, int p, int n, int m, float *phic, float *clo, float *chi,
-                            int pc, int nc, int mc, double M)
-{
-    int J = blockIdx.x * blockDim.x + threadIdx.x, I = blockIdx.y;
-    if (J >= mc || I >= nc) return;
-    double v;
-    if (I < nc - 1)
-        v = 0.25 * fw_row_bd(b, d, p, m, 2 * I, J, mc) + 0.5 * fw_row_bd(b, d, p, m, 2 * I + 1, J, mc) +
-            0.25 * fw_row_bd(b, d, p, m, 2 * I + 2, J, mc);
-    else
-        v = 0.5 * fw_row_bd(b, d, p, m, 2 * I, J, mc) + 0.5 * fw_row_bd(b, d, p, m, 2 * I + 1, J, mc);
-    double dl = -1e300, dh = 1e300;
-    for (int i = 2 * I; i <= 2 * I + 2 && i < n; i++)
-        for (int j = 2 * J; j <= 2 * J + 2 && j < m; j++) {
-            double ph = b[(long long)i * m + j] + (double)d[(long long)i * p + j];
-            dl = fmax(dl, -M - ph);
-            dh = fmin(dh, M - ph);
-        }
-    long long q = (long long)I * pc + J;
-    float pcv = (float)v;
-    phic[q] = pcv;
-    clo[q] = (float)((double)pcv + dl);
-    chi[q] = (float)((double)pcv + dh);
-}
-
-// sum of H(b + d) over the finest grid (Rada-Chen area term in the mixed mode)
-__global__ void k_sums_bd(const double *b, const float *d, int p, int n, int m, double eps, double *partial)
-{
-    __shared__ double r0[256];
-    int tid = threadIdx.x;
-    long long N = (long long)n * m;
-    double a0 = 0.0;
-    for (long long t = (long long)blockIdx.x * blockDim.x + tid; t < N; t += (long long)gridDim.x * blockDim.x) {
-        int i = (int)(t / m), j = (int)(t % m);
-        a0 += mg_heav64(b[t] + (double)d[(long long)i * p + j], eps);
-    }
-    r0[tid] = a0;
-    __syncthreads();
-    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-        if (tid < s) r0[tid] += r0[tid + s];
-        __syncthreads();
-    }
-    if (tid == 0) {
-        partial[3 * blockIdx.x] = r0[0];
-        partial[3 * blockIdx.x + 1] = 0.0;
-        partial[3 * blockIdx.x + 2] = 0.0;
-    }
-}
