@@ -35,7 +35,7 @@ class _Params(C.Structure):
                 ("sigma_g", C.c_double), ("sigma_d", C.c_double), ("Sigma", C.c_double),
                 ("M", C.c_double), ("nu1", C.c_int), ("nu2", C.c_int), ("levels", C.c_int),
                 ("coarse_iters", C.c_int), ("order", C.c_int), ("smoother", C.c_int),
-                ("obstacle", C.c_int), ("scaled", C.c_int)]
+                ("obstacle", C.c_int), ("scaled", C.c_int), ("run_max", C.c_int)]
 
 
 @dataclass
@@ -61,6 +61,7 @@ class OracleParams:
     smoother: int = 0         # 0 Hybrid Smoother 2, 1 GSLEX-I
     obstacle: int = 1         # 1 coarse corrections bounded by the fine slack
     scaled: int = 1           # 1 each row divided by delta_eps(psi_ij) > 0
+    run_max: int = 4          # 0 maximal runs, else runs cut into near-equal pieces of at most run_max
 
     def to_c(self) -> _Params:
         p = _Params()
@@ -117,7 +118,7 @@ def _load():
         _lib.or_hull.argtypes = [dp, C.c_int, dp]
         _lib.or_box_tridiag.restype = C.c_int
         _lib.or_box_tridiag.argtypes = [C.c_int, dp, dp, dp, dp, dp, dp, dp]
-        _lib.or_line_units.argtypes = [C.POINTER(C.c_uint8), C.c_int, C.c_int, C.POINTER(C.c_int)]
+        _lib.or_line_units.argtypes = [C.POINTER(C.c_uint8), C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int)]
         _lib.or_visit_order.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_long)]
         _lib.or_setup_maps.argtypes = [dp, C.c_int, C.c_int, dp, C.c_int, C.POINTER(_Params),
                                        dp, dp, dp, dp, dp]
@@ -159,11 +160,12 @@ def box_tridiag(lo, di, up, rh, bl, bh):
     return x if ok else None
 
 
-def line_units(labels_line, bit):
-    """Start position of the unit of every position of a line (visit order)."""
+def line_units(labels_line, bit, run_max=0):
+    """Start position of the unit of every position of a line (visit order);
+    run_max 0: maximal runs, else runs cut into pieces of at most run_max."""
     a = np.ascontiguousarray(labels_line, np.uint8)
     out = np.zeros(len(a), np.int32)
-    _load().or_line_units(a.ctypes.data_as(C.POINTER(C.c_uint8)), len(a), bit,
+    _load().or_line_units(a.ctypes.data_as(C.POINTER(C.c_uint8)), len(a), bit, run_max,
                           out.ctypes.data_as(C.POINTER(C.c_int)))
     return out
 

@@ -45,6 +45,7 @@ typedef struct {
     int smoother;       /* 0 = Hybrid Smoother 2, 1 = GSLEX-I                      */
     int obstacle;       /* 1 = coarse corrections bounded by the fine slack        */
     int scaled;         /* 1 = each row divided by its factor delta_eps(psi_ij)    */
+    int run_max;        /* 0 = maximal runs; else longer runs are cut into pieces  */
 } or_params;
 
 typedef struct {
@@ -655,22 +656,32 @@ static void run_update(or_ctx *c, or_level *L, const size_t *px, int len)
 /* pixel in the visit order into its run (Sec. 4.3, Fig. 3 step V); every    */
 /* other pixel is a point unit.  Returns the last position of the unit       */
 /* starting at t (t itself for a point unit).                                */
-static int unit_end(const uint8_t *lab_line, int len, int t, uint8_t bit)
+static int unit_end_max(const uint8_t *lab_line, int len, int t, uint8_t bit, int run_max)
 {
     if (!(lab_line[t] & bit)) return t;
-    int e = t;
+    int t0 = t, e = t;
+    while (t0 > 0 && (lab_line[t0 - 1] & bit)) t0--;
     while (e + 1 < len && (lab_line[e + 1] & bit)) e++;
-    if (e == t && t + 1 < len) e = t + 1;
+    if (e == t && t0 == t && t + 1 < len) return t + 1;
+    int rl = e - t0 + 1;
+    if (run_max <= 0 || rl <= run_max) return e;
+    /* cut into P = ceil(rl / run_max) pieces of near-equal length, longer first */
+    int P = (rl + run_max - 1) / run_max, base = rl / P, extra = rl % P, s = t0;
+    for (int k = 0; k < P; k++) {
+        int pl = base + (k < extra ? 1 : 0);
+        if (t < s + pl) return s + pl - 1;
+        s += pl;
+    }
     return e;
 }
 
 /* test hook: unit structure of a line of labels: writes for every position */
-/* the index of the first position of its unit                              */
-void or_line_units(const uint8_t *lab_line, int len, int bit, int *unit_start)
+/* the index of the first position of its unit (run_max 0: maximal runs)    */
+void or_line_units(const uint8_t *lab_line, int len, int bit, int run_max, int *unit_start)
 {
     int t = 0;
     while (t < len) {
-        int e = unit_end(lab_line, len, t, (uint8_t)(1u << bit));
+        int e = unit_end_max(lab_line, len, t, (uint8_t)(1u << bit), run_max);
         for (int u = t; u <= e; u++) unit_start[u] = t;
         t = e + 1;
     }
@@ -686,7 +697,7 @@ static void sweep_line(or_ctx *c, or_level *L, int s, int r)
     for (int t = 0; t < len; t++) ll[t] = L->lab[line_px(s, L->n, L->m, r, t)];
     int t = 0;
     while (t < len) {
-        int e = unit_end(ll, len, t, (uint8_t)(1u << s));
+        int e = unit_end_max(ll, len, t, (uint8_t)(1u << s), c->p.run_max);
         if (e == t && !(ll[t] & (1u << s))) { point_update(c, L, line_px(s, L->n, L->m, r, t)); t++; continue; }
         int k = 0;
         for (int u = t; u <= e; u++) px[k++] = line_px(s, L->n, L->m, r, u);
@@ -924,7 +935,7 @@ void or_params_default(or_params *p)
     p->model = 0; p->mu = 0.5; p->lambda1 = 6.5025; p->lambda2 = 6.5025;
     p->theta = 4.0; p->nu = 1.0; p->eps = 1.0; p->eps_tv_px = 1.0; p->beta = 16384.0;
     p->sigma_g = 1.0; p->sigma_d = 0.1; p->Sigma = 2.0; p->M = 4.0;
-    p->nu1 = 2; p->nu2 = 2; p->levels = 1; p->coarse_iters = 100; p->order = 1; p->smoother = 0; p->obstacle = 1; p->scaled = 1;
+    p->nu1 = 2; p->nu2 = 2; p->levels = 1; p->coarse_iters = 100; p->order = 1; p->smoother = 0; p->obstacle = 1; p->scaled = 1; p->run_max = 4;
 }
 
 or_ctx *or_create(const double *z, int n, int m, const double *markers, int k, const or_params *p)

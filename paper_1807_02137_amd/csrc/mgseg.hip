@@ -54,7 +54,6 @@ struct mgseg_ctx {
     double *part = nullptr;         // reduction partials
     int part_n = 0;
     float *scr = nullptr;           // run scratch
-    long long scr_field = 0;
     double *hull_d = nullptr, *mk_d = nullptr;
     int hv = 0, k = 0;
     std::vector<void *> allocs;
@@ -234,7 +233,7 @@ void launch_sweep(mgseg_ctx *c, int l, int s, const float *phi_old, float *phi_n
     const bool bnd = l > 0 || devm(c);
     A.lo = bnd ? (cm ? L.lo_cm : L.lo) : nullptr;
     A.hi = bnd ? (cm ? L.hi_cm : L.hi) : nullptr;
-    A.scr = c->scr; A.scr_field = c->scr_field;
+    A.scr = c->scr;
     A.area = c->p.model == 1 ? c->dsc + DS_AREA_FRZ : nullptr;
     A.pitch = cm ? L.pcm : L.prm;
     A.lpitch = A.pitch;
@@ -398,7 +397,7 @@ void coarsest(mgseg_ctx *c, int l)
         C.base = dev ? L.phic : nullptr; C.G = dev ? L.G : nullptr;
         C.area_b = dev && c->p.model == 1 ? c->dsc + area_b_slot(l) : nullptr;
         C.lo = L.lo; C.lo_cm = L.lo_cm; C.hi = L.hi; C.hi_cm = L.hi_cm;
-        C.lab = L.lab; C.lab_cm = L.lab_cm; C.scr = c->scr; C.scr_field = c->scr_field;
+        C.lab = L.lab; C.lab_cm = L.lab_cm;
         C.area = c->p.model == 1 ? c->dsc + DS_AREA_FRZ : nullptr;
         C.h2 = L.h * L.h; C.A1 = c->A1; C.nu = c->p.nu; C.eps = c->p.eps;
         C.n = L.n; C.m = L.m; C.prm = L.prm; C.pcm = L.pcm; C.iters = c->p.coarse_iters; C.scaled = c->p.scaled;
@@ -636,8 +635,11 @@ mgseg_status mgseg_setup(const float *image_dev, int n, int m, int pitch, const 
     c->dsc = dalloc<double>(c, DS_COUNT);
     c->part_n = 8 * RED_BLOCKS + (int)((N + 255) / 256) + n + 16;
     c->part = dalloc<double>(c, (size_t)c->part_n);
-    c->scr_field = (long long)N;
-    c->scr = dalloc<float>(c, (size_t)2 * SF_COUNT * N);
+    // unit rows of lines longer than the LDS holds: one plane per band
+    size_t scr_n = 1;
+    if (std::max(n, m) > RB_LDS_MAX)
+        scr_n = (size_t)RF_COUNT * std::max((size_t)((n + 3) / 4) * m, (size_t)((m + 3) / 4) * n);
+    c->scr = dalloc<float>(c, scr_n);
     double *zb = dalloc<double>(c, N), *t64 = dalloc<double>(c, N);
     c->mk_d = dalloc<double>(c, 2 * (size_t)k);
     c->hull_d = dalloc<double>(c, 2 * (size_t)k + 2);

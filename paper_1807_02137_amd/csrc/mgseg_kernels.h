@@ -742,7 +742,6 @@ struct CoarseArgs {
     const float *base, *G;          // deviation form (P0 holds e); null base: FP32 mode
     const double *area_b;           // deviation form, Rada-Chen: area term at the base
     uint8_t *lab, *lab_cm;
-    float *scr; long long scr_field;
     double *area;                   // slot for the area term (Rada-Chen), may be null
     double h2, A1, nu, eps;
     int n, m, prm, pcm, iters, scaled;
@@ -763,15 +762,15 @@ __global__ void __launch_bounds__(NT) k_coarse_smooth(CoarseArgs C)
 {
     __shared__ Ramp sh[NT / 64 > 0 ? NT / 64 : 1];
     __shared__ double red[NT];
-    __shared__ float rb[SF_COUNT * NT * K];
-    __shared__ uint8_t sst[NT * K];
+    __shared__ float rb[RF_COUNT * NT * K];
+    __shared__ uint64_t msk[(NT * K + 63) / 64];
     RunBuf RBr, RBc;
-    RBr.p = rb; RBr.fs = C.m; RBr.base = 0;
-    RBc.p = rb; RBc.fs = C.n; RBc.base = 0;
+    RBr.p = rb; RBr.fs = C.m;
+    RBc.p = rb; RBc.fs = C.n;
     const int n = C.n, m = C.m, tid = threadIdx.x;
     LineArgs R, T;
     R.psi = C.psi; R.w = C.w; R.fit = C.fit; R.F = C.F; R.lab = C.lab; R.lo = C.lo; R.hi = C.hi;
-    R.scr = C.scr; R.scr_field = C.scr_field; R.area = C.area; R.pitch = C.prm; R.lpitch = C.prm;
+    R.scr = nullptr; R.area = C.area; R.pitch = C.prm; R.lpitch = C.prm;
     R.nl = n; R.ml = m; R.kap = C.kap; R.e2 = C.e2; R.M = C.M; R.eps = (float)C.eps; R.scaled = C.scaled;
     T = R;
     T.psi = C.psi_cm; T.w = C.w_cm; T.fit = C.fit_cm; T.F = C.F_cm; T.lab = C.lab_cm; T.lo = C.lo_cm;
@@ -843,16 +842,16 @@ __global__ void __launch_bounds__(NT) k_coarse_smooth(CoarseArgs C)
         }
         // sweeps A and B (rows)
         R.phi_old = C.P0; R.phi_new = C.P1; R.bit = 0;
-        for (int b = 0; b < (n + 3) / 4; b++) sweep_band<NT, K, false>(R, b, RBr, RBr, sh, sst, true);
+        for (int b = 0; b < (n + 3) / 4; b++) sweep_band<NT, K, false>(R, b, RBr, msk, sh);
         R.phi_old = C.P1; R.phi_new = C.P2; R.bit = 1;
-        for (int b = 0; b < (n + 3) / 4; b++) sweep_band<NT, K, true>(R, b, RBr, RBr, sh, sst, true);
+        for (int b = 0; b < (n + 3) / 4; b++) sweep_band<NT, K, true>(R, b, RBr, msk, sh);
         block_transpose<NT>(C.P2, C.prm, C.T1, C.pcm, n, m);
         __syncthreads();
         // sweeps C and D (columns)
         T.phi_old = C.T1; T.phi_new = C.T2; T.bit = 2;
-        for (int b = 0; b < (m + 3) / 4; b++) sweep_band<NT, K, false>(T, b, RBc, RBc, sh, sst, true);
+        for (int b = 0; b < (m + 3) / 4; b++) sweep_band<NT, K, false>(T, b, RBc, msk, sh);
         T.phi_old = C.T2; T.phi_new = C.T1; T.bit = 3;
-        for (int b = 0; b < (m + 3) / 4; b++) sweep_band<NT, K, true>(T, b, RBc, RBc, sh, sst, true);
+        for (int b = 0; b < (m + 3) / 4; b++) sweep_band<NT, K, true>(T, b, RBc, msk, sh);
         block_transpose<NT>(C.T1, C.pcm, C.P0, C.prm, m, n);
         __syncthreads();
     }

@@ -255,6 +255,32 @@ def test_fig3_units():
     assert list(line_units(end, 0)) == [0, 1, 2, 3, 4]
 
 
+def test_long_runs_cut_into_near_equal_pieces():
+    """Runs longer than run_max become ceil(len / run_max) contiguous pieces covering the
+    run, lengths differing by at most one (longer first), none a single cell; shorter runs
+    and the single-cell rule are unchanged (run_max >= 3)."""
+    for rm in (3, 4, 8):
+        for rl in range(1, 41):
+            line = np.zeros(rl + 3, np.uint8)
+            line[1:1 + rl] = 1
+            u = line_units(line, 0, rm)
+            starts = sorted(set(u[1:1 + rl]))
+            lens = [int((u[1:1 + rl] == s0).sum()) for s0 in starts]
+            assert starts[0] == 1 and sum(lens) == rl
+            assert all(np.all(u[s0:s0 + ln] == s0) for s0, ln in zip(starts, lens))
+            if rl == 1:
+                assert list(u[1:3]) == [1, 1]              # the single star takes its successor
+            elif rl <= rm:
+                assert lens == [rl]
+            else:
+                assert len(lens) == -(-rl // rm)
+                assert max(lens) <= rm and min(lens) >= 2 and max(lens) - min(lens) <= 1
+                assert lens == sorted(lens, reverse=True)
+            assert u[1 + rl + 1] == 1 + rl + 1              # the cell after the run's successor is a point
+    # maximal runs with run_max = 0
+    assert list(line_units(np.array([1] * 9 + [0], np.uint8), 0, 0)) == [0] * 9 + [9]
+
+
 def test_fig4_visit_orders():
     """Fig. 4: the labels of the four sweeps on a 5 x 5 grid (x = column, y = row from the bottom)."""
     n = 5
