@@ -70,9 +70,12 @@ typedef struct {
     double M;               /* bound |phi| <= M                                      */
     int32_t nu1, nu2;       /* pre/post smoothing: Hybrid-2 outer iterations         */
     int32_t levels;         /* grids including the finest; 0 = as many as fit        */
-    int32_t coarse_iters;   /* outer iterations on the coarsest grid                 */
+    int32_t coarse_iters;   /* most outer iterations on the coarsest grid            */
     int32_t mixed_precision;/* 1: FP32 cycles + FP64 finest defect correction        */
     int32_t scaled;         /* 1: each equation row divided by delta_eps(psi_ij)     */
+    double coarse_rtol;     /* coarsest solve stops once an outer iteration moves no */
+                            /* value by more than coarse_rtol times the largest      */
+                            /* total change since that solve began                   */
 } mgseg_params;
 
 typedef struct {
@@ -150,7 +153,7 @@ mgseg_status mgseg_debug_set_c(mgseg_ctx *c, double c1, double c2);
 /* op: 0 freeze (coefficients, labels and psi at the current phi),
  *     1..4 one sweep A..D of Hybrid Smoother 2 with the current freeze,
  *     5 `arg` outer iterations (freeze + 4 sweeps),
- *     6 the coarsest-grid solve on this level,
+ *     6 the coarsest-grid solve (level must be the coarsest),
  *     7 the V-cycle from this level down (F of this level as set),
  *     8 residual r = F - N(phi), projected (result in field F of the next
  *       debug_get with field 11 = residual),

@@ -34,7 +34,7 @@ class _Params(C.Structure):
                 ("eps", C.c_double), ("eps_tv_px", C.c_double), ("beta", C.c_double),
                 ("sigma_g", C.c_double), ("sigma_d", C.c_double), ("Sigma", C.c_double),
                 ("M", C.c_double), ("nu1", C.c_int), ("nu2", C.c_int), ("levels", C.c_int),
-                ("coarse_iters", C.c_int), ("order", C.c_int), ("smoother", C.c_int),
+                ("coarse_iters", C.c_int), ("coarse_rtol", C.c_double), ("order", C.c_int), ("smoother", C.c_int),
                 ("obstacle", C.c_int), ("scaled", C.c_int), ("run_max", C.c_int)]
 
 
@@ -56,7 +56,8 @@ class OracleParams:
     nu1: int = 2
     nu2: int = 2
     levels: int = 1
-    coarse_iters: int = 100
+    coarse_iters: int = 10
+    coarse_rtol: float = 1e-4  # coarsest solve stops when an iteration moves nothing by more than this share
     order: int = 1            # 0 paper lexicographic lines, 1 four-class line order
     smoother: int = 0         # 0 Hybrid Smoother 2, 1 GSLEX-I
     obstacle: int = 1         # 1 coarse corrections bounded by the fine slack

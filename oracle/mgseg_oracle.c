@@ -40,7 +40,10 @@ typedef struct {
     double M;           /* box bound |phi| <= M (projection)                       */
     int nu1, nu2;       /* pre / post smoothing: Hybrid-2 outer iterations         */
     int levels;         /* number of grids including the finest                    */
-    int coarse_iters;   /* outer iterations of the coarsest-grid solve             */
+    int coarse_iters;   /* most outer iterations of the coarsest-grid solve        */
+    double coarse_rtol; /* coarsest solve stops once an outer iteration moves no   */
+                        /* value by more than coarse_rtol times the largest total  */
+                        /* change since the solve began                            */
     int order;          /* 0 = paper lexicographic line order, 1 = 4-colour line order */
     int smoother;       /* 0 = Hybrid Smoother 2, 1 = GSLEX-I                      */
     int obstacle;       /* 1 = coarse corrections bounded by the fine slack        */
@@ -825,7 +828,20 @@ static void coarsest(or_ctx *c, int l)
 {
     or_level *L = &c->lev[l];
     if (L->n * L->m == 1) { scalar_solve(c, l); return; }
-    smooth(c, l, c->p.coarse_iters);
+    size_t N = (size_t)L->n * L->m;
+    double *x0 = dalloc(N), *prev = dalloc(N);
+    memcpy(x0, L->phi, sizeof(double) * N);
+    for (int it = 0; it < c->p.coarse_iters; it++) {
+        memcpy(prev, L->phi, sizeof(double) * N);
+        smooth(c, l, 1);
+        double dmax = 0.0, tot = 0.0;
+        for (size_t q = 0; q < N; q++) {
+            dmax = fmax(dmax, fabs(L->phi[q] - prev[q]));
+            tot = fmax(tot, fabs(L->phi[q] - x0[q]));
+        }
+        if (dmax <= c->p.coarse_rtol * tot) break;
+    }
+    free(x0); free(prev);
 }
 
 static double l2(const double *v, size_t N)
@@ -935,7 +951,7 @@ void or_params_default(or_params *p)
     p->model = 0; p->mu = 0.5; p->lambda1 = 6.5025; p->lambda2 = 6.5025;
     p->theta = 4.0; p->nu = 1.0; p->eps = 1.0; p->eps_tv_px = 1.0; p->beta = 16384.0;
     p->sigma_g = 1.0; p->sigma_d = 0.1; p->Sigma = 2.0; p->M = 4.0;
-    p->nu1 = 2; p->nu2 = 2; p->levels = 1; p->coarse_iters = 100; p->order = 1; p->smoother = 0; p->obstacle = 1; p->scaled = 1; p->run_max = 4;
+    p->nu1 = 2; p->nu2 = 2; p->levels = 1; p->coarse_iters = 10; p->coarse_rtol = 1e-4; p->order = 1; p->smoother = 0; p->obstacle = 1; p->scaled = 1; p->run_max = 4;
 }
 
 or_ctx *or_create(const double *z, int n, int m, const double *markers, int k, const or_params *p)

@@ -23,7 +23,8 @@ enum {
     DS_AREA64 = 4,            // area term at the FP64 finest phi
     DS_RES = 5,               // last residual norm
     DS_AREAB0 = 8,            // deviation form: area term at the base of level l is slot DS_AREAB0 + l
-    DS_COUNT = 8 + MAXLEV
+    DS_CO = 8 + MAXLEV,       // coarsest-solve changes (2 slots)
+    DS_COUNT = 8 + MAXLEV + 2
 };
 
 struct Level {
@@ -53,7 +54,8 @@ struct mgseg_ctx {
     double *dsc = nullptr;          // device scalars
     double *part = nullptr;         // reduction partials
     int part_n = 0;
-    float *scr = nullptr;           // run scratch
+    float *scr = nullptr;           // unit-row scratch of long lines
+    float *co_prev = nullptr, *co_entry = nullptr;   // multi-kernel coarsest solve
     double *hull_d = nullptr, *mk_d = nullptr;
     int hv = 0, k = 0;
     std::vector<void *> allocs;
@@ -162,7 +164,7 @@ void area_term(mgseg_ctx *c, int l, const float *phi, int pp, int slot)
     int nb = std::min(RED_BLOCKS, std::max(1, (L.n * L.m + 255) / 256));
     hipLaunchKernelGGL(k_sums<float>, dim3(nb), dim3(256), 0, c->s, phi, pp, (const float *)nullptr, 0, L.n, L.m,
                        c->p.eps, c->part);
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, c->s, c->part, nb, 0, (double)L.n * L.m, L.h * L.h, c->A1,
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FIN_NT), 0, c->s, c->part, nb, 0, (double)L.n * L.m, L.h * L.h, c->A1,
                        c->p.nu, c->dsc + slot);
 }
 
@@ -171,8 +173,8 @@ void update_fit(mgseg_ctx *c)
     for (int l = 0; l < c->L; l++) {
         Level &L = c->lev[l];
         hipLaunchKernelGGL(k_fit, grid2(L.n, L.m), dim3(256), 0, c->s, L.z, L.d, L.prm, L.n, L.m, c->dsc + DS_C1,
-                           (float)c->p.lambda1, (float)c->p.lambda2, (float)c->p.theta, c->p.model, L.fit);
-        transpose_f(c, L.fit, L.prm, L.fit_cm, L.pcm, L.n, L.m);
+                           (float)c->p.lambda1, (float)c->p.lambda2, (float)c->p.theta, c->p.model, L.fit, L.fit_cm,
+                           L.pcm);
     }
 }
 
@@ -183,7 +185,7 @@ void update_c(mgseg_ctx *c)
     int nb = std::min(RED_BLOCKS, std::max(1, (c->n * c->m + 255) / 256));
     hipLaunchKernelGGL(k_sums<double>, dim3(nb), dim3(256), 0, c->s, c->phi64, c->m, L.z, L.prm, c->n, c->m,
                        c->p.eps, c->part);
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, c->s, c->part, nb, 1, (double)c->n * c->m, 0.0, 0.0, 0.0,
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FIN_NT), 0, c->s, c->part, nb, 1, (double)c->n * c->m, 0.0, 0.0, 0.0,
                        c->dsc + DS_C1);
     update_fit(c);
 }
@@ -197,7 +199,7 @@ void res64(mgseg_ctx *c)
         int nb = std::min(RED_BLOCKS, std::max(1, (c->n * c->m + 255) / 256));
         hipLaunchKernelGGL(k_sums<double>, dim3(nb), dim3(256), 0, c->s, c->phi64, c->m, (const float *)nullptr, 0,
                            c->n, c->m, c->p.eps, c->part);
-        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, c->s, c->part, nb, 0, (double)c->n * c->m,
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FIN_NT), 0, c->s, c->part, nb, 0, (double)c->n * c->m,
                            L.h * L.h, c->A1, c->p.nu, c->dsc + DS_AREA64);
     }
     Res64Args A;
@@ -212,19 +214,20 @@ void res64(mgseg_ctx *c)
     A.partial = c->part;
     dim3 g = grid2(c->n, c->m);
     hipLaunchKernelGGL(k_res64, g, dim3(256), 0, c->s, A);
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, c->s, c->part, (int)(g.x * g.y), 2, 0.0, 0.0, 0.0, 0.0,
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FIN_NT), 0, c->s, c->part, (int)(g.x * g.y), 2, 0.0, 0.0, 0.0, 0.0,
                        c->dsc + DS_RES);
 }
 
 // --------------------------------------------------------------------------
 // one directional sweep on level l: s = 0 (A), 1 (B) row-major, 2 (C), 3 (D)
 // column-major; phi_old -> phi_new in the layout of the sweep
-void launch_sweep(mgseg_ctx *c, int l, int s, const float *phi_old, float *phi_new)
+void launch_sweep(mgseg_ctx *c, int l, int s, const float *phi_old, float *phi_new, float *tout = nullptr,
+                  int tpitch = 0)
 {
     Level &L = c->lev[l];
     bool cm = s >= 2;
     LineArgs A;
-    A.phi_old = phi_old; A.phi_new = phi_new;
+    A.phi_old = phi_old; A.phi_new = phi_new; A.tout = tout; A.tpitch = tpitch;
     A.psi = cm ? L.psi_cm : L.psi;
     A.w = cm ? L.w_cm : L.w;
     A.fit = devm(c) ? nullptr : (cm ? L.fit_cm : L.fit);
@@ -297,6 +300,7 @@ DevArgs<BT> dev_args(mgseg_ctx *c, int l, const BT *b, int pb)
     A.b = b; A.pb = pb;
     A.e = L.P[0]; A.G = L.G; A.w = L.w; A.fit = L.fit; A.lo = L.lo; A.hi = L.hi;
     A.psi = L.psi; A.T = L.F; A.r = L.r; A.lab = L.lab;
+    A.psi_cm = nullptr; A.T_cm = nullptr; A.lab_cm = nullptr; A.pc = L.pcm;
     A.area_b = c->p.model == 1 ? c->dsc + area_b_slot(l) : nullptr;
     A.area_u = nullptr;
     A.p = L.prm; A.n = L.n; A.m = L.m; A.scaled = c->p.scaled;
@@ -321,7 +325,7 @@ void dev_area(mgseg_ctx *c, int l, int slot)
     else
         hipLaunchKernelGGL(k_sums_dev<float>, dim3(nb), dim3(256), 0, c->s, L.phic, L.prm, L.P[0], L.prm, L.n, L.m,
                            c->p.eps, c->part);
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, c->s, c->part, nb, 0, (double)L.n * L.m, L.h * L.h, c->A1,
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FIN_NT), 0, c->s, c->part, nb, 0, (double)L.n * L.m, L.h * L.h, c->A1,
                        c->p.nu, c->dsc + slot);
 }
 
@@ -336,20 +340,15 @@ void freeze(mgseg_ctx *c, int l)
         with_dev(c, l, [&](auto A) {
             using BT = std::remove_const_t<std::remove_pointer_t<decltype(A.b)>>;
             A.area_u = rc ? c->dsc + DS_AREA_FRZ : nullptr;
+            A.psi_cm = L.psi_cm; A.T_cm = L.F_cm; A.lab_cm = L.lab_cm;
             hipLaunchKernelGGL(k_freeze_dev<BT>, grid2(L.n, L.m), dim3(256), 0, c->s, A);
         });
-        transpose_f(c, L.psi, L.prm, L.psi_cm, L.pcm, L.n, L.m);
-        transpose_f(c, L.F, L.prm, L.F_cm, L.pcm, L.n, L.m);
-        transpose_u8(c, L.lab, L.prm, L.lab_cm, L.pcm, L.n, L.m);
         L.has_F = true;
         chk(c);
         return;
     }
-    (void)hipMemcpyAsync(L.psi, L.P[0], sizeof(float) * (size_t)L.n * L.prm, hipMemcpyDeviceToDevice, c->s);
-    transpose_f(c, L.psi, L.prm, L.psi_cm, L.pcm, L.n, L.m);
-    hipLaunchKernelGGL(k_labels, grid2(L.n, L.m), dim3(256), 0, c->s, L.psi, L.w, L.prm, L.n, L.m, lev_e2(c, l),
-                       (float)c->p.Sigma, L.lab, L.prm);
-    transpose_u8(c, L.lab, L.prm, L.lab_cm, L.pcm, L.n, L.m);
+    hipLaunchKernelGGL(k_freeze32, grid2(L.n, L.m), dim3(256), 0, c->s, L.P[0], L.w, L.prm, L.n, L.m, lev_e2(c, l),
+                       (float)c->p.Sigma, L.psi, L.psi_cm, L.lab, L.lab_cm, L.pcm);
     if (c->p.model == 1) area_term(c, l, L.psi, L.prm, DS_AREA_FRZ);
     chk(c);
 }
@@ -360,11 +359,9 @@ void outer(mgseg_ctx *c, int l)
     Level &L = c->lev[l];
     freeze(c, l);
     launch_sweep(c, l, 0, L.P[0], L.P[1]);
-    launch_sweep(c, l, 1, L.P[1], L.P[2]);
-    transpose_f(c, L.P[2], L.prm, L.T[1], L.pcm, L.n, L.m);
+    launch_sweep(c, l, 1, L.P[1], nullptr, L.T[1], L.pcm);     // written column-major
     launch_sweep(c, l, 2, L.T[1], L.T[2]);
-    launch_sweep(c, l, 3, L.T[2], L.T[1]);
-    transpose_f(c, L.T[1], L.pcm, L.P[0], L.prm, L.m, L.n);
+    launch_sweep(c, l, 3, L.T[2], nullptr, L.P[0], L.prm);     // written row-major
     chk(c);
 }
 
@@ -388,26 +385,36 @@ void coarsest(mgseg_ctx *c, int l)
         chk(c);
         return;
     }
-    if (L.n <= 64 && L.m <= 64 && l > 0) {
+    if (L.n <= 64 && L.m <= 64 && L.n * L.m <= CO_MAX_CELLS && l > 0) {
         CoarseArgs C;
-        C.P0 = L.P[0]; C.P1 = L.P[1]; C.P2 = L.P[2]; C.T1 = L.T[1]; C.T2 = L.T[2];
-        C.psi = L.psi; C.psi_cm = L.psi_cm;
-        C.w = L.w; C.w_cm = L.w_cm; C.fit = L.fit; C.fit_cm = L.fit_cm;
-        C.F = (dev || L.has_F) ? L.F : nullptr; C.F_cm = (dev || L.has_F) ? L.F_cm : nullptr;
+        C.P0 = L.P[0]; C.w = L.w; C.fit = L.fit; C.lo = L.lo; C.hi = L.hi;
+        C.F = (!dev && L.has_F) ? L.F : nullptr;
         C.base = dev ? L.phic : nullptr; C.G = dev ? L.G : nullptr;
         C.area_b = dev && c->p.model == 1 ? c->dsc + area_b_slot(l) : nullptr;
-        C.lo = L.lo; C.lo_cm = L.lo_cm; C.hi = L.hi; C.hi_cm = L.hi_cm;
-        C.lab = L.lab; C.lab_cm = L.lab_cm;
         C.area = c->p.model == 1 ? c->dsc + DS_AREA_FRZ : nullptr;
         C.h2 = L.h * L.h; C.A1 = c->A1; C.nu = c->p.nu; C.eps = c->p.eps;
-        C.n = L.n; C.m = L.m; C.prm = L.prm; C.pcm = L.pcm; C.iters = c->p.coarse_iters; C.scaled = c->p.scaled;
+        C.n = L.n; C.m = L.m; C.prm = L.prm; C.iters = c->p.coarse_iters; C.scaled = c->p.scaled;
         C.kap = (float)(c->p.mu / L.h); C.e2 = lev_e2(c, l); C.M = (float)c->p.M; C.Sigma = (float)c->p.Sigma;
-        hipLaunchKernelGGL((k_coarse_smooth<64, 1>), dim3(1), dim3(64), 0, c->s, C);
-        if (dev) L.has_F = true;
+        C.rtol = (float)c->p.coarse_rtol;
+        hipLaunchKernelGGL((k_coarse_smooth<64>), dim3(1), dim3(64), coarse_lds_bytes(L.n, L.m), c->s, C);
         chk(c);
         return;
     }
-    smooth(c, l, c->p.coarse_iters);
+    // multi-kernel path: one outer iteration per step, with the stopping test
+    // read back after each
+    const size_t bytes = sizeof(float) * (size_t)L.n * L.prm;
+    (void)hipMemcpyAsync(c->co_entry, L.P[0], bytes, hipMemcpyDeviceToDevice, c->s);
+    for (int it = 0; it < c->p.coarse_iters; it++) {
+        (void)hipMemcpyAsync(c->co_prev, L.P[0], bytes, hipMemcpyDeviceToDevice, c->s);
+        outer(c, l);
+        hipLaunchKernelGGL(k_coarse_delta, dim3(1), dim3(256), 0, c->s, L.P[0], c->co_prev, c->co_entry, L.prm, L.n,
+                           L.m, c->dsc + DS_CO);
+        double d[2] = {0.0, 0.0};
+        (void)hipMemcpyAsync(d, c->dsc + DS_CO, sizeof(d), hipMemcpyDeviceToHost, c->s);
+        if (hipStreamSynchronize(c->s) != hipSuccess) { chk(c); return; }
+        if (d[0] <= c->p.coarse_rtol * d[1]) break;
+    }
+    chk(c);
 }
 
 void residual(mgseg_ctx *c, int l, float *r, double *partial)
@@ -450,7 +457,8 @@ void vcycle_from(mgseg_ctx *c, int l0)
             with_dev(c, l, [&](auto A) {
                 using BT = std::remove_const_t<std::remove_pointer_t<decltype(A.b)>>;
                 hipLaunchKernelGGL(k_restrict_dev<BT>, gc, dim3(256), 0, c->s, A.b, A.pb, L.P[0], L.lo, L.hi, L.prm,
-                                   L.n, L.m, Lc.phic, Lc.P[0], Lc.lo, Lc.hi, Lc.prm, Lc.n, Lc.m);
+                                   L.n, L.m, Lc.phic, Lc.P[0], Lc.lo, Lc.hi, Lc.prm, Lc.n, Lc.m, Lc.lo_cm, Lc.hi_cm,
+                                   Lc.pcm);
             });
             if (c->p.model == 1) area_term(c, l + 1, Lc.phic, Lc.prm, DS_AREAB0 + l + 1);
         } else {
@@ -464,10 +472,10 @@ void vcycle_from(mgseg_ctx *c, int l0)
                                (float)(c->p.mu / Lc.h), lev_e2(c, l + 1), (float)c->p.eps,
                                c->p.model == 1 ? c->dsc + DS_AREA_EVAL : nullptr, c->p.scaled, Lc.F, Lc.P[0]);
             transpose_f(c, Lc.F, Lc.prm, Lc.F_cm, Lc.pcm, Lc.n, Lc.m);
+            transpose_f(c, Lc.lo, Lc.prm, Lc.lo_cm, Lc.pcm, Lc.n, Lc.m);
+            transpose_f(c, Lc.hi, Lc.prm, Lc.hi_cm, Lc.pcm, Lc.n, Lc.m);
             Lc.has_F = true;
         }
-        transpose_f(c, Lc.lo, Lc.prm, Lc.lo_cm, Lc.pcm, Lc.n, Lc.m);
-        transpose_f(c, Lc.hi, Lc.prm, Lc.hi_cm, Lc.pcm, Lc.n, Lc.m);
         chk(c);
     }
     coarsest(c, c->L - 1);
@@ -515,9 +523,7 @@ mgseg_status one_cycle(mgseg_ctx *c, double *rel_out)
     dim3 g = grid2(c->n, c->m);
     if (c->p.mixed_precision) {
         hipLaunchKernelGGL(k_start0, g, dim3(256), 0, c->s, c->phi64, c->n, c->m, c->p.M, L0.P[0], L0.lo, L0.hi,
-                           L0.prm);
-        transpose_f(c, L0.lo, L0.prm, L0.lo_cm, L0.pcm, L0.n, L0.m);
-        transpose_f(c, L0.hi, L0.prm, L0.hi_cm, L0.pcm, L0.n, L0.m);
+                           L0.prm, L0.lo_cm, L0.hi_cm, L0.pcm);
     }
     vcycle_from(c, 0);
     if (c->p.mixed_precision)
@@ -559,8 +565,8 @@ void mgseg_params_default(mgseg_params *p)
     p->model = MGSEG_SPENCER_CHEN;
     p->mu = 0.5; p->lambda1 = 6.5025; p->lambda2 = 6.5025; p->theta = 4.0; p->nu = 1.0;
     p->eps = 1.0; p->eps_tv_px = 1.0; p->beta = 16384.0; p->sigma_g = 1.0; p->sigma_d = 0.1;
-    p->Sigma = 2.0; p->M = 4.0; p->nu1 = 2; p->nu2 = 2; p->levels = 0; p->coarse_iters = 100;
-    p->mixed_precision = 1; p->scaled = 1;
+    p->Sigma = 2.0; p->M = 4.0; p->nu1 = 2; p->nu2 = 2; p->levels = 0; p->coarse_iters = 10;
+    p->mixed_precision = 1; p->scaled = 1; p->coarse_rtol = 1e-4;
 }
 
 const char *mgseg_strerror(mgseg_status s)
@@ -594,7 +600,7 @@ mgseg_status mgseg_setup(const float *image_dev, int n, int m, int pitch, const 
     *out = nullptr;
     if (!image_dev || !markers_host || !p || k < 1 || k > 64 || n < 1 || m < 1 || pitch < m) return MGSEG_E_ARG;
     if (p->struct_size != sizeof(mgseg_params)) return MGSEG_E_ARG;
-    if (p->nu1 < 0 || p->nu2 < 0 || p->coarse_iters < 0 || !(p->M > 0.0) || !(p->eps > 0.0) || p->levels < 0 ||
+    if (p->nu1 < 0 || p->nu2 < 0 || p->coarse_iters < 0 || !(p->coarse_rtol >= 0.0) || !(p->M > 0.0) || !(p->eps > 0.0) || p->levels < 0 ||
         p->levels > MAXLEV)
         return MGSEG_E_ARG;
     for (int t = 0; t < 2 * k; t++)
@@ -640,6 +646,11 @@ mgseg_status mgseg_setup(const float *image_dev, int n, int m, int pitch, const 
     if (std::max(n, m) > RB_LDS_MAX)
         scr_n = (size_t)RF_COUNT * std::max((size_t)((n + 3) / 4) * m, (size_t)((m + 3) / 4) * n);
     c->scr = dalloc<float>(c, scr_n);
+    {
+        const Level &Lc = c->lev[Lv - 1];
+        c->co_prev = dalloc<float>(c, (size_t)Lc.n * Lc.prm);
+        c->co_entry = dalloc<float>(c, (size_t)Lc.n * Lc.prm);
+    }
     double *zb = dalloc<double>(c, N), *t64 = dalloc<double>(c, N);
     c->mk_d = dalloc<double>(c, 2 * (size_t)k);
     c->hull_d = dalloc<double>(c, 2 * (size_t)k + 2);
@@ -877,7 +888,10 @@ mgseg_status mgseg_debug_op(mgseg_ctx *c, int l, int op, int arg)
         transpose_f(c, L.T[2], L.pcm, L.P[0], L.prm, L.m, L.n);
         break;
     case 5: smooth(c, l, arg); break;
-    case 6: coarsest(c, l); break;
+    case 6:
+        if (l != c->L - 1) return MGSEG_E_ARG;
+        coarsest(c, l);
+        break;
     case 7: vcycle_from(c, l); break;
     case 8: residual(c, l, L.r, nullptr); break;
     case 9: update_c(c); break;

@@ -51,7 +51,7 @@ __device__ __forceinline__ float mg_face(float psiP, float psiQ, float tpP, floa
     float dn = psiQ - psiP;
     float dt = ((tpP + tpQ) - (tmP + tmQ)) * 0.25f;
     float wf = 0.5f * (wP + wQ);
-    return wf / sqrtf(dn * dn + dt * dt + e2);
+    return wf * __builtin_amdgcn_rsqf(dn * dn + dt * dt + e2);
 }
 __device__ __forceinline__ double mg_face64(double psiP, double psiQ, double tpP, double tpQ,
                                             double tmP, double tmQ, double wP, double wQ, double e2)
@@ -96,6 +96,8 @@ struct LineArgs {
     const float *psi, *w, *fit, *F;     // F may be null (zero)
     const uint8_t *lab;
     const float *lo, *hi;
+    float *tout;                        // non-null: new values written transposed,
+    int tpitch;                         //   cell q of line r at tout[q * tpitch + r]
     float *scr;                         // unit-row scratch of lines longer than RB_LDS_MAX
     const double *area;                 // Rada-Chen area term (null: 0)
     int pitch, lpitch, nl, ml;
@@ -131,9 +133,10 @@ struct RunBuf {
 };
 
 struct RunRegs {
-    float a[RUN_MAX], c[RUN_MAX], r[RUN_MAX], lo[RUN_MAX], hi[RUN_MAX], x[RUN_MAX];
+    float a[RUN_MAX], c[RUN_MAX], r[RUN_MAX], lo[RUN_MAX], hi[RUN_MAX];
     float sig;         // old value of the cell after the unit (0 at the line end)
     int L;
+    unsigned hh, hl;   // bit k: the old value of cell k sits at its upper / lower bound
     bool ok;           // false: an S = 0 cell, the unit keeps its values
 };
 
@@ -141,49 +144,48 @@ __device__ __forceinline__ void run_load(const RunBuf &B, int ps, int L, int ml,
 {
     R.L = L;
     R.ok = true;
+    R.hh = 0u; R.hl = 0u;
 #pragma unroll
     for (int k = 0; k < RUN_MAX; k++) {
         if (k < L) {
             R.a[k] = B.at(RF_A, ps + k); R.c[k] = B.at(RF_C, ps + k); R.r[k] = B.at(RF_R, ps + k);
-            R.lo[k] = B.at(RF_LO, ps + k); R.hi[k] = B.at(RF_HI, ps + k); R.x[k] = B.at(RF_X, ps + k);
+            R.lo[k] = B.at(RF_LO, ps + k); R.hi[k] = B.at(RF_HI, ps + k);
+            const float x = B.at(RF_X, ps + k);
+            if (x >= R.hi[k]) R.hh |= 1u << k;
+            else if (x <= R.lo[k]) R.hl |= 1u << k;
             if (isnan(R.a[k])) R.ok = false;
         } else {
-            R.a[k] = 0.0f; R.c[k] = 0.0f; R.r[k] = 0.0f; R.lo[k] = 0.0f; R.hi[k] = 0.0f; R.x[k] = 0.0f;
+            R.a[k] = 0.0f; R.c[k] = 0.0f; R.r[k] = 0.0f; R.lo[k] = 0.0f; R.hi[k] = 0.0f;
         }
     }
     R.sig = ps + L < ml ? B.at(RF_X, ps + L) : 0.0f;
 }
 
-// Thomas pass with held rows as identity rows y_k = bound; held[k] in {-1, 0, +1}
-__device__ __forceinline__ bool run_thomas_regs(const RunRegs &R, const int (&held)[RUN_MAX], float x,
+// Thomas pass with held rows (bit k of hh / hl) as identity rows y_k = bound
+__device__ __forceinline__ bool run_thomas_regs(const RunRegs &R, unsigned hh, unsigned hl, float x,
                                                 float (&y)[RUN_MAX])
 {
-    float pu[RUN_MAX], qq[RUN_MAX];
+    float qq[RUN_MAX];
     float pprev = x, qprev = 0.0f;
 #pragma unroll
     for (int k = 0; k < RUN_MAX; k++) {
-        if (k >= R.L) { pu[k] = 0.0f; qq[k] = 0.0f; continue; }
-        if (held[k] != 0) {
-            pu[k] = held[k] > 0 ? R.hi[k] : R.lo[k];
-            qq[k] = 0.0f;
-        } else {
+        if (k >= R.L) { y[k] = 0.0f; qq[k] = 0.0f; continue; }
+        if ((hh >> k) & 1u) { y[k] = R.hi[k]; qq[k] = 0.0f; }
+        else if ((hl >> k) & 1u) { y[k] = R.lo[k]; qq[k] = 0.0f; }
+        else {
             const float a = R.a[k];
             const float den = (k == 0) ? 1.0f : 1.0f - a * qprev;
             if (!(den > 0.0f)) return false;
-            const float inv = 1.0f / den;
-            pu[k] = (a * pprev - R.r[k]) * inv;
-            if (k == R.L - 1) { pu[k] = pu[k] + R.c[k] * inv * R.sig; qq[k] = 0.0f; }
+            const float inv = __builtin_amdgcn_rcpf(den);
+            y[k] = (a * pprev - R.r[k]) * inv;
+            if (k == R.L - 1) { y[k] = y[k] + R.c[k] * inv * R.sig; qq[k] = 0.0f; }
             else qq[k] = R.c[k] * inv;
         }
-        pprev = pu[k]; qprev = qq[k];
+        pprev = y[k]; qprev = qq[k];
     }
-    float yn = 0.0f;
 #pragma unroll
-    for (int kk = RUN_MAX - 1; kk >= 0; kk--) {
-        if (kk >= R.L) { y[kk] = 0.0f; continue; }
-        yn = (kk == R.L - 1) ? pu[kk] : fmaf(qq[kk], yn, pu[kk]);
-        y[kk] = yn;
-    }
+    for (int k = RUN_MAX - 2; k >= 0; k--)
+        if (k + 1 < R.L) y[k] = fmaf(qq[k], y[k + 1], y[k]);
     return true;
 }
 
@@ -191,32 +193,36 @@ __device__ __forceinline__ bool run_thomas_regs(const RunRegs &R, const int (&he
 // where its row pushes outward.  Active-set iteration: free cells solved
 // exactly with held cells as known values, free cells outside the box held,
 // held cells whose residual turns inward released, until stable (at most
-// 2 L + 4 passes).  pin = -1 / +1 holds cell 0 at its lower / upper bound
-// (the limit of an incoming value -> -inf / +inf); pin = 0 uses x.
+// 2 L + 4 passes), starting from the cells whose old value sits at a bound.
+// pin = -1 / +1 holds cell 0 at its lower / upper bound (the limit of an
+// incoming value -> -inf / +inf); pin = 0 uses x.
 __device__ __forceinline__ bool run_vi_regs(const RunRegs &R, float x, int pin, float (&y)[RUN_MAX])
 {
     if (!R.ok) return false;
-    int held[RUN_MAX];
-#pragma unroll
-    for (int k = 0; k < RUN_MAX; k++) held[k] = (k == 0) ? pin : 0;
+    unsigned hh = R.hh, hl = R.hl;
+    if (pin > 0) { hh |= 1u; hl &= ~1u; }
+    else if (pin < 0) { hl |= 1u; hh &= ~1u; }
     for (int it = 0; it < 2 * R.L + 4; it++) {
-        if (!run_thomas_regs(R, held, x, y)) return false;
-        bool changed = false;
+        if (!run_thomas_regs(R, hh, hl, x, y)) return false;
+        unsigned nh = hh, nl = hl;
 #pragma unroll
         for (int k = 0; k < RUN_MAX; k++) {
             if (k >= R.L) continue;
-            if (held[k] == 0) {
-                if (y[k] > R.hi[k]) { held[k] = 1; changed = true; }
-                else if (y[k] < R.lo[k]) { held[k] = -1; changed = true; }
+            const unsigned bit = 1u << k;
+            if (!((hh | hl) & bit)) {
+                if (y[k] > R.hi[k]) nh |= bit;
+                else if (y[k] < R.lo[k]) nl |= bit;
             } else if (!(k == 0 && pin != 0)) {
                 const float yp = (k == 0) ? x : y[k > 0 ? k - 1 : 0];
                 const float yn = (k == R.L - 1) ? R.sig : y[k + 1 < RUN_MAX ? k + 1 : k];
                 const float v = R.a[k] * yp + R.c[k] * yn - R.r[k] - y[k];
                 const float tau = RUN_TOL * (fabsf(R.a[k] * yp) + fabsf(R.c[k] * yn) + fabsf(R.r[k]) + fabsf(y[k]));
-                if ((held[k] > 0 && v < -tau) || (held[k] < 0 && v > tau)) { held[k] = 0; changed = true; }
+                if ((hh & bit) && v < -tau) nh &= ~bit;
+                if ((hl & bit) && v > tau) nl &= ~bit;
             }
         }
-        if (!changed) break;
+        if (nh == hh && nl == hl) break;
+        hh = nh; hl = nl;
     }
 #pragma unroll
     for (int k = 0; k < RUN_MAX; k++)
@@ -235,7 +241,7 @@ __device__ __forceinline__ bool run_affine_regs(const RunRegs &R, float &uL, flo
         const float a = R.a[k];
         const float den = (k == 0) ? 1.0f : 1.0f - a * q;
         if (!(den > 0.0f)) return false;
-        const float inv = 1.0f / den;
+        const float inv = __builtin_amdgcn_rcpf(den);
         const float npu = (k == 0) ? -R.r[k] * inv : (a * pu - R.r[k]) * inv;
         const float npv = (k == 0) ? a * inv : a * pv * inv;
         pu = npu; pv = npv;
@@ -258,27 +264,22 @@ __device__ __forceinline__ float last_of(const float (&y)[RUN_MAX], int L)
 // The map from the value entering the unit to the value of its last cell is
 // the clipped ramp clip(u_L + v_L x, y-, y+): y_L is the unconstrained
 // affine solution while every cell is free, and constant (y- / y+, the
-// solutions with cell 0 held at its bounds) once a cell holds.
-__device__ __forceinline__ Ramp unit_ramp(const RunRegs &R)
+// solutions with cell 0 held at its bounds) once a cell holds.  yold: the
+// old value of the last cell (kept by a unit with an S = 0 cell).
+__device__ __forceinline__ Ramp unit_ramp(const RunRegs &R, float yold)
 {
     float uL = 0.0f, vL = 0.0f, ylo = 0.0f, yhi = 0.0f, y[RUN_MAX];
     bool ok = run_affine_regs(R, uL, vL);
-    if (ok) {
-        if (R.a[0] > 0.0f) {
-            ok = run_vi_regs(R, 0.0f, -1, y);
-            ylo = last_of(y, R.L);
-            ok = ok && run_vi_regs(R, 0.0f, +1, y);
-            yhi = last_of(y, R.L);
-        } else {
-            ok = run_vi_regs(R, 0.0f, 0, y);
-            ylo = yhi = last_of(y, R.L);
-            vL = 0.0f; uL = ylo;
-        }
+    const bool coupled = R.a[0] > 0.0f;
+#pragma nounroll
+    for (int s = 0; s < 2 && ok; s++) {
+        ok = run_vi_regs(R, 0.0f, coupled ? (s == 0 ? -1 : 1) : 0, y);
+        const float v = last_of(y, R.L);
+        if (s == 0) ylo = v;
+        else yhi = v;
+        if (!coupled) { yhi = ylo; vL = 0.0f; uL = ylo; break; }
     }
-    if (!ok) {
-        const float yold = last_of(R.x, R.L);
-        return Ramp{0.0f, yold, yold, yold};
-    }
+    if (!ok) return Ramp{0.0f, yold, yold, yold};
     return Ramp{vL, uL, fminf(ylo, yhi), fmaxf(ylo, yhi)};
 }
 
@@ -432,8 +433,8 @@ __device__ __forceinline__ void sweep_line(const LineArgs &A, int r, const RunBu
             const float hi = A.lo ? A.hi[ro + q] : A.M;
             const float pold = old[q];
             const bool ok = S > 0.0f;
+            const float inv = ok ? __builtin_amdgcn_rcpf(S) : 0.0f;
             if (ok) {
-                const float inv = 1.0f / S;
                 pa[k] = Lp * inv;
                 pb[k] = (Ls * sig - rhs) * inv;
                 plo[k] = lo;
@@ -441,9 +442,9 @@ __device__ __forceinline__ void sweep_line(const LineArgs &A, int r, const RunBu
             } else {                          // S == 0: the cell keeps its value
                 pa[k] = 0.0f; pb[k] = pold; plo[k] = pold; phv[k] = pold;
             }
-            B.at(RF_A, p) = ok ? Lp / S : __builtin_nanf("");
-            B.at(RF_C, p) = ok ? Ls / S : 0.0f;
-            B.at(RF_R, p) = ok ? rhs / S : 0.0f;
+            B.at(RF_A, p) = ok ? Lp * inv : __builtin_nanf("");
+            B.at(RF_C, p) = ok ? Ls * inv : 0.0f;
+            B.at(RF_R, p) = ok ? rhs * inv : 0.0f;
             B.at(RF_LO, p) = lo;
             B.at(RF_HI, p) = hi;
             B.at(RF_X, p) = pold;
@@ -474,7 +475,7 @@ __device__ __forceinline__ void sweep_line(const LineArgs &A, int r, const RunBu
                     uL[k] = L;
                     RunRegs R;
                     run_load(B, p, L, ml, R);
-                    um[k] = unit_ramp(R);
+                    um[k] = unit_ramp(R, B.at(RF_X, p + L - 1));
                 }
             } else if (p >= 1 && mask_bit(msk, p - 1) && (p < 2 || !mask_bit(msk, p - 2))) {
                 inunit |= 1u << k;         // the cell after a single starred cell
@@ -515,7 +516,7 @@ __device__ __forceinline__ void sweep_line(const LineArgs &A, int r, const RunBu
             float y[RUN_MAX];
             if (!run_vi_regs(R, xin[k], 0, y)) {
 #pragma unroll
-                for (int c = 0; c < RUN_MAX; c++) y[c] = R.x[c];
+                for (int c = 0; c < RUN_MAX; c++) y[c] = c < uL[k] ? B.at(RF_X, p + c) : 0.0f;
             }
 #pragma unroll
             for (int c = 0; c < RUN_MAX; c++)
@@ -529,11 +530,19 @@ __device__ __forceinline__ void sweep_line(const LineArgs &A, int r, const RunBu
         }
     }
     if (write) {
-        float *orow = A.phi_new + ro;
+        if (A.tout) {
 #pragma unroll
-        for (int k = 0; k < K; k++) {
-            const int p = k * NT + t;
-            if (p < ml) orow[cell(p)] = val[k];
+            for (int k = 0; k < K; k++) {
+                const int p = k * NT + t;
+                if (p < ml) A.tout[(long long)cell(p) * A.tpitch + r] = val[k];
+            }
+        } else {
+            float *orow = A.phi_new + ro;
+#pragma unroll
+            for (int k = 0; k < K; k++) {
+                const int p = k * NT + t;
+                if (p < ml) orow[cell(p)] = val[k];
+            }
         }
     }
     __syncthreads();

@@ -238,12 +238,17 @@ __device__ __forceinline__ uint8_t cell_label(const float *psi, const float *w, 
     return label_of(G, n, m, i, j, Sigma);
 }
 
-__global__ void k_labels(const float *psi, const float *w, int p, int n, int m, float e2, float Sigma,
-                         uint8_t *lab, int lp)
+
+// FP32-mode freeze: psi = phi and the labels, both layouts
+__global__ void k_freeze32(const float *phi, const float *w, int p, int n, int m, float e2, float Sigma, float *psi,
+                           float *psi_cm, uint8_t *lab, uint8_t *lab_cm, int pc)
 {
     int j = blockIdx.x * blockDim.x + threadIdx.x, i = blockIdx.y;
     if (j >= m || i >= n) return;
-    lab[(long long)i * lp + j] = cell_label(psi, w, p, n, m, i, j, e2, Sigma);
+    const long long q = (long long)i * p + j, qc = (long long)j * pc + i;
+    const uint8_t b = cell_label(phi, w, p, n, m, i, j, e2, Sigma);
+    psi[q] = psi_cm[qc] = phi[q];
+    lab[q] = lab_cm[qc] = b;
 }
 
 // ==========================================================================
@@ -310,7 +315,7 @@ __global__ void k_coarse_rhs(const float *phic, const float *w, const float *fit
 
 // fit map with the current c1, c2 (Spencer-Chen adds theta d)
 __global__ void k_fit(const float *z, const float *d, int p, int n, int m, const double *c12, float l1, float l2,
-                      float theta, int model, float *fit)
+                      float theta, int model, float *fit, float *fit_cm, int pc)
 {
     int j = blockIdx.x * blockDim.x + threadIdx.x, i = blockIdx.y;
     if (j >= m || i >= n) return;
@@ -320,6 +325,7 @@ __global__ void k_fit(const float *z, const float *d, int p, int n, int m, const
     float v = l1 * a * a - l2 * b * b;
     if (model == 0) v += theta * d[q];
     fit[q] = v;
+    fit_cm[(long long)j * pc + i] = v;
 }
 
 // ==========================================================================
@@ -353,19 +359,32 @@ __global__ void k_sums(const T *phi, int pp, const float *z, int pz, int n, int 
 // finalize: mode 0 -> area term 2 nu (h^2 sum H - A1) into out[0];
 //           mode 1 -> c1, c2 (eq. c1c2) into out[0], out[1];
 //           mode 2 -> sqrt(sum of partial r^2) into out[0] (partials of stride 1)
-__global__ void k_finalize(const double *partial, int nb, int mode, double N, double h2, double A1, double nu,
-                           double *out)
+#define FIN_NT 256
+__global__ void __launch_bounds__(FIN_NT) k_finalize(const double *partial, int nb, int mode, double N, double h2,
+                                                     double A1, double nu, double *out)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    // deterministic: fixed strided assignment of partials, then a fixed tree
+    __shared__ double r0[FIN_NT], r1[FIN_NT], r2[FIN_NT];
+    const int t = threadIdx.x;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
     if (mode == 2) {
-        double s = 0.0;
-        for (int b = 0; b < nb; b++) s += partial[b];
-        out[0] = sqrt(s);
-        return;
+        for (int b = t; b < nb; b += FIN_NT) a0 += partial[b];
+    } else {
+        for (int b = t; b < nb; b += FIN_NT) {
+            a0 += partial[3 * b]; a1 += partial[3 * b + 1]; a2 += partial[3 * b + 2];
+        }
     }
-    double sH = 0.0, sHz = 0.0, sz = 0.0;
-    for (int b = 0; b < nb; b++) { sH += partial[3 * b]; sHz += partial[3 * b + 1]; sz += partial[3 * b + 2]; }
-    if (mode == 0) {
+    r0[t] = a0; r1[t] = a1; r2[t] = a2;
+    __syncthreads();
+    for (int s = FIN_NT / 2; s > 0; s >>= 1) {
+        if (t < s) { r0[t] += r0[t + s]; r1[t] += r1[t + s]; r2[t] += r2[t + s]; }
+        __syncthreads();
+    }
+    if (t != 0) return;
+    const double sH = r0[0], sHz = r1[0], sz = r2[0];
+    if (mode == 2) {
+        out[0] = sqrt(sH);
+    } else if (mode == 0) {
         out[0] = 2.0 * nu * (h2 * sH - A1);
     } else {
         out[0] = sH > 0.0 ? sHz / sH : 0.0;
@@ -562,15 +581,16 @@ __global__ void k_scalar_solve(ScalarArgs S)
 // grids: e = 0 with bounds from the finer grid's slack.
 
 // finest-grid cycle start: e = 0, bounds of e = [-M - b, M - b]
-__global__ void k_start0(const double *b, int n, int m, double M, float *e, float *lo, float *hi, int p)
+__global__ void k_start0(const double *b, int n, int m, double M, float *e, float *lo, float *hi, int p,
+                         float *lo_cm, float *hi_cm, int pc)
 {
     int j = blockIdx.x * blockDim.x + threadIdx.x, i = blockIdx.y;
     if (j >= m || i >= n) return;
     double v = b[(long long)i * m + j];
     long long q = (long long)i * p + j;
     e[q] = 0.0f;
-    lo[q] = (float)(-M - v);
-    hi[q] = (float)(M - v);
+    lo[q] = lo_cm[(long long)j * pc + i] = (float)(-M - v);
+    hi[q] = hi_cm[(long long)j * pc + i] = (float)(M - v);
 }
 
 // finest-grid cycle end: phi64 = clip(b + e); a deviation at its bound lands
@@ -592,6 +612,9 @@ struct DevArgs {
     const float *e, *G, *w, *fit, *lo, *hi;    // row pitch p
     float *psi, *T, *r;                        // outputs (pitch p), null: not written
     uint8_t *lab;                              // labels (pitch p), null: not written
+    float *psi_cm, *T_cm;                      // column-major copies (pitch pc), null: not written
+    uint8_t *lab_cm;
+    int pc;
     const double *area_b, *area_u;             // Rada-Chen area terms at b and at b + e (null: 0)
     int p, n, m, scaled;
     float kap, e2, eps, Sigma;
@@ -650,6 +673,12 @@ __global__ void k_freeze_dev(DevArgs<BT> A)
     A.psi[q] = u0;
     A.T[q] = (float)t;
     A.lab[q] = lab;
+    if (A.psi_cm) {
+        const long long qc = (long long)j * A.pc + i;
+        A.psi_cm[qc] = u0;
+        A.T_cm[qc] = (float)t;
+        A.lab_cm[qc] = lab;
+    }
 }
 
 // residual in deviation form: r = F - N(b + e) = T(b + e) - L_{b+e} e, projected
@@ -682,7 +711,8 @@ __device__ __forceinline__ double fw_row_dev(const BT *b, int pb, const float *e
 }
 template <typename BT>
 __global__ void k_restrict_dev(const BT *b, int pb, const float *e, const float *lo, const float *hi, int p, int n,
-                               int m, float *bc, float *ec, float *clo, float *chi, int pc, int nc, int mc)
+                               int m, float *bc, float *ec, float *clo, float *chi, int pc, int nc, int mc,
+                               float *clo_cm, float *chi_cm, int pcc)
 {
     int J = blockIdx.x * blockDim.x + threadIdx.x, I = blockIdx.y;
     if (J >= mc || I >= nc) return;
@@ -704,6 +734,8 @@ __global__ void k_restrict_dev(const BT *b, int pb, const float *e, const float 
     ec[q] = 0.0f;
     clo[q] = dl;
     chi[q] = dh;
+    clo_cm[(long long)J * pcc + I] = dl;
+    chi_cm[(long long)J * pcc + I] = dh;
 }
 
 // sum of H(b + e) over a level (area term of the Rada-Chen model)
@@ -732,128 +764,182 @@ __global__ void k_sums_dev(const BT *b, int pb, const float *e, int p, int n, in
 }
 
 // ==========================================================================
-// Coarsest-grid solve in one workgroup: `iters` outer iterations of Hybrid
-// Smoother 2 (freeze + sweeps A, B, C, D), exactly the steps of the
-// multi-kernel path, with block barriers in place of kernel boundaries.
+// Coarsest-grid solve in one workgroup: outer iterations of Hybrid Smoother 2
+// (freeze + sweeps A, B, C, D), exactly the steps of the multi-kernel path,
+// with block barriers in place of kernel boundaries and every array of the
+// level staged in LDS; at most `iters` of them, stopping after the first
+// iteration that moves no value by more than rtol times the largest change
+// since the solve began.
 struct CoarseArgs {
-    float *P0, *P1, *P2, *T1, *T2, *psi, *psi_cm;
-    const float *w, *w_cm, *fit, *fit_cm, *lo, *lo_cm, *hi, *hi_cm;
-    float *F, *F_cm;                // FP32 mode: F (may be null); deviation form: T, written here
+    float *P0;                      // state in / out (row pitch prm)
+    const float *w, *fit, *lo, *hi; // row-major, pitch prm
+    const float *F;                 // FP32 mode: F (may be null)
     const float *base, *G;          // deviation form (P0 holds e); null base: FP32 mode
     const double *area_b;           // deviation form, Rada-Chen: area term at the base
-    uint8_t *lab, *lab_cm;
     double *area;                   // slot for the area term (Rada-Chen), may be null
     double h2, A1, nu, eps;
-    int n, m, prm, pcm, iters, scaled;
-    float kap, e2, M, Sigma;
+    int n, m, prm, iters, scaled;
+    float kap, e2, M, Sigma, rtol;
 };
+#define CO_ARRAYS 20
+#define CO_MAX_CELLS 768
+__host__ __device__ inline size_t coarse_lds_bytes(int n, int m)
+{
+    const size_t N = (size_t)n * m;
+    return CO_ARRAYS * N * sizeof(float) + ((2 * N + 7) / 8) * 8;
+}
+
+// largest change of the state over one outer iteration and since the
+// coarsest solve began (multi-kernel coarsest path): out[0], out[1]
+__global__ void __launch_bounds__(256) k_coarse_delta(const float *x, const float *prev, const float *entry, int p,
+                                                      int n, int m, double *out)
+{
+    __shared__ float r0[256], r1[256];
+    const int t = threadIdx.x;
+    float a = 0.0f, b = 0.0f;
+    for (int q = t; q < n * m; q += 256) {
+        const int k = (q / m) * p + q % m;
+        a = fmaxf(a, fabsf(x[k] - prev[k]));
+        b = fmaxf(b, fabsf(x[k] - entry[k]));
+    }
+    r0[t] = a; r1[t] = b;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (t < s) { r0[t] = fmaxf(r0[t], r0[t + s]); r1[t] = fmaxf(r1[t], r1[t + s]); }
+        __syncthreads();
+    }
+    if (t == 0) { out[0] = r0[0]; out[1] = r1[0]; }
+}
 
 template <int NT>
 __device__ void block_transpose(const float *in, int pin, float *out, int pout, int n, int m)
 {
     for (int t = threadIdx.x; t < n * m; t += NT) {
         int i = t / m, j = t % m;
-        out[(long long)j * pout + i] = in[(long long)i * pin + j];
+        out[j * pout + i] = in[i * pin + j];
     }
 }
 
-template <int NT, int K>
-__global__ void __launch_bounds__(NT) k_coarse_smooth(CoarseArgs C)
+template <int NT>
+__global__ void __launch_bounds__(NT) k_coarse_smooth(CoarseArgs G)
 {
     __shared__ Ramp sh[NT / 64 > 0 ? NT / 64 : 1];
     __shared__ double red[NT];
-    __shared__ float rb[RF_COUNT * NT * K];
-    __shared__ uint64_t msk[(NT * K + 63) / 64];
+    __shared__ float rdt[NT];
+    __shared__ float rb[RF_COUNT * NT];
+    __shared__ uint64_t msk[(NT + 63) / 64];
+    extern __shared__ float co[];
+    const int n = G.n, m = G.m, N = n * m, tid = threadIdx.x;
+    const bool dev = G.base != nullptr;
+    // LDS arrays: row-major with pitch m, column-major with pitch n
+    float *P0 = co, *P1 = co + N, *P2 = co + 2 * N, *T1 = co + 3 * N, *T2 = co + 4 * N;
+    float *psi = co + 5 * N, *psi_cm = co + 6 * N;
+    float *w = co + 7 * N, *w_cm = co + 8 * N, *fit = co + 9 * N, *fit_cm = co + 10 * N;
+    float *lo = co + 11 * N, *lo_cm = co + 12 * N, *hi = co + 13 * N, *hi_cm = co + 14 * N;
+    float *F = co + 15 * N, *F_cm = co + 16 * N, *base = co + 17 * N, *Gv = co + 18 * N, *E = co + 19 * N;
+    uint8_t *lab = reinterpret_cast<uint8_t *>(co + CO_ARRAYS * N), *lab_cm = lab + N;
+    for (int t = tid; t < N; t += NT) {
+        const int i = t / m, j = t % m, qg = i * G.prm + j, qr = t, qc = j * n + i;
+        P0[qr] = E[qr] = G.P0[qg];
+        w[qr] = w_cm[qc] = G.w[qg];
+        fit[qr] = fit_cm[qc] = G.fit[qg];
+        lo[qr] = lo_cm[qc] = G.lo[qg];
+        hi[qr] = hi_cm[qc] = G.hi[qg];
+        const float fv = (!dev && G.F) ? G.F[qg] : 0.0f;
+        F[qr] = F_cm[qc] = fv;
+        base[qr] = dev ? G.base[qg] : 0.0f;
+        Gv[qr] = dev ? G.G[qg] : 0.0f;
+    }
+    __syncthreads();
     RunBuf RBr, RBc;
-    RBr.p = rb; RBr.fs = C.m;
-    RBc.p = rb; RBc.fs = C.n;
-    const int n = C.n, m = C.m, tid = threadIdx.x;
+    RBr.p = rb; RBr.fs = m;
+    RBc.p = rb; RBc.fs = n;
     LineArgs R, T;
-    R.psi = C.psi; R.w = C.w; R.fit = C.fit; R.F = C.F; R.lab = C.lab; R.lo = C.lo; R.hi = C.hi;
-    R.scr = nullptr; R.area = C.area; R.pitch = C.prm; R.lpitch = C.prm;
-    R.nl = n; R.ml = m; R.kap = C.kap; R.e2 = C.e2; R.M = C.M; R.eps = (float)C.eps; R.scaled = C.scaled;
+    R.psi = psi; R.w = w; R.fit = dev ? nullptr : fit; R.F = F; R.lab = lab; R.lo = lo; R.hi = hi;
+    R.scr = nullptr; R.tout = nullptr; R.tpitch = 0; R.area = G.area; R.pitch = m; R.lpitch = m;
+    R.nl = n; R.ml = m; R.kap = G.kap; R.e2 = G.e2; R.M = G.M; R.eps = (float)G.eps; R.scaled = G.scaled;
     T = R;
-    T.psi = C.psi_cm; T.w = C.w_cm; T.fit = C.fit_cm; T.F = C.F_cm; T.lab = C.lab_cm; T.lo = C.lo_cm;
-    T.hi = C.hi_cm; T.pitch = C.pcm; T.lpitch = C.pcm; T.nl = m; T.ml = n;
-    const bool dev = C.base != nullptr;
-    if (dev) { R.fit = nullptr; T.fit = nullptr; }
+    T.psi = psi_cm; T.w = w_cm; T.fit = dev ? nullptr : fit_cm; T.F = F_cm; T.lab = lab_cm; T.lo = lo_cm;
+    T.hi = hi_cm; T.pitch = n; T.lpitch = n; T.nl = m; T.ml = n;
     DevArgs<float> D;
-    D.b = C.base; D.pb = C.prm; D.e = C.P0; D.G = C.G; D.w = C.w; D.fit = C.fit; D.lo = C.lo; D.hi = C.hi;
+    D.b = base; D.pb = m; D.e = P0; D.G = Gv; D.w = w; D.fit = fit; D.lo = lo; D.hi = hi;
     D.psi = nullptr; D.T = nullptr; D.r = nullptr; D.lab = nullptr;
-    D.area_b = C.area_b; D.area_u = C.area;
-    D.p = C.prm; D.n = n; D.m = m; D.scaled = C.scaled;
-    D.kap = C.kap; D.e2 = C.e2; D.eps = (float)C.eps; D.Sigma = C.Sigma;
-    for (int it = 0; it < C.iters; it++) {
+    D.psi_cm = nullptr; D.T_cm = nullptr; D.lab_cm = nullptr; D.pc = n;
+    D.area_b = G.area_b; D.area_u = G.area;
+    D.p = m; D.n = n; D.m = m; D.scaled = G.scaled;
+    D.kap = G.kap; D.e2 = G.e2; D.eps = (float)G.eps; D.Sigma = G.Sigma;
+    for (int it = 0; it < G.iters; it++) {
         // freeze
-        if (dev) {
-            double acc = 0.0;
-            if (C.area) {
-                for (int t = tid; t < n * m; t += NT) {
-                    long long q = (long long)(t / m) * C.prm + t % m;
-                    acc += mg_heav64((double)C.base[q] + (double)C.P0[q], C.eps);
-                }
-                red[tid] = acc;
-                __syncthreads();
-                if (tid == 0) {
-                    double s = 0.0;
-                    for (int k = 0; k < NT; k++) s += red[k];
-                    *C.area = 2.0 * C.nu * (C.h2 * s - C.A1);
-                }
-                __syncthreads();
+        double acc = 0.0;
+        if (G.area) {
+            for (int t = tid; t < N; t += NT)
+                acc += mg_heav64(dev ? (double)base[t] + (double)P0[t] : (double)P0[t], G.eps);
+            red[tid] = acc;
+            __syncthreads();
+            if (tid == 0) {
+                double s = 0.0;
+                for (int k = 0; k < NT; k++) s += red[k];
+                *G.area = 2.0 * G.nu * (G.h2 * s - G.A1);
             }
-            for (int t = tid; t < n * m; t += NT) {
-                int i = t / m, j = t % m;
+            __syncthreads();
+        }
+        if (dev) {
+            for (int t = tid; t < N; t += NT) {
+                const int i = t / m, j = t % m, qc = j * n + i;
                 double Le;
                 float u0;
                 uint8_t b;
                 const double tv = dev_cell(D, i, j, false, Le, u0, b);
-                long long qr = (long long)i * C.prm + j, qc = (long long)j * C.pcm + i;
-                C.psi[qr] = u0; C.psi_cm[qc] = u0;
-                C.F[qr] = (float)tv; C.F_cm[qc] = (float)tv;
-                C.lab[qr] = b; C.lab_cm[qc] = b;
+                psi[t] = u0; psi_cm[qc] = u0;
+                F[t] = (float)tv; F_cm[qc] = (float)tv;
+                lab[t] = b; lab_cm[qc] = b;
             }
-            __syncthreads();
         } else {
-            for (int t = tid; t < n * m; t += NT) {
-                int i = t / m, j = t % m;
-                float v = C.P0[(long long)i * C.prm + j];
-                C.psi[(long long)i * C.prm + j] = v;
-                C.psi_cm[(long long)j * C.pcm + i] = v;
+            for (int t = tid; t < N; t += NT) {
+                const int i = t / m, j = t % m;
+                psi[t] = P0[t];
+                psi_cm[j * n + i] = P0[t];
             }
             __syncthreads();
-            double acc = 0.0;
-            for (int t = tid; t < n * m; t += NT) {
-                int i = t / m, j = t % m;
-                uint8_t b = cell_label(C.psi, C.w, C.prm, n, m, i, j, C.e2, C.Sigma);
-                C.lab[(long long)i * C.prm + j] = b;
-                C.lab_cm[(long long)j * C.pcm + i] = b;
-                acc += mg_heav64((double)C.psi[(long long)i * C.prm + j], C.eps);
+            for (int t = tid; t < N; t += NT) {
+                const int i = t / m, j = t % m;
+                const uint8_t b = cell_label(psi, w, m, n, m, i, j, G.e2, G.Sigma);
+                lab[t] = b;
+                lab_cm[j * n + i] = b;
             }
-            if (C.area) {
-                red[tid] = acc;
-                __syncthreads();
-                if (tid == 0) {
-                    double s = 0.0;
-                    for (int k = 0; k < NT; k++) s += red[k];
-                    *C.area = 2.0 * C.nu * (C.h2 * s - C.A1);
-                }
-            }
-            __syncthreads();
         }
+        __syncthreads();
         // sweeps A and B (rows)
-        R.phi_old = C.P0; R.phi_new = C.P1; R.bit = 0;
-        for (int b = 0; b < (n + 3) / 4; b++) sweep_band<NT, K, false>(R, b, RBr, msk, sh);
-        R.phi_old = C.P1; R.phi_new = C.P2; R.bit = 1;
-        for (int b = 0; b < (n + 3) / 4; b++) sweep_band<NT, K, true>(R, b, RBr, msk, sh);
-        block_transpose<NT>(C.P2, C.prm, C.T1, C.pcm, n, m);
+        R.phi_old = P0; R.phi_new = P1; R.bit = 0;
+        for (int b = 0; b < (n + 3) / 4; b++) sweep_band<NT, 1, false>(R, b, RBr, msk, sh);
+        R.phi_old = P1; R.phi_new = P2; R.bit = 1;
+        for (int b = 0; b < (n + 3) / 4; b++) sweep_band<NT, 1, true>(R, b, RBr, msk, sh);
+        block_transpose<NT>(P2, m, T1, n, n, m);
         __syncthreads();
         // sweeps C and D (columns)
-        T.phi_old = C.T1; T.phi_new = C.T2; T.bit = 2;
-        for (int b = 0; b < (m + 3) / 4; b++) sweep_band<NT, K, false>(T, b, RBc, msk, sh);
-        T.phi_old = C.T2; T.phi_new = C.T1; T.bit = 3;
-        for (int b = 0; b < (m + 3) / 4; b++) sweep_band<NT, K, true>(T, b, RBc, msk, sh);
-        block_transpose<NT>(C.T1, C.pcm, C.P0, C.prm, m, n);
+        T.phi_old = T1; T.phi_new = T2; T.bit = 2;
+        for (int b = 0; b < (m + 3) / 4; b++) sweep_band<NT, 1, false>(T, b, RBc, msk, sh);
+        T.phi_old = T2; T.phi_new = T1; T.bit = 3;
+        for (int b = 0; b < (m + 3) / 4; b++) sweep_band<NT, 1, true>(T, b, RBc, msk, sh);
+        float dmax = 0.0f, tot = 0.0f;
+        for (int t = tid; t < N; t += NT) {
+            const int i = t / m, j = t % m;
+            const float v = T1[j * n + i];
+            dmax = fmaxf(dmax, fabsf(v - P0[t]));
+            tot = fmaxf(tot, fabsf(v - E[t]));
+            P0[t] = v;
+        }
+        red[tid] = (double)dmax;
+        rdt[tid] = tot;
         __syncthreads();
+        for (int s = NT / 2; s > 0; s >>= 1) {
+            if (tid < s) { red[tid] = fmax(red[tid], red[tid + s]); rdt[tid] = fmaxf(rdt[tid], rdt[tid + s]); }
+            __syncthreads();
+        }
+        const bool stop = red[0] <= (double)G.rtol * (double)rdt[0];
+        __syncthreads();
+        if (stop) break;
     }
+    for (int t = tid; t < N; t += NT) G.P0[(t / m) * G.prm + t % m] = P0[t];
 }
 

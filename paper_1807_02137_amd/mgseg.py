@@ -37,7 +37,7 @@ class _Params(C.Structure):
                 ("beta", C.c_double), ("sigma_g", C.c_double), ("sigma_d", C.c_double),
                 ("Sigma", C.c_double), ("M", C.c_double), ("nu1", C.c_int32), ("nu2", C.c_int32),
                 ("levels", C.c_int32), ("coarse_iters", C.c_int32), ("mixed_precision", C.c_int32),
-                ("scaled", C.c_int32)]
+                ("scaled", C.c_int32), ("coarse_rtol", C.c_double)]
 
 
 class _Stats(C.Structure):
@@ -64,9 +64,10 @@ class Params:
     nu1: int = 2
     nu2: int = 2
     levels: int = 0
-    coarse_iters: int = 100
+    coarse_iters: int = 10
     mixed_precision: int = 1
     scaled: int = 1
+    coarse_rtol: float = 1e-4
 
     def to_c(self) -> _Params:
         p = _Params()
