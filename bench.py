@@ -14,6 +14,7 @@ oracle timed on a bounded sample of the same workload.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -23,6 +24,43 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_1024_traffic.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1807_02137_amd", "csrc", f)
+                  for f in ("mgseg_device.h", "mgseg_kernels.h", "mgseg.hip")]
+
+
+def kernel_source_sha() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per finest-grid sweep launch from the recorded FETCH_SIZE /
+    WRITE_SIZE counters (scaled by a plain copy of known size), or None when
+    the kernel sources have changed since they were taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha") != kernel_source_sha():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def calibrate_copy(mib: int = 1024):
+    """One plain device-to-device copy of `mib` MiB (read + write of that many
+    bytes): the reference for scaling the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    a = torch.empty(mib * (1 << 20) // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": a.numel() * 4}))
 SEED = 2000
 N = 1024
 LEVELS = 9
@@ -37,13 +75,17 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one plain copy of known size (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU path is a design note, not an implementation.", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     import torch
 
     from paper_1807_02137_amd import build, mgseg, synth
@@ -119,7 +161,7 @@ def main():
         "converged": all(oks),
         "time_to_tol_ms": wall / args.steps * 1e3,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": "k_sweep (finest-grid directional sweep)",
                      "launches": prof_n, "avg_us": avg_ms * 1e3, "bytes_per_launch": prof_bytes},
         "cpu_baseline": cpu,
