@@ -129,3 +129,100 @@ def test_solve_parity(seed):
     assert flips <= max(1, int(1e-4 * pg.size))
     assert dmax <= 1e-4
     s.close()
+
+
+@pytest.mark.parametrize("seed", [1000, 1001, 1002])
+def test_solve_parity_rada_chen(seed):
+    """Rada-Chen model (area term of eq. rcfunc): the same end-to-end bar."""
+    say("case solve rada-chen seed", seed)
+    inst, s, o = make(seed, model=1)
+    hg = []
+    for _ in range(40):
+        hg.append(s.vcycle())
+        if hg[-1] <= 1e-6:
+            break
+    k, hist = o.solve(1e-6, 40)
+    pg, po = s.phi().cpu().numpy(), o.get("phi")
+    agree = (pg > 0) == (po > 0)
+    flips = int((~agree).sum())
+    dmax = float(np.abs(pg - po)[agree].max())
+    say(f"gpu {len(hg)} cycles rel {hg[-1]:.2e}; oracle {k} cycles; flips {flips} max|dphi| {dmax:.3e}")
+    assert hg[-1] <= 1e-6 and k > 0
+    assert flips <= max(1, int(1e-4 * pg.size))
+    assert dmax <= 1e-4
+    s.close()
+
+
+@pytest.mark.parametrize("shape", [(40, 72, 3), (24, 200, 3), (16, 16, 5), (96, 160, 5)])
+def test_solve_parity_ragged_shapes(shape):
+    """Non-square grids whose lines are not multiples of the 64-lane wave, and a
+    hierarchy that ends on a 1x1 grid (scalar coarsest solve)."""
+    n, m, L = shape
+    say("case ragged shape", n, m, "levels", L)
+    inst = synth.tiny_instance(7, n, m)
+    s = mgseg.Solver(inst.image, inst.markers, mgseg.Params(levels=L))
+    o = Oracle(inst.image, inst.markers, OracleParams(levels=L))
+    hg = []
+    for _ in range(40):
+        hg.append(s.vcycle())
+        if hg[-1] <= 1e-6:
+            break
+    k, hist = o.solve(1e-6, 40)
+    pg, po = s.phi().cpu().numpy(), o.get("phi")
+    agree = (pg > 0) == (po > 0)
+    flips = int((~agree).sum())
+    dmax = float(np.abs(pg - po)[agree].max()) if agree.any() else 0.0
+    say(f"gpu {len(hg)} cycles rel {hg[-1]:.2e}; oracle {k} cycles; flips {flips} max|dphi| {dmax:.3e}")
+    assert hg[-1] <= 1e-6 and k > 0
+    assert flips <= 1
+    assert dmax <= 1e-4
+    s.close()
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_degenerate_marker_sets(k):
+    """One or two markers: the marker hull is a point or a segment (zero area)."""
+    say("case degenerate markers", k)
+    inst = synth.config1(1003)
+    mk = inst.markers[:k]
+    s = mgseg.Solver(inst.image, mk, mgseg.Params(levels=6))
+    o = Oracle(inst.image, mk, OracleParams(levels=6))
+    assert np.abs(s.get("phi64") - o.get("phi")).max() <= 1e-12
+    assert s.scalars()["A1"] == 0.0 and o.scalars()["A1"] == 0.0
+    for _ in range(3):
+        rg = s.vcycle()
+        ro, _ = o.vcycle()
+    pg, po = s.get("phi64"), o.get("phi")
+    flips = int(((pg > 0) != (po > 0)).sum())
+    say(f"after 3 cycles: rel gpu {rg:.3e} oracle {ro:.3e} flips {flips}")
+    assert flips <= 2
+    s.close()
+
+
+def test_full_size_solution_has_oracle_residual():
+    """1024x1024 ellipse image in the benchmark's configuration (9 grids): the GPU
+    solve reaches 1e-6, and the FP64 oracle, evaluating the projected residual of
+    the discrete system at the GPU's phi (with c1, c2 recomputed from it),
+    agrees that the relative residual is below 1e-6 (rounding allowance 10 %)."""
+    say("case full size 1024x1024 seed 2000")
+    inst = synth.config2(2000, 1024)
+    s = mgseg.Solver(inst.image, inst.markers, mgseg.Params(levels=9))
+    cyc, rel, ok = s.solve(1e-6, 80)
+    st = s.stats()
+    phi = s.phi().cpu().numpy()
+    say(f"gpu {cyc} cycles rel {rel:.3e}")
+    o = Oracle(inst.image, inst.markers, OracleParams(levels=1))
+    res0 = o.scalars()["res0"]
+    assert abs(res0 - st["res0"]) <= 1e-9 * res0
+    o.set("phi", phi)
+    o.update_c()
+    sc = o.scalars()
+    assert abs(sc["c1"] - st["c1"]) <= 1e-9 and abs(sc["c2"] - st["c2"]) <= 1e-9
+    rel_or = o.res_norm() / res0
+    mask = phi > 0
+    iou = (mask & inst.target).sum() / max((mask | inst.target).sum(), 1)
+    say(f"oracle rel residual at the gpu phi {rel_or:.3e}; IoU with the generator target {iou:.3f}")
+    assert ok and rel <= 1e-6
+    assert rel_or <= 1.1e-6
+    assert iou >= 0.9
+    s.close()
