@@ -112,12 +112,8 @@ struct LineArgs {
 // into its unit (a single starred cell at the line end stays alone).  Runs
 // longer than RUN_MAX are cut into ceil(len / RUN_MAX) pieces of near-equal
 // length (the longer pieces first), each solved as its own unit, so that
-// every unit fits in registers.
-#define RUN_MAX 4
-// A held cell is released only when its residual points inward by more than
-// FP32 rounding, so that the hold / release iteration cannot alternate on a
-// cell whose free value equals its bound.
-#define RUN_TOL 1e-6f
+// every unit has a closed-form solution.
+#define RUN_MAX 3
 
 // Row buffer of the line being swept, indexed by visit position p:
 //   a y_{p-1} - y_p + c y_{p+1} = r  (a = NaN marks S = 0), box [lo, hi],
@@ -132,155 +128,147 @@ struct RunBuf {
     __device__ __forceinline__ float &at(int f, int q) const { return p[f * fs + q]; }
 };
 
-struct RunRegs {
-    float a[RUN_MAX], c[RUN_MAX], r[RUN_MAX], lo[RUN_MAX], hi[RUN_MAX];
-    float sig;         // old value of the cell after the unit (0 at the line end)
-    int L;
-    unsigned hh, hl;   // bit k: the old value of cell k sits at its upper / lower bound
-    bool ok;           // false: an S = 0 cell, the unit keeps its values
+// Units of one or two cells in closed form.  The box-constrained problem of
+// an M-matrix row set is the projected one: every cell sits at the projection
+// of its row.  One cell: y0 = clip(a0 x + c0 sig - r0, lo0, hi0), a clipped
+// ramp of x.  Two cells: y0 = clip(a0 x - r0 + c0 y1, lo0, hi0) and
+// y1 = clip(a1 y0 + c1 sig - r1, lo1, hi1) compose into
+// y1 = clip(a1 c0 y1 + b, L', U') (ramp composition), whose unique fixed point
+// for 0 <= a1 c0 < 1 is clip(b / (1 - a1 c0), L', U'); y0 then follows.
+struct PairRows {
+    float a0, c0, r0, lo0, hi0, x0, a1, al1, lo1, hi1, x1;   // al1 = c1 sig - r1
+    bool ok;
 };
-
-__device__ __forceinline__ void run_load(const RunBuf &B, int ps, int L, int ml, RunRegs &R)
+__device__ __forceinline__ void pair_load(const RunBuf &B, int ps, int L, int ml, PairRows &P)
 {
-    R.L = L;
-    R.ok = true;
-    R.hh = 0u; R.hl = 0u;
-#pragma unroll
-    for (int k = 0; k < RUN_MAX; k++) {
-        if (k < L) {
-            R.a[k] = B.at(RF_A, ps + k); R.c[k] = B.at(RF_C, ps + k); R.r[k] = B.at(RF_R, ps + k);
-            R.lo[k] = B.at(RF_LO, ps + k); R.hi[k] = B.at(RF_HI, ps + k);
-            const float x = B.at(RF_X, ps + k);
-            if (x >= R.hi[k]) R.hh |= 1u << k;
-            else if (x <= R.lo[k]) R.hl |= 1u << k;
-            if (isnan(R.a[k])) R.ok = false;
-        } else {
-            R.a[k] = 0.0f; R.c[k] = 0.0f; R.r[k] = 0.0f; R.lo[k] = 0.0f; R.hi[k] = 0.0f;
-        }
+    P.a0 = B.at(RF_A, ps); P.c0 = B.at(RF_C, ps); P.r0 = B.at(RF_R, ps);
+    P.lo0 = B.at(RF_LO, ps); P.hi0 = B.at(RF_HI, ps); P.x0 = B.at(RF_X, ps);
+    P.ok = !isnan(P.a0);
+    if (L == 2) {
+        P.a1 = B.at(RF_A, ps + 1);
+        const float sig = ps + 2 < ml ? B.at(RF_X, ps + 2) : 0.0f;
+        P.al1 = B.at(RF_C, ps + 1) * sig - B.at(RF_R, ps + 1);
+        P.lo1 = B.at(RF_LO, ps + 1); P.hi1 = B.at(RF_HI, ps + 1); P.x1 = B.at(RF_X, ps + 1);
+        P.ok = P.ok && !isnan(P.a1) && (1.0f - P.a1 * P.c0) > 0.0f;
+    } else {
+        const float sig = ps + 1 < ml ? B.at(RF_X, ps + 1) : 0.0f;
+        P.r0 -= P.c0 * sig;            // one cell: the successor's old value is known
+        P.c0 = 0.0f;
+        P.a1 = 0.0f; P.al1 = 0.0f; P.lo1 = 0.0f; P.hi1 = 0.0f; P.x1 = 0.0f;
     }
-    R.sig = ps + L < ml ? B.at(RF_X, ps + L) : 0.0f;
+}
+// chain ramp x -> value of the unit's last cell
+__device__ __forceinline__ Ramp pair_ramp(const PairRows &P, int L)
+{
+    if (!P.ok) {
+        const float yo = L == 2 ? P.x1 : P.x0;
+        return Ramp{0.0f, yo, yo, yo};
+    }
+    if (L == 1) return Ramp{P.a0, -P.r0, P.lo0, P.hi0};
+    const float inv = __builtin_amdgcn_rcpf(1.0f - P.a1 * P.c0);
+    const float Lp = mg_clip(fmaf(P.a1, P.lo0, P.al1), P.lo1, P.hi1);
+    const float Up = mg_clip(fmaf(P.a1, P.hi0, P.al1), P.lo1, P.hi1);
+    return Ramp{P.a1 * P.a0 * inv, (P.al1 - P.a1 * P.r0) * inv, Lp, Up};
+}
+// the unit's values at the entering value x
+__device__ __forceinline__ void pair_solve(const PairRows &P, int L, float x, float &y0, float &y1)
+{
+    if (!P.ok) { y0 = P.x0; y1 = P.x1; return; }
+    if (L == 1) { y0 = mg_clip(fmaf(P.a0, x, -P.r0), P.lo0, P.hi0); y1 = 0.0f; return; }
+    y1 = ramp_eval(pair_ramp(P, 2), x);
+    y0 = mg_clip(fmaf(P.c0, y1, fmaf(P.a0, x, -P.r0)), P.lo0, P.hi0);
 }
 
-// Thomas pass with held rows (bit k of hh / hl) as identity rows y_k = bound
-__device__ __forceinline__ bool run_thomas_regs(const RunRegs &R, unsigned hh, unsigned hl, float x,
-                                                float (&y)[RUN_MAX])
+// Units of three cells.  With the middle value y1 given, the end cells are
+// the clipped ramps y0 = R0(y1) = clip(a0 x - r0 + c0 y1, lo0, hi0) and
+// y2 = R2(y1) = clip(c2 sig - r2 + a2 y1, lo2, hi2), so the middle cell solves
+// y1 = clip(h(y1), lo1, hi1) with h = -r1 + a1 R0 + c1 R2 monotone piecewise
+// linear of slope < 1.  psi(y) = y - clip(h(y)) increases: its root lies between
+// the largest candidate point (lo1, hi1, the ramps' kinks) with psi <= 0 and the
+// smallest with psi >= 0, where h is linear, so it is the fixed point of that
+// linear piece.  As a map of x the last cell is the clipped ramp
+// clip(u + v x, y-, y+): u + v x the all-free solution, y-/y+ the two-cell
+// solutions of cells 1, 2 with cell 0 held at lo0 / hi0.
+struct TriRows {
+    float a0, c0, r0, lo0, hi0, a1, c1, r1, lo1, hi1, a2, al2, lo2, hi2, x0, x1, x2;   // al2 = c2 sig - r2
+    bool ok;
+};
+__device__ __forceinline__ void tri_load(const RunBuf &B, int ps, int ml, TriRows &T)
 {
-    float qq[RUN_MAX];
-    float pprev = x, qprev = 0.0f;
-#pragma unroll
-    for (int k = 0; k < RUN_MAX; k++) {
-        if (k >= R.L) { y[k] = 0.0f; qq[k] = 0.0f; continue; }
-        if ((hh >> k) & 1u) { y[k] = R.hi[k]; qq[k] = 0.0f; }
-        else if ((hl >> k) & 1u) { y[k] = R.lo[k]; qq[k] = 0.0f; }
-        else {
-            const float a = R.a[k];
-            const float den = (k == 0) ? 1.0f : 1.0f - a * qprev;
-            if (!(den > 0.0f)) return false;
-            const float inv = __builtin_amdgcn_rcpf(den);
-            y[k] = (a * pprev - R.r[k]) * inv;
-            if (k == R.L - 1) { y[k] = y[k] + R.c[k] * inv * R.sig; qq[k] = 0.0f; }
-            else qq[k] = R.c[k] * inv;
-        }
-        pprev = y[k]; qprev = qq[k];
-    }
-#pragma unroll
-    for (int k = RUN_MAX - 2; k >= 0; k--)
-        if (k + 1 < R.L) y[k] = fmaf(qq[k], y[k + 1], y[k]);
-    return true;
+    T.a0 = B.at(RF_A, ps); T.c0 = B.at(RF_C, ps); T.r0 = B.at(RF_R, ps);
+    T.lo0 = B.at(RF_LO, ps); T.hi0 = B.at(RF_HI, ps); T.x0 = B.at(RF_X, ps);
+    T.a1 = B.at(RF_A, ps + 1); T.c1 = B.at(RF_C, ps + 1); T.r1 = B.at(RF_R, ps + 1);
+    T.lo1 = B.at(RF_LO, ps + 1); T.hi1 = B.at(RF_HI, ps + 1); T.x1 = B.at(RF_X, ps + 1);
+    T.a2 = B.at(RF_A, ps + 2);
+    const float sig = ps + 3 < ml ? B.at(RF_X, ps + 3) : 0.0f;
+    T.al2 = B.at(RF_C, ps + 2) * sig - B.at(RF_R, ps + 2);
+    T.lo2 = B.at(RF_LO, ps + 2); T.hi2 = B.at(RF_HI, ps + 2); T.x2 = B.at(RF_X, ps + 2);
+    T.ok = !isnan(T.a0) && !isnan(T.a1) && !isnan(T.a2) && (1.0f - T.a1 * T.c0 - T.c1 * T.a2) > 0.0f &&
+           (1.0f - T.a2 * T.c1) > 0.0f;
 }
-
-// The unit's variational inequality: y in [lo, hi], y_k at a bound only
-// where its row pushes outward.  Active-set iteration: free cells solved
-// exactly with held cells as known values, free cells outside the box held,
-// held cells whose residual turns inward released, until stable (at most
-// 2 L + 4 passes), starting from the cells whose old value sits at a bound.
-// pin = -1 / +1 holds cell 0 at its lower / upper bound (the limit of an
-// incoming value -> -inf / +inf); pin = 0 uses x.
-__device__ __forceinline__ bool run_vi_regs(const RunRegs &R, float x, int pin, float (&y)[RUN_MAX])
+__device__ __forceinline__ void tri_solve(const TriRows &T, float x, float &y0, float &y1, float &y2)
 {
-    if (!R.ok) return false;
-    unsigned hh = R.hh, hl = R.hl;
-    if (pin > 0) { hh |= 1u; hl &= ~1u; }
-    else if (pin < 0) { hl |= 1u; hh &= ~1u; }
-    for (int it = 0; it < 2 * R.L + 4; it++) {
-        if (!run_thomas_regs(R, hh, hl, x, y)) return false;
-        unsigned nh = hh, nl = hl;
+    if (!T.ok) { y0 = T.x0; y1 = T.x1; y2 = T.x2; return; }
+    const float al0 = fmaf(T.a0, x, -T.r0);
+    auto R0 = [&](float y) { return mg_clip(fmaf(T.c0, y, al0), T.lo0, T.hi0); };
+    auto R2 = [&](float y) { return mg_clip(fmaf(T.a2, y, T.al2), T.lo2, T.hi2); };
+    auto psi = [&](float y) {
+        return y - mg_clip(fmaf(T.c1, R2(y), fmaf(T.a1, R0(y), -T.r1)), T.lo1, T.hi1);
+    };
+    float cand[4];
+    const float big = 3.0e38f;
+    cand[0] = T.c0 > 0.0f ? (T.lo0 - al0) * __builtin_amdgcn_rcpf(T.c0) : big;
+    cand[1] = T.c0 > 0.0f ? (T.hi0 - al0) * __builtin_amdgcn_rcpf(T.c0) : big;
+    cand[2] = T.a2 > 0.0f ? (T.lo2 - T.al2) * __builtin_amdgcn_rcpf(T.a2) : big;
+    cand[3] = T.a2 > 0.0f ? (T.hi2 - T.al2) * __builtin_amdgcn_rcpf(T.a2) : big;
+    float plo = T.lo1, phi = T.hi1;
 #pragma unroll
-        for (int k = 0; k < RUN_MAX; k++) {
-            if (k >= R.L) continue;
-            const unsigned bit = 1u << k;
-            if (!((hh | hl) & bit)) {
-                if (y[k] > R.hi[k]) nh |= bit;
-                else if (y[k] < R.lo[k]) nl |= bit;
-            } else if (!(k == 0 && pin != 0)) {
-                const float yp = (k == 0) ? x : y[k > 0 ? k - 1 : 0];
-                const float yn = (k == R.L - 1) ? R.sig : y[k + 1 < RUN_MAX ? k + 1 : k];
-                const float v = R.a[k] * yp + R.c[k] * yn - R.r[k] - y[k];
-                const float tau = RUN_TOL * (fabsf(R.a[k] * yp) + fabsf(R.c[k] * yn) + fabsf(R.r[k]) + fabsf(y[k]));
-                if ((hh & bit) && v < -tau) nh &= ~bit;
-                if ((hl & bit) && v > tau) nl &= ~bit;
-            }
-        }
-        if (nh == hh && nl == hl) break;
-        hh = nh; hl = nl;
+    for (int k = 0; k < 4; k++) {
+        const float p = mg_clip(cand[k], T.lo1, T.hi1);
+        const float v = psi(p);
+        if (v <= 0.0f && p > plo) plo = p;
+        if (v >= 0.0f && p < phi) phi = p;
     }
-#pragma unroll
-    for (int k = 0; k < RUN_MAX; k++)
-        if (k < R.L) y[k] = mg_clip(y[k], R.lo[k], R.hi[k]);
-    return true;
-}
-
-// unconstrained affine solution of the last cell: y_L = u_L + v_L x
-__device__ __forceinline__ bool run_affine_regs(const RunRegs &R, float &uL, float &vL)
-{
-    if (!R.ok) return false;
-    float pu = 0.0f, pv = 0.0f, q = 0.0f;
-#pragma unroll
-    for (int k = 0; k < RUN_MAX; k++) {
-        if (k >= R.L) continue;
-        const float a = R.a[k];
-        const float den = (k == 0) ? 1.0f : 1.0f - a * q;
-        if (!(den > 0.0f)) return false;
-        const float inv = __builtin_amdgcn_rcpf(den);
-        const float npu = (k == 0) ? -R.r[k] * inv : (a * pu - R.r[k]) * inv;
-        const float npv = (k == 0) ? a * inv : a * pv * inv;
-        pu = npu; pv = npv;
-        if (k == R.L - 1) { pu = pu + R.c[k] * inv * R.sig; q = 0.0f; }
-        else q = R.c[k] * inv;
+    if (!(phi > plo)) {
+        y1 = plo;
+    } else {
+        // the linear piece of h on (plo, phi)
+        const float m = 0.5f * (plo + phi);
+        float sl = 0.0f, t = -T.r1;
+        const float v0 = fmaf(T.c0, m, al0), v2 = fmaf(T.a2, m, T.al2);
+        if (v0 <= T.lo0) t = fmaf(T.a1, T.lo0, t);
+        else if (v0 >= T.hi0) t = fmaf(T.a1, T.hi0, t);
+        else { sl = fmaf(T.a1, T.c0, sl); t = fmaf(T.a1, al0, t); }
+        if (v2 <= T.lo2) t = fmaf(T.c1, T.lo2, t);
+        else if (v2 >= T.hi2) t = fmaf(T.c1, T.hi2, t);
+        else { sl = fmaf(T.c1, T.a2, sl); t = fmaf(T.c1, T.al2, t); }
+        y1 = mg_clip(mg_clip(t * __builtin_amdgcn_rcpf(1.0f - sl), T.lo1, T.hi1), plo, phi);
     }
-    uL = pu; vL = pv;
-    return true;
+    y0 = R0(y1);
+    y2 = R2(y1);
 }
-
-__device__ __forceinline__ float last_of(const float (&y)[RUN_MAX], int L)
+// two-cell solution of cells 1, 2 with cell 0 fixed at y0: value of cell 2
+__device__ __forceinline__ float tri_tail(const TriRows &T, float y0)
 {
-    float v = y[0];
-#pragma unroll
-    for (int k = 1; k < RUN_MAX; k++)
-        if (k == L - 1) v = y[k];
-    return v;
+    const float al1 = fmaf(T.a1, y0, -T.r1);
+    const float Lp = mg_clip(fmaf(T.a2, T.lo1, T.al2), T.lo2, T.hi2);
+    const float Up = mg_clip(fmaf(T.a2, T.hi1, T.al2), T.lo2, T.hi2);
+    return mg_clip(fmaf(T.a2, al1, T.al2) * __builtin_amdgcn_rcpf(1.0f - T.a2 * T.c1), Lp, Up);
 }
-
-// The map from the value entering the unit to the value of its last cell is
-// the clipped ramp clip(u_L + v_L x, y-, y+): y_L is the unconstrained
-// affine solution while every cell is free, and constant (y- / y+, the
-// solutions with cell 0 held at its bounds) once a cell holds.  yold: the
-// old value of the last cell (kept by a unit with an S = 0 cell).
-__device__ __forceinline__ Ramp unit_ramp(const RunRegs &R, float yold)
+__device__ __forceinline__ Ramp tri_ramp(const TriRows &T)
 {
-    float uL = 0.0f, vL = 0.0f, ylo = 0.0f, yhi = 0.0f, y[RUN_MAX];
-    bool ok = run_affine_regs(R, uL, vL);
-    const bool coupled = R.a[0] > 0.0f;
-#pragma nounroll
-    for (int s = 0; s < 2 && ok; s++) {
-        ok = run_vi_regs(R, 0.0f, coupled ? (s == 0 ? -1 : 1) : 0, y);
-        const float v = last_of(y, R.L);
-        if (s == 0) ylo = v;
-        else yhi = v;
-        if (!coupled) { yhi = ylo; vL = 0.0f; uL = ylo; break; }
+    if (!T.ok) return Ramp{0.0f, T.x2, T.x2, T.x2};
+    if (!(T.a0 > 0.0f)) {
+        float y0, y1, y2;
+        tri_solve(T, 0.0f, y0, y1, y2);
+        return Ramp{0.0f, y2, y2, y2};
     }
-    if (!ok) return Ramp{0.0f, yold, yold, yold};
-    return Ramp{vL, uL, fminf(ylo, yhi), fmaxf(ylo, yhi)};
+    // all cells free: y1 = (-r1 + a1 (a0 x - r0) + c1 al2) / D, y2 = al2 + a2 y1
+    const float invD = __builtin_amdgcn_rcpf(1.0f - T.a1 * T.c0 - T.c1 * T.a2);
+    const float u1 = (fmaf(T.c1, T.al2, -T.r1) - T.a1 * T.r0) * invD;
+    const float v1 = T.a1 * T.a0 * invD;
+    const float ym = tri_tail(T, T.lo0), yp = tri_tail(T, T.hi0);
+    return Ramp{T.a2 * v1, fmaf(T.a2, u1, T.al2), fminf(ym, yp), fmaxf(ym, yp)};
 }
 
 // starred-cell bit masks of the line (LDS): bit p of word p / 64
@@ -324,38 +312,62 @@ __device__ __forceinline__ void unit_of(const uint64_t *msk, int nw, int ml, int
 }
 
 // --------------------------------------------------------------------------
-// Block-wide exclusive scan of ramps in thread order: wave-level shuffles,
-// then the wave totals through LDS.  Also returns the block total.
-__device__ __forceinline__ Ramp shfl_ramp(const Ramp &r, int src_lane)
+// Block-wide exclusive scan of ramps in thread order.  Within a wave:
+// Hillis-Steele over rows of 16 lanes with DPP row shifts, then the row
+// totals with DPP row broadcasts (lanes whose source is outside the pattern
+// take the identity).  Across waves: the wave totals go through LDS and one
+// wave-level scan of them gives every wave its prefix.  wtot holds two sets
+// of NT/64 totals used alternately (parity), so consecutive scans need one
+// barrier each.
+template <int CTRL, int ROWM = 0xf>
+__device__ __forceinline__ float dpp_f(float old, float src)
 {
-    return Ramp{__shfl(r.a, src_lane), __shfl(r.b, src_lane), __shfl(r.lo, src_lane), __shfl(r.hi, src_lane)};
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(src), CTRL, ROWM, 0xf,
+                                                      false));
+}
+template <int CTRL, int ROWM = 0xf>
+__device__ __forceinline__ Ramp dpp_ramp(const Ramp &r)
+{
+    const Ramp id = ramp_id();
+    return Ramp{dpp_f<CTRL, ROWM>(id.a, r.a), dpp_f<CTRL, ROWM>(id.b, r.b), dpp_f<CTRL, ROWM>(id.lo, r.lo),
+                dpp_f<CTRL, ROWM>(id.hi, r.hi)};
+}
+// inclusive scan over the 64 lanes of a wave (lane order)
+__device__ __forceinline__ Ramp wave_scan_incl(Ramp v)
+{
+    v = ramp_comp(v, dpp_ramp<0x111>(v));          // row_shr:1
+    v = ramp_comp(v, dpp_ramp<0x112>(v));          // row_shr:2
+    v = ramp_comp(v, dpp_ramp<0x114>(v));          // row_shr:4
+    v = ramp_comp(v, dpp_ramp<0x118>(v));          // row_shr:8
+    v = ramp_comp(v, dpp_ramp<0x142, 0xa>(v));     // row_bcast:15 into rows 1, 3
+    v = ramp_comp(v, dpp_ramp<0x143, 0xc>(v));     // row_bcast:31 into rows 2, 3
+    return v;
+}
+__device__ __forceinline__ Ramp readlane_ramp(const Ramp &r, int lane)
+{
+    return Ramp{__int_as_float(__builtin_amdgcn_readlane(__float_as_int(r.a), lane)),
+                __int_as_float(__builtin_amdgcn_readlane(__float_as_int(r.b), lane)),
+                __int_as_float(__builtin_amdgcn_readlane(__float_as_int(r.lo), lane)),
+                __int_as_float(__builtin_amdgcn_readlane(__float_as_int(r.hi), lane))};
 }
 
 template <int NT>
-__device__ __forceinline__ Ramp block_scan_excl(Ramp mine, Ramp *wtot, Ramp &total)
+__device__ __forceinline__ Ramp block_scan_excl(Ramp mine, Ramp *wtot, int parity, Ramp &total)
 {
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     constexpr int NW = NT / 64;
-    Ramp inc = mine;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        Ramp o = shfl_ramp(inc, (lane - off) & 63);
-        if (lane >= off) inc = ramp_comp(inc, o);
-    }
-    Ramp ex = shfl_ramp(inc, (lane - 1) & 63);
-    if (lane == 0) ex = ramp_id();
+    const Ramp inc = wave_scan_incl(mine);
+    Ramp ex = dpp_ramp<0x138>(inc);                 // wave_shr:1 (lane 0: identity)
     if (NW > 1) {
-        if (lane == 63) wtot[wave] = inc;
+        Ramp *wt = wtot + parity * NW;
+        if (lane == 63) wt[wave] = inc;
         __syncthreads();
-        Ramp pre = ramp_id();
-        for (int w = 0; w < wave; w++) pre = ramp_comp(wtot[w], pre);
-        ex = ramp_comp(ex, pre);
-        Ramp tot = ramp_id();
-        for (int w = 0; w < NW; w++) tot = ramp_comp(wtot[w], tot);
-        total = tot;
-        __syncthreads();
+        const Ramp ws = wave_scan_incl(lane < NW ? wt[lane] : ramp_id());
+        const int wv = __builtin_amdgcn_readfirstlane(wave);
+        if (wv > 0) ex = ramp_comp(ex, readlane_ramp(ws, wv - 1));
+        total = readlane_ramp(ws, NW - 1);
     } else {
-        total = shfl_ramp(inc, 63);
+        total = readlane_ramp(inc, 63);
     }
     return ex;
 }
@@ -473,9 +485,15 @@ __device__ __forceinline__ void sweep_line(const LineArgs &A, int r, const RunBu
                 if (ps == p) {
                     ustart |= 1u << k;
                     uL[k] = L;
-                    RunRegs R;
-                    run_load(B, p, L, ml, R);
-                    um[k] = unit_ramp(R, B.at(RF_X, p + L - 1));
+                    if (L <= 2) {
+                        PairRows Q;
+                        pair_load(B, p, L, ml, Q);
+                        um[k] = pair_ramp(Q, L);
+                    } else {
+                        TriRows T3;
+                        tri_load(B, p, ml, T3);
+                        um[k] = tri_ramp(T3);
+                    }
                 }
             } else if (p >= 1 && mask_bit(msk, p - 1) && (p < 2 || !mask_bit(msk, p - 2))) {
                 inunit |= 1u << k;         // the cell after a single starred cell
@@ -496,7 +514,7 @@ __device__ __forceinline__ void sweep_line(const LineArgs &A, int r, const RunBu
             else if ((ustart >> k) & 1) u = um[k];
         }
         Ramp tot;
-        const Ramp ex = block_scan_excl<NT>(u, wtot, tot);
+        const Ramp ex = block_scan_excl<NT>(u, wtot, k & 1, tot);
         const float x = ramp_eval(ex, carry);
         if (p < ml) {
             if ((ustart >> k) & 1) xin[k] = x;
@@ -511,16 +529,22 @@ __device__ __forceinline__ void sweep_line(const LineArgs &A, int r, const RunBu
         for (int k = 0; k < K; k++) {
             if (!((ustart >> k) & 1)) continue;
             const int p = k * NT + t;
-            RunRegs R;
-            run_load(B, p, uL[k], ml, R);
-            float y[RUN_MAX];
-            if (!run_vi_regs(R, xin[k], 0, y)) {
-#pragma unroll
-                for (int c = 0; c < RUN_MAX; c++) y[c] = c < uL[k] ? B.at(RF_X, p + c) : 0.0f;
+            if (uL[k] <= 2) {
+                PairRows Q;
+                pair_load(B, p, uL[k], ml, Q);
+                float y0, y1;
+                pair_solve(Q, uL[k], xin[k], y0, y1);
+                B.at(RF_Y, p) = y0;
+                if (uL[k] == 2) B.at(RF_Y, p + 1) = y1;
+                continue;
             }
-#pragma unroll
-            for (int c = 0; c < RUN_MAX; c++)
-                if (c < uL[k]) B.at(RF_Y, p + c) = y[c];
+            TriRows T3;
+            tri_load(B, p, ml, T3);
+            float y0, y1, y2;
+            tri_solve(T3, xin[k], y0, y1, y2);
+            B.at(RF_Y, p) = y0;
+            B.at(RF_Y, p + 1) = y1;
+            B.at(RF_Y, p + 2) = y2;
         }
         __syncthreads();
 #pragma unroll
@@ -604,7 +628,7 @@ template <int NT, int K, bool REV>
 __global__ void __launch_bounds__(NT) k_sweep(LineArgs A)
 {
     extern __shared__ uint64_t smem64[];
-    __shared__ Ramp wtot[NT / 64 > 0 ? NT / 64 : 1];
+    __shared__ Ramp wtot[2 * (NT / 64 > 0 ? NT / 64 : 1)];
     uint64_t *msk = smem64;
     RunBuf B;
     B.fs = A.ml;

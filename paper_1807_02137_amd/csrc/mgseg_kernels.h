@@ -823,7 +823,7 @@ __device__ void block_transpose(const float *in, int pin, float *out, int pout, 
 template <int NT>
 __global__ void __launch_bounds__(NT) k_coarse_smooth(CoarseArgs G)
 {
-    __shared__ Ramp sh[NT / 64 > 0 ? NT / 64 : 1];
+    __shared__ Ramp sh[2 * (NT / 64 > 0 ? NT / 64 : 1)];
     __shared__ double red[NT];
     __shared__ float rdt[NT];
     __shared__ float rb[RF_COUNT * NT];
