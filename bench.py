@@ -111,14 +111,16 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     cycles, rels, oks = [], [], []
-    prof_ms, prof_n, prof_bytes = 0.0, 0, 0.0
     for _ in range(args.steps):
-        cyc, rel, ok, prof = step(profile=True)
+        cyc, rel, ok, _ = step()
         cycles.append(cyc); rels.append(rel); oks.append(ok)
-        prof_ms += prof[0]; prof_n += prof[1]; prof_bytes = prof[2]
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     wall = t1 - t0
+    # kernel timing: one more solve outside the timed region, launched eagerly
+    # with HIP events around every finest-grid sweep on the solver's stream
+    _, _, _, prof = step(profile=True)
+    prof_ms, prof_n, prof_bytes = prof
     npts = N * N
     value = npts * sum(cycles) / wall
     avg_ms = prof_ms / max(prof_n, 1)

@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <type_traits>
@@ -61,6 +62,10 @@ struct mgseg_ctx {
     std::vector<void *> allocs;
     hipError_t err = hipSuccess;
     bool oom = false;
+    // one V-cycle captured as a HIP graph (replayed on s); cap: private capture stream
+    hipGraphExec_t gexec = nullptr;
+    hipStream_t cap = nullptr;
+    bool graph_failed = false;
     // event timing of the finest-grid sweep launches
     bool prof_on = false;
     std::vector<hipEvent_t> ev_pool;
@@ -341,7 +346,8 @@ void freeze(mgseg_ctx *c, int l)
             using BT = std::remove_const_t<std::remove_pointer_t<decltype(A.b)>>;
             A.area_u = rc ? c->dsc + DS_AREA_FRZ : nullptr;
             A.psi_cm = L.psi_cm; A.T_cm = L.F_cm; A.lab_cm = L.lab_cm;
-            hipLaunchKernelGGL(k_freeze_dev<BT>, grid2(L.n, L.m), dim3(256), 0, c->s, A);
+            dim3 gt((L.m + TILE - 1) / TILE, (L.n + TILE - 1) / TILE);
+            hipLaunchKernelGGL(k_freeze_dev<BT>, gt, dim3(TILE, TILE), 0, c->s, A);
         });
         L.has_F = true;
         chk(c);
@@ -515,7 +521,10 @@ mgseg_status refresh_and_residual(mgseg_ctx *c)
     return MGSEG_OK;
 }
 
-mgseg_status one_cycle(mgseg_ctx *c, double *rel_out)
+// the device work of one cycle (V-cycle, finest update, c refresh, FP64
+// residual, eta partials), all on c->s and without host synchronisation
+// unless the coarsest grid needs the multi-kernel path
+void enqueue_cycle(mgseg_ctx *c)
 {
     Level &L0 = c->lev[0];
     size_t N = (size_t)c->n * c->m;
@@ -535,6 +544,60 @@ mgseg_status one_cycle(mgseg_ctx *c, double *rel_out)
     int nb = std::min(RED_BLOCKS, std::max(1, (int)((N + 255) / 256)));
     hipLaunchKernelGGL(k_eta, dim3(nb), dim3(256), 0, c->s, c->phi64, c->prev64, (long long)N, c->part + 4 * RED_BLOCKS);
     chk(c);
+}
+
+// A cycle can be captured when no step synchronises with the host: the
+// coarsest grid is 1x1 or fits the single-workgroup kernel.  Event timing
+// and MGSEG_GRAPH=0 in the environment keep the eager launches.
+bool graph_usable(const mgseg_ctx *c)
+{
+    if (c->prof_on || c->graph_failed) return false;
+    const char *env = std::getenv("MGSEG_GRAPH");
+    if (env && env[0] == '0') return false;
+    const Level &Lc = c->lev[c->L - 1];
+    if (Lc.n * Lc.m == 1) return true;
+    return c->L > 1 && Lc.n <= 64 && Lc.m <= 64 && Lc.n * Lc.m <= CO_MAX_CELLS;
+}
+
+// capture enqueue_cycle on a private stream, instantiate once
+bool build_graph(mgseg_ctx *c)
+{
+    if (!c->cap && hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    hipStream_t user = c->s;
+    c->s = c->cap;
+    hipGraph_t g = nullptr;
+    bool ok = hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (ok) {
+        enqueue_cycle(c);
+        ok = hipStreamEndCapture(c->cap, &g) == hipSuccess && g != nullptr && c->err == hipSuccess;
+    }
+    c->s = user;
+    if (ok) ok = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0) == hipSuccess;
+    if (g) (void)hipGraphDestroy(g);
+    if (!ok) {
+        c->gexec = nullptr;
+        (void)hipGetLastError();
+        c->err = hipSuccess;
+    }
+    return ok;
+}
+
+mgseg_status one_cycle(mgseg_ctx *c, double *rel_out)
+{
+    size_t N = (size_t)c->n * c->m;
+    bool launched = false;
+    if (graph_usable(c)) {
+        if (!c->gexec && !build_graph(c)) c->graph_failed = true;
+        if (c->gexec) {
+            if (hipGraphLaunch(c->gexec, c->s) == hipSuccess) launched = true;
+            else { (void)hipGetLastError(); c->graph_failed = true; }
+        }
+    }
+    if (!launched) enqueue_cycle(c);
+    int nb = std::min(RED_BLOCKS, std::max(1, (int)((N + 255) / 256)));
     std::vector<double> eh(2 * nb);
     double res = 0.0;
     (void)hipMemcpyAsync(&res, c->dsc + DS_RES, sizeof(double), hipMemcpyDeviceToHost, c->s);
@@ -588,6 +651,8 @@ void mgseg_destroy(mgseg_ctx *c)
 {
     if (!c) return;
     if (c->s) (void)hipStreamSynchronize(c->s);
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->cap) (void)hipStreamDestroy(c->cap);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     for (void *p : c->allocs) (void)hipFree(p);
     delete c;

@@ -583,10 +583,17 @@ __device__ __forceinline__ void sweep_band(const LineArgs &A, int b, const RunBu
     // site.  Forward order: r0, r0+1, r0+2, [r0+4 recomputed], r0+3.
     // Reverse order: r0+3, r0+2, r0+1, [r0-1 recomputed], r0.
     float prev[K], red[K], cur[K];
+    // transposed output of a full band: the band's 4 lines are 4 consecutive
+    // floats of the output layout, written as one 16-byte store per cell
+    float o0[K], o1[K], o2[K], o3[K];
 #pragma unroll
-    for (int k = 0; k < K; k++) { prev[k] = 0.0f; red[k] = 0.0f; cur[k] = 0.0f; }
-    const int nl = A.nl;
+    for (int k = 0; k < K; k++) {
+        prev[k] = 0.0f; red[k] = 0.0f; cur[k] = 0.0f;
+        o0[k] = 0.0f; o1[k] = 0.0f; o2[k] = 0.0f; o3[k] = 0.0f;
+    }
+    const int nl = A.nl, ml = A.ml;
     const int r0 = 4 * b;
+    const bool pack = A.tout != nullptr && r0 + 3 < nl;
     bool have_prev = false;      // prev holds the previously processed own line
 #pragma nounroll
     for (int st = 0; st < 5; st++) {
@@ -605,13 +612,30 @@ __device__ __forceinline__ void sweep_band(const LineArgs &A, int b, const RunBu
             int rn = REV ? r0 - 1 : r0 + 4;
             dn_fresh = rn >= 0 && rn < nl;
         }
-        sweep_line<NT, K, REV>(A, r, B, msk, !redundant, prev, up_fresh, red, dn_fresh, cur, wtot);
+        sweep_line<NT, K, REV>(A, r, B, msk, !redundant && !pack, prev, up_fresh, red, dn_fresh, cur, wtot);
+        const int li = r - r0;
 #pragma unroll
         for (int k = 0; k < K; k++) {
             if (redundant) red[k] = cur[k];
             else prev[k] = cur[k];
+            if (!redundant) {
+                if (li == 0) o0[k] = cur[k];
+                else if (li == 1) o1[k] = cur[k];
+                else if (li == 2) o2[k] = cur[k];
+                else o3[k] = cur[k];
+            }
         }
         if (!redundant) have_prev = true;
+    }
+    if (pack) {
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+            const int p = k * NT + threadIdx.x;
+            if (p >= ml) continue;
+            const int q = REV ? ml - 1 - p : p;
+            *reinterpret_cast<float4 *>(A.tout + (long long)q * A.tpitch + r0) =
+                make_float4(o0[k], o1[k], o2[k], o3[k]);
+        }
     }
 }
 

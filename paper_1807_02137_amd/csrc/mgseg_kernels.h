@@ -659,25 +659,39 @@ __device__ __forceinline__ double dev_cell(const DevArgs<BT> &A, int i, int j, b
     return t;
 }
 
-// freeze in deviation form: psi = fl32(b + e), T, labels
+// freeze in deviation form: psi = fl32(b + e), T, labels.  32 x 32 tiles:
+// row-major outputs written directly, column-major copies through LDS so that
+// both layouts are written coalesced.  Block (32, 32), one cell per thread.
 template <typename BT>
-__global__ void k_freeze_dev(DevArgs<BT> A)
+__global__ void __launch_bounds__(1024) k_freeze_dev(DevArgs<BT> A)
 {
-    int j = blockIdx.x * blockDim.x + threadIdx.x, i = blockIdx.y;
-    if (j >= A.m || i >= A.n) return;
-    double Le;
-    float u0;
-    uint8_t lab;
-    const double t = dev_cell(A, i, j, false, Le, u0, lab);
-    const long long q = (long long)i * A.p + j;
-    A.psi[q] = u0;
-    A.T[q] = (float)t;
-    A.lab[q] = lab;
-    if (A.psi_cm) {
-        const long long qc = (long long)j * A.pc + i;
-        A.psi_cm[qc] = u0;
-        A.T_cm[qc] = (float)t;
-        A.lab_cm[qc] = lab;
+    __shared__ float tp[TILE][TILE + 1], tt[TILE][TILE + 1];
+    __shared__ uint8_t tl[TILE][TILE + 1];
+    const int bx = blockIdx.x * TILE, by = blockIdx.y * TILE;
+    for (int y = threadIdx.y; y < TILE; y += blockDim.y) {
+        const int i = by + y, j = bx + threadIdx.x;
+        if (i < A.n && j < A.m) {
+            double Le;
+            float u0;
+            uint8_t lab;
+            const double t = dev_cell(A, i, j, false, Le, u0, lab);
+            const long long q = (long long)i * A.p + j;
+            A.psi[q] = u0;
+            A.T[q] = (float)t;
+            A.lab[q] = lab;
+            tp[y][threadIdx.x] = u0; tt[y][threadIdx.x] = (float)t; tl[y][threadIdx.x] = lab;
+        }
+    }
+    if (!A.psi_cm) return;
+    __syncthreads();
+    for (int y = threadIdx.y; y < TILE; y += blockDim.y) {
+        const int j = bx + y, i = by + threadIdx.x;
+        if (i < A.n && j < A.m) {
+            const long long qc = (long long)j * A.pc + i;
+            A.psi_cm[qc] = tp[threadIdx.x][y];
+            A.T_cm[qc] = tt[threadIdx.x][y];
+            A.lab_cm[qc] = tl[threadIdx.x][y];
+        }
     }
 }
 
