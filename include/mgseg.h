@@ -173,6 +173,52 @@ mgseg_status mgseg_profile(mgseg_ctx *c, int kernel, int enable);
 mgseg_status mgseg_profile_read(mgseg_ctx *c, int kernel, double *total_ms, int *count,
                                 double *bytes_per_launch);
 
+/* ------------------------------------------------------------------------
+ * Batches of images of uneven size.  Each image is solved by its own
+ * context exactly as by mgseg_setup / mgseg_solve (Algorithm-1 box with
+ * Hybrid Smoother 2); the batch issues the images' V-cycles on `nstreams`
+ * internal streams so that the latency-bound coarse grids of different
+ * images overlap, waits once per round of cycles, and drops converged images
+ * from later rounds.  Results are bit-identical to solving the images one by
+ * one.
+ *   images_dev[i], n[i], m[i], pitch[i], markers_host[i], k[i]: as in
+ *     mgseg_setup for image i (count >= 1); p: shared parameters (levels = 0
+ *     lets each image take as many grids as its size allows).
+ *   stream: the caller's stream; setup work is enqueued on it, and
+ *     mgseg_solve_batch makes the internal streams wait for it on entry and
+ *     it wait for them on return.
+ * Errors: as mgseg_setup, for the first image that fails (earlier contexts
+ * are released).
+ */
+typedef struct mgseg_batch mgseg_batch;
+mgseg_status mgseg_setup_batch(int count, const float *const *images_dev, const int *n, const int *m,
+                               const int *pitch, const float *const *markers_host, const int *k,
+                               const mgseg_params *p, void *stream, mgseg_batch **out);
+
+/* Autotuner: one untimed round of cycles, then `trial_rounds` timed rounds of
+ * one V-cycle on every image for each stream count in {1, 2, 4, 8} (at most
+ * the image count); keeps the fastest.  The tuning cycles are real V-cycles
+ * and count in the images' cycle totals.  Outputs (may be null): the chosen
+ * stream count and its measured time per round in milliseconds. */
+mgseg_status mgseg_batch_tune(mgseg_batch *b, int trial_rounds, int *nstreams_out, double *ms_per_round_out);
+
+/* Sets the stream count (1..8) without tuning. */
+mgseg_status mgseg_batch_set_streams(mgseg_batch *b, int nstreams);
+
+/* V-cycles on every image whose |r~|/|r~_0| is above tol, until all are at
+ * tol or have done max_cycles cycles in total.  cycles_out[count] and
+ * rel_out[count] (may be null) receive each image's totals.  Returns
+ * MGSEG_E_NOT_CONVERGED (outputs valid) if any image stopped at max_cycles. */
+mgseg_status mgseg_solve_batch(mgseg_batch *b, double tol, int max_cycles, int *cycles_out, double *rel_out);
+
+/* The context of image `index` (owned by the batch; valid until
+ * mgseg_destroy_batch): use it with mgseg_get_phi, mgseg_get_mask,
+ * mgseg_get_stats. */
+mgseg_status mgseg_batch_ctx(mgseg_batch *b, int index, mgseg_ctx **view);
+
+/* Releases every context and stream of the batch (NULL is a no-op). */
+void mgseg_destroy_batch(mgseg_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,6 +1,7 @@
 // mgseg.hip -- libmgseg host driver and C ABI (see include/mgseg.h).
 #include <hip/hip_runtime.h>
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -23,6 +24,7 @@ enum {
     DS_AREA_EVAL = 3,         // area term for operator evaluations
     DS_AREA64 = 4,            // area term at the FP64 finest phi
     DS_RES = 5,               // last residual norm
+    DS_ETA = 6,               // last relative change of phi (right after DS_RES)
     DS_AREAB0 = 8,            // deviation form: area term at the base of level l is slot DS_AREAB0 + l
     DS_CO = 8 + MAXLEV,       // coarsest-solve changes (2 slots)
     DS_COUNT = 8 + MAXLEV + 2
@@ -57,6 +59,9 @@ struct mgseg_ctx {
     int part_n = 0;
     float *scr = nullptr;           // unit-row scratch of long lines
     float *co_prev = nullptr, *co_entry = nullptr;   // multi-kernel coarsest solve
+    int *flags = nullptr;           // device flags: [0] coarsest solve finished
+    double *hres = nullptr;         // pinned host copy of DS_RES, DS_ETA
+    const int *sweep_skip = nullptr;
     double *hull_d = nullptr, *mk_d = nullptr;
     int hv = 0, k = 0;
     std::vector<void *> allocs;
@@ -232,7 +237,7 @@ void launch_sweep(mgseg_ctx *c, int l, int s, const float *phi_old, float *phi_n
     Level &L = c->lev[l];
     bool cm = s >= 2;
     LineArgs A;
-    A.phi_old = phi_old; A.phi_new = phi_new; A.tout = tout; A.tpitch = tpitch;
+    A.phi_old = phi_old; A.phi_new = phi_new; A.tout = tout; A.tpitch = tpitch; A.skip = c->sweep_skip;
     A.psi = cm ? L.psi_cm : L.psi;
     A.w = cm ? L.w_cm : L.w;
     A.fit = devm(c) ? nullptr : (cm ? L.fit_cm : L.fit);
@@ -406,20 +411,20 @@ void coarsest(mgseg_ctx *c, int l)
         chk(c);
         return;
     }
-    // multi-kernel path: one outer iteration per step, with the stopping test
-    // read back after each
+    // multi-kernel path: all coarse_iters outer iterations are enqueued; the
+    // stopping test sets a device flag after which the sweeps return at once
+    // (the freezes of the remaining iterations recompute the same state)
     const size_t bytes = sizeof(float) * (size_t)L.n * L.prm;
+    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, c->s, c->flags, 0);
     (void)hipMemcpyAsync(c->co_entry, L.P[0], bytes, hipMemcpyDeviceToDevice, c->s);
+    c->sweep_skip = c->flags;
     for (int it = 0; it < c->p.coarse_iters; it++) {
         (void)hipMemcpyAsync(c->co_prev, L.P[0], bytes, hipMemcpyDeviceToDevice, c->s);
         outer(c, l);
         hipLaunchKernelGGL(k_coarse_delta, dim3(1), dim3(256), 0, c->s, L.P[0], c->co_prev, c->co_entry, L.prm, L.n,
-                           L.m, c->dsc + DS_CO);
-        double d[2] = {0.0, 0.0};
-        (void)hipMemcpyAsync(d, c->dsc + DS_CO, sizeof(d), hipMemcpyDeviceToHost, c->s);
-        if (hipStreamSynchronize(c->s) != hipSuccess) { chk(c); return; }
-        if (d[0] <= c->p.coarse_rtol * d[1]) break;
+                           L.m, c->p.coarse_rtol, c->flags);
     }
+    c->sweep_skip = nullptr;
     chk(c);
 }
 
@@ -543,20 +548,20 @@ void enqueue_cycle(mgseg_ctx *c)
     refresh_and_residual(c);
     int nb = std::min(RED_BLOCKS, std::max(1, (int)((N + 255) / 256)));
     hipLaunchKernelGGL(k_eta, dim3(nb), dim3(256), 0, c->s, c->phi64, c->prev64, (long long)N, c->part + 4 * RED_BLOCKS);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FIN_NT), 0, c->s, c->part + 4 * RED_BLOCKS, nb, 3, 0.0, 0.0, 0.0, 0.0,
+                       c->dsc + DS_ETA);
     chk(c);
 }
 
-// A cycle can be captured when no step synchronises with the host: the
-// coarsest grid is 1x1 or fits the single-workgroup kernel.  Event timing
-// and MGSEG_GRAPH=0 in the environment keep the eager launches.
+// Every step of a cycle runs without host synchronisation, so the whole
+// cycle can be captured.  Event timing and MGSEG_GRAPH=0 in the environment
+// keep the eager launches.
 bool graph_usable(const mgseg_ctx *c)
 {
     if (c->prof_on || c->graph_failed) return false;
     const char *env = std::getenv("MGSEG_GRAPH");
     if (env && env[0] == '0') return false;
-    const Level &Lc = c->lev[c->L - 1];
-    if (Lc.n * Lc.m == 1) return true;
-    return c->L > 1 && Lc.n <= 64 && Lc.m <= 64 && Lc.n * Lc.m <= CO_MAX_CELLS;
+    return true;
 }
 
 // capture enqueue_cycle on a private stream, instantiate once
@@ -585,9 +590,10 @@ bool build_graph(mgseg_ctx *c)
     return ok;
 }
 
-mgseg_status one_cycle(mgseg_ctx *c, double *rel_out)
+// enqueue one cycle and the copy of its residual norm and eta to pinned host
+// memory; cycle_end reads them after the stream has been synchronised
+void cycle_begin(mgseg_ctx *c)
 {
-    size_t N = (size_t)c->n * c->m;
     bool launched = false;
     if (graph_usable(c)) {
         if (!c->gexec && !build_graph(c)) c->graph_failed = true;
@@ -597,22 +603,29 @@ mgseg_status one_cycle(mgseg_ctx *c, double *rel_out)
         }
     }
     if (!launched) enqueue_cycle(c);
-    int nb = std::min(RED_BLOCKS, std::max(1, (int)((N + 255) / 256)));
-    std::vector<double> eh(2 * nb);
-    double res = 0.0;
-    (void)hipMemcpyAsync(&res, c->dsc + DS_RES, sizeof(double), hipMemcpyDeviceToHost, c->s);
-    (void)hipMemcpyAsync(eh.data(), c->part + 4 * RED_BLOCKS, sizeof(double) * 2 * nb, hipMemcpyDeviceToHost, c->s);
-    mgseg_status st = sync_status(c);
-    if (st != MGSEG_OK) return st;
-    double d2 = 0.0, p2 = 0.0;
-    for (int b = 0; b < nb; b++) { d2 += eh[2 * b]; p2 += eh[2 * b + 1]; }
-    c->eta = p2 > 0.0 ? std::sqrt(d2 / p2) : 0.0;
+    (void)hipMemcpyAsync(c->hres, c->dsc + DS_RES, 2 * sizeof(double), hipMemcpyDeviceToHost, c->s);
+    chk(c);
+}
+
+mgseg_status cycle_end(mgseg_ctx *c, double *rel_out)
+{
+    if (c->err != hipSuccess) return MGSEG_E_HIP;
+    const double res = c->hres[0];
+    c->eta = c->hres[1];
     c->res = res;
     c->cycles++;
     c->rel = c->res0 > 0.0 ? res / c->res0 : 0.0;
     if (rel_out) *rel_out = c->rel;
     if (!std::isfinite(res)) return MGSEG_E_NONFINITE;
     return MGSEG_OK;
+}
+
+mgseg_status one_cycle(mgseg_ctx *c, double *rel_out)
+{
+    cycle_begin(c);
+    mgseg_status st = sync_status(c);
+    if (st != MGSEG_OK) return st;
+    return cycle_end(c, rel_out);
 }
 
 }  // namespace
@@ -653,6 +666,7 @@ void mgseg_destroy(mgseg_ctx *c)
     if (c->s) (void)hipStreamSynchronize(c->s);
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     if (c->cap) (void)hipStreamDestroy(c->cap);
+    if (c->hres) (void)hipHostFree(c->hres);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     for (void *p : c->allocs) (void)hipFree(p);
     delete c;
@@ -715,6 +729,12 @@ mgseg_status mgseg_setup(const float *image_dev, int n, int m, int pitch, const 
         const Level &Lc = c->lev[Lv - 1];
         c->co_prev = dalloc<float>(c, (size_t)Lc.n * Lc.prm);
         c->co_entry = dalloc<float>(c, (size_t)Lc.n * Lc.prm);
+    }
+    c->flags = dalloc<int>(c, 4);
+    if (hipHostMalloc((void **)&c->hres, 2 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        c->hres = nullptr;
+        c->oom = true;
     }
     double *zb = dalloc<double>(c, N), *t64 = dalloc<double>(c, N);
     c->mk_d = dalloc<double>(c, 2 * (size_t)k);
@@ -996,6 +1016,198 @@ mgseg_status mgseg_profile_read(mgseg_ctx *c, int kernel, double *total_ms, int 
         double per = 4.0 * 3 + 1.0 + 4.0 + (devm(c) ? 8.0 + 4.0 : 4.0 + (c->lev[0].has_F ? 4.0 : 0.0));
         *bytes_per_launch = (double)c->n * c->m * per;
     }
+    return MGSEG_OK;
+}
+
+
+}  // extern "C"
+
+// --------------------------------------------------------------------------
+// batches
+struct mgseg_batch {
+    std::vector<mgseg_ctx *> ctx;
+    std::vector<int> order;                 // images by decreasing size (LPT)
+    std::vector<hipStream_t> streams;       // internal streams (default priority)
+    std::vector<hipEvent_t> done;           // one per internal stream
+    hipEvent_t entry = nullptr;
+    hipStream_t user = nullptr;
+    int nstreams = 4;
+};
+
+namespace {
+
+// longest-processing-time assignment of images to the first S streams
+void batch_assign(mgseg_batch *b, int S)
+{
+    std::vector<double> load(S, 0.0);
+    for (int i : b->order) {
+        int best = 0;
+        for (int s = 1; s < S; s++)
+            if (load[s] < load[best]) best = s;
+        load[best] += (double)b->ctx[i]->n * b->ctx[i]->m;
+        b->ctx[i]->s = b->streams[best];
+    }
+    b->nstreams = S;
+}
+
+// one cycle on every listed image, then one wait per stream
+mgseg_status batch_round(mgseg_batch *b, const std::vector<int> &imgs, std::vector<double> &rel)
+{
+    for (int i : imgs) cycle_begin(b->ctx[i]);
+    mgseg_status st = MGSEG_OK;
+    for (int s = 0; s < b->nstreams; s++)
+        if (hipStreamSynchronize(b->streams[s]) != hipSuccess) st = MGSEG_E_HIP;
+    if (st != MGSEG_OK) return st;
+    for (int i : imgs) {
+        mgseg_status e = cycle_end(b->ctx[i], &rel[i]);
+        if (e != MGSEG_OK) st = e;
+    }
+    return st;
+}
+
+void batch_enter(mgseg_batch *b)
+{
+    (void)hipEventRecord(b->entry, b->user);
+    for (int s = 0; s < (int)b->streams.size(); s++) (void)hipStreamWaitEvent(b->streams[s], b->entry, 0);
+}
+
+void batch_leave(mgseg_batch *b)
+{
+    for (int s = 0; s < (int)b->streams.size(); s++) {
+        (void)hipEventRecord(b->done[s], b->streams[s]);
+        (void)hipStreamWaitEvent(b->user, b->done[s], 0);
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+void mgseg_destroy_batch(mgseg_batch *b)
+{
+    if (!b) return;
+    for (auto s : b->streams) (void)hipStreamSynchronize(s);
+    for (auto c : b->ctx) {
+        c->s = b->user;           // contexts release their buffers on the caller's stream
+        mgseg_destroy(c);
+    }
+    for (auto e : b->done) (void)hipEventDestroy(e);
+    if (b->entry) (void)hipEventDestroy(b->entry);
+    for (auto s : b->streams) (void)hipStreamDestroy(s);
+    delete b;
+}
+
+mgseg_status mgseg_setup_batch(int count, const float *const *images_dev, const int *n, const int *m,
+                               const int *pitch, const float *const *markers_host, const int *k,
+                               const mgseg_params *p, void *stream, mgseg_batch **out)
+{
+    if (!out) return MGSEG_E_ARG;
+    *out = nullptr;
+    if (count < 1 || !images_dev || !n || !m || !pitch || !markers_host || !k || !p) return MGSEG_E_ARG;
+    mgseg_batch *b = new (std::nothrow) mgseg_batch();
+    if (!b) return MGSEG_E_NOMEM;
+    b->user = (hipStream_t)stream;
+    for (int s = 0; s < 8; s++) {
+        hipStream_t h = nullptr;
+        hipEvent_t e = nullptr;
+        if (hipStreamCreateWithFlags(&h, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+            (void)hipGetLastError();
+            if (h) (void)hipStreamDestroy(h);
+            mgseg_destroy_batch(b);
+            return MGSEG_E_HIP;
+        }
+        b->streams.push_back(h);
+        b->done.push_back(e);
+    }
+    if (hipEventCreateWithFlags(&b->entry, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        mgseg_destroy_batch(b);
+        return MGSEG_E_HIP;
+    }
+    for (int i = 0; i < count; i++) {
+        mgseg_ctx *c = nullptr;
+        mgseg_status st = mgseg_setup(images_dev[i], n[i], m[i], pitch[i], markers_host[i], k[i], p, stream, &c);
+        if (st != MGSEG_OK) { mgseg_destroy_batch(b); return st; }
+        b->ctx.push_back(c);
+    }
+    b->order.resize(count);
+    for (int i = 0; i < count; i++) b->order[i] = i;
+    std::stable_sort(b->order.begin(), b->order.end(), [&](int x, int y) {
+        return (double)b->ctx[x]->n * b->ctx[x]->m > (double)b->ctx[y]->n * b->ctx[y]->m;
+    });
+    batch_assign(b, std::min(4, count));
+    *out = b;
+    return MGSEG_OK;
+}
+
+mgseg_status mgseg_batch_set_streams(mgseg_batch *b, int nstreams)
+{
+    if (!b || nstreams < 1 || nstreams > (int)b->streams.size()) return MGSEG_E_ARG;
+    for (auto s : b->streams) (void)hipStreamSynchronize(s);
+    batch_assign(b, nstreams);
+    return MGSEG_OK;
+}
+
+mgseg_status mgseg_batch_tune(mgseg_batch *b, int trial_rounds, int *nstreams_out, double *ms_per_round_out)
+{
+    if (!b || trial_rounds < 1) return MGSEG_E_ARG;
+    const int count = (int)b->ctx.size();
+    std::vector<int> all(count);
+    for (int i = 0; i < count; i++) all[i] = i;
+    std::vector<double> rel(count, 0.0);
+    batch_enter(b);
+    mgseg_status st = batch_round(b, all, rel);      // untimed: first use captures each cycle
+    int best = b->nstreams;
+    double best_ms = 1e300;
+    for (int S = 1; S <= 8 && st == MGSEG_OK; S *= 2) {
+        if (S > count) break;
+        batch_assign(b, S);
+        auto t0 = std::chrono::steady_clock::now();
+        for (int r = 0; r < trial_rounds && st == MGSEG_OK; r++) st = batch_round(b, all, rel);
+        const double ms =
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count() / trial_rounds;
+        if (ms < best_ms) { best_ms = ms; best = S; }
+    }
+    batch_assign(b, best);
+    batch_leave(b);
+    if (nstreams_out) *nstreams_out = best;
+    if (ms_per_round_out) *ms_per_round_out = best_ms;
+    return st;
+}
+
+mgseg_status mgseg_solve_batch(mgseg_batch *b, double tol, int max_cycles, int *cycles_out, double *rel_out)
+{
+    if (!b || !(tol > 0.0) || max_cycles < 0) return MGSEG_E_ARG;
+    const int count = (int)b->ctx.size();
+    std::vector<double> rel(count, 0.0);
+    for (int i = 0; i < count; i++) rel[i] = b->ctx[i]->rel;
+    batch_enter(b);
+    mgseg_status st = MGSEG_OK;
+    for (;;) {
+        std::vector<int> act;
+        for (int i : b->order)
+            if (rel[i] > tol && b->ctx[i]->cycles < max_cycles) act.push_back(i);
+        if (act.empty()) break;
+        st = batch_round(b, act, rel);
+        if (st != MGSEG_OK && st != MGSEG_E_NONFINITE) break;
+        if (st == MGSEG_E_NONFINITE) break;
+    }
+    batch_leave(b);
+    bool all_ok = true;
+    for (int i = 0; i < count; i++) {
+        if (cycles_out) cycles_out[i] = b->ctx[i]->cycles;
+        if (rel_out) rel_out[i] = b->ctx[i]->rel;
+        if (!(b->ctx[i]->rel <= tol)) all_ok = false;
+    }
+    if (st != MGSEG_OK) return st;
+    return all_ok ? MGSEG_OK : MGSEG_E_NOT_CONVERGED;
+}
+
+mgseg_status mgseg_batch_ctx(mgseg_batch *b, int index, mgseg_ctx **view)
+{
+    if (!b || !view || index < 0 || index >= (int)b->ctx.size()) return MGSEG_E_ARG;
+    *view = b->ctx[index];
     return MGSEG_OK;
 }
 

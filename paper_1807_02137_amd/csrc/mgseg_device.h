@@ -96,6 +96,7 @@ struct LineArgs {
     const float *psi, *w, *fit, *F;     // F may be null (zero)
     const uint8_t *lab;
     const float *lo, *hi;
+    const int *skip;                    // non-null and set: the launch does nothing
     float *tout;                        // non-null: new values written transposed,
     int tpitch;                         //   cell q of line r at tout[q * tpitch + r]
     float *scr;                         // unit-row scratch of lines longer than RB_LDS_MAX
@@ -651,6 +652,7 @@ __host__ __device__ inline size_t sweep_lds_bytes(int ml)
 template <int NT, int K, bool REV>
 __global__ void __launch_bounds__(NT) k_sweep(LineArgs A)
 {
+    if (A.skip && *A.skip) return;
     extern __shared__ uint64_t smem64[];
     __shared__ Ramp wtot[2 * (NT / 64 > 0 ? NT / 64 : 1)];
     uint64_t *msk = smem64;

@@ -359,6 +359,7 @@ __global__ void k_sums(const T *phi, int pp, const float *z, int pz, int n, int 
 // finalize: mode 0 -> area term 2 nu (h^2 sum H - A1) into out[0];
 //           mode 1 -> c1, c2 (eq. c1c2) into out[0], out[1];
 //           mode 2 -> sqrt(sum of partial r^2) into out[0] (partials of stride 1)
+//           mode 3 -> sqrt(sum d^2 / sum p^2) into out[0] (pairs of partials: eta)
 #define FIN_NT 256
 __global__ void __launch_bounds__(FIN_NT) k_finalize(const double *partial, int nb, int mode, double N, double h2,
                                                      double A1, double nu, double *out)
@@ -369,6 +370,8 @@ __global__ void __launch_bounds__(FIN_NT) k_finalize(const double *partial, int 
     double a0 = 0.0, a1 = 0.0, a2 = 0.0;
     if (mode == 2) {
         for (int b = t; b < nb; b += FIN_NT) a0 += partial[b];
+    } else if (mode == 3) {
+        for (int b = t; b < nb; b += FIN_NT) { a0 += partial[2 * b]; a1 += partial[2 * b + 1]; }
     } else {
         for (int b = t; b < nb; b += FIN_NT) {
             a0 += partial[3 * b]; a1 += partial[3 * b + 1]; a2 += partial[3 * b + 2];
@@ -384,6 +387,8 @@ __global__ void __launch_bounds__(FIN_NT) k_finalize(const double *partial, int 
     const double sH = r0[0], sHz = r1[0], sz = r2[0];
     if (mode == 2) {
         out[0] = sqrt(sH);
+    } else if (mode == 3) {
+        out[0] = sHz > 0.0 ? sqrt(sH / sHz) : 0.0;
     } else if (mode == 0) {
         out[0] = 2.0 * nu * (h2 * sH - A1);
     } else {
@@ -804,9 +809,11 @@ __host__ __device__ inline size_t coarse_lds_bytes(int n, int m)
 }
 
 // largest change of the state over one outer iteration and since the
-// coarsest solve began (multi-kernel coarsest path): out[0], out[1]
+// coarsest solve began (multi-kernel coarsest path); once the change is at
+// most rtol times the total change, *stop is set and the remaining sweeps of
+// the coarsest solve return at once (no host synchronisation)
 __global__ void __launch_bounds__(256) k_coarse_delta(const float *x, const float *prev, const float *entry, int p,
-                                                      int n, int m, double *out)
+                                                      int n, int m, double rtol, int *stop)
 {
     __shared__ float r0[256], r1[256];
     const int t = threadIdx.x;
@@ -822,7 +829,12 @@ __global__ void __launch_bounds__(256) k_coarse_delta(const float *x, const floa
         if (t < s) { r0[t] = fmaxf(r0[t], r0[t + s]); r1[t] = fmaxf(r1[t], r1[t + s]); }
         __syncthreads();
     }
-    if (t == 0) { out[0] = r0[0]; out[1] = r1[0]; }
+    if (t == 0 && (double)r0[0] <= rtol * (double)r1[0]) stop[0] = 1;
+}
+
+__global__ void k_set_int(int *p, int v)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) p[0] = v;
 }
 
 template <int NT>
@@ -870,7 +882,7 @@ __global__ void __launch_bounds__(NT) k_coarse_smooth(CoarseArgs G)
     RBc.p = rb; RBc.fs = n;
     LineArgs R, T;
     R.psi = psi; R.w = w; R.fit = dev ? nullptr : fit; R.F = F; R.lab = lab; R.lo = lo; R.hi = hi;
-    R.scr = nullptr; R.tout = nullptr; R.tpitch = 0; R.area = G.area; R.pitch = m; R.lpitch = m;
+    R.scr = nullptr; R.skip = nullptr; R.tout = nullptr; R.tpitch = 0; R.area = G.area; R.pitch = m; R.lpitch = m;
     R.nl = n; R.ml = m; R.kap = G.kap; R.e2 = G.e2; R.M = G.M; R.eps = (float)G.eps; R.scaled = G.scaled;
     T = R;
     T.psi = psi_cm; T.w = w_cm; T.fit = dev ? nullptr : fit_cm; T.F = F_cm; T.lab = lab_cm; T.lo = lo_cm;

@@ -109,10 +109,19 @@ def lib():
         L.mgseg_debug_op.argtypes = [vp, C.c_int, C.c_int, C.c_int]
         L.mgseg_profile.argtypes = [vp, C.c_int, C.c_int]
         L.mgseg_profile_read.argtypes = [vp, C.c_int, dp, ip, dp]
+        L.mgseg_setup_batch.argtypes = [C.c_int, C.POINTER(vp), ip, ip, ip, C.POINTER(C.POINTER(C.c_float)), ip,
+                                        C.POINTER(_Params), vp, C.POINTER(vp)]
+        L.mgseg_batch_tune.argtypes = [vp, C.c_int, ip, dp]
+        L.mgseg_batch_set_streams.argtypes = [vp, C.c_int]
+        L.mgseg_solve_batch.argtypes = [vp, C.c_double, C.c_int, ip, dp]
+        L.mgseg_batch_ctx.argtypes = [vp, C.c_int, C.POINTER(vp)]
+        L.mgseg_destroy_batch.argtypes = [vp]
+        L.mgseg_destroy_batch.restype = None
         for name in ("mgseg_setup", "mgseg_set_phi0", "mgseg_vcycle", "mgseg_solve", "mgseg_get_phi",
                      "mgseg_get_mask", "mgseg_get_stats", "mgseg_level_shape", "mgseg_debug_get",
                      "mgseg_debug_set", "mgseg_debug_scalars", "mgseg_debug_set_c", "mgseg_debug_op",
-                     "mgseg_profile", "mgseg_profile_read"):
+                     "mgseg_profile", "mgseg_profile_read", "mgseg_setup_batch", "mgseg_batch_tune",
+                     "mgseg_batch_set_streams", "mgseg_solve_batch", "mgseg_batch_ctx"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -233,3 +242,72 @@ class Solver:
 
     def op(self, name, level=0, arg=0):
         _check(self.L.mgseg_debug_op(self.ctx, level, OP[name], arg), f"op {name}")
+
+
+class _View(Solver):
+    """One image of a batch (the batch owns the context)."""
+
+    def __init__(self, L, ctx, n, m, params):
+        self.L, self.ctx, self.n, self.m, self.params = L, ctx, n, m, params
+
+    def close(self):
+        self.ctx = None
+
+
+class Batch:
+    """Images of uneven size solved together (mgseg_setup_batch): each image by
+    its own context, V-cycles issued on internal streams, one wait per round."""
+
+    def __init__(self, images, markers, params: Params | None = None, stream=None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("mgseg needs a GPU (HIP device)")
+        self.L = lib()
+        self.params = params or Params()
+        self._imgs = [torch.as_tensor(im, dtype=torch.float32).to("cuda").contiguous() for im in images]
+        self._mk = [np.ascontiguousarray(np.asarray(mk, np.float32).reshape(-1, 2)) for mk in markers]
+        cnt = len(self._imgs)
+        vp = C.c_void_p
+        imgs = (vp * cnt)(*[im.data_ptr() for im in self._imgs])
+        ns = (C.c_int * cnt)(*[im.shape[0] for im in self._imgs])
+        ms = (C.c_int * cnt)(*[im.shape[1] for im in self._imgs])
+        mks = (C.POINTER(C.c_float) * cnt)(*[mk.ctypes.data_as(C.POINTER(C.c_float)) for mk in self._mk])
+        ks = (C.c_int * cnt)(*[len(mk) for mk in self._mk])
+        self._p = self.params.to_c()
+        self.stream = stream or torch.cuda.current_stream()
+        b = C.c_void_p()
+        _check(self.L.mgseg_setup_batch(cnt, imgs, ns, ms, ms, mks, ks, C.byref(self._p), _stream_ptr(self.stream),
+                                        C.byref(b)), "mgseg_setup_batch")
+        self.b, self.count = b, cnt
+
+    def tune(self, trial_rounds=1):
+        s, ms = C.c_int(), C.c_double()
+        _check(self.L.mgseg_batch_tune(self.b, trial_rounds, C.byref(s), C.byref(ms)), "mgseg_batch_tune")
+        return s.value, ms.value
+
+    def set_streams(self, n):
+        _check(self.L.mgseg_batch_set_streams(self.b, n), "mgseg_batch_set_streams")
+
+    def solve(self, tol=1e-6, max_cycles=50):
+        cyc = (C.c_int * self.count)()
+        rel = (C.c_double * self.count)()
+        code = self.L.mgseg_solve_batch(self.b, tol, max_cycles, cyc, rel)
+        if code not in (0, 6):
+            raise MgsegError(code, "mgseg_solve_batch")
+        return list(cyc), list(rel), code == 0
+
+    def image(self, i) -> Solver:
+        c = C.c_void_p()
+        _check(self.L.mgseg_batch_ctx(self.b, i, C.byref(c)), "mgseg_batch_ctx")
+        n, m = self._imgs[i].shape
+        return _View(self.L, c, n, m, self.params)
+
+    def close(self):
+        if getattr(self, "b", None):
+            self.L.mgseg_destroy_batch(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

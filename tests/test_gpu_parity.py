@@ -248,3 +248,64 @@ def test_graph_replays_match_eager_launches():
         say(f"cycle {k}: rel {ra:.3e} / {rb:.3e}, identical {np.array_equal(pa, pb)}")
         assert ra == rb and np.array_equal(pa, pb)
     a.close(); b.close()
+
+
+def _batch_inputs():
+    insts = [synth.tiny_instance(7, 40, 72), synth.config1(1001), synth.tiny_instance(9, 96, 160),
+             synth.tiny_instance(11, 252, 252), synth.tiny_instance(13, 130, 72)]
+    return insts
+
+
+def test_batch_matches_single_solves():
+    """Images of uneven size solved as one batch on several streams give the
+    same cycles and bit-identical phi as solving each alone; two of them end
+    on coarse grids larger than the single-workgroup kernel takes (63x63,
+    65x36), which exercises the multi-kernel coarsest solve and its device-side
+    stopping test."""
+    say("case batch vs single solves")
+    insts = _batch_inputs()
+    p = mgseg.Params(levels=0)
+    b = mgseg.Batch([i.image for i in insts], [i.markers for i in insts], p)
+    b.set_streams(3)
+    cyc, rel, ok = b.solve(1e-6, 40)
+    say("batch cycles", cyc, "rel", ["%.1e" % r for r in rel])
+    assert ok
+    for k, inst in enumerate(insts):
+        s = mgseg.Solver(inst.image, inst.markers, p)
+        c1, r1, ok1 = s.solve(1e-6, 40)
+        pa = b.image(k).get("phi64")
+        pb = s.get("phi64")
+        say(f"image {k} {inst.image.shape}: batch {cyc[k]} cycles, single {c1}; identical {np.array_equal(pa, pb)}")
+        assert ok1 and c1 == cyc[k] and np.array_equal(pa, pb)
+        s.close()
+    b.close()
+
+
+def test_batch_large_coarsest_matches_oracle():
+    """252x252 on 3 grids ends on a 63x63 coarsest grid (multi-kernel coarsest
+    solve with the device-side stop): same bar as the other end-to-end tests."""
+    say("case large coarsest grid vs oracle")
+    inst = synth.tiny_instance(11, 252, 252)
+    s = mgseg.Solver(inst.image, inst.markers, mgseg.Params(levels=3))
+    o = Oracle(inst.image, inst.markers, OracleParams(levels=3))
+    cg, rg, okg = s.solve(1e-6, 40)
+    k, hist = o.solve(1e-6, 40)
+    pg, po = s.phi().cpu().numpy(), o.get("phi")
+    agree = (pg > 0) == (po > 0)
+    flips = int((~agree).sum())
+    dmax = float(np.abs(pg - po)[agree].max())
+    say(f"gpu {cg} cycles rel {rg:.2e}; oracle {k} cycles; flips {flips} max|dphi| {dmax:.3e}")
+    assert okg and k > 0 and flips <= 1 and dmax <= 1e-4
+    s.close()
+
+
+def test_batch_tuner_picks_a_stream_count():
+    say("case batch tuner")
+    insts = _batch_inputs()
+    b = mgseg.Batch([i.image for i in insts], [i.markers for i in insts], mgseg.Params(levels=0))
+    S, ms = b.tune(1)
+    say(f"tuner: {S} streams, {ms:.2f} ms per round")
+    assert S in (1, 2, 4) and ms > 0
+    cyc, rel, ok = b.solve(1e-6, 40)
+    assert ok
+    b.close()
