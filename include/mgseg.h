@@ -219,6 +219,56 @@ mgseg_status mgseg_batch_ctx(mgseg_batch *b, int index, mgseg_ctx **view);
 /* Releases every context and stream of the batch (NULL is a no-op). */
 void mgseg_destroy_batch(mgseg_batch *b);
 
+/* ------------------------------------------------------------------------
+ * Learned warm start.  A small convolutional encoder-decoder maps the
+ * network input (image z, marker distance map d of Sec. 2.2, marker mask) to
+ * an initial level set phi0 = M tanh(o); the V-cycle then finishes the solve
+ * from it (mgseg_set_phi0), so the network only changes where the solve
+ * starts, never its fixed point.  depth levels with widths base * 2^l; every
+ * level's block is two 3x3 convolutions (zero padding) each followed by ReLU;
+ * 2x2 average pooling down, nearest 2x up-sampling with the encoder's output
+ * of the same level concatenated after it; 1x1 head.
+ * Convolutions run as bf16 matrix-core products with FP32 accumulation;
+ * FP32 master weights with Adam.  All tensors are device NCHW FP32 at the
+ * boundary.
+ */
+typedef struct mgseg_net mgseg_net;
+
+/* New network with He-normal weights from `seed` (deterministic).
+ * Errors: MGSEG_E_ARG (base_channels not in 1..256, depth not in 2..6). */
+mgseg_status mgseg_net_create(int base_channels, int depth, uint64_t seed, mgseg_net **out);
+
+/* phi0_dev[B][H][W] = M tanh(net(in_dev[B][3][H][W])); keeps the activations
+ * for mgseg_net_backward.  H, W multiples of 2^(depth-1) (else MGSEG_E_SHAPE). */
+mgseg_status mgseg_net_forward(mgseg_net *n, const float *in_dev, int B, int H, int W, double M, float *phi0_dev,
+                               void *stream);
+
+/* Loss mean((tanh(o) - clip(target / M, -1, 1))^2) of the last forward and the
+ * gradients of every parameter; target_dev[B][H][W] as in that forward;
+ * *loss_host (may be null) after a stream sync.  MGSEG_E_STATE without a
+ * preceding forward. */
+mgseg_status mgseg_net_backward(mgseg_net *n, const float *target_dev, double M, float *loss_host, void *stream);
+
+/* One Adam step (bias-corrected moments) with the gradients of the last
+ * backward; 0 <= b1, b2 < 1, eps > 0, lr >= 0 (else MGSEG_E_ARG). */
+mgseg_status mgseg_net_adam_step(mgseg_net *n, double lr, double b1, double b2, double eps, void *stream);
+
+/* Parameters in a fixed order: the encoder's convolutions (two per level,
+ * level 0 first), then the decoder's (two per level 0..depth-2), each weights
+ * [OC][IC][3][3] then biases [OC]; head weights [base], head bias.  Count,
+ * copy out (values and / or gradients; host buffers of `count` floats), copy
+ * in (which also clears the Adam moments and step count). */
+mgseg_status mgseg_net_param_count(mgseg_net *n, long long *count);
+mgseg_status mgseg_net_get_params(mgseg_net *n, float *host, float *grad_host);
+mgseg_status mgseg_net_set_params(mgseg_net *n, const float *host);
+void mgseg_net_destroy(mgseg_net *n);
+
+/* The network input of a context: out_dev[3][n][m] = (z, d, marker mask). */
+mgseg_status mgseg_ctx_features(mgseg_ctx *c, float *out_dev);
+
+/* Forward pass on the context's features, then mgseg_set_phi0 with the result. */
+mgseg_status mgseg_predict_phi0(mgseg_ctx *c, mgseg_net *n);
+
 #ifdef __cplusplus
 }
 #endif

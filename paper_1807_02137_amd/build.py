@@ -6,8 +6,8 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = os.path.join(HERE, "csrc", "mgseg.hip")
-DEPS = [SRC, os.path.join(HERE, "csrc", "mgseg_device.h"), os.path.join(HERE, "csrc", "mgseg_kernels.h"),
+SRCS = [os.path.join(HERE, "csrc", "mgseg.hip"), os.path.join(HERE, "csrc", "mgseg_net.hip")]
+DEPS = [*SRCS, os.path.join(HERE, "csrc", "mgseg_device.h"), os.path.join(HERE, "csrc", "mgseg_kernels.h"),
         os.path.join(ROOT, "include", "mgseg.h")]
 LIB_DIR = os.path.join(HERE, "lib")
 LIB = os.path.join(LIB_DIR, "libmgseg.so")
@@ -23,7 +23,7 @@ def build(verbose: bool = False) -> str:
     """Compile csrc/mgseg.hip into lib/libmgseg.so (always recompiles)."""
     os.makedirs(LIB_DIR, exist_ok=True)
     tmp = LIB + f".tmp{os.getpid()}"
-    cmd = ["hipcc", *HIPCC_FLAGS, SRC, "-o", tmp]
+    cmd = ["hipcc", *HIPCC_FLAGS, *SRCS, "-o", tmp]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError("hipcc failed:\n" + res.stdout + res.stderr)

@@ -1211,4 +1211,35 @@ mgseg_status mgseg_batch_ctx(mgseg_batch *b, int index, mgseg_ctx **view)
     return MGSEG_OK;
 }
 
+
+// ---- learned warm start on a context
+mgseg_status mgseg_ctx_features(mgseg_ctx *c, float *out_dev)
+{
+    if (!c || !out_dev) return MGSEG_E_ARG;
+    Level &L = c->lev[0];
+    hipLaunchKernelGGL(k_features, grid2(c->n, c->m), dim3(256), 0, c->s, L.z, L.d, L.prm, c->n, c->m, c->mk_d, c->k,
+                       out_dev);
+    chk(c);
+    return sync_status(c);
+}
+
+mgseg_status mgseg_predict_phi0(mgseg_ctx *c, mgseg_net *net)
+{
+    if (!c || !net) return MGSEG_E_ARG;
+    const size_t N = (size_t)c->n * c->m;
+    float *feat = nullptr, *phi = nullptr;
+    if (hipMalloc(&feat, sizeof(float) * 3 * N) != hipSuccess || hipMalloc(&phi, sizeof(float) * N) != hipSuccess) {
+        (void)hipGetLastError();
+        if (feat) (void)hipFree(feat);
+        return MGSEG_E_NOMEM;
+    }
+    mgseg_status st = mgseg_ctx_features(c, feat);
+    if (st == MGSEG_OK) st = mgseg_net_forward(net, feat, 1, c->n, c->m, c->p.M, phi, c->s);
+    if (st == MGSEG_OK) st = mgseg_set_phi0(c, phi, c->m);
+    (void)hipStreamSynchronize(c->s);
+    (void)hipFree(feat);
+    (void)hipFree(phi);
+    return st;
+}
+
 }  // extern "C"

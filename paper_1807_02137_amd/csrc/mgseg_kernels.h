@@ -969,3 +969,16 @@ __global__ void __launch_bounds__(NT) k_coarse_smooth(CoarseArgs G)
     for (int t = tid; t < N; t += NT) G.P0[(t / m) * G.prm + t % m] = P0[t];
 }
 
+// network input of the finest grid: z, d, marker mask (1 at a marker's cell)
+__global__ void k_features(const float *z, const float *d, int p, int n, int m, const double *mk, int k, float *out)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x, i = blockIdx.y;
+    if (j >= m || i >= n) return;
+    const long long q = (long long)i * m + j, HW = (long long)n * m;
+    out[q] = z[(long long)i * p + j];
+    out[HW + q] = d[(long long)i * p + j];
+    float mk1 = 0.0f;
+    for (int t = 0; t < k; t++)
+        if ((int)floor(mk[2 * t]) == i && (int)floor(mk[2 * t + 1]) == j) mk1 = 1.0f;
+    out[2 * HW + q] = mk1;
+}

@@ -117,11 +117,24 @@ def lib():
         L.mgseg_batch_ctx.argtypes = [vp, C.c_int, C.POINTER(vp)]
         L.mgseg_destroy_batch.argtypes = [vp]
         L.mgseg_destroy_batch.restype = None
+        L.mgseg_net_create.argtypes = [C.c_int, C.c_int, C.c_uint64, C.POINTER(vp)]
+        L.mgseg_net_forward.argtypes = [vp, vp, C.c_int, C.c_int, C.c_int, C.c_double, vp, vp]
+        L.mgseg_net_backward.argtypes = [vp, vp, C.c_double, C.POINTER(C.c_float), vp]
+        L.mgseg_net_adam_step.argtypes = [vp, C.c_double, C.c_double, C.c_double, C.c_double, vp]
+        L.mgseg_net_param_count.argtypes = [vp, C.POINTER(C.c_longlong)]
+        L.mgseg_net_get_params.argtypes = [vp, vp, vp]
+        L.mgseg_net_set_params.argtypes = [vp, vp]
+        L.mgseg_net_destroy.argtypes = [vp]
+        L.mgseg_net_destroy.restype = None
+        L.mgseg_ctx_features.argtypes = [vp, vp]
+        L.mgseg_predict_phi0.argtypes = [vp, vp]
         for name in ("mgseg_setup", "mgseg_set_phi0", "mgseg_vcycle", "mgseg_solve", "mgseg_get_phi",
                      "mgseg_get_mask", "mgseg_get_stats", "mgseg_level_shape", "mgseg_debug_get",
                      "mgseg_debug_set", "mgseg_debug_scalars", "mgseg_debug_set_c", "mgseg_debug_op",
                      "mgseg_profile", "mgseg_profile_read", "mgseg_setup_batch", "mgseg_batch_tune",
-                     "mgseg_batch_set_streams", "mgseg_solve_batch", "mgseg_batch_ctx"):
+                     "mgseg_batch_set_streams", "mgseg_solve_batch", "mgseg_batch_ctx", "mgseg_net_create",
+                     "mgseg_net_forward", "mgseg_net_backward", "mgseg_net_adam_step", "mgseg_net_param_count",
+                     "mgseg_net_get_params", "mgseg_net_set_params", "mgseg_ctx_features", "mgseg_predict_phi0"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -201,6 +214,16 @@ class Solver:
         s = _Stats()
         _check(self.L.mgseg_get_stats(self.ctx, C.byref(s)), "mgseg_get_stats")
         return {f[0]: getattr(s, f[0]) for f in _Stats._fields_}
+
+    def features(self) -> torch.Tensor:
+        """Network input of this image: [3, n, m] = (z, d, marker mask)."""
+        out = torch.empty((3, self.n, self.m), dtype=torch.float32, device="cuda")
+        _check(self.L.mgseg_ctx_features(self.ctx, C.c_void_p(out.data_ptr())), "mgseg_ctx_features")
+        return out
+
+    def predict_phi0(self, net: "Net"):
+        """Start the solve from the network's phi0 for this image."""
+        _check(self.L.mgseg_predict_phi0(self.ctx, net.h), "mgseg_predict_phi0")
 
     # ---- single steps (tests, profiling)
     def shape(self, level=0):
@@ -305,6 +328,68 @@ class Batch:
         if getattr(self, "b", None):
             self.L.mgseg_destroy_batch(self.b)
             self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Net:
+    """Warm-start network (mgseg_net_*): forward, backward, Adam, all on the GPU."""
+
+    def __init__(self, base=16, depth=4, seed=0):
+        if not torch.cuda.is_available():
+            raise RuntimeError("mgseg needs a GPU (HIP device)")
+        self.L = lib()
+        self.base, self.depth = base, depth
+        h = C.c_void_p()
+        _check(self.L.mgseg_net_create(base, depth, seed, C.byref(h)), "mgseg_net_create")
+        self.h = h
+        cnt = C.c_longlong()
+        _check(self.L.mgseg_net_param_count(self.h, C.byref(cnt)), "mgseg_net_param_count")
+        self.count = cnt.value
+
+    def forward(self, x: torch.Tensor, M: float, stream=None) -> torch.Tensor:
+        """x [B, 3, H, W] FP32 on the device -> phi0 [B, H, W]."""
+        x = x.to(device="cuda", dtype=torch.float32).contiguous()
+        B, ch, H, W = x.shape
+        if ch != 3:
+            raise ValueError("the network takes 3 input channels")
+        out = torch.empty((B, H, W), dtype=torch.float32, device="cuda")
+        self._keep = x
+        _check(self.L.mgseg_net_forward(self.h, C.c_void_p(x.data_ptr()), B, H, W, M, C.c_void_p(out.data_ptr()),
+                                        _stream_ptr(stream)), "mgseg_net_forward")
+        return out
+
+    def backward(self, target: torch.Tensor, M: float, stream=None) -> float:
+        t = target.to(device="cuda", dtype=torch.float32).contiguous()
+        loss = C.c_float()
+        _check(self.L.mgseg_net_backward(self.h, C.c_void_p(t.data_ptr()), M, C.byref(loss), _stream_ptr(stream)),
+               "mgseg_net_backward")
+        return loss.value
+
+    def adam_step(self, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8, stream=None):
+        _check(self.L.mgseg_net_adam_step(self.h, lr, b1, b2, eps, _stream_ptr(stream)), "mgseg_net_adam_step")
+
+    def params(self):
+        """(values, gradients) as FP32 host arrays in the library's order."""
+        p, g = np.zeros(self.count, np.float32), np.zeros(self.count, np.float32)
+        _check(self.L.mgseg_net_get_params(self.h, p.ctypes.data_as(C.c_void_p), g.ctypes.data_as(C.c_void_p)),
+               "mgseg_net_get_params")
+        return p, g
+
+    def set_params(self, values):
+        v = np.ascontiguousarray(values, np.float32)
+        if v.size != self.count:
+            raise ValueError(f"expected {self.count} parameters, got {v.size}")
+        _check(self.L.mgseg_net_set_params(self.h, v.ctypes.data_as(C.c_void_p)), "mgseg_net_set_params")
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.mgseg_net_destroy(self.h)
+            self.h = None
 
     def __del__(self):
         try:

@@ -1,0 +1,204 @@
+"""GPU parity of the warm-start network against its FP64 reference.
+
+The library's network (bf16 matrix-core convolutions, FP32 accumulation and
+master weights) is driven through the C ABI; the FP64 NumPy reference
+(oracle/cnn.py, pinned by finite differences) evaluates the same parameters
+on the same seeded input.
+
+Tolerances.  The GPU stores the input, the convolution weights, every
+activation and every activation gradient in bf16 (8 significant bits, unit
+roundoff u = 2^-9) and accumulates in FP32.
+
+Forward against the exact FP64 network: a depth-3 network chains about 11
+such roundings between input and output, so a relative error of about
+sqrt(11) * 2 u ~ 1.3e-2 (RMS) is expected; the bar is 3e-2.
+
+Gradients: the weight gradients are sums over all pixels whose terms cancel
+strongly, which multiplies the storage error; against the exact network a
+tensor can be off by tens of percent (measured on the CPU with the
+bf16-storage reference: up to 0.4).  So the gradients are compared with the
+reference that rounds at the same points (store=bf16): the two then differ
+only in the order and precision of accumulation (FP32 against FP64) and in
+the rare bf16 rounding that this flips (probability ~ 2^-24 / 2^-9 per
+stored value), and the bar is 1e-2 per tensor, with 0.98 as the cosine
+against the exact gradient (one wrong index, tap or channel gives relative
+errors of order 1).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from oracle import Oracle, OracleParams, cnn  # noqa: E402
+from paper_1807_02137_amd import mgseg, synth  # noqa: E402
+
+M = 4.0
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def features(rng, B, H, W):
+    """Network-input-like values: z in [0, 1], d in [0, 1], a sparse 0/1 mask."""
+    x = np.empty((B, 3, H, W))
+    x[:, 0] = rng.uniform(0, 1, (B, H, W))
+    x[:, 1] = rng.uniform(0, 1, (B, H, W))
+    x[:, 2] = (rng.uniform(0, 1, (B, H, W)) < 0.05).astype(float)
+    return x
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a - b)) / max(np.linalg.norm(np.ravel(b)), 1e-30))
+
+
+def groups(base, depth):
+    """(name, start, size) of every parameter tensor in the library's order."""
+    C, enc, dec = cnn.shapes(base, depth)
+    out, off = [], 0
+    for tag, lst in (("enc", enc), ("dec", dec)):
+        for i, (ic, oc) in enumerate(lst):
+            out.append((f"{tag}{i}.w", off, oc * ic * 9)); off += oc * ic * 9
+            out.append((f"{tag}{i}.b", off, oc)); off += oc
+    out.append(("head.w", off, C[0])); off += C[0]
+    out.append(("head.b", off, 1)); off += 1
+    return out
+
+
+CASES = [  # (B, H, W, base, depth, seed): several MFMA tiles, ragged pixel and channel counts
+    (2, 20, 36, 4, 3, 1),
+    (1, 32, 32, 8, 4, 2),
+    (3, 8, 12, 6, 2, 3),
+]
+
+
+@pytest.mark.parametrize("B,H,W,base,depth,seed", CASES)
+def test_forward_matches_reference(B, H, W, base, depth, seed):
+    say(f"case net forward B{B} {H}x{W} base {base} depth {depth} seed {seed}")
+    net = mgseg.Net(base, depth, seed)
+    theta, _ = net.params()
+    assert theta.size == cnn.param_count(base, depth)
+    x = features(np.random.default_rng(seed), B, H, W)
+    phi = net.forward(torch.tensor(x, dtype=torch.float32), M).cpu().numpy()
+    ref, _ = cnn.forward(theta.astype(np.float64), x, base, depth, M)
+    refq, _ = cnn.forward(theta.astype(np.float64), x, base, depth, M, store=cnn.bf16)
+    say(f"  rel to exact {rel(phi, ref):.3e}, to bf16-storage ref {rel(phi, refq):.3e}")
+    assert rel(phi, ref) <= 3e-2
+    assert rel(phi, refq) <= 2e-3
+    net.close()
+
+
+@pytest.mark.parametrize("B,H,W,base,depth,seed", CASES)
+def test_gradients_match_reference(B, H, W, base, depth, seed):
+    say(f"case net gradients B{B} {H}x{W} base {base} depth {depth} seed {seed}")
+    net = mgseg.Net(base, depth, seed)
+    rng = np.random.default_rng(100 + seed)
+    theta, _ = net.params()
+    x = features(rng, B, H, W)
+    tgt = rng.uniform(-6, 6, (B, H, W))
+    net.forward(torch.tensor(x, dtype=torch.float32), M)
+    loss = net.backward(torch.tensor(tgt, dtype=torch.float32), M)
+    _, g = net.params()
+    th = theta.astype(np.float64)
+    loss_ref, g_ref = cnn.loss_and_grad(th, x, tgt, base, depth, M, store=cnn.bf16)
+    loss_ex, g_ex = cnn.loss_and_grad(th, x, tgt, base, depth, M)
+    say(f"  loss {loss:.6f} bf16-storage ref {loss_ref:.6f} exact {loss_ex:.6f}")
+    assert abs(loss - loss_ref) <= 1e-4 * loss_ref
+    assert abs(loss - loss_ex) <= 1e-2 * loss_ex
+    worst = (0.0, "")
+    for name, off, k in groups(base, depth):
+        r = rel(g[off:off + k], g_ref[off:off + k])
+        worst = max(worst, (r, name))
+    cos = float(g @ g_ex / (np.linalg.norm(g) * np.linalg.norm(g_ex)))
+    say(f"  worst tensor rel {worst[0]:.3e} ({worst[1]}); cosine to the exact gradient {cos:.6f}")
+    assert worst[0] <= 1e-2, worst
+    assert cos >= 0.98
+    net.close()
+
+
+def test_adam_steps_follow_the_update_rule():
+    say("case net adam")
+    base, depth = 4, 3
+    net = mgseg.Net(base, depth, 7)
+    rng = np.random.default_rng(7)
+    x = torch.tensor(features(rng, 2, 16, 16), dtype=torch.float32)
+    tgt = torch.tensor(rng.uniform(-6, 6, (2, 16, 16)), dtype=torch.float32)
+    m = np.zeros(net.count); v = np.zeros(net.count)
+    lr, b1, b2, eps = 1e-2, 0.9, 0.999, 1e-8
+    for t in (1, 2, 3):
+        net.forward(x, M)
+        net.backward(tgt, M)
+        p_before, g = net.params()
+        g = g.astype(np.float64)
+        m = b1 * m + (1 - b1) * g
+        v = b2 * v + (1 - b2) * g * g
+        p = p_before.astype(np.float64) - lr * (m / (1 - b1 ** t)) / (np.sqrt(v / (1 - b2 ** t)) + eps)
+        net.adam_step(lr, b1, b2, eps)
+        p_after, _ = net.params()
+        assert np.abs(p_after - p).max() <= 1e-6 * max(1.0, np.abs(p).max()), t
+    net.close()
+
+
+def test_training_lowers_the_loss_on_a_fixed_batch():
+    say("case net training")
+    net = mgseg.Net(8, 3, 11)
+    rng = np.random.default_rng(11)
+    xs = features(rng, 4, 32, 32)
+    # a target the network can represent: a smooth function of the input
+    tgt = M * np.tanh(3.0 * (xs[:, 0] - 0.5) - 2.0 * (xs[:, 1] - 0.5))
+    x, t = torch.tensor(xs, dtype=torch.float32), torch.tensor(tgt, dtype=torch.float32)
+    losses = []
+    for _ in range(60):
+        net.forward(x, M)
+        losses.append(net.backward(t, M))
+        net.adam_step(3e-3)
+    say(f"  loss {losses[0]:.4f} -> {losses[-1]:.4f}")
+    assert losses[-1] < 0.3 * losses[0]
+    net.close()
+
+
+def test_forward_rejects_bad_shapes():
+    net = mgseg.Net(4, 3, 0)
+    with pytest.raises(mgseg.MgsegError):
+        net.forward(torch.zeros((1, 3, 18, 16)), M)          # 18 not a multiple of 4
+    with pytest.raises(mgseg.MgsegError):
+        net.backward(torch.zeros((1, 18, 16)), M)            # no forward yet
+    net.close()
+
+
+def test_context_features_match_the_oracle():
+    say("case features seed 1000")
+    inst = synth.config1(1000)
+    s = mgseg.Solver(inst.image, inst.markers, mgseg.Params(levels=6))
+    o = Oracle(inst.image, inst.markers, OracleParams(levels=6))
+    f = s.features().cpu().numpy()
+    z, d = o.get("z"), o.get("d")
+    assert np.abs(f[0] - z).max() <= 1e-6 * max(1.0, np.abs(z).max())
+    assert np.abs(f[1] - d).max() <= 1e-6 * max(1.0, np.abs(d).max())
+    mk = np.zeros_like(z)
+    for r, c in np.floor(inst.markers).astype(int):
+        mk[r, c] = 1.0
+    assert np.array_equal(f[2], mk)
+    s.close()
+
+
+def test_predicted_phi0_is_the_forward_pass_of_the_features():
+    say("case predict_phi0 seed 1001")
+    inst = synth.config1(1001)
+    s = mgseg.Solver(inst.image, inst.markers, mgseg.Params(levels=6))
+    net = mgseg.Net(4, 3, 5)
+    phi = net.forward(s.features()[None], M)[0].double().cpu().numpy()
+    s.predict_phi0(net)
+    assert np.abs(s.get("phi64") - phi).max() <= 1e-6
+    cyc, relres, ok = s.solve(1e-6, 10)
+    say(f"  10 cycles from the network's phi0: rel {relres:.2e}")
+    assert relres < 1.0
+    net.close()
+    s.close()

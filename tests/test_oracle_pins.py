@@ -350,3 +350,67 @@ def test_selectivity_gate_config1():
         iou = (mask & inst.target).sum() / max((mask | inst.target).sum(), 1)
         good += iou >= 0.9
     assert good >= 9
+
+
+# ---------------------------------------------------------------- warm-start network reference
+def test_cnn_reference_gradient_matches_finite_differences():
+    """The hand-written backward pass of the FP64 network reference against
+    central finite differences of its own loss on a tiny instance."""
+    from oracle import cnn
+    rng = np.random.default_rng(11)
+    base, depth, M = 2, 3, 4.0
+    theta = rng.normal(scale=0.4, size=cnn.param_count(base, depth))
+    x = rng.normal(size=(2, 3, 8, 8))
+    tgt = rng.uniform(-5, 5, size=(2, 8, 8))
+    loss, g = cnn.loss_and_grad(theta, x, tgt, base, depth, M)
+    idx = rng.choice(theta.size, 40, replace=False)
+    h = 1e-6
+    for i in idx:
+        tp, tm = theta.copy(), theta.copy()
+        tp[i] += h; tm[i] -= h
+        fd = (cnn.loss_and_grad(tp, x, tgt, base, depth, M)[0] - cnn.loss_and_grad(tm, x, tgt, base, depth, M)[0]) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(fd)) + 1e-9, (i, fd, g[i])
+
+
+def test_cnn_reference_conv_is_a_correlation():
+    """conv3 with a kernel that is 1 at (ky, kx) and 0 elsewhere shifts the input
+    by (ky - 1, kx - 1) with zero fill."""
+    from oracle import cnn
+    x = np.arange(2 * 1 * 5 * 6, dtype=float).reshape(2, 1, 5, 6)
+    for ky in range(3):
+        for kx in range(3):
+            W = np.zeros((1, 1, 3, 3)); W[0, 0, ky, kx] = 1.0
+            y = cnn.conv3(x, W, np.zeros(1))
+            xp = np.pad(x, ((0, 0), (0, 0), (1, 1), (1, 1)))
+            assert np.array_equal(y, xp[:, :, ky:ky + 5, kx:kx + 6])
+
+
+def test_bf16_rounding_is_nearest_even():
+    """bfloat16 keeps 8 significant bits: 1 + 2^-8 is a tie between 1 and
+    1 + 2^-7 and goes to the even 1; 1 + 3 2^-8 goes up to 1 + 2^-6; signs,
+    zero and exactly representable values pass through."""
+    from oracle import cnn
+    x = np.array([1.0, 1 + 2.0 ** -8, 1 + 3 * 2.0 ** -8, 1 + 2.0 ** -7, -(1 + 3 * 2.0 ** -8), 0.0, 0.15625, 3.0e38])
+    # 3e38 = 1.7632 2^127; the nearest 8-bit significand is 226 / 128
+    want = np.array([1.0, 1.0, 1 + 2.0 ** -6, 1 + 2.0 ** -7, -(1 + 2.0 ** -6), 0.0, 0.15625, 226 * 2.0 ** 120])
+    assert np.array_equal(cnn.bf16(x), want)
+
+
+def test_cnn_reference_storage_rounding_hook():
+    """With the identity as the storage rounding the reference is the exact
+    network; with bf16 it differs from it by no more than bfloat16 storage
+    explains (a relative error of a few 2^-9 on the output)."""
+    from oracle import cnn
+    rng = np.random.default_rng(3)
+    base, depth, M = 3, 3, 4.0
+    theta = rng.normal(scale=0.3, size=cnn.param_count(base, depth))
+    x = rng.uniform(0, 1, (1, 3, 8, 8))
+    tgt = rng.uniform(-5, 5, (1, 8, 8))
+    a, _ = cnn.forward(theta, x, base, depth, M)
+    b, _ = cnn.forward(theta, x, base, depth, M, store=lambda v: v)
+    assert np.array_equal(a, b)
+    la, ga = cnn.loss_and_grad(theta, x, tgt, base, depth, M)
+    lb, gb = cnn.loss_and_grad(theta, x, tgt, base, depth, M, store=lambda v: v)
+    assert la == lb and np.array_equal(ga, gb)
+    c, _ = cnn.forward(theta, x, base, depth, M, store=cnn.bf16)
+    assert 0 < np.linalg.norm(c - a) <= 0.05 * np.linalg.norm(a)
