@@ -104,9 +104,12 @@ const char *mgseg_strerror(mgseg_status s);
  * the initial c1, c2 (eq. c1c2) and the initial residual norm.
  *   image_dev        : n x m float, values in [0, 1], row pitch `pitch`.
  *   markers_host     : k (row, col) pairs of floats in pixel coordinates;
- *                      the centre of cell (i, j) is (i + 0.5, j + 0.5).
+ *                      the centre of cell (i, j) is (i + 0.5, j + 0.5);
+ *                      every marker inside the image (0 <= row < n,
+ *                      0 <= col < m), 1 <= k <= 64.
  *   stream           : a hipStream_t (0 = default stream), passed as void*.
- * Errors: MGSEG_E_ARG (null pointers, k < 1, pitch < m, bad struct_size),
+ * Errors: MGSEG_E_ARG (null pointers, k out of range, a marker outside the
+ * image or not finite, pitch < m, bad struct_size),
  * MGSEG_E_SHAPE (n or m not divisible by 2^(levels-1)), MGSEG_E_NOMEM.
  */
 mgseg_status mgseg_setup(const float *image_dev, int n, int m, int pitch,
@@ -116,6 +119,11 @@ mgseg_status mgseg_setup(const float *image_dev, int n, int m, int pitch,
 /* Replaces the finest phi (warm start), clamped to [-M, M]; recomputes c1,
  * c2 and the reference residual norm; resets the cycle counter. */
 mgseg_status mgseg_set_phi0(mgseg_ctx *c, const float *phi_dev, int pitch);
+
+/* Restores the marker-based initial level set of mgseg_setup (a copy kept
+ * by the context), with c1, c2, the reference residual norm and the cycle
+ * counter as after setup: the start of a fresh solve of the same image. */
+mgseg_status mgseg_reset_phi0(mgseg_ctx *c);
 
 /* One FAS V-cycle (Algorithm-1 box, gamma = 1) followed by the c1, c2
  * refresh (Sec. 5); returns |r~|/|r~_0| after the refresh. */
@@ -243,11 +251,17 @@ mgseg_status mgseg_net_create(int base_channels, int depth, uint64_t seed, mgseg
 mgseg_status mgseg_net_forward(mgseg_net *n, const float *in_dev, int B, int H, int W, double M, float *phi0_dev,
                                void *stream);
 
-/* Loss mean((tanh(o) - clip(target / M, -1, 1))^2) of the last forward and the
- * gradients of every parameter; target_dev[B][H][W] as in that forward;
- * *loss_host (may be null) after a stream sync.  MGSEG_E_STATE without a
- * preceding forward. */
-mgseg_status mgseg_net_backward(mgseg_net *n, const float *target_dev, double M, float *loss_host, void *stream);
+/* Loss of the last forward against target_dev[B][H][W] and the gradients of
+ * every parameter.  With tg = clip(target / M, -1, 1) and the object weight
+ * w = pos_weight where tg > 0, 1 elsewhere (pos_weight > 0, else
+ * MGSEG_E_ARG; it balances the small object class), the loss is the
+ * weighted binary cross-entropy of (1 + tanh o) / 2 against (1 + tg) / 2,
+ * mean(w (softplus(2 o) - o (1 + tg))): minimal at tanh o = tg, with
+ * dloss/do = w (tanh o - tg) / N, which stays away from zero where the
+ * output saturates on the wrong side.  *loss_host (may be null) after a
+ * stream sync.  MGSEG_E_STATE without a preceding forward. */
+mgseg_status mgseg_net_backward(mgseg_net *n, const float *target_dev, double M, double pos_weight, float *loss_host,
+                                void *stream);
 
 /* One Adam step (bias-corrected moments) with the gradients of the last
  * backward; 0 <= b1, b2 < 1, eps > 0, lr >= 0 (else MGSEG_E_ARG). */
@@ -266,8 +280,16 @@ void mgseg_net_destroy(mgseg_net *n);
 /* The network input of a context: out_dev[3][n][m] = (z, d, marker mask). */
 mgseg_status mgseg_ctx_features(mgseg_ctx *c, float *out_dev);
 
-/* Forward pass on the context's features, then mgseg_set_phi0 with the result. */
-mgseg_status mgseg_predict_phi0(mgseg_ctx *c, mgseg_net *n);
+/* Forward pass on the context's features; the result becomes the initial
+ * level set (as mgseg_set_phi0) only if it is positive at the cell of every
+ * marker: a selective segmentation contains its markers, and a network
+ * output that leaves one out (the empty level set phi = -M is a stationary
+ * point of the box-constrained problem) would lead the solve to another
+ * fixed point.  Otherwise the marker-based phi0 is restored
+ * (mgseg_reset_phi0), so the solve always starts from a valid guess.
+ * *accepted_out (may be null): 1 if the network's phi0 was taken.  Allocates
+ * the features and the network output (4 n m floats) for the call. */
+mgseg_status mgseg_predict_phi0(mgseg_ctx *c, mgseg_net *n, int *accepted_out);
 
 #ifdef __cplusplus
 }

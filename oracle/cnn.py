@@ -15,7 +15,10 @@ convolutions with ReLU, cb(x) = relu(conv_b(relu(conv_a(x))))):
     e_0 = cb(x),        e_l = cb(avgpool2(e_{l-1}))        l = 1..D-1
     d_{D-1} = e_{D-1},  d_l = cb([up2(d_{l+1}) | e_l])     l = D-2..0
     o = w . d_0 + b,        phi0 = M tanh(o)
-    loss = mean((tanh(o) - clip(target / M, -1, 1))^2)
+    t = clip(target / M, -1, 1),  w = pos_weight where t > 0, 1 elsewhere,
+    loss = mean(w (softplus(2 o) - o (1 + t)))
+(the binary cross-entropy of (1 + tanh o) / 2 against (1 + t) / 2, minimal
+at tanh o = t).
 conv3 is a 3x3 convolution with zero padding: out[o, y, x] =
 sum_{c, ky, kx} W[o, c, ky, kx] in[c, y + ky - 1, x + kx - 1] + b[o].
 Parameters in the GPU library's order: the encoder's convolutions (a then b
@@ -164,17 +167,18 @@ def forward(theta, x, base, depth, M, store=None):
     return M * np.tanh(o), cache
 
 
-def loss_and_grad(theta, x, target, base, depth, M, store=None):
+def loss_and_grad(theta, x, target, base, depth, M, store=None, pos_weight=1.0):
     """Loss of the forward pass and its gradient with respect to theta (store
     as in forward: None exact, bf16 with the GPU's storage roundings)."""
     q = store or _ident
     P = unpack(np.asarray(theta, np.float64), base, depth)
     _, c = forward(theta, x, base, depth, M, store)
-    th = np.tanh(c["o"])
+    o = c["o"]
     t = np.clip(np.asarray(target, np.float64) / M, -1.0, 1.0)
-    N = th.size
-    loss = float(((th - t) ** 2).mean())
-    dO = 2.0 * (th - t) * (1.0 - th * th) / N
+    N = o.size
+    w = np.where(t > 0, pos_weight, 1.0)
+    loss = float((w * (np.logaddexp(0.0, 2.0 * o) - o * (1.0 + t))).mean())
+    dO = w * (np.tanh(o) - t) / N
     G = {"enc": [None] * (2 * depth), "dec": [None] * (2 * depth - 2)}
     G["hw"] = np.einsum("bhw,bchw->c", dO, c["dec"][0][1])
     G["hb"] = np.array([dO.sum()])

@@ -54,12 +54,13 @@ struct mgseg_ctx {
     int cycles = 0;
     Level lev[MAXLEV];
     double *phi64 = nullptr, *w64 = nullptr, *d64 = nullptr, *g64 = nullptr, *prev64 = nullptr;
+    double *phi0m = nullptr;        // the marker-based initial level set of setup
     double *dsc = nullptr;          // device scalars
     double *part = nullptr;         // reduction partials
     int part_n = 0;
     float *scr = nullptr;           // unit-row scratch of long lines
     float *co_prev = nullptr, *co_entry = nullptr;   // multi-kernel coarsest solve
-    int *flags = nullptr;           // device flags: [0] coarsest solve finished
+    int *flags = nullptr;           // device flags: [0] coarsest solve finished, [1] markers inside phi0
     double *hres = nullptr;         // pinned host copy of DS_RES, DS_ETA
     const int *sweep_skip = nullptr;
     double *hull_d = nullptr, *mk_d = nullptr;
@@ -684,6 +685,10 @@ mgseg_status mgseg_setup(const float *image_dev, int n, int m, int pitch, const 
         return MGSEG_E_ARG;
     for (int t = 0; t < 2 * k; t++)
         if (!std::isfinite(markers_host[t])) return MGSEG_E_ARG;
+    for (int t = 0; t < k; t++)
+        if (!(markers_host[2 * t] >= 0.0f && markers_host[2 * t] < (float)n && markers_host[2 * t + 1] >= 0.0f &&
+              markers_host[2 * t + 1] < (float)m))
+            return MGSEG_E_ARG;
     int Lv = p->levels;
     if (Lv == 0) {
         Lv = 1;
@@ -716,7 +721,7 @@ mgseg_status mgseg_setup(const float *image_dev, int n, int m, int pitch, const 
         L.lab = dalloc<uint8_t>(c, Nr); L.lab_cm = dalloc<uint8_t>(c, Nc);
     }
     c->phi64 = dalloc<double>(c, N); c->w64 = dalloc<double>(c, N); c->d64 = dalloc<double>(c, N);
-    c->g64 = dalloc<double>(c, N); c->prev64 = dalloc<double>(c, N);
+    c->g64 = dalloc<double>(c, N); c->prev64 = dalloc<double>(c, N); c->phi0m = dalloc<double>(c, N);
     c->dsc = dalloc<double>(c, DS_COUNT);
     c->part_n = 8 * RED_BLOCKS + (int)((N + 255) / 256) + n + 16;
     c->part = dalloc<double>(c, (size_t)c->part_n);
@@ -784,6 +789,7 @@ mgseg_status mgseg_setup(const float *image_dev, int n, int m, int pitch, const 
         Level &L = c->lev[l];
         transpose_f(c, L.w, L.prm, L.w_cm, L.pcm, L.n, L.m);
     }
+    (void)hipMemcpyAsync(c->phi0m, c->phi64, sizeof(double) * N, hipMemcpyDeviceToDevice, c->s);
     chk(c);
     refresh_and_residual(c);
     mgseg_status st = sync_status(c);
@@ -1223,7 +1229,21 @@ mgseg_status mgseg_ctx_features(mgseg_ctx *c, float *out_dev)
     return sync_status(c);
 }
 
-mgseg_status mgseg_predict_phi0(mgseg_ctx *c, mgseg_net *net)
+mgseg_status mgseg_reset_phi0(mgseg_ctx *c)
+{
+    if (!c) return MGSEG_E_ARG;
+    Level &L0 = c->lev[0];
+    (void)hipMemcpyAsync(c->phi64, c->phi0m, sizeof(double) * (size_t)c->n * c->m, hipMemcpyDeviceToDevice, c->s);
+    hipLaunchKernelGGL(k_copy64to32, grid2(c->n, c->m), dim3(256), 0, c->s, c->phi64, c->n, c->m, L0.P[0], L0.prm);
+    refresh_and_residual(c);
+    mgseg_status st = sync_status(c);
+    if (st != MGSEG_OK) return st;
+    c->res0 = read_scalar(c, DS_RES);
+    c->res = c->res0; c->rel = 1.0; c->cycles = 0;
+    return MGSEG_OK;
+}
+
+mgseg_status mgseg_predict_phi0(mgseg_ctx *c, mgseg_net *net, int *accepted_out)
 {
     if (!c || !net) return MGSEG_E_ARG;
     const size_t N = (size_t)c->n * c->m;
@@ -1235,7 +1255,15 @@ mgseg_status mgseg_predict_phi0(mgseg_ctx *c, mgseg_net *net)
     }
     mgseg_status st = mgseg_ctx_features(c, feat);
     if (st == MGSEG_OK) st = mgseg_net_forward(net, feat, 1, c->n, c->m, c->p.M, phi, c->s);
-    if (st == MGSEG_OK) st = mgseg_set_phi0(c, phi, c->m);
+    int inside = 0;
+    if (st == MGSEG_OK) {
+        hipLaunchKernelGGL(k_markers_inside, dim3(1), dim3(256), 0, c->s, phi, c->n, c->m, c->mk_d, c->k, c->flags + 1);
+        (void)hipMemcpyAsync(&inside, c->flags + 1, sizeof(int), hipMemcpyDeviceToHost, c->s);
+        chk(c);
+        st = sync_status(c);
+    }
+    if (st == MGSEG_OK) st = inside ? mgseg_set_phi0(c, phi, c->m) : mgseg_reset_phi0(c);
+    if (accepted_out) *accepted_out = st == MGSEG_OK ? inside : 0;
     (void)hipStreamSynchronize(c->s);
     (void)hipFree(feat);
     (void)hipFree(phi);

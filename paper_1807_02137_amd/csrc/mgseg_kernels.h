@@ -467,6 +467,13 @@ __global__ void k_copy32to64(const float *phi32, int p32, double *phi64, int n, 
     phi64[(long long)i * m + j] = (double)phi32[(long long)i * p32 + j];
 }
 
+__global__ void k_copy64to32(const double *phi64, int n, int m, float *phi32, int p32)
+{
+    int j = blockIdx.x * blockDim.x + threadIdx.x, i = blockIdx.y;
+    if (j >= m || i >= n) return;
+    phi32[(long long)i * p32 + j] = (float)phi64[(long long)i * m + j];
+}
+
 __global__ void k_set_phi0(const float *src, int ps, double M, double *phi64, float *phi32, int p32, int n, int m)
 {
     int j = blockIdx.x * blockDim.x + threadIdx.x, i = blockIdx.y;
@@ -981,4 +988,19 @@ __global__ void k_features(const float *z, const float *d, int p, int n, int m, 
     for (int t = 0; t < k; t++)
         if ((int)floor(mk[2 * t]) == i && (int)floor(mk[2 * t + 1]) == j) mk1 = 1.0f;
     out[2 * HW + q] = mk1;
+}
+
+// flag = 1 if phi (dense n x m) is positive at the cell of every marker (row, col), else 0.
+// One block of 256 threads.
+__global__ void k_markers_inside(const float *phi, int n, int m, const double *mk, int k, int *flag)
+{
+    __shared__ int bad;
+    if (threadIdx.x == 0) bad = 0;
+    __syncthreads();
+    for (int t = threadIdx.x; t < k; t += blockDim.x) {
+        const long long i = (long long)floor(mk[2 * t]), j = (long long)floor(mk[2 * t + 1]);
+        if (i < 0 || i >= n || j < 0 || j >= m || !(phi[i * m + j] > 0.0f)) atomicOr(&bad, 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) flag[0] = bad ? 0 : 1;
 }

@@ -259,8 +259,8 @@ __global__ void k_to_bf16(const float *x, uint16_t *y, long long n)
     if (t < n) y[t] = f2bf(x[t]);
 }
 
-// head: o = w . d0 + b, phi0 = M tanh(o) (FP32 from the FP32 copy of d0)
-__global__ void k_head(const float *d0, int C, int HW, int B, const float *w, const float *b, float M, float *th,
+// head: o = w . d0 + b, phi0 = M tanh(o) (FP32 from the FP32 copy of d0); keeps o for the loss
+__global__ void k_head(const float *d0, int C, int HW, int B, const float *w, const float *b, float M, float *ob,
                        float *phi)
 {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -269,17 +269,20 @@ __global__ void k_head(const float *d0, int C, int HW, int B, const float *w, co
     const float *x = d0 + (long long)bi * C * HW + p;
     float o = b[0];
     for (int c = 0; c < C; c++) o = fmaf(w[c], x[(long long)c * HW], o);
-    const float tt = tanhf(o);
-    th[t] = tt;
-    phi[t] = M * tt;
+    ob[t] = o;
+    phi[t] = M * tanhf(o);
 }
 
-// loss = mean (tanh(o) - target/M)^2 with target clipped to [-M, M];
-// dO = 2/N (tanh - t)(1 - tanh^2); head gradient partials per block;
-// gd0 = w dO (bf16, then relu-masked by the caller)
-__global__ void __launch_bounds__(256) k_head_bwd(const float *th, const float *target, float M, const float *d0,
-                                                  int C, int HW, int B, const float *w, uint16_t *gd0, float *part,
-                                                  int maxc)
+// Loss: binary cross-entropy of p = sigmoid(2 o) = (1 + tanh o) / 2 against the
+// soft target q = (1 + tg) / 2, tg = clip(target / M, -1, 1), weighted by
+// w = pw on the object (tg > 0) and 1 elsewhere, averaged over the N pixels:
+//   loss = mean w (softplus(2 o) - 2 o q),   dloss/do = w (tanh o - tg) / N,
+// whose minimum is at tanh o = tg and whose gradient does not vanish where the
+// output saturates on the wrong side.  Head gradient partials per block;
+// gd0 = w_head dO (bf16, then relu-masked by the caller).
+__global__ void __launch_bounds__(256) k_head_bwd(const float *ob, const float *target, float M, float pw,
+                                                  const float *d0, int C, int HW, int B, const float *w, uint16_t *gd0,
+                                                  float *part, int maxc)
 {
     __shared__ float red[256];
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -289,9 +292,11 @@ __global__ void __launch_bounds__(256) k_head_bwd(const float *th, const float *
     if (t < N) {
         bi = (int)(t / HW); p = (int)(t % HW);
         const float tg = fminf(fmaxf(target[t] / M, -1.0f), 1.0f);
-        const float e = th[t] - tg;
-        loss = e * e;
-        dO = 2.0f * e * (1.0f - th[t] * th[t]) / (float)N;
+        const float q = tg > 0.0f ? pw : 1.0f;
+        const float x = 2.0f * ob[t];
+        const float sp = fmaxf(x, 0.0f) + log1pf(expf(-fabsf(x)));
+        loss = q * (sp - x * 0.5f * (1.0f + tg));
+        dO = q * (tanhf(ob[t]) - tg) / (float)N;
         for (int c = 0; c < C; c++) gd0[(long long)bi * C * HW + (long long)c * HW + p] = f2bf(w[c] * dO);
     }
     // partials: [0] loss, [1] db, [2 + c] dw_c
@@ -365,7 +370,7 @@ struct mgseg_net {
     std::vector<uint16_t *> pool;            // pool[l] = avgpool(e_l), level l+1
     uint16_t *ebot = nullptr;                // e_{depth-1}
     std::vector<uint16_t *> dact;            // d_l (l < depth-1)
-    float *d0f = nullptr, *th = nullptr, *phi = nullptr;
+    float *d0f = nullptr, *ob = nullptr, *phi = nullptr;   // FP32 d_0, head output o, M tanh(o)
     // gradients
     std::vector<uint16_t *> gemid, gdmid, gcat, gpool, gdact;
     uint16_t *gebot = nullptr;
@@ -428,7 +433,7 @@ bool ensure_acts(mgseg_net *n, int B, int H, int W)
     n->ebot = nalloc<uint16_t>(v, (size_t)B * chan(n, D - 1) * hwb, fail);
     n->gebot = nalloc<uint16_t>(v, (size_t)B * chan(n, D - 1) * hwb, fail);
     n->d0f = nalloc<float>(v, (size_t)B * chan(n, 0) * H * W, fail);
-    n->th = nalloc<float>(v, (size_t)B * H * W, fail);
+    n->ob = nalloc<float>(v, (size_t)B * H * W, fail);
     n->phi = nalloc<float>(v, (size_t)B * H * W, fail);
     // weight-gradient partials: chunks of 4096 pixels, the largest convolution of any level
     long long need = 0, needb = 0;
@@ -661,14 +666,15 @@ mgseg_status mgseg_net_forward(mgseg_net *n, const float *in_dev, int B, int H, 
         dnbs = (long long)ce * hw;
     }
     hipLaunchKernelGGL(k_head, dim3(nblk((long long)B * HW0)), dim3(256), 0, s, n->d0f, chan(n, 0), (int)HW0, B, n->hw,
-                       n->hb, (float)M, n->th, phi0_dev ? phi0_dev : n->phi);
+                       n->hb, (float)M, n->ob, phi0_dev ? phi0_dev : n->phi);
     if (hipGetLastError() != hipSuccess) return MGSEG_E_HIP;
     return MGSEG_OK;
 }
 
-mgseg_status mgseg_net_backward(mgseg_net *n, const float *target_dev, double M, float *loss_host, void *stream)
+mgseg_status mgseg_net_backward(mgseg_net *n, const float *target_dev, double M, double pos_weight, float *loss_host,
+                                void *stream)
 {
-    if (!n || !target_dev || !(M > 0.0)) return MGSEG_E_ARG;
+    if (!n || !target_dev || !(M > 0.0) || !(pos_weight > 0.0)) return MGSEG_E_ARG;
     if (n->B == 0) return MGSEG_E_STATE;
     hipStream_t s = (hipStream_t)stream;
     const int D = n->depth, B = n->B, H = n->H, W = n->W, C0 = chan(n, 0);
@@ -676,7 +682,8 @@ mgseg_status mgseg_net_backward(mgseg_net *n, const float *target_dev, double M,
     const unsigned nb = nblk((long long)B * HW0);
     const int maxc = C0 + 2;
     // head and loss; gradient of d_0 -> gdact[0]
-    hipLaunchKernelGGL(k_head_bwd, dim3(nb), dim3(256), 0, s, n->th, target_dev, (float)M, n->d0f, C0, (int)HW0, B,
+    hipLaunchKernelGGL(k_head_bwd, dim3(nb), dim3(256), 0, s, n->ob, target_dev, (float)M, (float)pos_weight, n->d0f,
+                       C0, (int)HW0, B,
                        n->hw, n->gdact[0], n->hpart, maxc);
     hipLaunchKernelGGL(k_head_reduce, dim3(1), dim3(256), 0, s, n->hpart, (int)nb, maxc, C0, n->loss, n->ghb, n->ghw,
                        (long long)B * HW0);

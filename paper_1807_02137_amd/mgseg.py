@@ -119,7 +119,7 @@ def lib():
         L.mgseg_destroy_batch.restype = None
         L.mgseg_net_create.argtypes = [C.c_int, C.c_int, C.c_uint64, C.POINTER(vp)]
         L.mgseg_net_forward.argtypes = [vp, vp, C.c_int, C.c_int, C.c_int, C.c_double, vp, vp]
-        L.mgseg_net_backward.argtypes = [vp, vp, C.c_double, C.POINTER(C.c_float), vp]
+        L.mgseg_net_backward.argtypes = [vp, vp, C.c_double, C.c_double, C.POINTER(C.c_float), vp]
         L.mgseg_net_adam_step.argtypes = [vp, C.c_double, C.c_double, C.c_double, C.c_double, vp]
         L.mgseg_net_param_count.argtypes = [vp, C.POINTER(C.c_longlong)]
         L.mgseg_net_get_params.argtypes = [vp, vp, vp]
@@ -127,14 +127,16 @@ def lib():
         L.mgseg_net_destroy.argtypes = [vp]
         L.mgseg_net_destroy.restype = None
         L.mgseg_ctx_features.argtypes = [vp, vp]
-        L.mgseg_predict_phi0.argtypes = [vp, vp]
+        L.mgseg_predict_phi0.argtypes = [vp, vp, ip]
+        L.mgseg_reset_phi0.argtypes = [vp]
         for name in ("mgseg_setup", "mgseg_set_phi0", "mgseg_vcycle", "mgseg_solve", "mgseg_get_phi",
                      "mgseg_get_mask", "mgseg_get_stats", "mgseg_level_shape", "mgseg_debug_get",
                      "mgseg_debug_set", "mgseg_debug_scalars", "mgseg_debug_set_c", "mgseg_debug_op",
                      "mgseg_profile", "mgseg_profile_read", "mgseg_setup_batch", "mgseg_batch_tune",
                      "mgseg_batch_set_streams", "mgseg_solve_batch", "mgseg_batch_ctx", "mgseg_net_create",
                      "mgseg_net_forward", "mgseg_net_backward", "mgseg_net_adam_step", "mgseg_net_param_count",
-                     "mgseg_net_get_params", "mgseg_net_set_params", "mgseg_ctx_features", "mgseg_predict_phi0"):
+                     "mgseg_net_get_params", "mgseg_net_set_params", "mgseg_ctx_features", "mgseg_predict_phi0",
+                     "mgseg_reset_phi0"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -221,9 +223,17 @@ class Solver:
         _check(self.L.mgseg_ctx_features(self.ctx, C.c_void_p(out.data_ptr())), "mgseg_ctx_features")
         return out
 
-    def predict_phi0(self, net: "Net"):
-        """Start the solve from the network's phi0 for this image."""
-        _check(self.L.mgseg_predict_phi0(self.ctx, net.h), "mgseg_predict_phi0")
+    def predict_phi0(self, net: "Net") -> bool:
+        """Start the solve from the network's phi0 for this image if it holds
+        every marker, else from the marker-based phi0; True if the network's
+        phi0 was taken."""
+        acc = C.c_int()
+        _check(self.L.mgseg_predict_phi0(self.ctx, net.h, C.byref(acc)), "mgseg_predict_phi0")
+        return bool(acc.value)
+
+    def reset_phi0(self):
+        """Back to the marker-based initial level set of setup."""
+        _check(self.L.mgseg_reset_phi0(self.ctx), "mgseg_reset_phi0")
 
     # ---- single steps (tests, profiling)
     def shape(self, level=0):
@@ -363,11 +373,11 @@ class Net:
                                         _stream_ptr(stream)), "mgseg_net_forward")
         return out
 
-    def backward(self, target: torch.Tensor, M: float, stream=None) -> float:
+    def backward(self, target: torch.Tensor, M: float, pos_weight: float = 1.0, stream=None) -> float:
         t = target.to(device="cuda", dtype=torch.float32).contiguous()
         loss = C.c_float()
-        _check(self.L.mgseg_net_backward(self.h, C.c_void_p(t.data_ptr()), M, C.byref(loss), _stream_ptr(stream)),
-               "mgseg_net_backward")
+        _check(self.L.mgseg_net_backward(self.h, C.c_void_p(t.data_ptr()), M, pos_weight, C.byref(loss),
+                                         _stream_ptr(stream)), "mgseg_net_backward")
         return loss.value
 
     def adam_step(self, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8, stream=None):

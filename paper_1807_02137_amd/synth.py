@@ -68,12 +68,21 @@ def _pick_markers(rng, mask, k, min_dist, max_dist=None):
     return pts[chosen].astype(np.float64)
 
 
+def _box(n, lo, hi):
+    """Index range [a, b) that holds every cell centre i + 0.5 in [lo, hi],
+    widened by 2 cells (the overlap test dilates by one) and clipped."""
+    return max(int(math.floor(lo - 0.5)) - 2, 0), min(int(math.ceil(hi - 0.5)) + 3, n)
+
+
 def _shapes(rng, n, m, count, scale, margin=2, min_count=None, tries=1000):
-    """Non-overlapping discs / rectangles (rejection after 1-px dilation)."""
+    """Non-overlapping discs / rectangles (rejection after 1-px dilation).
+    Each candidate is evaluated on its bounding box only (the same inclusion
+    test at the same cell centres as on the whole grid); shapes are returned
+    as full-size masks."""
     occupied = np.zeros((n, m), bool)
-    shapes = []
+    boxes = []
     attempts = 0
-    while len(shapes) < count and attempts < tries * count:
+    while len(boxes) < count and attempts < tries * count:
         attempts += 1
         if rng.random() < 0.5:
             r = rng.uniform(8, 24) * scale
@@ -81,7 +90,11 @@ def _shapes(rng, n, m, count, scale, margin=2, min_count=None, tries=1000):
             cx = rng.uniform(margin + r, m - margin - r) if m - 2 * (margin + r) > 0 else None
             if cy is None or cx is None:
                 continue
-            mask = _disc(n, m, cy, cx, r)
+            i0, i1 = _box(n, cy - r, cy + r)
+            j0, j1 = _box(m, cx - r, cx + r)
+            yy = np.arange(i0, i1)[:, None] + 0.5
+            xx = np.arange(j0, j1)[None, :] + 0.5
+            mask = (yy - cy) ** 2 + (xx - cx) ** 2 <= r * r
         else:
             hh = rng.uniform(12, 40) * scale
             ww = rng.uniform(12, 40) * scale
@@ -89,15 +102,24 @@ def _shapes(rng, n, m, count, scale, margin=2, min_count=None, tries=1000):
                 continue
             y0 = rng.uniform(margin, n - margin - hh)
             x0 = rng.uniform(margin, m - margin - ww)
-            mask = _rect(n, m, y0, x0, hh, ww)
+            i0, i1 = _box(n, y0, y0 + hh)
+            j0, j1 = _box(m, x0, x0 + ww)
+            yy = np.arange(i0, i1)[:, None] + 0.5
+            xx = np.arange(j0, j1)[None, :] + 0.5
+            mask = (yy >= y0) & (yy <= y0 + hh) & (xx >= x0) & (xx <= x0 + ww)
         if mask.sum() == 0:
             continue
-        if (ndimage.binary_dilation(mask) & occupied).any():
+        if (ndimage.binary_dilation(mask) & occupied[i0:i1, j0:j1]).any():
             continue
-        occupied |= mask
-        shapes.append(mask)
-    if min_count is not None and len(shapes) < min_count:
+        occupied[i0:i1, j0:j1] |= mask
+        boxes.append((i0, i1, j0, j1, mask))
+    if min_count is not None and len(boxes) < min_count:
         raise RuntimeError("shape placement failed")
+    shapes = []
+    for i0, i1, j0, j1, mask in boxes:
+        full = np.zeros((n, m), bool)
+        full[i0:i1, j0:j1] = mask
+        shapes.append(full)
     return shapes
 
 
@@ -228,6 +250,13 @@ def config5(seed: int, n: int = 512) -> Instance:
     noise = float(rng.uniform(0.02, 0.1))
     k = int(rng.integers(3, 9))
     return shapes_instance(seed * 7 + 1, n, n, count, 4.0 * n / 512.0, noise, k, f"c5_{n}", min_count=4)
+
+
+def config5_arrays(seed_n):
+    """(image, markers, seed) of config5(seed, n) for a worker process."""
+    seed, n = seed_n
+    inst = config5(seed, n)
+    return inst.image, inst.markers, seed
 
 
 def tiny_instance(seed: int, n: int = 16, m: int = 16, markers: int = 3) -> Instance:

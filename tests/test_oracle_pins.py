@@ -362,14 +362,27 @@ def test_cnn_reference_gradient_matches_finite_differences():
     theta = rng.normal(scale=0.4, size=cnn.param_count(base, depth))
     x = rng.normal(size=(2, 3, 8, 8))
     tgt = rng.uniform(-5, 5, size=(2, 8, 8))
-    loss, g = cnn.loss_and_grad(theta, x, tgt, base, depth, M)
+    pw = 2.5
+    loss, g = cnn.loss_and_grad(theta, x, tgt, base, depth, M, pos_weight=pw)
     idx = rng.choice(theta.size, 40, replace=False)
     h = 1e-6
+
+    def L(t):
+        return cnn.loss_and_grad(t, x, tgt, base, depth, M, pos_weight=pw)[0]
+
     for i in idx:
         tp, tm = theta.copy(), theta.copy()
         tp[i] += h; tm[i] -= h
-        fd = (cnn.loss_and_grad(tp, x, tgt, base, depth, M)[0] - cnn.loss_and_grad(tm, x, tgt, base, depth, M)[0]) / (2 * h)
+        fd = (L(tp) - L(tm)) / (2 * h)
         assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(fd)) + 1e-9, (i, fd, g[i])
+    # the loss is the weighted cross-entropy of p = sigmoid(2 o) against
+    # q = (1 + t) / 2, written out from its definition
+    t = np.clip(tgt / M, -1, 1)
+    o = cnn.forward(theta, x, base, depth, M)[1]["o"]
+    p = 1.0 / (1.0 + np.exp(-2.0 * o))
+    q = (1.0 + t) / 2.0
+    ce = -(q * np.log(p) + (1 - q) * np.log(1 - p))
+    assert np.isclose(loss, (np.where(t > 0, pw, 1.0) * ce).mean(), rtol=1e-10)
 
 
 def test_cnn_reference_conv_is_a_correlation():
