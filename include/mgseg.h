@@ -242,8 +242,10 @@ void mgseg_destroy_batch(mgseg_batch *b);
  */
 typedef struct mgseg_net mgseg_net;
 
-/* New network with He-normal weights from `seed` (deterministic).
- * Errors: MGSEG_E_ARG (base_channels not in 1..256, depth not in 2..6). */
+/* New network with He-normal weights from `seed` (deterministic).  Channel
+ * counts are multiples of the 16-wide matrix-core tile.
+ * Errors: MGSEG_E_ARG (base_channels not a multiple of 16 in 16..256, depth
+ * not in 2..6, or base_channels * 2^(depth-1) above 512). */
 mgseg_status mgseg_net_create(int base_channels, int depth, uint64_t seed, mgseg_net **out);
 
 /* phi0_dev[B][H][W] = M tanh(net(in_dev[B][3][H][W])); keeps the activations

@@ -7,8 +7,26 @@
 //   encoder  e_l = cb(p_{l-1}), p_l = avgpool2(e_l)     (e_0 = cb(input))
 //   decoder  d_l = cb([up2(d_{l+1}) | e_l])              (d_{D-1} = e_{D-1})
 //   head     o = w . d_0 + b (1x1),  phi0 = M tanh(o)
-// Storage: activations and convolution weights in bf16, accumulation in FP32
-// (MFMA 16x16x16 bf16), FP32 master weights with Adam.  Tensors are NCHW.
+//
+// Storage: activations and their gradients in bf16, channels last (NHWC:
+// pixel-major, the channels of a pixel contiguous; a batch is one run of
+// pixels, image by image); convolution weights packed in bf16 as
+// [OC][tap][IC] (and, for the data gradient, the tap-reversed transpose
+// [IC][tap][OC]); FP32 master weights with Adam.  Every channel count is a
+// multiple of 16 (the input's 3 channels are padded with zeros to 16).
+//
+// Convolutions are implicit GEMMs on the matrix cores
+// (mfma_f32_16x16x16bf16, FP32 accumulation):
+//   forward / data gradient (k_conv): M = output channels, N = pixels,
+//     K = 9 taps x input channels.  A block computes 32 channels x an 8 x 32
+//     pixel tile; per 16-channel chunk the tile's input halo (10 x 34
+//     pixels) is staged in LDS and each wave keeps the weights of all 9
+//     taps in registers.
+//   weight gradient (k_wgrad): M = output channels, N = 9 taps x input
+//     channels, K = pixels.  A block owns 32 x (9 x 16) weights and walks a
+//     strided share of the pixel tiles, staging the output gradient and the
+//     input halo transposed (pixels contiguous) in LDS; one partial sum per
+//     block, added in a fixed order (deterministic).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <algorithm>
@@ -24,6 +42,15 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 namespace {
 
+constexpr int CIN0 = 16;                       // input channels after padding
+constexpr int TY = 8, TX = 32;                 // pixel tile of a block
+constexpr int HY = TY + 2, HX = TX + 2;        // its halo
+constexpr int HP = 24;                         // LDS elements per halo pixel in k_conv (16 used; 48 B keeps lanes apart)
+constexpr int OCB = 32;                        // output channels per block
+constexpr int GTS = TY * TX + 8;               // k_wgrad: LDS row of the transposed output gradient
+constexpr int XRS = 36;                        // k_wgrad: LDS halo row (34 used)
+constexpr int XTS = HY * XRS + 4;              // k_wgrad: LDS plane of one input channel
+
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 __device__ __forceinline__ uint16_t f2bf(float x)
 {
@@ -35,240 +62,356 @@ __device__ __forceinline__ uint16_t f2bf(float x)
 }
 
 // --------------------------------------------------------------------------
-// 3x3 convolution, zero padding, stride 1, as an implicit GEMM:
-//   out[b, oc, p] = sum_{ic, r} Wk[oc, ic*9 + r] in[b, ic, p + off(r)] (+ bias[oc]), off(r) = (r/3-1, r%3-1)
-// Block 256 = 4 waves; block tile 32 oc x 32 pixels (pixels of all images in
-// one index, px = b*HW + p); each wave one 16 x 16 MFMA tile, K in steps of
-// 16.  in / out: bf16 with channel stride HW and image strides ibs / obs.
+// 3x3 convolution, zero padding, stride 1:
+//   out[px, oc] = act( sum_{r, ic} W[oc, r, ic] in[px + off(r), ic] + bias[oc] ),  off(r) = (r/3 - 1, r%3 - 1)
+// with act = ReLU (relu), then zeroed where mask[px, oc] <= 0 (mask set).
+// Views: element (px, c) of a view is at ptr[px * ps + off + c].
 struct ConvArgs {
-    const uint16_t *in; long long ibs;
-    const uint16_t *W; int K;            // Wk row-major [OC][K], K = IC*9
-    const float *bias;                   // may be null
-    uint16_t *out; long long obs;
-    float *out32; long long o32bs;       // optional FP32 copy of the output (null: none)
-    int IC, OC, H, Wd, B, relu;
+    const uint16_t *in; int ips, ioff;
+    const uint16_t *Wk;                  // packed [OC][9][IC]
+    const float *bias;                   // [OC] or null
+    uint16_t *out; int ops, ooff;
+    float *out32;                        // optional dense FP32 copy [px][OC]
+    const uint16_t *mask; int mps, moff; // optional
+    int IC, OC, H, W, relu;
 };
 
-__global__ void __launch_bounds__(256) k_conv3x3(ConvArgs A)
+__global__ void __launch_bounds__(256) k_conv(ConvArgs A)
 {
+    __shared__ __attribute__((aligned(16))) uint16_t halo[HY * HX * HP];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int HW = A.H * A.Wd;
-    const long long NP = (long long)A.B * HW;
-    const int oc0 = blockIdx.y * 32 + (wave >> 1) * 16;
-    const long long px0 = (long long)blockIdx.x * 32 + (wave & 1) * 16;
-    // this lane's B-column pixel and A-row channel
-    const long long pxb = px0 + (lane & 15);
-    const bool pvalid = pxb < NP;
-    const int bimg = pvalid ? (int)(pxb / HW) : 0;
-    const int pp = pvalid ? (int)(pxb % HW) : 0;
-    const int py = pp / A.Wd, pxx = pp % A.Wd;
-    const uint16_t *inb = A.in + (long long)bimg * A.ibs;
-    const int arow = oc0 + (lane & 15);
-    const uint16_t *wrow = A.W + (long long)(arow < A.OC ? arow : 0) * A.K;
-    f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-    for (int k0 = 0; k0 < A.K; k0 += 16) {
-        bf16x4 a, bv;
+    const int l16 = lane & 15, g4 = (lane >> 4) * 4;
+    const int tilesx = (A.W + TX - 1) / TX;
+    const int ty0 = (int)(blockIdx.x / tilesx) * TY, tx0 = (int)(blockIdx.x % tilesx) * TX;
+    const int oc0 = blockIdx.y * OCB;
+    const long long img = (long long)blockIdx.z * A.H * A.W;
+    const bool two = oc0 + 16 < A.OC;               // second 16-channel tile present (uniform)
+    f32x4 acc[2][4];
 #pragma unroll
-        for (int i = 0; i < 4; i++) {
-            const int k = k0 + 4 * (lane >> 4) + i;
-            uint16_t av = 0, bvv = 0;
-            if (k < A.K) {
-                if (arow < A.OC) av = wrow[k];
-                if (pvalid) {
-                    const int ic = k / 9, r = k - 9 * ic;
-                    const int yy = py + r / 3 - 1, xx = pxx + r % 3 - 1;
-                    if (yy >= 0 && yy < A.H && xx >= 0 && xx < A.Wd) bvv = inb[(long long)ic * HW + yy * A.Wd + xx];
-                }
-            }
-            a[i] = (short)av;
-            bv[i] = (short)bvv;
+    for (int t = 0; t < 2; t++)
+#pragma unroll
+        for (int p = 0; p < 4; p++) acc[t][p] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    const uint16_t *w0 = A.Wk + (long long)(oc0 + l16) * 9 * A.IC + g4;
+    const uint16_t *w1 = A.Wk + (long long)(oc0 + 16 + (two ? l16 : 0)) * 9 * A.IC + g4;
+    for (int c0 = 0; c0 < A.IC; c0 += 16) {
+        bf16x4 wa[2][9];
+#pragma unroll
+        for (int r = 0; r < 9; r++) {
+            wa[0][r] = *(const bf16x4 *)(w0 + r * A.IC + c0);
+            wa[1][r] = two ? *(const bf16x4 *)(w1 + r * A.IC + c0) : bf16x4{0, 0, 0, 0};
         }
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bv, acc, 0, 0, 0);
-    }
-    // D[row = 4*(lane/16) + i][col = lane % 16]
-    const long long px = px0 + (lane & 15);
-    if (px >= NP) return;
-    const int ob = (int)(px / HW), op = (int)(px % HW);
+        __syncthreads();                            // the previous chunk's halo is no longer read
+        for (int u = threadIdx.x; u < HY * HX * 2; u += 256) {
+            const int hp = u >> 1, half = u & 1;
+            const int hy = hp / HX, hx = hp - hy * HX;
+            const int y = ty0 + hy - 1, x = tx0 + hx - 1;
+            uint4 v = {0u, 0u, 0u, 0u};
+            if (y >= 0 && y < A.H && x >= 0 && x < A.W)
+                v = *(const uint4 *)(A.in + (img + (long long)y * A.W + x) * A.ips + A.ioff + c0 + 8 * half);
+            *(uint4 *)(halo + hp * HP + 8 * half) = v;
+        }
+        __syncthreads();
 #pragma unroll
-    for (int i = 0; i < 4; i++) {
-        const int oc = oc0 + 4 * (lane >> 4) + i;
-        if (oc >= A.OC) continue;
-        float v = acc[i] + (A.bias ? A.bias[oc] : 0.0f);
-        if (A.relu) v = fmaxf(v, 0.0f);
-        A.out[(long long)ob * A.obs + (long long)oc * HW + op] = f2bf(v);
-        if (A.out32) A.out32[(long long)ob * A.o32bs + (long long)oc * HW + op] = v;
+        for (int r = 0; r < 9; r++) {
+            const int dy = r / 3, dx = r % 3;
+#pragma unroll
+            for (int p = 0; p < 4; p++) {
+                const int yr = 2 * wave + (p >> 1), xo = 16 * (p & 1);
+                const bf16x4 bv = *(const bf16x4 *)(halo + ((yr + dy) * HX + xo + l16 + dx) * HP + g4);
+                acc[0][p] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wa[0][r], bv, acc[0][p], 0, 0, 0);
+                if (two) acc[1][p] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wa[1][r], bv, acc[1][p], 0, 0, 0);
+            }
+        }
+    }
+    // D[row = 4 (lane / 16) + i][col = lane % 16]: 4 consecutive channels of one pixel
+#pragma unroll
+    for (int p = 0; p < 4; p++) {
+        const int y = ty0 + 2 * wave + (p >> 1), x = tx0 + 16 * (p & 1) + l16;
+        if (y >= A.H || x >= A.W) continue;
+        const long long px = img + (long long)y * A.W + x;
+#pragma unroll
+        for (int t = 0; t < 2; t++) {
+            if (t == 1 && !two) continue;
+            const int oc = oc0 + 16 * t + g4;
+            float v[4];
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                v[i] = acc[t][p][i] + (A.bias ? A.bias[oc + i] : 0.0f);
+                if (A.relu) v[i] = fmaxf(v[i], 0.0f);
+            }
+            if (A.mask) {
+                const uint16_t *mk = A.mask + px * A.mps + A.moff + oc;
+#pragma unroll
+                for (int i = 0; i < 4; i++)
+                    if (!(bf2f(mk[i]) > 0.0f)) v[i] = 0.0f;
+            }
+            bf16x4 o;
+#pragma unroll
+            for (int i = 0; i < 4; i++) o[i] = (short)f2bf(v[i]);
+            *(bf16x4 *)(A.out + px * A.ops + A.ooff + oc) = o;
+            if (A.out32) *(f32x4 *)(A.out32 + px * A.OC + oc) = f32x4{v[0], v[1], v[2], v[3]};
+        }
     }
 }
 
-// weight gradient: dW[oc, ic*9 + r] = sum_{b, p} g[b, oc, p] x[b, ic, p + off(r)],
-// dbias[oc] = sum g.  M = OC (16 per wave-tile), N = IC*9 (16), K = pixels;
-// each block takes a chunk of CH pixels and writes its partial sums (FP32)
-// to part[chunk][OC][K] / partb[chunk][OC]; k_wgrad_reduce adds the chunks in
-// order (deterministic).  Block 256: 4 waves along N.
+// --------------------------------------------------------------------------
+// weight gradient: dW[oc, r, ic] = sum_px g[px, oc] x[px + off(r), ic],  db[oc] = sum_px g[px, oc].
+// Block (p, oc block of 32, ic chunk of 16) adds up the pixel tiles p, p + P, ...
+// and writes part[p][oc][r][ic] (IC = padded count) and, for ic chunk 0, partb[p][oc].
 struct WgradArgs {
-    const uint16_t *g; long long gbs;     // gradient of the conv output (relu-masked), bf16
-    const uint16_t *x; long long xbs;     // conv input
+    const uint16_t *g; int gps, goff;    // output gradient (already ReLU-masked)
+    const uint16_t *x; int xps, xoff;    // convolution input
     float *part, *partb;
-    int IC, OC, H, Wd, B, chunk;
+    int IC, OC, H, W, B, P;
 };
+
+__device__ __forceinline__ uint32_t pack2(uint16_t a, uint16_t b) { return (uint32_t)a | ((uint32_t)b << 16); }
 
 __global__ void __launch_bounds__(256) k_wgrad(WgradArgs A)
 {
+    // gT [oc][tile pixel] and xT [ic][halo row][halo col]; at the end the same memory adds up the waves
+    __shared__ __attribute__((aligned(16))) uint16_t lds[OCB * GTS + 16 * XTS];
+    static_assert(3 * 9 * 256 * 2 <= OCB * GTS + 16 * XTS, "wave reduction does not fit");
+    uint16_t *const gT = lds, *const xT = lds + OCB * GTS;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int HW = A.H * A.Wd, K = A.IC * 9;
-    const long long NP = (long long)A.B * HW;
-    const int oc0 = blockIdx.y * 16;
-    const int n0 = blockIdx.z * 64 + wave * 16;
-    const long long c0 = (long long)blockIdx.x * A.chunk;
-    const int arow = oc0 + (lane & 15);            // A[m = oc][k = px]
-    const int ncol = n0 + (lane & 15);             // B[k = px][n = ic*9 + r]
-    const int ic = ncol / 9, r = ncol - 9 * (ncol / 9);
-    const int dy = r / 3 - 1, dx = r % 3 - 1;
-    f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-    float bsum = 0.0f;
-    for (long long k0 = c0; k0 < c0 + A.chunk && k0 < NP; k0 += 16) {
-        bf16x4 a, bv;
+    const int l16 = lane & 15, g4 = (lane >> 4) * 4;
+    const int oc0 = blockIdx.y * OCB, c0 = blockIdx.z * 16;
+    const bool two = oc0 + 16 < A.OC;
+    const bool dobias = blockIdx.z == 0;
+    const int tilesx = (A.W + TX - 1) / TX, tiles = tilesx * ((A.H + TY - 1) / TY);
+    const int T = tiles * A.B;
+    f32x4 acc[2][9];
 #pragma unroll
-        for (int i = 0; i < 4; i++) {
-            const long long px = k0 + 4 * (lane >> 4) + i;
-            uint16_t av = 0, bvv = 0;
-            if (px < NP && px < c0 + A.chunk) {
-                const int b = (int)(px / HW), p = (int)(px % HW);
-                if (arow < A.OC) av = A.g[(long long)b * A.gbs + (long long)arow * HW + p];
-                if (ncol < K) {
-                    const int y = p / A.Wd + dy, xx = p % A.Wd + dx;
-                    if (y >= 0 && y < A.H && xx >= 0 && xx < A.Wd)
-                        bvv = A.x[(long long)b * A.xbs + (long long)ic * HW + y * A.Wd + xx];
+    for (int t = 0; t < 2; t++)
+#pragma unroll
+        for (int r = 0; r < 9; r++) acc[t][r] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    float bsum = 0.0f;
+    for (int tile = blockIdx.x; tile < T; tile += A.P) {
+        const int b = tile / tiles, tt = tile % tiles;
+        const int ty0 = (tt / tilesx) * TY, tx0 = (tt % tilesx) * TX;
+        const long long img = (long long)b * A.H * A.W;
+        __syncthreads();
+        // g: pixel pairs x 8-channel groups, written transposed as (pixel, pixel + 1) pairs
+        for (int u = threadIdx.x; u < (TY * TX / 2) * (OCB / 8); u += 256) {
+            const int pp = u % (TY * TX / 2), cg = u / (TY * TX / 2);
+            const int q = 2 * pp, yr = q / TX, xr = q % TX;
+            const int y = ty0 + yr, x = tx0 + xr;
+            uint4 v0 = {0u, 0u, 0u, 0u}, v1 = {0u, 0u, 0u, 0u};
+            const int oc = oc0 + 8 * cg;
+            if (y < A.H && oc < A.OC) {
+                const uint16_t *s = A.g + (img + (long long)y * A.W + x) * A.gps + A.goff + oc;
+                if (x < A.W) v0 = *(const uint4 *)s;
+                if (x + 1 < A.W) v1 = *(const uint4 *)(s + A.gps);
+            }
+            const uint16_t *a0 = (const uint16_t *)&v0, *a1 = (const uint16_t *)&v1;
+#pragma unroll
+            for (int j = 0; j < 8; j++) *(uint32_t *)(gT + (8 * cg + j) * GTS + q) = pack2(a0[j], a1[j]);
+        }
+        // x halo: column pairs x 8-channel halves
+        for (int u = threadIdx.x; u < HY * (HX / 2) * 2; u += 256) {
+            const int pp = u % (HY * (HX / 2)), half = u / (HY * (HX / 2));
+            const int hy = pp / (HX / 2), hx = 2 * (pp % (HX / 2));
+            const int y = ty0 + hy - 1, x = tx0 + hx - 1;
+            uint4 v0 = {0u, 0u, 0u, 0u}, v1 = {0u, 0u, 0u, 0u};
+            if (y >= 0 && y < A.H) {
+                const long long row = img + (long long)y * A.W;
+                if (x >= 0 && x < A.W) v0 = *(const uint4 *)(A.x + (row + x) * A.xps + A.xoff + c0 + 8 * half);
+                if (x + 1 < A.W) v1 = *(const uint4 *)(A.x + (row + x + 1) * A.xps + A.xoff + c0 + 8 * half);
+            }
+            const uint16_t *a0 = (const uint16_t *)&v0, *a1 = (const uint16_t *)&v1;
+#pragma unroll
+            for (int j = 0; j < 8; j++) *(uint32_t *)(xT + (8 * half + j) * XTS + hy * XRS + hx) = pack2(a0[j], a1[j]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < 4; s++) {
+            const int yr = 2 * wave + (s >> 1), xo = 16 * (s & 1);
+            const bf16x4 a0 = *(const bf16x4 *)(gT + l16 * GTS + yr * TX + xo + g4);
+            const bf16x4 a1 = two ? *(const bf16x4 *)(gT + (16 + l16) * GTS + yr * TX + xo + g4) : bf16x4{0, 0, 0, 0};
+#pragma unroll
+            for (int dy = 0; dy < 3; dy++) {
+                const uint16_t *row = xT + l16 * XTS + (yr + dy) * XRS + xo + g4;
+                const bf16x4 e0 = *(const bf16x4 *)row, e1 = *(const bf16x4 *)(row + 4);
+                const bf16x4 b1 = bf16x4{e0[1], e0[2], e0[3], e1[0]};
+                const bf16x4 b2 = bf16x4{e0[2], e0[3], e1[0], e1[1]};
+                acc[0][3 * dy + 0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, e0, acc[0][3 * dy + 0], 0, 0, 0);
+                acc[0][3 * dy + 1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, b1, acc[0][3 * dy + 1], 0, 0, 0);
+                acc[0][3 * dy + 2] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, b2, acc[0][3 * dy + 2], 0, 0, 0);
+                if (two) {
+                    acc[1][3 * dy + 0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, e0, acc[1][3 * dy + 0], 0, 0, 0);
+                    acc[1][3 * dy + 1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, b1, acc[1][3 * dy + 1], 0, 0, 0);
+                    acc[1][3 * dy + 2] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, b2, acc[1][3 * dy + 2], 0, 0, 0);
                 }
             }
-            a[i] = (short)av;
-            bv[i] = (short)bvv;
-            if (wave == 0 && blockIdx.z == 0) bsum += bf2f(av);
         }
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bv, acc, 0, 0, 0);
+        if (dobias) {
+            // thread (oc = tid / 8, part = tid % 8) adds 32 pixels of the tile
+            const int oc = threadIdx.x >> 3, part = threadIdx.x & 7;
+            float s = 0.0f;
+            for (int q = 0; q < TY * TX / 8; q++) s += bf2f(gT[oc * GTS + part * (TY * TX / 8) + q]);
+            bsum += s;
+        }
     }
-    const long long pbase = (long long)blockIdx.x * A.OC * K;
+    // every wave holds the sums over its own rows of each tile: wave 0 adds waves 1, 2, 3 (in that order)
+    // and writes the block's partial, D[row = oc][col = ic]
+    float *red = (float *)lds;
+    const long long K9 = 9LL * A.IC;
+    float *pb = A.part + (long long)blockIdx.x * A.OC * K9;
 #pragma unroll
-    for (int i = 0; i < 4; i++) {
-        const int oc = oc0 + 4 * (lane >> 4) + i;
-        if (oc < A.OC && ncol < K) A.part[pbase + (long long)oc * K + ncol] = acc[i];
+    for (int t = 0; t < 2; t++) {
+        if (t == 1 && !two) break;
+        __syncthreads();
+        if (wave > 0) {
+#pragma unroll
+            for (int r = 0; r < 9; r++)
+#pragma unroll
+                for (int i = 0; i < 4; i++) red[((wave - 1) * 9 + r) * 256 + i * 64 + lane] = acc[t][r][i];
+        }
+        __syncthreads();
+        if (wave == 0) {
+#pragma unroll
+            for (int r = 0; r < 9; r++)
+#pragma unroll
+                for (int i = 0; i < 4; i++) {
+                    float v = acc[t][r][i];
+                    for (int w = 0; w < 3; w++) v += red[(w * 9 + r) * 256 + i * 64 + lane];
+                    pb[(long long)(oc0 + 16 * t + g4 + i) * K9 + r * A.IC + c0 + l16] = v;
+                }
+        }
     }
-    if (wave == 0 && blockIdx.z == 0) {
-        // bias: lanes with the same row (lane % 16) hold the 4 pixel groups
-        bsum += __shfl_xor(bsum, 16);
-        bsum += __shfl_xor(bsum, 32);
-        if (lane < 16 && arow < A.OC) A.partb[(long long)blockIdx.x * A.OC + arow] = bsum;
+    if (dobias) {
+        // the 8 threads of one channel are consecutive lanes
+        bsum += __shfl_xor(bsum, 1);
+        bsum += __shfl_xor(bsum, 2);
+        bsum += __shfl_xor(bsum, 4);
+        const int oc = oc0 + (threadIdx.x >> 3);
+        if ((threadIdx.x & 7) == 0 && oc < A.OC) A.partb[(long long)blockIdx.x * A.OC + oc] = bsum;
     }
 }
 
-__global__ void k_wgrad_reduce(const float *part, const float *partb, int nchunk, int OC, int K, float *dW, float *db)
+// dW (master layout [OC][ICr][3][3]) = sum over the P partials [OC][9][IC] of the real channels ic < ICr
+__global__ void k_wgrad_reduce(const float *part, const float *partb, int P, int OC, int IC, int ICr, float *dW,
+                               float *db)
 {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long long NW = (long long)OC * K;
+    const long long NW = (long long)OC * ICr * 9;
+    const long long stride = (long long)OC * 9 * IC;
     if (t < NW) {
-        float s = 0.0f;
-        for (int c = 0; c < nchunk; c++) s += part[(long long)c * NW + t];
-        dW[t] = s;
+        const int oc = (int)(t / (ICr * 9)), rem = (int)(t % (ICr * 9)), ic = rem / 9, r = rem % 9;
+        const float *s = part + ((long long)oc * 9 + r) * IC + ic;
+        float acc = 0.0f;
+        for (int p = 0; p < P; p++) acc += s[(long long)p * stride];
+        dW[t] = acc;
     } else if (t < NW + OC) {
         const int oc = (int)(t - NW);
-        float s = 0.0f;
-        for (int c = 0; c < nchunk; c++) s += partb[(long long)c * OC + oc];
-        db[oc] = s;
+        float acc = 0.0f;
+        for (int p = 0; p < P; p++) acc += partb[(long long)p * OC + oc];
+        db[oc] = acc;
     }
 }
 
-// Wt[ic, oc*9 + r] = W[oc, ic*9 + 8 - r]: the data gradient is the convolution
-// of the output gradient with the flipped, transposed kernel
-__global__ void k_flip_weights(const uint16_t *W, int IC, int OC, uint16_t *Wt)
+// master [OC][ICr][3][3] -> packed [OC][9][IC] (zero for ic >= ICr) and, if Wt, the data-gradient
+// weights [ICr][9][OC] with the taps reversed (Wt[ic, r, oc] = W[oc, ic, 8 - r])
+__global__ void k_pack_weights(const float *w, int OC, int ICr, int IC, uint16_t *Wp, uint16_t *Wt)
 {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= IC * OC * 9) return;
-    const int ic = t / (OC * 9), rem = t % (OC * 9), oc = rem / 9, r = rem % 9;
-    Wt[t] = W[(long long)oc * IC * 9 + ic * 9 + (8 - r)];
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < (long long)OC * 9 * IC) {
+        const int oc = (int)(t / (9 * IC)), rem = (int)(t % (9 * IC)), r = rem / IC, ic = rem % IC;
+        Wp[t] = ic < ICr ? f2bf(w[((long long)oc * ICr + ic) * 9 + r]) : (uint16_t)0;
+    }
+    if (Wt && t < (long long)ICr * 9 * OC) {
+        const int ic = (int)(t / (9 * OC)), rem = (int)(t % (9 * OC)), r = rem / OC, oc = rem % OC;
+        Wt[t] = f2bf(w[((long long)oc * ICr + ic) * 9 + (8 - r)]);
+    }
 }
 
-// g <- g * (y > 0) over C channels of B images (strides in elements)
-__global__ void k_relu_mask(uint16_t *g, long long gbs, const uint16_t *y, long long ybs, int C, int HW, int B)
-{
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long long per = (long long)C * HW;
-    if (t >= per * B) return;
-    const int b = (int)(t / per);
-    const long long q = t % per;
-    if (!(bf2f(y[(long long)b * ybs + q]) > 0.0f)) g[(long long)b * gbs + q] = 0;
-}
-
-// 2x2 average pooling and its adjoint (accumulating: g_in += 0.25 g_out)
-__global__ void k_avgpool(const uint16_t *x, long long xbs, uint16_t *y, long long ybs, int C, int H, int W, int B)
-{
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const int h = H / 2, w = W / 2;
-    const long long per = (long long)C * h * w;
-    if (t >= per * B) return;
-    const int b = (int)(t / per);
-    const long long q = t % per;
-    const int c = (int)(q / (h * w)), yy = (int)(q % (h * w)) / w, xx = (int)(q % w);
-    const uint16_t *s = x + (long long)b * xbs + (long long)c * H * W + (2 * yy) * W + 2 * xx;
-    y[(long long)b * ybs + q] = f2bf(0.25f * (bf2f(s[0]) + bf2f(s[1]) + bf2f(s[W]) + bf2f(s[W + 1])));
-}
-__global__ void k_avgpool_bwd(const uint16_t *gy, long long gybs, uint16_t *gx, long long gxbs, int C, int H, int W,
-                              int B)
-{
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long long per = (long long)C * H * W;
-    if (t >= per * B) return;
-    const int b = (int)(t / per);
-    const long long q = t % per;
-    const int c = (int)(q / ((long long)H * W)), yy = (int)(q % ((long long)H * W)) / W, xx = (int)(q % W);
-    const int h = H / 2, w = W / 2;
-    const float g = bf2f(gy[(long long)b * gybs + (long long)c * h * w + (yy / 2) * w + xx / 2]);
-    uint16_t *d = gx + (long long)b * gxbs + q;
-    *d = f2bf(bf2f(*d) + 0.25f * g);
-}
-
-// nearest 2x upsampling into channels [0, C) of y, and its adjoint (2x2 sums)
-__global__ void k_upsample(const uint16_t *x, long long xbs, uint16_t *y, long long ybs, int C, int h, int w, int B)
-{
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const int H = 2 * h, W = 2 * w;
-    const long long per = (long long)C * H * W;
-    if (t >= per * B) return;
-    const int b = (int)(t / per);
-    const long long q = t % per;
-    const int c = (int)(q / ((long long)H * W)), yy = (int)(q % ((long long)H * W)) / W, xx = (int)(q % W);
-    y[(long long)b * ybs + q] = x[(long long)b * xbs + (long long)c * h * w + (yy / 2) * w + xx / 2];
-}
-__global__ void k_upsample_bwd(const uint16_t *gy, long long gybs, uint16_t *gx, long long gxbs, int C, int h, int w,
-                               int B)
-{
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long long per = (long long)C * h * w;
-    if (t >= per * B) return;
-    const int b = (int)(t / per);
-    const long long q = t % per;
-    const int c = (int)(q / ((long long)h * w)), yy = (int)(q % ((long long)h * w)) / w, xx = (int)(q % w);
-    const int W = 2 * w;
-    const uint16_t *s = gy + (long long)b * gybs + (long long)c * 4 * h * w + (2 * yy) * W + 2 * xx;
-    gx[(long long)b * gxbs + q] = f2bf(bf2f(s[0]) + bf2f(s[1]) + bf2f(s[W]) + bf2f(s[W + 1]));
-}
-
-// input features (FP32 NCHW, 3 channels) to bf16
-__global__ void k_to_bf16(const float *x, uint16_t *y, long long n)
-{
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < n) y[t] = f2bf(x[t]);
-}
-
-// head: o = w . d0 + b, phi0 = M tanh(o) (FP32 from the FP32 copy of d0); keeps o for the loss
-__global__ void k_head(const float *d0, int C, int HW, int B, const float *w, const float *b, float M, float *ob,
-                       float *phi)
+// --------------------------------------------------------------------------
+// input features FP32 [B][3][H][W] -> bf16 [B*H*W][16] (channels 3..15 zero)
+__global__ void k_pack_input(const float *x, long long HW, int B, uint16_t *y)
 {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (long long)B * HW) return;
-    const int bi = (int)(t / HW), p = (int)(t % HW);
-    const float *x = d0 + (long long)bi * C * HW + p;
+    const long long b = t / HW, p = t % HW;
+    bf16x4 v0 = {0, 0, 0, 0}, z = {0, 0, 0, 0};
+    for (int c = 0; c < 3; c++) v0[c] = (short)f2bf(x[(b * 3 + c) * HW + p]);
+    bf16x4 *d = (bf16x4 *)(y + t * CIN0);
+    d[0] = v0; d[1] = z; d[2] = z; d[3] = z;
+}
+
+// 2x2 average pooling: out[(b, y, x), c] (dense, C per pixel) from the view (ps, off) at twice the size
+__global__ void k_avgpool(const uint16_t *in, int ps, int off, int C, int h, int w, int B, uint16_t *out)
+{
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long long)B * h * w * C) return;
+    const long long q = t / C;
+    const int c = (int)(t % C);
+    const long long b = q / ((long long)h * w);
+    const int yy = (int)((q / w) % h), xx = (int)(q % w);
+    const int W = 2 * w;
+    const long long f = b * 4LL * h * w + (long long)(2 * yy) * W + 2 * xx;
+    const uint16_t *s = in + off + c;
+    const float v = bf2f(s[f * ps]) + bf2f(s[(f + 1) * ps]) + bf2f(s[(f + W) * ps]) + bf2f(s[(f + W + 1) * ps]);
+    out[t] = f2bf(0.25f * v);
+}
+
+// gradient of e (view g: the skip part of the concatenation's gradient) += 0.25 gpool of its coarse
+// pixel, rounded, then zeroed where e <= 0
+__global__ void k_avgpool_bwd(const uint16_t *gp, int C, int h, int w, int B, uint16_t *g, int gps, int goff,
+                              const uint16_t *e, int eps, int eoff)
+{
+    const int H = 2 * h, W = 2 * w;
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long long)B * H * W * C) return;
+    const long long px = t / C;
+    const int c = (int)(t % C);
+    const long long b = px / ((long long)H * W);
+    const int y = (int)((px / W) % H), x = (int)(px % W);
+    const float gc = bf2f(gp[((b * h + y / 2) * w + x / 2) * C + c]);
+    uint16_t *d = g + px * gps + goff + c;
+    const float v = bf2f(*d) + 0.25f * gc;
+    *d = bf2f(e[px * eps + eoff + c]) > 0.0f ? f2bf(v) : (uint16_t)0;
+}
+
+// nearest 2x up-sampling of the dense coarse d [(b, y, x)][C] into channels [0, C) of the view (ps, 0)
+__global__ void k_upsample(const uint16_t *d, int C, int h, int w, int B, uint16_t *out, int ps)
+{
+    const int H = 2 * h, W = 2 * w;
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long long)B * H * W * C) return;
+    const long long px = t / C;
+    const int c = (int)(t % C);
+    const long long b = px / ((long long)H * W);
+    const int y = (int)((px / W) % H), x = (int)(px % W);
+    out[px * ps + c] = d[((b * h + y / 2) * w + x / 2) * C + c];
+}
+
+// adjoint of k_upsample (2x2 sums of channels [0, C) of the view), rounded, zeroed where y <= 0;
+// writes the dense coarse gradient [(b, y, x)][C]
+__global__ void k_upsample_bwd(const uint16_t *g, int ps, int C, int h, int w, int B, const uint16_t *y,
+                               uint16_t *gd)
+{
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long long)B * h * w * C) return;
+    const long long q = t / C;
+    const int c = (int)(t % C);
+    const long long b = q / ((long long)h * w);
+    const int yy = (int)((q / w) % h), xx = (int)(q % w);
+    const int W = 2 * w;
+    const long long f = b * 4LL * h * w + (long long)(2 * yy) * W + 2 * xx;
+    const uint16_t *s = g + c;
+    const float v = bf2f(s[f * ps]) + bf2f(s[(f + 1) * ps]) + bf2f(s[(f + W) * ps]) + bf2f(s[(f + W + 1) * ps]);
+    gd[t] = bf2f(y[t]) > 0.0f ? f2bf(v) : (uint16_t)0;
+}
+
+// head: o = w . d0 + b, phi0 = M tanh(o) (FP32 from the FP32 copy of d0, [px][C]); keeps o for the loss
+__global__ void k_head(const float *d0, int C, long long NP, const float *w, const float *b, float M, float *ob,
+                       float *phi)
+{
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= NP) return;
+    const float *x = d0 + t * C;
     float o = b[0];
-    for (int c = 0; c < C; c++) o = fmaf(w[c], x[(long long)c * HW], o);
+    for (int c = 0; c < C; c++) o = fmaf(w[c], x[c], o);
     ob[t] = o;
     phi[t] = M * tanhf(o);
 }
@@ -279,30 +422,28 @@ __global__ void k_head(const float *d0, int C, int HW, int B, const float *w, co
 //   loss = mean w (softplus(2 o) - 2 o q),   dloss/do = w (tanh o - tg) / N,
 // whose minimum is at tanh o = tg and whose gradient does not vanish where the
 // output saturates on the wrong side.  Head gradient partials per block;
-// gd0 = w_head dO (bf16, then relu-masked by the caller).
+// gd0 = w_head dO, zeroed where the stored d0 <= 0 (bf16, [px][C]).
 __global__ void __launch_bounds__(256) k_head_bwd(const float *ob, const float *target, float M, float pw,
-                                                  const float *d0, int C, int HW, int B, const float *w, uint16_t *gd0,
-                                                  float *part, int maxc)
+                                                  const float *d0, const uint16_t *d0b, int C, long long N,
+                                                  const float *w, uint16_t *gd0, float *part, int maxc)
 {
     __shared__ float red[256];
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long long N = (long long)B * HW;
     float loss = 0.0f, dO = 0.0f;
-    int bi = 0, p = 0;
     if (t < N) {
-        bi = (int)(t / HW); p = (int)(t % HW);
         const float tg = fminf(fmaxf(target[t] / M, -1.0f), 1.0f);
         const float q = tg > 0.0f ? pw : 1.0f;
         const float x = 2.0f * ob[t];
         const float sp = fmaxf(x, 0.0f) + log1pf(expf(-fabsf(x)));
         loss = q * (sp - x * 0.5f * (1.0f + tg));
         dO = q * (tanhf(ob[t]) - tg) / (float)N;
-        for (int c = 0; c < C; c++) gd0[(long long)bi * C * HW + (long long)c * HW + p] = f2bf(w[c] * dO);
+        for (int c = 0; c < C; c++)
+            gd0[t * C + c] = bf2f(d0b[t * C + c]) > 0.0f ? f2bf(w[c] * dO) : (uint16_t)0;
     }
     // partials: [0] loss, [1] db, [2 + c] dw_c
     for (int j = 0; j < C + 2 && j < maxc; j++) {
         float v = 0.0f;
-        if (t < N) v = j == 0 ? loss : (j == 1 ? dO : dO * d0[(long long)bi * C * HW + (long long)(j - 2) * HW + p]);
+        if (t < N) v = j == 0 ? loss : (j == 1 ? dO : dO * d0[t * C + (j - 2)]);
         red[threadIdx.x] = v;
         __syncthreads();
         for (int s = 128; s > 0; s >>= 1) {
@@ -325,9 +466,9 @@ __global__ void k_head_reduce(const float *part, int nb, int maxc, int C, float 
     else dw[j - 2] = s;
 }
 
-// Adam on FP32 master weights; bf16 copies for the convolutions
+// Adam on FP32 master weights
 __global__ void k_adam(float *p, const float *g, float *m, float *v, long long n, float lr, float b1, float b2,
-                       float eps, float c1, float c2, uint16_t *pb)
+                       float eps, float c1, float c2)
 {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n) return;
@@ -335,13 +476,6 @@ __global__ void k_adam(float *p, const float *g, float *m, float *v, long long n
     m[t] = b1 * m[t] + (1.0f - b1) * gg;
     v[t] = b2 * v[t] + (1.0f - b2) * gg * gg;
     p[t] -= lr * (m[t] / c1) / (sqrtf(v[t] / c2) + eps);
-    if (pb) pb[t] = f2bf(p[t]);
-}
-
-__global__ void k_f32_to_bf16(const float *x, uint16_t *y, long long n)
-{
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < n) y[t] = f2bf(x[t]);
 }
 
 inline unsigned nblk(long long n, int t = 256) { return (unsigned)((n + t - 1) / t); }
@@ -350,10 +484,15 @@ inline unsigned nblk(long long n, int t = 256) { return (unsigned)((n + t - 1) /
 
 // ==========================================================================
 struct NetLayer {
-    int IC, OC;
+    int IC, ICr, OC;                         // input channels as stored (padded), real input channels, outputs
     float *w32 = nullptr, *b32 = nullptr, *gw = nullptr, *gb = nullptr;
     float *mw = nullptr, *vw = nullptr, *mb = nullptr, *vb = nullptr;
-    uint16_t *wbf = nullptr, *wflip = nullptr;
+    uint16_t *wp = nullptr, *wt = nullptr;   // packed forward weights, data-gradient weights (null: none needed)
+};
+
+// a bf16 NHWC view: element (px, c) at p[px * ps + off + c]
+struct View {
+    uint16_t *p; int ps, off;
 };
 
 struct mgseg_net {
@@ -362,16 +501,16 @@ struct mgseg_net {
     std::vector<NetLayer> enc, dec;
     float *hw = nullptr, *hb = nullptr, *ghw = nullptr, *ghb = nullptr, *mhw = nullptr, *vhw = nullptr,
           *mhb = nullptr, *vhb = nullptr;
-    // activations for the current (B, H, W)
+    // activations for the current (B, H, W), NHWC
     int B = 0, H = 0, W = 0;
-    uint16_t *x0 = nullptr;                  // input, bf16
-    std::vector<uint16_t *> emid, dmid;      // first convolution's output of encoder / decoder block l
-    std::vector<uint16_t *> cat;             // cat[l]: [up(d_{l+1}) | e_l] at level l (l < depth-1)
-    std::vector<uint16_t *> pool;            // pool[l] = avgpool(e_l), level l+1
-    uint16_t *ebot = nullptr;                // e_{depth-1}
-    std::vector<uint16_t *> dact;            // d_l (l < depth-1)
-    float *d0f = nullptr, *ob = nullptr, *phi = nullptr;   // FP32 d_0, head output o, M tanh(o)
-    // gradients
+    uint16_t *x0 = nullptr;                  // input [px][16]
+    std::vector<uint16_t *> emid, dmid;      // first convolution's output of encoder / decoder block l [px][C_l]
+    std::vector<uint16_t *> cat;             // cat[l]: [px][C_{l+1} + C_l] = [up(d_{l+1}) | e_l] (l < depth-1)
+    std::vector<uint16_t *> pool;            // pool[l] = avgpool(e_l) at level l+1, [px][C_l]
+    uint16_t *ebot = nullptr;                // e_{depth-1} [px][C_{depth-1}]
+    std::vector<uint16_t *> dact;            // d_l [px][C_l] (l < depth-1)
+    float *d0f = nullptr, *ob = nullptr, *phi = nullptr;   // FP32 d_0 [px][C_0], head output o, M tanh(o)
+    // gradients (same shapes)
     std::vector<uint16_t *> gemid, gdmid, gcat, gpool, gdact;
     uint16_t *gebot = nullptr;
     float *part = nullptr, *partb = nullptr, *hpart = nullptr, *loss = nullptr;
@@ -380,6 +519,8 @@ struct mgseg_net {
 };
 
 namespace {
+
+constexpr long long PART_MAX = 16LL << 20;   // floats of weight-gradient partials
 
 int chan(const mgseg_net *n, int l) { return n->base << l; }
 
@@ -404,6 +545,15 @@ void free_acts(mgseg_net *n)
     n->B = n->H = n->W = 0;
 }
 
+// partial count of a weight gradient: at most 256, the pixel tile count, and PART_MAX floats in all
+int wgrad_parts(const NetLayer &L, int B, int h, int w)
+{
+    const long long tiles = (long long)B * ((h + TY - 1) / TY) * ((w + TX - 1) / TX);
+    const long long per = (long long)L.OC * 9 * L.IC;
+    const long long P = std::min<long long>(256, std::max<long long>(1, PART_MAX / per));
+    return (int)std::min(P, tiles);
+}
+
 bool ensure_acts(mgseg_net *n, int B, int H, int W)
 {
     if (n->B == B && n->H == H && n->W == W) return true;
@@ -411,42 +561,39 @@ bool ensure_acts(mgseg_net *n, int B, int H, int W)
     bool fail = false;
     auto &v = n->act_allocs;
     const int D = n->depth;
-    n->x0 = nalloc<uint16_t>(v, (size_t)B * 3 * H * W, fail);
+    n->x0 = nalloc<uint16_t>(v, (size_t)B * CIN0 * H * W, fail);
     for (int l = 0; l < D; l++) {
-        const size_t hw = (size_t)(H >> l) * (W >> l);
+        const size_t np = (size_t)B * (H >> l) * (W >> l);
         const int ce = chan(n, l);
-        n->emid.push_back(nalloc<uint16_t>(v, (size_t)B * ce * hw, fail));
-        n->gemid.push_back(nalloc<uint16_t>(v, (size_t)B * ce * hw, fail));
+        n->emid.push_back(nalloc<uint16_t>(v, np * ce, fail));
+        n->gemid.push_back(nalloc<uint16_t>(v, np * ce, fail));
         if (l == D - 1) break;
         const int cu = chan(n, l + 1);
-        n->cat.push_back(nalloc<uint16_t>(v, (size_t)B * (cu + ce) * hw, fail));
-        n->gcat.push_back(nalloc<uint16_t>(v, (size_t)B * (cu + ce) * hw, fail));
-        const size_t hw1 = (size_t)(H >> (l + 1)) * (W >> (l + 1));
-        n->pool.push_back(nalloc<uint16_t>(v, (size_t)B * ce * hw1, fail));
-        n->gpool.push_back(nalloc<uint16_t>(v, (size_t)B * ce * hw1, fail));
-        n->dmid.push_back(nalloc<uint16_t>(v, (size_t)B * ce * hw, fail));
-        n->gdmid.push_back(nalloc<uint16_t>(v, (size_t)B * ce * hw, fail));
-        n->dact.push_back(nalloc<uint16_t>(v, (size_t)B * ce * hw, fail));
-        n->gdact.push_back(nalloc<uint16_t>(v, (size_t)B * ce * hw, fail));
+        n->cat.push_back(nalloc<uint16_t>(v, np * (cu + ce), fail));
+        n->gcat.push_back(nalloc<uint16_t>(v, np * (cu + ce), fail));
+        n->pool.push_back(nalloc<uint16_t>(v, np / 4 * ce, fail));
+        n->gpool.push_back(nalloc<uint16_t>(v, np / 4 * ce, fail));
+        n->dmid.push_back(nalloc<uint16_t>(v, np * ce, fail));
+        n->gdmid.push_back(nalloc<uint16_t>(v, np * ce, fail));
+        n->dact.push_back(nalloc<uint16_t>(v, np * ce, fail));
+        n->gdact.push_back(nalloc<uint16_t>(v, np * ce, fail));
     }
-    const size_t hwb = (size_t)(H >> (D - 1)) * (W >> (D - 1));
-    n->ebot = nalloc<uint16_t>(v, (size_t)B * chan(n, D - 1) * hwb, fail);
-    n->gebot = nalloc<uint16_t>(v, (size_t)B * chan(n, D - 1) * hwb, fail);
+    const size_t npb = (size_t)B * (H >> (D - 1)) * (W >> (D - 1));
+    n->ebot = nalloc<uint16_t>(v, npb * chan(n, D - 1), fail);
+    n->gebot = nalloc<uint16_t>(v, npb * chan(n, D - 1), fail);
     n->d0f = nalloc<float>(v, (size_t)B * chan(n, 0) * H * W, fail);
     n->ob = nalloc<float>(v, (size_t)B * H * W, fail);
     n->phi = nalloc<float>(v, (size_t)B * H * W, fail);
-    // weight-gradient partials: chunks of 4096 pixels, the largest convolution of any level
     long long need = 0, needb = 0;
-    auto acc_need = [&](int IC, int OC, long long NP) {
-        const long long ch = (NP + 4095) / 4096;
-        need = std::max(need, ch * OC * IC * 9LL);
-        needb = std::max(needb, ch * OC);
-    };
     for (int l = 0; l < D; l++) {
-        const long long NP = (long long)B * (H >> l) * (W >> l);
-        acc_need(l == 0 ? 3 : chan(n, l - 1), chan(n, l), NP);
-        acc_need(chan(n, l), chan(n, l), NP);
-        if (l < D - 1) acc_need(chan(n, l + 1) + chan(n, l), chan(n, l), NP);
+        const int h = H >> l, w = W >> l;
+        auto acc_need = [&](const NetLayer &L) {
+            const int P = wgrad_parts(L, B, h, w);
+            need = std::max(need, (long long)P * L.OC * 9 * L.IC);
+            needb = std::max(needb, (long long)P * L.OC);
+        };
+        acc_need(n->enc[2 * l]); acc_need(n->enc[2 * l + 1]);
+        if (l < D - 1) { acc_need(n->dec[2 * l]); acc_need(n->dec[2 * l + 1]); }
     }
     n->part = nalloc<float>(v, (size_t)need, fail);
     n->partb = nalloc<float>(v, (size_t)needb, fail);
@@ -457,66 +604,51 @@ bool ensure_acts(mgseg_net *n, int B, int H, int W)
     return true;
 }
 
-void conv(hipStream_t s, const uint16_t *in, long long ibs, const uint16_t *W, const float *bias, int IC, int OC,
-          uint16_t *out, long long obs, int H, int Wd, int B, int relu, float *out32 = nullptr, long long o32bs = 0)
+void conv(hipStream_t s, View in, const uint16_t *Wk, const float *bias, int IC, int OC, View out, int H, int W, int B,
+          int relu, float *out32 = nullptr, const uint16_t *mask = nullptr, int mps = 0, int moff = 0)
 {
     ConvArgs A;
-    A.in = in; A.ibs = ibs; A.W = W; A.K = IC * 9; A.bias = bias; A.out = out; A.obs = obs;
-    A.out32 = out32; A.o32bs = o32bs; A.IC = IC; A.OC = OC; A.H = H; A.Wd = Wd; A.B = B; A.relu = relu;
-    const long long NP = (long long)B * H * Wd;
-    dim3 g((unsigned)((NP + 31) / 32), (unsigned)((OC + 31) / 32));
-    hipLaunchKernelGGL(k_conv3x3, g, dim3(256), 0, s, A);
+    A.in = in.p; A.ips = in.ps; A.ioff = in.off; A.Wk = Wk; A.bias = bias;
+    A.out = out.p; A.ops = out.ps; A.ooff = out.off; A.out32 = out32;
+    A.mask = mask; A.mps = mps; A.moff = moff;
+    A.IC = IC; A.OC = OC; A.H = H; A.W = W; A.relu = relu;
+    const unsigned tiles = (unsigned)(((H + TY - 1) / TY) * ((W + TX - 1) / TX));
+    dim3 g(tiles, (unsigned)((OC + OCB - 1) / OCB), (unsigned)B);
+    hipLaunchKernelGGL(k_conv, g, dim3(256), 0, s, A);
 }
 
-void wgrad(mgseg_net *n, hipStream_t s, const uint16_t *g, long long gbs, const uint16_t *x, long long xbs, int IC,
-           int OC, int H, int Wd, int B, float *dW, float *db)
+void wgrad(mgseg_net *n, hipStream_t s, View g, View x, NetLayer &L, int H, int W, int B)
 {
     WgradArgs A;
-    A.g = g; A.gbs = gbs; A.x = x; A.xbs = xbs; A.part = n->part; A.partb = n->partb;
-    A.IC = IC; A.OC = OC; A.H = H; A.Wd = Wd; A.B = B; A.chunk = 4096;
-    const long long NP = (long long)B * H * Wd;
-    const int nch = (int)((NP + 4095) / 4096);
-    const int K = IC * 9;
-    dim3 gr((unsigned)nch, (unsigned)((OC + 15) / 16), (unsigned)((K + 63) / 64));
+    A.g = g.p; A.gps = g.ps; A.goff = g.off; A.x = x.p; A.xps = x.ps; A.xoff = x.off;
+    A.part = n->part; A.partb = n->partb;
+    A.IC = L.IC; A.OC = L.OC; A.H = H; A.W = W; A.B = B;
+    A.P = wgrad_parts(L, B, H, W);
+    dim3 gr((unsigned)A.P, (unsigned)((L.OC + OCB - 1) / OCB), (unsigned)(L.IC / 16));
     hipLaunchKernelGGL(k_wgrad, gr, dim3(256), 0, s, A);
-    const long long tot = (long long)OC * K + OC;
-    hipLaunchKernelGGL(k_wgrad_reduce, dim3(nblk(tot)), dim3(256), 0, s, n->part, n->partb, nch, OC, K, dW, db);
-}
-
-void dgrad(hipStream_t s, NetLayer &L, const uint16_t *g, long long gbs, uint16_t *gx, long long gxbs, int H, int Wd,
-           int B)
-{
-    hipLaunchKernelGGL(k_flip_weights, dim3(nblk((long long)L.IC * L.OC * 9)), dim3(256), 0, s, L.wbf, L.IC, L.OC,
-                       L.wflip);
-    conv(s, g, gbs, L.wflip, nullptr, L.OC, L.IC, gx, gxbs, H, Wd, B, 0);
-}
-
-void relu_mask(hipStream_t s, uint16_t *g, long long gbs, const uint16_t *y, long long ybs, int C, long long hw, int B)
-{
-    hipLaunchKernelGGL(k_relu_mask, dim3(nblk((long long)B * C * hw)), dim3(256), 0, s, g, gbs, y, ybs, C, (int)hw, B);
+    const long long tot = (long long)L.OC * L.ICr * 9 + L.OC;
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3(nblk(tot)), dim3(256), 0, s, n->part, n->partb, A.P, L.OC, L.IC, L.ICr,
+                       L.gw, L.gb);
 }
 
 // forward of one block: mid = relu(conv_a(x)), y = relu(conv_b(mid))
-void block_fwd(hipStream_t s, NetLayer &a, NetLayer &b, const uint16_t *x, long long xbs, uint16_t *mid, uint16_t *y,
-               long long ybs, int h, int w, int B, float *y32 = nullptr)
+void block_fwd(hipStream_t s, NetLayer &a, NetLayer &b, View x, uint16_t *mid, View y, int h, int w, int B,
+               float *y32 = nullptr)
 {
-    const long long hw = (long long)h * w;
-    conv(s, x, xbs, a.wbf, a.b32, a.IC, a.OC, mid, (long long)a.OC * hw, h, w, B, 1);
-    conv(s, mid, (long long)a.OC * hw, b.wbf, b.b32, b.IC, b.OC, y, ybs, h, w, B, 1, y32, (long long)b.OC * hw);
+    conv(s, x, a.wp, a.b32, a.IC, a.OC, View{mid, a.OC, 0}, h, w, B, 1);
+    conv(s, View{mid, a.OC, 0}, b.wp, b.b32, b.IC, b.OC, y, h, w, B, 1, y32);
 }
 
-// backward of one block: gy (gradient of y, overwritten) -> weight gradients and, when gx is set, the gradient of x
-void block_bwd(mgseg_net *n, hipStream_t s, NetLayer &a, NetLayer &b, const uint16_t *x, long long xbs,
-               const uint16_t *mid, uint16_t *gmid, const uint16_t *y, uint16_t *gy, long long ybs, uint16_t *gx, int h,
-               int w, int B)
+// backward of one block, gy = gradient of y already zeroed where y <= 0: weight gradients, and the
+// gradient of x into gx when gx.p is set
+void block_bwd(mgseg_net *n, hipStream_t s, NetLayer &a, NetLayer &b, View x, uint16_t *mid, uint16_t *gmid, View gy,
+               View gx, int h, int w, int B)
 {
-    const long long hw = (long long)h * w, mbs = (long long)a.OC * hw;
-    relu_mask(s, gy, ybs, y, ybs, b.OC, hw, B);
-    wgrad(n, s, gy, ybs, mid, mbs, b.IC, b.OC, h, w, B, b.gw, b.gb);
-    dgrad(s, b, gy, ybs, gmid, mbs, h, w, B);
-    relu_mask(s, gmid, mbs, mid, mbs, a.OC, hw, B);
-    wgrad(n, s, gmid, mbs, x, xbs, a.IC, a.OC, h, w, B, a.gw, a.gb);
-    if (gx) dgrad(s, a, gmid, mbs, gx, xbs, h, w, B);
+    const View vm{mid, a.OC, 0}, vgm{gmid, a.OC, 0};
+    wgrad(n, s, gy, vm, b, h, w, B);
+    conv(s, gy, b.wt, nullptr, b.OC, b.IC, vgm, h, w, B, 0, nullptr, mid, a.OC, 0);
+    wgrad(n, s, vgm, x, a, h, w, B);
+    if (gx.p) conv(s, vgm, a.wt, nullptr, a.OC, a.ICr, gx, h, w, B, 0);
 }
 
 // SplitMix64 + Box-Muller: He-normal initial weights from the seed
@@ -533,38 +665,51 @@ struct Rng {
     double normal() { return std::sqrt(-2.0 * std::log(uni())) * std::cos(6.283185307179586 * uni()); }
 };
 
-bool make_layer(mgseg_net *n, NetLayer &L, int IC, int OC, Rng &rng)
+void pack(hipStream_t s, NetLayer &L)
+{
+    const long long nt = std::max((long long)L.OC * 9 * L.IC, (long long)L.ICr * 9 * L.OC);
+    hipLaunchKernelGGL(k_pack_weights, dim3(nblk(nt)), dim3(256), 0, s, L.w32, L.OC, L.ICr, L.IC, L.wp, L.wt);
+}
+
+bool make_layer(mgseg_net *n, NetLayer &L, int ICr, int IC, int OC, bool need_dgrad, Rng &rng)
 {
     bool fail = false;
     auto &v = n->par_allocs;
-    const size_t nw = (size_t)OC * IC * 9;
-    L.IC = IC; L.OC = OC;
+    const size_t nw = (size_t)OC * ICr * 9;
+    L.IC = IC; L.ICr = ICr; L.OC = OC;
     L.w32 = nalloc<float>(v, nw, fail); L.b32 = nalloc<float>(v, OC, fail);
     L.gw = nalloc<float>(v, nw, fail); L.gb = nalloc<float>(v, OC, fail);
     L.mw = nalloc<float>(v, nw, fail); L.vw = nalloc<float>(v, nw, fail);
     L.mb = nalloc<float>(v, OC, fail); L.vb = nalloc<float>(v, OC, fail);
-    L.wbf = nalloc<uint16_t>(v, nw, fail); L.wflip = nalloc<uint16_t>(v, nw, fail);
+    L.wp = nalloc<uint16_t>(v, (size_t)OC * 9 * IC, fail);
+    L.wt = need_dgrad ? nalloc<uint16_t>(v, nw, fail) : nullptr;
     if (fail) return false;
     std::vector<float> w(nw);
-    const double sd = std::sqrt(2.0 / (9.0 * IC));
+    const double sd = std::sqrt(2.0 / (9.0 * ICr));
     for (auto &x : w) x = (float)(sd * rng.normal());
     (void)hipMemcpy(L.w32, w.data(), nw * sizeof(float), hipMemcpyHostToDevice);
-    hipLaunchKernelGGL(k_f32_to_bf16, dim3(nblk((long long)nw)), dim3(256), 0, 0, L.w32, L.wbf, (long long)nw);
+    pack(0, L);
     return true;
 }
 
-// parameters in a fixed order: the convolutions enc[0..2D-1], then dec[0..2D-3], each w (OC*IC*9) then b (OC);
+// parameters in a fixed order: the convolutions enc[0..2D-1], then dec[0..2D-3], each w (OC*ICr*9) then b (OC);
 // head w (C0), head b (1)
 template <class F>
 void for_params(mgseg_net *n, F f)
 {
     for (auto *v : {&n->enc, &n->dec})
         for (auto &L : *v) {
-            f(L.w32, L.gw, L.mw, L.vw, L.wbf, (long long)L.OC * L.IC * 9);
-            f(L.b32, L.gb, L.mb, L.vb, (uint16_t *)nullptr, (long long)L.OC);
+            f(L.w32, L.gw, L.mw, L.vw, (long long)L.OC * L.ICr * 9);
+            f(L.b32, L.gb, L.mb, L.vb, (long long)L.OC);
         }
-    f(n->hw, n->ghw, n->mhw, n->vhw, (uint16_t *)nullptr, (long long)chan(n, 0));
-    f(n->hb, n->ghb, n->mhb, n->vhb, (uint16_t *)nullptr, 1LL);
+    f(n->hw, n->ghw, n->mhw, n->vhw, (long long)chan(n, 0));
+    f(n->hb, n->ghb, n->mhb, n->vhb, 1LL);
+}
+
+void pack_all(mgseg_net *n, hipStream_t s)
+{
+    for (auto *v : {&n->enc, &n->dec})
+        for (auto &L : *v) pack(s, L);
 }
 
 }  // namespace
@@ -583,7 +728,8 @@ mgseg_status mgseg_net_create(int base_channels, int depth, uint64_t seed, mgseg
 {
     if (!out) return MGSEG_E_ARG;
     *out = nullptr;
-    if (base_channels < 1 || base_channels > 256 || depth < 2 || depth > 6) return MGSEG_E_ARG;
+    if (base_channels < 16 || base_channels > 256 || base_channels % 16 || depth < 2 || depth > 6) return MGSEG_E_ARG;
+    if ((base_channels << (depth - 1)) > 512) return MGSEG_E_ARG;
     mgseg_net *n = new (std::nothrow) mgseg_net();
     if (!n) return MGSEG_E_NOMEM;
     n->base = base_channels; n->depth = depth;
@@ -592,12 +738,14 @@ mgseg_status mgseg_net_create(int base_channels, int depth, uint64_t seed, mgseg
     n->dec.resize(2 * (depth - 1));
     bool ok = true;
     for (int l = 0; l < depth && ok; l++) {
-        ok = make_layer(n, n->enc[2 * l], l == 0 ? 3 : chan(n, l - 1), chan(n, l), rng);
-        if (ok) ok = make_layer(n, n->enc[2 * l + 1], chan(n, l), chan(n, l), rng);
+        const int ic = l == 0 ? 3 : chan(n, l - 1);
+        ok = make_layer(n, n->enc[2 * l], ic, l == 0 ? CIN0 : ic, chan(n, l), l > 0, rng);
+        if (ok) ok = make_layer(n, n->enc[2 * l + 1], chan(n, l), chan(n, l), chan(n, l), true, rng);
     }
     for (int l = 0; l < depth - 1 && ok; l++) {
-        ok = make_layer(n, n->dec[2 * l], chan(n, l + 1) + chan(n, l), chan(n, l), rng);
-        if (ok) ok = make_layer(n, n->dec[2 * l + 1], chan(n, l), chan(n, l), rng);
+        const int ic = chan(n, l + 1) + chan(n, l);
+        ok = make_layer(n, n->dec[2 * l], ic, ic, chan(n, l), true, rng);
+        if (ok) ok = make_layer(n, n->dec[2 * l + 1], chan(n, l), chan(n, l), chan(n, l), true, rng);
     }
     bool fail = !ok;
     auto &v = n->par_allocs;
@@ -623,50 +771,33 @@ mgseg_status mgseg_net_forward(mgseg_net *n, const float *in_dev, int B, int H, 
     if (H % (1 << (D - 1)) || W % (1 << (D - 1))) return MGSEG_E_SHAPE;
     if (!ensure_acts(n, B, H, W)) return MGSEG_E_NOMEM;
     hipStream_t s = (hipStream_t)stream;
-    const long long HW0 = (long long)H * W;
-    hipLaunchKernelGGL(k_to_bf16, dim3(nblk((long long)B * 3 * HW0)), dim3(256), 0, s, in_dev, n->x0,
-                       (long long)B * 3 * HW0);
+    const long long NP0 = (long long)B * H * W;
+    hipLaunchKernelGGL(k_pack_input, dim3(nblk(NP0)), dim3(256), 0, s, in_dev, (long long)H * W, B, n->x0);
     // encoder
-    const uint16_t *cur = n->x0;
-    long long curbs = 3 * HW0;
+    View cur{n->x0, CIN0, 0};
     for (int l = 0; l < D; l++) {
         const int h = H >> l, w = W >> l, ce = chan(n, l);
-        const long long hw = (long long)h * w;
-        uint16_t *outp;
-        long long obs;
+        const View e = l < D - 1 ? View{n->cat[l], chan(n, l + 1) + ce, chan(n, l + 1)} : View{n->ebot, ce, 0};
+        block_fwd(s, n->enc[2 * l], n->enc[2 * l + 1], cur, n->emid[l], e, h, w, B);
         if (l < D - 1) {
-            const int cu = chan(n, l + 1);
-            outp = n->cat[l] + (long long)cu * hw;     // e_l in the skip slice of cat[l]
-            obs = (long long)(cu + ce) * hw;
-        } else {
-            outp = n->ebot;
-            obs = (long long)ce * hw;
-        }
-        block_fwd(s, n->enc[2 * l], n->enc[2 * l + 1], cur, curbs, n->emid[l], outp, obs, h, w, B);
-        if (l < D - 1) {
-            hipLaunchKernelGGL(k_avgpool, dim3(nblk((long long)B * ce * hw / 4)), dim3(256), 0, s, outp, obs,
-                               n->pool[l], (long long)ce * hw / 4, ce, h, w, B);
-            cur = n->pool[l];
-            curbs = (long long)ce * hw / 4;
+            hipLaunchKernelGGL(k_avgpool, dim3(nblk((long long)B * (h / 2) * (w / 2) * ce)), dim3(256), 0, s, e.p,
+                               e.ps, e.off, ce, h / 2, w / 2, B, n->pool[l]);
+            cur = View{n->pool[l], ce, 0};
         }
     }
     // decoder
     const uint16_t *dn = n->ebot;
-    long long dnbs = (long long)chan(n, D - 1) * (H >> (D - 1)) * (W >> (D - 1));
     for (int l = D - 2; l >= 0; l--) {
         const int h = H >> l, w = W >> l;
-        const long long hw = (long long)h * w;
         const int cu = chan(n, l + 1), ce = chan(n, l);
-        const long long cbs = (long long)(cu + ce) * hw;
-        hipLaunchKernelGGL(k_upsample, dim3(nblk((long long)B * cu * hw)), dim3(256), 0, s, dn, dnbs, n->cat[l], cbs,
-                           cu, h / 2, w / 2, B);
-        block_fwd(s, n->dec[2 * l], n->dec[2 * l + 1], n->cat[l], cbs, n->dmid[l], n->dact[l], (long long)ce * hw, h,
-                  w, B, l == 0 ? n->d0f : nullptr);
+        hipLaunchKernelGGL(k_upsample, dim3(nblk((long long)B * h * w * cu)), dim3(256), 0, s, dn, cu, h / 2, w / 2, B,
+                           n->cat[l], cu + ce);
+        block_fwd(s, n->dec[2 * l], n->dec[2 * l + 1], View{n->cat[l], cu + ce, 0}, n->dmid[l],
+                  View{n->dact[l], ce, 0}, h, w, B, l == 0 ? n->d0f : nullptr);
         dn = n->dact[l];
-        dnbs = (long long)ce * hw;
     }
-    hipLaunchKernelGGL(k_head, dim3(nblk((long long)B * HW0)), dim3(256), 0, s, n->d0f, chan(n, 0), (int)HW0, B, n->hw,
-                       n->hb, (float)M, n->ob, phi0_dev ? phi0_dev : n->phi);
+    hipLaunchKernelGGL(k_head, dim3(nblk(NP0)), dim3(256), 0, s, n->d0f, chan(n, 0), NP0, n->hw, n->hb, (float)M,
+                       n->ob, phi0_dev ? phi0_dev : n->phi);
     if (hipGetLastError() != hipSuccess) return MGSEG_E_HIP;
     return MGSEG_OK;
 }
@@ -678,48 +809,42 @@ mgseg_status mgseg_net_backward(mgseg_net *n, const float *target_dev, double M,
     if (n->B == 0) return MGSEG_E_STATE;
     hipStream_t s = (hipStream_t)stream;
     const int D = n->depth, B = n->B, H = n->H, W = n->W, C0 = chan(n, 0);
-    const long long HW0 = (long long)H * W;
-    const unsigned nb = nblk((long long)B * HW0);
+    const long long NP0 = (long long)B * H * W;
+    const unsigned nb = nblk(NP0);
     const int maxc = C0 + 2;
-    // head and loss; gradient of d_0 -> gdact[0]
+    // head and loss; gradient of d_0 (masked) -> gdact[0]
     hipLaunchKernelGGL(k_head_bwd, dim3(nb), dim3(256), 0, s, n->ob, target_dev, (float)M, (float)pos_weight, n->d0f,
-                       C0, (int)HW0, B,
-                       n->hw, n->gdact[0], n->hpart, maxc);
+                       n->dact[0], C0, NP0, n->hw, n->gdact[0], n->hpart, maxc);
     hipLaunchKernelGGL(k_head_reduce, dim3(1), dim3(256), 0, s, n->hpart, (int)nb, maxc, C0, n->loss, n->ghb, n->ghw,
-                       (long long)B * HW0);
+                       NP0);
     // decoder, level 0 first
     for (int l = 0; l <= D - 2; l++) {
         const int h = H >> l, w = W >> l;
-        const long long hw = (long long)h * w;
         const int cu = chan(n, l + 1), ce = chan(n, l);
-        const long long cbs = (long long)(cu + ce) * hw;
-        block_bwd(n, s, n->dec[2 * l], n->dec[2 * l + 1], n->cat[l], cbs, n->dmid[l], n->gdmid[l], n->dact[l],
-                  n->gdact[l], (long long)ce * hw, n->gcat[l], h, w, B);
-        // up-sampled part of the input -> gradient of the level below's d (or of e_bottom)
+        block_bwd(n, s, n->dec[2 * l], n->dec[2 * l + 1], View{n->cat[l], cu + ce, 0}, n->dmid[l], n->gdmid[l],
+                  View{n->gdact[l], ce, 0}, View{n->gcat[l], cu + ce, 0}, h, w, B);
+        // up-sampled part of the input -> gradient of the level below's d (or of e_bottom), masked by it
         uint16_t *gdn = (l + 1 <= D - 2) ? n->gdact[l + 1] : n->gebot;
-        hipLaunchKernelGGL(k_upsample_bwd, dim3(nblk((long long)B * cu * hw / 4)), dim3(256), 0, s, n->gcat[l], cbs,
-                           gdn, (long long)cu * hw / 4, cu, h / 2, w / 2, B);
+        const uint16_t *ydn = (l + 1 <= D - 2) ? n->dact[l + 1] : n->ebot;
+        hipLaunchKernelGGL(k_upsample_bwd, dim3(nblk((long long)B * (h / 2) * (w / 2) * cu)), dim3(256), 0, s,
+                           n->gcat[l], cu + ce, cu, h / 2, w / 2, B, ydn, gdn);
     }
     // encoder, bottom up
     for (int l = D - 1; l >= 0; l--) {
         const int h = H >> l, w = W >> l, ce = chan(n, l);
-        const long long hw = (long long)h * w;
-        uint16_t *g, *y;
-        long long gbs;
+        View g;
         if (l == D - 1) {
-            g = n->gebot; y = n->ebot; gbs = (long long)ce * hw;
+            g = View{n->gebot, ce, 0};
         } else {
             const int cu = chan(n, l + 1);
-            gbs = (long long)(cu + ce) * hw;
-            g = n->gcat[l] + (long long)cu * hw; y = n->cat[l] + (long long)cu * hw;
-            // pooled path: g_e += avgpool^T(g_pool)
-            hipLaunchKernelGGL(k_avgpool_bwd, dim3(nblk((long long)B * ce * hw)), dim3(256), 0, s, n->gpool[l],
-                               (long long)ce * hw / 4, g, gbs, ce, h, w, B);
+            g = View{n->gcat[l], cu + ce, cu};
+            // pooled path: g_e += avgpool^T(g_pool), then the ReLU mask of e
+            hipLaunchKernelGGL(k_avgpool_bwd, dim3(nblk((long long)B * h * w * ce)), dim3(256), 0, s, n->gpool[l], ce,
+                               h / 2, w / 2, B, g.p, g.ps, g.off, n->cat[l], cu + ce, cu);
         }
-        const uint16_t *x = l == 0 ? n->x0 : n->pool[l - 1];
-        const long long xbs = l == 0 ? 3 * hw : (long long)chan(n, l - 1) * hw;
-        block_bwd(n, s, n->enc[2 * l], n->enc[2 * l + 1], x, xbs, n->emid[l], n->gemid[l], y, g, gbs,
-                  l > 0 ? n->gpool[l - 1] : nullptr, h, w, B);
+        const View x = l == 0 ? View{n->x0, CIN0, 0} : View{n->pool[l - 1], chan(n, l - 1), 0};
+        const View gx = l > 0 ? View{n->gpool[l - 1], chan(n, l - 1), 0} : View{nullptr, 0, 0};
+        block_bwd(n, s, n->enc[2 * l], n->enc[2 * l + 1], x, n->emid[l], n->gemid[l], g, gx, h, w, B);
     }
     if (hipGetLastError() != hipSuccess) return MGSEG_E_HIP;
     if (loss_host) {
@@ -738,10 +863,11 @@ mgseg_status mgseg_net_adam_step(mgseg_net *n, double lr, double b1, double b2, 
     hipStream_t s = (hipStream_t)stream;
     n->steps++;
     const float c1 = (float)(1.0 - std::pow(b1, n->steps)), c2 = (float)(1.0 - std::pow(b2, n->steps));
-    for_params(n, [&](float *p, float *g, float *m, float *v, uint16_t *pb, long long cnt) {
+    for_params(n, [&](float *p, float *g, float *m, float *v, long long cnt) {
         hipLaunchKernelGGL(k_adam, dim3(nblk(cnt)), dim3(256), 0, s, p, g, m, v, cnt, (float)lr, (float)b1, (float)b2,
-                           (float)eps, c1, c2, pb);
+                           (float)eps, c1, c2);
     });
+    pack_all(n, s);
     return hipGetLastError() == hipSuccess ? MGSEG_OK : MGSEG_E_HIP;
 }
 
@@ -749,7 +875,7 @@ mgseg_status mgseg_net_param_count(mgseg_net *n, long long *count)
 {
     if (!n || !count) return MGSEG_E_ARG;
     long long c = 0;
-    for_params(n, [&](float *, float *, float *, float *, uint16_t *, long long k) { c += k; });
+    for_params(n, [&](float *, float *, float *, float *, long long k) { c += k; });
     *count = c;
     return MGSEG_OK;
 }
@@ -760,7 +886,7 @@ mgseg_status mgseg_net_get_params(mgseg_net *n, float *host, float *grad_host)
     if (hipDeviceSynchronize() != hipSuccess) return MGSEG_E_HIP;
     long long off = 0;
     bool ok = true;
-    for_params(n, [&](float *p, float *g, float *, float *, uint16_t *, long long k) {
+    for_params(n, [&](float *p, float *g, float *, float *, long long k) {
         if (host) ok &= hipMemcpy(host + off, p, k * sizeof(float), hipMemcpyDeviceToHost) == hipSuccess;
         if (grad_host) ok &= hipMemcpy(grad_host + off, g, k * sizeof(float), hipMemcpyDeviceToHost) == hipSuccess;
         off += k;
@@ -774,12 +900,12 @@ mgseg_status mgseg_net_set_params(mgseg_net *n, const float *host)
     if (hipDeviceSynchronize() != hipSuccess) return MGSEG_E_HIP;
     long long off = 0;
     bool ok = true;
-    for_params(n, [&](float *p, float *, float *m, float *v, uint16_t *pb, long long k) {
+    for_params(n, [&](float *p, float *, float *m, float *v, long long k) {
         ok &= hipMemcpy(p, host + off, k * sizeof(float), hipMemcpyHostToDevice) == hipSuccess;
         ok &= hipMemset(m, 0, k * sizeof(float)) == hipSuccess && hipMemset(v, 0, k * sizeof(float)) == hipSuccess;
-        if (pb) hipLaunchKernelGGL(k_f32_to_bf16, dim3(nblk(k)), dim3(256), 0, 0, p, pb, k);
         off += k;
     });
+    pack_all(n, 0);
     n->steps = 0;
     return ok && hipDeviceSynchronize() == hipSuccess ? MGSEG_OK : MGSEG_E_HIP;
 }
