@@ -282,7 +282,9 @@ void mgseg_net_destroy(mgseg_net *n);
 /* The network input of a context: out_dev[3][n][m] = (z, d, marker mask). */
 mgseg_status mgseg_ctx_features(mgseg_ctx *c, float *out_dev);
 
-/* Forward pass on the context's features; the result becomes the initial
+/* Forward pass on the context's features, phi0 = scale M tanh(o)
+ * (0 < scale <= 1, else MGSEG_E_ARG: a smaller amplitude leaves the
+ * interfaces softer for the V-cycle to move); the result becomes the initial
  * level set (as mgseg_set_phi0) only if it is positive at the cell of every
  * marker: a selective segmentation contains its markers, and a network
  * output that leaves one out (the empty level set phi = -M is a stationary
@@ -291,7 +293,7 @@ mgseg_status mgseg_ctx_features(mgseg_ctx *c, float *out_dev);
  * (mgseg_reset_phi0), so the solve always starts from a valid guess.
  * *accepted_out (may be null): 1 if the network's phi0 was taken.  Allocates
  * the features and the network output (4 n m floats) for the call. */
-mgseg_status mgseg_predict_phi0(mgseg_ctx *c, mgseg_net *n, int *accepted_out);
+mgseg_status mgseg_predict_phi0(mgseg_ctx *c, mgseg_net *n, double scale, int *accepted_out);
 
 #ifdef __cplusplus
 }

@@ -1243,9 +1243,9 @@ mgseg_status mgseg_reset_phi0(mgseg_ctx *c)
     return MGSEG_OK;
 }
 
-mgseg_status mgseg_predict_phi0(mgseg_ctx *c, mgseg_net *net, int *accepted_out)
+mgseg_status mgseg_predict_phi0(mgseg_ctx *c, mgseg_net *net, double scale, int *accepted_out)
 {
-    if (!c || !net) return MGSEG_E_ARG;
+    if (!c || !net || !(scale > 0.0 && scale <= 1.0)) return MGSEG_E_ARG;
     const size_t N = (size_t)c->n * c->m;
     float *feat = nullptr, *phi = nullptr;
     if (hipMalloc(&feat, sizeof(float) * 3 * N) != hipSuccess || hipMalloc(&phi, sizeof(float) * N) != hipSuccess) {
@@ -1254,7 +1254,7 @@ mgseg_status mgseg_predict_phi0(mgseg_ctx *c, mgseg_net *net, int *accepted_out)
         return MGSEG_E_NOMEM;
     }
     mgseg_status st = mgseg_ctx_features(c, feat);
-    if (st == MGSEG_OK) st = mgseg_net_forward(net, feat, 1, c->n, c->m, c->p.M, phi, c->s);
+    if (st == MGSEG_OK) st = mgseg_net_forward(net, feat, 1, c->n, c->m, scale * c->p.M, phi, c->s);
     int inside = 0;
     if (st == MGSEG_OK) {
         hipLaunchKernelGGL(k_markers_inside, dim3(1), dim3(256), 0, c->s, phi, c->n, c->m, c->mk_d, c->k, c->flags + 1);

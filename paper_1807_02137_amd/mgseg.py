@@ -127,7 +127,7 @@ def lib():
         L.mgseg_net_destroy.argtypes = [vp]
         L.mgseg_net_destroy.restype = None
         L.mgseg_ctx_features.argtypes = [vp, vp]
-        L.mgseg_predict_phi0.argtypes = [vp, vp, ip]
+        L.mgseg_predict_phi0.argtypes = [vp, vp, C.c_double, ip]
         L.mgseg_reset_phi0.argtypes = [vp]
         for name in ("mgseg_setup", "mgseg_set_phi0", "mgseg_vcycle", "mgseg_solve", "mgseg_get_phi",
                      "mgseg_get_mask", "mgseg_get_stats", "mgseg_level_shape", "mgseg_debug_get",
@@ -223,12 +223,12 @@ class Solver:
         _check(self.L.mgseg_ctx_features(self.ctx, C.c_void_p(out.data_ptr())), "mgseg_ctx_features")
         return out
 
-    def predict_phi0(self, net: "Net") -> bool:
-        """Start the solve from the network's phi0 for this image if it holds
-        every marker, else from the marker-based phi0; True if the network's
-        phi0 was taken."""
+    def predict_phi0(self, net: "Net", scale: float = 1.0) -> bool:
+        """Start the solve from the network's phi0 (times scale) for this image
+        if it holds every marker, else from the marker-based phi0; True if the
+        network's phi0 was taken."""
         acc = C.c_int()
-        _check(self.L.mgseg_predict_phi0(self.ctx, net.h, C.byref(acc)), "mgseg_predict_phi0")
+        _check(self.L.mgseg_predict_phi0(self.ctx, net.h, scale, C.byref(acc)), "mgseg_predict_phi0")
         return bool(acc.value)
 
     def reset_phi0(self):

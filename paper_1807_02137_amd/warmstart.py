@@ -83,15 +83,18 @@ def object_weight(data: Dataset) -> float:
     return float(np.sqrt((1 - f) / f))
 
 
-def train(net: mgseg.Net, data: Dataset, M: float, epochs=10, batch=8, lr=1e-3, seed=0, pos_weight=None,
-          log=None):
-    """Adam on mean(w (tanh(o) - phi / M)^2) (w = pos_weight on object
-    pixels, default object_weight(data)) over shuffled mini-batches; returns
-    the mean loss of every epoch."""
+def train(net: mgseg.Net, data: Dataset, M: float, epochs=10, batch=8, lr=1e-3, lr_final=None, seed=0,
+          pos_weight=None, log=None):
+    """Adam on the network's weighted cross-entropy against phi / M (object
+    weight pos_weight, default object_weight(data)) over shuffled
+    mini-batches, the step size falling from lr to lr_final (default lr / 20)
+    along a half cosine; returns the mean loss of every epoch."""
     g = torch.Generator().manual_seed(seed)
     N = data.feats.shape[0]
     pw = object_weight(data) if pos_weight is None else pos_weight
-    hist = []
+    lr_final = lr / 20 if lr_final is None else lr_final
+    steps = max(1, epochs * (N // batch))
+    hist, k = [], 0
     for ep in range(epochs):
         perm = torch.randperm(N, generator=g)
         tot, cnt = 0.0, 0
@@ -101,7 +104,8 @@ def train(net: mgseg.Net, data: Dataset, M: float, epochs=10, batch=8, lr=1e-3, 
             t = data.phi.index_select(0, idx)
             net.forward(x, M)
             tot += net.backward(t, M, pw)
-            net.adam_step(lr)
+            net.adam_step(lr_final + 0.5 * (lr - lr_final) * (1 + np.cos(np.pi * k / steps)))
+            k += 1
             cnt += 1
         hist.append(tot / max(cnt, 1))
         if log:
@@ -122,10 +126,10 @@ def _timed_solve(s: mgseg.Solver, tol_abs, max_cycles, prep=None):
                 converged=bool(ok))
 
 
-def evaluate(net: mgseg.Net | None, instances, params: mgseg.Params, tol=1e-6, max_cycles=80, zero=True):
+def evaluate(net: mgseg.Net | None, instances, params: mgseg.Params, tol=1e-6, max_cycles=80, zero=True, scale=1.0):
     """Per instance: the marker-based phi0 (the method without the network),
-    the network's phi0 (taken only if it holds every marker, else the marker
-    start) and (if `zero`) phi0 = 0, each solved to the same absolute
+    the network's phi0 times `scale` (taken only if it holds every marker,
+    else the marker start) and (if `zero`) phi0 = 0, each solved to the same absolute
     residual; also the share of pixels whose final masks differ from the
     marker-based solve's (a start that reaches the residual at another fixed
     point, e.g. the empty level set, has not reached equal accuracy)."""
@@ -139,7 +143,7 @@ def evaluate(net: mgseg.Net | None, instances, params: mgseg.Params, tol=1e-6, m
         ref_mask = s.mask()
         if net is not None:
             acc = []
-            row["learned"] = _timed_solve(s, tol_abs, max_cycles, prep=lambda: acc.append(s.predict_phi0(net)))
+            row["learned"] = _timed_solve(s, tol_abs, max_cycles, prep=lambda: acc.append(s.predict_phi0(net, scale)))
             row["learned"]["accepted"] = acc[0]
             row["learned"]["mask_diff"] = float((s.mask() != ref_mask).float().mean())
         if zero:
@@ -167,3 +171,94 @@ def summarize(rows):
         if "accepted" in rs[0]:
             summ[key]["accepted"] = int(sum(r["accepted"] for r in rs))
     return summ
+
+
+def choose_scale(net: mgseg.Net, instances, params: mgseg.Params, scales=(1.0, 0.5, 0.25), log=None):
+    """The amplitude of the network's phi0 with the fewest mean cycles among
+    those that reach the marker start's fixed point on at least as many of
+    `instances` (a validation split, never the held-out set) as scale 1."""
+    stats = {}
+    for sc in scales:
+        summ = summarize(evaluate(net, instances, params, zero=False, scale=sc))["learned"]
+        stats[sc] = summ
+        if log:
+            log(f"scale {sc}: {summ['cycles']:.1f} cycles, {summ['same_fixed_point']}/{summ['count']} at the "
+                f"marker start's fixed point")
+    floor = stats[scales[0]]["same_fixed_point"]
+    ok = [sc for sc in scales if stats[sc]["same_fixed_point"] >= floor]
+    return min(ok, key=lambda sc: stats[sc]["cycles"])
+
+
+def save(net: mgseg.Net, path, scale=1.0):
+    """The network's parameters (library order), its shape and the amplitude
+    of its phi0, as .npz."""
+    p, _ = net.params()
+    np.savez(path, params=p, base=net.base, depth=net.depth, scale=scale)
+
+
+def load(path):
+    """(network, amplitude) saved by save()."""
+    d = np.load(path)
+    net = mgseg.Net(int(d["base"]), int(d["depth"]))
+    net.set_params(d["params"])
+    return net, float(d["scale"]) if "scale" in d else 1.0
+
+
+def main(argv=None):
+    import argparse
+    import json
+
+    ap = argparse.ArgumentParser(description="train / evaluate the warm-start network on 4-20-shape images")
+    ap.add_argument("--train", type=int, default=0, help="training instances (0: load --weights)")
+    ap.add_argument("--eval", type=int, default=16, help="held-out instances")
+    ap.add_argument("--n", type=int, default=512, help="image side")
+    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--batch", type=int, default=8)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--base", type=int, default=32)
+    ap.add_argument("--depth", type=int, default=4)
+    ap.add_argument("--weights", default=None, help="where to save (with --train) or load the parameters")
+    ap.add_argument("--workers", type=int, default=16)
+    ap.add_argument("--json", default=None, help="write the evaluation summary here")
+    ap.add_argument("--val", type=int, default=0, help="validation instances for the amplitude (0: keep it)")
+    a = ap.parse_args(argv)
+
+    def log(*x):
+        print(*x, flush=True)
+
+    t0 = time.perf_counter()
+    tr = generate(TRAIN_SEEDS[:a.train], a.n, a.workers) if a.train else []
+    he = generate(HELDOUT_SEEDS[:a.eval], a.n, a.workers) if a.eval else []
+    log(f"drew {len(tr)} training and {len(he)} held-out instances in {time.perf_counter() - t0:.1f} s")
+    params = mgseg.Params(levels=synth.levels_for(a.n, a.n))
+    if a.train:
+        t0 = time.perf_counter()
+        data = solve_targets(tr, params, log=log)
+        log(f"targets: {len(data.seeds)} kept, {len(data.dropped)} not converged, "
+            f"{np.mean(data.cycles):.1f} cycles on average, {time.perf_counter() - t0:.1f} s")
+        net = mgseg.Net(a.base, a.depth, 1)
+        t0 = time.perf_counter()
+        train(net, data, params.M, a.epochs, a.batch, a.lr, log=log)
+        torch.cuda.synchronize()
+        log(f"trained {a.epochs} epochs in {time.perf_counter() - t0:.1f} s")
+        del data
+        scale = 1.0
+    else:
+        net, scale = load(a.weights)
+    if a.val:
+        va = generate(TRAIN_SEEDS[len(TRAIN_SEEDS) - a.val:], a.n, a.workers)
+        scale = choose_scale(net, va, params, log=log)
+        log(f"amplitude {scale}")
+    if a.weights and (a.train or a.val):
+        save(net, a.weights, scale)
+    if he:
+        rows = evaluate(net, he, params, scale=scale)
+        summ = summarize(rows)
+        log(json.dumps(summ))
+        if a.json:
+            with open(a.json, "w") as f:
+                json.dump(dict(summary=summ, rows=rows), f, indent=1)
+
+
+if __name__ == "__main__":
+    main()

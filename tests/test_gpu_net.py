@@ -220,6 +220,10 @@ def test_predicted_phi0_is_taken_when_it_holds_the_markers():
     assert (phi > 0).all()
     assert s.predict_phi0(net)
     assert np.abs(s.get("phi64") - phi).max() <= 1e-6
+    assert s.predict_phi0(net, 0.25)
+    assert np.abs(s.get("phi64") - 0.25 * phi).max() <= 1e-6
+    with pytest.raises(mgseg.MgsegError):
+        s.predict_phi0(net, 0.0)
     assert s.stats()["cycles"] == 0
     net.close()
     s.close()

@@ -1,0 +1,56 @@
+"""What the trained warm-start network gains over the method without it.
+
+The shipped network (paper_1807_02137_amd/weights/warmstart_512_b32_d4.npz:
+base 32, depth 4, trained by the library's own kernels on 2048 seeded
+512x512 images of 4-20 shapes, amplitude chosen on a validation split) is
+evaluated on held-out seeds the training never saw.  Every start is solved
+by the same FAS V-cycle to the same absolute residual (1e-6 times the
+marker-based start's), so the comparison is at equal accuracy; a start that
+reaches that residual at another fixed point (another segmentation) is
+counted as such.  The quantities are cycle counts, deterministic for given
+seeds; wall times are printed, not asserted.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1807_02137_amd import mgseg, synth, warmstart  # noqa: E402
+
+WEIGHTS = os.path.join(os.path.dirname(warmstart.__file__), "weights", "warmstart_512_b32_d4.npz")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def test_learned_start_needs_fewer_cycles_at_equal_accuracy():
+    seeds = warmstart.HELDOUT_SEEDS[:12]
+    say(f"case warm-start gain, held-out seeds {seeds.start}..{seeds.stop - 1}")
+    net, scale = warmstart.load(WEIGHTS)
+    assert 0 < scale <= 1
+    inst = warmstart.generate(seeds, 512, workers=1)
+    rows = warmstart.evaluate(net, inst, mgseg.Params(levels=synth.levels_for(512, 512)), zero=False, scale=scale)
+    for r in rows:
+        m, lr = r["marker"], r["learned"]
+        say(f"  {r['seed']}: marker {m['cycles']:2d} cycles {m['ms']:6.1f} ms | learned (taken: {lr['accepted']}) "
+            f"{lr['cycles']:2d} cycles {lr['ms']:6.1f} ms, final masks differ in {100 * lr['mask_diff']:.2f}% of pixels")
+    s = warmstart.summarize(rows)
+    say(f"  mean: marker {s['marker']['cycles']:.1f} cycles / {s['marker']['ms']:.1f} ms, learned "
+        f"{s['learned']['cycles']:.1f} cycles / {s['learned']['ms']:.1f} ms; same fixed point "
+        f"{s['learned']['same_fixed_point']}/{len(rows)}, network output taken {s['learned']['accepted']}/{len(rows)}")
+    # the learned start reaches the tolerance wherever the marker start does
+    for r in rows:
+        assert r["learned"]["converged"] or not r["marker"]["converged"], r["seed"]
+    assert s["learned"]["accepted"] >= 9
+    assert s["learned"]["same_fixed_point"] >= 9
+    assert s["learned"]["cycles"] < s["marker"]["cycles"]
+    net.close()
