@@ -24,6 +24,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+MFMA_BF16_PEAK_TFLOPS = 2500.0          # dense bf16 matrix-core peak
+WEIGHTS = os.path.join(ROOT, "paper_1807_02137_amd", "weights", "warmstart_512_b32_d4.npz")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_1024_traffic.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1807_02137_amd", "csrc", f)
                   for f in ("mgseg_device.h", "mgseg_kernels.h", "mgseg.hip")]
@@ -108,6 +110,112 @@ def batch_bench(count: int):
         "speedup_vs_one_stream": out["tuned"]["value"] / out["one_stream"]["value"]}))
 
 
+def warmstart_bench(steps: int, warmup: int, count: int):
+    """Learned warm start on 512x512 images of 4-20 shapes (held-out seeds).
+
+    One step = for each of `count` held-out images: setup, the network's
+    phi0 (features + forward pass + marker check), and V-cycles until the
+    finest residual is at most 1e-6 times that of the marker-based phi0 (the
+    same absolute accuracy as the plain solve).  The plain (marker phi0) and
+    phi0 = 0 starts are timed the same way for comparison, and the share of
+    images whose final segmentation equals the plain solve's is reported.
+    The roofline is that of the convolution kernel (k_conv) over a forward
+    and a training step of 8 images, timed with HIP events per launch."""
+    import numpy as np
+    import torch
+    from paper_1807_02137_amd import build, mgseg, synth, warmstart
+    if not os.path.exists(build.LIB):
+        build.build()
+    inst = warmstart.generate(warmstart.HELDOUT_SEEDS[:count], 512, workers=8)
+    print(f"c5: {count} held-out images drawn", file=sys.stderr, flush=True)
+    torch.cuda.set_device(0)
+    net, scale = warmstart.load(WEIGHTS)
+    params = mgseg.Params(levels=synth.levels_for(512, 512))
+    stream = torch.cuda.current_stream()
+    zeros = torch.zeros((512, 512), dtype=torch.float32, device="cuda")
+    imgs = [(torch.from_numpy(i).to("cuda"), mk) for i, mk, _ in inst]
+
+    def solve_one(img, mk, start):
+        s = mgseg.Solver(img, mk, params, stream=stream)
+        r0 = s.scalars()["res0"]
+        taken = None
+        if start == "learned":
+            taken = s.predict_phi0(net, scale)
+        elif start == "zero":
+            s.set_phi0(zeros)
+        res0 = s.scalars()["res0"]
+        cyc, ok = 0, True
+        if res0 > TOL * r0:
+            cyc, _, ok = s.solve(TOL * r0 / res0, MAX_CYCLES)
+        mask = s.mask()
+        s.close()
+        return cyc, ok, mask, taken
+
+    res = {}
+    for start in ("marker", "learned", "zero"):
+        for _ in range(warmup):
+            for img, mk in imgs:
+                solve_one(img, mk, start)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        runs = []
+        for _ in range(steps):
+            runs = [solve_one(img, mk, start) for img, mk in imgs]
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        res[start] = dict(wall=wall, runs=runs)
+        print(f"c5 {start}: {wall / steps * 1e3:.1f} ms per pass", file=sys.stderr, flush=True)
+    ref = [r[2] for r in res["marker"]["runs"]]
+
+    def summary(start):
+        runs = res[start]["runs"]
+        same = [bool((r[2] == m).all()) for r, m in zip(runs, ref)]
+        out = {"ms_per_image": res[start]["wall"] / (steps * count) * 1e3,
+               "cycles": [r[0] for r in runs], "mean_cycles": float(np.mean([r[0] for r in runs])),
+               "converged": int(sum(r[1] for r in runs)), "same_segmentation_as_plain": int(sum(same))}
+        if start == "learned":
+            out["network_phi0_taken"] = int(sum(bool(r[3]) for r in runs))
+        return out
+
+    # convolution roofline: forward and training step on 8 held-out images
+    feats = []
+    for img, mk in imgs[:8]:
+        s = mgseg.Solver(img, mk, params, stream=stream)
+        feats.append(s.features())
+        s.close()
+    x = torch.stack(feats)
+    net.forward(x, params.M)
+    torch.cuda.synchronize()
+    net.profile(True)
+    net.forward(x, params.M)
+    f_ms, f_n, f_fl = net.profile_read()
+    tgt = torch.zeros((x.shape[0], 512, 512), dtype=torch.float32, device="cuda")
+    net.backward(tgt, params.M)                     # warm the backward buffers
+    net.profile(True)
+    net.forward(x, params.M)
+    net.backward(tgt, params.M)
+    b_ms, b_n, b_fl = net.profile_read()
+    net.profile(False)
+    achieved = f_fl / (f_ms * 1e-3) / 1e12
+    plain, learned = summary("marker"), summary("learned")
+    print(json.dumps({
+        "metric": "time to the plain solve's residual (1e-6 of the marker start's), learned warm start",
+        "value": learned["ms_per_image"], "unit": "ms per 512x512 image", "n_gpus": 1, "steps": steps,
+        "warmup": warmup, "ms_per_step": learned["ms_per_image"] * count, "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16 network + f32/f64 solve", "data": "synthetic",
+        "config": {"workload": f"{count} held-out 512x512 images of 4-20 shapes (seeds "
+                               f"{warmstart.HELDOUT_SEEDS.start}..{warmstart.HELDOUT_SEEDS.start + count - 1}), "
+                               "8 grids, network base 32 depth 4, amplitude %.2f" % scale},
+        "learned": learned, "plain": plain, "zero": summary("zero"),
+        "speedup_vs_plain": plain["ms_per_image"] / learned["ms_per_image"],
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / MFMA_BF16_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "k_conv (bf16 implicit-GEMM 3x3 convolution), forward pass of 8 images",
+                     "launches": f_n, "avg_us": f_ms / max(f_n, 1) * 1e3, "flops_per_launch": f_fl / max(f_n, 1)},
+        "training_step": {"conv_launches": b_n, "conv_ms": b_ms, "conv_tflops": b_fl / (b_ms * 1e-3) / 1e12},
+    }))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -117,9 +225,11 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain copy of known size (counter calibration) and exit")
-    ap.add_argument("--workload", default="c2", choices=("c2", "c3"),
-                    help="c2: the 1024x1024 solve (default); c3: the 64-image batch of uneven sizes")
+    ap.add_argument("--workload", default="c2", choices=("c2", "c3", "c5"),
+                    help="c2: the 1024x1024 solve (default); c3: the 64-image batch of uneven sizes; "
+                         "c5: the learned warm start on 512x512 held-out images")
     ap.add_argument("--batch-count", type=int, default=64)
+    ap.add_argument("--c5-images", type=int, default=16)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -131,6 +241,9 @@ def main():
         return
     if args.workload == "c3":
         batch_bench(args.batch_count)
+        return
+    if args.workload == "c5":
+        warmstart_bench(args.steps, args.warmup, args.c5_images)
         return
     import torch
 

@@ -279,6 +279,15 @@ mgseg_status mgseg_net_get_params(mgseg_net *n, float *host, float *grad_host);
 mgseg_status mgseg_net_set_params(mgseg_net *n, const float *host);
 void mgseg_net_destroy(mgseg_net *n);
 
+/* Convolution timing.  While enabled, every k_conv launch (forward and data
+ * gradient) is bracketed by HIP events on its stream and its algorithmic
+ * flops (2 * 9 * input channels that carry data * output channels * pixels)
+ * are added up; mgseg_net_profile(n, 1) also clears the record.  _read
+ * synchronises the device and returns the summed launch time (ms), the launch
+ * count and the flops (outputs may be null). */
+mgseg_status mgseg_net_profile(mgseg_net *n, int enable);
+mgseg_status mgseg_net_profile_read(mgseg_net *n, double *total_ms, int *launches, double *flops);
+
 /* The network input of a context: out_dev[3][n][m] = (z, d, marker mask). */
 mgseg_status mgseg_ctx_features(mgseg_ctx *c, float *out_dev);
 

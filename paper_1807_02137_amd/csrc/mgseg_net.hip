@@ -516,6 +516,11 @@ struct mgseg_net {
     float *part = nullptr, *partb = nullptr, *hpart = nullptr, *loss = nullptr;
     std::vector<void *> act_allocs, par_allocs;
     int steps = 0;
+    // k_conv launch timing (mgseg_net_profile): event pairs, algorithmic flops
+    bool prof = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    double prof_flops = 0.0;
 };
 
 namespace {
@@ -604,8 +609,11 @@ bool ensure_acts(mgseg_net *n, int B, int H, int W)
     return true;
 }
 
-void conv(hipStream_t s, View in, const uint16_t *Wk, const float *bias, int IC, int OC, View out, int H, int W, int B,
-          int relu, float *out32 = nullptr, const uint16_t *mask = nullptr, int mps = 0, int moff = 0)
+// icr: the input channels that carry data (the stored count IC may include zero padding); used for the
+// algorithmic flop count of a profiled launch
+void conv(mgseg_net *n, hipStream_t s, View in, const uint16_t *Wk, const float *bias, int IC, int OC, View out, int H,
+          int W, int B, int relu, float *out32 = nullptr, const uint16_t *mask = nullptr, int mps = 0, int moff = 0,
+          int icr = 0)
 {
     ConvArgs A;
     A.in = in.p; A.ips = in.ps; A.ioff = in.off; A.Wk = Wk; A.bias = bias;
@@ -614,7 +622,22 @@ void conv(hipStream_t s, View in, const uint16_t *Wk, const float *bias, int IC,
     A.IC = IC; A.OC = OC; A.H = H; A.W = W; A.relu = relu;
     const unsigned tiles = (unsigned)(((H + TY - 1) / TY) * ((W + TX - 1) / TX));
     dim3 g(tiles, (unsigned)((OC + OCB - 1) / OCB), (unsigned)B);
+    hipEvent_t e[2] = {nullptr, nullptr};
+    if (n->prof) {
+        while (n->ev_pool.size() < n->ev_used + 2) {
+            hipEvent_t ev;
+            if (hipEventCreate(&ev) != hipSuccess) { (void)hipGetLastError(); break; }
+            n->ev_pool.push_back(ev);
+        }
+        if (n->ev_pool.size() >= n->ev_used + 2) {
+            e[0] = n->ev_pool[n->ev_used]; e[1] = n->ev_pool[n->ev_used + 1];
+            n->ev_used += 2;
+            n->prof_flops += 2.0 * 9.0 * (icr ? icr : IC) * OC * (double)H * W * B;
+            (void)hipEventRecord(e[0], s);
+        }
+    }
     hipLaunchKernelGGL(k_conv, g, dim3(256), 0, s, A);
+    if (e[1]) (void)hipEventRecord(e[1], s);
 }
 
 void wgrad(mgseg_net *n, hipStream_t s, View g, View x, NetLayer &L, int H, int W, int B)
@@ -632,11 +655,11 @@ void wgrad(mgseg_net *n, hipStream_t s, View g, View x, NetLayer &L, int H, int 
 }
 
 // forward of one block: mid = relu(conv_a(x)), y = relu(conv_b(mid))
-void block_fwd(hipStream_t s, NetLayer &a, NetLayer &b, View x, uint16_t *mid, View y, int h, int w, int B,
-               float *y32 = nullptr)
+void block_fwd(mgseg_net *n, hipStream_t s, NetLayer &a, NetLayer &b, View x, uint16_t *mid, View y, int h, int w,
+               int B, float *y32 = nullptr)
 {
-    conv(s, x, a.wp, a.b32, a.IC, a.OC, View{mid, a.OC, 0}, h, w, B, 1);
-    conv(s, View{mid, a.OC, 0}, b.wp, b.b32, b.IC, b.OC, y, h, w, B, 1, y32);
+    conv(n, s, x, a.wp, a.b32, a.IC, a.OC, View{mid, a.OC, 0}, h, w, B, 1, nullptr, nullptr, 0, 0, a.ICr);
+    conv(n, s, View{mid, a.OC, 0}, b.wp, b.b32, b.IC, b.OC, y, h, w, B, 1, y32);
 }
 
 // backward of one block, gy = gradient of y already zeroed where y <= 0: weight gradients, and the
@@ -646,9 +669,9 @@ void block_bwd(mgseg_net *n, hipStream_t s, NetLayer &a, NetLayer &b, View x, ui
 {
     const View vm{mid, a.OC, 0}, vgm{gmid, a.OC, 0};
     wgrad(n, s, gy, vm, b, h, w, B);
-    conv(s, gy, b.wt, nullptr, b.OC, b.IC, vgm, h, w, B, 0, nullptr, mid, a.OC, 0);
+    conv(n, s, gy, b.wt, nullptr, b.OC, b.IC, vgm, h, w, B, 0, nullptr, mid, a.OC, 0);
     wgrad(n, s, vgm, x, a, h, w, B);
-    if (gx.p) conv(s, vgm, a.wt, nullptr, a.OC, a.ICr, gx, h, w, B, 0);
+    if (gx.p) conv(n, s, vgm, a.wt, nullptr, a.OC, a.ICr, gx, h, w, B, 0);
 }
 
 // SplitMix64 + Box-Muller: He-normal initial weights from the seed
@@ -720,6 +743,7 @@ void mgseg_net_destroy(mgseg_net *n)
 {
     if (!n) return;
     free_acts(n);
+    for (hipEvent_t e : n->ev_pool) (void)hipEventDestroy(e);
     for (void *p : n->par_allocs) (void)hipFree(p);
     delete n;
 }
@@ -778,7 +802,7 @@ mgseg_status mgseg_net_forward(mgseg_net *n, const float *in_dev, int B, int H, 
     for (int l = 0; l < D; l++) {
         const int h = H >> l, w = W >> l, ce = chan(n, l);
         const View e = l < D - 1 ? View{n->cat[l], chan(n, l + 1) + ce, chan(n, l + 1)} : View{n->ebot, ce, 0};
-        block_fwd(s, n->enc[2 * l], n->enc[2 * l + 1], cur, n->emid[l], e, h, w, B);
+        block_fwd(n, s, n->enc[2 * l], n->enc[2 * l + 1], cur, n->emid[l], e, h, w, B);
         if (l < D - 1) {
             hipLaunchKernelGGL(k_avgpool, dim3(nblk((long long)B * (h / 2) * (w / 2) * ce)), dim3(256), 0, s, e.p,
                                e.ps, e.off, ce, h / 2, w / 2, B, n->pool[l]);
@@ -792,7 +816,7 @@ mgseg_status mgseg_net_forward(mgseg_net *n, const float *in_dev, int B, int H, 
         const int cu = chan(n, l + 1), ce = chan(n, l);
         hipLaunchKernelGGL(k_upsample, dim3(nblk((long long)B * h * w * cu)), dim3(256), 0, s, dn, cu, h / 2, w / 2, B,
                            n->cat[l], cu + ce);
-        block_fwd(s, n->dec[2 * l], n->dec[2 * l + 1], View{n->cat[l], cu + ce, 0}, n->dmid[l],
+        block_fwd(n, s, n->dec[2 * l], n->dec[2 * l + 1], View{n->cat[l], cu + ce, 0}, n->dmid[l],
                   View{n->dact[l], ce, 0}, h, w, B, l == 0 ? n->d0f : nullptr);
         dn = n->dact[l];
     }
@@ -908,6 +932,32 @@ mgseg_status mgseg_net_set_params(mgseg_net *n, const float *host)
     pack_all(n, 0);
     n->steps = 0;
     return ok && hipDeviceSynchronize() == hipSuccess ? MGSEG_OK : MGSEG_E_HIP;
+}
+
+mgseg_status mgseg_net_profile(mgseg_net *n, int enable)
+{
+    if (!n) return MGSEG_E_ARG;
+    if (hipDeviceSynchronize() != hipSuccess) return MGSEG_E_HIP;
+    n->prof = enable != 0;
+    n->ev_used = 0;
+    n->prof_flops = 0.0;
+    return MGSEG_OK;
+}
+
+mgseg_status mgseg_net_profile_read(mgseg_net *n, double *total_ms, int *launches, double *flops)
+{
+    if (!n) return MGSEG_E_ARG;
+    if (hipDeviceSynchronize() != hipSuccess) return MGSEG_E_HIP;
+    double ms = 0.0;
+    for (size_t i = 0; i + 1 < n->ev_used; i += 2) {
+        float t = 0.0f;
+        if (hipEventElapsedTime(&t, n->ev_pool[i], n->ev_pool[i + 1]) != hipSuccess) return MGSEG_E_HIP;
+        ms += t;
+    }
+    if (total_ms) *total_ms = ms;
+    if (launches) *launches = (int)(n->ev_used / 2);
+    if (flops) *flops = n->prof_flops;
+    return MGSEG_OK;
 }
 
 }  // extern "C"

@@ -127,6 +127,8 @@ def lib():
         L.mgseg_net_destroy.argtypes = [vp]
         L.mgseg_net_destroy.restype = None
         L.mgseg_ctx_features.argtypes = [vp, vp]
+        L.mgseg_net_profile.argtypes = [vp, C.c_int]
+        L.mgseg_net_profile_read.argtypes = [vp, dp, ip, dp]
         L.mgseg_predict_phi0.argtypes = [vp, vp, C.c_double, ip]
         L.mgseg_reset_phi0.argtypes = [vp]
         for name in ("mgseg_setup", "mgseg_set_phi0", "mgseg_vcycle", "mgseg_solve", "mgseg_get_phi",
@@ -136,7 +138,7 @@ def lib():
                      "mgseg_batch_set_streams", "mgseg_solve_batch", "mgseg_batch_ctx", "mgseg_net_create",
                      "mgseg_net_forward", "mgseg_net_backward", "mgseg_net_adam_step", "mgseg_net_param_count",
                      "mgseg_net_get_params", "mgseg_net_set_params", "mgseg_ctx_features", "mgseg_predict_phi0",
-                     "mgseg_reset_phi0"):
+                     "mgseg_reset_phi0", "mgseg_net_profile", "mgseg_net_profile_read"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -395,6 +397,16 @@ class Net:
         if v.size != self.count:
             raise ValueError(f"expected {self.count} parameters, got {v.size}")
         _check(self.L.mgseg_net_set_params(self.h, v.ctypes.data_as(C.c_void_p)), "mgseg_net_set_params")
+
+    def profile(self, enable=True):
+        """Time every convolution launch with HIP events (clears the record)."""
+        _check(self.L.mgseg_net_profile(self.h, int(enable)), "mgseg_net_profile")
+
+    def profile_read(self):
+        """(summed convolution launch time in ms, launches, algorithmic flops)."""
+        ms, n, fl = C.c_double(), C.c_int(), C.c_double()
+        _check(self.L.mgseg_net_profile_read(self.h, C.byref(ms), C.byref(n), C.byref(fl)), "mgseg_net_profile_read")
+        return ms.value, n.value, fl.value
 
     def close(self):
         if getattr(self, "h", None):

@@ -119,7 +119,7 @@ def _timed_solve(s: mgseg.Solver, tol_abs, max_cycles, prep=None):
     t0 = time.perf_counter()
     if prep is not None:
         prep()
-    res0 = s.stats()["res0"]
+    res0 = s.scalars()["res0"]
     cyc, rel, ok = s.solve(max(tol_abs / res0, 1e-300), max_cycles) if res0 > tol_abs else (0, res0, True)
     torch.cuda.synchronize()
     return dict(ms=1e3 * (time.perf_counter() - t0), cycles=cyc, res0=res0, res=rel * res0 if cyc else res0,
@@ -136,7 +136,7 @@ def evaluate(net: mgseg.Net | None, instances, params: mgseg.Params, tol=1e-6, m
     out = []
     for img, mk, seed in instances:
         s = mgseg.Solver(img, mk, params)
-        r0 = s.stats()["res0"]
+        r0 = s.scalars()["res0"]
         tol_abs = tol * r0
         row = dict(seed=seed, res0_marker=r0)
         row["marker"] = _timed_solve(s, tol_abs, max_cycles)
