@@ -373,6 +373,55 @@ __device__ __forceinline__ Ramp block_scan_excl(Ramp mine, Ramp *wtot, int parit
     return ex;
 }
 
+// Global inputs of one cell of a line (the frozen state of the sweep and the
+// old values): everything phase 1 of a line step reads from memory, so that
+// the next line's reads can be issued before the current line is computed.
+struct CellIn {
+    float p0, pp, pm, p0p, p0m, ppp, ppm, pmp, pmm;   // psi at (r,q), (r+1,q), (r-1,q), (r,q+), (r,q-), (r+1,q+), (r+1,q-), (r-1,q+), (r-1,q-)
+    float w00, wp, wm, w0p, w0m;                      // w at (r,q), (r+1,q), (r-1,q), (r,q+), (r,q-)
+    float fit, F, vu, vd, sig, pold, lo, hi;
+    unsigned lab;
+};
+
+// Reads the inputs of line r (rows mirrored at the grid edge, q+ / q- the
+// mirrored in-line neighbours); vu / vd are read only where the neighbour line
+// exists and is not supplied fresh by the caller.
+template <int NT, int K, bool REV>
+__device__ __forceinline__ void line_load(const LineArgs &A, int r, bool up_fresh, bool dn_fresh, CellIn (&L)[K])
+{
+    const int t = threadIdx.x;
+    const int nl = A.nl, ml = A.ml, P = A.pitch;
+    const int ru = REV ? r + 1 : r - 1, rd = REV ? r - 1 : r + 1;
+    const int rm1 = mg_mirror(r - 1, nl), rp1 = mg_mirror(r + 1, nl);
+    const long long ro = (long long)r * P;
+    const float *ps0 = A.psi + ro, *psm = A.psi + (long long)rm1 * P, *psp = A.psi + (long long)rp1 * P;
+    const float *w0 = A.w + ro, *wm = A.w + (long long)rm1 * P, *wp = A.w + (long long)rp1 * P;
+    const float *old = A.phi_old + ro;
+    const uint8_t *lrow = A.lab + (long long)r * A.lpitch;
+    const bool rd_up = ru >= 0 && ru < nl && !up_fresh, rd_dn = rd >= 0 && rd < nl && !dn_fresh;
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+        const int p = k * NT + t;
+        CellIn &c = L[k];
+        if (p >= ml) continue;
+        const int q = REV ? ml - 1 - p : p;
+        const int qm = mg_mirror(q - 1, ml), qp = mg_mirror(q + 1, ml);
+        c.lab = lrow[q];
+        c.p0 = ps0[q]; c.pp = psp[q]; c.pm = psm[q];
+        c.p0p = ps0[qp]; c.p0m = ps0[qm];
+        c.ppp = psp[qp]; c.ppm = psp[qm]; c.pmp = psm[qp]; c.pmm = psm[qm];
+        c.w00 = w0[q]; c.wp = wp[q]; c.wm = wm[q]; c.w0p = w0[qp]; c.w0m = w0[qm];
+        c.fit = A.fit ? A.fit[ro + q] : 0.0f;
+        c.F = A.F ? A.F[ro + q] : 0.0f;
+        c.vu = rd_up ? A.phi_old[(long long)ru * P + q] : 0.0f;
+        c.vd = rd_dn ? A.phi_old[(long long)rd * P + q] : 0.0f;
+        c.sig = p + 1 < ml ? old[REV ? ml - 2 - p : p + 1] : 0.0f;
+        c.lo = A.lo ? A.lo[ro + q] : -A.M;
+        c.hi = A.lo ? A.hi[ro + q] : A.M;
+        c.pold = old[q];
+    }
+}
+
 // --------------------------------------------------------------------------
 // One line of one directional sweep.  Cells are taken in visit order
 // (REV: q = ml-1 down to 0); thread t handles visit positions p = k*NT + t
@@ -386,25 +435,20 @@ __device__ __forceinline__ Ramp block_scan_excl(Ramp mine, Ramp *wtot, int parit
 template <int NT, int K, bool REV>
 __device__ __forceinline__ void sweep_line(const LineArgs &A, int r, const RunBuf &B, uint64_t *msk, bool write,
                                            const float (&upv)[K], bool up_fresh, const float (&dnv)[K],
-                                           bool dn_fresh, float (&val)[K], Ramp *wtot)
+                                           bool dn_fresh, float (&val)[K], Ramp *wtot, const CellIn (&L)[K])
 {
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int nl = A.nl, ml = A.ml, P = A.pitch, nw = (ml + 63) >> 6;
     const int ru = REV ? r + 1 : r - 1;      // upstream line
     const int rd = REV ? r - 1 : r + 1;      // downstream line
-    const int rm1 = mg_mirror(r - 1, nl), rp1 = mg_mirror(r + 1, nl);
     const long long ro = (long long)r * P;
-    const float *ps0 = A.psi + ro, *psm = A.psi + (long long)rm1 * P, *psp = A.psi + (long long)rp1 * P;
-    const float *w0 = A.w + ro, *wm = A.w + (long long)rm1 * P, *wp = A.w + (long long)rp1 * P;
-    const float *old = A.phi_old + ro;
-    const uint8_t *lrow = A.lab + (long long)r * A.lpitch;
     const float e2 = A.e2;
     const float area = A.area ? (float)(*A.area) : 0.0f;
     const bool has_up = ru >= 0 && ru < nl, has_dn = rd >= 0 && rd < nl;
     auto cell = [&](int p) { return REV ? ml - 1 - p : p; };
 
     // phase 1: frozen coefficients (eq. abcdrc), point ramps, unit rows,
-    // starred masks
+    // starred masks, from the line's inputs read by line_load
     float pa[K], pb[K], plo[K], phv[K];
     unsigned sm = 0;
     bool any_star = false;
@@ -414,37 +458,31 @@ __device__ __forceinline__ void sweep_line(const LineArgs &A, int r, const RunBu
         pa[k] = 0.0f; pb[k] = 0.0f; plo[k] = 0.0f; phv[k] = 0.0f;
         bool s0 = false;
         if (p < ml) {
+            const CellIn &c = L[k];
             const int q = cell(p);
-            s0 = ((lrow[q] >> A.bit) & 1) != 0;
-            const bool has_next = p + 1 < ml;
-            const int qm = mg_mirror(q - 1, ml), qp = mg_mirror(q + 1, ml);
-            const float p0 = ps0[q];
-            const float w00 = w0[q];
+            s0 = ((c.lab >> A.bit) & 1) != 0;
+            const float p0 = c.p0;
             float xp = 0.0f, xm = 0.0f, lp = 0.0f, lm = 0.0f;
-            if (r + 1 < nl)
-                xp = mg_face(p0, psp[q], ps0[qp], psp[qp], ps0[qm], psp[qm], w00, wp[q], e2);
-            if (r > 0)
-                xm = mg_face(psm[q], p0, psm[qp], ps0[qp], psm[qm], ps0[qm], wm[q], w00, e2);
-            if (q + 1 < ml)
-                lp = mg_face(p0, ps0[q + 1], psp[q], psp[q + 1], psm[q], psm[q + 1], w00, w0[q + 1], e2);
-            if (q > 0)
-                lm = mg_face(ps0[q - 1], p0, psp[q - 1], psp[q], psm[q - 1], psm[q], w0[q - 1], w00, e2);
+            if (r + 1 < nl) xp = mg_face(p0, c.pp, c.p0p, c.ppp, c.p0m, c.ppm, c.w00, c.wp, e2);
+            if (r > 0) xm = mg_face(c.pm, p0, c.pmp, c.p0p, c.pmm, c.p0m, c.wm, c.w00, e2);
+            if (q + 1 < ml) lp = mg_face(p0, c.p0p, c.pp, c.ppp, c.pm, c.pmp, c.w00, c.w0p, e2);
+            if (q > 0) lm = mg_face(c.p0m, p0, c.ppm, c.pp, c.pmm, c.pm, c.w0m, c.w00, e2);
             const float dl = A.scaled ? 1.0f : mg_delta(p0, A.eps);
             const float sc = A.kap * dl;
             xp *= sc; xm *= sc; lp *= sc; lm *= sc;
             const float S = xp + xm + lp + lm;
-            const float f = A.fit ? dl * (A.fit[ro + q] + area) : 0.0f;   // null fit: f is part of F
-            const float Fv = A.F ? A.F[ro + q] : 0.0f;
+            const float f = A.fit ? dl * (c.fit + area) : 0.0f;   // null fit: f is part of F
+            const float Fv = c.F;
             const float Xu = REV ? xp : xm, Xd = REV ? xm : xp;
             const float Lp = REV ? lp : lm, Ls = REV ? lm : lp;
             float vu = 0.0f, vd = 0.0f;
-            if (has_up) vu = up_fresh ? upv[k] : A.phi_old[(long long)ru * P + q];
-            if (has_dn) vd = dn_fresh ? dnv[k] : A.phi_old[(long long)rd * P + q];
+            if (has_up) vu = up_fresh ? upv[k] : c.vu;
+            if (has_dn) vd = dn_fresh ? dnv[k] : c.vd;
             const float rhs = f + Fv - Xu * vu - Xd * vd;
-            const float sig = has_next ? old[cell(p + 1)] : 0.0f;
-            const float lo = A.lo ? A.lo[ro + q] : -A.M;
-            const float hi = A.lo ? A.hi[ro + q] : A.M;
-            const float pold = old[q];
+            const float sig = c.sig;
+            const float lo = c.lo;
+            const float hi = c.hi;
+            const float pold = c.pold;
             const bool ok = S > 0.0f;
             const float inv = ok ? __builtin_amdgcn_rcpf(S) : 0.0f;
             if (ok) {
@@ -577,12 +615,46 @@ __device__ __forceinline__ void sweep_line(const LineArgs &A, int r, const RunBu
 // processed in the class order 0,1,2,3 (forward) or 3,2,1,0 (reverse); the
 // neighbouring band's first-processed line is recomputed (not written) where
 // a line of this band needs it fresh.
-template <int NT, int K, bool REV>
+//
+// Step st of the band (0..4): its line, whether it is the recomputed
+// neighbour, and whether its up / down neighbour values are fresh registers.
+// Forward order: r0, r0+1, r0+2, [r0+4 recomputed], r0+3.
+// Reverse order: r0+3, r0+2, r0+1, [r0-1 recomputed], r0.
+template <bool REV>
+__device__ __forceinline__ int band_line(int r0, int st)
+{
+    if (!REV) return (st < 3) ? r0 + st : (st == 3 ? r0 + 4 : r0 + 3);
+    return (st < 3) ? r0 + 3 - st : (st == 3 ? r0 - 1 : r0);
+}
+template <bool REV>
+__device__ __forceinline__ void band_step(int r0, int nl, int st, int &r, bool &redundant, bool &up_fresh,
+                                          bool &dn_fresh)
+{
+    r = band_line<REV>(r0, st);
+    redundant = st == 3;
+    // an own line processed before this step (steps 0, 1, 2 are own lines)
+    bool have_prev = false;
+    for (int s2 = 0; s2 < 3 && s2 < st; s2++) {
+        const int rr = band_line<REV>(r0, s2);
+        have_prev |= rr >= 0 && rr < nl;
+    }
+    if (redundant) { up_fresh = false; dn_fresh = false; }
+    else if (st < 3) { up_fresh = have_prev; dn_fresh = false; }
+    else {
+        // the last own line: upstream = the line processed just before it,
+        // downstream = the recomputed neighbour line (if it exists)
+        up_fresh = have_prev;
+        const int rn = REV ? r0 - 1 : r0 + 4;
+        dn_fresh = rn >= 0 && rn < nl;
+    }
+}
+
+// PF: read the next step's inputs (line_load) before computing the current
+// line, so that their latency overlaps the current line's phases (costs the
+// registers of one more CellIn per round).
+template <int NT, int K, bool REV, bool PF = false>
 __device__ __forceinline__ void sweep_band(const LineArgs &A, int b, const RunBuf &B, uint64_t *msk, Ramp *wtot)
 {
-    // Five line steps (the band's four lines plus the recomputed one), one call
-    // site.  Forward order: r0, r0+1, r0+2, [r0+4 recomputed], r0+3.
-    // Reverse order: r0+3, r0+2, r0+1, [r0-1 recomputed], r0.
     float prev[K], red[K], cur[K];
     // transposed output of a full band: the band's 4 lines are 4 consecutive
     // floats of the output layout, written as one 16-byte store per cell
@@ -595,25 +667,31 @@ __device__ __forceinline__ void sweep_band(const LineArgs &A, int b, const RunBu
     const int nl = A.nl, ml = A.ml;
     const int r0 = 4 * b;
     const bool pack = A.tout != nullptr && r0 + 3 < nl;
-    bool have_prev = false;      // prev holds the previously processed own line
+    auto valid = [&](int st) { const int r = band_line<REV>(r0, st); return r >= 0 && r < nl; };
+    CellIn la[K], lb[K];
+    int st = 0;
+    while (st < 5 && !valid(st)) st++;
+    if (PF && st < 5) {
+        int r; bool rdd, uf, df;
+        band_step<REV>(r0, nl, st, r, rdd, uf, df);
+        line_load<NT, K, REV>(A, r, uf, df, la);
+    }
 #pragma nounroll
-    for (int st = 0; st < 5; st++) {
-        int r;
-        bool redundant = (st == 3);
-        if (!REV) r = (st < 3) ? r0 + st : (st == 3 ? r0 + 4 : r0 + 3);
-        else r = (st < 3) ? r0 + 3 - st : (st == 3 ? r0 - 1 : r0);
-        if (r < 0 || r >= nl) continue;
-        bool up_fresh, dn_fresh;
-        if (redundant) { up_fresh = false; dn_fresh = false; }
-        else if (st < 3) { up_fresh = have_prev; dn_fresh = false; }
-        else {
-            // the last own line: upstream = the line processed just before it,
-            // downstream = the recomputed neighbour line (if it exists)
-            up_fresh = have_prev;
-            int rn = REV ? r0 - 1 : r0 + 4;
-            dn_fresh = rn >= 0 && rn < nl;
+    while (st < 5) {
+        int r; bool redundant, up_fresh, dn_fresh;
+        band_step<REV>(r0, nl, st, r, redundant, up_fresh, dn_fresh);
+        int nx = st + 1;
+        while (nx < 5 && !valid(nx)) nx++;
+        if (PF) {
+            if (nx < 5) {
+                int r2; bool rd2, uf2, df2;
+                band_step<REV>(r0, nl, nx, r2, rd2, uf2, df2);
+                line_load<NT, K, REV>(A, r2, uf2, df2, lb);
+            }
+        } else {
+            line_load<NT, K, REV>(A, r, up_fresh, dn_fresh, la);
         }
-        sweep_line<NT, K, REV>(A, r, B, msk, !redundant && !pack, prev, up_fresh, red, dn_fresh, cur, wtot);
+        sweep_line<NT, K, REV>(A, r, B, msk, !redundant && !pack, prev, up_fresh, red, dn_fresh, cur, wtot, la);
         const int li = r - r0;
 #pragma unroll
         for (int k = 0; k < K; k++) {
@@ -625,8 +703,9 @@ __device__ __forceinline__ void sweep_band(const LineArgs &A, int b, const RunBu
                 else if (li == 2) o2[k] = cur[k];
                 else o3[k] = cur[k];
             }
+            if (PF) la[k] = lb[k];
         }
-        if (!redundant) have_prev = true;
+        st = nx;
     }
     if (pack) {
 #pragma unroll
@@ -660,5 +739,6 @@ __global__ void __launch_bounds__(NT) k_sweep(LineArgs A)
     B.fs = A.ml;
     if (A.ml <= RB_LDS_MAX) B.p = reinterpret_cast<float *>(smem64 + sweep_mask_words(A.ml));
     else B.p = A.scr + (long long)blockIdx.x * RF_COUNT * A.ml;
-    sweep_band<NT, K, REV>(A, blockIdx.x, B, msk, wtot);
+    // read-ahead of the next line where the registers allow it (not at 1024 threads, 128 registers per lane)
+    sweep_band<NT, K, REV, (NT <= 512 && K == 1)>(A, blockIdx.x, B, msk, wtot);
 }
