@@ -338,20 +338,47 @@ __global__ void k_pack_input(const float *x, long long HW, int B, uint16_t *y)
     d[0] = v0; d[1] = z; d[2] = z; d[3] = z;
 }
 
+// 8 bf16 values in 16 bytes
+struct bf8 {
+    uint4 v;
+    __device__ __forceinline__ float get(int i) const
+    {
+        const uint32_t w = i < 2 ? v.x : (i < 4 ? v.y : (i < 6 ? v.z : v.w));
+        return bf2f((uint16_t)((i & 1) ? (w >> 16) : (w & 0xffffu)));
+    }
+};
+__device__ __forceinline__ uint4 pack8(const float (&f)[8])
+{
+    uint4 o;
+    o.x = (uint32_t)f2bf(f[0]) | ((uint32_t)f2bf(f[1]) << 16);
+    o.y = (uint32_t)f2bf(f[2]) | ((uint32_t)f2bf(f[3]) << 16);
+    o.z = (uint32_t)f2bf(f[4]) | ((uint32_t)f2bf(f[5]) << 16);
+    o.w = (uint32_t)f2bf(f[6]) | ((uint32_t)f2bf(f[7]) << 16);
+    return o;
+}
+__device__ __forceinline__ bf8 ld8(const uint16_t *p) { return bf8{*(const uint4 *)p}; }
+
+// The elementwise kernels below take 8 consecutive channels (16 bytes) per
+// thread: channel counts, view strides and offsets are multiples of 8.
+
 // 2x2 average pooling: out[(b, y, x), c] (dense, C per pixel) from the view (ps, off) at twice the size
 __global__ void k_avgpool(const uint16_t *in, int ps, int off, int C, int h, int w, int B, uint16_t *out)
 {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (long long)B * h * w * C) return;
-    const long long q = t / C;
-    const int c = (int)(t % C);
+    const int C8 = C / 8;
+    if (t >= (long long)B * h * w * C8) return;
+    const long long q = t / C8;
+    const int c = (int)(t % C8) * 8;
     const long long b = q / ((long long)h * w);
     const int yy = (int)((q / w) % h), xx = (int)(q % w);
     const int W = 2 * w;
     const long long f = b * 4LL * h * w + (long long)(2 * yy) * W + 2 * xx;
     const uint16_t *s = in + off + c;
-    const float v = bf2f(s[f * ps]) + bf2f(s[(f + 1) * ps]) + bf2f(s[(f + W) * ps]) + bf2f(s[(f + W + 1) * ps]);
-    out[t] = f2bf(0.25f * v);
+    const bf8 a = ld8(s + f * ps), bq = ld8(s + (f + 1) * ps), cq = ld8(s + (f + W) * ps), d = ld8(s + (f + W + 1) * ps);
+    float o[8];
+#pragma unroll
+    for (int i = 0; i < 8; i++) o[i] = 0.25f * (a.get(i) + bq.get(i) + cq.get(i) + d.get(i));
+    *(uint4 *)(out + q * C + c) = pack8(o);
 }
 
 // gradient of e (view g: the skip part of the concatenation's gradient) += 0.25 gpool of its coarse
@@ -359,30 +386,33 @@ __global__ void k_avgpool(const uint16_t *in, int ps, int off, int C, int h, int
 __global__ void k_avgpool_bwd(const uint16_t *gp, int C, int h, int w, int B, uint16_t *g, int gps, int goff,
                               const uint16_t *e, int eps, int eoff)
 {
-    const int H = 2 * h, W = 2 * w;
+    const int H = 2 * h, W = 2 * w, C8 = C / 8;
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (long long)B * H * W * C) return;
-    const long long px = t / C;
-    const int c = (int)(t % C);
+    if (t >= (long long)B * H * W * C8) return;
+    const long long px = t / C8;
+    const int c = (int)(t % C8) * 8;
     const long long b = px / ((long long)H * W);
     const int y = (int)((px / W) % H), x = (int)(px % W);
-    const float gc = bf2f(gp[((b * h + y / 2) * w + x / 2) * C + c]);
+    const bf8 gc = ld8(gp + ((b * h + y / 2) * w + x / 2) * C + c);
     uint16_t *d = g + px * gps + goff + c;
-    const float v = bf2f(*d) + 0.25f * gc;
-    *d = bf2f(e[px * eps + eoff + c]) > 0.0f ? f2bf(v) : (uint16_t)0;
+    const bf8 gv = ld8(d), ev = ld8(e + px * eps + eoff + c);
+    float o[8];
+#pragma unroll
+    for (int i = 0; i < 8; i++) o[i] = ev.get(i) > 0.0f ? gv.get(i) + 0.25f * gc.get(i) : 0.0f;
+    *(uint4 *)d = pack8(o);
 }
 
 // nearest 2x up-sampling of the dense coarse d [(b, y, x)][C] into channels [0, C) of the view (ps, 0)
 __global__ void k_upsample(const uint16_t *d, int C, int h, int w, int B, uint16_t *out, int ps)
 {
-    const int H = 2 * h, W = 2 * w;
+    const int H = 2 * h, W = 2 * w, C8 = C / 8;
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (long long)B * H * W * C) return;
-    const long long px = t / C;
-    const int c = (int)(t % C);
+    if (t >= (long long)B * H * W * C8) return;
+    const long long px = t / C8;
+    const int c = (int)(t % C8) * 8;
     const long long b = px / ((long long)H * W);
     const int y = (int)((px / W) % H), x = (int)(px % W);
-    out[px * ps + c] = d[((b * h + y / 2) * w + x / 2) * C + c];
+    *(uint4 *)(out + px * ps + c) = *(const uint4 *)(d + ((b * h + y / 2) * w + x / 2) * C + c);
 }
 
 // adjoint of k_upsample (2x2 sums of channels [0, C) of the view), rounded, zeroed where y <= 0;
@@ -390,17 +420,22 @@ __global__ void k_upsample(const uint16_t *d, int C, int h, int w, int B, uint16
 __global__ void k_upsample_bwd(const uint16_t *g, int ps, int C, int h, int w, int B, const uint16_t *y,
                                uint16_t *gd)
 {
+    const int C8 = C / 8;
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (long long)B * h * w * C) return;
-    const long long q = t / C;
-    const int c = (int)(t % C);
+    if (t >= (long long)B * h * w * C8) return;
+    const long long q = t / C8;
+    const int c = (int)(t % C8) * 8;
     const long long b = q / ((long long)h * w);
     const int yy = (int)((q / w) % h), xx = (int)(q % w);
     const int W = 2 * w;
     const long long f = b * 4LL * h * w + (long long)(2 * yy) * W + 2 * xx;
     const uint16_t *s = g + c;
-    const float v = bf2f(s[f * ps]) + bf2f(s[(f + 1) * ps]) + bf2f(s[(f + W) * ps]) + bf2f(s[(f + W + 1) * ps]);
-    gd[t] = bf2f(y[t]) > 0.0f ? f2bf(v) : (uint16_t)0;
+    const bf8 a = ld8(s + f * ps), bq = ld8(s + (f + 1) * ps), cq = ld8(s + (f + W) * ps), d = ld8(s + (f + W + 1) * ps);
+    const bf8 yv = ld8(y + q * C + c);
+    float o[8];
+#pragma unroll
+    for (int i = 0; i < 8; i++) o[i] = yv.get(i) > 0.0f ? a.get(i) + bq.get(i) + cq.get(i) + d.get(i) : 0.0f;
+    *(uint4 *)(gd + q * C + c) = pack8(o);
 }
 
 // head: o = w . d0 + b, phi0 = M tanh(o) (FP32 from the FP32 copy of d0, [px][C]); keeps o for the loss
@@ -409,9 +444,15 @@ __global__ void k_head(const float *d0, int C, long long NP, const float *w, con
 {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= NP) return;
-    const float *x = d0 + t * C;
+    const float4 *x = (const float4 *)(d0 + t * C);
     float o = b[0];
-    for (int c = 0; c < C; c++) o = fmaf(w[c], x[c], o);
+    for (int c = 0; c < C / 4; c++) {
+        const float4 v = x[c];
+        o = fmaf(w[4 * c], v.x, o);
+        o = fmaf(w[4 * c + 1], v.y, o);
+        o = fmaf(w[4 * c + 2], v.z, o);
+        o = fmaf(w[4 * c + 3], v.w, o);
+    }
     ob[t] = o;
     phi[t] = M * tanhf(o);
 }
@@ -421,49 +462,84 @@ __global__ void k_head(const float *d0, int C, long long NP, const float *w, con
 // w = pw on the object (tg > 0) and 1 elsewhere, averaged over the N pixels:
 //   loss = mean w (softplus(2 o) - 2 o q),   dloss/do = w (tanh o - tg) / N,
 // whose minimum is at tanh o = tg and whose gradient does not vanish where the
-// output saturates on the wrong side.  Head gradient partials per block;
-// gd0 = w_head dO, zeroed where the stored d0 <= 0 (bf16, [px][C]).
-__global__ void __launch_bounds__(256) k_head_bwd(const float *ob, const float *target, float M, float pw,
-                                                  const float *d0, const uint16_t *d0b, int C, long long N,
-                                                  const float *w, uint16_t *gd0, float *part, int maxc)
+// output saturates on the wrong side.  Per pixel: the loss term and dO to
+// lossb / dob, and gd0 = w_head dO, zeroed where the stored d0 <= 0 (bf16, [px][C]).
+__global__ void k_head_bwd(const float *ob, const float *target, float M, float pw, const uint16_t *d0b, int C,
+                           long long N, const float *w, uint16_t *gd0, float *dob, float *lossb)
 {
-    __shared__ float red[256];
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    float loss = 0.0f, dO = 0.0f;
-    if (t < N) {
-        const float tg = fminf(fmaxf(target[t] / M, -1.0f), 1.0f);
-        const float q = tg > 0.0f ? pw : 1.0f;
-        const float x = 2.0f * ob[t];
-        const float sp = fmaxf(x, 0.0f) + log1pf(expf(-fabsf(x)));
-        loss = q * (sp - x * 0.5f * (1.0f + tg));
-        dO = q * (tanhf(ob[t]) - tg) / (float)N;
-        for (int c = 0; c < C; c++)
-            gd0[t * C + c] = bf2f(d0b[t * C + c]) > 0.0f ? f2bf(w[c] * dO) : (uint16_t)0;
-    }
-    // partials: [0] loss, [1] db, [2 + c] dw_c
-    for (int j = 0; j < C + 2 && j < maxc; j++) {
-        float v = 0.0f;
-        if (t < N) v = j == 0 ? loss : (j == 1 ? dO : dO * d0[t * C + (j - 2)]);
-        red[threadIdx.x] = v;
-        __syncthreads();
-        for (int s = 128; s > 0; s >>= 1) {
-            if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) part[(long long)blockIdx.x * maxc + j] = red[0];
-        __syncthreads();
+    if (t >= N) return;
+    const float tg = fminf(fmaxf(target[t] / M, -1.0f), 1.0f);
+    const float q = tg > 0.0f ? pw : 1.0f;
+    const float x = 2.0f * ob[t];
+    const float sp = fmaxf(x, 0.0f) + log1pf(expf(-fabsf(x)));
+    lossb[t] = q * (sp - x * 0.5f * (1.0f + tg));
+    const float dO = q * (tanhf(ob[t]) - tg) / (float)N;
+    dob[t] = dO;
+    for (int c = 0; c < C; c += 8) {
+        const bf8 m = ld8(d0b + t * C + c);
+        float o[8];
+#pragma unroll
+        for (int i = 0; i < 8; i++) o[i] = m.get(i) > 0.0f ? w[c + i] * dO : 0.0f;
+        *(uint4 *)(gd0 + t * C + c) = pack8(o);
     }
 }
 
-__global__ void k_head_reduce(const float *part, int nb, int maxc, int C, float *loss, float *db, float *dw, long long N)
+// partial sums of the head gradient over chunks of HCH pixels: part[chunk][j], j = 0: loss,
+// 1: db = sum dO, 2 + c: dw_c = sum dO d0[., c].  Thread (g, c) = (tid / C, tid % C) adds the
+// pixels g, g + G, ... of the chunk (G = 256 / C groups, channel-coalesced reads), then the groups
+// are added in a fixed order.
+constexpr int HCH = 4096;
+__global__ void __launch_bounds__(256) k_head_grad(const float *d0, const float *dob, const float *lossb, int C,
+                                                   long long N, float *part)
 {
-    const int j = threadIdx.x;
-    if (j >= C + 2) return;
+    __shared__ float red[256], rl[256], rd[256];
+    const int G = 256 / C, tid = threadIdx.x;
+    const int g = tid / C, c = tid % C;
+    const long long p0 = (long long)blockIdx.x * HCH, p1 = p0 + HCH < N ? p0 + HCH : N;
+    float acc = 0.0f, al = 0.0f, ad = 0.0f;
+    if (g < G) {
+        for (long long px = p0 + g; px < p1; px += G) {
+            const float d = dob[px];
+            acc = fmaf(d, d0[px * C + c], acc);
+            if (c == 0) { al += lossb[px]; ad += d; }
+        }
+    }
+    red[tid] = acc; rl[tid] = al; rd[tid] = ad;
+    __syncthreads();
+    const int maxc = C + 2;
+    if (tid < C) {
+        float sw = 0.0f;
+        for (int k = 0; k < G; k++) sw += red[k * C + tid];
+        part[(long long)blockIdx.x * maxc + 2 + tid] = sw;
+    }
+    if (tid == 0) {
+        float sl = 0.0f, sd = 0.0f;
+        for (int k = 0; k < G; k++) { sl += rl[k * C]; sd += rd[k * C]; }
+        part[(long long)blockIdx.x * maxc] = sl;
+        part[(long long)blockIdx.x * maxc + 1] = sd;
+    }
+}
+
+// column j of the partials (one block per column): loss / N, db, dw
+__global__ void __launch_bounds__(256) k_head_reduce(const float *part, int nb, int maxc, float *loss, float *db,
+                                                     float *dw, long long N)
+{
+    __shared__ float red[256];
+    const int j = blockIdx.x;
     float s = 0.0f;
-    for (int b = 0; b < nb; b++) s += part[(long long)b * maxc + j];
-    if (j == 0) loss[0] = s / (float)N;
-    else if (j == 1) db[0] = s;
-    else dw[j - 2] = s;
+    for (int b = threadIdx.x; b < nb; b += 256) s += part[(long long)b * maxc + j];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (j == 0) loss[0] = red[0] / (float)N;
+        else if (j == 1) db[0] = red[0];
+        else dw[j - 2] = red[0];
+    }
 }
 
 // Adam on FP32 master weights
@@ -514,6 +590,7 @@ struct mgseg_net {
     std::vector<uint16_t *> gemid, gdmid, gcat, gpool, gdact;
     uint16_t *gebot = nullptr;
     float *part = nullptr, *partb = nullptr, *hpart = nullptr, *loss = nullptr;
+    float *dob = nullptr, *lossb = nullptr;  // per-pixel dloss/do and loss terms
     std::vector<void *> act_allocs, par_allocs;
     int steps = 0;
     // k_conv launch timing (mgseg_net_profile): event pairs, algorithmic flops
@@ -602,7 +679,9 @@ bool ensure_acts(mgseg_net *n, int B, int H, int W)
     }
     n->part = nalloc<float>(v, (size_t)need, fail);
     n->partb = nalloc<float>(v, (size_t)needb, fail);
-    n->hpart = nalloc<float>(v, (size_t)nblk((long long)B * H * W) * (chan(n, 0) + 2), fail);
+    n->hpart = nalloc<float>(v, (size_t)((B * (long long)H * W + HCH - 1) / HCH) * (chan(n, 0) + 2), fail);
+    n->dob = nalloc<float>(v, (size_t)B * H * W, fail);
+    n->lossb = nalloc<float>(v, (size_t)B * H * W, fail);
     n->loss = nalloc<float>(v, 4, fail);
     if (fail) { free_acts(n); return false; }
     n->B = B; n->H = H; n->W = W;
@@ -804,7 +883,7 @@ mgseg_status mgseg_net_forward(mgseg_net *n, const float *in_dev, int B, int H, 
         const View e = l < D - 1 ? View{n->cat[l], chan(n, l + 1) + ce, chan(n, l + 1)} : View{n->ebot, ce, 0};
         block_fwd(n, s, n->enc[2 * l], n->enc[2 * l + 1], cur, n->emid[l], e, h, w, B);
         if (l < D - 1) {
-            hipLaunchKernelGGL(k_avgpool, dim3(nblk((long long)B * (h / 2) * (w / 2) * ce)), dim3(256), 0, s, e.p,
+            hipLaunchKernelGGL(k_avgpool, dim3(nblk((long long)B * (h / 2) * (w / 2) * (ce / 8))), dim3(256), 0, s, e.p,
                                e.ps, e.off, ce, h / 2, w / 2, B, n->pool[l]);
             cur = View{n->pool[l], ce, 0};
         }
@@ -814,7 +893,7 @@ mgseg_status mgseg_net_forward(mgseg_net *n, const float *in_dev, int B, int H, 
     for (int l = D - 2; l >= 0; l--) {
         const int h = H >> l, w = W >> l;
         const int cu = chan(n, l + 1), ce = chan(n, l);
-        hipLaunchKernelGGL(k_upsample, dim3(nblk((long long)B * h * w * cu)), dim3(256), 0, s, dn, cu, h / 2, w / 2, B,
+        hipLaunchKernelGGL(k_upsample, dim3(nblk((long long)B * h * w * (cu / 8))), dim3(256), 0, s, dn, cu, h / 2, w / 2, B,
                            n->cat[l], cu + ce);
         block_fwd(n, s, n->dec[2 * l], n->dec[2 * l + 1], View{n->cat[l], cu + ce, 0}, n->dmid[l],
                   View{n->dact[l], ce, 0}, h, w, B, l == 0 ? n->d0f : nullptr);
@@ -834,12 +913,13 @@ mgseg_status mgseg_net_backward(mgseg_net *n, const float *target_dev, double M,
     hipStream_t s = (hipStream_t)stream;
     const int D = n->depth, B = n->B, H = n->H, W = n->W, C0 = chan(n, 0);
     const long long NP0 = (long long)B * H * W;
-    const unsigned nb = nblk(NP0);
     const int maxc = C0 + 2;
+    const unsigned nch = (unsigned)((NP0 + HCH - 1) / HCH);
     // head and loss; gradient of d_0 (masked) -> gdact[0]
-    hipLaunchKernelGGL(k_head_bwd, dim3(nb), dim3(256), 0, s, n->ob, target_dev, (float)M, (float)pos_weight, n->d0f,
-                       n->dact[0], C0, NP0, n->hw, n->gdact[0], n->hpart, maxc);
-    hipLaunchKernelGGL(k_head_reduce, dim3(1), dim3(256), 0, s, n->hpart, (int)nb, maxc, C0, n->loss, n->ghb, n->ghw,
+    hipLaunchKernelGGL(k_head_bwd, dim3(nblk(NP0)), dim3(256), 0, s, n->ob, target_dev, (float)M, (float)pos_weight,
+                       n->dact[0], C0, NP0, n->hw, n->gdact[0], n->dob, n->lossb);
+    hipLaunchKernelGGL(k_head_grad, dim3(nch), dim3(256), 0, s, n->d0f, n->dob, n->lossb, C0, NP0, n->hpart);
+    hipLaunchKernelGGL(k_head_reduce, dim3(maxc), dim3(256), 0, s, n->hpart, (int)nch, maxc, n->loss, n->ghb, n->ghw,
                        NP0);
     // decoder, level 0 first
     for (int l = 0; l <= D - 2; l++) {
@@ -850,7 +930,7 @@ mgseg_status mgseg_net_backward(mgseg_net *n, const float *target_dev, double M,
         // up-sampled part of the input -> gradient of the level below's d (or of e_bottom), masked by it
         uint16_t *gdn = (l + 1 <= D - 2) ? n->gdact[l + 1] : n->gebot;
         const uint16_t *ydn = (l + 1 <= D - 2) ? n->dact[l + 1] : n->ebot;
-        hipLaunchKernelGGL(k_upsample_bwd, dim3(nblk((long long)B * (h / 2) * (w / 2) * cu)), dim3(256), 0, s,
+        hipLaunchKernelGGL(k_upsample_bwd, dim3(nblk((long long)B * (h / 2) * (w / 2) * (cu / 8))), dim3(256), 0, s,
                            n->gcat[l], cu + ce, cu, h / 2, w / 2, B, ydn, gdn);
     }
     // encoder, bottom up
@@ -863,7 +943,7 @@ mgseg_status mgseg_net_backward(mgseg_net *n, const float *target_dev, double M,
             const int cu = chan(n, l + 1);
             g = View{n->gcat[l], cu + ce, cu};
             // pooled path: g_e += avgpool^T(g_pool), then the ReLU mask of e
-            hipLaunchKernelGGL(k_avgpool_bwd, dim3(nblk((long long)B * h * w * ce)), dim3(256), 0, s, n->gpool[l], ce,
+            hipLaunchKernelGGL(k_avgpool_bwd, dim3(nblk((long long)B * h * w * (ce / 8))), dim3(256), 0, s, n->gpool[l], ce,
                                h / 2, w / 2, B, g.p, g.ps, g.off, n->cat[l], cu + ce, cu);
         }
         const View x = l == 0 ? View{n->x0, CIN0, 0} : View{n->pool[l - 1], chan(n, l - 1), 0};
