@@ -87,6 +87,11 @@ typedef struct {
     int32_t cycles;         /* V-cycles done since setup / last set_phi0             */
     int32_t levels;
     double frac_fg;         /* fraction of pixels with phi > 0                       */
+    double energy;          /* the model's discrete energy at the finest phi with    */
+                            /* the current c1, c2 (Sec. 2: the Spencer-Chen or       */
+                            /* Rada-Chen functional; central differences, h^2 cells) */
+    double frac_D;          /* fraction of finest cells in the jump set at the last  */
+                            /* freeze (Sec. 4.3)                                     */
 } mgseg_stats;
 
 /* Fills *p with the defaults. */
@@ -141,6 +146,18 @@ mgseg_status mgseg_get_phi(mgseg_ctx *c, double *phi_dev, int pitch);
 mgseg_status mgseg_get_mask(mgseg_ctx *c, uint8_t *mask_dev, int pitch);
 
 mgseg_status mgseg_get_stats(mgseg_ctx *c, mgseg_stats *s);
+
+/* Checkpoint of a solve: the FP64 finest phi with the cycle counter, the
+ * residual norms and eta.  mgseg_get_state writes it to the host buffer
+ * blob of *bytes bytes; with blob = NULL, or *bytes too small (then
+ * MGSEG_E_ARG), it only sets *bytes to the size needed (a 64-byte header +
+ * 8 n m).  mgseg_set_state restores it into a context set up from the same
+ * image, markers and parameters (else MGSEG_E_SHAPE for another shape or
+ * level count, MGSEG_E_ARG for a blob that is not a state): c1, c2 and the
+ * residual are recomputed from phi, so the solve continues exactly as the
+ * one the state was taken from. */
+mgseg_status mgseg_get_state(mgseg_ctx *c, void *blob, size_t *bytes);
+mgseg_status mgseg_set_state(mgseg_ctx *c, const void *blob, size_t bytes);
 
 /* Releases every device buffer of the context (NULL is a no-op). */
 void mgseg_destroy(mgseg_ctx *c);

@@ -27,7 +27,8 @@ enum {
     DS_ETA = 6,               // last relative change of phi (right after DS_RES)
     DS_AREAB0 = 8,            // deviation form: area term at the base of level l is slot DS_AREAB0 + l
     DS_CO = 8 + MAXLEV,       // coarsest-solve changes (2 slots)
-    DS_COUNT = 8 + MAXLEV + 2
+    DS_ENERGY = 8 + MAXLEV + 2,   // the model's energy (mgseg_get_stats)
+    DS_COUNT = 8 + MAXLEV + 3
 };
 
 struct Level {
@@ -857,17 +858,83 @@ mgseg_status mgseg_get_mask(mgseg_ctx *c, uint8_t *mask_dev, int pitch)
 mgseg_status mgseg_get_stats(mgseg_ctx *c, mgseg_stats *s)
 {
     if (!c || !s) return MGSEG_E_ARG;
-    double c12[2] = {0, 0};
+    Level &L0 = c->lev[0];
+    const size_t N = (size_t)c->n * c->m;
+    const int nb = std::min(RED_BLOCKS, std::max(1, (int)((N + 255) / 256)));
+    EnergyArgs E;
+    E.phi = c->phi64; E.g = c->g64; E.d = c->d64; E.dsc = c->dsc + DS_C1; E.z = L0.z; E.pz = L0.prm;
+    E.n = c->n; E.m = c->m; E.model = c->p.model; E.h = c->h0; E.mu = c->p.mu; E.lambda1 = c->p.lambda1;
+    E.lambda2 = c->p.lambda2; E.theta = c->p.theta; E.eps = c->p.eps; E.partial = c->part;
+    hipLaunchKernelGGL(k_energy, dim3(nb), dim3(256), 0, c->s, E);
+    hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(256), 0, c->s, c->part, nb, c->h0 * c->h0, (double)N, c->p.model,
+                       c->p.nu, c->A1, c->dsc + DS_ENERGY);
+    hipLaunchKernelGGL(k_count_labels, dim3(nb), dim3(256), 0, c->s, L0.lab, L0.prm, c->n, c->m, c->part + 2 * RED_BLOCKS);
+    chk(c);
+    double c12[2] = {0, 0}, en = 0.0;
+    std::vector<double> cnt(nb);
     (void)hipMemcpyAsync(c12, c->dsc + DS_C1, sizeof(c12), hipMemcpyDeviceToHost, c->s);
+    (void)hipMemcpyAsync(&en, c->dsc + DS_ENERGY, sizeof(double), hipMemcpyDeviceToHost, c->s);
+    (void)hipMemcpyAsync(cnt.data(), c->part + 2 * RED_BLOCKS, sizeof(double) * nb, hipMemcpyDeviceToHost, c->s);
     mgseg_status st = sync_status(c);
     if (st != MGSEG_OK) return st;
-    std::vector<double> ph((size_t)c->n * c->m);
+    std::vector<double> ph(N);
     (void)hipMemcpy(ph.data(), c->phi64, sizeof(double) * ph.size(), hipMemcpyDeviceToHost);
     size_t fg = 0;
     for (double v : ph) fg += v > 0.0;
+    double nd = 0.0;
+    for (double v : cnt) nd += v;
     s->c1 = c12[0]; s->c2 = c12[1]; s->rel_res = c->rel; s->res = c->res; s->res0 = c->res0;
     s->eta = c->eta; s->cycles = c->cycles; s->levels = c->L;
     s->frac_fg = ph.empty() ? 0.0 : (double)fg / (double)ph.size();
+    s->energy = en;
+    s->frac_D = N ? nd / (double)N : 0.0;
+    return MGSEG_OK;
+}
+
+namespace {
+struct StateHeader {
+    uint64_t magic;
+    int32_t n, m, levels, cycles;
+    double res0, res, rel, eta;
+    uint64_t reserved;
+};
+static_assert(sizeof(StateHeader) == 64, "state header is 64 bytes");
+constexpr uint64_t STATE_MAGIC = 0x3154535347534d47ull;   // "GMSGSST1"
+}  // namespace
+
+mgseg_status mgseg_get_state(mgseg_ctx *c, void *blob, size_t *bytes)
+{
+    if (!c || !bytes) return MGSEG_E_ARG;
+    const size_t N = (size_t)c->n * c->m, need = sizeof(StateHeader) + sizeof(double) * N;
+    if (!blob) { *bytes = need; return MGSEG_OK; }
+    if (*bytes < need) { *bytes = need; return MGSEG_E_ARG; }
+    StateHeader h{STATE_MAGIC, c->n, c->m, c->L, c->cycles, c->res0, c->res, c->rel, c->eta, 0};
+    std::memcpy(blob, &h, sizeof(h));
+    (void)hipMemcpyAsync(static_cast<char *>(blob) + sizeof(h), c->phi64, sizeof(double) * N, hipMemcpyDeviceToHost,
+                         c->s);
+    mgseg_status st = sync_status(c);
+    if (st != MGSEG_OK) return st;
+    *bytes = need;
+    return MGSEG_OK;
+}
+
+mgseg_status mgseg_set_state(mgseg_ctx *c, const void *blob, size_t bytes)
+{
+    if (!c || !blob || bytes < sizeof(StateHeader)) return MGSEG_E_ARG;
+    StateHeader h;
+    std::memcpy(&h, blob, sizeof(h));
+    if (h.magic != STATE_MAGIC) return MGSEG_E_ARG;
+    if (h.n != c->n || h.m != c->m || h.levels != c->L) return MGSEG_E_SHAPE;
+    const size_t N = (size_t)c->n * c->m;
+    if (bytes < sizeof(h) + sizeof(double) * N || h.cycles < 0) return MGSEG_E_ARG;
+    Level &L0 = c->lev[0];
+    (void)hipMemcpyAsync(c->phi64, static_cast<const char *>(blob) + sizeof(h), sizeof(double) * N,
+                         hipMemcpyHostToDevice, c->s);
+    hipLaunchKernelGGL(k_copy64to32, grid2(c->n, c->m), dim3(256), 0, c->s, c->phi64, c->n, c->m, L0.P[0], L0.prm);
+    refresh_and_residual(c);
+    mgseg_status st = sync_status(c);
+    if (st != MGSEG_OK) return st;
+    c->res0 = h.res0; c->res = h.res; c->rel = h.rel; c->eta = h.eta; c->cycles = h.cycles;
     return MGSEG_OK;
 }
 

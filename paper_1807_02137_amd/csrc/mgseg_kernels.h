@@ -1004,3 +1004,91 @@ __global__ void k_markers_inside(const float *phi, int n, int m, const double *m
     __syncthreads();
     if (threadIdx.x == 0) flag[0] = bad ? 0 : 1;
 }
+
+// The model's discrete energy at the finest FP64 phi (Sec. 2, the functional
+// whose Euler-Lagrange equation the cycle solves): per cell h^2 times
+//   mu w delta_eps(phi) |grad phi| + lambda1 (z - c1)^2 H + lambda2 (z - c2)^2 (1 - H) (+ theta d H, Spencer-Chen)
+// with central differences at mirrored edges and w = g (Spencer-Chen) or g d
+// (Rada-Chen).  Per-block partials of the sum and of sum H, in FP64.
+struct EnergyArgs {
+    const double *phi, *g, *d, *dsc;
+    const float *z;
+    int pz, n, m, model;
+    double h, mu, lambda1, lambda2, theta, eps;
+    double *partial;
+};
+__global__ void __launch_bounds__(256) k_energy(EnergyArgs A)
+{
+    __shared__ double r0[256], r1[256];
+    const int tid = threadIdx.x;
+    const long long N = (long long)A.n * A.m;
+    const double c1 = A.dsc[0], c2 = A.dsc[1];
+    double e = 0.0, sh = 0.0;
+    for (long long t = (long long)blockIdx.x * blockDim.x + tid; t < N; t += (long long)gridDim.x * blockDim.x) {
+        const int i = (int)(t / A.m), j = (int)(t % A.m);
+        const double ph = A.phi[t];
+        const double gx = (A.phi[(long long)i * A.m + mg_mirror(j + 1, A.m)] - A.phi[(long long)i * A.m + mg_mirror(j - 1, A.m)]) /
+                          (2.0 * A.h);
+        const double gy = (A.phi[(long long)mg_mirror(i + 1, A.n) * A.m + j] - A.phi[(long long)mg_mirror(i - 1, A.n) * A.m + j]) /
+                          (2.0 * A.h);
+        const double H = mg_heav64(ph, A.eps);
+        const double zz = (double)A.z[(long long)i * A.pz + j];
+        const double a = zz - c1, b = zz - c2;
+        const double w = A.model == 1 ? A.g[t] * A.d[t] : A.g[t];
+        double v = A.mu * w * mg_delta64(ph, A.eps) * sqrt(gx * gx + gy * gy) + A.lambda1 * a * a * H +
+                   A.lambda2 * b * b * (1.0 - H);
+        if (A.model == 0) v += A.theta * A.d[t] * H;
+        e += v;
+        sh += H;
+    }
+    r0[tid] = e; r1[tid] = sh;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s) { r0[tid] += r0[tid + s]; r1[tid] += r1[tid + s]; }
+        __syncthreads();
+    }
+    if (tid == 0) { A.partial[2 * blockIdx.x] = r0[0]; A.partial[2 * blockIdx.x + 1] = r1[0]; }
+}
+
+// adds the nb partials of k_energy in a fixed order: out = h^2 sum + (Rada-Chen) nu (a1^2 + a2^2),
+// a1 = h^2 sum H - A1, a2 = h^2 (N - sum H) - (1 - A1)
+__global__ void __launch_bounds__(256) k_energy_final(const double *partial, int nb, double h2, double N, int model,
+                                                      double nu, double A1, double *out)
+{
+    __shared__ double r0[256], r1[256];
+    const int tid = threadIdx.x;
+    double e = 0.0, sh = 0.0;
+    for (int b = tid; b < nb; b += 256) { e += partial[2 * b]; sh += partial[2 * b + 1]; }
+    r0[tid] = e; r1[tid] = sh;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s) { r0[tid] += r0[tid + s]; r1[tid] += r1[tid + s]; }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        double E = r0[0] * h2;
+        if (model == 1) {
+            const double a1 = h2 * r1[0] - A1, a2 = h2 * (N - r1[0]) - (1.0 - A1);
+            E += nu * (a1 * a1 + a2 * a2);
+        }
+        out[0] = E;
+    }
+}
+
+// per-block counts of the nonzero labels of an n x m byte grid with row pitch p
+__global__ void __launch_bounds__(256) k_count_labels(const uint8_t *lab, int p, int n, int m, double *partial)
+{
+    __shared__ double r[256];
+    const int tid = threadIdx.x;
+    const long long N = (long long)n * m;
+    double cnt = 0.0;
+    for (long long t = (long long)blockIdx.x * blockDim.x + tid; t < N; t += (long long)gridDim.x * blockDim.x)
+        cnt += lab[(t / m) * p + t % m] != 0 ? 1.0 : 0.0;
+    r[tid] = cnt;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s) r[tid] += r[tid + s];
+        __syncthreads();
+    }
+    if (tid == 0) partial[blockIdx.x] = r[0];
+}

@@ -43,7 +43,7 @@ class _Params(C.Structure):
 class _Stats(C.Structure):
     _fields_ = [("c1", C.c_double), ("c2", C.c_double), ("rel_res", C.c_double), ("res", C.c_double),
                 ("res0", C.c_double), ("eta", C.c_double), ("cycles", C.c_int32), ("levels", C.c_int32),
-                ("frac_fg", C.c_double)]
+                ("frac_fg", C.c_double), ("energy", C.c_double), ("frac_D", C.c_double)]
 
 
 @dataclass
@@ -108,6 +108,8 @@ def lib():
         L.mgseg_debug_set_c.argtypes = [vp, C.c_double, C.c_double]
         L.mgseg_debug_op.argtypes = [vp, C.c_int, C.c_int, C.c_int]
         L.mgseg_profile.argtypes = [vp, C.c_int, C.c_int]
+        L.mgseg_get_state.argtypes = [vp, vp, C.POINTER(C.c_size_t)]
+        L.mgseg_set_state.argtypes = [vp, vp, C.c_size_t]
         L.mgseg_profile_read.argtypes = [vp, C.c_int, dp, ip, dp]
         L.mgseg_setup_batch.argtypes = [C.c_int, C.POINTER(vp), ip, ip, ip, C.POINTER(C.POINTER(C.c_float)), ip,
                                         C.POINTER(_Params), vp, C.POINTER(vp)]
@@ -138,7 +140,8 @@ def lib():
                      "mgseg_batch_set_streams", "mgseg_solve_batch", "mgseg_batch_ctx", "mgseg_net_create",
                      "mgseg_net_forward", "mgseg_net_backward", "mgseg_net_adam_step", "mgseg_net_param_count",
                      "mgseg_net_get_params", "mgseg_net_set_params", "mgseg_ctx_features", "mgseg_predict_phi0",
-                     "mgseg_reset_phi0", "mgseg_net_profile", "mgseg_net_profile_read"):
+                     "mgseg_reset_phi0", "mgseg_net_profile", "mgseg_net_profile_read",
+                     "mgseg_get_state", "mgseg_set_state"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -236,6 +239,19 @@ class Solver:
     def reset_phi0(self):
         """Back to the marker-based initial level set of setup."""
         _check(self.L.mgseg_reset_phi0(self.ctx), "mgseg_reset_phi0")
+
+    def get_state(self) -> bytes:
+        """Checkpoint: the FP64 finest phi with the cycle counter and residual norms."""
+        n = C.c_size_t(0)
+        _check(self.L.mgseg_get_state(self.ctx, None, C.byref(n)), "mgseg_get_state")
+        buf = C.create_string_buffer(n.value)
+        _check(self.L.mgseg_get_state(self.ctx, buf, C.byref(n)), "mgseg_get_state")
+        return buf.raw[:n.value]
+
+    def set_state(self, blob: bytes):
+        """Resume from get_state() of a solve of the same image, markers and parameters."""
+        buf = C.create_string_buffer(bytes(blob), len(blob))
+        _check(self.L.mgseg_set_state(self.ctx, buf, len(blob)), "mgseg_set_state")
 
     # ---- single steps (tests, profiling)
     def shape(self, level=0):

@@ -309,3 +309,63 @@ def test_batch_tuner_picks_a_stream_count():
     cyc, rel, ok = b.solve(1e-6, 40)
     assert ok
     b.close()
+
+
+# ---------------------------------------------------------------- energy, jump-set share, checkpoint
+@pytest.mark.parametrize("model", [0, 1])
+def test_energy_and_jump_share_match_the_oracle(model):
+    """The model's discrete energy at the GPU's converged phi (with the c1, c2
+    of that phi) against the oracle's energy at the same phi; the share of
+    finest cells in the jump set after a freeze against the oracle's labels
+    (which may differ in at most 2 near-tie cells)."""
+    say(f"case energy model {model} seed 1000")
+    inst = synth.config1(1000)
+    s = mgseg.Solver(inst.image, inst.markers, mgseg.Params(levels=6, model=model))
+    o = Oracle(inst.image, inst.markers, OracleParams(levels=6, model=model))
+    s.solve(1e-6, 60)
+    o.set("phi", s.phi().cpu().numpy())
+    o.update_c()
+    e_gpu, e_or = s.stats()["energy"], o.energy()
+    say(f"  energy GPU {e_gpu:.15g} oracle {e_or:.15g}")
+    assert abs(e_gpu - e_or) <= 1e-12 * abs(e_or)
+    s.op("freeze", 0)
+    o.freeze(0)
+    fd = s.stats()["frac_D"]
+    lab = o.labels()
+    assert abs(fd - (lab != 0).mean()) <= 2.0 / lab.size
+    assert 0.0 < fd < 1.0
+    s.close()
+
+
+def test_checkpoint_resumes_the_same_solve():
+    """A solve stopped after 3 cycles, saved, and resumed in a fresh context
+    from the same inputs ends bit for bit where the uninterrupted solve ends."""
+    say("case checkpoint seed 1001")
+    inst = synth.config1(1001)
+    p = mgseg.Params(levels=6)
+    a = mgseg.Solver(inst.image, inst.markers, p)
+    for _ in range(3):
+        a.vcycle()
+    blob = a.get_state()
+    assert len(blob) == 64 + 8 * 128 * 128
+    ca, ra, oka = a.solve(1e-6, 60)
+    phi_a, st_a = a.phi().cpu().numpy(), a.stats()
+    b = mgseg.Solver(inst.image, inst.markers, p)
+    b.set_state(blob)
+    assert b.stats()["cycles"] == 3
+    cb, rb, okb = b.solve(1e-6, 60)
+    phi_b, st_b = b.phi().cpu().numpy(), b.stats()
+    assert oka and okb and ca == cb and ra == rb
+    assert np.array_equal(phi_a, phi_b)
+    assert st_a["cycles"] == st_b["cycles"] and st_a["res0"] == st_b["res0"]
+    # a state of another shape or a damaged blob is refused
+    c = mgseg.Solver(inst.image[:64, :64], inst.markers[inst.markers.max(axis=1) < 64] if
+                     (inst.markers.max(axis=1) < 64).any() else np.array([[10.5, 10.5]]), mgseg.Params(levels=5))
+    with pytest.raises(mgseg.MgsegError):
+        c.set_state(blob)
+    with pytest.raises(mgseg.MgsegError):
+        b.set_state(b"\0" * len(blob))
+    with pytest.raises(mgseg.MgsegError):
+        b.set_state(blob[:100])
+    for x in (a, b, c):
+        x.close()
