@@ -111,7 +111,9 @@ const char *mgseg_strerror(mgseg_status s);
  *   markers_host     : k (row, col) pairs of floats in pixel coordinates;
  *                      the centre of cell (i, j) is (i + 0.5, j + 0.5);
  *                      every marker inside the image (0 <= row < n,
- *                      0 <= col < m), 1 <= k <= 64.
+ *                      0 <= col < m), 1 <= k <= 64 (Rada-Chen: k >= 3,
+ *                      for its polygon area A1).
+ *   n, m             : at least 2.
  *   stream           : a hipStream_t (0 = default stream), passed as void*.
  * Errors: MGSEG_E_ARG (null pointers, k out of range, a marker outside the
  * image or not finite, pitch < m, bad struct_size),

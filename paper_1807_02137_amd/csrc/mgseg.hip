@@ -679,8 +679,9 @@ mgseg_status mgseg_setup(const float *image_dev, int n, int m, int pitch, const 
 {
     if (!out) return MGSEG_E_ARG;
     *out = nullptr;
-    if (!image_dev || !markers_host || !p || k < 1 || k > 64 || n < 1 || m < 1 || pitch < m) return MGSEG_E_ARG;
+    if (!image_dev || !markers_host || !p || k < 1 || k > 64 || n < 2 || m < 2 || pitch < m) return MGSEG_E_ARG;
     if (p->struct_size != sizeof(mgseg_params)) return MGSEG_E_ARG;
+    if (p->model == MGSEG_RADA_CHEN && k < 3) return MGSEG_E_ARG;   // the marker polygon needs an area (A1 > 0)
     if (p->nu1 < 0 || p->nu2 < 0 || p->coarse_iters < 0 || !(p->coarse_rtol >= 0.0) || !(p->M > 0.0) || !(p->eps > 0.0) || p->levels < 0 ||
         p->levels > MAXLEV)
         return MGSEG_E_ARG;

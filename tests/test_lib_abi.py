@@ -68,7 +68,27 @@ def test_setup_rejects_bad_arguments_before_any_device_work(lib):
     # non-finite marker
     bad = (C.c_float * 6)(10, float("nan"), 10, 20, 20, 15)
     assert lib.mgseg_setup(img, 64, 64, 64, bad, 3, C.byref(p), None, C.byref(out)) == 1
+    # marker outside the image
+    far = (C.c_float * 6)(10, 10, 64, 20, 20, 15)
+    assert lib.mgseg_setup(img, 64, 64, 64, far, 3, C.byref(p), None, C.byref(out)) == 1
+    neg = (C.c_float * 6)(10, 10, 10, -0.5, 20, 15)
+    assert lib.mgseg_setup(img, 64, 64, 64, neg, 3, C.byref(p), None, C.byref(out)) == 1
+    # a grid of one row or column
+    assert lib.mgseg_setup(img, 1, 64, 64, mk, 3, C.byref(mgseg.Params(levels=1).to_c()), None, C.byref(out)) == 1
+    # Rada-Chen needs a marker polygon of positive area: at least 3 markers
+    rc = mgseg.Params(model=1).to_c()
+    assert lib.mgseg_setup(img, 64, 64, 64, mk, 2, C.byref(rc), None, C.byref(out)) == 1
     assert not out.value
+    # network sizes
+    net = C.c_void_p()
+    for base, depth in ((8, 3), (24, 3), (0, 3), (16, 1), (16, 7), (64, 5)):
+        assert lib.mgseg_net_create(base, depth, 0, C.byref(net)) == 1
+    assert not net.value
+    # checkpoint and batch entry points with null handles
+    n = C.c_size_t(0)
+    assert lib.mgseg_get_state(None, None, C.byref(n)) == 1
+    assert lib.mgseg_set_state(None, None, 0) == 1
+    assert lib.mgseg_solve_batch(None, 1e-6, 10, None, None) == 1
     # null context everywhere
     assert lib.mgseg_vcycle(None, None) == 1
     assert lib.mgseg_solve(None, 1e-6, 10, None, None) == 1
