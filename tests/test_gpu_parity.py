@@ -179,6 +179,51 @@ def test_solve_parity_ragged_shapes(shape):
     s.close()
 
 
+def long_line_instance(n, m, tiles=8, seed=11):
+    """Tiles of one disc each side by side, so that the jump set (and so the
+    starred units) appears all along lines of m cells; transposed when n > m."""
+    tr = n > m
+    a, b = (m, n) if tr else (n, m)
+    parts = [synth.tiny_instance(seed + t, a, b // tiles) for t in range(tiles)]
+    img = np.concatenate([p.image for p in parts], axis=1)
+    mk = parts[0].markers
+    if tr:
+        img, mk = np.ascontiguousarray(img.T), mk[:, ::-1].copy()
+    return img, mk
+
+
+@pytest.mark.parametrize("shape", [(32, 1600), (32, 2304), (2304, 32)])
+@pytest.mark.parametrize("sweep", [0, 1, 2, 3])
+def test_single_sweep_long_lines(shape, sweep):
+    """Lines longer than one 1024-thread workgroup: 2 cells per thread with the
+    unit rows in LDS (1600 cells), 4 cells per thread with the rows in the
+    global scratch plane (2304 cells, along the rows and along the columns);
+    one sweep from the same frozen state and labels against the oracle."""
+    n, m = shape
+    say("case long-line sweep", "ABCD"[sweep], n, m)
+    img, mk = long_line_instance(n, m)
+    s = mgseg.Solver(img, mk, mgseg.Params(levels=3, mixed_precision=0))
+    o = Oracle(img, mk, OracleParams(levels=3))
+    o.smooth(2, 0)
+    phi = o.get("phi")
+    s.set("phi", phi.astype(np.float32))
+    o.set("phi", phi.astype(np.float32).astype(np.float64))
+    s.op("freeze", 0)
+    o.freeze(0)
+    lab = o.labels()
+    s.set("labels", lab)
+    s.op(["sweep_A", "sweep_B", "sweep_C", "sweep_D"][sweep], 0)
+    o.sweep(sweep, 0)
+    d = np.abs(s.get("phi").astype(np.float64) - o.get("phi"))
+    starred = (lab >> sweep) & 1
+    long_axis = 1 if m > n else 0
+    beyond = np.nonzero(starred.any(axis=1 - long_axis))[0]
+    say("max |dphi|", d.max(), "starred", int(starred.sum()), "last starred position", int(beyond.max()) if beyond.size else -1)
+    assert beyond.size and beyond.max() > 1024        # units beyond the first workgroup's cells
+    assert d.max() <= 2e-4
+    s.close()
+
+
 @pytest.mark.parametrize("k", [1, 2])
 def test_degenerate_marker_sets(k):
     """One or two markers: the marker hull is a point or a segment (zero area)."""
