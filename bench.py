@@ -63,6 +63,24 @@ def calibrate_copy(mib: int = 1024):
     b.copy_(a)
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes": a.numel() * 4}))
+def copy_bandwidth(mib: int = 1024, reps: int = 5) -> float:
+    """GB/s of a plain device-to-device copy of `mib` MiB (read + write counted),
+    best of `reps`: the bandwidth a streaming kernel reaches on this GPU."""
+    import torch
+    a = torch.empty(mib * (1 << 20) // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    best = 0.0
+    for _ in range(reps + 1):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        best = max(best, 2 * a.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9)
+    del a, b
+    return best
+
+
 SEED = 2000
 N = 1024
 LEVELS = 9
@@ -216,6 +234,59 @@ def warmstart_bench(steps: int, warmup: int, count: int):
     }))
 
 
+def large_bench(steps: int, max_cycles: int = MAX_CYCLES):
+    """The 8192x8192 solve: 200 star polygons (seed 4000), 12 grids down to 4x4
+    (carried down to 1x1 the cycle does not converge on this content, in the
+    oracle either), FP32 cycles + FP64 finest residual, to rel. residual 1e-6
+    (at most max_cycles).  Lines of 8192 cells run 8 cells per thread."""
+    import torch
+    from paper_1807_02137_amd import build, mgseg, synth
+    if not os.path.exists(build.LIB):
+        build.build()
+    t0 = time.perf_counter()
+    inst = synth.config4(4000)
+    print(f"c4: image drawn in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    torch.cuda.set_device(0)
+    n = inst.image.shape[0]
+    img = torch.from_numpy(inst.image).to("cuda")
+    params = mgseg.Params(levels=12)
+    stream = torch.cuda.current_stream()
+    cycles, rels, oks = [], [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        s = mgseg.Solver(img, inst.markers, params, stream=stream)
+        cyc, rel, ok = s.solve(TOL, max_cycles)
+        s.close()
+        cycles.append(cyc); rels.append(rel); oks.append(ok)
+        print(f"c4: solve {len(cycles)}: {cyc} cycles, rel {rel:.2e}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    # finest-sweep timing: 3 event-profiled cycles
+    s = mgseg.Solver(img, inst.markers, params, stream=stream)
+    s.profile(True)
+    for _ in range(3):
+        s.vcycle()
+    prof_ms, prof_n, prof_bytes = s.profile_read()
+    s.close()
+    avg_ms = prof_ms / max(prof_n, 1)
+    achieved = prof_bytes / (avg_ms * 1e-3) / 1e9 if prof_n else 0.0
+    copy = copy_bandwidth()
+    print(json.dumps({
+        "metric": "grid-pts/s per V-cycle (solve to rel. residual 1e-6)",
+        "value": n * n * sum(cycles) / wall, "unit": "grid-pts/s per V-cycle", "n_gpus": 1, "steps": steps,
+        "warmup": 0, "ms_per_step": wall / steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "8192x8192 image of 200 star polygons, 8 markers, Spencer-Chen, FAS V(2,2), "
+                               "12 grids (4x4 coarsest), Hybrid Smoother 2, tol 1e-6", "seed": 4000},
+        "cycles_per_solve": cycles, "rel_res": rels, "converged": all(oks),
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "copy_gbs": copy,
+                     "frac_of_copy": achieved / copy, "kernel": "k_sweep (finest-grid directional sweep, 8192-cell lines)",
+                     "launches": prof_n, "avg_us": avg_ms * 1e3, "bytes_per_launch": prof_bytes},
+    }))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -225,11 +296,14 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain copy of known size (counter calibration) and exit")
-    ap.add_argument("--workload", default="c2", choices=("c2", "c3", "c5"),
+    ap.add_argument("--workload", default="c2", choices=("c2", "c3", "c4", "c5"),
                     help="c2: the 1024x1024 solve (default); c3: the 64-image batch of uneven sizes; "
-                         "c5: the learned warm start on 512x512 held-out images")
+                         "c4: the 8192x8192 solve; c5: the learned warm start on 512x512 held-out images")
+    ap.add_argument("--model", default="sc", choices=("sc", "rc"),
+                    help="c2 only: Spencer-Chen (default) or Rada-Chen")
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--c5-images", type=int, default=16)
+    ap.add_argument("--max-cycles", type=int, default=MAX_CYCLES, help="c4 only: cycle cap of a solve")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -245,6 +319,9 @@ def main():
     if args.workload == "c5":
         warmstart_bench(args.steps, args.warmup, args.c5_images)
         return
+    if args.workload == "c4":
+        large_bench(args.steps, args.max_cycles)
+        return
     import torch
 
     from paper_1807_02137_amd import build, mgseg, synth
@@ -253,7 +330,8 @@ def main():
     torch.cuda.set_device(0)
     inst = synth.config2(SEED, N)
     img = torch.from_numpy(inst.image).to("cuda")
-    params = mgseg.Params(levels=LEVELS)
+    model = 1 if args.model == "rc" else 0
+    params = mgseg.Params(levels=LEVELS, model=model)
     stream = torch.cuda.current_stream()
 
     def step(profile=False):
@@ -284,12 +362,13 @@ def main():
     value = npts * sum(cycles) / wall
     avg_ms = prof_ms / max(prof_n, 1)
     achieved = prof_bytes / (avg_ms * 1e-3) / 1e9 if prof_n else 0.0
+    copy = copy_bandwidth()
 
     cpu = None
     if not args.no_cpu_baseline:
         from oracle import Oracle, OracleParams
         tc0 = time.perf_counter()
-        o = Oracle(inst.image, inst.markers, OracleParams(levels=LEVELS))
+        o = Oracle(inst.image, inst.markers, OracleParams(levels=LEVELS, model=model))
         k = 0
         while True:
             o.vcycle()
@@ -297,9 +376,15 @@ def main():
             if time.perf_counter() - tc0 >= args.cpu_seconds:
                 break
         tc = time.perf_counter() - tc0
+        model_name = "unknown CPU"
+        try:
+            with open("/proc/cpuinfo") as fh:
+                model_name = next(l.split(":", 1)[1].strip() for l in fh if l.startswith("model name"))
+        except (OSError, StopIteration):
+            pass
         cpu = {"value": npts * k / tc, "unit": "grid-pts/s per V-cycle", "cores": 1, "kind": "oracle",
                "sample": f"oracle setup + {k} V-cycles of the same 1024x1024 image ({tc:.1f} s, "
-                         "single-threaded FP64 C)"}
+                         f"single-threaded FP64 C, gcc -O2, {model_name}, {os.cpu_count()} host threads visible)"}
 
     out = {
         "metric": "grid-pts/s per V-cycle (solve to rel. residual 1e-6)",
@@ -314,7 +399,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64",
         "data": "synthetic",
-        "config": {"workload": "1024x1024 12-ellipse image, 6 markers, Spencer-Chen, FAS V(2,2), "
+        "config": {"workload": "1024x1024 12-ellipse image, 6 markers, "
+                               f"{'Rada-Chen' if model else 'Spencer-Chen'}, FAS V(2,2), "
                                "9 grids, Hybrid Smoother 2, tol 1e-6", "seed": SEED,
                    "parallelism": "single GPU"},
         "cycles_per_solve": cycles,
@@ -322,7 +408,8 @@ def main():
         "converged": all(oks),
         "time_to_tol_ms": wall / args.steps * 1e3,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic() if not model else None,
+                     "copy_gbs": copy, "frac_of_copy": achieved / copy,
                      "kernel": "k_sweep (finest-grid directional sweep)",
                      "launches": prof_n, "avg_us": avg_ms * 1e3, "bytes_per_launch": prof_bytes},
         "cpu_baseline": cpu,
