@@ -59,7 +59,6 @@ struct mgseg_ctx {
     double *dsc = nullptr;          // device scalars
     double *part = nullptr;         // reduction partials
     int part_n = 0;
-    float *scr = nullptr;           // unit-row scratch of long lines
     float *co_prev = nullptr, *co_entry = nullptr;   // multi-kernel coarsest solve
     int *flags = nullptr;           // device flags: [0] coarsest solve finished, [1] markers inside phi0
     double *hres = nullptr;         // pinned host copy of DS_RES, DS_ETA
@@ -248,7 +247,6 @@ void launch_sweep(mgseg_ctx *c, int l, int s, const float *phi_old, float *phi_n
     const bool bnd = l > 0 || devm(c);
     A.lo = bnd ? (cm ? L.lo_cm : L.lo) : nullptr;
     A.hi = bnd ? (cm ? L.hi_cm : L.hi) : nullptr;
-    A.scr = c->scr;
     A.area = c->p.model == 1 ? c->dsc + DS_AREA_FRZ : nullptr;
     A.pitch = cm ? L.pcm : L.prm;
     A.lpitch = A.pitch;
@@ -259,15 +257,20 @@ void launch_sweep(mgseg_ctx *c, int l, int s, const float *phi_old, float *phi_n
     bool rev = (s == 1 || s == 3);
     int bands = (A.nl + 3) / 4;
     int ml = A.ml;
-    if (ml > 8192) {   // one workgroup holds a whole line: 1024 threads x 8 cells
+    if (ml > 8192) {   // setup accepts sides up to 8192
         if (c->err == hipSuccess) c->err = hipErrorInvalidValue;
         return;
     }
-    const size_t lds = sweep_lds_bytes(ml);
+    const size_t lds = sweep_lds_bytes(ml), llds = long_lds_bytes<1024>(ml);
 #define MG_SWEEP(NT, K)                                                                                  \
     do {                                                                                                 \
         if (rev) hipLaunchKernelGGL((k_sweep<NT, K, true>), dim3(bands), dim3(NT), lds, c->s, A);     \
         else hipLaunchKernelGGL((k_sweep<NT, K, false>), dim3(bands), dim3(NT), lds, c->s, A);        \
+    } while (0)
+#define MG_SWEEP_LONG()                                                                                    \
+    do {                                                                                                   \
+        if (rev) hipLaunchKernelGGL((k_sweep_long<1024, true>), dim3(bands), dim3(1024), llds, c->s, A);  \
+        else hipLaunchKernelGGL((k_sweep_long<1024, false>), dim3(bands), dim3(1024), llds, c->s, A);     \
     } while (0)
     hipEvent_t e0 = nullptr, e1 = nullptr;
     bool timed = c->prof_on && l == 0;
@@ -289,10 +292,9 @@ void launch_sweep(mgseg_ctx *c, int l, int s, const float *phi_old, float *phi_n
     else if (ml <= 256) MG_SWEEP(256, 1);
     else if (ml <= 512) MG_SWEEP(512, 1);
     else if (ml <= 1024) MG_SWEEP(1024, 1);
-    else if (ml <= 2048) MG_SWEEP(1024, 2);
-    else if (ml <= 4096) MG_SWEEP(1024, 4);
-    else MG_SWEEP(1024, 8);
+    else MG_SWEEP_LONG();
 #undef MG_SWEEP
+#undef MG_SWEEP_LONG
     if (timed) {
         (void)hipEventRecord(e1, c->s);
         c->ev_used.push_back({e0, e1});
@@ -699,6 +701,21 @@ mgseg_status mgseg_setup(const float *image_dev, int n, int m, int pitch, const 
     int div = 1 << (Lv - 1);
     if (n % div || m % div) return MGSEG_E_SHAPE;
     if (n > 8192 || m > 8192) return MGSEG_E_SHAPE;
+    // lines longer than one workgroup keep the band's previous and recomputed
+    // lines in LDS: the device must allow that much per workgroup
+    if (std::max(n, m) > 1024) {
+        const size_t need = long_lds_bytes<1024>(std::max(n, m));   // dynamic; the wave totals are static
+        int dev = 0, lds_max = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+            return MGSEG_E_HIP;
+        if (need + 2 * (1024 / 64) * sizeof(Ramp) > (size_t)lds_max) return MGSEG_E_SHAPE;
+        if (hipFuncSetAttribute(reinterpret_cast<const void *>(&k_sweep_long<1024, false>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)need) != hipSuccess ||
+            hipFuncSetAttribute(reinterpret_cast<const void *>(&k_sweep_long<1024, true>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)need) != hipSuccess)
+            return MGSEG_E_HIP;
+    }
 
     mgseg_ctx *c = new (std::nothrow) mgseg_ctx();
     if (!c) return MGSEG_E_NOMEM;
@@ -727,11 +744,6 @@ mgseg_status mgseg_setup(const float *image_dev, int n, int m, int pitch, const 
     c->dsc = dalloc<double>(c, DS_COUNT);
     c->part_n = 8 * RED_BLOCKS + (int)((N + 255) / 256) + n + 16;
     c->part = dalloc<double>(c, (size_t)c->part_n);
-    // unit rows of lines longer than the LDS holds: one plane per band
-    size_t scr_n = 1;
-    if (std::max(n, m) > RB_LDS_MAX)
-        scr_n = (size_t)RF_COUNT * std::max((size_t)((n + 3) / 4) * m, (size_t)((m + 3) / 4) * n);
-    c->scr = dalloc<float>(c, scr_n);
     {
         const Level &Lc = c->lev[Lv - 1];
         c->co_prev = dalloc<float>(c, (size_t)Lc.n * Lc.prm);

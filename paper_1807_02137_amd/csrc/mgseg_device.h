@@ -99,7 +99,6 @@ struct LineArgs {
     const int *skip;                    // non-null and set: the launch does nothing
     float *tout;                        // non-null: new values written transposed,
     int tpitch;                         //   cell q of line r at tout[q * tpitch + r]
-    float *scr;                         // unit-row scratch of lines longer than RB_LDS_MAX
     const double *area;                 // Rada-Chen area term (null: 0)
     int pitch, lpitch, nl, ml;
     float kap, e2, M, eps;
@@ -118,15 +117,36 @@ struct LineArgs {
 
 // Row buffer of the line being swept, indexed by visit position p:
 //   a y_{p-1} - y_p + c y_{p+1} = r  (a = NaN marks S = 0), box [lo, hi],
-// x = old value, y = new value of a unit cell.  LDS for lines up to
-// RB_LDS_MAX cells, else a global scratch plane of the band.
+// x = old value, y = new value of a unit cell.  In LDS: the whole line for
+// lines of one workgroup, a ring of two rounds for longer lines.
 enum { RF_A = 0, RF_C, RF_R, RF_LO, RF_HI, RF_X, RF_Y, RF_COUNT };
-#define RB_LDS_MAX 2048
 
 struct RunBuf {
     float *p;
     int fs;            // elements between fields (>= line length)
     __device__ __forceinline__ float &at(int f, int q) const { return p[f * fs + q]; }
+    // old value of the cell after position `last` (0 past the line end)
+    __device__ __forceinline__ float sig_after(int last, int ml) const
+    {
+        return last + 1 < ml ? at(RF_X, last + 1) : 0.0f;
+    }
+    __device__ __forceinline__ float &y(int q) const { return at(RF_Y, q); }
+};
+
+// 64-bit starred-mask words of a line of ml cells
+__host__ __device__ inline int sweep_mask_words(int ml) { return (ml + 63) / 64; }
+
+// Row buffer of lines longer than one workgroup: a ring of SLOTS positions
+// (two rounds of the line).  Only unit cells are stored; the successor's old
+// value sits beside each cell (RG_S), and a unit's new values overwrite its
+// RF_A entries once the unit has read its rows (only the unit reads them).
+enum { RG_S = RF_Y };
+template <int SLOTS>
+struct RingBuf {
+    float *p;
+    __device__ __forceinline__ float &at(int f, int q) const { return p[f * SLOTS + (q & (SLOTS - 1))]; }
+    __device__ __forceinline__ float sig_after(int last, int) const { return at(RG_S, last); }
+    __device__ __forceinline__ float &y(int q) const { return at(RF_A, q); }
 };
 
 // Units of one or two cells in closed form.  The box-constrained problem of
@@ -140,19 +160,20 @@ struct PairRows {
     float a0, c0, r0, lo0, hi0, x0, a1, al1, lo1, hi1, x1;   // al1 = c1 sig - r1
     bool ok;
 };
-__device__ __forceinline__ void pair_load(const RunBuf &B, int ps, int L, int ml, PairRows &P)
+template <class Buf>
+__device__ __forceinline__ void pair_load(const Buf &B, int ps, int L, int ml, PairRows &P)
 {
     P.a0 = B.at(RF_A, ps); P.c0 = B.at(RF_C, ps); P.r0 = B.at(RF_R, ps);
     P.lo0 = B.at(RF_LO, ps); P.hi0 = B.at(RF_HI, ps); P.x0 = B.at(RF_X, ps);
     P.ok = !isnan(P.a0);
     if (L == 2) {
         P.a1 = B.at(RF_A, ps + 1);
-        const float sig = ps + 2 < ml ? B.at(RF_X, ps + 2) : 0.0f;
+        const float sig = B.sig_after(ps + 1, ml);
         P.al1 = B.at(RF_C, ps + 1) * sig - B.at(RF_R, ps + 1);
         P.lo1 = B.at(RF_LO, ps + 1); P.hi1 = B.at(RF_HI, ps + 1); P.x1 = B.at(RF_X, ps + 1);
         P.ok = P.ok && !isnan(P.a1) && (1.0f - P.a1 * P.c0) > 0.0f;
     } else {
-        const float sig = ps + 1 < ml ? B.at(RF_X, ps + 1) : 0.0f;
+        const float sig = B.sig_after(ps, ml);
         P.r0 -= P.c0 * sig;            // one cell: the successor's old value is known
         P.c0 = 0.0f;
         P.a1 = 0.0f; P.al1 = 0.0f; P.lo1 = 0.0f; P.hi1 = 0.0f; P.x1 = 0.0f;
@@ -194,14 +215,15 @@ struct TriRows {
     float a0, c0, r0, lo0, hi0, a1, c1, r1, lo1, hi1, a2, al2, lo2, hi2, x0, x1, x2;   // al2 = c2 sig - r2
     bool ok;
 };
-__device__ __forceinline__ void tri_load(const RunBuf &B, int ps, int ml, TriRows &T)
+template <class Buf>
+__device__ __forceinline__ void tri_load(const Buf &B, int ps, int ml, TriRows &T)
 {
     T.a0 = B.at(RF_A, ps); T.c0 = B.at(RF_C, ps); T.r0 = B.at(RF_R, ps);
     T.lo0 = B.at(RF_LO, ps); T.hi0 = B.at(RF_HI, ps); T.x0 = B.at(RF_X, ps);
     T.a1 = B.at(RF_A, ps + 1); T.c1 = B.at(RF_C, ps + 1); T.r1 = B.at(RF_R, ps + 1);
     T.lo1 = B.at(RF_LO, ps + 1); T.hi1 = B.at(RF_HI, ps + 1); T.x1 = B.at(RF_X, ps + 1);
     T.a2 = B.at(RF_A, ps + 2);
-    const float sig = ps + 3 < ml ? B.at(RF_X, ps + 3) : 0.0f;
+    const float sig = B.sig_after(ps + 2, ml);
     T.al2 = B.at(RF_C, ps + 2) * sig - B.at(RF_R, ps + 2);
     T.lo2 = B.at(RF_LO, ps + 2); T.hi2 = B.at(RF_HI, ps + 2); T.x2 = B.at(RF_X, ps + 2);
     T.ok = !isnan(T.a0) && !isnan(T.a1) && !isnan(T.a2) && (1.0f - T.a1 * T.c0 - T.c1 * T.a2) > 0.0f &&
@@ -383,43 +405,121 @@ struct CellIn {
     unsigned lab;
 };
 
-// Reads the inputs of line r (rows mirrored at the grid edge, q+ / q- the
-// mirrored in-line neighbours); vu / vd are read only where the neighbour line
-// exists and is not supplied fresh by the caller.
-template <int NT, int K, bool REV>
-__device__ __forceinline__ void line_load(const LineArgs &A, int r, bool up_fresh, bool dn_fresh, CellIn (&L)[K])
+// Rows of line r that its cells read (rows mirrored at the grid edge); vu / vd
+// are set only where the neighbour line exists and is not supplied fresh by
+// the caller, fit / F / lo / hi where the arrays exist.
+struct LineRows {
+    const float *ps0, *psm, *psp, *w0, *wm, *wp, *old, *fit, *F, *lo, *hi, *vu, *vd;
+    const uint8_t *lab;
+    float M;
+};
+template <bool REV>
+__device__ __forceinline__ LineRows line_rows(const LineArgs &A, int r, bool up_fresh, bool dn_fresh)
 {
-    const int t = threadIdx.x;
-    const int nl = A.nl, ml = A.ml, P = A.pitch;
+    const int nl = A.nl, P = A.pitch;
     const int ru = REV ? r + 1 : r - 1, rd = REV ? r - 1 : r + 1;
     const int rm1 = mg_mirror(r - 1, nl), rp1 = mg_mirror(r + 1, nl);
     const long long ro = (long long)r * P;
-    const float *ps0 = A.psi + ro, *psm = A.psi + (long long)rm1 * P, *psp = A.psi + (long long)rp1 * P;
-    const float *w0 = A.w + ro, *wm = A.w + (long long)rm1 * P, *wp = A.w + (long long)rp1 * P;
-    const float *old = A.phi_old + ro;
-    const uint8_t *lrow = A.lab + (long long)r * A.lpitch;
-    const bool rd_up = ru >= 0 && ru < nl && !up_fresh, rd_dn = rd >= 0 && rd < nl && !dn_fresh;
+    LineRows R;
+    R.ps0 = A.psi + ro; R.psm = A.psi + (long long)rm1 * P; R.psp = A.psi + (long long)rp1 * P;
+    R.w0 = A.w + ro; R.wm = A.w + (long long)rm1 * P; R.wp = A.w + (long long)rp1 * P;
+    R.old = A.phi_old + ro;
+    R.fit = A.fit ? A.fit + ro : nullptr;
+    R.F = A.F ? A.F + ro : nullptr;
+    R.lo = A.lo ? A.lo + ro : nullptr;
+    R.hi = A.lo ? A.hi + ro : nullptr;
+    R.vu = ru >= 0 && ru < nl && !up_fresh ? A.phi_old + (long long)ru * P : nullptr;
+    R.vd = rd >= 0 && rd < nl && !dn_fresh ? A.phi_old + (long long)rd * P : nullptr;
+    R.lab = A.lab + (long long)r * A.lpitch;
+    R.M = A.M;
+    return R;
+}
+// Reads the inputs of visit position p (q+ / q- the mirrored in-line neighbours).
+template <bool REV>
+__device__ __forceinline__ void cell_load(const LineRows &R, int ml, int p, CellIn &c)
+{
+    const int q = REV ? ml - 1 - p : p;
+    const int qm = mg_mirror(q - 1, ml), qp = mg_mirror(q + 1, ml);
+    c.lab = R.lab[q];
+    c.p0 = R.ps0[q]; c.pp = R.psp[q]; c.pm = R.psm[q];
+    c.p0p = R.ps0[qp]; c.p0m = R.ps0[qm];
+    c.ppp = R.psp[qp]; c.ppm = R.psp[qm]; c.pmp = R.psm[qp]; c.pmm = R.psm[qm];
+    c.w00 = R.w0[q]; c.wp = R.wp[q]; c.wm = R.wm[q]; c.w0p = R.w0[qp]; c.w0m = R.w0[qm];
+    c.fit = R.fit ? R.fit[q] : 0.0f;
+    c.F = R.F ? R.F[q] : 0.0f;
+    c.vu = R.vu ? R.vu[q] : 0.0f;
+    c.vd = R.vd ? R.vd[q] : 0.0f;
+    c.sig = p + 1 < ml ? R.old[REV ? ml - 2 - p : p + 1] : 0.0f;
+    c.lo = R.lo ? R.lo[q] : -R.M;
+    c.hi = R.lo ? R.hi[q] : R.M;
+    c.pold = R.old[q];
+}
+template <int NT, int K, bool REV>
+__device__ __forceinline__ void line_load(const LineArgs &A, int r, bool up_fresh, bool dn_fresh, CellIn (&L)[K])
+{
+    const LineRows R = line_rows<REV>(A, r, up_fresh, dn_fresh);
 #pragma unroll
     for (int k = 0; k < K; k++) {
-        const int p = k * NT + t;
-        CellIn &c = L[k];
-        if (p >= ml) continue;
-        const int q = REV ? ml - 1 - p : p;
-        const int qm = mg_mirror(q - 1, ml), qp = mg_mirror(q + 1, ml);
-        c.lab = lrow[q];
-        c.p0 = ps0[q]; c.pp = psp[q]; c.pm = psm[q];
-        c.p0p = ps0[qp]; c.p0m = ps0[qm];
-        c.ppp = psp[qp]; c.ppm = psp[qm]; c.pmp = psm[qp]; c.pmm = psm[qm];
-        c.w00 = w0[q]; c.wp = wp[q]; c.wm = wm[q]; c.w0p = w0[qp]; c.w0m = w0[qm];
-        c.fit = A.fit ? A.fit[ro + q] : 0.0f;
-        c.F = A.F ? A.F[ro + q] : 0.0f;
-        c.vu = rd_up ? A.phi_old[(long long)ru * P + q] : 0.0f;
-        c.vd = rd_dn ? A.phi_old[(long long)rd * P + q] : 0.0f;
-        c.sig = p + 1 < ml ? old[REV ? ml - 2 - p : p + 1] : 0.0f;
-        c.lo = A.lo ? A.lo[ro + q] : -A.M;
-        c.hi = A.lo ? A.hi[ro + q] : A.M;
-        c.pold = old[q];
+        const int p = k * NT + threadIdx.x;
+        if (p < A.ml) cell_load<REV>(R, A.ml, p, L[k]);
     }
+}
+
+// The frozen coefficients of cell (r, q) (eq. abcdrc) as the row
+// a y_prev - y + c y_next = rr of its line, with the cross-line neighbours at
+// vu / vd moved into rr; pb = c sig - rr is the point update's offset with the
+// successor at its old value.  ok = false where S = 0 (the cell keeps x).
+struct CellRow {
+    float a, c, rr, pb, lo, hi, x;
+    bool ok;
+};
+template <bool REV>
+__device__ __forceinline__ CellRow cell_row(const LineArgs &A, const CellIn &c, int r, int q, float vu, float vd,
+                                            float area)
+{
+    const int nl = A.nl, ml = A.ml;
+    const float e2 = A.e2;
+    const float p0 = c.p0;
+    float xp = 0.0f, xm = 0.0f, lp = 0.0f, lm = 0.0f;
+    if (r + 1 < nl) xp = mg_face(p0, c.pp, c.p0p, c.ppp, c.p0m, c.ppm, c.w00, c.wp, e2);
+    if (r > 0) xm = mg_face(c.pm, p0, c.pmp, c.p0p, c.pmm, c.p0m, c.wm, c.w00, e2);
+    if (q + 1 < ml) lp = mg_face(p0, c.p0p, c.pp, c.ppp, c.pm, c.pmp, c.w00, c.w0p, e2);
+    if (q > 0) lm = mg_face(c.p0m, p0, c.ppm, c.pp, c.pmm, c.pm, c.w0m, c.w00, e2);
+    const float dl = A.scaled ? 1.0f : mg_delta(p0, A.eps);
+    const float sc = A.kap * dl;
+    xp *= sc; xm *= sc; lp *= sc; lm *= sc;
+    const float S = xp + xm + lp + lm;
+    const float f = A.fit ? dl * (c.fit + area) : 0.0f;   // null fit: f is part of F
+    const float Xu = REV ? xp : xm, Xd = REV ? xm : xp;
+    const float Lp = REV ? lp : lm, Ls = REV ? lm : lp;
+    const float rhs = f + c.F - Xu * vu - Xd * vd;
+    CellRow w;
+    w.ok = S > 0.0f;
+    const float inv = w.ok ? __builtin_amdgcn_rcpf(S) : 0.0f;
+    w.a = Lp * inv;
+    w.c = Ls * inv;
+    w.rr = rhs * inv;
+    w.pb = (Ls * c.sig - rhs) * inv;
+    w.lo = c.lo;
+    w.hi = c.hi;
+    w.x = c.pold;
+    return w;
+}
+// the point update as a clipped ramp of the entering value
+__device__ __forceinline__ Ramp cell_ramp(const CellRow &w)
+{
+    return w.ok ? Ramp{w.a, w.pb, w.lo, w.hi} : Ramp{0.0f, w.x, w.x, w.x};
+}
+// the row stored for the unit solves (a = NaN marks S = 0)
+template <class Buf>
+__device__ __forceinline__ void row_store(const Buf &B, int p, const CellRow &w)
+{
+    B.at(RF_A, p) = w.ok ? w.a : __builtin_nanf("");
+    B.at(RF_C, p) = w.ok ? w.c : 0.0f;
+    B.at(RF_R, p) = w.ok ? w.rr : 0.0f;
+    B.at(RF_LO, p) = w.lo;
+    B.at(RF_HI, p) = w.hi;
+    B.at(RF_X, p) = w.x;
 }
 
 // --------------------------------------------------------------------------
@@ -442,7 +542,6 @@ __device__ __forceinline__ void sweep_line(const LineArgs &A, int r, const RunBu
     const int ru = REV ? r + 1 : r - 1;      // upstream line
     const int rd = REV ? r - 1 : r + 1;      // downstream line
     const long long ro = (long long)r * P;
-    const float e2 = A.e2;
     const float area = A.area ? (float)(*A.area) : 0.0f;
     const bool has_up = ru >= 0 && ru < nl, has_dn = rd >= 0 && rd < nl;
     auto cell = [&](int p) { return REV ? ml - 1 - p : p; };
@@ -459,46 +558,14 @@ __device__ __forceinline__ void sweep_line(const LineArgs &A, int r, const RunBu
         bool s0 = false;
         if (p < ml) {
             const CellIn &c = L[k];
-            const int q = cell(p);
             s0 = ((c.lab >> A.bit) & 1) != 0;
-            const float p0 = c.p0;
-            float xp = 0.0f, xm = 0.0f, lp = 0.0f, lm = 0.0f;
-            if (r + 1 < nl) xp = mg_face(p0, c.pp, c.p0p, c.ppp, c.p0m, c.ppm, c.w00, c.wp, e2);
-            if (r > 0) xm = mg_face(c.pm, p0, c.pmp, c.p0p, c.pmm, c.p0m, c.wm, c.w00, e2);
-            if (q + 1 < ml) lp = mg_face(p0, c.p0p, c.pp, c.ppp, c.pm, c.pmp, c.w00, c.w0p, e2);
-            if (q > 0) lm = mg_face(c.p0m, p0, c.ppm, c.pp, c.pmm, c.pm, c.w0m, c.w00, e2);
-            const float dl = A.scaled ? 1.0f : mg_delta(p0, A.eps);
-            const float sc = A.kap * dl;
-            xp *= sc; xm *= sc; lp *= sc; lm *= sc;
-            const float S = xp + xm + lp + lm;
-            const float f = A.fit ? dl * (c.fit + area) : 0.0f;   // null fit: f is part of F
-            const float Fv = c.F;
-            const float Xu = REV ? xp : xm, Xd = REV ? xm : xp;
-            const float Lp = REV ? lp : lm, Ls = REV ? lm : lp;
             float vu = 0.0f, vd = 0.0f;
             if (has_up) vu = up_fresh ? upv[k] : c.vu;
             if (has_dn) vd = dn_fresh ? dnv[k] : c.vd;
-            const float rhs = f + Fv - Xu * vu - Xd * vd;
-            const float sig = c.sig;
-            const float lo = c.lo;
-            const float hi = c.hi;
-            const float pold = c.pold;
-            const bool ok = S > 0.0f;
-            const float inv = ok ? __builtin_amdgcn_rcpf(S) : 0.0f;
-            if (ok) {
-                pa[k] = Lp * inv;
-                pb[k] = (Ls * sig - rhs) * inv;
-                plo[k] = lo;
-                phv[k] = hi;
-            } else {                          // S == 0: the cell keeps its value
-                pa[k] = 0.0f; pb[k] = pold; plo[k] = pold; phv[k] = pold;
-            }
-            B.at(RF_A, p) = ok ? Lp * inv : __builtin_nanf("");
-            B.at(RF_C, p) = ok ? Ls * inv : 0.0f;
-            B.at(RF_R, p) = ok ? rhs * inv : 0.0f;
-            B.at(RF_LO, p) = lo;
-            B.at(RF_HI, p) = hi;
-            B.at(RF_X, p) = pold;
+            const CellRow w = cell_row<REV>(A, c, r, cell(p), vu, vd, area);
+            const Ramp u = cell_ramp(w);
+            pa[k] = u.a; pb[k] = u.b; plo[k] = u.lo; phv[k] = u.hi;
+            row_store(B, p, w);
         }
         const unsigned long long bm = __ballot(s0);
         if (lane == 0 && k * NT + wave * 64 < ml) msk[((k * NT) >> 6) + wave] = bm;
@@ -573,23 +640,23 @@ __device__ __forceinline__ void sweep_line(const LineArgs &A, int r, const RunBu
                 pair_load(B, p, uL[k], ml, Q);
                 float y0, y1;
                 pair_solve(Q, uL[k], xin[k], y0, y1);
-                B.at(RF_Y, p) = y0;
-                if (uL[k] == 2) B.at(RF_Y, p + 1) = y1;
+                B.y(p) = y0;
+                if (uL[k] == 2) B.y(p + 1) = y1;
                 continue;
             }
             TriRows T3;
             tri_load(B, p, ml, T3);
             float y0, y1, y2;
             tri_solve(T3, xin[k], y0, y1, y2);
-            B.at(RF_Y, p) = y0;
-            B.at(RF_Y, p + 1) = y1;
-            B.at(RF_Y, p + 2) = y2;
+            B.y(p) = y0;
+            B.y(p + 1) = y1;
+            B.y(p + 2) = y2;
         }
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < K; k++) {
             const int p = k * NT + t;
-            if (p < ml && ((inunit >> k) & 1)) val[k] = B.at(RF_Y, p);
+            if (p < ml && ((inunit >> k) & 1)) val[k] = B.y(p);
         }
     }
     if (write) {
@@ -719,13 +786,169 @@ __device__ __forceinline__ void sweep_band(const LineArgs &A, int b, const RunBu
     }
 }
 
-// dynamic LDS: [starred masks, 8 B per 64 cells][RF_COUNT * ml floats unit rows
-// when ml <= RB_LDS_MAX, else a global scratch plane per band]
-__host__ __device__ inline int sweep_mask_words(int ml) { return (ml + 63) / 64; }
+// --------------------------------------------------------------------------
+// Lines longer than one workgroup: NT threads take K rounds of NT cells, one
+// round after another, so that only one round's inputs are held at a time.
+// A unit's chain ramp sits at its LAST position (its other cells take the
+// identity): the scan's exclusive prefix there is the value entering the
+// unit, and a unit that begins in the last two cells of a round is solved
+// in the next round, where all of its rows are known.  The unit rows live in
+// a ring of two rounds (RingBuf).  A cell's new value is written as soon as
+// it is final (cells of a unit that ends in the next round: one round
+// later).  LDS holds the previous own line (the fresh upstream neighbour,
+// prev) and the recomputed neighbour line (red), each cell at its visit
+// position, read and written only by the thread that owns the position.
+// The transposed output of a full band goes out as float2 pairs of lines
+// (0, 1) and (2, 3), written when the pair's second line is done.  The
+// rounds are a loop, not unrolled: one copy of the round's code, and no
+// per-round addresses held across rounds.
+template <int NT, bool REV>
+__device__ __forceinline__ void long_band(const LineArgs &A, int b, float *ring, float *prev, float *red,
+                                          uint64_t *msk, Ramp *wtot)
+{
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int nl = A.nl, ml = A.ml, nw = (ml + 63) >> 6;
+    const RingBuf<2 * NT> B{ring};
+    const float area = A.area ? (float)(*A.area) : 0.0f;
+    auto cell = [&](int p) { return REV ? ml - 1 - p : p; };
+    const int K = (ml + NT - 1) / NT;
+    const int r0 = 4 * b;
+    const bool pack = A.tout != nullptr && r0 + 3 < nl;
+#pragma nounroll
+    for (int st = 0; st < 5; st++) {
+        int r; bool redundant, up_fresh, dn_fresh;
+        band_step<REV>(r0, nl, st, r, redundant, up_fresh, dn_fresh);
+        if (r < 0 || r >= nl) continue;
+        const bool has_up = REV ? r + 1 < nl : r > 0, has_dn = REV ? r > 0 : r + 1 < nl;
+        const LineRows R = line_rows<REV>(A, r, up_fresh, dn_fresh);
+        // steps 1 and 4 end a pair of own lines (forward: 0,1 and 2,3; reverse: 3,2 and 1,0)
+        const bool pair_w = pack && (st == 1 || st == 4);
+        const bool single_w = !redundant && !pack;
+        const int rp = r0 + ((r - r0) & 2);
+        // the final value v of position p: write it, keep it
+        auto fin = [&](int p, float v) {
+            const long long q = cell(p);
+            if (single_w) {
+                if (A.tout) A.tout[q * A.tpitch + r] = v;
+                else A.phi_new[(long long)r * A.pitch + q] = v;
+            } else if (pair_w) {
+                const float o = prev[p];
+                *reinterpret_cast<float2 *>(A.tout + q * A.tpitch + rp) = REV ? make_float2(v, o) : make_float2(o, v);
+            }
+            if (redundant) red[p] = v;
+            else prev[p] = v;
+        };
+        // starred masks of the whole line
+#pragma nounroll
+        for (int k = 0; k < K; k++) {
+            const int p = k * NT + t;
+            const bool s0 = p < ml && ((R.lab[cell(p)] >> A.bit) & 1) != 0;
+            const unsigned long long bm = __ballot(s0);
+            if (lane == 0 && k * NT + wave * 64 < ml) msk[((k * NT) >> 6) + wave] = bm;
+        }
+        __syncthreads();
+        float carry = 0.0f;
+        bool pend = false;                       // the last round's cell waits for a unit ending in this one
+#pragma nounroll
+        for (int k = 0; k < K; k++) {
+            const int p = k * NT + t;
+            const bool in = p < ml;
+            CellRow w;
+            w.ok = false; w.x = 0.0f;
+            bool inu = false, last = false;
+            int ps = p, L = 1;
+            if (in) {
+                CellIn c;
+                cell_load<REV>(R, ml, p, c);
+                const float vu = has_up ? (up_fresh ? prev[p] : c.vu) : 0.0f;
+                const float vd = has_dn ? (dn_fresh ? red[p] : c.vd) : 0.0f;
+                w = cell_row<REV>(A, c, r, cell(p), vu, vd, area);
+                if (mask_bit(msk, p)) {
+                    unit_of(msk, nw, ml, p, ps, L);
+                    inu = true;
+                } else if (p >= 1 && mask_bit(msk, p - 1) && (p < 2 || !mask_bit(msk, p - 2))) {
+                    ps = p - 1; L = 2;               // the cell after a single starred cell
+                    inu = true;
+                }
+                last = inu && ps + L - 1 == p;
+                if (inu) {
+                    row_store(B, p, w);
+                    B.at(RG_S, p) = c.sig;
+                }
+            }
+            const bool uk = __syncthreads_or(last);   // rows of the round visible
+            Ramp u = ramp_id();
+            if (in && !inu) u = cell_ramp(w);
+            if (last) {
+                if (L <= 2) {
+                    PairRows Q;
+                    pair_load(B, ps, L, ml, Q);
+                    u = pair_ramp(Q, L);
+                } else {
+                    TriRows T3;
+                    tri_load(B, ps, ml, T3);
+                    u = tri_ramp(T3);
+                }
+            }
+            Ramp tot;
+            const Ramp ex = block_scan_excl<NT>(u, wtot, k & 1, tot);
+            const float x = ramp_eval(ex, carry);
+            float v = 0.0f;
+            if (in && !inu) v = ramp_eval(u, x);
+            carry = ramp_eval(tot, carry);
+            if (uk) {
+                if (last) {
+                    // the rows are read again before the new values overwrite RF_A
+                    if (L <= 2) {
+                        PairRows Q;
+                        pair_load(B, ps, L, ml, Q);
+                        float y0, y1;
+                        pair_solve(Q, L, x, y0, y1);
+                        B.y(ps) = y0;
+                        if (L == 2) B.y(ps + 1) = y1;
+                    } else {
+                        TriRows T3;
+                        tri_load(B, ps, ml, T3);
+                        float y0, y1, y2;
+                        tri_solve(T3, x, y0, y1, y2);
+                        B.y(ps) = y0;
+                        B.y(ps + 1) = y1;
+                        B.y(ps + 2) = y2;
+                    }
+                }
+                __syncthreads();
+                if (inu && ps + L - 1 < (k + 1) * NT) v = B.y(p);
+                if (k > 0 && pend) fin(p - NT, B.y(p - NT));
+            }
+            pend = inu && ps + L - 1 >= (k + 1) * NT;
+            if (in && !pend) fin(p, v);
+        }
+    }
+}
+
+// dynamic LDS of the long-line kernel: [starred masks][RF_COUNT fields x 2 NT
+// ring][prev: ml floats][red: ml floats]
+template <int NT>
+__host__ __device__ inline size_t long_lds_bytes(int ml)
+{
+    return (size_t)sweep_mask_words(ml) * 8 + ((size_t)RF_COUNT * 2 * NT + 2 * (size_t)ml) * sizeof(float);
+}
+template <int NT, bool REV>
+__global__ void __launch_bounds__(NT) k_sweep_long(LineArgs A)
+{
+    if (A.skip && *A.skip) return;
+    extern __shared__ uint64_t smem64[];
+    __shared__ Ramp wtot[2 * (NT / 64)];
+    uint64_t *msk = smem64;
+    float *ring = reinterpret_cast<float *>(smem64 + sweep_mask_words(A.ml));
+    float *prev = ring + RF_COUNT * 2 * NT;
+    long_band<NT, REV>(A, blockIdx.x, ring, prev, prev + A.ml, msk, wtot);
+}
+
+// dynamic LDS: [starred masks, 8 B per 64 cells][RF_COUNT * ml floats unit rows]
 __host__ __device__ inline size_t sweep_lds_bytes(int ml)
 {
-    size_t mb = (size_t)sweep_mask_words(ml) * 8;
-    return ml <= RB_LDS_MAX ? mb + (size_t)RF_COUNT * ml * sizeof(float) : mb;
+    return (size_t)sweep_mask_words(ml) * 8 + (size_t)RF_COUNT * ml * sizeof(float);
 }
 
 template <int NT, int K, bool REV>
@@ -737,8 +960,7 @@ __global__ void __launch_bounds__(NT) k_sweep(LineArgs A)
     uint64_t *msk = smem64;
     RunBuf B;
     B.fs = A.ml;
-    if (A.ml <= RB_LDS_MAX) B.p = reinterpret_cast<float *>(smem64 + sweep_mask_words(A.ml));
-    else B.p = A.scr + (long long)blockIdx.x * RF_COUNT * A.ml;
+    B.p = reinterpret_cast<float *>(smem64 + sweep_mask_words(A.ml));
     // read-ahead of the next line where the registers allow it (not at 1024 threads, 128 registers per lane)
     sweep_band<NT, K, REV, (NT <= 512 && K == 1)>(A, blockIdx.x, B, msk, wtot);
 }

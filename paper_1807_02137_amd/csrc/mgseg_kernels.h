@@ -889,7 +889,7 @@ __global__ void __launch_bounds__(NT) k_coarse_smooth(CoarseArgs G)
     RBc.p = rb; RBc.fs = n;
     LineArgs R, T;
     R.psi = psi; R.w = w; R.fit = dev ? nullptr : fit; R.F = F; R.lab = lab; R.lo = lo; R.hi = hi;
-    R.scr = nullptr; R.skip = nullptr; R.tout = nullptr; R.tpitch = 0; R.area = G.area; R.pitch = m; R.lpitch = m;
+    R.skip = nullptr; R.tout = nullptr; R.tpitch = 0; R.area = G.area; R.pitch = m; R.lpitch = m;
     R.nl = n; R.ml = m; R.kap = G.kap; R.e2 = G.e2; R.M = G.M; R.eps = (float)G.eps; R.scaled = G.scaled;
     T = R;
     T.psi = psi_cm; T.w = w_cm; T.fit = dev ? nullptr : fit_cm; T.F = F_cm; T.lab = lab_cm; T.lo = lo_cm;

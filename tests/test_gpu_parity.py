@@ -192,13 +192,13 @@ def long_line_instance(n, m, tiles=8, seed=11):
     return img, mk
 
 
-@pytest.mark.parametrize("shape", [(32, 1600), (32, 2304), (2304, 32)])
+@pytest.mark.parametrize("shape", [(32, 1600), (32, 2304), (2304, 32), (16, 8192), (8192, 16)])
 @pytest.mark.parametrize("sweep", [0, 1, 2, 3])
 def test_single_sweep_long_lines(shape, sweep):
-    """Lines longer than one 1024-thread workgroup: 2 cells per thread with the
-    unit rows in LDS (1600 cells), 4 cells per thread with the rows in the
-    global scratch plane (2304 cells, along the rows and along the columns);
-    one sweep from the same frozen state and labels against the oracle."""
+    """Lines longer than one 1024-thread workgroup, taken in rounds of 1024
+    cells (1600 and 2304 cells: 2 and 3 rounds; 8192: 8 rounds), along the rows
+    and along the columns; one sweep from the same frozen state and labels
+    against the oracle."""
     n, m = shape
     say("case long-line sweep", "ABCD"[sweep], n, m)
     img, mk = long_line_instance(n, m)
@@ -220,6 +220,60 @@ def test_single_sweep_long_lines(shape, sweep):
     beyond = np.nonzero(starred.any(axis=1 - long_axis))[0]
     say("max |dphi|", d.max(), "starred", int(starred.sum()), "last starred position", int(beyond.max()) if beyond.size else -1)
     assert beyond.size and beyond.max() > 1024        # units beyond the first workgroup's cells
+    assert d.max() <= 2e-4
+    s.close()
+
+
+def plant_runs_across_rounds(lab, sweep, rnd=1024):
+    """Sets the sweep's starred bit on runs of 1-5 cells that straddle every
+    rnd-cell boundary of the visit order (the run of line i starts 1 + i % 3
+    cells before the boundary and has 1 + i % 5 cells, with unstarred cells on
+    both sides), so that units begin in one round and end in the next."""
+    lab = lab.copy()
+    v = lab if sweep < 2 else lab.T          # lines along the second axis
+    nl, ml = v.shape
+    rev = sweep in (1, 3)
+    bit = np.uint8(1 << sweep)
+    planted = 0
+    for i in range(nl):
+        for bnd in range(rnd, ml, rnd):
+            p0, L = bnd - 1 - i % 3, 1 + i % 5
+            for p in range(p0 - 1, min(p0 + L + 1, ml)):
+                q = ml - 1 - p if rev else p
+                if p0 <= p < p0 + L:
+                    v[i, q] |= bit
+                else:
+                    v[i, q] &= ~bit
+            planted += p0 + L - 1 >= bnd
+    return lab, planted
+
+
+@pytest.mark.parametrize("shape,sweep", [((16, 3000), 0), ((16, 3000), 1), ((8, 8192), 0), ((8, 8192), 1),
+                                         ((8192, 8), 2), ((8192, 8), 3)])
+def test_single_sweep_units_across_rounds(shape, sweep):
+    """Units that begin in one 1024-cell round of a long line and end in the
+    next (planted starred runs of 1-5 cells on every round boundary; runs of 4
+    and 5 cells are cut into two units, single cells take their successor):
+    one sweep against the oracle from the same state and the same labels."""
+    n, m = shape
+    say("case units across rounds", "ABCD"[sweep], n, m)
+    img, mk = long_line_instance(n, m)
+    s = mgseg.Solver(img, mk, mgseg.Params(levels=3, mixed_precision=0))
+    o = Oracle(img, mk, OracleParams(levels=3))
+    o.smooth(2, 0)
+    phi = o.get("phi")
+    s.set("phi", phi.astype(np.float32))
+    o.set("phi", phi.astype(np.float32).astype(np.float64))
+    s.op("freeze", 0)
+    o.freeze(0)
+    lab, planted = plant_runs_across_rounds(o.labels(), sweep)
+    assert planted > 0
+    o.set_labels(lab)
+    s.set("labels", lab)
+    s.op(["sweep_A", "sweep_B", "sweep_C", "sweep_D"][sweep], 0)
+    o.sweep(sweep, 0)
+    d = np.abs(s.get("phi").astype(np.float64) - o.get("phi"))
+    say("max |dphi|", d.max(), "units across a boundary", planted)
     assert d.max() <= 2e-4
     s.close()
 
