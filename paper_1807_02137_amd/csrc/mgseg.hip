@@ -41,6 +41,7 @@ struct Level {
     float *w_cm = nullptr, *fit_cm = nullptr, *F_cm = nullptr, *lo_cm = nullptr, *hi_cm = nullptr;
     float *T[3] = {nullptr, nullptr, nullptr};
     float *psi_cm = nullptr;
+    float4 *cf = nullptr, *cf_cm = nullptr;   // deviation form: the sweeps' frozen face coefficients
     uint8_t *lab = nullptr, *lab_cm = nullptr;
     bool has_F = false;
 };
@@ -248,6 +249,9 @@ void launch_sweep(mgseg_ctx *c, int l, int s, const float *phi_old, float *phi_n
     A.lo = bnd ? (cm ? L.lo_cm : L.lo) : nullptr;
     A.hi = bnd ? (cm ? L.hi_cm : L.hi) : nullptr;
     A.area = c->p.model == 1 ? c->dsc + DS_AREA_FRZ : nullptr;
+    // deviation form: the freeze stored the scaled face coefficients (and the fit term is in T)
+    const bool cfm = devm(c) && L.cf != nullptr;
+    A.cf = cfm ? (cm ? L.cf_cm : L.cf) : nullptr;
     A.pitch = cm ? L.pcm : L.prm;
     A.lpitch = A.pitch;
     A.nl = cm ? L.m : L.n;
@@ -262,15 +266,25 @@ void launch_sweep(mgseg_ctx *c, int l, int s, const float *phi_old, float *phi_n
         return;
     }
     const size_t lds = sweep_lds_bytes(ml), llds = long_lds_bytes<1024>(ml);
-#define MG_SWEEP(NT, K)                                                                                  \
+#define MG_SWEEP_CF(NT, K, CF)                                                                       \
     do {                                                                                                 \
-        if (rev) hipLaunchKernelGGL((k_sweep<NT, K, true>), dim3(bands), dim3(NT), lds, c->s, A);     \
-        else hipLaunchKernelGGL((k_sweep<NT, K, false>), dim3(bands), dim3(NT), lds, c->s, A);        \
+        if (rev) hipLaunchKernelGGL((k_sweep<NT, K, true, CF>), dim3(bands), dim3(NT), lds, c->s, A); \
+        else hipLaunchKernelGGL((k_sweep<NT, K, false, CF>), dim3(bands), dim3(NT), lds, c->s, A);    \
     } while (0)
-#define MG_SWEEP_LONG()                                                                                    \
-    do {                                                                                                   \
-        if (rev) hipLaunchKernelGGL((k_sweep_long<1024, true>), dim3(bands), dim3(1024), llds, c->s, A);  \
-        else hipLaunchKernelGGL((k_sweep_long<1024, false>), dim3(bands), dim3(1024), llds, c->s, A);     \
+#define MG_SWEEP(NT, K)                 \
+    do {                                \
+        if (cfm) MG_SWEEP_CF(NT, K, true);  \
+        else MG_SWEEP_CF(NT, K, false); \
+    } while (0)
+#define MG_SWEEP_LONG_CF(CF)                                                                                    \
+    do {                                                                                                        \
+        if (rev) hipLaunchKernelGGL((k_sweep_long<1024, true, CF>), dim3(bands), dim3(1024), llds, c->s, A);   \
+        else hipLaunchKernelGGL((k_sweep_long<1024, false, CF>), dim3(bands), dim3(1024), llds, c->s, A);      \
+    } while (0)
+#define MG_SWEEP_LONG()                \
+    do {                               \
+        if (cfm) MG_SWEEP_LONG_CF(true);   \
+        else MG_SWEEP_LONG_CF(false);  \
     } while (0)
     hipEvent_t e0 = nullptr, e1 = nullptr;
     bool timed = c->prof_on && l == 0;
@@ -294,7 +308,9 @@ void launch_sweep(mgseg_ctx *c, int l, int s, const float *phi_old, float *phi_n
     else if (ml <= 1024) MG_SWEEP(1024, 1);
     else MG_SWEEP_LONG();
 #undef MG_SWEEP
+#undef MG_SWEEP_CF
 #undef MG_SWEEP_LONG
+#undef MG_SWEEP_LONG_CF
     if (timed) {
         (void)hipEventRecord(e1, c->s);
         c->ev_used.push_back({e0, e1});
@@ -315,6 +331,7 @@ DevArgs<BT> dev_args(mgseg_ctx *c, int l, const BT *b, int pb)
     A.e = L.P[0]; A.G = L.G; A.w = L.w; A.fit = L.fit; A.lo = L.lo; A.hi = L.hi;
     A.psi = L.psi; A.T = L.F; A.r = L.r; A.lab = L.lab;
     A.psi_cm = nullptr; A.T_cm = nullptr; A.lab_cm = nullptr; A.pc = L.pcm;
+    A.cf = nullptr; A.cf_cm = nullptr;
     A.area_b = c->p.model == 1 ? c->dsc + area_b_slot(l) : nullptr;
     A.area_u = nullptr;
     A.p = L.prm; A.n = L.n; A.m = L.m; A.scaled = c->p.scaled;
@@ -354,9 +371,14 @@ void freeze(mgseg_ctx *c, int l)
         with_dev(c, l, [&](auto A) {
             using BT = std::remove_const_t<std::remove_pointer_t<decltype(A.b)>>;
             A.area_u = rc ? c->dsc + DS_AREA_FRZ : nullptr;
-            A.psi_cm = L.psi_cm; A.T_cm = L.F_cm; A.lab_cm = L.lab_cm;
+            // with stored coefficients no sweep reads psi in the column layout
+            A.psi_cm = L.cf ? nullptr : L.psi_cm; A.T_cm = L.F_cm; A.lab_cm = L.lab_cm;
+            A.cf = L.cf; A.cf_cm = L.cf_cm;
             dim3 gt((L.m + TILE - 1) / TILE, (L.n + TILE - 1) / TILE);
-            hipLaunchKernelGGL(k_freeze_dev<BT>, gt, dim3(TILE, TILE), 0, c->s, A);
+            // large grids: 32 x 8 blocks (four rows per thread) so that several blocks
+            // share a CU across the tile's barrier; small grids: one row per thread
+            const int ty = (long long)gt.x * gt.y >= 4096 ? 8 : TILE;
+            hipLaunchKernelGGL(k_freeze_dev<BT>, gt, dim3(TILE, ty), 0, c->s, A);
         });
         L.has_F = true;
         chk(c);
@@ -710,11 +732,13 @@ mgseg_status mgseg_setup(const float *image_dev, int n, int m, int pitch, const 
             hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
             return MGSEG_E_HIP;
         if (need + 2 * (1024 / 64) * sizeof(Ramp) > (size_t)lds_max) return MGSEG_E_SHAPE;
-        if (hipFuncSetAttribute(reinterpret_cast<const void *>(&k_sweep_long<1024, false>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)need) != hipSuccess ||
-            hipFuncSetAttribute(reinterpret_cast<const void *>(&k_sweep_long<1024, true>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)need) != hipSuccess)
-            return MGSEG_E_HIP;
+        const void *fns[4] = {reinterpret_cast<const void *>(&k_sweep_long<1024, false, false>),
+                              reinterpret_cast<const void *>(&k_sweep_long<1024, true, false>),
+                              reinterpret_cast<const void *>(&k_sweep_long<1024, false, true>),
+                              reinterpret_cast<const void *>(&k_sweep_long<1024, true, true>)};
+        for (const void *fn : fns)
+            if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)need) != hipSuccess)
+                return MGSEG_E_HIP;
     }
 
     mgseg_ctx *c = new (std::nothrow) mgseg_ctx();
@@ -738,6 +762,7 @@ mgseg_status mgseg_setup(const float *image_dev, int n, int m, int pitch, const 
         L.w_cm = dalloc<float>(c, Nc); L.fit_cm = dalloc<float>(c, Nc); L.F_cm = dalloc<float>(c, Nc);
         L.lo_cm = dalloc<float>(c, Nc); L.hi_cm = dalloc<float>(c, Nc);
         L.lab = dalloc<uint8_t>(c, Nr); L.lab_cm = dalloc<uint8_t>(c, Nc);
+        if (p->mixed_precision) { L.cf = dalloc<float4>(c, Nr); L.cf_cm = dalloc<float4>(c, Nc); }
     }
     c->phi64 = dalloc<double>(c, N); c->w64 = dalloc<double>(c, N); c->d64 = dalloc<double>(c, N);
     c->g64 = dalloc<double>(c, N); c->prev64 = dalloc<double>(c, N); c->phi0m = dalloc<double>(c, N);
@@ -1095,11 +1120,14 @@ mgseg_status mgseg_profile_read(mgseg_ctx *c, int kernel, double *total_ms, int 
     }
     if (total_ms) *total_ms = tot;
     if (count) *count = (int)c->ev_used.size();
-    // compulsory bytes of one finest-grid sweep per cell: read phi, psi, w
-    // (4 B each), the label byte, F (4 B), fit (FP32 mode) or the bounds of
-    // the deviation (mixed mode, 8 B); write phi (4 B)
+    // compulsory bytes of one finest-grid sweep per cell.  Mixed mode: read
+    // phi (4 B), the four stored face coefficients (16 B), the label byte, T
+    // (4 B) and the bounds of the deviation (8 B); write phi (4 B): 37 B.
+    // FP32 mode: read phi, psi, w (4 B each), the label byte, fit and F (4 B
+    // each, F only where set); write phi (4 B).
     if (bytes_per_launch) {
-        double per = 4.0 * 3 + 1.0 + 4.0 + (devm(c) ? 8.0 + 4.0 : 4.0 + (c->lev[0].has_F ? 4.0 : 0.0));
+        const double per = devm(c) ? 4.0 + 16.0 + 1.0 + 4.0 + 8.0 + 4.0
+                                    : 4.0 * 3 + 1.0 + 4.0 + (c->lev[0].has_F ? 4.0 : 0.0) + 4.0;
         *bytes_per_launch = (double)c->n * c->m * per;
     }
     return MGSEG_OK;

@@ -100,6 +100,7 @@ struct LineArgs {
     float *tout;                        // non-null: new values written transposed,
     int tpitch;                         //   cell q of line r at tout[q * tpitch + r]
     const double *area;                 // Rada-Chen area term (null: 0)
+    const float4 *cf;                   // frozen scaled face coefficients (sweeps with CF; fit null)
     int pitch, lpitch, nl, ml;
     float kap, e2, M, eps;
     int bit, scaled;
@@ -402,6 +403,7 @@ struct CellIn {
     float p0, pp, pm, p0p, p0m, ppp, ppm, pmp, pmm;   // psi at (r,q), (r+1,q), (r-1,q), (r,q+), (r,q-), (r+1,q+), (r+1,q-), (r-1,q+), (r-1,q-)
     float w00, wp, wm, w0p, w0m;                      // w at (r,q), (r+1,q), (r-1,q), (r,q+), (r,q-)
     float fit, F, vu, vd, sig, pold, lo, hi;
+    float4 g;                                         // stored coefficients (CF): to r+1, r-1, q+1, q-1
     unsigned lab;
 };
 
@@ -410,6 +412,7 @@ struct CellIn {
 // the caller, fit / F / lo / hi where the arrays exist.
 struct LineRows {
     const float *ps0, *psm, *psp, *w0, *wm, *wp, *old, *fit, *F, *lo, *hi, *vu, *vd;
+    const float4 *cf;
     const uint8_t *lab;
     float M;
 };
@@ -430,21 +433,27 @@ __device__ __forceinline__ LineRows line_rows(const LineArgs &A, int r, bool up_
     R.hi = A.lo ? A.hi + ro : nullptr;
     R.vu = ru >= 0 && ru < nl && !up_fresh ? A.phi_old + (long long)ru * P : nullptr;
     R.vd = rd >= 0 && rd < nl && !dn_fresh ? A.phi_old + (long long)rd * P : nullptr;
+    R.cf = A.cf ? A.cf + ro : nullptr;
     R.lab = A.lab + (long long)r * A.lpitch;
     R.M = A.M;
     return R;
 }
-// Reads the inputs of visit position p (q+ / q- the mirrored in-line neighbours).
-template <bool REV>
+// Reads the inputs of visit position p (q+ / q- the mirrored in-line neighbours);
+// CF: the stored coefficients instead of psi and w.
+template <bool REV, bool CF = false>
 __device__ __forceinline__ void cell_load(const LineRows &R, int ml, int p, CellIn &c)
 {
     const int q = REV ? ml - 1 - p : p;
-    const int qm = mg_mirror(q - 1, ml), qp = mg_mirror(q + 1, ml);
     c.lab = R.lab[q];
-    c.p0 = R.ps0[q]; c.pp = R.psp[q]; c.pm = R.psm[q];
-    c.p0p = R.ps0[qp]; c.p0m = R.ps0[qm];
-    c.ppp = R.psp[qp]; c.ppm = R.psp[qm]; c.pmp = R.psm[qp]; c.pmm = R.psm[qm];
-    c.w00 = R.w0[q]; c.wp = R.wp[q]; c.wm = R.wm[q]; c.w0p = R.w0[qp]; c.w0m = R.w0[qm];
+    if (CF) {
+        c.g = R.cf[q];
+    } else {
+        const int qm = mg_mirror(q - 1, ml), qp = mg_mirror(q + 1, ml);
+        c.p0 = R.ps0[q]; c.pp = R.psp[q]; c.pm = R.psm[q];
+        c.p0p = R.ps0[qp]; c.p0m = R.ps0[qm];
+        c.ppp = R.psp[qp]; c.ppm = R.psp[qm]; c.pmp = R.psm[qp]; c.pmm = R.psm[qm];
+        c.w00 = R.w0[q]; c.wp = R.wp[q]; c.wm = R.wm[q]; c.w0p = R.w0[qp]; c.w0m = R.w0[qm];
+    }
     c.fit = R.fit ? R.fit[q] : 0.0f;
     c.F = R.F ? R.F[q] : 0.0f;
     c.vu = R.vu ? R.vu[q] : 0.0f;
@@ -454,14 +463,14 @@ __device__ __forceinline__ void cell_load(const LineRows &R, int ml, int p, Cell
     c.hi = R.lo ? R.hi[q] : R.M;
     c.pold = R.old[q];
 }
-template <int NT, int K, bool REV>
+template <int NT, int K, bool REV, bool CF = false>
 __device__ __forceinline__ void line_load(const LineArgs &A, int r, bool up_fresh, bool dn_fresh, CellIn (&L)[K])
 {
     const LineRows R = line_rows<REV>(A, r, up_fresh, dn_fresh);
 #pragma unroll
     for (int k = 0; k < K; k++) {
         const int p = k * NT + threadIdx.x;
-        if (p < A.ml) cell_load<REV>(R, A.ml, p, L[k]);
+        if (p < A.ml) cell_load<REV, CF>(R, A.ml, p, L[k]);
     }
 }
 
@@ -473,23 +482,29 @@ struct CellRow {
     float a, c, rr, pb, lo, hi, x;
     bool ok;
 };
-template <bool REV>
+// CF: the scaled face coefficients come from the freeze (the same products,
+// so the same bits) and the fit term is part of F.
+template <bool REV, bool CF = false>
 __device__ __forceinline__ CellRow cell_row(const LineArgs &A, const CellIn &c, int r, int q, float vu, float vd,
                                             float area)
 {
     const int nl = A.nl, ml = A.ml;
-    const float e2 = A.e2;
-    const float p0 = c.p0;
-    float xp = 0.0f, xm = 0.0f, lp = 0.0f, lm = 0.0f;
-    if (r + 1 < nl) xp = mg_face(p0, c.pp, c.p0p, c.ppp, c.p0m, c.ppm, c.w00, c.wp, e2);
-    if (r > 0) xm = mg_face(c.pm, p0, c.pmp, c.p0p, c.pmm, c.p0m, c.wm, c.w00, e2);
-    if (q + 1 < ml) lp = mg_face(p0, c.p0p, c.pp, c.ppp, c.pm, c.pmp, c.w00, c.w0p, e2);
-    if (q > 0) lm = mg_face(c.p0m, p0, c.ppm, c.pp, c.pmm, c.pm, c.w0m, c.w00, e2);
-    const float dl = A.scaled ? 1.0f : mg_delta(p0, A.eps);
-    const float sc = A.kap * dl;
-    xp *= sc; xm *= sc; lp *= sc; lm *= sc;
+    float xp = 0.0f, xm = 0.0f, lp = 0.0f, lm = 0.0f, f = 0.0f;
+    if (CF) {
+        xp = c.g.x; xm = c.g.y; lp = c.g.z; lm = c.g.w;
+    } else {
+        const float e2 = A.e2;
+        const float p0 = c.p0;
+        if (r + 1 < nl) xp = mg_face(p0, c.pp, c.p0p, c.ppp, c.p0m, c.ppm, c.w00, c.wp, e2);
+        if (r > 0) xm = mg_face(c.pm, p0, c.pmp, c.p0p, c.pmm, c.p0m, c.wm, c.w00, e2);
+        if (q + 1 < ml) lp = mg_face(p0, c.p0p, c.pp, c.ppp, c.pm, c.pmp, c.w00, c.w0p, e2);
+        if (q > 0) lm = mg_face(c.p0m, p0, c.ppm, c.pp, c.pmm, c.pm, c.w0m, c.w00, e2);
+        const float dl = A.scaled ? 1.0f : mg_delta(p0, A.eps);
+        const float sc = A.kap * dl;
+        xp *= sc; xm *= sc; lp *= sc; lm *= sc;
+        f = A.fit ? dl * (c.fit + area) : 0.0f;   // null fit: f is part of F
+    }
     const float S = xp + xm + lp + lm;
-    const float f = A.fit ? dl * (c.fit + area) : 0.0f;   // null fit: f is part of F
     const float Xu = REV ? xp : xm, Xd = REV ? xm : xp;
     const float Lp = REV ? lp : lm, Ls = REV ? lm : lp;
     const float rhs = f + c.F - Xu * vu - Xd * vd;
@@ -532,7 +547,7 @@ __device__ __forceinline__ void row_store(const Buf &B, int p, const CellRow &w)
 // thread's cells.  Every point and every unit is a clipped ramp of the value
 // entering it, so the line is one block scan; a unit's ramp sits at its first
 // position and its other cells take the identity.
-template <int NT, int K, bool REV>
+template <int NT, int K, bool REV, bool CF = false>
 __device__ __forceinline__ void sweep_line(const LineArgs &A, int r, const RunBuf &B, uint64_t *msk, bool write,
                                            const float (&upv)[K], bool up_fresh, const float (&dnv)[K],
                                            bool dn_fresh, float (&val)[K], Ramp *wtot, const CellIn (&L)[K])
@@ -562,7 +577,7 @@ __device__ __forceinline__ void sweep_line(const LineArgs &A, int r, const RunBu
             float vu = 0.0f, vd = 0.0f;
             if (has_up) vu = up_fresh ? upv[k] : c.vu;
             if (has_dn) vd = dn_fresh ? dnv[k] : c.vd;
-            const CellRow w = cell_row<REV>(A, c, r, cell(p), vu, vd, area);
+            const CellRow w = cell_row<REV, CF>(A, c, r, cell(p), vu, vd, area);
             const Ramp u = cell_ramp(w);
             pa[k] = u.a; pb[k] = u.b; plo[k] = u.lo; phv[k] = u.hi;
             row_store(B, p, w);
@@ -719,7 +734,7 @@ __device__ __forceinline__ void band_step(int r0, int nl, int st, int &r, bool &
 // PF: read the next step's inputs (line_load) before computing the current
 // line, so that their latency overlaps the current line's phases (costs the
 // registers of one more CellIn per round).
-template <int NT, int K, bool REV, bool PF = false>
+template <int NT, int K, bool REV, bool PF = false, bool CF = false>
 __device__ __forceinline__ void sweep_band(const LineArgs &A, int b, const RunBuf &B, uint64_t *msk, Ramp *wtot)
 {
     float prev[K], red[K], cur[K];
@@ -741,7 +756,7 @@ __device__ __forceinline__ void sweep_band(const LineArgs &A, int b, const RunBu
     if (PF && st < 5) {
         int r; bool rdd, uf, df;
         band_step<REV>(r0, nl, st, r, rdd, uf, df);
-        line_load<NT, K, REV>(A, r, uf, df, la);
+        line_load<NT, K, REV, CF>(A, r, uf, df, la);
     }
 #pragma nounroll
     while (st < 5) {
@@ -753,12 +768,12 @@ __device__ __forceinline__ void sweep_band(const LineArgs &A, int b, const RunBu
             if (nx < 5) {
                 int r2; bool rd2, uf2, df2;
                 band_step<REV>(r0, nl, nx, r2, rd2, uf2, df2);
-                line_load<NT, K, REV>(A, r2, uf2, df2, lb);
+                line_load<NT, K, REV, CF>(A, r2, uf2, df2, lb);
             }
         } else {
-            line_load<NT, K, REV>(A, r, up_fresh, dn_fresh, la);
+            line_load<NT, K, REV, CF>(A, r, up_fresh, dn_fresh, la);
         }
-        sweep_line<NT, K, REV>(A, r, B, msk, !redundant && !pack, prev, up_fresh, red, dn_fresh, cur, wtot, la);
+        sweep_line<NT, K, REV, CF>(A, r, B, msk, !redundant && !pack, prev, up_fresh, red, dn_fresh, cur, wtot, la);
         const int li = r - r0;
 #pragma unroll
         for (int k = 0; k < K; k++) {
@@ -802,7 +817,7 @@ __device__ __forceinline__ void sweep_band(const LineArgs &A, int b, const RunBu
 // (0, 1) and (2, 3), written when the pair's second line is done.  The
 // rounds are a loop, not unrolled: one copy of the round's code, and no
 // per-round addresses held across rounds.
-template <int NT, bool REV>
+template <int NT, bool REV, bool CF>
 __device__ __forceinline__ void long_band(const LineArgs &A, int b, float *ring, float *prev, float *red,
                                           uint64_t *msk, Ramp *wtot)
 {
@@ -859,10 +874,10 @@ __device__ __forceinline__ void long_band(const LineArgs &A, int b, float *ring,
             int ps = p, L = 1;
             if (in) {
                 CellIn c;
-                cell_load<REV>(R, ml, p, c);
+                cell_load<REV, CF>(R, ml, p, c);
                 const float vu = has_up ? (up_fresh ? prev[p] : c.vu) : 0.0f;
                 const float vd = has_dn ? (dn_fresh ? red[p] : c.vd) : 0.0f;
-                w = cell_row<REV>(A, c, r, cell(p), vu, vd, area);
+                w = cell_row<REV, CF>(A, c, r, cell(p), vu, vd, area);
                 if (mask_bit(msk, p)) {
                     unit_of(msk, nw, ml, p, ps, L);
                     inu = true;
@@ -933,7 +948,7 @@ __host__ __device__ inline size_t long_lds_bytes(int ml)
 {
     return (size_t)sweep_mask_words(ml) * 8 + ((size_t)RF_COUNT * 2 * NT + 2 * (size_t)ml) * sizeof(float);
 }
-template <int NT, bool REV>
+template <int NT, bool REV, bool CF>
 __global__ void __launch_bounds__(NT) k_sweep_long(LineArgs A)
 {
     if (A.skip && *A.skip) return;
@@ -942,7 +957,7 @@ __global__ void __launch_bounds__(NT) k_sweep_long(LineArgs A)
     uint64_t *msk = smem64;
     float *ring = reinterpret_cast<float *>(smem64 + sweep_mask_words(A.ml));
     float *prev = ring + RF_COUNT * 2 * NT;
-    long_band<NT, REV>(A, blockIdx.x, ring, prev, prev + A.ml, msk, wtot);
+    long_band<NT, REV, CF>(A, blockIdx.x, ring, prev, prev + A.ml, msk, wtot);
 }
 
 // dynamic LDS: [starred masks, 8 B per 64 cells][RF_COUNT * ml floats unit rows]
@@ -951,7 +966,7 @@ __host__ __device__ inline size_t sweep_lds_bytes(int ml)
     return (size_t)sweep_mask_words(ml) * 8 + (size_t)RF_COUNT * ml * sizeof(float);
 }
 
-template <int NT, int K, bool REV>
+template <int NT, int K, bool REV, bool CF>
 __global__ void __launch_bounds__(NT) k_sweep(LineArgs A)
 {
     if (A.skip && *A.skip) return;
@@ -961,6 +976,7 @@ __global__ void __launch_bounds__(NT) k_sweep(LineArgs A)
     RunBuf B;
     B.fs = A.ml;
     B.p = reinterpret_cast<float *>(smem64 + sweep_mask_words(A.ml));
-    // read-ahead of the next line where the registers allow it (not at 1024 threads, 128 registers per lane)
-    sweep_band<NT, K, REV, (NT <= 512 && K == 1)>(A, blockIdx.x, B, msk, wtot);
+    // read-ahead of the next line where the registers allow it (at 1024 threads, 128 registers per
+    // lane: only with the stored coefficients)
+    sweep_band<NT, K, REV, ((NT <= 512 || CF) && K == 1), CF>(A, blockIdx.x, B, msk, wtot);
 }

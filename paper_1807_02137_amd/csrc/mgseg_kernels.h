@@ -625,7 +625,9 @@ struct DevArgs {
     float *psi, *T, *r;                        // outputs (pitch p), null: not written
     uint8_t *lab;                              // labels (pitch p), null: not written
     float *psi_cm, *T_cm;                      // column-major copies (pitch pc), null: not written
+                                               // (T_cm null: no column-major output at all)
     uint8_t *lab_cm;
+    float4 *cf, *cf_cm;                        // scaled face coefficients for the sweeps, null: not written
     int pc;
     const double *area_b, *area_u;             // Rada-Chen area terms at b and at b + e (null: 0)
     int p, n, m, scaled;
@@ -633,10 +635,12 @@ struct DevArgs {
 };
 
 // T at cell (i, j) with psi = fl32(b + e); with want_Le also L_psi e
-// (FP64 sums of FP32 coefficients); u0 = psi_ij; lab = the cell's label at psi.
+// (FP64 sums of FP32 coefficients); u0 = psi_ij; lab = the cell's label at psi;
+// au = the four face coefficients at psi scaled by kap dl(psi) (to i+1, i-1,
+// j+1, j-1; 0 across the grid edge): the sweeps' frozen A, B, C, D.
 template <typename BT>
 __device__ __forceinline__ double dev_cell(const DevArgs<BT> &A, int i, int j, bool want_Le, double &Le, float &u0,
-                                           uint8_t &lab)
+                                           uint8_t &lab, float (&au)[4])
 {
     const int n = A.n, m = A.m;
     auto B64 = [&](int a, int c) { return (double)A.b[(long long)a * A.pb + c]; };
@@ -658,11 +662,13 @@ __device__ __forceinline__ double dev_cell(const DevArgs<BT> &A, int i, int j, b
     double t = (double)A.G[q];
     Le = 0.0;
 #pragma unroll
+    for (int f = 0; f < 4; f++) au[f] = gu[f] * scu;
+#pragma unroll
     for (int f = 0; f < 4; f++) {
         if (!in[f]) continue;
-        const float ab = gb[f] * scb, au = gu[f] * scu;
-        t += ((double)ab - (double)au) * (B64(ni[f], nj[f]) - b0);
-        if (want_Le) Le += (double)au * (E64(ni[f], nj[f]) - e0);
+        const float ab = gb[f] * scb;
+        t += ((double)ab - (double)au[f]) * (B64(ni[f], nj[f]) - b0);
+        if (want_Le) Le += (double)au[f] * (E64(ni[f], nj[f]) - e0);
     }
     const double fit = (double)A.fit[q];
     const double sb = A.area_b ? *A.area_b : 0.0, su = A.area_u ? *A.area_u : 0.0;
@@ -670,15 +676,27 @@ __device__ __forceinline__ double dev_cell(const DevArgs<BT> &A, int i, int j, b
     lab = label_of(gu, n, m, i, j, A.Sigma);
     return t;
 }
+template <typename BT>
+__device__ __forceinline__ double dev_cell(const DevArgs<BT> &A, int i, int j, bool want_Le, double &Le, float &u0,
+                                           uint8_t &lab)
+{
+    float au[4];
+    return dev_cell(A, i, j, want_Le, Le, u0, lab, au);
+}
 
-// freeze in deviation form: psi = fl32(b + e), T, labels.  32 x 32 tiles:
+// freeze in deviation form: psi = fl32(b + e), T, labels and (cf non-null)
+// the sweeps' scaled face coefficients, as (to the next line, to the previous
+// line, to the next cell, to the previous cell) of each layout: row-major
+// (i+1, i-1, j+1, j-1), column-major (j+1, j-1, i+1, i-1).  32 x 32 tiles:
 // row-major outputs written directly, column-major copies through LDS so that
-// both layouts are written coalesced.  Block (32, 32), one cell per thread.
+// both layouts are written coalesced.  Block (32, 32) or (32, 8): one or four
+// rows per thread.
 template <typename BT>
 __global__ void __launch_bounds__(1024) k_freeze_dev(DevArgs<BT> A)
 {
     __shared__ float tp[TILE][TILE + 1], tt[TILE][TILE + 1];
     __shared__ uint8_t tl[TILE][TILE + 1];
+    __shared__ float4 tc[TILE][TILE + 1];
     const int bx = blockIdx.x * TILE, by = blockIdx.y * TILE;
     for (int y = threadIdx.y; y < TILE; y += blockDim.y) {
         const int i = by + y, j = bx + threadIdx.x;
@@ -686,23 +704,27 @@ __global__ void __launch_bounds__(1024) k_freeze_dev(DevArgs<BT> A)
             double Le;
             float u0;
             uint8_t lab;
-            const double t = dev_cell(A, i, j, false, Le, u0, lab);
+            float au[4];
+            const double t = dev_cell(A, i, j, false, Le, u0, lab, au);
             const long long q = (long long)i * A.p + j;
             A.psi[q] = u0;
             A.T[q] = (float)t;
             A.lab[q] = lab;
+            if (A.cf) A.cf[q] = make_float4(au[0], au[1], au[2], au[3]);
             tp[y][threadIdx.x] = u0; tt[y][threadIdx.x] = (float)t; tl[y][threadIdx.x] = lab;
+            tc[y][threadIdx.x] = make_float4(au[2], au[3], au[0], au[1]);
         }
     }
-    if (!A.psi_cm) return;
+    if (!A.T_cm) return;
     __syncthreads();
     for (int y = threadIdx.y; y < TILE; y += blockDim.y) {
         const int j = bx + y, i = by + threadIdx.x;
         if (i < A.n && j < A.m) {
             const long long qc = (long long)j * A.pc + i;
-            A.psi_cm[qc] = tp[threadIdx.x][y];
+            if (A.psi_cm) A.psi_cm[qc] = tp[threadIdx.x][y];
             A.T_cm[qc] = tt[threadIdx.x][y];
             A.lab_cm[qc] = tl[threadIdx.x][y];
+            if (A.cf_cm) A.cf_cm[qc] = tc[threadIdx.x][y];
         }
     }
 }
@@ -889,7 +911,7 @@ __global__ void __launch_bounds__(NT) k_coarse_smooth(CoarseArgs G)
     RBc.p = rb; RBc.fs = n;
     LineArgs R, T;
     R.psi = psi; R.w = w; R.fit = dev ? nullptr : fit; R.F = F; R.lab = lab; R.lo = lo; R.hi = hi;
-    R.skip = nullptr; R.tout = nullptr; R.tpitch = 0; R.area = G.area; R.pitch = m; R.lpitch = m;
+    R.skip = nullptr; R.tout = nullptr; R.tpitch = 0; R.area = G.area; R.pitch = m; R.lpitch = m; R.cf = nullptr;
     R.nl = n; R.ml = m; R.kap = G.kap; R.e2 = G.e2; R.M = G.M; R.eps = (float)G.eps; R.scaled = G.scaled;
     T = R;
     T.psi = psi_cm; T.w = w_cm; T.fit = dev ? nullptr : fit_cm; T.F = F_cm; T.lab = lab_cm; T.lo = lo_cm;
@@ -897,7 +919,7 @@ __global__ void __launch_bounds__(NT) k_coarse_smooth(CoarseArgs G)
     DevArgs<float> D;
     D.b = base; D.pb = m; D.e = P0; D.G = Gv; D.w = w; D.fit = fit; D.lo = lo; D.hi = hi;
     D.psi = nullptr; D.T = nullptr; D.r = nullptr; D.lab = nullptr;
-    D.psi_cm = nullptr; D.T_cm = nullptr; D.lab_cm = nullptr; D.pc = n;
+    D.psi_cm = nullptr; D.T_cm = nullptr; D.lab_cm = nullptr; D.pc = n; D.cf = nullptr; D.cf_cm = nullptr;
     D.area_b = G.area_b; D.area_u = G.area;
     D.p = m; D.n = n; D.m = m; D.scaled = G.scaled;
     D.kap = G.kap; D.e2 = G.e2; D.eps = (float)G.eps; D.Sigma = G.Sigma;
