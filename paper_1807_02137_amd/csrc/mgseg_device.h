@@ -864,17 +864,21 @@ __device__ __forceinline__ void long_band(const LineArgs &A, int b, float *ring,
         __syncthreads();
         float carry = 0.0f;
         bool pend = false;                       // the last round's cell waits for a unit ending in this one
+        // the next round's inputs are read at the start of a round (round 0: here),
+        // so that their latency overlaps the round's computation
+        CellIn cn;
+        if (t < ml) cell_load<REV, CF>(R, ml, t, cn);
 #pragma nounroll
         for (int k = 0; k < K; k++) {
             const int p = k * NT + t;
             const bool in = p < ml;
+            const CellIn c = cn;
+            if (p + NT < ml) cell_load<REV, CF>(R, ml, p + NT, cn);
             CellRow w;
             w.ok = false; w.x = 0.0f;
             bool inu = false, last = false;
             int ps = p, L = 1;
             if (in) {
-                CellIn c;
-                cell_load<REV, CF>(R, ml, p, c);
                 const float vu = has_up ? (up_fresh ? prev[p] : c.vu) : 0.0f;
                 const float vd = has_dn ? (dn_fresh ? red[p] : c.vd) : 0.0f;
                 w = cell_row<REV, CF>(A, c, r, cell(p), vu, vd, area);
