@@ -118,9 +118,11 @@ struct LineArgs {
 
 // Row buffer of the line being swept, indexed by visit position p:
 //   a y_{p-1} - y_p + c y_{p+1} = r  (a = NaN marks S = 0), box [lo, hi],
-// x = old value, y = new value of a unit cell.  In LDS: the whole line for
-// lines of one workgroup, a ring of two rounds for longer lines.
+// x = old value; y = new value of a unit cell (the long-line ring only).  In
+// LDS: two buffers of the whole line (RB_FIELDS fields each) for lines of
+// one workgroup, a ring of two rounds (RF_COUNT fields) for longer lines.
 enum { RF_A = 0, RF_C, RF_R, RF_LO, RF_HI, RF_X, RF_Y, RF_COUNT };
+enum { RB_FIELDS = RF_Y };
 
 struct RunBuf {
     float *p;
@@ -131,7 +133,8 @@ struct RunBuf {
     {
         return last + 1 < ml ? at(RF_X, last + 1) : 0.0f;
     }
-    __device__ __forceinline__ float &y(int q) const { return at(RF_Y, q); }
+    // the other of the two buffers of a line
+    __device__ __forceinline__ RunBuf other(int k) const { return RunBuf{p + k * RB_FIELDS * fs, fs}; }
 };
 
 // 64-bit starred-mask words of a line of ml cells
@@ -538,159 +541,105 @@ __device__ __forceinline__ void row_store(const Buf &B, int p, const CellRow &w)
 }
 
 // --------------------------------------------------------------------------
-// One line of one directional sweep.  Cells are taken in visit order
-// (REV: q = ml-1 down to 0); thread t handles visit positions p = k*NT + t
-// for rounds k = 0..K-1, so that every load is coalesced.  REV takes the
-// upstream line at r+1.  up_fresh / dn_fresh: the cross-line neighbour
-// values are the caller's registers (same thread, same round = same cell)
-// instead of phi_old.  On return val[] holds the new values of the
-// thread's cells.  Every point and every unit is a clipped ramp of the value
-// entering it, so the line is one block scan; a unit's ramp sits at its first
-// position and its other cells take the identity.
+// One line of one directional sweep, one thread per cell (visit position
+// p = thread; REV: q = ml-1 down to 0), lines of at most NT cells.  REV takes
+// the upstream line at r+1.  up_fresh / dn_fresh: the cross-line neighbour
+// values are the caller's registers (same thread = same cell) instead of
+// phi_old.  On return val[0] holds the thread's new value.
+//
+// Every point and every unit is a clipped ramp of the value entering it, so
+// the line is one block scan.  A unit's chain ramp sits at its LAST cell and
+// its other cells take the identity, so that the scan's exclusive prefix at
+// every cell of a unit is the value entering the unit: each unit cell then
+// solves its unit from the rows in LDS and keeps its own value, with no
+// exchange of results.  Barriers: one after the rows and masks are written,
+// one inside the scan (several waves).  The rows live in one of two buffers
+// chosen by the caller's line parity, so that the next line can write the
+// other while this one's cells still read theirs after the scan; the masks
+// are read before the scan only.
 template <int NT, int K, bool REV, bool CF = false>
 __device__ __forceinline__ void sweep_line(const LineArgs &A, int r, const RunBuf &B, uint64_t *msk, bool write,
                                            const float (&upv)[K], bool up_fresh, const float (&dnv)[K],
                                            bool dn_fresh, float (&val)[K], Ramp *wtot, const CellIn (&L)[K])
 {
+    static_assert(K == 1, "one cell per thread: longer lines run in k_sweep_long");
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    const int nl = A.nl, ml = A.ml, P = A.pitch, nw = (ml + 63) >> 6;
+    const int nl = A.nl, ml = A.ml, nw = (ml + 63) >> 6;
     const int ru = REV ? r + 1 : r - 1;      // upstream line
     const int rd = REV ? r - 1 : r + 1;      // downstream line
-    const long long ro = (long long)r * P;
     const float area = A.area ? (float)(*A.area) : 0.0f;
     const bool has_up = ru >= 0 && ru < nl, has_dn = rd >= 0 && rd < nl;
-    auto cell = [&](int p) { return REV ? ml - 1 - p : p; };
+    const int p = t;
+    const bool in = p < ml;
+    const int q = REV ? ml - 1 - p : p;
 
-    // phase 1: frozen coefficients (eq. abcdrc), point ramps, unit rows,
-    // starred masks, from the line's inputs read by line_load
-    float pa[K], pb[K], plo[K], phv[K];
-    unsigned sm = 0;
-    bool any_star = false;
-#pragma unroll
-    for (int k = 0; k < K; k++) {
-        const int p = k * NT + t;
-        pa[k] = 0.0f; pb[k] = 0.0f; plo[k] = 0.0f; phv[k] = 0.0f;
-        bool s0 = false;
-        if (p < ml) {
-            const CellIn &c = L[k];
-            s0 = ((c.lab >> A.bit) & 1) != 0;
-            float vu = 0.0f, vd = 0.0f;
-            if (has_up) vu = up_fresh ? upv[k] : c.vu;
-            if (has_dn) vd = dn_fresh ? dnv[k] : c.vd;
-            const CellRow w = cell_row<REV, CF>(A, c, r, cell(p), vu, vd, area);
-            const Ramp u = cell_ramp(w);
-            pa[k] = u.a; pb[k] = u.b; plo[k] = u.lo; phv[k] = u.hi;
-            row_store(B, p, w);
-        }
-        const unsigned long long bm = __ballot(s0);
-        if (lane == 0 && k * NT + wave * 64 < ml) msk[((k * NT) >> 6) + wave] = bm;
-        if (s0) { sm |= 1u << k; any_star = true; }
+    // phase 1: frozen coefficients (eq. abcdrc), the row of the cell, starred masks
+    CellRow w;
+    w.ok = false; w.x = 0.0f;
+    bool s0 = false;
+    if (in) {
+        const CellIn &c = L[0];
+        s0 = ((c.lab >> A.bit) & 1) != 0;
+        float vu = 0.0f, vd = 0.0f;
+        if (has_up) vu = up_fresh ? upv[0] : c.vu;
+        if (has_dn) vd = dn_fresh ? dnv[0] : c.vd;
+        w = cell_row<REV, CF>(A, c, r, q, vu, vd, area);
+        row_store(B, p, w);
     }
-    any_star = __syncthreads_or(any_star);
+    const unsigned long long bm = __ballot(s0);
+    if (lane == 0 && wave * 64 < ml) msk[wave] = bm;
+    const bool any_star = __syncthreads_or(s0);
 
-    // phase 2: unit membership; units starting here get their chain ramp
-    unsigned inunit = 0, ustart = 0;
-    int uL[K];
-    Ramp um[K];
-#pragma unroll
-    for (int k = 0; k < K; k++) { uL[k] = 0; um[k] = ramp_id(); }
-    if (any_star) {
-#pragma unroll
-        for (int k = 0; k < K; k++) {
-            const int p = k * NT + t;
-            if (p >= ml) continue;
-            if ((sm >> k) & 1) {
-                inunit |= 1u << k;
-                int ps, L;
-                unit_of(msk, nw, ml, p, ps, L);
-                if (ps == p) {
-                    ustart |= 1u << k;
-                    uL[k] = L;
-                    if (L <= 2) {
-                        PairRows Q;
-                        pair_load(B, p, L, ml, Q);
-                        um[k] = pair_ramp(Q, L);
-                    } else {
-                        TriRows T3;
-                        tri_load(B, p, ml, T3);
-                        um[k] = tri_ramp(T3);
-                    }
-                }
-            } else if (p >= 1 && mask_bit(msk, p - 1) && (p < 2 || !mask_bit(msk, p - 2))) {
-                inunit |= 1u << k;         // the cell after a single starred cell
-            }
+    // phase 2: the cell's unit (ps, L; L = 0: a point); the unit's chain ramp at its last cell
+    int ps = p, Lu = 0;
+    Ramp u = ramp_id();
+    if (in) {
+        if (any_star) {
+            if (s0) unit_of(msk, nw, ml, p, ps, Lu);
+            else if (p >= 1 && mask_bit(msk, p - 1) && (p < 2 || !mask_bit(msk, p - 2))) { ps = p - 1; Lu = 2; }
         }
-    }
-
-    // phase 3: scan round by round in visit order; carry = value leaving the round
-    float carry = 0.0f;
-    float xin[K];
-#pragma unroll
-    for (int k = 0; k < K; k++) {
-        const int p = k * NT + t;
-        xin[k] = 0.0f;
-        Ramp u = ramp_id();
-        if (p < ml) {
-            if (!((inunit >> k) & 1)) u = Ramp{pa[k], pb[k], plo[k], phv[k]};
-            else if ((ustart >> k) & 1) u = um[k];
-        }
-        Ramp tot;
-        const Ramp ex = block_scan_excl<NT>(u, wtot, k & 1, tot);
-        const float x = ramp_eval(ex, carry);
-        if (p < ml) {
-            if ((ustart >> k) & 1) xin[k] = x;
-            if (!((inunit >> k) & 1)) val[k] = ramp_eval(u, x);
-        }
-        carry = ramp_eval(tot, carry);
-    }
-
-    // phase 4: units at their actual entering value
-    if (any_star) {
-#pragma unroll
-        for (int k = 0; k < K; k++) {
-            if (!((ustart >> k) & 1)) continue;
-            const int p = k * NT + t;
-            if (uL[k] <= 2) {
+        if (Lu == 0) {
+            u = cell_ramp(w);
+        } else if (ps + Lu - 1 == p) {
+            if (Lu <= 2) {
                 PairRows Q;
-                pair_load(B, p, uL[k], ml, Q);
-                float y0, y1;
-                pair_solve(Q, uL[k], xin[k], y0, y1);
-                B.y(p) = y0;
-                if (uL[k] == 2) B.y(p + 1) = y1;
-                continue;
+                pair_load(B, ps, Lu, ml, Q);
+                u = pair_ramp(Q, Lu);
+            } else {
+                TriRows T3;
+                tri_load(B, ps, ml, T3);
+                u = tri_ramp(T3);
             }
-            TriRows T3;
-            tri_load(B, p, ml, T3);
-            float y0, y1, y2;
-            tri_solve(T3, xin[k], y0, y1, y2);
-            B.y(p) = y0;
-            B.y(p + 1) = y1;
-            B.y(p + 2) = y2;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < K; k++) {
-            const int p = k * NT + t;
-            if (p < ml && ((inunit >> k) & 1)) val[k] = B.y(p);
         }
     }
-    if (write) {
-        if (A.tout) {
-#pragma unroll
-            for (int k = 0; k < K; k++) {
-                const int p = k * NT + t;
-                if (p < ml) A.tout[(long long)cell(p) * A.tpitch + r] = val[k];
-            }
+
+    // phase 3: the scan gives every cell the value entering it (a unit cell: entering its unit)
+    Ramp tot;
+    const Ramp ex = block_scan_excl<NT>(u, wtot, 0, tot);
+    const float x = ramp_eval(ex, 0.0f);
+    float v = 0.0f;
+    if (in) {
+        if (Lu == 0) {
+            v = ramp_eval(u, x);
+        } else if (Lu <= 2) {
+            PairRows Q;
+            pair_load(B, ps, Lu, ml, Q);
+            float y0, y1;
+            pair_solve(Q, Lu, x, y0, y1);
+            v = p == ps ? y0 : y1;
         } else {
-            float *orow = A.phi_new + ro;
-#pragma unroll
-            for (int k = 0; k < K; k++) {
-                const int p = k * NT + t;
-                if (p < ml) orow[cell(p)] = val[k];
-            }
+            TriRows T3;
+            tri_load(B, ps, ml, T3);
+            float y0, y1, y2;
+            tri_solve(T3, x, y0, y1, y2);
+            v = p == ps ? y0 : (p == ps + 1 ? y1 : y2);
         }
     }
-    __syncthreads();
+    val[0] = v;
+    if (write && in) {
+        if (A.tout) A.tout[(long long)q * A.tpitch + r] = v;
+        else A.phi_new[(long long)r * A.pitch + q] = v;
+    }
 }
 
 // One band of four lines (one per class r mod 4) of a directional sweep,
@@ -734,8 +683,12 @@ __device__ __forceinline__ void band_step(int r0, int nl, int st, int &r, bool &
 // PF: read the next step's inputs (line_load) before computing the current
 // line, so that their latency overlaps the current line's phases (costs the
 // registers of one more CellIn per round).
+// B: the first of two row buffers; lpar: the caller's running line count,
+// whose parity picks the buffer of each line (it continues across bands
+// that one workgroup takes one after another).
 template <int NT, int K, bool REV, bool PF = false, bool CF = false>
-__device__ __forceinline__ void sweep_band(const LineArgs &A, int b, const RunBuf &B, uint64_t *msk, Ramp *wtot)
+__device__ __forceinline__ void sweep_band(const LineArgs &A, int b, const RunBuf &B, uint64_t *msk, Ramp *wtot,
+                                           int &lpar)
 {
     float prev[K], red[K], cur[K];
     // transposed output of a full band: the band's 4 lines are 4 consecutive
@@ -773,7 +726,9 @@ __device__ __forceinline__ void sweep_band(const LineArgs &A, int b, const RunBu
         } else {
             line_load<NT, K, REV, CF>(A, r, up_fresh, dn_fresh, la);
         }
-        sweep_line<NT, K, REV, CF>(A, r, B, msk, !redundant && !pack, prev, up_fresh, red, dn_fresh, cur, wtot, la);
+        sweep_line<NT, K, REV, CF>(A, r, B.other(lpar & 1), msk, !redundant && !pack, prev, up_fresh, red, dn_fresh,
+                                   cur, wtot, la);
+        lpar++;
         const int li = r - r0;
 #pragma unroll
         for (int k = 0; k < K; k++) {
@@ -964,10 +919,10 @@ __global__ void __launch_bounds__(NT) k_sweep_long(LineArgs A)
     long_band<NT, REV, CF>(A, blockIdx.x, ring, prev, prev + A.ml, msk, wtot);
 }
 
-// dynamic LDS: [starred masks, 8 B per 64 cells][RF_COUNT * ml floats unit rows]
+// dynamic LDS: [starred masks, 8 B per 64 cells][2 x RB_FIELDS * ml floats of rows]
 __host__ __device__ inline size_t sweep_lds_bytes(int ml)
 {
-    return (size_t)sweep_mask_words(ml) * 8 + (size_t)RF_COUNT * ml * sizeof(float);
+    return (size_t)sweep_mask_words(ml) * 8 + 2 * (size_t)RB_FIELDS * ml * sizeof(float);
 }
 
 template <int NT, int K, bool REV, bool CF>
@@ -982,5 +937,6 @@ __global__ void __launch_bounds__(NT) k_sweep(LineArgs A)
     B.p = reinterpret_cast<float *>(smem64 + sweep_mask_words(A.ml));
     // read-ahead of the next line where the registers allow it (at 1024 threads, 128 registers per
     // lane: only with the stored coefficients)
-    sweep_band<NT, K, REV, ((NT <= 512 || CF) && K == 1), CF>(A, blockIdx.x, B, msk, wtot);
+    int lpar = 0;
+    sweep_band<NT, K, REV, ((NT <= 512 || CF) && K == 1), CF>(A, blockIdx.x, B, msk, wtot, lpar);
 }

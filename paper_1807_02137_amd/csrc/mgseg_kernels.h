@@ -881,7 +881,7 @@ __global__ void __launch_bounds__(NT) k_coarse_smooth(CoarseArgs G)
     __shared__ Ramp sh[2 * (NT / 64 > 0 ? NT / 64 : 1)];
     __shared__ double red[NT];
     __shared__ float rdt[NT];
-    __shared__ float rb[RF_COUNT * NT];
+    __shared__ float rb[2 * RB_FIELDS * NT];
     __shared__ uint64_t msk[(NT + 63) / 64];
     extern __shared__ float co[];
     const int n = G.n, m = G.m, N = n * m, tid = threadIdx.x;
@@ -964,18 +964,24 @@ __global__ void __launch_bounds__(NT) k_coarse_smooth(CoarseArgs G)
             }
         }
         __syncthreads();
-        // sweeps A and B (rows)
+        // sweeps A and B (rows); the sweep output is read by the next sweep
+        // after a barrier (the bands of one sweep read only its input)
+        int lpar = 0;
         R.phi_old = P0; R.phi_new = P1; R.bit = 0;
-        for (int b = 0; b < (n + 3) / 4; b++) sweep_band<NT, 1, false>(R, b, RBr, msk, sh);
+        for (int b = 0; b < (n + 3) / 4; b++) sweep_band<NT, 1, false>(R, b, RBr, msk, sh, lpar);
+        __syncthreads();
         R.phi_old = P1; R.phi_new = P2; R.bit = 1;
-        for (int b = 0; b < (n + 3) / 4; b++) sweep_band<NT, 1, true>(R, b, RBr, msk, sh);
+        for (int b = 0; b < (n + 3) / 4; b++) sweep_band<NT, 1, true>(R, b, RBr, msk, sh, lpar);
+        __syncthreads();
         block_transpose<NT>(P2, m, T1, n, n, m);
         __syncthreads();
         // sweeps C and D (columns)
         T.phi_old = T1; T.phi_new = T2; T.bit = 2;
-        for (int b = 0; b < (m + 3) / 4; b++) sweep_band<NT, 1, false>(T, b, RBc, msk, sh);
+        for (int b = 0; b < (m + 3) / 4; b++) sweep_band<NT, 1, false>(T, b, RBc, msk, sh, lpar);
+        __syncthreads();
         T.phi_old = T2; T.phi_new = T1; T.bit = 3;
-        for (int b = 0; b < (m + 3) / 4; b++) sweep_band<NT, 1, true>(T, b, RBc, msk, sh);
+        for (int b = 0; b < (m + 3) / 4; b++) sweep_band<NT, 1, true>(T, b, RBc, msk, sh, lpar);
+        __syncthreads();
         float dmax = 0.0f, tot = 0.0f;
         for (int t = tid; t < N; t += NT) {
             const int i = t / m, j = t % m;
