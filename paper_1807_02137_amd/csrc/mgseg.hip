@@ -182,12 +182,18 @@ void area_term(mgseg_ctx *c, int l, const float *phi, int pp, int slot)
 
 void update_fit(mgseg_ctx *c)
 {
+    FitLevels F;
+    F.L = c->L;
+    F.row0[0] = 0;
     for (int l = 0; l < c->L; l++) {
-        Level &L = c->lev[l];
-        hipLaunchKernelGGL(k_fit, grid2(L.n, L.m), dim3(256), 0, c->s, L.z, L.d, L.prm, L.n, L.m, c->dsc + DS_C1,
-                           (float)c->p.lambda1, (float)c->p.lambda2, (float)c->p.theta, c->p.model, L.fit, L.fit_cm,
-                           L.pcm);
+        const Level &L = c->lev[l];
+        F.z[l] = L.z; F.d[l] = L.d; F.fit[l] = L.fit; F.fit_cm[l] = L.fit_cm;
+        F.p[l] = L.prm; F.pc[l] = L.pcm; F.n[l] = L.n; F.m[l] = L.m;
+        F.row0[l + 1] = F.row0[l] + L.n;
     }
+    const dim3 g((c->m + 255) / 256, F.row0[c->L]);
+    hipLaunchKernelGGL(k_fit, g, dim3(256), 0, c->s, F, c->dsc + DS_C1, (float)c->p.lambda1, (float)c->p.lambda2,
+                       (float)c->p.theta, c->p.model);
 }
 
 // c1, c2 (eq. c1c2) from the FP64 finest phi
@@ -490,12 +496,12 @@ void vcycle_from(mgseg_ctx *c, int l0)
         residual(c, l, L.r, nullptr);
         dim3 gc = grid2(Lc.n, Lc.m);
         if (dev) {
-            hipLaunchKernelGGL(k_restrict, gc, dim3(256), 0, c->s, L.r, L.prm, Lc.G, Lc.prm, Lc.n, Lc.m);
+            // the residual (to G) and the state (base, deviation, bounds) in one launch
             with_dev(c, l, [&](auto A) {
                 using BT = std::remove_const_t<std::remove_pointer_t<decltype(A.b)>>;
                 hipLaunchKernelGGL(k_restrict_dev<BT>, gc, dim3(256), 0, c->s, A.b, A.pb, L.P[0], L.lo, L.hi, L.prm,
                                    L.n, L.m, Lc.phic, Lc.P[0], Lc.lo, Lc.hi, Lc.prm, Lc.n, Lc.m, Lc.lo_cm, Lc.hi_cm,
-                                   Lc.pcm);
+                                   Lc.pcm, L.r, Lc.G);
             });
             if (c->p.model == 1) area_term(c, l + 1, Lc.phic, Lc.prm, DS_AREAB0 + l + 1);
         } else {

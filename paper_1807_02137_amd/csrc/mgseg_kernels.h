@@ -107,19 +107,20 @@ __device__ __forceinline__ float fw_row(const float *row, int J, int mc)
     if (J < mc - 1) return 0.25f * row[2 * J] + 0.5f * row[2 * J + 1] + 0.25f * row[2 * J + 2];
     return 0.5f * row[2 * J] + 0.5f * row[2 * J + 1];
 }
+__device__ __forceinline__ float fw2(const float *f, int pf, int I, int J, int nc, int mc)
+{
+    const float *r0 = f + (long long)(2 * I) * pf, *r1 = r0 + pf;
+    if (I < nc - 1) {
+        const float *r2 = r1 + pf;
+        return 0.25f * fw_row(r0, J, mc) + 0.5f * fw_row(r1, J, mc) + 0.25f * fw_row(r2, J, mc);
+    }
+    return 0.5f * fw_row(r0, J, mc) + 0.5f * fw_row(r1, J, mc);
+}
 __global__ void k_restrict(const float *f, int pf, float *c, int pc, int nc, int mc)
 {
     int J = blockIdx.x * blockDim.x + threadIdx.x, I = blockIdx.y;
     if (J >= mc || I >= nc) return;
-    const float *r0 = f + (long long)(2 * I) * pf, *r1 = r0 + pf;
-    float v;
-    if (I < nc - 1) {
-        const float *r2 = r1 + pf;
-        v = 0.25f * fw_row(r0, J, mc) + 0.5f * fw_row(r1, J, mc) + 0.25f * fw_row(r2, J, mc);
-    } else {
-        v = 0.5f * fw_row(r0, J, mc) + 0.5f * fw_row(r1, J, mc);
-    }
-    c[(long long)I * pc + J] = v;
+    c[(long long)I * pc + J] = fw2(f, pf, I, J, nc, mc);
 }
 
 // coarse bounds of the box reading: the coarse unknown may move only as far as
@@ -313,19 +314,30 @@ __global__ void k_coarse_rhs(const float *phic, const float *w, const float *fit
     phi_init[q] = phic[q];
 }
 
-// fit map with the current c1, c2 (Spencer-Chen adds theta d)
-__global__ void k_fit(const float *z, const float *d, int p, int n, int m, const double *c12, float l1, float l2,
-                      float theta, int model, float *fit, float *fit_cm, int pc)
+// fit maps of every level with the current c1, c2 (Spencer-Chen adds theta d),
+// one launch: block row y covers row y - row0[l] of the level l whose rows
+// [row0[l], row0[l+1]) contain y
+#define FIT_MAXLEV 16
+struct FitLevels {
+    const float *z[FIT_MAXLEV], *d[FIT_MAXLEV];
+    float *fit[FIT_MAXLEV], *fit_cm[FIT_MAXLEV];
+    int p[FIT_MAXLEV], pc[FIT_MAXLEV], n[FIT_MAXLEV], m[FIT_MAXLEV], row0[FIT_MAXLEV + 1];
+    int L;
+};
+__global__ void k_fit(FitLevels F, const double *c12, float l1, float l2, float theta, int model)
 {
-    int j = blockIdx.x * blockDim.x + threadIdx.x, i = blockIdx.y;
-    if (j >= m || i >= n) return;
-    long long q = (long long)i * p + j;
-    float c1 = (float)c12[0], c2 = (float)c12[1];
-    float a = z[q] - c1, b = z[q] - c2;
+    const int y = blockIdx.y;
+    int l = 0;
+    while (l + 1 < F.L && y >= F.row0[l + 1]) l++;
+    const int i = y - F.row0[l], j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= F.m[l] || i >= F.n[l]) return;
+    const long long q = (long long)i * F.p[l] + j;
+    const float c1 = (float)c12[0], c2 = (float)c12[1];
+    const float a = F.z[l][q] - c1, b = F.z[l][q] - c2;
     float v = l1 * a * a - l2 * b * b;
-    if (model == 0) v += theta * d[q];
-    fit[q] = v;
-    fit_cm[(long long)j * pc + i] = v;
+    if (model == 0) v += theta * F.d[l][q];
+    F.fit[l][q] = v;
+    F.fit_cm[l][(long long)j * F.pc[l] + i] = v;
 }
 
 // ==========================================================================
@@ -757,13 +769,16 @@ __device__ __forceinline__ double fw_row_dev(const BT *b, int pb, const float *e
     if (J < mc - 1) return 0.25 * V(2 * J) + 0.5 * V(2 * J + 1) + 0.25 * V(2 * J + 2);
     return 0.5 * V(2 * J) + 0.5 * V(2 * J + 1);
 }
+// (also the restricted residual rc = FW r of the fine residual r, pitch p,
+// into Gc, pitch pc: both transfers of a level in one launch)
 template <typename BT>
 __global__ void k_restrict_dev(const BT *b, int pb, const float *e, const float *lo, const float *hi, int p, int n,
                                int m, float *bc, float *ec, float *clo, float *chi, int pc, int nc, int mc,
-                               float *clo_cm, float *chi_cm, int pcc)
+                               float *clo_cm, float *chi_cm, int pcc, const float *r, float *Gc)
 {
     int J = blockIdx.x * blockDim.x + threadIdx.x, I = blockIdx.y;
     if (J >= mc || I >= nc) return;
+    Gc[(long long)I * pc + J] = fw2(r, p, I, J, nc, mc);
     double v;
     if (I < nc - 1)
         v = 0.25 * fw_row_dev(b, pb, e, p, 2 * I, J, mc) + 0.5 * fw_row_dev(b, pb, e, p, 2 * I + 1, J, mc) +
