@@ -115,9 +115,13 @@ const char *mgseg_strerror(mgseg_status s);
  *                      for its polygon area A1).
  *   n, m             : at least 2.
  *   stream           : a hipStream_t (0 = default stream), passed as void*.
+ * Memory: every device array of the context is a piece of one allocation
+ * (about 230 B per finest-grid cell in the mixed mode, all levels), freed by
+ * mgseg_destroy.
  * Errors: MGSEG_E_ARG (null pointers, k out of range, a marker outside the
  * image or not finite, pitch < m, bad struct_size),
- * MGSEG_E_SHAPE (n or m not divisible by 2^(levels-1)), MGSEG_E_NOMEM.
+ * MGSEG_E_SHAPE (n or m not divisible by 2^(levels-1), a side above 8192, or
+ * lines longer than the device's LDS per workgroup allows), MGSEG_E_NOMEM.
  */
 mgseg_status mgseg_setup(const float *image_dev, int n, int m, int pitch,
                          const float *markers_host, int k, const mgseg_params *p,
@@ -319,8 +323,9 @@ mgseg_status mgseg_ctx_features(mgseg_ctx *c, float *out_dev);
  * point of the box-constrained problem) would lead the solve to another
  * fixed point.  Otherwise the marker-based phi0 is restored
  * (mgseg_reset_phi0), so the solve always starts from a valid guess.
- * *accepted_out (may be null): 1 if the network's phi0 was taken.  Allocates
- * the features and the network output (4 n m floats) for the call. */
+ * *accepted_out (may be null): 1 if the network's phi0 was taken.  The first
+ * call on a context allocates the features and the network output (4 n m
+ * floats); they stay with the context until mgseg_destroy. */
 mgseg_status mgseg_predict_phi0(mgseg_ctx *c, mgseg_net *n, double scale, int *accepted_out);
 
 #ifdef __cplusplus

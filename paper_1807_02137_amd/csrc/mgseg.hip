@@ -66,7 +66,9 @@ struct mgseg_ctx {
     const int *sweep_skip = nullptr;
     double *hull_d = nullptr, *mk_d = nullptr;
     int hv = 0, k = 0;
-    std::vector<void *> allocs;
+    char *arena = nullptr;          // every device array of the context (dalloc)
+    size_t arena_size = 0, arena_used = 0;
+    float *pred = nullptr;          // network input and output of mgseg_predict_phi0 (first call)
     hipError_t err = hipSuccess;
     bool oom = false;
     // one V-cycle captured as a HIP graph (replayed on s); cap: private capture stream
@@ -84,16 +86,20 @@ namespace {
 
 const int RED_BLOCKS = 1024;
 
+// A context's device arrays are pieces (256-byte aligned) of one allocation,
+// the arena: setup runs its allocation sequence once to size the arena
+// (arena null: dalloc only counts) and once to hand out the pieces, so that
+// setup makes one allocation and one zero fill and destroy one free.
 template <typename T>
 T *dalloc(mgseg_ctx *c, size_t count)
 {
-    void *p = nullptr;
     if (count == 0) count = 1;
-    hipError_t e = hipMalloc(&p, count * sizeof(T));
-    if (e != hipSuccess) { c->oom = true; (void)hipGetLastError(); return nullptr; }
-    c->allocs.push_back(p);
-    (void)hipMemsetAsync(p, 0, count * sizeof(T), c->s);
-    return (T *)p;
+    const size_t bytes = (count * sizeof(T) + 255) & ~(size_t)255;
+    const size_t off = c->arena_used;
+    c->arena_used += bytes;
+    if (!c->arena) return nullptr;
+    if (c->arena_used > c->arena_size) { c->oom = true; return nullptr; }
+    return reinterpret_cast<T *>(c->arena + off);
 }
 
 inline int pad64(int x) { return (x + 63) / 64 * 64; }
@@ -700,7 +706,8 @@ void mgseg_destroy(mgseg_ctx *c)
     if (c->cap) (void)hipStreamDestroy(c->cap);
     if (c->hres) (void)hipHostFree(c->hres);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
-    for (void *p : c->allocs) (void)hipFree(p);
+    if (c->arena) (void)hipFree(c->arena);
+    if (c->pred) (void)hipFree(c->pred);
     delete c;
 }
 
@@ -754,41 +761,66 @@ mgseg_status mgseg_setup(const float *image_dev, int n, int m, int pitch, const 
     c->L = Lv; c->n = n; c->m = m;
     c->h0 = 1.0 / std::sqrt((double)n * (double)m);
     size_t N = (size_t)n * m;
-    for (int l = 0; l < Lv; l++) {
-        Level &L = c->lev[l];
-        L.n = n >> l; L.m = m >> l; L.h = c->h0 * (double)(1 << l);
-        L.prm = pad64(L.m); L.pcm = pad64(L.n);
-        size_t Nr = (size_t)L.n * L.prm, Nc = (size_t)L.m * L.pcm;
-        L.z = dalloc<float>(c, Nr); L.d = dalloc<float>(c, Nr); L.w = dalloc<float>(c, Nr);
-        L.fit = dalloc<float>(c, Nr); L.F = dalloc<float>(c, Nr);
-        for (int t = 0; t < 3; t++) { L.P[t] = dalloc<float>(c, Nr); L.T[t] = dalloc<float>(c, Nc); }
-        L.psi = dalloc<float>(c, Nr); L.psi_cm = dalloc<float>(c, Nc);
-        L.phic = dalloc<float>(c, Nr); L.r = dalloc<float>(c, Nr); L.G = dalloc<float>(c, Nr);
-        L.lo = dalloc<float>(c, Nr); L.hi = dalloc<float>(c, Nr);
-        L.w_cm = dalloc<float>(c, Nc); L.fit_cm = dalloc<float>(c, Nc); L.F_cm = dalloc<float>(c, Nc);
-        L.lo_cm = dalloc<float>(c, Nc); L.hi_cm = dalloc<float>(c, Nc);
-        L.lab = dalloc<uint8_t>(c, Nr); L.lab_cm = dalloc<uint8_t>(c, Nc);
-        if (p->mixed_precision) { L.cf = dalloc<float4>(c, Nr); L.cf_cm = dalloc<float4>(c, Nc); }
+    // Gaussian kernel of the image smoothing
+    int R = (int)std::ceil(4.0 * p->sigma_g);
+    std::vector<double> ker(2 * R + 1);
+    double ks = 0.0;
+    for (int t = -R; t <= R; t++) {
+        double v = p->sigma_g > 0 ? std::exp(-(double)(t * t) / (2.0 * p->sigma_g * p->sigma_g)) : (t == 0);
+        ker[t + R] = v; ks += v;
     }
-    c->phi64 = dalloc<double>(c, N); c->w64 = dalloc<double>(c, N); c->d64 = dalloc<double>(c, N);
-    c->g64 = dalloc<double>(c, N); c->prev64 = dalloc<double>(c, N); c->phi0m = dalloc<double>(c, N);
-    c->dsc = dalloc<double>(c, DS_COUNT);
-    c->part_n = 8 * RED_BLOCKS + (int)((N + 255) / 256) + n + 16;
-    c->part = dalloc<double>(c, (size_t)c->part_n);
-    {
-        const Level &Lc = c->lev[Lv - 1];
-        c->co_prev = dalloc<float>(c, (size_t)Lc.n * Lc.prm);
-        c->co_entry = dalloc<float>(c, (size_t)Lc.n * Lc.prm);
+    for (auto &v : ker) v /= ks;
+    double *zb = nullptr, *t64 = nullptr, *ker_d = nullptr;
+    // the allocation sequence: sizing pass, then the pieces of the arena
+    auto carve = [&]() {
+        c->arena_used = 0;
+        for (int l = 0; l < Lv; l++) {
+            Level &L = c->lev[l];
+            L.n = n >> l; L.m = m >> l; L.h = c->h0 * (double)(1 << l);
+            L.prm = pad64(L.m); L.pcm = pad64(L.n);
+            size_t Nr = (size_t)L.n * L.prm, Nc = (size_t)L.m * L.pcm;
+            L.z = dalloc<float>(c, Nr); L.d = dalloc<float>(c, Nr); L.w = dalloc<float>(c, Nr);
+            L.fit = dalloc<float>(c, Nr); L.F = dalloc<float>(c, Nr);
+            for (int t = 0; t < 3; t++) { L.P[t] = dalloc<float>(c, Nr); L.T[t] = dalloc<float>(c, Nc); }
+            L.psi = dalloc<float>(c, Nr); L.psi_cm = dalloc<float>(c, Nc);
+            L.phic = dalloc<float>(c, Nr); L.r = dalloc<float>(c, Nr); L.G = dalloc<float>(c, Nr);
+            L.lo = dalloc<float>(c, Nr); L.hi = dalloc<float>(c, Nr);
+            L.w_cm = dalloc<float>(c, Nc); L.fit_cm = dalloc<float>(c, Nc); L.F_cm = dalloc<float>(c, Nc);
+            L.lo_cm = dalloc<float>(c, Nc); L.hi_cm = dalloc<float>(c, Nc);
+            L.lab = dalloc<uint8_t>(c, Nr); L.lab_cm = dalloc<uint8_t>(c, Nc);
+            if (p->mixed_precision) { L.cf = dalloc<float4>(c, Nr); L.cf_cm = dalloc<float4>(c, Nc); }
+        }
+        c->phi64 = dalloc<double>(c, N); c->w64 = dalloc<double>(c, N); c->d64 = dalloc<double>(c, N);
+        c->g64 = dalloc<double>(c, N); c->prev64 = dalloc<double>(c, N); c->phi0m = dalloc<double>(c, N);
+        c->dsc = dalloc<double>(c, DS_COUNT);
+        c->part_n = 8 * RED_BLOCKS + (int)((N + 255) / 256) + n + 16;
+        c->part = dalloc<double>(c, (size_t)c->part_n);
+        {
+            const Level &Lc = c->lev[Lv - 1];
+            c->co_prev = dalloc<float>(c, (size_t)Lc.n * Lc.prm);
+            c->co_entry = dalloc<float>(c, (size_t)Lc.n * Lc.prm);
+        }
+        c->flags = dalloc<int>(c, 4);
+        zb = dalloc<double>(c, N); t64 = dalloc<double>(c, N);
+        c->mk_d = dalloc<double>(c, 2 * (size_t)k);
+        c->hull_d = dalloc<double>(c, 2 * (size_t)k + 2);
+        ker_d = dalloc<double>(c, ker.size());
+    };
+    carve();
+    c->arena_size = c->arena_used;
+    if (hipMalloc((void **)&c->arena, c->arena_size) != hipSuccess) {
+        (void)hipGetLastError();
+        c->arena = nullptr;
+        mgseg_destroy(c);
+        return MGSEG_E_NOMEM;
     }
-    c->flags = dalloc<int>(c, 4);
+    carve();
+    (void)hipMemsetAsync(c->arena, 0, c->arena_size, c->s);
     if (hipHostMalloc((void **)&c->hres, 2 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
         c->hres = nullptr;
         c->oom = true;
     }
-    double *zb = dalloc<double>(c, N), *t64 = dalloc<double>(c, N);
-    c->mk_d = dalloc<double>(c, 2 * (size_t)k);
-    c->hull_d = dalloc<double>(c, 2 * (size_t)k + 2);
     if (c->oom) { mgseg_destroy(c); return MGSEG_E_NOMEM; }
 
     // markers and their convex hull
@@ -800,17 +832,6 @@ mgseg_status mgseg_setup(const float *image_dev, int n, int m, int pitch, const 
     (void)hipMemcpyAsync(c->mk_d, mk.data(), sizeof(double) * mk.size(), hipMemcpyHostToDevice, c->s);
     if (!hull.empty())
         (void)hipMemcpyAsync(c->hull_d, hull.data(), sizeof(double) * hull.size(), hipMemcpyHostToDevice, c->s);
-    // Gaussian kernel
-    int R = (int)std::ceil(4.0 * p->sigma_g);
-    std::vector<double> ker(2 * R + 1);
-    double ks = 0.0;
-    for (int t = -R; t <= R; t++) {
-        double v = p->sigma_g > 0 ? std::exp(-(double)(t * t) / (2.0 * p->sigma_g * p->sigma_g)) : (t == 0);
-        ker[t + R] = v; ks += v;
-    }
-    for (auto &v : ker) v /= ks;
-    double *ker_d = dalloc<double>(c, ker.size());
-    if (c->oom) { mgseg_destroy(c); return MGSEG_E_NOMEM; }
     (void)hipMemcpyAsync(ker_d, ker.data(), sizeof(double) * ker.size(), hipMemcpyHostToDevice, c->s);
 
     Level &L0 = c->lev[0];
@@ -1361,12 +1382,12 @@ mgseg_status mgseg_predict_phi0(mgseg_ctx *c, mgseg_net *net, double scale, int 
 {
     if (!c || !net || !(scale > 0.0 && scale <= 1.0)) return MGSEG_E_ARG;
     const size_t N = (size_t)c->n * c->m;
-    float *feat = nullptr, *phi = nullptr;
-    if (hipMalloc(&feat, sizeof(float) * 3 * N) != hipSuccess || hipMalloc(&phi, sizeof(float) * N) != hipSuccess) {
+    if (!c->pred && hipMalloc((void **)&c->pred, sizeof(float) * 4 * N) != hipSuccess) {
         (void)hipGetLastError();
-        if (feat) (void)hipFree(feat);
+        c->pred = nullptr;
         return MGSEG_E_NOMEM;
     }
+    float *feat = c->pred, *phi = c->pred + 3 * N;
     mgseg_status st = mgseg_ctx_features(c, feat);
     if (st == MGSEG_OK) st = mgseg_net_forward(net, feat, 1, c->n, c->m, scale * c->p.M, phi, c->s);
     int inside = 0;
@@ -1378,9 +1399,6 @@ mgseg_status mgseg_predict_phi0(mgseg_ctx *c, mgseg_net *net, double scale, int 
     }
     if (st == MGSEG_OK) st = inside ? mgseg_set_phi0(c, phi, c->m) : mgseg_reset_phi0(c);
     if (accepted_out) *accepted_out = st == MGSEG_OK ? inside : 0;
-    (void)hipStreamSynchronize(c->s);
-    (void)hipFree(feat);
-    (void)hipFree(phi);
     return st;
 }
 
