@@ -383,7 +383,8 @@ void freeze(mgseg_ctx *c, int l)
         with_dev(c, l, [&](auto A) {
             using BT = std::remove_const_t<std::remove_pointer_t<decltype(A.b)>>;
             A.area_u = rc ? c->dsc + DS_AREA_FRZ : nullptr;
-            // with stored coefficients no sweep reads psi in the column layout
+            // with stored coefficients no sweep reads psi
+            A.psi = L.cf ? nullptr : L.psi;
             A.psi_cm = L.cf ? nullptr : L.psi_cm; A.T_cm = L.F_cm; A.lab_cm = L.lab_cm;
             A.cf = L.cf; A.cf_cm = L.cf_cm;
             dim3 gt((L.m + TILE - 1) / TILE, (L.n + TILE - 1) / TILE);

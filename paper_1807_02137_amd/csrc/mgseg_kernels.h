@@ -634,7 +634,7 @@ template <typename BT>
 struct DevArgs {
     const BT *b; int pb;                       // base and its row pitch
     const float *e, *G, *w, *fit, *lo, *hi;    // row pitch p
-    float *psi, *T, *r;                        // outputs (pitch p), null: not written
+    float *psi, *T, *r;                        // outputs (pitch p); psi null: not written
     uint8_t *lab;                              // labels (pitch p), null: not written
     float *psi_cm, *T_cm;                      // column-major copies (pitch pc), null: not written
                                                // (T_cm null: no column-major output at all)
@@ -719,7 +719,7 @@ __global__ void __launch_bounds__(1024) k_freeze_dev(DevArgs<BT> A)
             float au[4];
             const double t = dev_cell(A, i, j, false, Le, u0, lab, au);
             const long long q = (long long)i * A.p + j;
-            A.psi[q] = u0;
+            if (A.psi) A.psi[q] = u0;
             A.T[q] = (float)t;
             A.lab[q] = lab;
             if (A.cf) A.cf[q] = make_float4(au[0], au[1], au[2], au[3]);
