@@ -398,6 +398,30 @@ def test_batch_large_coarsest_matches_oracle():
     s.close()
 
 
+def test_batch_of_uneven_images_matches_oracle_cycles():
+    """Five of the uneven batch images (288-416 rows, 6 grids each, seeds of the
+    64-image batch workload) solved as one batch on two streams: each reaches
+    1e-6 in the oracle's number of cycles (one more or less where the oracle's
+    last residual sits at the tolerance) with the oracle's segmentation."""
+    say("case uneven batch vs oracle cycle counts")
+    ks = (51, 21, 27, 15, 28)
+    insts = [synth.config3(k) for k in ks]
+    b = mgseg.Batch([i.image for i in insts], [i.markers for i in insts], mgseg.Params(levels=0))
+    b.set_streams(2)
+    cyc, rel, ok = b.solve(1e-6, 80)
+    assert ok
+    for k, inst, cg in zip(ks, insts, cyc):
+        n, m = inst.image.shape
+        L = synth.levels_for(n, m)
+        o = Oracle(inst.image, inst.markers, OracleParams(levels=L))
+        co, hist = o.solve(1e-6, 80)
+        pg, po = b.image(ks.index(k)).get("phi64"), o.get("phi")
+        flips = int(((pg > 0) != (po > 0)).sum())
+        say(f"image {k} {n}x{m}, {L} grids: gpu {cg} cycles, oracle {co}; flips {flips}")
+        assert abs(cg - co) <= 1 and flips <= 2
+    b.close()
+
+
 def test_batch_tuner_picks_a_stream_count():
     say("case batch tuner")
     insts = _batch_inputs()
