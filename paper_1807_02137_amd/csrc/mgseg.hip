@@ -278,15 +278,15 @@ void launch_sweep(mgseg_ctx *c, int l, int s, const float *phi_old, float *phi_n
         return;
     }
     const size_t lds = sweep_lds_bytes(ml), llds = long_lds_bytes<1024>(ml);
-#define MG_SWEEP_CF(NT, K, CF)                                                                       \
-    do {                                                                                                 \
-        if (rev) hipLaunchKernelGGL((k_sweep<NT, K, true, CF>), dim3(bands), dim3(NT), lds, c->s, A); \
-        else hipLaunchKernelGGL((k_sweep<NT, K, false, CF>), dim3(bands), dim3(NT), lds, c->s, A);    \
+#define MG_SWEEP_CF(NT, CF)                                                                       \
+    do {                                                                                              \
+        if (rev) hipLaunchKernelGGL((k_sweep<NT, true, CF>), dim3(bands), dim3(NT), lds, c->s, A); \
+        else hipLaunchKernelGGL((k_sweep<NT, false, CF>), dim3(bands), dim3(NT), lds, c->s, A);    \
     } while (0)
-#define MG_SWEEP(NT, K)                 \
-    do {                                \
-        if (cfm) MG_SWEEP_CF(NT, K, true);  \
-        else MG_SWEEP_CF(NT, K, false); \
+#define MG_SWEEP(NT)                   \
+    do {                               \
+        if (cfm) MG_SWEEP_CF(NT, true);    \
+        else MG_SWEEP_CF(NT, false);   \
     } while (0)
 #define MG_SWEEP_LONG_CF(CF)                                                                                    \
     do {                                                                                                        \
@@ -313,11 +313,11 @@ void launch_sweep(mgseg_ctx *c, int l, int s, const float *phi_old, float *phi_n
         (void)hipEventRecord(e0, c->s);
     }
     // one thread per cell up to 1024-cell lines; longer lines take rounds
-    if (ml <= 64) MG_SWEEP(64, 1);
-    else if (ml <= 128) MG_SWEEP(128, 1);
-    else if (ml <= 256) MG_SWEEP(256, 1);
-    else if (ml <= 512) MG_SWEEP(512, 1);
-    else if (ml <= 1024) MG_SWEEP(1024, 1);
+    if (ml <= 64) MG_SWEEP(64);
+    else if (ml <= 128) MG_SWEEP(128);
+    else if (ml <= 256) MG_SWEEP(256);
+    else if (ml <= 512) MG_SWEEP(512);
+    else if (ml <= 1024) MG_SWEEP(1024);
     else MG_SWEEP_LONG();
 #undef MG_SWEEP
 #undef MG_SWEEP_CF

@@ -401,7 +401,8 @@ __device__ __forceinline__ Ramp block_scan_excl(Ramp mine, Ramp *wtot, int parit
 
 // Global inputs of one cell of a line (the frozen state of the sweep and the
 // old values): everything phase 1 of a line step reads from memory, so that
-// the next line's reads can be issued before the current line is computed.
+// the next line's reads can be issued before the current line is computed
+// (sweep_band) or the next round's (long_band).
 struct CellIn {
     float p0, pp, pm, p0p, p0m, ppp, ppm, pmp, pmm;   // psi at (r,q), (r+1,q), (r-1,q), (r,q+), (r,q-), (r+1,q+), (r+1,q-), (r-1,q+), (r-1,q-)
     float w00, wp, wm, w0p, w0m;                      // w at (r,q), (r+1,q), (r-1,q), (r,q+), (r,q-)
@@ -465,16 +466,6 @@ __device__ __forceinline__ void cell_load(const LineRows &R, int ml, int p, Cell
     c.lo = R.lo ? R.lo[q] : -R.M;
     c.hi = R.lo ? R.hi[q] : R.M;
     c.pold = R.old[q];
-}
-template <int NT, int K, bool REV, bool CF = false>
-__device__ __forceinline__ void line_load(const LineArgs &A, int r, bool up_fresh, bool dn_fresh, CellIn (&L)[K])
-{
-    const LineRows R = line_rows<REV>(A, r, up_fresh, dn_fresh);
-#pragma unroll
-    for (int k = 0; k < K; k++) {
-        const int p = k * NT + threadIdx.x;
-        if (p < A.ml) cell_load<REV, CF>(R, A.ml, p, L[k]);
-    }
 }
 
 // The frozen coefficients of cell (r, q) (eq. abcdrc) as the row
@@ -545,7 +536,7 @@ __device__ __forceinline__ void row_store(const Buf &B, int p, const CellRow &w)
 // p = thread; REV: q = ml-1 down to 0), lines of at most NT cells.  REV takes
 // the upstream line at r+1.  up_fresh / dn_fresh: the cross-line neighbour
 // values are the caller's registers (same thread = same cell) instead of
-// phi_old.  On return val[0] holds the thread's new value.
+// phi_old.  Returns the thread's new value.
 //
 // Every point and every unit is a clipped ramp of the value entering it, so
 // the line is one block scan.  A unit's chain ramp sits at its LAST cell and
@@ -557,12 +548,11 @@ __device__ __forceinline__ void row_store(const Buf &B, int p, const CellRow &w)
 // chosen by the caller's line parity, so that the next line can write the
 // other while this one's cells still read theirs after the scan; the masks
 // are read before the scan only.
-template <int NT, int K, bool REV, bool CF = false>
-__device__ __forceinline__ void sweep_line(const LineArgs &A, int r, const RunBuf &B, uint64_t *msk, bool write,
-                                           const float (&upv)[K], bool up_fresh, const float (&dnv)[K],
-                                           bool dn_fresh, float (&val)[K], Ramp *wtot, const CellIn (&L)[K])
+template <int NT, bool REV, bool CF = false>
+__device__ __forceinline__ float sweep_line(const LineArgs &A, int r, const RunBuf &B, uint64_t *msk, bool write,
+                                            float upv, bool up_fresh, float dnv, bool dn_fresh, Ramp *wtot,
+                                            const CellIn &c)
 {
-    static_assert(K == 1, "one cell per thread: longer lines run in k_sweep_long");
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int nl = A.nl, ml = A.ml, nw = (ml + 63) >> 6;
     const int ru = REV ? r + 1 : r - 1;      // upstream line
@@ -578,11 +568,10 @@ __device__ __forceinline__ void sweep_line(const LineArgs &A, int r, const RunBu
     w.ok = false; w.x = 0.0f;
     bool s0 = false;
     if (in) {
-        const CellIn &c = L[0];
         s0 = ((c.lab >> A.bit) & 1) != 0;
         float vu = 0.0f, vd = 0.0f;
-        if (has_up) vu = up_fresh ? upv[0] : c.vu;
-        if (has_dn) vd = dn_fresh ? dnv[0] : c.vd;
+        if (has_up) vu = up_fresh ? upv : c.vu;
+        if (has_dn) vd = dn_fresh ? dnv : c.vd;
         w = cell_row<REV, CF>(A, c, r, q, vu, vd, area);
         row_store(B, p, w);
     }
@@ -635,11 +624,11 @@ __device__ __forceinline__ void sweep_line(const LineArgs &A, int r, const RunBu
             v = p == ps ? y0 : (p == ps + 1 ? y1 : y2);
         }
     }
-    val[0] = v;
     if (write && in) {
         if (A.tout) A.tout[(long long)q * A.tpitch + r] = v;
         else A.phi_new[(long long)r * A.pitch + q] = v;
     }
+    return v;
 }
 
 // One band of four lines (one per class r mod 4) of a directional sweep,
@@ -680,36 +669,33 @@ __device__ __forceinline__ void band_step(int r0, int nl, int st, int &r, bool &
     }
 }
 
-// PF: read the next step's inputs (line_load) before computing the current
-// line, so that their latency overlaps the current line's phases (costs the
-// registers of one more CellIn per round).
-// B: the first of two row buffers; lpar: the caller's running line count,
-// whose parity picks the buffer of each line (it continues across bands
-// that one workgroup takes one after another).
-template <int NT, int K, bool REV, bool PF = false, bool CF = false>
+// One band of a sweep with lines of at most NT cells, one cell per thread.
+// PF: read the next step's inputs before computing the current line, so that
+// their latency overlaps the current line's phases (the registers of one more
+// CellIn).  B: the first of two row buffers; lpar: the caller's running line
+// count, whose parity picks the buffer of each line (it continues across
+// bands that one workgroup takes one after another).
+template <int NT, bool REV, bool PF = false, bool CF = false>
 __device__ __forceinline__ void sweep_band(const LineArgs &A, int b, const RunBuf &B, uint64_t *msk, Ramp *wtot,
                                            int &lpar)
 {
-    float prev[K], red[K], cur[K];
     // transposed output of a full band: the band's 4 lines are 4 consecutive
     // floats of the output layout, written as one 16-byte store per cell
-    float o0[K], o1[K], o2[K], o3[K];
-#pragma unroll
-    for (int k = 0; k < K; k++) {
-        prev[k] = 0.0f; red[k] = 0.0f; cur[k] = 0.0f;
-        o0[k] = 0.0f; o1[k] = 0.0f; o2[k] = 0.0f; o3[k] = 0.0f;
-    }
-    const int nl = A.nl, ml = A.ml;
+    float prev = 0.0f, red = 0.0f, o0 = 0.0f, o1 = 0.0f, o2 = 0.0f, o3 = 0.0f;
+    const int nl = A.nl, ml = A.ml, t = threadIdx.x;
     const int r0 = 4 * b;
     const bool pack = A.tout != nullptr && r0 + 3 < nl;
     auto valid = [&](int st) { const int r = band_line<REV>(r0, st); return r >= 0 && r < nl; };
-    CellIn la[K], lb[K];
+    auto load = [&](int r, bool uf, bool df, CellIn &c) {
+        if (t < ml) cell_load<REV, CF>(line_rows<REV>(A, r, uf, df), ml, t, c);
+    };
+    CellIn la, lb;
     int st = 0;
     while (st < 5 && !valid(st)) st++;
     if (PF && st < 5) {
         int r; bool rdd, uf, df;
         band_step<REV>(r0, nl, st, r, rdd, uf, df);
-        line_load<NT, K, REV, CF>(A, r, uf, df, la);
+        load(r, uf, df, la);
     }
 #pragma nounroll
     while (st < 5) {
@@ -721,38 +707,29 @@ __device__ __forceinline__ void sweep_band(const LineArgs &A, int b, const RunBu
             if (nx < 5) {
                 int r2; bool rd2, uf2, df2;
                 band_step<REV>(r0, nl, nx, r2, rd2, uf2, df2);
-                line_load<NT, K, REV, CF>(A, r2, uf2, df2, lb);
+                load(r2, uf2, df2, lb);
             }
         } else {
-            line_load<NT, K, REV, CF>(A, r, up_fresh, dn_fresh, la);
+            load(r, up_fresh, dn_fresh, la);
         }
-        sweep_line<NT, K, REV, CF>(A, r, B.other(lpar & 1), msk, !redundant && !pack, prev, up_fresh, red, dn_fresh,
-                                   cur, wtot, la);
+        const float cur = sweep_line<NT, REV, CF>(A, r, B.other(lpar & 1), msk, !redundant && !pack, prev, up_fresh,
+                                                  red, dn_fresh, wtot, la);
         lpar++;
         const int li = r - r0;
-#pragma unroll
-        for (int k = 0; k < K; k++) {
-            if (redundant) red[k] = cur[k];
-            else prev[k] = cur[k];
-            if (!redundant) {
-                if (li == 0) o0[k] = cur[k];
-                else if (li == 1) o1[k] = cur[k];
-                else if (li == 2) o2[k] = cur[k];
-                else o3[k] = cur[k];
-            }
-            if (PF) la[k] = lb[k];
+        if (redundant) red = cur;
+        else prev = cur;
+        if (!redundant) {
+            if (li == 0) o0 = cur;
+            else if (li == 1) o1 = cur;
+            else if (li == 2) o2 = cur;
+            else o3 = cur;
         }
+        if (PF) la = lb;
         st = nx;
     }
-    if (pack) {
-#pragma unroll
-        for (int k = 0; k < K; k++) {
-            const int p = k * NT + threadIdx.x;
-            if (p >= ml) continue;
-            const int q = REV ? ml - 1 - p : p;
-            *reinterpret_cast<float4 *>(A.tout + (long long)q * A.tpitch + r0) =
-                make_float4(o0[k], o1[k], o2[k], o3[k]);
-        }
+    if (pack && t < ml) {
+        const int q = REV ? ml - 1 - t : t;
+        *reinterpret_cast<float4 *>(A.tout + (long long)q * A.tpitch + r0) = make_float4(o0, o1, o2, o3);
     }
 }
 
@@ -925,7 +902,7 @@ __host__ __device__ inline size_t sweep_lds_bytes(int ml)
     return (size_t)sweep_mask_words(ml) * 8 + 2 * (size_t)RB_FIELDS * ml * sizeof(float);
 }
 
-template <int NT, int K, bool REV, bool CF>
+template <int NT, bool REV, bool CF>
 __global__ void __launch_bounds__(NT) k_sweep(LineArgs A)
 {
     if (A.skip && *A.skip) return;
@@ -938,5 +915,5 @@ __global__ void __launch_bounds__(NT) k_sweep(LineArgs A)
     // read-ahead of the next line where the registers allow it (at 1024 threads, 128 registers per
     // lane: only with the stored coefficients)
     int lpar = 0;
-    sweep_band<NT, K, REV, ((NT <= 512 || CF) && K == 1), CF>(A, blockIdx.x, B, msk, wtot, lpar);
+    sweep_band<NT, REV, (NT <= 512 || CF), CF>(A, blockIdx.x, B, msk, wtot, lpar);
 }
