@@ -477,7 +477,8 @@ void residual(mgseg_ctx *c, int l, float *r, double *partial)
             using BT = std::remove_const_t<std::remove_pointer_t<decltype(A.b)>>;
             A.area_u = rc ? c->dsc + DS_AREA_EVAL : nullptr;
             A.r = r;
-            hipLaunchKernelGGL(k_res_dev<BT>, grid2(L.n, L.m), dim3(256), 0, c->s, A);
+            const dim3 gt((L.m + TILE - 1) / TILE, (L.n + TILE - 1) / TILE);
+            hipLaunchKernelGGL(k_res_dev<BT>, gt, dim3(TILE, 8), 0, c->s, A);
         });
         chk(c);
         return;

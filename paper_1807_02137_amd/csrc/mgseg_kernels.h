@@ -650,16 +650,17 @@ struct DevArgs {
 // (FP64 sums of FP32 coefficients); u0 = psi_ij; lab = the cell's label at psi;
 // au = the four face coefficients at psi scaled by kap dl(psi) (to i+1, i-1,
 // j+1, j-1; 0 across the grid edge): the sweeps' frozen A, B, C, D.
-template <typename BT>
-__device__ __forceinline__ double dev_cell(const DevArgs<BT> &A, int i, int j, bool want_Le, double &Le, float &u0,
-                                           uint8_t &lab, float (&au)[4])
+// Bv, Ev, Wv: b, e, w at a cell (global memory or a staged tile).
+template <typename BT, class BV, class EV, class WV>
+__device__ __forceinline__ double dev_cell_at(const DevArgs<BT> &A, int i, int j, bool want_Le, double &Le, float &u0,
+                                              uint8_t &lab, float (&au)[4], const BV &Bv, const EV &Ev, const WV &Wv)
 {
     const int n = A.n, m = A.m;
-    auto B64 = [&](int a, int c) { return (double)A.b[(long long)a * A.pb + c]; };
-    auto E64 = [&](int a, int c) { return (double)A.e[(long long)a * A.p + c]; };
-    auto Bf = [&](int a, int c) { return (float)A.b[(long long)a * A.pb + c]; };
+    auto B64 = [&](int a, int c) { return (double)Bv(a, c); };
+    auto E64 = [&](int a, int c) { return (double)Ev(a, c); };
+    auto Bf = [&](int a, int c) { return (float)Bv(a, c); };
     auto Uf = [&](int a, int c) { return (float)(B64(a, c) + E64(a, c)); };
-    auto W = [&](int a, int c) { return A.w[(long long)a * A.p + c]; };
+    auto W = [&](int a, int c) { return Wv(a, c); };
     float gb[4], gu[4];
     faces4(Bf, W, n, m, i, j, A.e2, gb);
     faces4(Uf, W, n, m, i, j, A.e2, gu);
@@ -690,10 +691,36 @@ __device__ __forceinline__ double dev_cell(const DevArgs<BT> &A, int i, int j, b
 }
 template <typename BT>
 __device__ __forceinline__ double dev_cell(const DevArgs<BT> &A, int i, int j, bool want_Le, double &Le, float &u0,
+                                           uint8_t &lab, float (&au)[4])
+{
+    return dev_cell_at(
+        A, i, j, want_Le, Le, u0, lab, au, [&](int a, int c) { return A.b[(long long)a * A.pb + c]; },
+        [&](int a, int c) { return A.e[(long long)a * A.p + c]; },
+        [&](int a, int c) { return A.w[(long long)a * A.p + c]; });
+}
+template <typename BT>
+__device__ __forceinline__ double dev_cell(const DevArgs<BT> &A, int i, int j, bool want_Le, double &Le, float &u0,
                                            uint8_t &lab)
 {
     float au[4];
     return dev_cell(A, i, j, want_Le, Le, u0, lab, au);
+}
+
+// b, e and w of the 32 x 32 tile at (by, bx) and a one-cell halo, mirrored
+// at the grid edge as the face stencil mirrors, staged in LDS by the block:
+// every value of the tile's stencils is then read from memory once.
+template <typename BT>
+__device__ __forceinline__ void stage_halo(const DevArgs<BT> &A, int by, int bx, BT (&hb)[TILE + 2][TILE + 2],
+                                           float (&he)[TILE + 2][TILE + 2], float (&hw)[TILE + 2][TILE + 2])
+{
+    const int nt = blockDim.x * blockDim.y, tid = threadIdx.y * blockDim.x + threadIdx.x;
+    for (int t = tid; t < (TILE + 2) * (TILE + 2); t += nt) {
+        const int yy = t / (TILE + 2), xx = t % (TILE + 2);
+        const int gi = mg_mirror(by - 1 + yy, A.n), gj = mg_mirror(bx - 1 + xx, A.m);
+        hb[yy][xx] = A.b[(long long)gi * A.pb + gj];
+        he[yy][xx] = A.e[(long long)gi * A.p + gj];
+        hw[yy][xx] = A.w[(long long)gi * A.p + gj];
+    }
 }
 
 // freeze in deviation form: psi = fl32(b + e), T, labels and (cf non-null)
@@ -702,14 +729,22 @@ __device__ __forceinline__ double dev_cell(const DevArgs<BT> &A, int i, int j, b
 // (i+1, i-1, j+1, j-1), column-major (j+1, j-1, i+1, i-1).  32 x 32 tiles:
 // row-major outputs written directly, column-major copies through LDS so that
 // both layouts are written coalesced.  Block (32, 32) or (32, 8): one or four
-// rows per thread.
+// rows per thread; the stencil inputs are staged in LDS (stage_halo).
 template <typename BT>
 __global__ void __launch_bounds__(1024) k_freeze_dev(DevArgs<BT> A)
 {
     __shared__ float tp[TILE][TILE + 1], tt[TILE][TILE + 1];
     __shared__ uint8_t tl[TILE][TILE + 1];
     __shared__ float4 tc[TILE][TILE + 1];
+    __shared__ BT hb[TILE + 2][TILE + 2];
+    __shared__ float he[TILE + 2][TILE + 2], hw[TILE + 2][TILE + 2];
     const int bx = blockIdx.x * TILE, by = blockIdx.y * TILE;
+    stage_halo(A, by, bx, hb, he, hw);
+    __syncthreads();
+    // grid cell (a, c) of the stencil of a tile cell lies in the staged halo
+    auto Bv = [&](int a, int c) { return hb[a - by + 1][c - bx + 1]; };
+    auto Ev = [&](int a, int c) { return he[a - by + 1][c - bx + 1]; };
+    auto Wv = [&](int a, int c) { return hw[a - by + 1][c - bx + 1]; };
     for (int y = threadIdx.y; y < TILE; y += blockDim.y) {
         const int i = by + y, j = bx + threadIdx.x;
         if (i < A.n && j < A.m) {
@@ -717,7 +752,7 @@ __global__ void __launch_bounds__(1024) k_freeze_dev(DevArgs<BT> A)
             float u0;
             uint8_t lab;
             float au[4];
-            const double t = dev_cell(A, i, j, false, Le, u0, lab, au);
+            const double t = dev_cell_at(A, i, j, false, Le, u0, lab, au, Bv, Ev, Wv);
             const long long q = (long long)i * A.p + j;
             if (A.psi) A.psi[q] = u0;
             A.T[q] = (float)t;
@@ -742,21 +777,33 @@ __global__ void __launch_bounds__(1024) k_freeze_dev(DevArgs<BT> A)
 }
 
 // residual in deviation form: r = F - N(b + e) = T(b + e) - L_{b+e} e, projected
-// on the bounds of e (zero where the correction would leave them)
+// on the bounds of e (zero where the correction would leave them).  32 x 32
+// tiles, block (32, 8), the stencil inputs staged in LDS (stage_halo).
 template <typename BT>
-__global__ void k_res_dev(DevArgs<BT> A)
+__global__ void __launch_bounds__(256) k_res_dev(DevArgs<BT> A)
 {
-    int j = blockIdx.x * blockDim.x + threadIdx.x, i = blockIdx.y;
-    if (j >= A.m || i >= A.n) return;
-    double Le;
-    float u0;
-    uint8_t lab;
-    const double t = dev_cell(A, i, j, true, Le, u0, lab);
-    const long long q = (long long)i * A.p + j;
-    double v = t - Le;
-    const float e = A.e[q];
-    if ((e >= A.hi[q] && v < 0.0) || (e <= A.lo[q] && v > 0.0)) v = 0.0;
-    A.r[q] = (float)v;
+    __shared__ BT hb[TILE + 2][TILE + 2];
+    __shared__ float he[TILE + 2][TILE + 2], hw[TILE + 2][TILE + 2];
+    const int bx = blockIdx.x * TILE, by = blockIdx.y * TILE;
+    stage_halo(A, by, bx, hb, he, hw);
+    __syncthreads();
+    auto Bv = [&](int a, int c) { return hb[a - by + 1][c - bx + 1]; };
+    auto Ev = [&](int a, int c) { return he[a - by + 1][c - bx + 1]; };
+    auto Wv = [&](int a, int c) { return hw[a - by + 1][c - bx + 1]; };
+    for (int y = threadIdx.y; y < TILE; y += blockDim.y) {
+        const int i = by + y, j = bx + threadIdx.x;
+        if (i >= A.n || j >= A.m) continue;
+        double Le;
+        float u0;
+        uint8_t lab;
+        float au[4];
+        const double t = dev_cell_at(A, i, j, true, Le, u0, lab, au, Bv, Ev, Wv);
+        const long long q = (long long)i * A.p + j;
+        double v = t - Le;
+        const float e = A.e[q];
+        if ((e >= A.hi[q] && v < 0.0) || (e <= A.lo[q] && v > 0.0)) v = 0.0;
+        A.r[q] = (float)v;
+    }
 }
 
 // restriction in deviation form: coarse base fl32(FW(b + e)) (FP64 sums),
