@@ -190,15 +190,16 @@ void update_fit(mgseg_ctx *c)
 {
     FitLevels F;
     F.L = c->L;
-    F.row0[0] = 0;
+    F.trow0[0] = 0;
     for (int l = 0; l < c->L; l++) {
         const Level &L = c->lev[l];
         F.z[l] = L.z; F.d[l] = L.d; F.fit[l] = L.fit; F.fit_cm[l] = L.fit_cm;
         F.p[l] = L.prm; F.pc[l] = L.pcm; F.n[l] = L.n; F.m[l] = L.m;
-        F.row0[l + 1] = F.row0[l] + L.n;
+        F.trow0[l + 1] = F.trow0[l] + (L.n + TILE - 1) / TILE;
     }
-    const dim3 g((c->m + 255) / 256, F.row0[c->L]);
-    hipLaunchKernelGGL(k_fit, g, dim3(256), 0, c->s, F, c->dsc + DS_C1, (float)c->p.lambda1, (float)c->p.lambda2,
+    const dim3 g((c->m + TILE - 1) / TILE, F.trow0[c->L]);
+    const dim3 tb(TILE, tile_rows((long long)g.x * g.y));
+    hipLaunchKernelGGL(k_fit, g, tb, 0, c->s, F, c->dsc + DS_C1, (float)c->p.lambda1, (float)c->p.lambda2,
                        (float)c->p.theta, c->p.model);
 }
 
@@ -388,10 +389,7 @@ void freeze(mgseg_ctx *c, int l)
             A.psi_cm = L.cf ? nullptr : L.psi_cm; A.T_cm = L.F_cm; A.lab_cm = L.lab_cm;
             A.cf = L.cf; A.cf_cm = L.cf_cm;
             dim3 gt((L.m + TILE - 1) / TILE, (L.n + TILE - 1) / TILE);
-            // large grids: 32 x 8 blocks (four rows per thread) so that several blocks
-            // share a CU across the tile's barrier; small grids: one row per thread
-            const int ty = (long long)gt.x * gt.y >= 4096 ? 8 : TILE;
-            hipLaunchKernelGGL(k_freeze_dev<BT>, gt, dim3(TILE, ty), 0, c->s, A);
+            hipLaunchKernelGGL(k_freeze_dev<BT>, gt, dim3(TILE, tile_rows((long long)gt.x * gt.y)), 0, c->s, A);
         });
         L.has_F = true;
         chk(c);
@@ -478,7 +476,7 @@ void residual(mgseg_ctx *c, int l, float *r, double *partial)
             A.area_u = rc ? c->dsc + DS_AREA_EVAL : nullptr;
             A.r = r;
             const dim3 gt((L.m + TILE - 1) / TILE, (L.n + TILE - 1) / TILE);
-            hipLaunchKernelGGL(k_res_dev<BT>, gt, dim3(TILE, 8), 0, c->s, A);
+            hipLaunchKernelGGL(k_res_dev<BT>, gt, dim3(TILE, tile_rows((long long)gt.x * gt.y)), 0, c->s, A);
         });
         chk(c);
         return;
@@ -507,9 +505,11 @@ void vcycle_from(mgseg_ctx *c, int l0)
             // the residual (to G) and the state (base, deviation, bounds) in one launch
             with_dev(c, l, [&](auto A) {
                 using BT = std::remove_const_t<std::remove_pointer_t<decltype(A.b)>>;
-                hipLaunchKernelGGL(k_restrict_dev<BT>, gc, dim3(256), 0, c->s, A.b, A.pb, L.P[0], L.lo, L.hi, L.prm,
-                                   L.n, L.m, Lc.phic, Lc.P[0], Lc.lo, Lc.hi, Lc.prm, Lc.n, Lc.m, Lc.lo_cm, Lc.hi_cm,
-                                   Lc.pcm, L.r, Lc.G);
+                const dim3 gct((Lc.m + TILE - 1) / TILE, (Lc.n + TILE - 1) / TILE);
+                const dim3 tb(TILE, tile_rows((long long)gct.x * gct.y));
+                hipLaunchKernelGGL(k_restrict_dev<BT>, gct, tb, 0, c->s, A.b, A.pb, L.P[0], L.lo, L.hi,
+                                   L.prm, L.n, L.m, Lc.phic, Lc.P[0], Lc.lo, Lc.hi, Lc.prm, Lc.n, Lc.m, Lc.lo_cm,
+                                   Lc.hi_cm, Lc.pcm, L.r, Lc.G);
             });
             if (c->p.model == 1) area_term(c, l + 1, Lc.phic, Lc.prm, DS_AREAB0 + l + 1);
         } else {
@@ -576,8 +576,10 @@ void enqueue_cycle(mgseg_ctx *c)
     (void)hipMemcpyAsync(c->prev64, c->phi64, sizeof(double) * N, hipMemcpyDeviceToDevice, c->s);
     dim3 g = grid2(c->n, c->m);
     if (c->p.mixed_precision) {
-        hipLaunchKernelGGL(k_start0, g, dim3(256), 0, c->s, c->phi64, c->n, c->m, c->p.M, L0.P[0], L0.lo, L0.hi,
-                           L0.prm, L0.lo_cm, L0.hi_cm, L0.pcm);
+        const dim3 gt((c->m + TILE - 1) / TILE, (c->n + TILE - 1) / TILE);
+        const dim3 tb(TILE, tile_rows((long long)gt.x * gt.y));
+        hipLaunchKernelGGL(k_start0, gt, tb, 0, c->s, c->phi64, c->n, c->m, c->p.M, L0.P[0], L0.lo, L0.hi, L0.prm,
+                           L0.lo_cm, L0.hi_cm, L0.pcm);
     }
     vcycle_from(c, 0);
     if (c->p.mixed_precision)

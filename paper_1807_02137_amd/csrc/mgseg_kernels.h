@@ -3,6 +3,10 @@
 #include "mgseg_device.h"
 
 #define TILE 32
+// rows of a 32 x 32-tile block: 8 (four rows per thread) on grids of many
+// tiles, where several blocks per CU overlap each other's barriers; 32 (one
+// row per thread, the shortest chain) on small grids
+__host__ __device__ inline int tile_rows(long long tiles) { return tiles >= 4096 ? 8 : TILE; }
 
 // ==========================================================================
 // Setup maps (Sec. 2.2).  Level-0 maps are computed in FP64.
@@ -315,29 +319,42 @@ __global__ void k_coarse_rhs(const float *phic, const float *w, const float *fit
 }
 
 // fit maps of every level with the current c1, c2 (Spencer-Chen adds theta d),
-// one launch: block row y covers row y - row0[l] of the level l whose rows
-// [row0[l], row0[l+1]) contain y
+// one launch of 32 x 32 tiles, block (32, tile_rows): block row y covers tile row
+// y - trow0[l] of the level l whose tile rows [trow0[l], trow0[l+1]) contain
+// y; the column-major copy goes through LDS
 #define FIT_MAXLEV 16
 struct FitLevels {
     const float *z[FIT_MAXLEV], *d[FIT_MAXLEV];
     float *fit[FIT_MAXLEV], *fit_cm[FIT_MAXLEV];
-    int p[FIT_MAXLEV], pc[FIT_MAXLEV], n[FIT_MAXLEV], m[FIT_MAXLEV], row0[FIT_MAXLEV + 1];
+    int p[FIT_MAXLEV], pc[FIT_MAXLEV], n[FIT_MAXLEV], m[FIT_MAXLEV], trow0[FIT_MAXLEV + 1];
     int L;
 };
-__global__ void k_fit(FitLevels F, const double *c12, float l1, float l2, float theta, int model)
+__global__ void __launch_bounds__(1024) k_fit(FitLevels F, const double *c12, float l1, float l2, float theta,
+                                             int model)
 {
-    const int y = blockIdx.y;
+    __shared__ float tf[TILE][TILE + 1];
     int l = 0;
-    while (l + 1 < F.L && y >= F.row0[l + 1]) l++;
-    const int i = y - F.row0[l], j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= F.m[l] || i >= F.n[l]) return;
-    const long long q = (long long)i * F.p[l] + j;
+    while (l + 1 < F.L && (int)blockIdx.y >= F.trow0[l + 1]) l++;
+    const int n = F.n[l], m = F.m[l];
+    const int by = ((int)blockIdx.y - F.trow0[l]) * TILE, bx = blockIdx.x * TILE;
+    if (bx >= m) return;                   // the whole block: narrower level
     const float c1 = (float)c12[0], c2 = (float)c12[1];
-    const float a = F.z[l][q] - c1, b = F.z[l][q] - c2;
-    float v = l1 * a * a - l2 * b * b;
-    if (model == 0) v += theta * F.d[l][q];
-    F.fit[l][q] = v;
-    F.fit_cm[l][(long long)j * F.pc[l] + i] = v;
+    for (int y = threadIdx.y; y < TILE; y += blockDim.y) {
+        const int i = by + y, j = bx + threadIdx.x;
+        if (i >= n || j >= m) continue;
+        const long long q = (long long)i * F.p[l] + j;
+        const float a = F.z[l][q] - c1, b = F.z[l][q] - c2;
+        float v = l1 * a * a - l2 * b * b;
+        if (model == 0) v += theta * F.d[l][q];
+        F.fit[l][q] = v;
+        tf[y][threadIdx.x] = v;
+    }
+    __syncthreads();
+    for (int y = threadIdx.y; y < TILE; y += blockDim.y) {
+        const int j = bx + y, i = by + threadIdx.x;
+        if (i >= n || j >= m) continue;
+        F.fit_cm[l][(long long)j * F.pc[l] + i] = tf[threadIdx.x][y];
+    }
 }
 
 // ==========================================================================
@@ -605,16 +622,33 @@ __global__ void k_scalar_solve(ScalarArgs S)
 // grids: e = 0 with bounds from the finer grid's slack.
 
 // finest-grid cycle start: e = 0, bounds of e = [-M - b, M - b]
-__global__ void k_start0(const double *b, int n, int m, double M, float *e, float *lo, float *hi, int p,
-                         float *lo_cm, float *hi_cm, int pc)
+// (32 x 32 tiles, block (32, 8) or (32, 32) as tile_rows picks; the
+// column-major bounds through LDS so that both layouts are written coalesced)
+__global__ void __launch_bounds__(1024) k_start0(const double *b, int n, int m, double M, float *e, float *lo,
+                                                float *hi, int p, float *lo_cm, float *hi_cm, int pc)
 {
-    int j = blockIdx.x * blockDim.x + threadIdx.x, i = blockIdx.y;
-    if (j >= m || i >= n) return;
-    double v = b[(long long)i * m + j];
-    long long q = (long long)i * p + j;
-    e[q] = 0.0f;
-    lo[q] = lo_cm[(long long)j * pc + i] = (float)(-M - v);
-    hi[q] = hi_cm[(long long)j * pc + i] = (float)(M - v);
+    __shared__ float tlo[TILE][TILE + 1], thi[TILE][TILE + 1];
+    const int bx = blockIdx.x * TILE, by = blockIdx.y * TILE;
+    for (int y = threadIdx.y; y < TILE; y += blockDim.y) {
+        const int i = by + y, j = bx + threadIdx.x;
+        if (i >= n || j >= m) continue;
+        const double v = b[(long long)i * m + j];
+        const long long q = (long long)i * p + j;
+        const float l = (float)(-M - v), h = (float)(M - v);
+        e[q] = 0.0f;
+        lo[q] = l;
+        hi[q] = h;
+        tlo[y][threadIdx.x] = l;
+        thi[y][threadIdx.x] = h;
+    }
+    __syncthreads();
+    for (int y = threadIdx.y; y < TILE; y += blockDim.y) {
+        const int j = bx + y, i = by + threadIdx.x;
+        if (i >= n || j >= m) continue;
+        const long long qc = (long long)j * pc + i;
+        lo_cm[qc] = tlo[threadIdx.x][y];
+        hi_cm[qc] = thi[threadIdx.x][y];
+    }
 }
 
 // finest-grid cycle end: phi64 = clip(b + e); a deviation at its bound lands
@@ -778,9 +812,9 @@ __global__ void __launch_bounds__(1024) k_freeze_dev(DevArgs<BT> A)
 
 // residual in deviation form: r = F - N(b + e) = T(b + e) - L_{b+e} e, projected
 // on the bounds of e (zero where the correction would leave them).  32 x 32
-// tiles, block (32, 8), the stencil inputs staged in LDS (stage_halo).
+// tiles, block (32, tile_rows), the stencil inputs staged in LDS (stage_halo).
 template <typename BT>
-__global__ void __launch_bounds__(256) k_res_dev(DevArgs<BT> A)
+__global__ void __launch_bounds__(1024) k_res_dev(DevArgs<BT> A)
 {
     __shared__ BT hb[TILE + 2][TILE + 2];
     __shared__ float he[TILE + 2][TILE + 2], hw[TILE + 2][TILE + 2];
@@ -817,14 +851,14 @@ __device__ __forceinline__ double fw_row_dev(const BT *b, int pb, const float *e
     return 0.5 * V(2 * J) + 0.5 * V(2 * J + 1);
 }
 // (also the restricted residual rc = FW r of the fine residual r, pitch p,
-// into Gc, pitch pc: both transfers of a level in one launch)
+// into Gc, pitch pc: both transfers of a level in one launch).  32 x 32
+// coarse tiles, block (32, tile_rows); the column-major bounds through LDS.
 template <typename BT>
-__global__ void k_restrict_dev(const BT *b, int pb, const float *e, const float *lo, const float *hi, int p, int n,
-                               int m, float *bc, float *ec, float *clo, float *chi, int pc, int nc, int mc,
-                               float *clo_cm, float *chi_cm, int pcc, const float *r, float *Gc)
+__device__ __forceinline__ void restrict_dev_cell(const BT *b, int pb, const float *e, const float *lo,
+                                                  const float *hi, int p, int n, int m, float *bc, float *ec,
+                                                  float *clo, float *chi, int pc, int nc, int mc, const float *r,
+                                                  float *Gc, int I, int J, float &dl, float &dh)
 {
-    int J = blockIdx.x * blockDim.x + threadIdx.x, I = blockIdx.y;
-    if (J >= mc || I >= nc) return;
     Gc[(long long)I * pc + J] = fw2(r, p, I, J, nc, mc);
     double v;
     if (I < nc - 1)
@@ -832,7 +866,8 @@ __global__ void k_restrict_dev(const BT *b, int pb, const float *e, const float 
             0.25 * fw_row_dev(b, pb, e, p, 2 * I + 2, J, mc);
     else
         v = 0.5 * fw_row_dev(b, pb, e, p, 2 * I, J, mc) + 0.5 * fw_row_dev(b, pb, e, p, 2 * I + 1, J, mc);
-    float dl = -MG_BIG, dh = MG_BIG;
+    dl = -MG_BIG;
+    dh = MG_BIG;
     for (int i = 2 * I; i <= 2 * I + 2 && i < n; i++)
         for (int j = 2 * J; j <= 2 * J + 2 && j < m; j++) {
             long long q = (long long)i * p + j;
@@ -844,8 +879,30 @@ __global__ void k_restrict_dev(const BT *b, int pb, const float *e, const float 
     ec[q] = 0.0f;
     clo[q] = dl;
     chi[q] = dh;
-    clo_cm[(long long)J * pcc + I] = dl;
-    chi_cm[(long long)J * pcc + I] = dh;
+}
+template <typename BT>
+__global__ void __launch_bounds__(1024) k_restrict_dev(const BT *b, int pb, const float *e, const float *lo,
+                                                      const float *hi, int p, int n, int m, float *bc, float *ec,
+                                                      float *clo, float *chi, int pc, int nc, int mc, float *clo_cm,
+                                                      float *chi_cm, int pcc, const float *r, float *Gc)
+{
+    __shared__ float tlo[TILE][TILE + 1], thi[TILE][TILE + 1];
+    const int bx = blockIdx.x * TILE, by = blockIdx.y * TILE;
+    for (int y = threadIdx.y; y < TILE; y += blockDim.y) {
+        const int I = by + y, J = bx + threadIdx.x;
+        if (I >= nc || J >= mc) continue;
+        float dl, dh;
+        restrict_dev_cell(b, pb, e, lo, hi, p, n, m, bc, ec, clo, chi, pc, nc, mc, r, Gc, I, J, dl, dh);
+        tlo[y][threadIdx.x] = dl;
+        thi[y][threadIdx.x] = dh;
+    }
+    __syncthreads();
+    for (int y = threadIdx.y; y < TILE; y += blockDim.y) {
+        const int J = bx + y, I = by + threadIdx.x;
+        if (I >= nc || J >= mc) continue;
+        clo_cm[(long long)J * pcc + I] = tlo[threadIdx.x][y];
+        chi_cm[(long long)J * pcc + I] = thi[threadIdx.x][y];
+    }
 }
 
 // sum of H(b + e) over a level (area term of the Rada-Chen model)
