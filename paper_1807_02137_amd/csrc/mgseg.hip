@@ -278,7 +278,7 @@ void launch_sweep(mgseg_ctx *c, int l, int s, const float *phi_old, float *phi_n
         if (c->err == hipSuccess) c->err = hipErrorInvalidValue;
         return;
     }
-    const size_t lds = sweep_lds_bytes(ml), llds = long_lds_bytes<1024>(ml);
+    const size_t lds = sweep_lds_bytes(ml), llds = long_lds_bytes<1024>(ml), lds2 = sweep2_lds_bytes(ml);
 #define MG_SWEEP_CF(NT, CF)                                                                       \
     do {                                                                                              \
         if (rev) hipLaunchKernelGGL((k_sweep<NT, true, CF>), dim3(bands), dim3(NT), lds, c->s, A); \
@@ -288,6 +288,16 @@ void launch_sweep(mgseg_ctx *c, int l, int s, const float *phi_old, float *phi_n
     do {                               \
         if (cfm) MG_SWEEP_CF(NT, true);    \
         else MG_SWEEP_CF(NT, false);   \
+    } while (0)
+#define MG_SWEEP2_CF(NT, CF)                                                                              \
+    do {                                                                                                  \
+        if (rev) hipLaunchKernelGGL((k_sweep2<NT, true, CF>), dim3(bands), dim3(2 * NT), lds2, c->s, A); \
+        else hipLaunchKernelGGL((k_sweep2<NT, false, CF>), dim3(bands), dim3(2 * NT), lds2, c->s, A);    \
+    } while (0)
+#define MG_SWEEP2(NT)                  \
+    do {                               \
+        if (cfm) MG_SWEEP2_CF(NT, true);   \
+        else MG_SWEEP2_CF(NT, false);  \
     } while (0)
 #define MG_SWEEP_LONG_CF(CF)                                                                                    \
     do {                                                                                                        \
@@ -313,15 +323,19 @@ void launch_sweep(mgseg_ctx *c, int l, int s, const float *phi_old, float *phi_n
         c->ev_next += 2;
         (void)hipEventRecord(e0, c->s);
     }
-    // one thread per cell up to 1024-cell lines; longer lines take rounds
-    if (ml <= 64) MG_SWEEP(64);
-    else if (ml <= 128) MG_SWEEP(128);
-    else if (ml <= 256) MG_SWEEP(256);
-    else if (ml <= 512) MG_SWEEP(512);
+    // one thread per cell up to 1024-cell lines; longer lines take rounds.  Up
+    // to 512 cells the workgroup has a second half that computes the
+    // recomputed neighbour line beside the band's first line.
+    if (ml <= 64) MG_SWEEP2(64);
+    else if (ml <= 128) MG_SWEEP2(128);
+    else if (ml <= 256) MG_SWEEP2(256);
+    else if (ml <= 512) MG_SWEEP2(512);
     else if (ml <= 1024) MG_SWEEP(1024);
     else MG_SWEEP_LONG();
 #undef MG_SWEEP
 #undef MG_SWEEP_CF
+#undef MG_SWEEP2
+#undef MG_SWEEP2_CF
 #undef MG_SWEEP_LONG
 #undef MG_SWEEP_LONG_CF
     if (timed) {

@@ -378,10 +378,11 @@ __device__ __forceinline__ Ramp readlane_ramp(const Ramp &r, int lane)
                 __int_as_float(__builtin_amdgcn_readlane(__float_as_int(r.hi), lane))};
 }
 
+// t: the thread's index in the group of NT threads that takes the scan.
 template <int NT>
-__device__ __forceinline__ Ramp block_scan_excl(Ramp mine, Ramp *wtot, int parity, Ramp &total)
+__device__ __forceinline__ Ramp block_scan_excl(Ramp mine, Ramp *wtot, int parity, Ramp &total, int t)
 {
-    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int lane = t & 63, wave = t >> 6;
     constexpr int NW = NT / 64;
     const Ramp inc = wave_scan_incl(mine);
     Ramp ex = dpp_ramp<0x138>(inc);                 // wave_shr:1 (lane 0: identity)
@@ -533,10 +534,12 @@ __device__ __forceinline__ void row_store(const Buf &B, int p, const CellRow &w)
 
 // --------------------------------------------------------------------------
 // One line of one directional sweep, one thread per cell (visit position
-// p = thread; REV: q = ml-1 down to 0), lines of at most NT cells.  REV takes
-// the upstream line at r+1.  up_fresh / dn_fresh: the cross-line neighbour
-// values are the caller's registers (same thread = same cell) instead of
-// phi_old.  Returns the thread's new value.
+// p = t, the thread's index in the group of NT threads that takes the line;
+// REV: q = ml-1 down to 0), lines of at most NT cells.  REV takes the upstream
+// line at r+1.  up_fresh / dn_fresh: the cross-line neighbour values are the
+// caller's registers (same thread = same cell) instead of phi_old.  act =
+// false: the group takes the step's barriers on no cells.  Returns the
+// thread's new value.
 //
 // Every point and every unit is a clipped ramp of the value entering it, so
 // the line is one block scan.  A unit's chain ramp sits at its LAST cell and
@@ -551,16 +554,16 @@ __device__ __forceinline__ void row_store(const Buf &B, int p, const CellRow &w)
 template <int NT, bool REV, bool CF = false>
 __device__ __forceinline__ float sweep_line(const LineArgs &A, int r, const RunBuf &B, uint64_t *msk, bool write,
                                             float upv, bool up_fresh, float dnv, bool dn_fresh, Ramp *wtot,
-                                            const CellIn &c)
+                                            const CellIn &c, int t, bool act)
 {
-    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int lane = t & 63, wave = t >> 6;
     const int nl = A.nl, ml = A.ml, nw = (ml + 63) >> 6;
     const int ru = REV ? r + 1 : r - 1;      // upstream line
     const int rd = REV ? r - 1 : r + 1;      // downstream line
     const float area = A.area ? (float)(*A.area) : 0.0f;
     const bool has_up = ru >= 0 && ru < nl, has_dn = rd >= 0 && rd < nl;
     const int p = t;
-    const bool in = p < ml;
+    const bool in = act && p < ml;
     const int q = REV ? ml - 1 - p : p;
 
     // phase 1: frozen coefficients (eq. abcdrc), the row of the cell, starred masks
@@ -604,7 +607,7 @@ __device__ __forceinline__ float sweep_line(const LineArgs &A, int r, const RunB
 
     // phase 3: the scan gives every cell the value entering it (a unit cell: entering its unit)
     Ramp tot;
-    const Ramp ex = block_scan_excl<NT>(u, wtot, 0, tot);
+    const Ramp ex = block_scan_excl<NT>(u, wtot, 0, tot, t);
     const float x = ramp_eval(ex, 0.0f);
     float v = 0.0f;
     if (in) {
@@ -713,7 +716,7 @@ __device__ __forceinline__ void sweep_band(const LineArgs &A, int b, const RunBu
             load(r, up_fresh, dn_fresh, la);
         }
         const float cur = sweep_line<NT, REV, CF>(A, r, B.other(lpar & 1), msk, !redundant && !pack, prev, up_fresh,
-                                                  red, dn_fresh, wtot, la);
+                                                  red, dn_fresh, wtot, la, t, true);
         lpar++;
         const int li = r - r0;
         if (redundant) red = cur;
@@ -728,6 +731,75 @@ __device__ __forceinline__ void sweep_band(const LineArgs &A, int b, const RunBu
         st = nx;
     }
     if (pack && t < ml) {
+        const int q = REV ? ml - 1 - t : t;
+        *reinterpret_cast<float4 *>(A.tout + (long long)q * A.tpitch + r0) = make_float4(o0, o1, o2, o3);
+    }
+}
+
+// One band of a sweep with lines of at most NT cells in a workgroup of 2 NT
+// threads.  The neighbouring band's line that the band recomputes reads old
+// values only (both of its cross-line neighbours are processed after it), so
+// the upper half computes it beside the band's first line and leaves it in
+// LDS (redl, by visit position), while the lower half takes the band's own
+// lines: four line steps instead of five.  Both halves make the same four
+// sweep_line calls (a half with no line takes them on no cells), so every
+// block barrier is reached by all waves.  Each half has its own masks, row
+// buffers and scan totals.
+template <int NT, bool REV, bool PF, bool CF>
+__device__ __forceinline__ void sweep_band2(const LineArgs &A, int b, const RunBuf &B0, const RunBuf &B1,
+                                            uint64_t *msk0, uint64_t *msk1, Ramp *wtot0, Ramp *wtot1, float *redl)
+{
+    const int nl = A.nl, ml = A.ml;
+    const int half = __builtin_amdgcn_readfirstlane((int)threadIdx.x / NT);
+    const int t = threadIdx.x - half * NT;
+    const int r0 = 4 * b;
+    const bool pack = A.tout != nullptr && r0 + 3 < nl;
+    const RunBuf B = half ? B1 : B0;
+    uint64_t *msk = half ? msk1 : msk0;
+    Ramp *wtot = half ? wtot1 : wtot0;
+    auto valid = [&](int st) { const int r = band_line<REV>(r0, st); return r >= 0 && r < nl; };
+    // the band step of this half's k-th call (-1: none): lower 0, 1, 2, 4; upper 3
+    auto step_of = [&](int k) { return half == 0 ? (k < 3 ? k : 4) : (k == 0 ? 3 : -1); };
+    auto load = [&](int k, CellIn &c) {
+        const int st = step_of(k);
+        if (st < 0 || !valid(st) || t >= ml) return;
+        int r; bool rdd, uf, df;
+        band_step<REV>(r0, nl, st, r, rdd, uf, df);
+        cell_load<REV, CF>(line_rows<REV>(A, r, uf, df), ml, t, c);
+    };
+    float prev = 0.0f, o0 = 0.0f, o1 = 0.0f, o2 = 0.0f, o3 = 0.0f;
+    CellIn la{}, lb{};
+    if (PF) load(0, la);
+#pragma nounroll
+    for (int k = 0; k < 4; k++) {
+        const int st = step_of(k);
+        const bool act = st >= 0 && valid(st);
+        int r = r0; bool redundant = false, up_fresh = false, dn_fresh = false;
+        if (act) band_step<REV>(r0, nl, st, r, redundant, up_fresh, dn_fresh);
+        if (PF) {
+            if (k + 1 < 4) load(k + 1, lb);
+        } else {
+            load(k, la);
+        }
+        // the recomputed line was left in LDS by the upper half at k = 0 (barriers of the calls between)
+        const float dnv = act && dn_fresh && t < ml ? redl[t] : 0.0f;
+        const float cur = sweep_line<NT, REV, CF>(A, r, B.other(k & 1), msk, act && !redundant && !pack, prev,
+                                                  up_fresh, dnv, dn_fresh, wtot, la, t, act);
+        if (act) {
+            if (redundant) {
+                if (t < ml) redl[t] = cur;
+            } else {
+                prev = cur;
+                const int li = r - r0;
+                if (li == 0) o0 = cur;
+                else if (li == 1) o1 = cur;
+                else if (li == 2) o2 = cur;
+                else o3 = cur;
+            }
+        }
+        if (PF) la = lb;
+    }
+    if (half == 0 && pack && t < ml) {
         const int q = REV ? ml - 1 - t : t;
         *reinterpret_cast<float4 *>(A.tout + (long long)q * A.tpitch + r0) = make_float4(o0, o1, o2, o3);
     }
@@ -842,7 +914,7 @@ __device__ __forceinline__ void long_band(const LineArgs &A, int b, float *ring,
                 }
             }
             Ramp tot;
-            const Ramp ex = block_scan_excl<NT>(u, wtot, k & 1, tot);
+            const Ramp ex = block_scan_excl<NT>(u, wtot, k & 1, tot, t);
             const float x = ramp_eval(ex, carry);
             float v = 0.0f;
             if (in && !inu) v = ramp_eval(u, x);
@@ -900,6 +972,30 @@ __global__ void __launch_bounds__(NT) k_sweep_long(LineArgs A)
 __host__ __device__ inline size_t sweep_lds_bytes(int ml)
 {
     return (size_t)sweep_mask_words(ml) * 8 + 2 * (size_t)RB_FIELDS * ml * sizeof(float);
+}
+
+// dynamic LDS of the two-half sweep: [masks of each half][2 x RB_FIELDS * ml
+// floats of rows of each half][ml floats of the recomputed line]
+__host__ __device__ inline size_t sweep2_lds_bytes(int ml)
+{
+    return 2 * sweep_lds_bytes(ml) + (size_t)ml * sizeof(float);
+}
+
+template <int NT, bool REV, bool CF>
+__global__ void __launch_bounds__(2 * NT) k_sweep2(LineArgs A)
+{
+    if (A.skip && *A.skip) return;
+    extern __shared__ uint64_t smem64[];
+    __shared__ Ramp wtot[2][2 * (NT / 64)];
+    const int nw = sweep_mask_words(A.ml);
+    RunBuf B0, B1;
+    B0.fs = A.ml;
+    B0.p = reinterpret_cast<float *>(smem64 + 2 * nw);
+    B1.fs = A.ml;
+    B1.p = B0.p + 2 * RB_FIELDS * A.ml;
+    float *redl = B1.p + 2 * RB_FIELDS * A.ml;
+    // read-ahead of the next line where the registers allow it (1024 threads: only with the stored coefficients)
+    sweep_band2<NT, REV, (NT <= 256 || CF), CF>(A, blockIdx.x, B0, B1, smem64, smem64 + nw, wtot[0], wtot[1], redl);
 }
 
 template <int NT, bool REV, bool CF>
