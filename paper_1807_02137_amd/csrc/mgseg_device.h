@@ -539,7 +539,8 @@ __device__ __forceinline__ void row_store(const Buf &B, int p, const CellRow &w)
 // line at r+1.  up_fresh / dn_fresh: the cross-line neighbour values are the
 // caller's registers (same thread = same cell) instead of phi_old.  act =
 // false: the group takes the step's barriers on no cells.  Returns the
-// thread's new value.
+// thread's new value.  WS: the group is one wave that needs no block barrier
+// (a wave-level fence makes the rows and masks visible to its lanes).
 //
 // Every point and every unit is a clipped ramp of the value entering it, so
 // the line is one block scan.  A unit's chain ramp sits at its LAST cell and
@@ -551,11 +552,19 @@ __device__ __forceinline__ void row_store(const Buf &B, int p, const CellRow &w)
 // chosen by the caller's line parity, so that the next line can write the
 // other while this one's cells still read theirs after the scan; the masks
 // are read before the scan only.
-template <int NT, bool REV, bool CF = false>
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+template <int NT, bool REV, bool CF = false, bool WS = false>
 __device__ __forceinline__ float sweep_line(const LineArgs &A, int r, const RunBuf &B, uint64_t *msk, bool write,
                                             float upv, bool up_fresh, float dnv, bool dn_fresh, Ramp *wtot,
                                             const CellIn &c, int t, bool act)
 {
+    static_assert(!WS || NT == 64, "a wave-synchronous line is one wave");
+    if (WS) wave_lds_sync();
     const int lane = t & 63, wave = t >> 6;
     const int nl = A.nl, ml = A.ml, nw = (ml + 63) >> 6;
     const int ru = REV ? r + 1 : r - 1;      // upstream line
@@ -580,7 +589,13 @@ __device__ __forceinline__ float sweep_line(const LineArgs &A, int r, const RunB
     }
     const unsigned long long bm = __ballot(s0);
     if (lane == 0 && wave * 64 < ml) msk[wave] = bm;
-    const bool any_star = __syncthreads_or(s0);
+    bool any_star;
+    if (WS) {
+        any_star = bm != 0ull;
+        wave_lds_sync();
+    } else {
+        any_star = __syncthreads_or(s0);
+    }
 
     // phase 2: the cell's unit (ps, L; L = 0: a point); the unit's chain ramp at its last cell
     int ps = p, Lu = 0;
@@ -744,11 +759,14 @@ __device__ __forceinline__ void sweep_band(const LineArgs &A, int b, const RunBu
 // lines: four line steps instead of five.  Both halves make the same four
 // sweep_line calls (a half with no line takes them on no cells), so every
 // block barrier is reached by all waves.  Each half has its own masks, row
-// buffers and scan totals.
+// buffers and scan totals.  Lines of one wave (NT = 64) take no block barrier
+// inside a step: each half runs its own steps, and one block barrier before
+// the last step publishes the recomputed line.
 template <int NT, bool REV, bool PF, bool CF>
 __device__ __forceinline__ void sweep_band2(const LineArgs &A, int b, const RunBuf &B0, const RunBuf &B1,
                                             uint64_t *msk0, uint64_t *msk1, Ramp *wtot0, Ramp *wtot1, float *redl)
 {
+    constexpr bool WS = NT == 64;
     const int nl = A.nl, ml = A.ml;
     const int half = __builtin_amdgcn_readfirstlane((int)threadIdx.x / NT);
     const int t = threadIdx.x - half * NT;
@@ -781,10 +799,14 @@ __device__ __forceinline__ void sweep_band2(const LineArgs &A, int b, const RunB
         } else {
             load(k, la);
         }
-        // the recomputed line was left in LDS by the upper half at k = 0 (barriers of the calls between)
+        // the recomputed line was left in LDS by the upper half at k = 0 (barriers of the calls between,
+        // or the one below for one-wave lines)
+        if (WS && k == 3) __syncthreads();
         const float dnv = act && dn_fresh && t < ml ? redl[t] : 0.0f;
-        const float cur = sweep_line<NT, REV, CF>(A, r, B.other(k & 1), msk, act && !redundant && !pack, prev,
-                                                  up_fresh, dnv, dn_fresh, wtot, la, t, act);
+        float cur = 0.0f;
+        if (!WS || act)
+            cur = sweep_line<NT, REV, CF, WS>(A, r, B.other(k & 1), msk, act && !redundant && !pack, prev, up_fresh,
+                                              dnv, dn_fresh, wtot, la, t, act);
         if (act) {
             if (redundant) {
                 if (t < ml) redl[t] = cur;
