@@ -34,9 +34,10 @@ __device__ __forceinline__ int mg_mirror(int t, int n)
     if (t >= n) t = 2 * n - t - 1;
     return t < 0 ? 0 : (t >= n ? n - 1 : t);
 }
+// clip(x, lo, hi) for lo <= hi: the median of the three (one instruction)
 __device__ __forceinline__ float mg_clip(float x, float lo, float hi)
 {
-    return fminf(fmaxf(x, lo), hi);
+    return __builtin_amdgcn_fmed3f(x, lo, hi);
 }
 
 // Face coefficient between cells P and Q (eq. abcdrc with the conservative
@@ -359,15 +360,17 @@ __device__ __forceinline__ Ramp dpp_ramp(const Ramp &r)
     return Ramp{dpp_f<CTRL, ROWM>(id.a, r.a), dpp_f<CTRL, ROWM>(id.b, r.b), dpp_f<CTRL, ROWM>(id.lo, r.lo),
                 dpp_f<CTRL, ROWM>(id.hi, r.hi)};
 }
-// inclusive scan over the 64 lanes of a wave (lane order)
+// inclusive scan in lane order, complete on the first LANES lanes of the wave
+// (the stages that only reach lanes at or above LANES are left out)
+template <int LANES = 64>
 __device__ __forceinline__ Ramp wave_scan_incl(Ramp v)
 {
-    v = ramp_comp(v, dpp_ramp<0x111>(v));          // row_shr:1
-    v = ramp_comp(v, dpp_ramp<0x112>(v));          // row_shr:2
-    v = ramp_comp(v, dpp_ramp<0x114>(v));          // row_shr:4
-    v = ramp_comp(v, dpp_ramp<0x118>(v));          // row_shr:8
-    v = ramp_comp(v, dpp_ramp<0x142, 0xa>(v));     // row_bcast:15 into rows 1, 3
-    v = ramp_comp(v, dpp_ramp<0x143, 0xc>(v));     // row_bcast:31 into rows 2, 3
+    if (LANES > 1) v = ramp_comp(v, dpp_ramp<0x111>(v));          // row_shr:1
+    if (LANES > 2) v = ramp_comp(v, dpp_ramp<0x112>(v));          // row_shr:2
+    if (LANES > 4) v = ramp_comp(v, dpp_ramp<0x114>(v));          // row_shr:4
+    if (LANES > 8) v = ramp_comp(v, dpp_ramp<0x118>(v));          // row_shr:8
+    if (LANES > 16) v = ramp_comp(v, dpp_ramp<0x142, 0xa>(v));    // row_bcast:15 into rows 1, 3
+    if (LANES > 32) v = ramp_comp(v, dpp_ramp<0x143, 0xc>(v));    // row_bcast:31 into rows 2, 3
     return v;
 }
 __device__ __forceinline__ Ramp readlane_ramp(const Ramp &r, int lane)
@@ -379,18 +382,21 @@ __device__ __forceinline__ Ramp readlane_ramp(const Ramp &r, int lane)
 }
 
 // t: the thread's index in the group of NT threads that takes the scan.
+// short16 (one wave): only the first 16 prefixes are wanted (total is then
+// not the line's).
 template <int NT>
-__device__ __forceinline__ Ramp block_scan_excl(Ramp mine, Ramp *wtot, int parity, Ramp &total, int t)
+__device__ __forceinline__ Ramp block_scan_excl(Ramp mine, Ramp *wtot, int parity, Ramp &total, int t,
+                                                bool short16 = false)
 {
     const int lane = t & 63, wave = t >> 6;
     constexpr int NW = NT / 64;
-    const Ramp inc = wave_scan_incl(mine);
+    const Ramp inc = NW == 1 && short16 ? wave_scan_incl<16>(mine) : wave_scan_incl<64>(mine);
     Ramp ex = dpp_ramp<0x138>(inc);                 // wave_shr:1 (lane 0: identity)
     if (NW > 1) {
         Ramp *wt = wtot + parity * NW;
         if (lane == 63) wt[wave] = inc;
         __syncthreads();
-        const Ramp ws = wave_scan_incl(lane < NW ? wt[lane] : ramp_id());
+        const Ramp ws = wave_scan_incl<NW>(lane < NW ? wt[lane] : ramp_id());
         const int wv = __builtin_amdgcn_readfirstlane(wave);
         if (wv > 0) ex = ramp_comp(ex, readlane_ramp(ws, wv - 1));
         total = readlane_ramp(ws, NW - 1);
@@ -622,7 +628,7 @@ __device__ __forceinline__ float sweep_line(const LineArgs &A, int r, const RunB
 
     // phase 3: the scan gives every cell the value entering it (a unit cell: entering its unit)
     Ramp tot;
-    const Ramp ex = block_scan_excl<NT>(u, wtot, 0, tot, t);
+    const Ramp ex = block_scan_excl<NT>(u, wtot, 0, tot, t, ml <= 16);
     const float x = ramp_eval(ex, 0.0f);
     float v = 0.0f;
     if (in) {
