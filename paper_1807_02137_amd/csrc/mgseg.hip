@@ -772,6 +772,12 @@ mgseg_status mgseg_setup(const float *image_dev, int n, int m, int pitch, const 
                 return MGSEG_E_HIP;
     }
 
+    // the one-workgroup coarsest solve stages its level in LDS (up to CO_MAX_CELLS cells)
+    if (hipFuncSetAttribute(reinterpret_cast<const void *>(&k_coarse_smooth<64>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)coarse_lds_bytes(CO_MAX_CELLS, 1)) !=
+        hipSuccess)
+        return MGSEG_E_HIP;
+
     mgseg_ctx *c = new (std::nothrow) mgseg_ctx();
     if (!c) return MGSEG_E_NOMEM;
     c->p = *p; c->p.levels = Lv;

@@ -485,12 +485,15 @@ struct CellRow {
 };
 // CF: the scaled face coefficients come from the freeze (the same products,
 // so the same bits) and the fit term is part of F.
-template <bool REV, bool CF = false>
-__device__ __forceinline__ CellRow cell_row(const LineArgs &A, const CellIn &c, int r, int q, float vu, float vd,
-                                            float area)
+// The scaled face coefficients of cell (r, q) to lines r+1, r-1 and cells
+// q+1, q-1 (zero across the grid edge) and the fit term f (eq. abcdrc); CF:
+// the coefficients stored by the freeze (the fit term is then part of F).
+template <bool CF = false>
+__device__ __forceinline__ void cell_coef(const LineArgs &A, const CellIn &c, int r, int q, float area, float &xp,
+                                          float &xm, float &lp, float &lm, float &f)
 {
     const int nl = A.nl, ml = A.ml;
-    float xp = 0.0f, xm = 0.0f, lp = 0.0f, lm = 0.0f, f = 0.0f;
+    xp = 0.0f; xm = 0.0f; lp = 0.0f; lm = 0.0f; f = 0.0f;
     if (CF) {
         xp = c.g.x; xm = c.g.y; lp = c.g.z; lm = c.g.w;
     } else {
@@ -505,6 +508,13 @@ __device__ __forceinline__ CellRow cell_row(const LineArgs &A, const CellIn &c, 
         xp *= sc; xm *= sc; lp *= sc; lm *= sc;
         f = A.fit ? dl * (c.fit + area) : 0.0f;   // null fit: f is part of F
     }
+}
+template <bool REV, bool CF = false>
+__device__ __forceinline__ CellRow cell_row(const LineArgs &A, const CellIn &c, int r, int q, float vu, float vd,
+                                            float area)
+{
+    float xp, xm, lp, lm, f;
+    cell_coef<CF>(A, c, r, q, area, xp, xm, lp, lm, f);
     const float S = xp + xm + lp + lm;
     const float Xu = REV ? xp : xm, Xd = REV ? xm : xp;
     const float Lp = REV ? lp : lm, Ls = REV ? lm : lp;

@@ -948,12 +948,13 @@ struct CoarseArgs {
     int n, m, prm, iters, scaled;
     float kap, e2, M, Sigma, rtol;
 };
-#define CO_ARRAYS 20
+#define CO_ARRAYS 18
 #define CO_MAX_CELLS 768
+// dynamic LDS: [two float4 coefficient arrays][CO_ARRAYS float arrays][two label arrays]
 __host__ __device__ inline size_t coarse_lds_bytes(int n, int m)
 {
     const size_t N = (size_t)n * m;
-    return CO_ARRAYS * N * sizeof(float) + ((2 * N + 7) / 8) * 8;
+    return 2 * N * sizeof(float4) + CO_ARRAYS * N * sizeof(float) + ((2 * N + 7) / 8) * 8;
 }
 
 // largest change of the state over one outer iteration and since the
@@ -1002,25 +1003,28 @@ __global__ void __launch_bounds__(NT) k_coarse_smooth(CoarseArgs G)
     __shared__ float rdt[NT];
     __shared__ float rb[2 * RB_FIELDS * NT];
     __shared__ uint64_t msk[(NT + 63) / 64];
-    extern __shared__ float co[];
+    extern __shared__ float4 co4[];
     const int n = G.n, m = G.m, N = n * m, tid = threadIdx.x;
     const bool dev = G.base != nullptr;
-    // LDS arrays: row-major with pitch m, column-major with pitch n
+    // LDS arrays: row-major with pitch m, column-major with pitch n.  cf / cf_cm: the
+    // frozen scaled face coefficients of each layout, (to the next line, to the previous
+    // line, to the next cell, to the previous cell); Fe / Fe_cm: F plus the fit term.
+    float4 *cf = co4, *cf_cm = co4 + N;
+    float *co = reinterpret_cast<float *>(co4 + 2 * N);
     float *P0 = co, *P1 = co + N, *P2 = co + 2 * N, *T1 = co + 3 * N, *T2 = co + 4 * N;
-    float *psi = co + 5 * N, *psi_cm = co + 6 * N;
-    float *w = co + 7 * N, *w_cm = co + 8 * N, *fit = co + 9 * N, *fit_cm = co + 10 * N;
-    float *lo = co + 11 * N, *lo_cm = co + 12 * N, *hi = co + 13 * N, *hi_cm = co + 14 * N;
-    float *F = co + 15 * N, *F_cm = co + 16 * N, *base = co + 17 * N, *Gv = co + 18 * N, *E = co + 19 * N;
+    float *psi = co + 5 * N, *w = co + 6 * N, *fit = co + 7 * N;
+    float *lo = co + 8 * N, *lo_cm = co + 9 * N, *hi = co + 10 * N, *hi_cm = co + 11 * N;
+    float *F = co + 12 * N, *Fe = co + 13 * N, *Fe_cm = co + 14 * N, *base = co + 15 * N, *Gv = co + 16 * N;
+    float *E = co + 17 * N;
     uint8_t *lab = reinterpret_cast<uint8_t *>(co + CO_ARRAYS * N), *lab_cm = lab + N;
     for (int t = tid; t < N; t += NT) {
         const int i = t / m, j = t % m, qg = i * G.prm + j, qr = t, qc = j * n + i;
         P0[qr] = E[qr] = G.P0[qg];
-        w[qr] = w_cm[qc] = G.w[qg];
-        fit[qr] = fit_cm[qc] = G.fit[qg];
+        w[qr] = G.w[qg];
+        fit[qr] = G.fit[qg];
         lo[qr] = lo_cm[qc] = G.lo[qg];
         hi[qr] = hi_cm[qc] = G.hi[qg];
-        const float fv = (!dev && G.F) ? G.F[qg] : 0.0f;
-        F[qr] = F_cm[qc] = fv;
+        F[qr] = (!dev && G.F) ? G.F[qg] : 0.0f;
         base[qr] = dev ? G.base[qg] : 0.0f;
         Gv[qr] = dev ? G.G[qg] : 0.0f;
     }
@@ -1028,13 +1032,18 @@ __global__ void __launch_bounds__(NT) k_coarse_smooth(CoarseArgs G)
     RunBuf RBr, RBc;
     RBr.p = rb; RBr.fs = m;
     RBc.p = rb; RBc.fs = n;
-    LineArgs R, T;
-    R.psi = psi; R.w = w; R.fit = dev ? nullptr : fit; R.F = F; R.lab = lab; R.lo = lo; R.hi = hi;
-    R.skip = nullptr; R.tout = nullptr; R.tpitch = 0; R.area = G.area; R.pitch = m; R.lpitch = m; R.cf = nullptr;
-    R.nl = n; R.ml = m; R.kap = G.kap; R.e2 = G.e2; R.M = G.M; R.eps = (float)G.eps; R.scaled = G.scaled;
+    // C: the row-major arguments the freeze evaluates the coefficients with; R / T: the
+    // row and column sweeps, which read the stored coefficients
+    LineArgs C, R, T;
+    C.psi = psi; C.w = w; C.fit = dev ? nullptr : fit; C.F = F; C.lab = lab; C.lo = lo; C.hi = hi;
+    C.skip = nullptr; C.tout = nullptr; C.tpitch = 0; C.area = G.area; C.pitch = m; C.lpitch = m; C.cf = nullptr;
+    C.nl = n; C.ml = m; C.kap = G.kap; C.e2 = G.e2; C.M = G.M; C.eps = (float)G.eps; C.scaled = G.scaled;
+    C.phi_old = P0; C.phi_new = nullptr; C.bit = 0;
+    R = C;
+    R.psi = nullptr; R.w = nullptr; R.fit = nullptr; R.F = Fe; R.cf = cf;
     T = R;
-    T.psi = psi_cm; T.w = w_cm; T.fit = dev ? nullptr : fit_cm; T.F = F_cm; T.lab = lab_cm; T.lo = lo_cm;
-    T.hi = hi_cm; T.pitch = n; T.lpitch = n; T.nl = m; T.ml = n;
+    T.F = Fe_cm; T.cf = cf_cm; T.lab = lab_cm; T.lo = lo_cm; T.hi = hi_cm; T.pitch = n; T.lpitch = n; T.nl = m;
+    T.ml = n;
     DevArgs<float> D;
     D.b = base; D.pb = m; D.e = P0; D.G = Gv; D.w = w; D.fit = fit; D.lo = lo; D.hi = hi;
     D.psi = nullptr; D.T = nullptr; D.r = nullptr; D.lab = nullptr;
@@ -1064,16 +1073,12 @@ __global__ void __launch_bounds__(NT) k_coarse_smooth(CoarseArgs G)
                 float u0;
                 uint8_t b;
                 const double tv = dev_cell(D, i, j, false, Le, u0, b);
-                psi[t] = u0; psi_cm[qc] = u0;
-                F[t] = (float)tv; F_cm[qc] = (float)tv;
+                psi[t] = u0;
+                F[t] = (float)tv;
                 lab[t] = b; lab_cm[qc] = b;
             }
         } else {
-            for (int t = tid; t < N; t += NT) {
-                const int i = t / m, j = t % m;
-                psi[t] = P0[t];
-                psi_cm[j * n + i] = P0[t];
-            }
+            for (int t = tid; t < N; t += NT) psi[t] = P0[t];
             __syncthreads();
             for (int t = tid; t < N; t += NT) {
                 const int i = t / m, j = t % m;
@@ -1083,23 +1088,41 @@ __global__ void __launch_bounds__(NT) k_coarse_smooth(CoarseArgs G)
             }
         }
         __syncthreads();
+        // the frozen scaled face coefficients and F plus the fit term of every cell, once for the
+        // four sweeps, in both layouts (the products the sweeps would form, so the same bits)
+        {
+            const float area = G.area ? (float)(*G.area) : 0.0f;
+            for (int t = tid; t < N; t += NT) {
+                const int i = t / m, j = t % m, qc = j * n + i;
+                CellIn c;
+                cell_load<false, false>(line_rows<false>(C, i, true, true), m, j, c);
+                float xp, xm, lp, lm, f;
+                cell_coef<false>(C, c, i, j, area, xp, xm, lp, lm, f);
+                cf[t] = make_float4(xp, xm, lp, lm);
+                cf_cm[qc] = make_float4(lp, lm, xp, xm);
+                const float fe = f + c.F;
+                Fe[t] = fe;
+                Fe_cm[qc] = fe;
+            }
+        }
+        __syncthreads();
         // sweeps A and B (rows); the sweep output is read by the next sweep
         // after a barrier (the bands of one sweep read only its input)
         int lpar = 0;
         R.phi_old = P0; R.phi_new = P1; R.bit = 0;
-        for (int b = 0; b < (n + 3) / 4; b++) sweep_band<NT, false>(R, b, RBr, msk, sh, lpar);
+        for (int b = 0; b < (n + 3) / 4; b++) sweep_band<NT, false, true, true>(R, b, RBr, msk, sh, lpar);
         __syncthreads();
         R.phi_old = P1; R.phi_new = P2; R.bit = 1;
-        for (int b = 0; b < (n + 3) / 4; b++) sweep_band<NT, true>(R, b, RBr, msk, sh, lpar);
+        for (int b = 0; b < (n + 3) / 4; b++) sweep_band<NT, true, true, true>(R, b, RBr, msk, sh, lpar);
         __syncthreads();
         block_transpose<NT>(P2, m, T1, n, n, m);
         __syncthreads();
         // sweeps C and D (columns)
         T.phi_old = T1; T.phi_new = T2; T.bit = 2;
-        for (int b = 0; b < (m + 3) / 4; b++) sweep_band<NT, false>(T, b, RBc, msk, sh, lpar);
+        for (int b = 0; b < (m + 3) / 4; b++) sweep_band<NT, false, true, true>(T, b, RBc, msk, sh, lpar);
         __syncthreads();
         T.phi_old = T2; T.phi_new = T1; T.bit = 3;
-        for (int b = 0; b < (m + 3) / 4; b++) sweep_band<NT, true>(T, b, RBc, msk, sh, lpar);
+        for (int b = 0; b < (m + 3) / 4; b++) sweep_band<NT, true, true, true>(T, b, RBc, msk, sh, lpar);
         __syncthreads();
         float dmax = 0.0f, tot = 0.0f;
         for (int t = tid; t < N; t += NT) {
