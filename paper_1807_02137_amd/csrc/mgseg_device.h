@@ -610,7 +610,9 @@ __device__ __forceinline__ float sweep_line(const LineArgs &A, int r, const RunB
         any_star = bm != 0ull;
         wave_lds_sync();
     } else {
-        any_star = __syncthreads_or(s0);
+        // one barrier makes the rows and masks visible; a line has a starred cell iff a mask word is non-zero
+        __syncthreads();
+        any_star = __ballot(lane < nw && msk[lane] != 0ull) != 0ull;
     }
 
     // phase 2: the cell's unit (ps, L; L = 0: a point); the unit's chain ramp at its last cell
@@ -861,7 +863,7 @@ __device__ __forceinline__ void sweep_band2(const LineArgs &A, int b, const RunB
 // per-round addresses held across rounds.
 template <int NT, bool REV, bool CF>
 __device__ __forceinline__ void long_band(const LineArgs &A, int b, float *ring, float *prev, float *red,
-                                          uint64_t *msk, Ramp *wtot)
+                                          uint64_t *msk, Ramp *wtot, unsigned *wlast)
 {
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int nl = A.nl, ml = A.ml, nw = (ml + 63) >> 6;
@@ -937,7 +939,11 @@ __device__ __forceinline__ void long_band(const LineArgs &A, int b, float *ring,
                     B.at(RG_S, p) = c.sig;
                 }
             }
-            const bool uk = __syncthreads_or(last);   // rows of the round visible
+            // rows of the round visible; uk: a unit of the block ends in this round
+            const unsigned long long lm = __ballot(last);
+            if (lane == 0) wlast[wave] = lm != 0ull ? 1u : 0u;
+            __syncthreads();
+            const bool uk = __ballot(lane < NT / 64 && wlast[lane] != 0u) != 0ull;
             Ramp u = ramp_id();
             if (in && !inu) u = cell_ramp(w);
             if (last) {
@@ -1000,10 +1006,11 @@ __global__ void __launch_bounds__(NT) k_sweep_long(LineArgs A)
     if (A.skip && *A.skip) return;
     extern __shared__ uint64_t smem64[];
     __shared__ Ramp wtot[2 * (NT / 64)];
+    __shared__ unsigned wlast[NT / 64];
     uint64_t *msk = smem64;
     float *ring = reinterpret_cast<float *>(smem64 + sweep_mask_words(A.ml));
     float *prev = ring + RF_COUNT * 2 * NT;
-    long_band<NT, REV, CF>(A, blockIdx.x, ring, prev, prev + A.ml, msk, wtot);
+    long_band<NT, REV, CF>(A, blockIdx.x, ring, prev, prev + A.ml, msk, wtot, wlast);
 }
 
 // dynamic LDS: [starred masks, 8 B per 64 cells][2 x RB_FIELDS * ml floats of rows]
