@@ -326,10 +326,9 @@ __device__ __forceinline__ int run_last(const uint64_t *msk, int nw, int p)
     }
     return (wi << 6) + __builtin_ctzll(z) - 1;
 }
-// unit of the starred position p: first position ps and length L
-__device__ __forceinline__ void unit_of(const uint64_t *msk, int nw, int ml, int p, int &ps, int &L)
+// unit of the starred position p of the maximal starred run t0..e: first position ps and length L
+__device__ __forceinline__ void unit_of_run(int t0, int e, int ml, int p, int &ps, int &L)
 {
-    const int t0 = run_first(msk, p), e = run_last(msk, nw, p);
     const int rl = e - t0 + 1;
     if (rl == 1) { ps = p; L = p + 1 < ml ? 2 : 1; return; }
     if (rl <= RUN_MAX) { ps = t0; L = rl; return; }
@@ -337,6 +336,16 @@ __device__ __forceinline__ void unit_of(const uint64_t *msk, int nw, int ml, int
     const int o = p - t0, big = extra * (base + 1);
     if (o < big) { ps = t0 + (o / (base + 1)) * (base + 1); L = base + 1; }
     else { ps = t0 + big + ((o - big) / base) * base; L = base; }
+}
+__device__ __forceinline__ void unit_of(const uint64_t *msk, int nw, int ml, int p, int &ps, int &L)
+{
+    unit_of_run(run_first(msk, p), run_last(msk, nw, p), ml, p, ps, L);
+}
+// the same on a line of at most 64 cells whose starred mask is the word bm
+__device__ __forceinline__ void unit_of1(uint64_t bm, int ml, int p, int &ps, int &L)
+{
+    const uint64_t zb = ~bm & ((1ull << p) - 1ull), za = ~bm & ~((2ull << p) - 1ull);
+    unit_of_run(zb ? 64 - __builtin_clzll(zb) : 0, za ? __builtin_ctzll(za) - 1 : 63, ml, p, ps, L);
 }
 
 // --------------------------------------------------------------------------
@@ -603,12 +612,14 @@ __device__ __forceinline__ float sweep_line(const LineArgs &A, int r, const RunB
         w = cell_row<REV, CF>(A, c, r, q, vu, vd, area);
         row_store(B, p, w);
     }
+    // a line of one wave keeps its starred mask in the ballot word (bm)
     const unsigned long long bm = __ballot(s0);
-    if (lane == 0 && wave * 64 < ml) msk[wave] = bm;
+    if (NT > 64 && lane == 0 && wave * 64 < ml) msk[wave] = bm;
     bool any_star;
-    if (WS) {
+    if (NT == 64) {
         any_star = bm != 0ull;
-        wave_lds_sync();
+        if (WS) wave_lds_sync();
+        else __syncthreads();
     } else {
         // one barrier makes the rows and masks visible; a line has a starred cell iff a mask word is non-zero
         __syncthreads();
@@ -620,8 +631,15 @@ __device__ __forceinline__ float sweep_line(const LineArgs &A, int r, const RunB
     Ramp u = ramp_id();
     if (in) {
         if (any_star) {
-            if (s0) unit_of(msk, nw, ml, p, ps, Lu);
-            else if (p >= 1 && mask_bit(msk, p - 1) && (p < 2 || !mask_bit(msk, p - 2))) { ps = p - 1; Lu = 2; }
+            if (NT == 64) {
+                if (s0) unit_of1(bm, ml, p, ps, Lu);
+                else if (p >= 1 && ((bm >> (p - 1)) & 1ull) && (p < 2 || !((bm >> (p - 2)) & 1ull))) {
+                    ps = p - 1; Lu = 2;
+                }
+            } else {
+                if (s0) unit_of(msk, nw, ml, p, ps, Lu);
+                else if (p >= 1 && mask_bit(msk, p - 1) && (p < 2 || !mask_bit(msk, p - 2))) { ps = p - 1; Lu = 2; }
+            }
         }
         if (Lu == 0) {
             u = cell_ramp(w);
@@ -711,7 +729,7 @@ __device__ __forceinline__ void band_step(int r0, int nl, int st, int &r, bool &
 // CellIn).  B: the first of two row buffers; lpar: the caller's running line
 // count, whose parity picks the buffer of each line (it continues across
 // bands that one workgroup takes one after another).
-template <int NT, bool REV, bool PF = false, bool CF = false>
+template <int NT, bool REV, bool PF = false, bool CF = false, bool WS = false>
 __device__ __forceinline__ void sweep_band(const LineArgs &A, int b, const RunBuf &B, uint64_t *msk, Ramp *wtot,
                                            int &lpar)
 {
@@ -748,8 +766,8 @@ __device__ __forceinline__ void sweep_band(const LineArgs &A, int b, const RunBu
         } else {
             load(r, up_fresh, dn_fresh, la);
         }
-        const float cur = sweep_line<NT, REV, CF>(A, r, B.other(lpar & 1), msk, !redundant && !pack, prev, up_fresh,
-                                                  red, dn_fresh, wtot, la, t, true);
+        const float cur = sweep_line<NT, REV, CF, WS>(A, r, B.other(lpar & 1), msk, !redundant && !pack, prev,
+                                                      up_fresh, red, dn_fresh, wtot, la, t, true);
         lpar++;
         const int li = r - r0;
         if (redundant) red = cur;

@@ -1110,19 +1110,19 @@ __global__ void __launch_bounds__(NT) k_coarse_smooth(CoarseArgs G)
         // after a barrier (the bands of one sweep read only its input)
         int lpar = 0;
         R.phi_old = P0; R.phi_new = P1; R.bit = 0;
-        for (int b = 0; b < (n + 3) / 4; b++) sweep_band<NT, false, true, true>(R, b, RBr, msk, sh, lpar);
+        for (int b = 0; b < (n + 3) / 4; b++) sweep_band<NT, false, true, true, NT == 64>(R, b, RBr, msk, sh, lpar);
         __syncthreads();
         R.phi_old = P1; R.phi_new = P2; R.bit = 1;
-        for (int b = 0; b < (n + 3) / 4; b++) sweep_band<NT, true, true, true>(R, b, RBr, msk, sh, lpar);
+        for (int b = 0; b < (n + 3) / 4; b++) sweep_band<NT, true, true, true, NT == 64>(R, b, RBr, msk, sh, lpar);
         __syncthreads();
         block_transpose<NT>(P2, m, T1, n, n, m);
         __syncthreads();
         // sweeps C and D (columns)
         T.phi_old = T1; T.phi_new = T2; T.bit = 2;
-        for (int b = 0; b < (m + 3) / 4; b++) sweep_band<NT, false, true, true>(T, b, RBc, msk, sh, lpar);
+        for (int b = 0; b < (m + 3) / 4; b++) sweep_band<NT, false, true, true, NT == 64>(T, b, RBc, msk, sh, lpar);
         __syncthreads();
         T.phi_old = T2; T.phi_new = T1; T.bit = 3;
-        for (int b = 0; b < (m + 3) / 4; b++) sweep_band<NT, true, true, true>(T, b, RBc, msk, sh, lpar);
+        for (int b = 0; b < (m + 3) / 4; b++) sweep_band<NT, true, true, true, NT == 64>(T, b, RBc, msk, sh, lpar);
         __syncthreads();
         float dmax = 0.0f, tot = 0.0f;
         for (int t = tid; t < N; t += NT) {
