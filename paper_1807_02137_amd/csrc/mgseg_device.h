@@ -391,15 +391,17 @@ __device__ __forceinline__ Ramp readlane_ramp(const Ramp &r, int lane)
 }
 
 // t: the thread's index in the group of NT threads that takes the scan.
-// short16 (one wave): only the first 16 prefixes are wanted (total is then
+// want (one wave): only the first `want` prefixes are needed (total is then
 // not the line's).
 template <int NT>
 __device__ __forceinline__ Ramp block_scan_excl(Ramp mine, Ramp *wtot, int parity, Ramp &total, int t,
-                                                bool short16 = false)
+                                                int want = 64)
 {
     const int lane = t & 63, wave = t >> 6;
     constexpr int NW = NT / 64;
-    const Ramp inc = NW == 1 && short16 ? wave_scan_incl<16>(mine) : wave_scan_incl<64>(mine);
+    const Ramp inc = NW > 1 || want > 32 ? wave_scan_incl<64>(mine)
+                     : want > 16         ? wave_scan_incl<32>(mine)
+                                         : wave_scan_incl<16>(mine);
     Ramp ex = dpp_ramp<0x138>(inc);                 // wave_shr:1 (lane 0: identity)
     if (NW > 1) {
         Ramp *wt = wtot + parity * NW;
@@ -658,7 +660,7 @@ __device__ __forceinline__ float sweep_line(const LineArgs &A, int r, const RunB
 
     // phase 3: the scan gives every cell the value entering it (a unit cell: entering its unit)
     Ramp tot;
-    const Ramp ex = block_scan_excl<NT>(u, wtot, 0, tot, t, ml <= 16);
+    const Ramp ex = block_scan_excl<NT>(u, wtot, 0, tot, t, ml);
     const float x = ramp_eval(ex, 0.0f);
     float v = 0.0f;
     if (in) {
@@ -792,8 +794,8 @@ __device__ __forceinline__ void sweep_band(const LineArgs &A, int b, const RunBu
 // values only (both of its cross-line neighbours are processed after it), so
 // the upper half computes it beside the band's first line and leaves it in
 // LDS (redl, by visit position), while the lower half takes the band's own
-// lines: four line steps instead of five.  Both halves make the same four
-// sweep_line calls (a half with no line takes them on no cells), so every
+// lines: four line steps instead of five.  Both halves take four steps (a
+// half with no line in a step takes only that step's barriers), so every
 // block barrier is reached by all waves.  Each half has its own masks, row
 // buffers and scan totals.  Lines of one wave (NT = 64) take no block barrier
 // inside a step: each half runs its own steps, and one block barrier before
@@ -840,9 +842,15 @@ __device__ __forceinline__ void sweep_band2(const LineArgs &A, int b, const RunB
         if (WS && k == 3) __syncthreads();
         const float dnv = act && dn_fresh && t < ml ? redl[t] : 0.0f;
         float cur = 0.0f;
-        if (!WS || act)
-            cur = sweep_line<NT, REV, CF, WS>(A, r, B.other(k & 1), msk, act && !redundant && !pack, prev, up_fresh,
-                                              dnv, dn_fresh, wtot, la, t, act);
+        if (act) {
+            cur = sweep_line<NT, REV, CF, WS>(A, r, B.other(k & 1), msk, !redundant && !pack, prev, up_fresh, dnv,
+                                              dn_fresh, wtot, la, t, true);
+        } else if (!WS) {
+            // a half with no line takes the line step's barriers only: the one after the rows and
+            // masks, and the scan's (several waves)
+            __syncthreads();
+            if (NT > 64) __syncthreads();
+        }
         if (act) {
             if (redundant) {
                 if (t < ml) redl[t] = cur;
