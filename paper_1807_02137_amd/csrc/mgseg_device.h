@@ -824,8 +824,12 @@ __device__ __forceinline__ void sweep_band2(const LineArgs &A, int b, const RunB
         cell_load<REV, CF>(line_rows<REV>(A, r, uf, df), ml, t, c);
     };
     float prev = 0.0f, o0 = 0.0f, o1 = 0.0f, o2 = 0.0f, o3 = 0.0f;
-    CellIn la{}, lb{};
-    if (PF) load(0, la);
+    // read-ahead: the next step's inputs; lines of one wave read all four steps' inputs at once
+    CellIn la{}, lb{}, lc{}, ld{};
+    if (PF) {
+        load(0, la);
+        if (WS) { load(1, lb); load(2, lc); load(3, ld); }
+    }
 #pragma nounroll
     for (int k = 0; k < 4; k++) {
         const int st = step_of(k);
@@ -833,7 +837,7 @@ __device__ __forceinline__ void sweep_band2(const LineArgs &A, int b, const RunB
         int r = r0; bool redundant = false, up_fresh = false, dn_fresh = false;
         if (act) band_step<REV>(r0, nl, st, r, redundant, up_fresh, dn_fresh);
         if (PF) {
-            if (k + 1 < 4) load(k + 1, lb);
+            if (!WS && k + 1 < 4) load(k + 1, lb);
         } else {
             load(k, la);
         }
@@ -863,7 +867,10 @@ __device__ __forceinline__ void sweep_band2(const LineArgs &A, int b, const RunB
                 else o3 = cur;
             }
         }
-        if (PF) la = lb;
+        if (PF) {
+            la = lb;
+            if (WS) { lb = lc; lc = ld; }
+        }
     }
     if (half == 0 && pack && t < ml) {
         const int q = REV ? ml - 1 - t : t;
