@@ -805,6 +805,8 @@ __device__ __forceinline__ void sweep_band2(const LineArgs &A, int b, const RunB
                                             uint64_t *msk0, uint64_t *msk1, Ramp *wtot0, Ramp *wtot1, float *redl)
 {
     constexpr bool WS = NT == 64;
+    // read all four steps' inputs at the start where the registers allow it
+    constexpr bool DEEP = PF && (WS || (CF && NT <= 512));
     const int nl = A.nl, ml = A.ml;
     const int half = __builtin_amdgcn_readfirstlane((int)threadIdx.x / NT);
     const int t = threadIdx.x - half * NT;
@@ -824,11 +826,11 @@ __device__ __forceinline__ void sweep_band2(const LineArgs &A, int b, const RunB
         cell_load<REV, CF>(line_rows<REV>(A, r, uf, df), ml, t, c);
     };
     float prev = 0.0f, o0 = 0.0f, o1 = 0.0f, o2 = 0.0f, o3 = 0.0f;
-    // read-ahead: the next step's inputs; lines of one wave read all four steps' inputs at once
+    // read-ahead: the next step's inputs, or (DEEP) all four steps' inputs at once
     CellIn la{}, lb{}, lc{}, ld{};
     if (PF) {
         load(0, la);
-        if (WS) { load(1, lb); load(2, lc); load(3, ld); }
+        if (DEEP) { load(1, lb); load(2, lc); load(3, ld); }
     }
 #pragma nounroll
     for (int k = 0; k < 4; k++) {
@@ -837,7 +839,7 @@ __device__ __forceinline__ void sweep_band2(const LineArgs &A, int b, const RunB
         int r = r0; bool redundant = false, up_fresh = false, dn_fresh = false;
         if (act) band_step<REV>(r0, nl, st, r, redundant, up_fresh, dn_fresh);
         if (PF) {
-            if (!WS && k + 1 < 4) load(k + 1, lb);
+            if (!DEEP && k + 1 < 4) load(k + 1, lb);
         } else {
             load(k, la);
         }
@@ -869,7 +871,7 @@ __device__ __forceinline__ void sweep_band2(const LineArgs &A, int b, const RunB
         }
         if (PF) {
             la = lb;
-            if (WS) { lb = lc; lc = ld; }
+            if (DEEP) { lb = lc; lc = ld; }
         }
     }
     if (half == 0 && pack && t < ml) {
