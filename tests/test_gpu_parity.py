@@ -224,6 +224,34 @@ def test_single_sweep_long_lines(shape, sweep):
     s.close()
 
 
+@pytest.mark.parametrize("shape", [(32, 776), (776, 32), (32, 1000)])
+def test_solve_parity_1024_thread_lines(shape):
+    """Lines of 513 to 1024 cells (the 1024-thread sweep) in the mixed mode,
+    along the rows and along the columns (776 cells: a ragged line), with the
+    jump set all along them: the solve ends at the oracle's segmentation within
+    the solve tolerance."""
+    n, m = shape
+    say("case 1024-thread lines", n, m)
+    img, mk = long_line_instance(n, m)
+    s = mgseg.Solver(img, mk, mgseg.Params(levels=3))
+    o = Oracle(img, mk, OracleParams(levels=3))
+    hg = []
+    for _ in range(40):
+        hg.append(s.vcycle())
+        if hg[-1] <= 1e-6:
+            break
+    k, hist = o.solve(1e-6, 40)
+    pg, po = s.phi().cpu().numpy(), o.get("phi")
+    agree = (pg > 0) == (po > 0)
+    flips = int((~agree).sum())
+    dmax = float(np.abs(pg - po)[agree].max())
+    say(f"gpu {len(hg)} cycles rel {hg[-1]:.2e}; oracle {k} cycles; flips {flips} max|dphi| {dmax:.3e}")
+    assert hg[-1] <= 1e-6 and k > 0
+    assert flips <= 1
+    assert dmax <= 1e-4
+    s.close()
+
+
 def plant_runs_across_rounds(lab, sweep, rnd=1024):
     """Sets the sweep's starred bit on runs of 1-5 cells that straddle every
     rnd-cell boundary of the visit order (the run of line i starts 1 + i % 3
