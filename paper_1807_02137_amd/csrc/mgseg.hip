@@ -427,8 +427,39 @@ void outer(mgseg_ctx *c, int l)
     chk(c);
 }
 
+// arguments of the one-workgroup smoother on level l (a coarse grid)
+CoarseArgs coarse_args(mgseg_ctx *c, int l, int iters, double rtol)
+{
+    Level &L = c->lev[l];
+    const bool dev = devm(c);
+    CoarseArgs C;
+    C.P0 = L.P[0]; C.w = L.w; C.fit = L.fit; C.lo = L.lo; C.hi = L.hi;
+    C.F = (!dev && L.has_F) ? L.F : nullptr;
+    C.base = dev ? L.phic : nullptr; C.G = dev ? L.G : nullptr;
+    C.area_b = dev && c->p.model == 1 ? c->dsc + area_b_slot(l) : nullptr;
+    C.area = c->p.model == 1 ? c->dsc + DS_AREA_FRZ : nullptr;
+    C.h2 = L.h * L.h; C.A1 = c->A1; C.nu = c->p.nu; C.eps = c->p.eps;
+    C.n = L.n; C.m = L.m; C.prm = L.prm; C.iters = iters; C.scaled = c->p.scaled;
+    C.kap = (float)(c->p.mu / L.h); C.e2 = lev_e2(c, l); C.M = (float)c->p.M; C.Sigma = (float)c->p.Sigma;
+    C.rtol = (float)rtol;
+    return C;
+}
+// a coarse grid the one-workgroup smoother holds in LDS
+bool lds_level(mgseg_ctx *c, int l)
+{
+    const Level &L = c->lev[l];
+    return l > 0 && L.n <= 64 && L.m <= 64 && L.n * L.m <= CO_MAX_CELLS;
+}
+
 void smooth(mgseg_ctx *c, int l, int iters)
 {
+    if (iters > 0 && lds_level(c, l) && c->L > 1) {
+        // the small grids: all outer iterations in one workgroup, one band per wave
+        hipLaunchKernelGGL((k_coarse_smooth<512>), dim3(1), dim3(512), coarse_lds_bytes(c->lev[l].n, c->lev[l].m),
+                           c->s, coarse_args(c, l, iters, 0.0));
+        chk(c);
+        return;
+    }
     for (int it = 0; it < iters; it++) outer(c, l);
 }
 
@@ -447,17 +478,8 @@ void coarsest(mgseg_ctx *c, int l)
         chk(c);
         return;
     }
-    if (L.n <= 64 && L.m <= 64 && L.n * L.m <= CO_MAX_CELLS && l > 0) {
-        CoarseArgs C;
-        C.P0 = L.P[0]; C.w = L.w; C.fit = L.fit; C.lo = L.lo; C.hi = L.hi;
-        C.F = (!dev && L.has_F) ? L.F : nullptr;
-        C.base = dev ? L.phic : nullptr; C.G = dev ? L.G : nullptr;
-        C.area_b = dev && c->p.model == 1 ? c->dsc + area_b_slot(l) : nullptr;
-        C.area = c->p.model == 1 ? c->dsc + DS_AREA_FRZ : nullptr;
-        C.h2 = L.h * L.h; C.A1 = c->A1; C.nu = c->p.nu; C.eps = c->p.eps;
-        C.n = L.n; C.m = L.m; C.prm = L.prm; C.iters = c->p.coarse_iters; C.scaled = c->p.scaled;
-        C.kap = (float)(c->p.mu / L.h); C.e2 = lev_e2(c, l); C.M = (float)c->p.M; C.Sigma = (float)c->p.Sigma;
-        C.rtol = (float)c->p.coarse_rtol;
+    if (lds_level(c, l)) {
+        const CoarseArgs C = coarse_args(c, l, c->p.coarse_iters, c->p.coarse_rtol);
         hipLaunchKernelGGL((k_coarse_smooth<64>), dim3(1), dim3(64), coarse_lds_bytes(L.n, L.m), c->s, C);
         chk(c);
         return;
@@ -775,7 +797,10 @@ mgseg_status mgseg_setup(const float *image_dev, int n, int m, int pitch, const 
     // the one-workgroup coarsest solve stages its level in LDS (up to CO_MAX_CELLS cells)
     if (hipFuncSetAttribute(reinterpret_cast<const void *>(&k_coarse_smooth<64>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)coarse_lds_bytes(CO_MAX_CELLS, 1)) !=
-        hipSuccess)
+            hipSuccess ||
+        hipFuncSetAttribute(reinterpret_cast<const void *>(&k_coarse_smooth<512>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)coarse_lds_bytes(CO_MAX_CELLS, 1)) !=
+            hipSuccess)
         return MGSEG_E_HIP;
 
     mgseg_ctx *c = new (std::nothrow) mgseg_ctx();

@@ -738,7 +738,8 @@ __device__ __forceinline__ void sweep_band(const LineArgs &A, int b, const RunBu
     // transposed output of a full band: the band's 4 lines are 4 consecutive
     // floats of the output layout, written as one 16-byte store per cell
     float prev = 0.0f, red = 0.0f, o0 = 0.0f, o1 = 0.0f, o2 = 0.0f, o3 = 0.0f;
-    const int nl = A.nl, ml = A.ml, t = threadIdx.x;
+    // t: the thread's cell in the group of NT threads that takes the band
+    const int nl = A.nl, ml = A.ml, t = threadIdx.x % NT;
     const int r0 = 4 * b;
     const bool pack = A.tout != nullptr && r0 + 3 < nl;
     auto valid = [&](int st) { const int r = band_line<REV>(r0, st); return r >= 0 && r < nl; };

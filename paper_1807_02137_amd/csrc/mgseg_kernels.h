@@ -931,12 +931,15 @@ __global__ void k_sums_dev(const BT *b, int pb, const float *e, int p, int n, in
 }
 
 // ==========================================================================
-// Coarsest-grid solve in one workgroup: outer iterations of Hybrid Smoother 2
-// (freeze + sweeps A, B, C, D), exactly the steps of the multi-kernel path,
+// Outer iterations of Hybrid Smoother 2 (freeze + sweeps A, B, C, D) on a
+// small grid in one workgroup, exactly the steps of the multi-kernel path,
 // with block barriers in place of kernel boundaries and every array of the
 // level staged in LDS; at most `iters` of them, stopping after the first
 // iteration that moves no value by more than rtol times the largest change
-// since the solve began.
+// since the workgroup began (rtol = 0: only once an iteration moves nothing,
+// after which every further one would give the same state).  The coarsest
+// solve and the smoothing of the small grids.  Each wave of the NT threads
+// takes bands of 4 lines (lines of at most 64 cells, one wave each).
 struct CoarseArgs {
     float *P0;                      // state in / out (row pitch prm)
     const float *w, *fit, *lo, *hi; // row-major, pitch prm
@@ -949,7 +952,7 @@ struct CoarseArgs {
     float kap, e2, M, Sigma, rtol;
 };
 #define CO_ARRAYS 18
-#define CO_MAX_CELLS 768
+#define CO_MAX_CELLS 1024
 // dynamic LDS: [two float4 coefficient arrays][CO_ARRAYS float arrays][two label arrays]
 __host__ __device__ inline size_t coarse_lds_bytes(int n, int m)
 {
@@ -1005,6 +1008,8 @@ __global__ void __launch_bounds__(NT) k_coarse_smooth(CoarseArgs G)
     __shared__ uint64_t msk[(NT + 63) / 64];
     extern __shared__ float4 co4[];
     const int n = G.n, m = G.m, N = n * m, tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform, so bands stay scalar
+    constexpr int NWV = NT / 64;
     const bool dev = G.base != nullptr;
     // LDS arrays: row-major with pitch m, column-major with pitch n.  cf / cf_cm: the
     // frozen scaled face coefficients of each layout, (to the next line, to the previous
@@ -1029,9 +1034,12 @@ __global__ void __launch_bounds__(NT) k_coarse_smooth(CoarseArgs G)
         Gv[qr] = dev ? G.G[qg] : 0.0f;
     }
     __syncthreads();
+    // each wave's row buffers, mask word and scan totals
     RunBuf RBr, RBc;
-    RBr.p = rb; RBr.fs = m;
-    RBc.p = rb; RBc.fs = n;
+    RBr.p = rb + wave * 2 * RB_FIELDS * 64; RBr.fs = m;
+    RBc.p = RBr.p; RBc.fs = n;
+    uint64_t *mskw = msk + wave;
+    Ramp *shw = sh + 2 * wave;
     // C: the row-major arguments the freeze evaluates the coefficients with; R / T: the
     // row and column sweeps, which read the stored coefficients
     LineArgs C, R, T;
@@ -1110,19 +1118,23 @@ __global__ void __launch_bounds__(NT) k_coarse_smooth(CoarseArgs G)
         // after a barrier (the bands of one sweep read only its input)
         int lpar = 0;
         R.phi_old = P0; R.phi_new = P1; R.bit = 0;
-        for (int b = 0; b < (n + 3) / 4; b++) sweep_band<NT, false, true, true, NT == 64>(R, b, RBr, msk, sh, lpar);
+        for (int b = wave; b < (n + 3) / 4; b += NWV)
+            sweep_band<64, false, true, true, true>(R, b, RBr, mskw, shw, lpar);
         __syncthreads();
         R.phi_old = P1; R.phi_new = P2; R.bit = 1;
-        for (int b = 0; b < (n + 3) / 4; b++) sweep_band<NT, true, true, true, NT == 64>(R, b, RBr, msk, sh, lpar);
+        for (int b = wave; b < (n + 3) / 4; b += NWV)
+            sweep_band<64, true, true, true, true>(R, b, RBr, mskw, shw, lpar);
         __syncthreads();
         block_transpose<NT>(P2, m, T1, n, n, m);
         __syncthreads();
         // sweeps C and D (columns)
         T.phi_old = T1; T.phi_new = T2; T.bit = 2;
-        for (int b = 0; b < (m + 3) / 4; b++) sweep_band<NT, false, true, true, NT == 64>(T, b, RBc, msk, sh, lpar);
+        for (int b = wave; b < (m + 3) / 4; b += NWV)
+            sweep_band<64, false, true, true, true>(T, b, RBc, mskw, shw, lpar);
         __syncthreads();
         T.phi_old = T2; T.phi_new = T1; T.bit = 3;
-        for (int b = 0; b < (m + 3) / 4; b++) sweep_band<NT, true, true, true, NT == 64>(T, b, RBc, msk, sh, lpar);
+        for (int b = wave; b < (m + 3) / 4; b += NWV)
+            sweep_band<64, true, true, true, true>(T, b, RBc, mskw, shw, lpar);
         __syncthreads();
         float dmax = 0.0f, tot = 0.0f;
         for (int t = tid; t < N; t += NT) {
