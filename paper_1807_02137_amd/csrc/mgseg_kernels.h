@@ -936,8 +936,7 @@ __global__ void k_sums_dev(const BT *b, int pb, const float *e, int p, int n, in
 // with block barriers in place of kernel boundaries and every array of the
 // level staged in LDS; at most `iters` of them, stopping after the first
 // iteration that moves no value by more than rtol times the largest change
-// since the workgroup began (rtol = 0: only once an iteration moves nothing,
-// after which every further one would give the same state).  The coarsest
+// since the workgroup began (rtol = 0: all `iters`, with no test).  The coarsest
 // solve and the smoothing of the small grids.  Each wave of the NT threads
 // takes bands of 4 lines (lines of at most 64 cells, one wave each).
 struct CoarseArgs {
@@ -1143,6 +1142,11 @@ __global__ void __launch_bounds__(NT) k_coarse_smooth(CoarseArgs G)
             dmax = fmaxf(dmax, fabsf(v - P0[t]));
             tot = fmaxf(tot, fabsf(v - E[t]));
             P0[t] = v;
+        }
+        if (!(G.rtol > 0.0f)) {
+            // no stopping test: an iteration that moves nothing leaves every further one the same
+            __syncthreads();
+            continue;
         }
         red[tid] = (double)dmax;
         rdt[tid] = tot;
