@@ -453,7 +453,8 @@ bool lds_level(mgseg_ctx *c, int l)
 
 void smooth(mgseg_ctx *c, int l, int iters)
 {
-    if (iters > 0 && lds_level(c, l) && c->L > 1) {
+    // grids of at most 8 bands each way: one band per wave of 512 threads
+    if (iters > 0 && lds_level(c, l) && c->lev[l].n <= 32 && c->lev[l].m <= 32) {
         // the small grids: all outer iterations in one workgroup, one band per wave
         hipLaunchKernelGGL((k_coarse_smooth<512>), dim3(1), dim3(512), coarse_lds_bytes(c->lev[l].n, c->lev[l].m),
                            c->s, coarse_args(c, l, iters, 0.0));
@@ -479,8 +480,12 @@ void coarsest(mgseg_ctx *c, int l)
         return;
     }
     if (lds_level(c, l)) {
+        // one wave for a grid of one band, else one band per wave of 512 threads
         const CoarseArgs C = coarse_args(c, l, c->p.coarse_iters, c->p.coarse_rtol);
-        hipLaunchKernelGGL((k_coarse_smooth<64>), dim3(1), dim3(64), coarse_lds_bytes(L.n, L.m), c->s, C);
+        if (L.n <= 4 && L.m <= 4)
+            hipLaunchKernelGGL((k_coarse_smooth<64>), dim3(1), dim3(64), coarse_lds_bytes(L.n, L.m), c->s, C);
+        else
+            hipLaunchKernelGGL((k_coarse_smooth<512>), dim3(1), dim3(512), coarse_lds_bytes(L.n, L.m), c->s, C);
         chk(c);
         return;
     }
