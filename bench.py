@@ -306,8 +306,8 @@ def main():
     ap.add_argument("--max-cycles", type=int, default=MAX_CYCLES, help="c4 only: cycle cap of a solve")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU path is a design note, not an implementation.", file=sys.stderr)
+        print(f"bench.py: libmgseg runs on one GPU (asked for --gpus {args.gpus}); "
+              "sharding a solve or a batch over several GPUs is not implemented.", file=sys.stderr)
         sys.exit(2)
 
     if args.calibrate_copy:
