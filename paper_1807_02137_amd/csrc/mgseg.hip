@@ -453,9 +453,8 @@ bool lds_level(mgseg_ctx *c, int l)
 
 void smooth(mgseg_ctx *c, int l, int iters)
 {
-    // grids of at most 8 bands each way: one band per wave of 512 threads
+    // grids of at most 8 bands each way: all outer iterations in one workgroup, one band per wave
     if (iters > 0 && lds_level(c, l) && c->lev[l].n <= 32 && c->lev[l].m <= 32) {
-        // the small grids: all outer iterations in one workgroup, one band per wave
         hipLaunchKernelGGL((k_coarse_smooth<512>), dim3(1), dim3(512), coarse_lds_bytes(c->lev[l].n, c->lev[l].m),
                            c->s, coarse_args(c, l, iters, 0.0));
         chk(c);
@@ -799,7 +798,8 @@ mgseg_status mgseg_setup(const float *image_dev, int n, int m, int pitch, const 
                 return MGSEG_E_HIP;
     }
 
-    // the one-workgroup coarsest solve stages its level in LDS (up to CO_MAX_CELLS cells)
+    // the one-workgroup smoother (coarsest solve, small grids) stages its level in LDS (up to
+    // CO_MAX_CELLS cells)
     if (hipFuncSetAttribute(reinterpret_cast<const void *>(&k_coarse_smooth<64>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)coarse_lds_bytes(CO_MAX_CELLS, 1)) !=
             hipSuccess ||
