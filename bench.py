@@ -27,6 +27,7 @@ HBM_PEAK_GBS = 8000.0
 MFMA_BF16_PEAK_TFLOPS = 2500.0          # dense bf16 matrix-core peak
 WEIGHTS = os.path.join(ROOT, "paper_1807_02137_amd", "weights", "warmstart_512_b32_d4.npz")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_1024_traffic.json")
+MODEL_NAMES = {"sc": "Spencer-Chen", "rc": "Rada-Chen", "cv": "global Chan-Vese (w = 1, no selection term)"}
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1807_02137_amd", "csrc", f)
                   for f in ("mgseg_device.h", "mgseg_kernels.h", "mgseg.hip")]
 
@@ -299,8 +300,8 @@ def main():
     ap.add_argument("--workload", default="c2", choices=("c2", "c3", "c4", "c5"),
                     help="c2: the 1024x1024 solve (default); c3: the 64-image batch of uneven sizes; "
                          "c4: the 8192x8192 solve; c5: the learned warm start on 512x512 held-out images")
-    ap.add_argument("--model", default="sc", choices=("sc", "rc"),
-                    help="c2 only: Spencer-Chen (default) or Rada-Chen")
+    ap.add_argument("--model", default="sc", choices=("sc", "rc", "cv"),
+                    help="c2 only: Spencer-Chen (default), Rada-Chen or the global Chan-Vese workload")
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--c5-images", type=int, default=16)
     ap.add_argument("--max-cycles", type=int, default=MAX_CYCLES, help="c4 only: cycle cap of a solve")
@@ -331,7 +332,8 @@ def main():
     inst = synth.config2(SEED, N)
     img = torch.from_numpy(inst.image).to("cuda")
     model = 1 if args.model == "rc" else 0
-    params = mgseg.Params(levels=LEVELS, model=model)
+    params = (mgseg.chan_vese_params(levels=LEVELS) if args.model == "cv"
+              else mgseg.Params(levels=LEVELS, model=model))
     stream = torch.cuda.current_stream()
 
     def step(profile=False):
@@ -368,7 +370,8 @@ def main():
     if not args.no_cpu_baseline:
         from oracle import Oracle, OracleParams
         tc0 = time.perf_counter()
-        o = Oracle(inst.image, inst.markers, OracleParams(levels=LEVELS, model=model))
+        okw = dict(mgseg.CHAN_VESE) if args.model == "cv" else {"model": model}
+        o = Oracle(inst.image, inst.markers, OracleParams(levels=LEVELS, **okw))
         k = 0
         while True:
             o.vcycle()
@@ -400,7 +403,7 @@ def main():
         "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": "1024x1024 12-ellipse image, 6 markers, "
-                               f"{'Rada-Chen' if model else 'Spencer-Chen'}, FAS V(2,2), "
+                               f"{MODEL_NAMES[args.model]}, FAS V(2,2), "
                                "9 grids, Hybrid Smoother 2, tol 1e-6", "seed": SEED,
                    "parallelism": "single GPU"},
         "cycles_per_solve": cycles,
@@ -408,7 +411,8 @@ def main():
         "converged": all(oks),
         "time_to_tol_ms": wall / args.steps * 1e3,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic() if not model else None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic() if args.model == "sc" else None,
                      "copy_gbs": copy, "frac_of_copy": achieved / copy,
                      "kernel": "k_sweep (finest-grid directional sweep)",
                      "launches": prof_n, "avg_us": avg_ms * 1e3, "bytes_per_launch": prof_bytes},

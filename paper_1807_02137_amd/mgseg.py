@@ -77,6 +77,22 @@ class Params:
         return p
 
 
+# The global two-phase model (Chan-Vese, eq. cv / cvls) that the paper's
+# methods also apply to, as a setting of the selective model: the edge weight
+# w = g = 1/(1 + beta |grad|^2) is 1 everywhere at beta = 0, and theta = 0
+# drops the selection (distance) term.  The paper gives no weights for it; mu =
+# 0.05 at the default lambdas keeps the two-phase partition of a clean
+# two-intensity image (at mu = 0.5 the one-phase state has the lower energy on
+# such images of a few objects).
+CHAN_VESE = {"model": 0, "beta": 0.0, "theta": 0.0, "mu": 0.05}
+
+
+def chan_vese_params(**kw) -> Params:
+    """Params of the global Chan-Vese workload (Spencer-Chen with w = 1 and no
+    selection term); keyword arguments override."""
+    return Params(**{**CHAN_VESE, **kw})
+
+
 _lib = None
 
 

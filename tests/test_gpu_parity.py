@@ -153,6 +153,32 @@ def test_solve_parity_rada_chen(seed):
     s.close()
 
 
+@pytest.mark.parametrize("seed", [1000, 1001])
+def test_solve_parity_chan_vese(seed):
+    """The global Chan-Vese workload (edge weight 1, no selection term) on the
+    same kernels: the same end-to-end bar as the selective model."""
+    say("case solve chan-vese seed", seed)
+    inst = synth.config1(seed)
+    s = mgseg.Solver(inst.image, inst.markers, mgseg.chan_vese_params(levels=6))
+    o = Oracle(inst.image, inst.markers, OracleParams(levels=6, beta=0.0, theta=0.0, mu=0.05))
+    hg = []
+    for _ in range(40):
+        hg.append(s.vcycle())
+        if hg[-1] <= 1e-6:
+            break
+    k, hist = o.solve(1e-6, 40)
+    pg, po = s.phi().cpu().numpy(), o.get("phi")
+    agree = (pg > 0) == (po > 0)
+    flips = int((~agree).sum())
+    dmax = float(np.abs(pg - po)[agree].max())
+    say(f"gpu {len(hg)} cycles rel {hg[-1]:.2e}; oracle {k} cycles; flips {flips} max|dphi| {dmax:.3e}; "
+        f"foreground {(pg > 0).mean():.3f}")
+    assert hg[-1] <= 1e-6 and k > 0
+    assert flips <= max(1, int(1e-4 * pg.size))
+    assert dmax <= 1e-4
+    s.close()
+
+
 @pytest.mark.parametrize("shape", [(40, 72, 3), (24, 200, 3), (16, 16, 5), (96, 160, 5)])
 def test_solve_parity_ragged_shapes(shape):
     """Non-square grids whose lines are not multiples of the 64-lane wave, and a

@@ -412,6 +412,42 @@ def test_fas_fixed_point_agrees_with_time_marching():
     assert np.abs(o.get("phi") - phi_mg).max() <= 1e-8
 
 
+# The global two-phase model (Chan-Vese, eq. cv / cvls) as a setting of the selective one:
+# w = g = 1 at beta = 0 and no selection term at theta = 0.
+CHAN_VESE = dict(beta=0.0, theta=0.0, mu=0.05)
+
+
+def _two_phase(lo, hi):
+    img = np.full((48, 48), lo)
+    img[12:36, 10:38] = hi
+    rect = np.zeros((48, 48), bool)
+    rect[12:36, 10:38] = True
+    return img, rect
+
+
+def test_chan_vese_two_phase_partition_and_reversal_symmetry():
+    """Chan-Vese on a clean two-intensity image: the edge weight is 1 (closed form
+    of g at beta = 0), the solve ends on the textbook partition (the rectangle), and
+    the model is symmetric under intensity reversal z -> 1 - z with lambda1 = lambda2
+    (the fit terms are unchanged when c1, c2 -> 1 - c1, 1 - c2): the same phi, and
+    c1, c2 reflected about 1/2."""
+    mk = np.array([[24.5, 24.5], [20.5, 20.5], [28.5, 30.5]])
+    img, rect = _two_phase(0.2, 0.8)
+    a = Oracle(img, mk, OracleParams(levels=4, **CHAN_VESE))
+    assert np.array_equal(a.get("w"), np.ones_like(img))
+    k, hist = a.solve(1e-8, 80)
+    assert k > 0
+    pa, sa = a.get("phi"), a.scalars()
+    assert np.array_equal(pa > 0, rect)
+    assert 0.6 < sa["c1"] < 0.8 and 0.2 < sa["c2"] < 0.3
+    b = Oracle(1.0 - img, mk, OracleParams(levels=4, **CHAN_VESE))
+    k2, _ = b.solve(1e-8, 80)
+    pb, sb = b.get("phi"), b.scalars()
+    assert k2 == k
+    assert np.abs(pa - pb).max() <= 1e-9
+    assert abs(sa["c1"] + sb["c1"] - 1.0) <= 1e-9 and abs(sa["c2"] + sb["c2"] - 1.0) <= 1e-9
+
+
 def test_selectivity_gate_config1():
     """Calibration gate of the selection weight: the segmentation of config-1 inputs picks
     the marked object (IoU >= 0.9 on at least 90 % of seeds)."""
