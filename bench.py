@@ -302,6 +302,9 @@ def main():
                          "c4: the 8192x8192 solve; c5: the learned warm start on 512x512 held-out images")
     ap.add_argument("--model", default="sc", choices=("sc", "rc", "cv"),
                     help="c2 only: Spencer-Chen (default), Rada-Chen or the global Chan-Vese workload")
+    ap.add_argument("--smoother", default="hs2", choices=("hs2", "gslex"),
+                    help="c2 only: Hybrid Smoother 2 (default, the paper's Algorithm 3) or GSLEX-I "
+                         "(its Algorithm 1 with a standard smoother)")
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--c5-images", type=int, default=16)
     ap.add_argument("--max-cycles", type=int, default=MAX_CYCLES, help="c4 only: cycle cap of a solve")
@@ -332,8 +335,9 @@ def main():
     inst = synth.config2(SEED, N)
     img = torch.from_numpy(inst.image).to("cuda")
     model = 1 if args.model == "rc" else 0
-    params = (mgseg.chan_vese_params(levels=LEVELS) if args.model == "cv"
-              else mgseg.Params(levels=LEVELS, model=model))
+    smoother = 1 if args.smoother == "gslex" else 0
+    params = (mgseg.chan_vese_params(levels=LEVELS, smoother=smoother) if args.model == "cv"
+              else mgseg.Params(levels=LEVELS, model=model, smoother=smoother))
     stream = torch.cuda.current_stream()
 
     def step(profile=False):
@@ -371,6 +375,7 @@ def main():
         from oracle import Oracle, OracleParams
         tc0 = time.perf_counter()
         okw = dict(mgseg.CHAN_VESE) if args.model == "cv" else {"model": model}
+        okw["smoother"] = smoother
         o = Oracle(inst.image, inst.markers, OracleParams(levels=LEVELS, **okw))
         k = 0
         while True:
@@ -404,7 +409,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "1024x1024 12-ellipse image, 6 markers, "
                                f"{MODEL_NAMES[args.model]}, FAS V(2,2), "
-                               "9 grids, Hybrid Smoother 2, tol 1e-6", "seed": SEED,
+                               f"9 grids, {'GSLEX-I' if smoother else 'Hybrid Smoother 2'}, tol 1e-6",
+                   "seed": SEED,
                    "parallelism": "single GPU"},
         "cycles_per_solve": cycles,
         "rel_res": rels,
@@ -412,7 +418,7 @@ def main():
         "time_to_tol_ms": wall / args.steps * 1e3,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic() if args.model == "sc" else None,
+                     "traffic": measured_traffic() if args.model == "sc" and not smoother else None,
                      "copy_gbs": copy, "frac_of_copy": achieved / copy,
                      "kernel": "k_sweep (finest-grid directional sweep)",
                      "launches": prof_n, "avg_us": avg_ms * 1e3, "bytes_per_launch": prof_bytes},

@@ -76,6 +76,11 @@ typedef struct {
     double coarse_rtol;     /* coarsest solve stops once an outer iteration moves no */
                             /* value by more than coarse_rtol times the largest      */
                             /* total change since that solve began                   */
+    int32_t smoother;       /* 0: Hybrid Smoother 2 (Sec. 4.3, the paper's Algorithm */
+                            /* 3); 1: GSLEX-I (Sec. 3.2), one point Gauss-Seidel     */
+                            /* pass per outer iteration in the rows' four-class      */
+                            /* order, the standard smoother of the paper's Algorithm */
+                            /* 1; default 0                                          */
 } mgseg_params;
 
 typedef struct {

@@ -759,10 +759,16 @@ static void freeze(or_ctx *c, int l)
 }
 
 /* GSLEX-I: lexicographic point Gauss-Seidel with frozen coefficients        */
+/* (Sec. 3.2), every pixel a point update in the order of sweep A: rows top  */
+/* to bottom, each left to right (order = 0), or the rows in the four        */
+/* classes of the parallel line order, each row left to right (order = 1).   */
 static void gslex_sweep(or_ctx *c, int l)
 {
     or_level *L = &c->lev[l];
-    for (size_t q = 0; q < (size_t)L->n * L->m; q++) point_update(c, L, q);
+    const int n = L->n, m = L->m;
+    for (int k = 0; k < (c->p.order == 0 ? 1 : 4); k++)
+        for (int i = (c->p.order == 0 ? 0 : k); i < n; i += (c->p.order == 0 ? 1 : 4))
+            for (int j = 0; j < m; j++) point_update(c, L, (size_t)i * m + j);
 }
 
 static void smooth(or_ctx *c, int l, int iters)

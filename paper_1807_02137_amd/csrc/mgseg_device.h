@@ -87,6 +87,10 @@ __device__ __forceinline__ Ramp ramp_comp(const Ramp &g, const Ramp &f)
     return o;
 }
 
+// a label bit no cell carries (the labels use bits 0-3, one per sweep): a
+// sweep with it has no starred cell, every cell a point update
+#define LAB_NONE 4
+
 // --------------------------------------------------------------------------
 // Line-sweep arguments.  All arrays are in the layout of the sweep; `lab`
 // holds one byte per cell with bit s set when the cell is starred in sweep

@@ -949,6 +949,7 @@ struct CoarseArgs {
     double h2, A1, nu, eps;
     int n, m, prm, iters, scaled;
     float kap, e2, M, Sigma, rtol;
+    int smoother;                   // 1: GSLEX-I (sweep A's order, every cell a point) in place of HS2
 };
 #define CO_ARRAYS 18
 #define CO_MAX_CELLS 1024
@@ -1116,25 +1117,31 @@ __global__ void __launch_bounds__(NT) k_coarse_smooth(CoarseArgs G)
         // sweeps A and B (rows); the sweep output is read by the next sweep
         // after a barrier (the bands of one sweep read only its input)
         int lpar = 0;
-        R.phi_old = P0; R.phi_new = P1; R.bit = 0;
+        R.phi_old = P0; R.phi_new = P1; R.bit = G.smoother == 1 ? LAB_NONE : 0;
         for (int b = wave; b < (n + 3) / 4; b += NWV)
             sweep_band<64, false, true, true, true>(R, b, RBr, mskw, shw, lpar);
         __syncthreads();
-        R.phi_old = P1; R.phi_new = P2; R.bit = 1;
-        for (int b = wave; b < (n + 3) / 4; b += NWV)
-            sweep_band<64, true, true, true, true>(R, b, RBr, mskw, shw, lpar);
-        __syncthreads();
-        block_transpose<NT>(P2, m, T1, n, n, m);
-        __syncthreads();
-        // sweeps C and D (columns)
-        T.phi_old = T1; T.phi_new = T2; T.bit = 2;
-        for (int b = wave; b < (m + 3) / 4; b += NWV)
-            sweep_band<64, false, true, true, true>(T, b, RBc, mskw, shw, lpar);
-        __syncthreads();
-        T.phi_old = T2; T.phi_new = T1; T.bit = 3;
-        for (int b = wave; b < (m + 3) / 4; b += NWV)
-            sweep_band<64, true, true, true, true>(T, b, RBc, mskw, shw, lpar);
-        __syncthreads();
+        if (G.smoother == 1) {
+            // GSLEX-I: the pass of sweep A is the whole outer iteration
+            block_transpose<NT>(P1, m, T1, n, n, m);
+            __syncthreads();
+        } else {
+            R.phi_old = P1; R.phi_new = P2; R.bit = 1;
+            for (int b = wave; b < (n + 3) / 4; b += NWV)
+                sweep_band<64, true, true, true, true>(R, b, RBr, mskw, shw, lpar);
+            __syncthreads();
+            block_transpose<NT>(P2, m, T1, n, n, m);
+            __syncthreads();
+            // sweeps C and D (columns)
+            T.phi_old = T1; T.phi_new = T2; T.bit = 2;
+            for (int b = wave; b < (m + 3) / 4; b += NWV)
+                sweep_band<64, false, true, true, true>(T, b, RBc, mskw, shw, lpar);
+            __syncthreads();
+            T.phi_old = T2; T.phi_new = T1; T.bit = 3;
+            for (int b = wave; b < (m + 3) / 4; b += NWV)
+                sweep_band<64, true, true, true, true>(T, b, RBc, mskw, shw, lpar);
+            __syncthreads();
+        }
         float dmax = 0.0f, tot = 0.0f;
         for (int t = tid; t < N; t += NT) {
             const int i = t / m, j = t % m;

@@ -38,7 +38,7 @@ def test_params_struct_matches(lib):
     lib.mgseg_params_default(C.byref(p))
     assert p.struct_size == C.sizeof(mgseg._Params)
     d = mgseg.Params()
-    for f in ("mu", "lambda1", "theta", "M", "Sigma", "eps_tv_px", "nu1", "nu2", "coarse_iters"):
+    for f in ("mu", "lambda1", "theta", "M", "Sigma", "eps_tv_px", "nu1", "nu2", "coarse_iters", "smoother"):
         assert getattr(p, f) == getattr(d, f), f
 
 

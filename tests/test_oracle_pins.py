@@ -347,6 +347,22 @@ def test_smoother_fixed_point_is_projected_solution():
     assert o.res_norm() <= 1e-10 * r0
 
 
+@pytest.mark.parametrize("order", [0, 1])
+def test_gslex_fixed_point_is_hybrid_smoother_2_fixed_point(order):
+    """GSLEX-I (Sec. 3.2; lexicographic rows, or the rows in the four classes)
+    iterated alone also drives the projected residual to rounding level, and ends
+    where Hybrid Smoother 2 ends: both solve the same box-constrained problem."""
+    inst, a = _tiny(seed=11, n=24, m=24, smoother=1, order=order)
+    r0 = a.res_norm()
+    for _ in range(30):
+        a.smooth(5, 0)
+    assert a.res_norm() <= 1e-10 * r0
+    _, b = _tiny(seed=11, n=24, m=24, smoother=0, order=order)
+    for _ in range(30):
+        b.smooth(5, 0)
+    assert np.abs(a.get("phi") - b.get("phi")).max() <= 1e-6
+
+
 def test_fas_converges_and_residual_decreases():
     """The cycle converges; each c1, c2 refresh (Sec. 5) moves the discrete system, so the
     history may rise while the region means settle, and decreases once they have."""
