@@ -81,6 +81,12 @@ typedef struct {
                             /* pass per outer iteration in the rows' four-class      */
                             /* order, the standard smoother of the paper's Algorithm */
                             /* 1; default 0                                          */
+    int32_t run_max;        /* superpixels of Hybrid Smoother 2 (Sec. 4.3, Fig. 3):  */
+                            /* 0 (default) solves every maximal run of starred cells */
+                            /* on a line as one unit, as the paper does (lines       */
+                            /* longer than 1024 cells cut runs at 1024 cells); k > 0 */
+                            /* cuts longer runs into ceil(len / k) near-equal pieces */
+                            /* (3: every unit in closed form); negative: MGSEG_E_ARG */
 } mgseg_params;
 
 typedef struct {

@@ -62,7 +62,7 @@ class OracleParams:
     smoother: int = 0         # 0 Hybrid Smoother 2, 1 GSLEX-I
     obstacle: int = 1         # 1 coarse corrections bounded by the fine slack
     scaled: int = 1           # 1 each row divided by delta_eps(psi_ij) > 0
-    run_max: int = 3          # 0 maximal runs, else runs cut into near-equal pieces of at most run_max
+    run_max: int = 0          # 0 maximal runs (Sec. 4.3), else runs cut into near-equal pieces of at most run_max
 
     def to_c(self) -> _Params:
         p = _Params()

@@ -957,7 +957,7 @@ void or_params_default(or_params *p)
     p->model = 0; p->mu = 0.5; p->lambda1 = 6.5025; p->lambda2 = 6.5025;
     p->theta = 4.0; p->nu = 1.0; p->eps = 1.0; p->eps_tv_px = 1.0; p->beta = 16384.0;
     p->sigma_g = 1.0; p->sigma_d = 0.1; p->Sigma = 2.0; p->M = 4.0;
-    p->nu1 = 2; p->nu2 = 2; p->levels = 1; p->coarse_iters = 10; p->coarse_rtol = 1e-4; p->order = 1; p->smoother = 0; p->obstacle = 1; p->scaled = 1; p->run_max = 3;
+    p->nu1 = 2; p->nu2 = 2; p->levels = 1; p->coarse_iters = 10; p->coarse_rtol = 1e-4; p->order = 1; p->smoother = 0; p->obstacle = 1; p->scaled = 1; p->run_max = 0;
 }
 
 or_ctx *or_create(const double *z, int n, int m, const double *markers, int k, const or_params *p)

@@ -272,7 +272,7 @@ void launch_sweep(mgseg_ctx *c, int l, int s, const float *phi_old, float *phi_n
     A.nl = cm ? L.m : L.n;
     A.ml = cm ? L.n : L.m;
     A.kap = (float)(c->p.mu / L.h); A.e2 = lev_e2(c, l); A.M = (float)c->p.M; A.eps = (float)c->p.eps;
-    A.bit = bit < 0 ? s : bit; A.scaled = c->p.scaled;
+    A.bit = bit < 0 ? s : bit; A.scaled = c->p.scaled; A.run_max = c->p.run_max;
     bool rev = (s == 1 || s == 3);
     int bands = (A.nl + 3) / 4;
     int ml = A.ml;
@@ -452,6 +452,7 @@ CoarseArgs coarse_args(mgseg_ctx *c, int l, int iters, double rtol)
     C.kap = (float)(c->p.mu / L.h); C.e2 = lev_e2(c, l); C.M = (float)c->p.M; C.Sigma = (float)c->p.Sigma;
     C.rtol = (float)rtol;
     C.smoother = c->p.smoother;
+    C.run_max = c->p.run_max;
     return C;
 }
 // a coarse grid the one-workgroup smoother holds in LDS
@@ -734,7 +735,7 @@ void mgseg_params_default(mgseg_params *p)
     p->mu = 0.5; p->lambda1 = 6.5025; p->lambda2 = 6.5025; p->theta = 4.0; p->nu = 1.0;
     p->eps = 1.0; p->eps_tv_px = 1.0; p->beta = 16384.0; p->sigma_g = 1.0; p->sigma_d = 0.1;
     p->Sigma = 2.0; p->M = 4.0; p->nu1 = 2; p->nu2 = 2; p->levels = 0; p->coarse_iters = 10;
-    p->mixed_precision = 1; p->scaled = 1; p->coarse_rtol = 1e-4; p->smoother = 0;
+    p->mixed_precision = 1; p->scaled = 1; p->coarse_rtol = 1e-4; p->smoother = 0; p->run_max = 0;
 }
 
 const char *mgseg_strerror(mgseg_status s)
@@ -774,7 +775,7 @@ mgseg_status mgseg_setup(const float *image_dev, int n, int m, int pitch, const 
     if (p->struct_size != sizeof(mgseg_params)) return MGSEG_E_ARG;
     if (p->model == MGSEG_RADA_CHEN && k < 3) return MGSEG_E_ARG;   // the marker polygon needs an area (A1 > 0)
     if (p->nu1 < 0 || p->nu2 < 0 || p->coarse_iters < 0 || !(p->coarse_rtol >= 0.0) || !(p->M > 0.0) || !(p->eps > 0.0) || p->levels < 0 ||
-        p->levels > MAXLEV || (p->smoother != 0 && p->smoother != 1))
+        p->levels > MAXLEV || (p->smoother != 0 && p->smoother != 1) || p->run_max < 0)
         return MGSEG_E_ARG;
     for (int t = 0; t < 2 * k; t++)
         if (!std::isfinite(markers_host[t])) return MGSEG_E_ARG;

@@ -109,25 +109,26 @@ struct LineArgs {
     int pitch, lpitch, nl, ml;
     float kap, e2, M, eps;
     int bit, scaled;
+    int run_max;                        // 0: maximal runs; else runs cut into pieces of at most run_max
 };
 
 // --------------------------------------------------------------------------
 // Collective units of Hybrid Smoother 2 (Sec. 4.3, Fig. 3).  A maximal run
-// of starred cells along the line is solved as one box-constrained
-// tridiagonal system; a single starred cell takes the next cell of the line
-// into its unit (a single starred cell at the line end stays alone).  Runs
-// longer than RUN_MAX are cut into ceil(len / RUN_MAX) pieces of near-equal
-// length (the longer pieces first), each solved as its own unit, so that
-// every unit has a closed-form solution.
-#define RUN_MAX 3
-
+// of starred cells along the line (the paper's superpixel) is solved as one
+// box-constrained tridiagonal system; a single starred cell takes the next
+// cell of the line into its unit (a single starred cell at the line end
+// stays alone).  With LineArgs::run_max > 0 runs longer than run_max are cut
+// into ceil(len / run_max) pieces of near-equal length (the longer pieces
+// first), each solved as its own unit; lines longer than one workgroup cut
+// runs at the workgroup size (their row ring holds two rounds).
+//
 // Row buffer of the line being swept, indexed by visit position p:
 //   a y_{p-1} - y_p + c y_{p+1} = r  (a = NaN marks S = 0), box [lo, hi],
-// x = old value; y = new value of a unit cell (the long-line ring only).  In
-// LDS: two buffers of the whole line (RB_FIELDS fields each) for lines of
+// x = old value.  Units of more than three cells also use P, Q (their
+// elimination, then scratch of the exact solve) and O (their new values).
+// In LDS: two buffers of the whole line (RB_FIELDS fields each) for lines of
 // one workgroup, a ring of two rounds (RF_COUNT fields) for longer lines.
-enum { RF_A = 0, RF_C, RF_R, RF_LO, RF_HI, RF_X, RF_Y, RF_COUNT };
-enum { RB_FIELDS = RF_Y };
+enum { RF_A = 0, RF_C, RF_R, RF_LO, RF_HI, RF_X, RF_P, RF_Q, RF_O, RB_FIELDS };
 
 struct RunBuf {
     float *p;
@@ -147,15 +148,14 @@ __host__ __device__ inline int sweep_mask_words(int ml) { return (ml + 63) / 64;
 
 // Row buffer of lines longer than one workgroup: a ring of SLOTS positions
 // (two rounds of the line).  Only unit cells are stored; the successor's old
-// value sits beside each cell (RG_S), and a unit's new values overwrite its
-// RF_A entries once the unit has read its rows (only the unit reads them).
-enum { RG_S = RF_Y };
+// value sits beside each cell (RG_S), and a unit's new values go to RF_O.
+enum { RG_S = RB_FIELDS, RF_COUNT };
 template <int SLOTS>
 struct RingBuf {
     float *p;
     __device__ __forceinline__ float &at(int f, int q) const { return p[f * SLOTS + (q & (SLOTS - 1))]; }
     __device__ __forceinline__ float sig_after(int last, int) const { return at(RG_S, last); }
-    __device__ __forceinline__ float &y(int q) const { return at(RF_A, q); }
+    __device__ __forceinline__ float &y(int q) const { return at(RF_O, q); }
 };
 
 // Units of one or two cells in closed form.  The box-constrained problem of
@@ -330,26 +330,193 @@ __device__ __forceinline__ int run_last(const uint64_t *msk, int nw, int p)
     }
     return (wi << 6) + __builtin_ctzll(z) - 1;
 }
-// unit of the starred position p of the maximal starred run t0..e: first position ps and length L
-__device__ __forceinline__ void unit_of_run(int t0, int e, int ml, int p, int &ps, int &L)
+// unit of the starred position p of the maximal starred run t0..e: first
+// position ps and length L; cap > 0 cuts runs longer than cap into
+// ceil(len / cap) near-equal pieces, the longer ones first
+__device__ __forceinline__ void unit_of_run(int t0, int e, int ml, int p, int cap, int &ps, int &L)
 {
     const int rl = e - t0 + 1;
     if (rl == 1) { ps = p; L = p + 1 < ml ? 2 : 1; return; }
-    if (rl <= RUN_MAX) { ps = t0; L = rl; return; }
-    const int np = (rl + RUN_MAX - 1) / RUN_MAX, base = rl / np, extra = rl % np;
+    if (cap <= 0 || rl <= cap) { ps = t0; L = rl; return; }
+    const int np = (rl + cap - 1) / cap, base = rl / np, extra = rl % np;
     const int o = p - t0, big = extra * (base + 1);
     if (o < big) { ps = t0 + (o / (base + 1)) * (base + 1); L = base + 1; }
     else { ps = t0 + big + ((o - big) / base) * base; L = base; }
 }
-__device__ __forceinline__ void unit_of(const uint64_t *msk, int nw, int ml, int p, int &ps, int &L)
+__device__ __forceinline__ void unit_of(const uint64_t *msk, int nw, int ml, int p, int cap, int &ps, int &L)
 {
-    unit_of_run(run_first(msk, p), run_last(msk, nw, p), ml, p, ps, L);
+    unit_of_run(run_first(msk, p), run_last(msk, nw, p), ml, p, cap, ps, L);
 }
 // the same on a line of at most 64 cells whose starred mask is the word bm
-__device__ __forceinline__ void unit_of1(uint64_t bm, int ml, int p, int &ps, int &L)
+__device__ __forceinline__ void unit_of1(uint64_t bm, int ml, int p, int cap, int &ps, int &L)
 {
     const uint64_t zb = ~bm & ((1ull << p) - 1ull), za = ~bm & ~((2ull << p) - 1ull);
-    unit_of_run(zb ? 64 - __builtin_clzll(zb) : 0, za ? __builtin_ctzll(za) - 1 : 63, ml, p, ps, L);
+    unit_of_run(zb ? 64 - __builtin_clzll(zb) : 0, za ? __builtin_ctzll(za) - 1 : 63, ml, p, cap, ps, L);
+}
+// a maximal starred run of at least four cells in the mask words w0 (then
+// w1, the next word): units of more than three cells are possible
+__device__ __forceinline__ bool has_run4(uint64_t w0, uint64_t w1)
+{
+    const uint64_t s1 = (w0 >> 1) | (w1 << 63), s2 = (w0 >> 2) | (w1 << 62), s3 = (w0 >> 3) | (w1 << 61);
+    return (w0 & s1 & s2 & s3) != 0ull;
+}
+// the cut of the sweep's runs: units of more than three cells exist unless
+// runs are cut into pieces of at most three
+__device__ __forceinline__ bool long_units_possible(const LineArgs &A)
+{
+    return A.bit != LAB_NONE && !(A.run_max >= 1 && A.run_max <= 3);
+}
+
+// Units of more than three cells.  Rows k = 0..L-1 of the unit (positions
+// ps + k):  y_k = a_k y_{k-1} + c_k y_{k+1} - r_k  on [lo_k, hi_k], with
+// y_{-1} = x (the entering value) and y_L = s (the successor's old value).
+//
+// Chain ramp.  Eliminating the unit from its far end without the box gives
+// y_k = P_k y_{k-1} + Q_k (P_{L-1} = a, Q_{L-1} = c s - r, then
+// P_k = a_k / (1 - c_k P_{k+1}), Q_k = (c_k Q_{k+1} - r_k) / (1 - c_k P_{k+1})).
+// For the box-constrained unit the last value is a monotone function of x
+// that is affine (slope P_0 ... P_{L-1}) where no cell is at a bound and
+// constant elsewhere, because a cell at a bound separates the cells after it
+// from x.  Writing Z_k(t) = clip(P_k t + Q_k, lo_k, hi_k), the composition
+// Z_{L-1} o ... o Z_0 is such a clipped ramp, and it has the right limits:
+// as x -> -inf (+inf) cell 0 goes to lo_0 (hi_0) and the composition of the
+// remaining Z's gives the tail's last value with cell 0 held there (the same
+// argument one cell further on).  So the chain ramp is that composition,
+// with no iteration and no case analysis.  (A cell with a_k = 0 is the limit
+// of small a_k, where both sides are continuous.)
+//
+// Values at x.  The forward substitution y_k = Z_k(y_{k-1}) is exact where no
+// cell after k is held at a bound by the true solution; it is checked row by
+// row (every cell must be the projection of its own row).  Where the check
+// fails, a primal-dual active-set iteration finishes the solve: cells held at
+// a bound are fixed there, the free chains between them are solved exactly
+// (one forward elimination and one back substitution over the unit), free
+// cells that leave the box are held, held cells whose row points back into
+// the box are released, until no cell changes (Hintermueller, Ito & Kunisch:
+// finite for M-matrices).  One thread takes the whole unit.
+//
+// A unit with a cell of S = 0 (a = NaN) or a vanishing pivot keeps its old
+// values; RF_P at its last position is then NaN.
+template <class Buf>
+__device__ __forceinline__ Ramp long_ramp(const Buf &B, int ps, int L, int ml)
+{
+    const int last = ps + L - 1;
+    float Pn = 0.0f, Qn = B.sig_after(last, ml);
+    Ramp T = ramp_id();
+    #pragma nounroll
+    for (int q = last; q >= ps; q--) {
+        const float a = B.at(RF_A, q), c = B.at(RF_C, q), r = B.at(RF_R, q);
+        const float den = 1.0f - c * Pn;
+        if (isnan(a) || !(den > 0.0f)) {
+            B.at(RF_P, last) = __builtin_nanf("");
+            const float yo = B.at(RF_X, last);
+            return Ramp{0.0f, yo, yo, yo};
+        }
+        const float inv = 1.0f / den;
+        Pn = a * inv;
+        Qn = fmaf(c, Qn, -r) * inv;
+        B.at(RF_P, q) = Pn;
+        B.at(RF_Q, q) = Qn;
+        T = ramp_comp(T, Ramp{Pn, Qn, B.at(RF_LO, q), B.at(RF_HI, q)});
+    }
+    return T;
+}
+// the unit's row k evaluated at its neighbours' new values (the value the cell
+// would take free of its box); mag: the size of its terms, the scale of its rounding
+template <class Buf>
+__device__ __forceinline__ float long_row(const Buf &B, int q, int ps, int last, float x, float s, float &mag)
+{
+    const float yp = q == ps ? x : B.at(RF_O, q - 1);
+    const float yn = q == last ? s : B.at(RF_O, q + 1);
+    const float ta = B.at(RF_A, q) * yp, tc = B.at(RF_C, q) * yn, r = B.at(RF_R, q);
+    mag = fabsf(ta) + fabsf(tc) + fabsf(r);
+    return (ta + tc) - r;
+}
+template <class Buf>
+__device__ __forceinline__ void long_solve(const Buf &B, int ps, int L, int ml, float x)
+{
+    const int last = ps + L - 1;
+    if (isnan(B.at(RF_P, last))) {
+        #pragma nounroll
+        for (int q = ps; q <= last; q++) B.at(RF_O, q) = B.at(RF_X, q);
+        return;
+    }
+    const float s = B.sig_after(last, ml);
+    float y = x;
+    #pragma nounroll
+    for (int q = ps; q <= last; q++) {
+        y = mg_clip(fmaf(B.at(RF_P, q), y, B.at(RF_Q, q)), B.at(RF_LO, q), B.at(RF_HI, q));
+        B.at(RF_O, q) = y;
+    }
+    // every cell at the projection of its own row (to rounding)?
+    bool good = true;
+    #pragma nounroll
+    for (int q = ps; q <= last && good; q++) {
+        float mag;
+        const float v = long_row(B, q, ps, last, x, s, mag);
+        const float pv = mg_clip(v, B.at(RF_LO, q), B.at(RF_HI, q));
+        good = fabsf(pv - B.at(RF_O, q)) <= 1e-5f * mag;
+    }
+    if (good) return;
+    // active-set iteration.  RF_P holds the held state between passes (-1 held
+    // at lo, -2 held at hi, else free) and the elimination factor E >= 0 of a
+    // free cell within a pass; RF_Q the elimination's F (a held cell: its bound).
+    #pragma nounroll
+    for (int q = ps; q <= last; q++) {
+        const float v = B.at(RF_O, q);
+        B.at(RF_P, q) = v <= B.at(RF_LO, q) ? -1.0f : (v >= B.at(RF_HI, q) ? -2.0f : 0.0f);
+    }
+    #pragma nounroll
+    for (int it = 0; it < L + 8; it++) {
+        // forward elimination of the free chains: y_q = E_q y_{q+1} + F_q
+        float Ep = 0.0f, Fp = x;
+        #pragma nounroll
+        for (int q = ps; q <= last; q++) {
+            const float st = B.at(RF_P, q);
+            if (st < 0.0f) {
+                Ep = 0.0f;
+                Fp = st == -1.0f ? B.at(RF_LO, q) : B.at(RF_HI, q);
+            } else {
+                const float a = B.at(RF_A, q);
+                const float inv = 1.0f / (1.0f - a * Ep);
+                Ep = B.at(RF_C, q) * inv;
+                Fp = fmaf(a, Fp, -B.at(RF_R, q)) * inv;
+                B.at(RF_P, q) = Ep;
+            }
+            B.at(RF_Q, q) = Fp;
+        }
+        float yn = s;
+        #pragma nounroll
+        for (int q = last; q >= ps; q--) {
+            const float e = B.at(RF_P, q);
+            yn = e < 0.0f ? B.at(RF_Q, q) : fmaf(e, yn, B.at(RF_Q, q));
+            B.at(RF_O, q) = yn;
+        }
+        // new held state: free cells outside the box are held; a held cell is
+        // released where its row points back into the box (beyond rounding)
+        bool changed = false;
+        #pragma nounroll
+        for (int q = ps; q <= last; q++) {
+            const float lo = B.at(RF_LO, q), hi = B.at(RF_HI, q), yv = B.at(RF_O, q), was = B.at(RF_P, q);
+            float st = 0.0f;
+            if (was < 0.0f) {
+                float mag;
+                const float v = long_row(B, q, ps, last, x, s, mag);
+                const float tol = 2e-6f * (mag + fabsf(was == -1.0f ? lo : hi));
+                if (was == -1.0f) st = v > lo + tol ? 0.0f : -1.0f;
+                else st = v < hi - tol ? 0.0f : -2.0f;
+            } else if (yv < lo) {
+                st = -1.0f;
+            } else if (yv > hi) {
+                st = -2.0f;
+            }
+            changed |= (st < 0.0f) != (was < 0.0f);
+            B.at(RF_P, q) = st;
+        }
+        if (!changed) break;
+    }
+    #pragma nounroll
+    for (int q = ps; q <= last; q++) B.at(RF_O, q) = mg_clip(B.at(RF_O, q), B.at(RF_LO, q), B.at(RF_HI, q));
 }
 
 // --------------------------------------------------------------------------
@@ -621,15 +788,19 @@ __device__ __forceinline__ float sweep_line(const LineArgs &A, int r, const RunB
     // a line of one wave keeps its starred mask in the ballot word (bm)
     const unsigned long long bm = __ballot(s0);
     if (NT > 64 && lane == 0 && wave * 64 < ml) msk[wave] = bm;
-    bool any_star;
+    bool any_star, any_long = false;
+    const bool lmode = long_units_possible(A);
     if (NT == 64) {
         any_star = bm != 0ull;
+        any_long = lmode && has_run4(bm, 0ull);
         if (WS) wave_lds_sync();
         else __syncthreads();
     } else {
         // one barrier makes the rows and masks visible; a line has a starred cell iff a mask word is non-zero
         __syncthreads();
-        any_star = __ballot(lane < nw && msk[lane] != 0ull) != 0ull;
+        const uint64_t w0 = lane < nw ? msk[lane] : 0ull;
+        any_star = __ballot(w0 != 0ull) != 0ull;
+        if (lmode) any_long = __ballot(has_run4(w0, lane + 1 < nw ? msk[lane + 1] : 0ull)) != 0ull;
     }
 
     // phase 2: the cell's unit (ps, L; L = 0: a point); the unit's chain ramp at its last cell
@@ -638,12 +809,12 @@ __device__ __forceinline__ float sweep_line(const LineArgs &A, int r, const RunB
     if (in) {
         if (any_star) {
             if (NT == 64) {
-                if (s0) unit_of1(bm, ml, p, ps, Lu);
+                if (s0) unit_of1(bm, ml, p, A.run_max, ps, Lu);
                 else if (p >= 1 && ((bm >> (p - 1)) & 1ull) && (p < 2 || !((bm >> (p - 2)) & 1ull))) {
                     ps = p - 1; Lu = 2;
                 }
             } else {
-                if (s0) unit_of(msk, nw, ml, p, ps, Lu);
+                if (s0) unit_of(msk, nw, ml, p, A.run_max, ps, Lu);
                 else if (p >= 1 && mask_bit(msk, p - 1) && (p < 2 || !mask_bit(msk, p - 2))) { ps = p - 1; Lu = 2; }
             }
         }
@@ -654,10 +825,12 @@ __device__ __forceinline__ float sweep_line(const LineArgs &A, int r, const RunB
                 PairRows Q;
                 pair_load(B, ps, Lu, ml, Q);
                 u = pair_ramp(Q, Lu);
-            } else {
+            } else if (Lu == 3) {
                 TriRows T3;
                 tri_load(B, ps, ml, T3);
                 u = tri_ramp(T3);
+            } else {
+                u = long_ramp(B, ps, Lu, ml);
             }
         }
     }
@@ -666,10 +839,24 @@ __device__ __forceinline__ float sweep_line(const LineArgs &A, int r, const RunB
     Ramp tot;
     const Ramp ex = block_scan_excl<NT>(u, wtot, 0, tot, t, ml);
     const float x = ramp_eval(ex, 0.0f);
+    // units of more than three cells: the thread of the last cell solves the unit into RF_O;
+    // one-wave lines synchronise only where such a unit exists, wider lines always (the
+    // other half of a two-half workgroup takes the same barrier)
+    if (NT == 64 && WS) {
+        if (any_long) {
+            if (in && Lu > 3 && ps + Lu - 1 == p) long_solve(B, ps, Lu, ml, x);
+            wave_lds_sync();
+        }
+    } else if (lmode) {
+        if (in && Lu > 3 && ps + Lu - 1 == p) long_solve(B, ps, Lu, ml, x);
+        __syncthreads();
+    }
     float v = 0.0f;
     if (in) {
         if (Lu == 0) {
             v = ramp_eval(u, x);
+        } else if (Lu > 3) {
+            v = B.at(RF_O, p);
         } else if (Lu <= 2) {
             PairRows Q;
             pair_load(B, ps, Lu, ml, Q);
@@ -858,9 +1045,10 @@ __device__ __forceinline__ void sweep_band2(const LineArgs &A, int b, const RunB
                                               dn_fresh, wtot, la, t, true);
         } else if (!WS) {
             // a half with no line takes the line step's barriers only: the one after the rows and
-            // masks, and the scan's (several waves)
+            // masks, the scan's (several waves) and the one after the long-unit solves
             __syncthreads();
             if (NT > 64) __syncthreads();
+            if (long_units_possible(A)) __syncthreads();
         }
         if (act) {
             if (redundant) {
@@ -890,8 +1078,9 @@ __device__ __forceinline__ void sweep_band2(const LineArgs &A, int b, const RunB
 // round after another, so that only one round's inputs are held at a time.
 // A unit's chain ramp sits at its LAST position (its other cells take the
 // identity): the scan's exclusive prefix there is the value entering the
-// unit, and a unit that begins in the last two cells of a round is solved
-// in the next round, where all of its rows are known.  The unit rows live in
+// unit, and a unit that begins in one round and ends in the next is solved
+// in the next round, where all of its rows are known (units are at most one
+// round long, so the ring of two rounds holds every row of a unit).  The unit rows live in
 // a ring of two rounds (RingBuf).  A cell's new value is written as soon as
 // it is final (cells of a unit that ends in the next round: one round
 // later).  LDS holds the previous own line (the fresh upstream neighbour,
@@ -967,7 +1156,7 @@ __device__ __forceinline__ void long_band(const LineArgs &A, int b, float *ring,
                 const float vd = has_dn ? (dn_fresh ? red[p] : c.vd) : 0.0f;
                 w = cell_row<REV, CF>(A, c, r, cell(p), vu, vd, area);
                 if (mask_bit(msk, p)) {
-                    unit_of(msk, nw, ml, p, ps, L);
+                    unit_of(msk, nw, ml, p, A.run_max > 0 && A.run_max < NT ? A.run_max : NT, ps, L);
                     inu = true;
                 } else if (p >= 1 && mask_bit(msk, p - 1) && (p < 2 || !mask_bit(msk, p - 2))) {
                     ps = p - 1; L = 2;               // the cell after a single starred cell
@@ -991,10 +1180,12 @@ __device__ __forceinline__ void long_band(const LineArgs &A, int b, float *ring,
                     PairRows Q;
                     pair_load(B, ps, L, ml, Q);
                     u = pair_ramp(Q, L);
-                } else {
+                } else if (L == 3) {
                     TriRows T3;
                     tri_load(B, ps, ml, T3);
                     u = tri_ramp(T3);
+                } else {
+                    u = long_ramp(B, ps, L, ml);
                 }
             }
             Ramp tot;
@@ -1005,7 +1196,6 @@ __device__ __forceinline__ void long_band(const LineArgs &A, int b, float *ring,
             carry = ramp_eval(tot, carry);
             if (uk) {
                 if (last) {
-                    // the rows are read again before the new values overwrite RF_A
                     if (L <= 2) {
                         PairRows Q;
                         pair_load(B, ps, L, ml, Q);
@@ -1013,6 +1203,8 @@ __device__ __forceinline__ void long_band(const LineArgs &A, int b, float *ring,
                         pair_solve(Q, L, x, y0, y1);
                         B.y(ps) = y0;
                         if (L == 2) B.y(ps + 1) = y1;
+                    } else if (L > 3) {
+                        long_solve(B, ps, L, ml, x);
                     } else {
                         TriRows T3;
                         tri_load(B, ps, ml, T3);

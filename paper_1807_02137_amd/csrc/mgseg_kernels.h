@@ -950,6 +950,7 @@ struct CoarseArgs {
     int n, m, prm, iters, scaled;
     float kap, e2, M, Sigma, rtol;
     int smoother;                   // 1: GSLEX-I (sweep A's order, every cell a point) in place of HS2
+    int run_max;                    // 0: maximal runs of starred cells; else the cut (LineArgs::run_max)
 };
 #define CO_ARRAYS 18
 #define CO_MAX_CELLS 1024
@@ -1046,6 +1047,7 @@ __global__ void __launch_bounds__(NT) k_coarse_smooth(CoarseArgs G)
     C.psi = psi; C.w = w; C.fit = dev ? nullptr : fit; C.F = F; C.lab = lab; C.lo = lo; C.hi = hi;
     C.skip = nullptr; C.tout = nullptr; C.tpitch = 0; C.area = G.area; C.pitch = m; C.lpitch = m; C.cf = nullptr;
     C.nl = n; C.ml = m; C.kap = G.kap; C.e2 = G.e2; C.M = G.M; C.eps = (float)G.eps; C.scaled = G.scaled;
+    C.run_max = G.run_max;
     C.phi_old = P0; C.phi_new = nullptr; C.bit = 0;
     R = C;
     R.psi = nullptr; R.w = nullptr; R.fit = nullptr; R.F = Fe; R.cf = cf;

@@ -37,7 +37,8 @@ class _Params(C.Structure):
                 ("beta", C.c_double), ("sigma_g", C.c_double), ("sigma_d", C.c_double),
                 ("Sigma", C.c_double), ("M", C.c_double), ("nu1", C.c_int32), ("nu2", C.c_int32),
                 ("levels", C.c_int32), ("coarse_iters", C.c_int32), ("mixed_precision", C.c_int32),
-                ("scaled", C.c_int32), ("coarse_rtol", C.c_double), ("smoother", C.c_int32)]
+                ("scaled", C.c_int32), ("coarse_rtol", C.c_double), ("smoother", C.c_int32),
+                ("run_max", C.c_int32)]
 
 
 class _Stats(C.Structure):
@@ -69,6 +70,7 @@ class Params:
     scaled: int = 1
     coarse_rtol: float = 1e-4
     smoother: int = 0           # 0 Hybrid Smoother 2, 1 GSLEX-I
+    run_max: int = 0            # 0 maximal superpixel runs (the paper's); k > 0 runs cut into pieces of <= k
 
     def to_c(self) -> _Params:
         p = _Params()

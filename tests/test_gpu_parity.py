@@ -363,6 +363,98 @@ def test_single_sweep_units_across_rounds(shape, sweep):
     s.close()
 
 
+def plant_long_runs(lab, sweep, lengths, seed=0):
+    """Sets the sweep's starred bit on runs of the given lengths along every
+    line (visit order), separated by at least one unstarred cell: the first
+    run of line i starts at its first cell, the others at seeded positions,
+    so that units of many cells (the paper's superpixels) appear at the line
+    start, inside the line, across 1024-cell round boundaries and at the end."""
+    lab = lab.copy()
+    v = lab if sweep < 2 else lab.T
+    nl, ml = v.shape
+    rev = sweep in (1, 3)
+    bit = np.uint8(1 << sweep)
+    rng = np.random.default_rng(seed)
+    planted = []
+    for i in range(nl):
+        p = 0 if i % 2 == 0 else int(rng.integers(0, 8))
+        k = i
+        while p < ml:
+            L = min(lengths[k % len(lengths)], ml - p)
+            k += 1
+            for t in range(p, min(p + L + 1, ml)):
+                q = ml - 1 - t if rev else t
+                if t < p + L:
+                    v[i, q] |= bit
+                else:
+                    v[i, q] &= ~bit
+            planted.append(L)
+            p += L + 1 + int(rng.integers(0, 40))
+    return lab, planted
+
+
+@pytest.mark.parametrize("shape,sweep,lengths", [
+    ((16, 64), 0, [4, 5, 7, 16, 31]), ((16, 64), 1, [64]), ((64, 16), 2, [6, 9, 40]), ((64, 16), 3, [64]),
+    ((16, 200), 0, [4, 13, 63, 64, 65]), ((16, 200), 1, [200]), ((200, 16), 3, [5, 120]),
+    ((16, 512), 0, [8, 100, 300]), ((512, 16), 2, [512]),
+    ((16, 1000), 0, [4, 33, 600]), ((16, 1000), 1, [1000]), ((1000, 16), 2, [17, 250]), ((1000, 16), 3, [999]),
+    ((8, 3000), 0, [5, 90, 700, 1024]), ((8, 3000), 1, [1000, 40]), ((3000, 8), 2, [300, 1024]),
+    ((3000, 8), 3, [7, 1024, 64]),
+])
+def test_single_sweep_long_units(shape, sweep, lengths):
+    """Units of four to 1024 cells (maximal runs solved as one box-constrained
+    tridiagonal system each, Sec. 4.3), planted over the oracle's labels on
+    lines of every sweep kernel (one wave, two-half, 1024 threads, rounds of
+    1024 cells with units across the round boundaries): one sweep from the same
+    state against the oracle, which solves each run by its own active-set
+    method.  The state has cells at both bounds inside the runs."""
+    n, m = shape
+    say("case long units", "ABCD"[sweep], n, m, lengths)
+    img, mk = long_line_instance(n, m) if max(n, m) > 64 else (synth.tiny_instance(7, n, m).image,
+                                                              synth.tiny_instance(7, n, m).markers)
+    s = mgseg.Solver(img, mk, mgseg.Params(levels=3, mixed_precision=0))
+    o = Oracle(img, mk, OracleParams(levels=3))
+    o.smooth(2, 0)
+    phi = o.get("phi")
+    s.set("phi", phi.astype(np.float32))
+    o.set("phi", phi.astype(np.float32).astype(np.float64))
+    s.op("freeze", 0)
+    o.freeze(0)
+    lab, planted = plant_long_runs(o.labels(), sweep, lengths)
+    o.set_labels(lab)
+    s.set("labels", lab)
+    s.op(["sweep_A", "sweep_B", "sweep_C", "sweep_D"][sweep], 0)
+    o.sweep(sweep, 0)
+    new = o.get("phi")
+    d = np.abs(s.get("phi").astype(np.float64) - new)
+    at_bound = int((np.abs(new) >= 4.0 - 1e-12).sum())
+    say("max |dphi|", d.max(), "units", len(planted), "longest", max(planted), "cells at a bound", at_bound)
+    assert max(planted) >= 4 and at_bound > 0
+    assert d.max() <= 2e-4
+    s.close()
+
+
+@pytest.mark.parametrize("seed", [1000, 1001])
+def test_solve_parity_three_cell_cut(seed):
+    """The labelled option that cuts every run into pieces of at most three
+    cells (run_max = 3, each piece in closed form) on both sides."""
+    say("case three-cell cut seed", seed)
+    inst, s, o = make(seed, run_max=3)
+    k, hist = o.solve(1e-6, 40)
+    hg = []
+    for _ in range(40):
+        hg.append(s.vcycle())
+        if hg[-1] <= 1e-6:
+            break
+    pg, po = s.phi().cpu().numpy(), o.get("phi")
+    agree = (pg > 0) == (po > 0)
+    flips = int((~agree).sum())
+    say(f"gpu {len(hg)} cycles; oracle {k}; flips {flips} max|dphi| {np.abs(pg - po)[agree].max():.3e}")
+    assert hg[-1] <= 1e-6 and k > 0 and flips <= 1
+    assert np.abs(pg - po)[agree].max() <= 1e-4
+    s.close()
+
+
 @pytest.mark.parametrize("k", [1, 2])
 def test_degenerate_marker_sets(k):
     """One or two markers: the marker hull is a point or a segment (zero area)."""
