@@ -371,7 +371,7 @@ __device__ __forceinline__ bool long_units_possible(const LineArgs &A)
 // ps + k):  y_k = a_k y_{k-1} + c_k y_{k+1} - r_k  on [lo_k, hi_k], with
 // y_{-1} = x (the entering value) and y_L = s (the successor's old value).
 //
-// Chain ramp.  Eliminating the unit from its far end without the box gives
+// Eliminating the unit from its far end without the box gives
 // y_k = P_k y_{k-1} + Q_k (P_{L-1} = a, Q_{L-1} = c s - r, then
 // P_k = a_k / (1 - c_k P_{k+1}), Q_k = (c_k Q_{k+1} - r_k) / (1 - c_k P_{k+1})).
 // For the box-constrained unit the last value is a monotone function of x
@@ -381,48 +381,62 @@ __device__ __forceinline__ bool long_units_possible(const LineArgs &A)
 // Z_{L-1} o ... o Z_0 is such a clipped ramp, and it has the right limits:
 // as x -> -inf (+inf) cell 0 goes to lo_0 (hi_0) and the composition of the
 // remaining Z's gives the tail's last value with cell 0 held there (the same
-// argument one cell further on).  So the chain ramp is that composition,
-// with no iteration and no case analysis.  (A cell with a_k = 0 is the limit
-// of small a_k, where both sides are continuous.)
+// argument one cell further on).  So in the line scan every cell of such a
+// unit contributes its Z_k, and the scan carries the exact last value of the
+// unit on to the cells after it.  (A cell with a_k = 0 is the limit of small
+// a_k, where both sides are continuous.)
 //
-// Values at x.  The forward substitution y_k = Z_k(y_{k-1}) is exact where no
-// cell after k is held at a bound by the true solution; it is checked row by
-// row (every cell must be the projection of its own row).  Where the check
-// fails, a primal-dual active-set iteration finishes the solve: cells held at
-// a bound are fixed there, the free chains between them are solved exactly
-// (one forward elimination and one back substitution over the unit), free
-// cells that leave the box are held, held cells whose row points back into
-// the box are released, until no cell changes (Hintermueller, Ito & Kunisch:
-// finite for M-matrices).  One thread takes the whole unit.
+// Values inside the unit.  The scan's values z_k = Z_k(z_{k-1}) (z_{-1} = x)
+// are the unit's values wherever no cell after k is held at a bound by the
+// true solution; they are checked row by row (every cell must be the
+// projection of its own row).  A unit that fails the check is finished by a
+// primal-dual active-set iteration: cells held at a bound are fixed there,
+// the free chains between them are solved exactly (one forward elimination
+// and one back substitution over the unit), free cells that leave the box are
+// held, held cells whose row points back into the box are released, until no
+// cell changes (Hintermueller, Ito & Kunisch: finite for M-matrices).  One
+// thread takes such a unit.
 //
-// A unit with a cell of S = 0 (a = NaN) or a vanishing pivot keeps its old
-// values; RF_P at its last position is then NaN.
+// Rows of S = 0 cannot be starred (the jump test needs a non-zero interior
+// coefficient), so units of more than three cells have none; a cell of S = 0
+// placed in one anyway keeps its old value inside the elimination.  The
+// pivots are positive: the rows are strictly diagonally dominant through the
+// coefficients across the line.
+
+// P_k, Q_k of position p by elimination from the unit's last position down to
+// p; P1 / Q1 are P_{k+1}, Q_{k+1} (for the last cell: 0 and s)
 template <class Buf>
-__device__ __forceinline__ Ramp long_ramp(const Buf &B, int ps, int L, int ml)
+__device__ __forceinline__ void long_elim(const Buf &B, int p, int last, float s, float &P, float &Q, float &P1,
+                                          float &Q1)
 {
-    const int last = ps + L - 1;
-    float Pn = 0.0f, Qn = B.sig_after(last, ml);
-    Ramp T = ramp_id();
-    #pragma nounroll
-    for (int q = last; q >= ps; q--) {
-        const float a = B.at(RF_A, q), c = B.at(RF_C, q), r = B.at(RF_R, q);
-        const float den = 1.0f - c * Pn;
-        if (isnan(a) || !(den > 0.0f)) {
-            B.at(RF_P, last) = __builtin_nanf("");
-            const float yo = B.at(RF_X, last);
-            return Ramp{0.0f, yo, yo, yo};
+    float Pn = 0.0f, Qn = s, Pp = 0.0f, Qp = s;
+    // four rows per step: their reads are issued together, ahead of the dependent chain
+    for (int q = last; q >= p; q -= 4) {
+        float a[4], c[4], r[4];
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const int qq = q - j >= p ? q - j : p;
+            a[j] = B.at(RF_A, qq); c[j] = B.at(RF_C, qq); r[j] = B.at(RF_R, qq);
         }
-        const float inv = 1.0f / den;
-        Pn = a * inv;
-        Qn = fmaf(c, Qn, -r) * inv;
-        B.at(RF_P, q) = Pn;
-        B.at(RF_Q, q) = Qn;
-        T = ramp_comp(T, Ramp{Pn, Qn, B.at(RF_LO, q), B.at(RF_HI, q)});
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            if (q - j < p) break;
+            Pp = Pn; Qp = Qn;
+            if (isnan(a[j])) {
+                Pn = 0.0f; Qn = B.at(RF_X, q - j);
+            } else {
+                const float inv = __builtin_amdgcn_rcpf(fmaf(-c[j], Pn, 1.0f));
+                Pn = a[j] * inv;
+                Qn = fmaf(c[j], Qn, -r[j]) * inv;
+            }
+        }
     }
-    return T;
+    P = Pn; Q = Qn; P1 = Pp; Q1 = Qp;
 }
-// the unit's row k evaluated at its neighbours' new values (the value the cell
-// would take free of its box); mag: the size of its terms, the scale of its rounding
+
+// the unit's row at position q evaluated at its neighbours' values in RF_O
+// (the value the cell would take free of its box); mag: the size of its
+// terms, the scale of its rounding
 template <class Buf>
 __device__ __forceinline__ float long_row(const Buf &B, int q, int ps, int last, float x, float s, float &mag)
 {
@@ -432,53 +446,42 @@ __device__ __forceinline__ float long_row(const Buf &B, int q, int ps, int last,
     mag = fabsf(ta) + fabsf(tc) + fabsf(r);
     return (ta + tc) - r;
 }
+// does z_q (in RF_O) sit at the projection of its row?
+__device__ __forceinline__ bool long_row_ok(float z, float v, float mag, float lo, float hi)
+{
+    return fabsf(mg_clip(v, lo, hi) - z) <= 1e-5f * mag;
+}
+
+// The active-set iteration of a unit from the values in RF_O (its starting
+// held set: the cells there at a bound); the result replaces RF_O.  RF_P
+// holds the held state between passes (-1 held at lo, -2 held at hi, -3 a
+// cell of S = 0 held at its old value, else free) and the elimination factor
+// E >= 0 of a free cell within a pass; RF_Q the elimination's F (a held cell:
+// its value).
 template <class Buf>
-__device__ __forceinline__ void long_solve(const Buf &B, int ps, int L, int ml, float x)
+__device__ __forceinline__ void long_active_set(const Buf &B, int ps, int L, int ml, float x)
 {
     const int last = ps + L - 1;
-    if (isnan(B.at(RF_P, last))) {
-        #pragma nounroll
-        for (int q = ps; q <= last; q++) B.at(RF_O, q) = B.at(RF_X, q);
-        return;
-    }
     const float s = B.sig_after(last, ml);
-    float y = x;
-    #pragma nounroll
-    for (int q = ps; q <= last; q++) {
-        y = mg_clip(fmaf(B.at(RF_P, q), y, B.at(RF_Q, q)), B.at(RF_LO, q), B.at(RF_HI, q));
-        B.at(RF_O, q) = y;
-    }
-    // every cell at the projection of its own row (to rounding)?
-    bool good = true;
-    #pragma nounroll
-    for (int q = ps; q <= last && good; q++) {
-        float mag;
-        const float v = long_row(B, q, ps, last, x, s, mag);
-        const float pv = mg_clip(v, B.at(RF_LO, q), B.at(RF_HI, q));
-        good = fabsf(pv - B.at(RF_O, q)) <= 1e-5f * mag;
-    }
-    if (good) return;
-    // active-set iteration.  RF_P holds the held state between passes (-1 held
-    // at lo, -2 held at hi, else free) and the elimination factor E >= 0 of a
-    // free cell within a pass; RF_Q the elimination's F (a held cell: its bound).
-    #pragma nounroll
+#pragma nounroll
     for (int q = ps; q <= last; q++) {
         const float v = B.at(RF_O, q);
-        B.at(RF_P, q) = v <= B.at(RF_LO, q) ? -1.0f : (v >= B.at(RF_HI, q) ? -2.0f : 0.0f);
+        B.at(RF_P, q) = isnan(B.at(RF_A, q)) ? -3.0f
+                        : (v <= B.at(RF_LO, q) ? -1.0f : (v >= B.at(RF_HI, q) ? -2.0f : 0.0f));
     }
-    #pragma nounroll
+#pragma nounroll
     for (int it = 0; it < L + 8; it++) {
         // forward elimination of the free chains: y_q = E_q y_{q+1} + F_q
         float Ep = 0.0f, Fp = x;
-        #pragma nounroll
+#pragma nounroll
         for (int q = ps; q <= last; q++) {
             const float st = B.at(RF_P, q);
             if (st < 0.0f) {
                 Ep = 0.0f;
-                Fp = st == -1.0f ? B.at(RF_LO, q) : B.at(RF_HI, q);
+                Fp = st == -1.0f ? B.at(RF_LO, q) : (st == -2.0f ? B.at(RF_HI, q) : B.at(RF_X, q));
             } else {
                 const float a = B.at(RF_A, q);
-                const float inv = 1.0f / (1.0f - a * Ep);
+                const float inv = __builtin_amdgcn_rcpf(fmaf(-a, Ep, 1.0f));
                 Ep = B.at(RF_C, q) * inv;
                 Fp = fmaf(a, Fp, -B.at(RF_R, q)) * inv;
                 B.at(RF_P, q) = Ep;
@@ -486,7 +489,7 @@ __device__ __forceinline__ void long_solve(const Buf &B, int ps, int L, int ml, 
             B.at(RF_Q, q) = Fp;
         }
         float yn = s;
-        #pragma nounroll
+#pragma nounroll
         for (int q = last; q >= ps; q--) {
             const float e = B.at(RF_P, q);
             yn = e < 0.0f ? B.at(RF_Q, q) : fmaf(e, yn, B.at(RF_Q, q));
@@ -495,11 +498,13 @@ __device__ __forceinline__ void long_solve(const Buf &B, int ps, int L, int ml, 
         // new held state: free cells outside the box are held; a held cell is
         // released where its row points back into the box (beyond rounding)
         bool changed = false;
-        #pragma nounroll
+#pragma nounroll
         for (int q = ps; q <= last; q++) {
             const float lo = B.at(RF_LO, q), hi = B.at(RF_HI, q), yv = B.at(RF_O, q), was = B.at(RF_P, q);
             float st = 0.0f;
-            if (was < 0.0f) {
+            if (was == -3.0f) {
+                st = -3.0f;
+            } else if (was < 0.0f) {
                 float mag;
                 const float v = long_row(B, q, ps, last, x, s, mag);
                 const float tol = 2e-6f * (mag + fabsf(was == -1.0f ? lo : hi));
@@ -515,8 +520,56 @@ __device__ __forceinline__ void long_solve(const Buf &B, int ps, int L, int ml, 
         }
         if (!changed) break;
     }
-    #pragma nounroll
+#pragma nounroll
     for (int q = ps; q <= last; q++) B.at(RF_O, q) = mg_clip(B.at(RF_O, q), B.at(RF_LO, q), B.at(RF_HI, q));
+}
+
+// One thread per unit (lines longer than one workgroup).  The chain ramp:
+// the composition of the unit's Z_k, built during one elimination that also
+// stores P_k, Q_k.
+template <class Buf>
+__device__ __forceinline__ Ramp long_ramp(const Buf &B, int ps, int L, int ml)
+{
+    const int last = ps + L - 1;
+    float Pn = 0.0f, Qn = B.sig_after(last, ml);
+    Ramp T = ramp_id();
+#pragma nounroll
+    for (int q = last; q >= ps; q--) {
+        const float a = B.at(RF_A, q), c = B.at(RF_C, q), r = B.at(RF_R, q);
+        if (isnan(a)) {
+            Pn = 0.0f; Qn = B.at(RF_X, q);
+        } else {
+            const float inv = __builtin_amdgcn_rcpf(fmaf(-c, Pn, 1.0f));
+            Pn = a * inv;
+            Qn = fmaf(c, Qn, -r) * inv;
+        }
+        B.at(RF_P, q) = Pn;
+        B.at(RF_Q, q) = Qn;
+        T = ramp_comp(T, Ramp{Pn, Qn, B.at(RF_LO, q), B.at(RF_HI, q)});
+    }
+    return T;
+}
+// the unit's values at x into RF_O: forward substitution through the Z_k,
+// the row check, the active-set iteration where it fails
+template <class Buf>
+__device__ __forceinline__ void long_solve(const Buf &B, int ps, int L, int ml, float x)
+{
+    const int last = ps + L - 1;
+    const float s = B.sig_after(last, ml);
+    float y = x;
+#pragma nounroll
+    for (int q = ps; q <= last; q++) {
+        y = mg_clip(fmaf(B.at(RF_P, q), y, B.at(RF_Q, q)), B.at(RF_LO, q), B.at(RF_HI, q));
+        B.at(RF_O, q) = y;
+    }
+    bool good = true;
+#pragma nounroll
+    for (int q = ps; q <= last && good; q++) {
+        float mag;
+        const float v = long_row(B, q, ps, last, x, s, mag);
+        good = long_row_ok(B.at(RF_O, q), v, mag, B.at(RF_LO, q), B.at(RF_HI, q));
+    }
+    if (!good) long_active_set(B, ps, L, ml, x);
 }
 
 // --------------------------------------------------------------------------
@@ -750,6 +803,12 @@ __device__ __forceinline__ void row_store(const Buf &B, int p, const CellRow &w)
 // chosen by the caller's line parity, so that the next line can write the
 // other while this one's cells still read theirs after the scan; the masks
 // are read before the scan only.
+// OR of the per-wave flags of the workgroup (after the barrier that published them)
+__device__ __forceinline__ bool block_flag(const unsigned *wflag)
+{
+    const int ln = threadIdx.x & 63;
+    return __ballot(ln < (int)(blockDim.x >> 6) && wflag[ln] != 0u) != 0ull;
+}
 __device__ __forceinline__ void wave_lds_sync()
 {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -759,7 +818,7 @@ __device__ __forceinline__ void wave_lds_sync()
 template <int NT, bool REV, bool CF = false, bool WS = false>
 __device__ __forceinline__ float sweep_line(const LineArgs &A, int r, const RunBuf &B, uint64_t *msk, bool write,
                                             float upv, bool up_fresh, float dnv, bool dn_fresh, Ramp *wtot,
-                                            const CellIn &c, int t, bool act)
+                                            unsigned *wbad, const CellIn &c, int t, bool act)
 {
     static_assert(!WS || NT == 64, "a wave-synchronous line is one wave");
     if (WS) wave_lds_sync();
@@ -803,9 +862,11 @@ __device__ __forceinline__ float sweep_line(const LineArgs &A, int r, const RunB
         if (lmode) any_long = __ballot(has_run4(w0, lane + 1 < nw ? msk[lane + 1] : 0ull)) != 0ull;
     }
 
-    // phase 2: the cell's unit (ps, L; L = 0: a point); the unit's chain ramp at its last cell
+    // phase 2: the cell's unit (ps, L; L = 0: a point); the chain ramp of a unit of at most three
+    // cells at its last cell; every cell of a longer unit its own Z_k
     int ps = p, Lu = 0;
     Ramp u = ramp_id();
+    float lP1 = 0.0f, lQ1 = 0.0f;
     if (in) {
         if (any_star) {
             if (NT == 64) {
@@ -820,43 +881,45 @@ __device__ __forceinline__ float sweep_line(const LineArgs &A, int r, const RunB
         }
         if (Lu == 0) {
             u = cell_ramp(w);
+        } else if (Lu > 3) {
+            const int last = ps + Lu - 1;
+            float P, Q;
+            long_elim(B, p, last, B.sig_after(last, ml), P, Q, lP1, lQ1);
+            u = Ramp{P, Q, w.lo, w.hi};
+            if (p == ps) B.at(RF_P, ps) = 0.0f;      // the unit's failed-check flag
         } else if (ps + Lu - 1 == p) {
             if (Lu <= 2) {
                 PairRows Q;
                 pair_load(B, ps, Lu, ml, Q);
                 u = pair_ramp(Q, Lu);
-            } else if (Lu == 3) {
+            } else {
                 TriRows T3;
                 tri_load(B, ps, ml, T3);
                 u = tri_ramp(T3);
-            } else {
-                u = long_ramp(B, ps, Lu, ml);
             }
         }
     }
 
-    // phase 3: the scan gives every cell the value entering it (a unit cell: entering its unit)
+    // phase 3: the scan gives every cell the value entering it (a cell of a unit of at most three
+    // cells: entering its unit; of a longer unit: its predecessor's value z in the unit's Z chain)
     Ramp tot;
     const Ramp ex = block_scan_excl<NT>(u, wtot, 0, tot, t, ml);
     const float x = ramp_eval(ex, 0.0f);
-    // units of more than three cells: the thread of the last cell solves the unit into RF_O;
-    // one-wave lines synchronise only where such a unit exists, wider lines always (the
-    // other half of a two-half workgroup takes the same barrier)
-    if (NT == 64 && WS) {
-        if (any_long) {
-            if (in && Lu > 3 && ps + Lu - 1 == p) long_solve(B, ps, Lu, ml, x);
-            wave_lds_sync();
-        }
-    } else if (lmode) {
-        if (in && Lu > 3 && ps + Lu - 1 == p) long_solve(B, ps, Lu, ml, x);
-        __syncthreads();
-    }
     float v = 0.0f;
+    bool lbad = false;
     if (in) {
         if (Lu == 0) {
             v = ramp_eval(u, x);
         } else if (Lu > 3) {
-            v = B.at(RF_O, p);
+            // z_k, and the check of the cell's row at z_{k-1} (= x) and z_{k+1} = Z_{k+1}(z_k)
+            v = ramp_eval(u, x);
+            const int last = ps + Lu - 1;
+            const float yn = p == last ? lQ1 : mg_clip(fmaf(lP1, v, lQ1), B.at(RF_LO, p + 1), B.at(RF_HI, p + 1));
+            const float ta = w.a * x, tc = w.c * yn;
+            lbad = w.ok && !long_row_ok(v, (ta + tc) - w.rr, fabsf(ta) + fabsf(tc) + fabsf(w.rr), w.lo, w.hi);
+            B.at(RF_O, p) = v;
+            B.at(RF_Q, p) = v <= w.lo ? -1.0f : (v >= w.hi ? -2.0f : 0.0f);   // held state of z
+            if (lbad) B.at(RF_P, ps) = 1.0f;
         } else if (Lu <= 2) {
             PairRows Q;
             pair_load(B, ps, Lu, ml, Q);
@@ -870,6 +933,105 @@ __device__ __forceinline__ float sweep_line(const LineArgs &A, int r, const RunB
             tri_solve(T3, x, y0, y1, y2);
             v = p == ps ? y0 : (p == ps + 1 ? y1 : y2);
         }
+    }
+    // A unit of more than three cells that fails the check is repaired by the active-set
+    // iteration run in parallel: the held state of every cell of such a unit lives in RF_Q (-1 at
+    // lo, -2 at hi, 0 free; at first the state of z), every cell eliminates its free chain up to
+    // the next held cell, a second scan substitutes, and the cells update their held states, until
+    // none changes.  After eight such passes the thread of the unit's first cell (which holds the
+    // entering value) would finish the unit with the serial iteration.  One-wave lines synchronise
+    // only where a unit failed; wider lines publish one flag per wave and take one barrier (the
+    // other half of a two-half workgroup takes it too), and the repair's barriers only where a
+    // unit failed.
+    bool repair = false;
+    if (NT == 64 && WS) {
+        repair = any_long && __ballot(lbad) != 0ull;
+        if (repair) wave_lds_sync();
+    } else if (lmode) {
+        const unsigned long long bb = __ballot(lbad);
+        if (lane == 0) wbad[threadIdx.x >> 6] = bb != 0ull ? 1u : 0u;
+        __syncthreads();
+        repair = block_flag(wbad);
+    }
+    if (repair) {
+        const int last = ps + Lu - 1;
+        const bool fu = in && Lu > 3 && B.at(RF_P, ps) != 0.0f;
+        const float su = fu ? B.sig_after(last, ml) : 0.0f;
+        float yv = v;
+        for (int pass = 0;; pass++) {
+            Ramp u2 = ramp_id();
+            float st = 0.0f;
+            if (fu) {
+                st = B.at(RF_Q, p);
+                float P2 = 0.0f, Q2 = su;
+#pragma nounroll
+                for (int qq = last; qq >= p; qq--) {
+                    const float sq = B.at(RF_Q, qq);
+                    if (sq < 0.0f) {
+                        P2 = 0.0f;
+                        Q2 = sq == -1.0f ? B.at(RF_LO, qq) : B.at(RF_HI, qq);
+                    } else {
+                        const float cq = B.at(RF_C, qq);
+                        const float inv = __builtin_amdgcn_rcpf(fmaf(-cq, P2, 1.0f));
+                        P2 = B.at(RF_A, qq) * inv;
+                        Q2 = fmaf(cq, Q2, -B.at(RF_R, qq)) * inv;
+                    }
+                }
+                if (st < 0.0f) {
+                    u2 = Ramp{0.0f, Q2, Q2, Q2};
+                } else if (p == ps) {
+                    const float y0 = fmaf(P2, x, Q2);
+                    u2 = Ramp{0.0f, y0, y0, y0};
+                } else {
+                    u2 = Ramp{P2, Q2, -MG_BIG, MG_BIG};
+                }
+            }
+            Ramp tot2;
+            const Ramp ex2 = block_scan_excl<NT>(u2, wtot, 0, tot2, t, ml);
+            if (fu) {
+                yv = ramp_eval(u2, ramp_eval(ex2, 0.0f));
+                B.at(RF_O, p) = yv;
+            }
+            if (NT == 64 && WS) wave_lds_sync();
+            else __syncthreads();
+            // new held state: a free cell outside its box is held; a held cell is released where
+            // its row points back into the box (beyond rounding)
+            bool chg = false;
+            if (fu) {
+                float ns = 0.0f;
+                if (st == 0.0f) {
+                    ns = yv < w.lo ? -1.0f : (yv > w.hi ? -2.0f : 0.0f);
+                } else {
+                    const float yp = p == ps ? x : B.at(RF_O, p - 1);
+                    const float yn = p == last ? su : B.at(RF_O, p + 1);
+                    const float ta = w.a * yp, tc = w.c * yn;
+                    const float vr = (ta + tc) - w.rr;
+                    const float tol = 2e-6f * (fabsf(ta) + fabsf(tc) + fabsf(w.rr) + fabsf(yv));
+                    ns = st == -1.0f ? (vr > w.lo + tol ? 0.0f : -1.0f) : (vr < w.hi - tol ? 0.0f : -2.0f);
+                }
+                chg = (ns < 0.0f) != (st < 0.0f);
+                B.at(RF_Q, p) = ns;
+            }
+            bool more;
+            if (NT == 64 && WS) {
+                more = __ballot(chg) != 0ull;
+                if (more) wave_lds_sync();
+            } else {
+                const unsigned long long bc = __ballot(chg);
+                if (lane == 0) wbad[threadIdx.x >> 6] = bc != 0ull ? 1u : 0u;
+                __syncthreads();
+                more = block_flag(wbad);
+            }
+            if (!more) break;
+            if (pass == 7) {
+                if (fu && p == ps) long_active_set(B, ps, Lu, ml, x);
+                if (NT == 64 && WS) wave_lds_sync();
+                else __syncthreads();
+                if (fu) yv = B.at(RF_O, p);
+                break;
+            }
+        }
+        if (fu) v = mg_clip(yv, w.lo, w.hi);
     }
     if (write && in) {
         if (A.tout) A.tout[(long long)q * A.tpitch + r] = v;
@@ -924,7 +1086,7 @@ __device__ __forceinline__ void band_step(int r0, int nl, int st, int &r, bool &
 // bands that one workgroup takes one after another).
 template <int NT, bool REV, bool PF = false, bool CF = false, bool WS = false>
 __device__ __forceinline__ void sweep_band(const LineArgs &A, int b, const RunBuf &B, uint64_t *msk, Ramp *wtot,
-                                           int &lpar)
+                                           unsigned *wbad, int &lpar)
 {
     // transposed output of a full band: the band's 4 lines are 4 consecutive
     // floats of the output layout, written as one 16-byte store per cell
@@ -961,7 +1123,7 @@ __device__ __forceinline__ void sweep_band(const LineArgs &A, int b, const RunBu
             load(r, up_fresh, dn_fresh, la);
         }
         const float cur = sweep_line<NT, REV, CF, WS>(A, r, B.other(lpar & 1), msk, !redundant && !pack, prev,
-                                                      up_fresh, red, dn_fresh, wtot, la, t, true);
+                                                      up_fresh, red, dn_fresh, wtot, wbad, la, t, true);
         lpar++;
         const int li = r - r0;
         if (redundant) red = cur;
@@ -994,7 +1156,8 @@ __device__ __forceinline__ void sweep_band(const LineArgs &A, int b, const RunBu
 // the last step publishes the recomputed line.
 template <int NT, bool REV, bool PF, bool CF>
 __device__ __forceinline__ void sweep_band2(const LineArgs &A, int b, const RunBuf &B0, const RunBuf &B1,
-                                            uint64_t *msk0, uint64_t *msk1, Ramp *wtot0, Ramp *wtot1, float *redl)
+                                            uint64_t *msk0, uint64_t *msk1, Ramp *wtot0, Ramp *wtot1, float *redl,
+                                            unsigned *wbad)
 {
     constexpr bool WS = NT == 64;
     // read all four steps' inputs at the start where the registers allow it
@@ -1042,13 +1205,32 @@ __device__ __forceinline__ void sweep_band2(const LineArgs &A, int b, const RunB
         float cur = 0.0f;
         if (act) {
             cur = sweep_line<NT, REV, CF, WS>(A, r, B.other(k & 1), msk, !redundant && !pack, prev, up_fresh, dnv,
-                                              dn_fresh, wtot, la, t, true);
+                                              dn_fresh, wtot, wbad, la, t, true);
         } else if (!WS) {
             // a half with no line takes the line step's barriers only: the one after the rows and
-            // masks, the scan's (several waves) and the one after the long-unit solves
+            // masks, the scan's (several waves), and those of the long-unit check (its waves
+            // publish no failure)
             __syncthreads();
             if (NT > 64) __syncthreads();
-            if (long_units_possible(A)) __syncthreads();
+            if (long_units_possible(A)) {
+                const bool l0 = (threadIdx.x & 63) == 0;
+                if (l0) wbad[threadIdx.x >> 6] = 0u;
+                __syncthreads();
+                if (block_flag(wbad)) {
+                    // the repair's passes: scan, values, flags (and the serial finish after eight)
+                    for (int pass = 0;; pass++) {
+                        if (NT > 64) __syncthreads();
+                        __syncthreads();
+                        if (l0) wbad[threadIdx.x >> 6] = 0u;
+                        __syncthreads();
+                        if (!block_flag(wbad)) break;
+                        if (pass == 7) {
+                            __syncthreads();
+                            break;
+                        }
+                    }
+                }
+            }
         }
         if (act) {
             if (redundant) {
@@ -1264,6 +1446,7 @@ __global__ void __launch_bounds__(2 * NT) k_sweep2(LineArgs A)
     if (A.skip && *A.skip) return;
     extern __shared__ uint64_t smem64[];
     __shared__ Ramp wtot[2][2 * (NT / 64)];
+    __shared__ unsigned wbad[2 * (NT / 64)];
     const int nw = sweep_mask_words(A.ml);
     RunBuf B0, B1;
     B0.fs = A.ml;
@@ -1272,7 +1455,8 @@ __global__ void __launch_bounds__(2 * NT) k_sweep2(LineArgs A)
     B1.p = B0.p + 2 * RB_FIELDS * A.ml;
     float *redl = B1.p + 2 * RB_FIELDS * A.ml;
     // read-ahead of the next line where the registers allow it (1024 threads: only with the stored coefficients)
-    sweep_band2<NT, REV, (NT <= 256 || CF), CF>(A, blockIdx.x, B0, B1, smem64, smem64 + nw, wtot[0], wtot[1], redl);
+    sweep_band2<NT, REV, (NT <= 256 || CF), CF>(A, blockIdx.x, B0, B1, smem64, smem64 + nw, wtot[0], wtot[1], redl,
+                                                wbad);
 }
 
 template <int NT, bool REV, bool CF>
@@ -1281,6 +1465,7 @@ __global__ void __launch_bounds__(NT) k_sweep(LineArgs A)
     if (A.skip && *A.skip) return;
     extern __shared__ uint64_t smem64[];
     __shared__ Ramp wtot[2 * (NT / 64 > 0 ? NT / 64 : 1)];
+    __shared__ unsigned wbad[NT / 64 > 0 ? NT / 64 : 1];
     uint64_t *msk = smem64;
     RunBuf B;
     B.fs = A.ml;
@@ -1288,5 +1473,5 @@ __global__ void __launch_bounds__(NT) k_sweep(LineArgs A)
     // read-ahead of the next line where the registers allow it (at 1024 threads, 128 registers per
     // lane: only with the stored coefficients)
     int lpar = 0;
-    sweep_band<NT, REV, (NT <= 512 || CF), CF>(A, blockIdx.x, B, msk, wtot, lpar);
+    sweep_band<NT, REV, (NT <= 512 || CF), CF>(A, blockIdx.x, B, msk, wtot, wbad, lpar);
 }

@@ -1121,7 +1121,7 @@ __global__ void __launch_bounds__(NT) k_coarse_smooth(CoarseArgs G)
         int lpar = 0;
         R.phi_old = P0; R.phi_new = P1; R.bit = G.smoother == 1 ? LAB_NONE : 0;
         for (int b = wave; b < (n + 3) / 4; b += NWV)
-            sweep_band<64, false, true, true, true>(R, b, RBr, mskw, shw, lpar);
+            sweep_band<64, false, true, true, true>(R, b, RBr, mskw, shw, nullptr, lpar);
         __syncthreads();
         if (G.smoother == 1) {
             // GSLEX-I: the pass of sweep A is the whole outer iteration
@@ -1130,18 +1130,18 @@ __global__ void __launch_bounds__(NT) k_coarse_smooth(CoarseArgs G)
         } else {
             R.phi_old = P1; R.phi_new = P2; R.bit = 1;
             for (int b = wave; b < (n + 3) / 4; b += NWV)
-                sweep_band<64, true, true, true, true>(R, b, RBr, mskw, shw, lpar);
+                sweep_band<64, true, true, true, true>(R, b, RBr, mskw, shw, nullptr, lpar);
             __syncthreads();
             block_transpose<NT>(P2, m, T1, n, n, m);
             __syncthreads();
             // sweeps C and D (columns)
             T.phi_old = T1; T.phi_new = T2; T.bit = 2;
             for (int b = wave; b < (m + 3) / 4; b += NWV)
-                sweep_band<64, false, true, true, true>(T, b, RBc, mskw, shw, lpar);
+                sweep_band<64, false, true, true, true>(T, b, RBc, mskw, shw, nullptr, lpar);
             __syncthreads();
             T.phi_old = T2; T.phi_new = T1; T.bit = 3;
             for (int b = wave; b < (m + 3) / 4; b += NWV)
-                sweep_band<64, true, true, true, true>(T, b, RBc, mskw, shw, lpar);
+                sweep_band<64, true, true, true, true>(T, b, RBc, mskw, shw, nullptr, lpar);
             __syncthreads();
         }
         float dmax = 0.0f, tot = 0.0f;
