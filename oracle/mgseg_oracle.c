@@ -782,58 +782,17 @@ static void smooth(or_ctx *c, int l, int iters)
 
 /* ------------------------------------------------------------------------ */
 /* Coarsest grid.  The paper solves it "exactly" with 100 AOS iterations    */
-/* (Sec. 5); here the smoother itself is iterated coarse_iters times.  A     */
-/* 1x1 grid has S = 0, so its scalar equation N(phi) = F is solved directly */
-/* on [-M, M]: among the solutions of the box-constrained problem (interior */
-/* roots, or a bound where the residual pushes outward) the one nearest the  */
-/* current value is taken.                                                   */
-static double scalar_r(or_ctx *c, int l, double phi)
-{
-    or_level *L = &c->lev[l];
-    double s = 0.0;
-    if (c->p.model == 1) s = 2.0 * c->p.nu * (L->h * L->h * Heps(phi, c->p.eps) - c->A1);
-    double N = -(c->p.scaled ? 1.0 : deps(phi, c->p.eps)) * (L->fit[0] + s);
-    return L->F[0] - N;
-}
-
-static void scalar_solve(or_ctx *c, int l)
-{
-    or_level *L = &c->lev[l];
-    double lo = L->lo[0], hi = L->hi[0], cur = L->phi[0];
-    double best = cur, bestd = 1e300;
-    const int NS = 4096;
-    /* bounds that are solutions of the box-constrained problem */
-    if (scalar_r(c, l, lo) >= 0.0) { best = lo; bestd = fabs(cur - lo); }
-    if (scalar_r(c, l, hi) <= 0.0 && fabs(hi - cur) < bestd) { best = hi; bestd = fabs(hi - cur); }
-    /* interior roots: sign changes on a uniform grid, refined by bisection */
-    double a = lo, ra = scalar_r(c, l, a);
-    for (int t = 1; t <= NS && hi > lo; t++) {
-        double b = lo + (hi - lo) * t / NS, rb = scalar_r(c, l, b);
-        double root = 0.0;
-        int found = 0;
-        if (ra == 0.0) { root = a; found = 1; }
-        else if (rb != 0.0 && ((ra < 0.0) != (rb < 0.0))) {
-            double x0 = a, x1 = b, r0 = ra;
-            for (int it = 0; it < 200; it++) {
-                double mid = 0.5 * (x0 + x1);
-                if (mid <= x0 || mid >= x1) break;
-                double rm = scalar_r(c, l, mid);
-                if (rm == 0.0) { x0 = x1 = mid; break; }
-                if ((rm < 0.0) == (r0 < 0.0)) { x0 = mid; r0 = rm; } else x1 = mid;
-            }
-            root = 0.5 * (x0 + x1); found = 1;
-        }
-        if (found && fabs(root - cur) < bestd) { bestd = fabs(root - cur); best = root; }
-        a = b; ra = rb;
-    }
-    if (ra == 0.0 && fabs(a - cur) < bestd) best = a;
-    L->phi[0] = best;
-}
-
+/* (Sec. 5); here the smoother itself is iterated coarse_iters times, with   */
+/* a relative stop.  A grid of one cell has no interior face: the discrete  */
+/* curvature operator (eq. abcdrc) vanishes there, and with it the smooth    */
+/* error components that a coarse grid exists to correct (Sec. 3.1); its    */
+/* scalar equation carries only the fit term, which with rows scaled by     */
+/* delta_eps is a constant and has no solution in general.  Such a grid     */
+/* therefore returns the state it received: a zero coarse correction.       */
 static void coarsest(or_ctx *c, int l)
 {
     or_level *L = &c->lev[l];
-    if (L->n * L->m == 1) { scalar_solve(c, l); return; }
+    if (L->n * L->m == 1) return;                 /* no interior face: zero correction */
     size_t N = (size_t)L->n * L->m;
     double *x0 = dalloc(N), *prev = dalloc(N);
     memcpy(x0, L->phi, sizeof(double) * N);

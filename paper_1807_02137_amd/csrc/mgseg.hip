@@ -143,6 +143,31 @@ int host_hull(const std::vector<double> &pts, std::vector<double> &hull)
     return (int)H.size();
 }
 
+// the hull as device edges (start, unit direction, length, outward normal and
+// its offset) followed by its vertices: edges[8 ne] then vertices[2 hv];
+// ne = hv for a polygon, 1 for a segment, 0 for a point
+int hull_geometry(const std::vector<double> &hull, int hv, std::vector<double> &out, int &ne, int &closed)
+{
+    out.clear();
+    closed = hv >= 3;
+    ne = hv >= 3 ? hv : (hv == 2 ? 1 : 0);
+    double cr = 0.0, cc = 0.0;
+    for (int v = 0; v < hv; v++) { cr += hull[2 * v] / hv; cc += hull[2 * v + 1] / hv; }
+    for (int e = 0; e < ne; e++) {
+        const int f = (e + 1) % hv;
+        const double ar = hull[2 * e], ac = hull[2 * e + 1];
+        const double dr = hull[2 * f] - ar, dc = hull[2 * f + 1] - ac, len = std::hypot(dr, dc);
+        const double ur = dr / len, uc = dc / len;
+        double nr = uc, nc = -ur;
+        // outward: away from the vertices' centroid (a polygon), either side (a segment)
+        if (closed && nr * (cr - ar) + nc * (cc - ac) > 0.0) { nr = -nr; nc = -nc; }
+        const double e8[8] = {ar, ac, ur, uc, len, nr, nc, nr * ar + nc * ac};
+        out.insert(out.end(), e8, e8 + 8);
+    }
+    out.insert(out.end(), hull.begin(), hull.begin() + 2 * hv);
+    return ne;
+}
+
 double host_area(const std::vector<double> &h, int hv)
 {
     if (hv < 3) return 0.0;
@@ -478,17 +503,10 @@ void coarsest(mgseg_ctx *c, int l)
 {
     Level &L = c->lev[l];
     const bool dev = devm(c);
-    if (L.n * L.m == 1 && !(dev && l == 0)) {
-        ScalarArgs S;
-        S.phi = L.P[0]; S.F = dev ? L.G : L.F; S.fit = L.fit;
-        S.lo = l > 0 ? L.lo : nullptr; S.hi = l > 0 ? L.hi : nullptr;
-        S.base = dev ? L.phic : nullptr;
-        S.h2 = L.h * L.h; S.A1 = c->A1; S.nu = c->p.nu; S.eps = c->p.eps; S.M = c->p.M;
-        S.model = c->p.model; S.scaled = c->p.scaled;
-        hipLaunchKernelGGL(k_scalar_solve, dim3(1), dim3(64), 0, c->s, S);
-        chk(c);
-        return;
-    }
+    // a grid of one cell has no interior face, so the curvature operator (and the
+    // smooth error a coarse grid corrects) vanishes there: it returns the state it
+    // received, a zero coarse correction
+    if (L.n * L.m == 1) return;
     if (lds_level(c, l)) {
         // one wave for a grid of one band, else one band per wave of 512 threads
         const CoarseArgs C = coarse_args(c, l, c->p.coarse_iters, c->p.coarse_rtol);
@@ -868,7 +886,7 @@ mgseg_status mgseg_setup(const float *image_dev, int n, int m, int pitch, const 
         c->flags = dalloc<int>(c, 4);
         zb = dalloc<double>(c, N); t64 = dalloc<double>(c, N);
         c->mk_d = dalloc<double>(c, 2 * (size_t)k);
-        c->hull_d = dalloc<double>(c, 2 * (size_t)k + 2);
+        c->hull_d = dalloc<double>(c, 10 * (size_t)k + 10);
         ker_d = dalloc<double>(c, ker.size());
     };
     carve();
@@ -894,21 +912,29 @@ mgseg_status mgseg_setup(const float *image_dev, int n, int m, int pitch, const 
     c->k = k;
     c->hv = host_hull(mk, hull);
     c->A1 = host_area(hull, c->hv) * c->h0 * c->h0;
+    std::vector<double> geo;
+    int ne = 0, closed = 0;
+    hull_geometry(hull, c->hv, geo, ne, closed);
     (void)hipMemcpyAsync(c->mk_d, mk.data(), sizeof(double) * mk.size(), hipMemcpyHostToDevice, c->s);
-    if (!hull.empty())
-        (void)hipMemcpyAsync(c->hull_d, hull.data(), sizeof(double) * hull.size(), hipMemcpyHostToDevice, c->s);
+    if (!geo.empty())
+        (void)hipMemcpyAsync(c->hull_d, geo.data(), sizeof(double) * geo.size(), hipMemcpyHostToDevice, c->s);
     (void)hipMemcpyAsync(ker_d, ker.data(), sizeof(double) * ker.size(), hipMemcpyHostToDevice, c->s);
 
     Level &L0 = c->lev[0];
     dim3 g = grid2(n, m);
     hipLaunchKernelGGL(k_blur_rows, g, dim3(256), 0, c->s, image_dev, pitch, t64, n, m, ker_d, R);
     hipLaunchKernelGGL(k_blur_cols, g, dim3(256), 0, c->s, t64, zb, n, m, ker_d, R);
-    SetupArgs S;
-    S.zb = zb; S.z = image_dev; S.pz = pitch; S.mk = c->mk_d; S.k = k; S.hull = c->hull_d; S.hv = c->hv;
-    S.h0 = c->h0; S.beta = p->beta; S.sigma_d = p->sigma_d; S.M = p->M; S.model = p->model; S.n = n; S.m = m;
-    S.g64 = c->g64; S.d64 = c->d64; S.w64 = c->w64; S.phi64 = c->phi64;
+    const dim3 gt((m + TILE - 1) / TILE, (n + TILE - 1) / TILE);
+    hipLaunchKernelGGL(k_edge_detector, gt, dim3(256), 0, c->s, zb, n, m, p->beta, c->g64);
+    MarkerArgs S;
+    S.mk = c->mk_d; S.k = k;
+    S.edge = reinterpret_cast<const HullEdge *>(c->hull_d); S.ne = ne;
+    S.vtx = c->hull_d + 8 * (size_t)ne; S.nv = c->hv; S.closed = closed;
+    S.h0 = c->h0; S.sigma_d = p->sigma_d; S.M = p->M; S.model = p->model; S.n = n; S.m = m;
+    S.g64 = c->g64; S.z = image_dev; S.pz = pitch;
+    S.d64 = c->d64; S.w64 = c->w64; S.phi64 = c->phi64;
     S.w32 = L0.w; S.d32 = L0.d; S.z32 = L0.z; S.phi32 = L0.P[0]; S.p32 = L0.prm;
-    hipLaunchKernelGGL(k_setup_maps, g, dim3(256), 0, c->s, S);
+    hipLaunchKernelGGL(k_marker_maps, g, dim3(256), 0, c->s, S);
     for (int l = 1; l < Lv; l++) {
         Level &Lf = c->lev[l - 1], &Lc = c->lev[l];
         dim3 gc = grid2(Lc.n, Lc.m);
@@ -995,8 +1021,10 @@ mgseg_status mgseg_get_stats(mgseg_ctx *c, mgseg_stats *s)
     E.phi = c->phi64; E.g = c->g64; E.d = c->d64; E.dsc = c->dsc + DS_C1; E.z = L0.z; E.pz = L0.prm;
     E.n = c->n; E.m = c->m; E.model = c->p.model; E.h = c->h0; E.mu = c->p.mu; E.lambda1 = c->p.lambda1;
     E.lambda2 = c->p.lambda2; E.theta = c->p.theta; E.eps = c->p.eps; E.partial = c->part;
-    hipLaunchKernelGGL(k_energy, dim3(nb), dim3(256), 0, c->s, E);
-    hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(256), 0, c->s, c->part, nb, c->h0 * c->h0, (double)N, c->p.model,
+    const dim3 ge((c->m + TILE - 1) / TILE, (c->n + TILE - 1) / TILE);
+    const int nbe = (int)(ge.x * ge.y);
+    hipLaunchKernelGGL(k_energy, ge, dim3(256), 0, c->s, E);
+    hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(256), 0, c->s, c->part, nbe, c->h0 * c->h0, (double)N, c->p.model,
                        c->p.nu, c->A1, c->dsc + DS_ENERGY);
     hipLaunchKernelGGL(k_count_labels, dim3(nb), dim3(256), 0, c->s, L0.lab, L0.prm, c->n, c->m, c->part + 2 * RED_BLOCKS);
     chk(c);

@@ -37,69 +37,104 @@ __global__ void k_blur_cols(const double *in, double *out, int n, int m, const d
     out[(long long)i * m + j] = s;
 }
 
-struct SetupArgs {
-    const double *zb;       // blurred image (dense n x m)
-    const float *z; int pz;
-    const double *mk; int k;        // markers (row, col) pixel coords
-    const double *hull; int hv;     // convex hull vertices
-    double h0, beta, sigma_d, M;
+// Setup maps of the finest grid (Sec. 2.2 and Sec. 5), computed per cell:
+//  g   : the edge detector 1/(1 + beta |grad(G_sigma * z)|^2), the gradient by
+//        central differences of the blurred image per pixel, mirrored edges;
+//  d   : the marker distance function, the product over the markers of
+//        1 - exp(-|x_k - x|^2 / (2 sigma_d^2)) in domain units (formed with
+//        expm1, exact where a marker is close);
+//  w   : g (Spencer-Chen) or d g (Rada-Chen), the weight of the curvature term;
+//  phi0: the signed distance in pixels to the boundary of the marker polygon
+//        (the convex hull of the markers), positive inside, clamped to [-M, M].
+// The hull reaches the device as its edges: start vertex, unit direction,
+// length, and the unit outward normal with its offset, so that the line
+// through an edge is {x : nrm . x = off}.  For a closed hull (three or more
+// vertices) a point is inside when it lies on the inner side of every edge
+// line, and its distance to the boundary is then the least distance to an
+// edge line (convexity).  Outside, the nearest boundary point is either a
+// vertex or the foot of the perpendicular on an edge whose foot falls within
+// it.  One or two markers give an open hull (a point or a segment): every
+// cell is outside.
+struct HullEdge {
+    double ar, ac;      // start vertex (row, col)
+    double ur, uc;      // unit direction
+    double len;         // length
+    double nr, nc;      // unit outward normal
+    double off;         // nrm . start vertex
+};
+#define MG_MAX_HULL 64
+
+struct MarkerArgs {
+    const double *mk; int k;          // markers (row, col) in pixels
+    const HullEdge *edge; int ne;     // hull edges (a segment: one edge; a point: none)
+    const double *vtx; int nv;        // hull vertices (row, col)
+    int closed;                       // 1: the hull is a polygon with an inside
+    double h0, sigma_d, M;
     int model, n, m;
-    double *g64, *d64, *w64, *phi64;   // dense n x m
+    const double *g64;
+    const float *z; int pz;
+    double *d64, *w64, *phi64;
     float *w32, *d32, *z32, *phi32; int p32;
 };
 
-__device__ double seg_dist64(double px, double py, double ax, double ay, double bx, double by)
+// signed distance (pixels) of the point (pr, pc) to the hull boundary, + inside
+__device__ double hull_signed_distance(const MarkerArgs &A, double pr, double pc)
 {
-    double vx = bx - ax, vy = by - ay, wx = px - ax, wy = py - ay;
-    double L2 = vx * vx + vy * vy;
-    double t = L2 > 0.0 ? (wx * vx + wy * vy) / L2 : 0.0;
-    t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
-    double dx = px - (ax + t * vx), dy = py - (ay + t * vy);
-    return sqrt(dx * dx + dy * dy);
+    double worst = -1e300;            // largest signed distance to an edge line (outward positive)
+    double nearest = 1e300;           // least distance to a boundary point found so far
+    for (int e = 0; e < A.ne; e++) {
+        const HullEdge E = A.edge[e];
+        const double rr = pr - E.ar, rc = pc - E.ac;
+        const double side = fma(E.nr, pr, fma(E.nc, pc, -E.off));
+        worst = fmax(worst, side);
+        const double along = fma(rr, E.ur, rc * E.uc);
+        if (along > 0.0 && along < E.len) nearest = fmin(nearest, fabs(side));
+    }
+    if (A.closed && worst <= 0.0) return -worst;
+    for (int v = 0; v < A.nv; v++) nearest = fmin(nearest, hypot(pr - A.vtx[2 * v], pc - A.vtx[2 * v + 1]));
+    return -nearest;
 }
 
-// signed distance (pixels) to the marker-polygon boundary, + inside (Sec. 5)
-__device__ double hull_sd(const double *hull, int hv, double pr, double pc)
+// edge detector from the blurred image: a 32 x 32 tile with a mirrored one-cell
+// halo staged in LDS, each cell's four neighbours read from there
+__global__ void __launch_bounds__(256) k_edge_detector(const double *zb, int n, int m, double beta, double *g64)
 {
-    if (hv == 0) return -1e30;
-    if (hv == 1) return -sqrt((pr - hull[0]) * (pr - hull[0]) + (pc - hull[1]) * (pc - hull[1]));
-    double dmin = 1e300;
-    bool inside = hv >= 3;
-    for (int t = 0; t < hv; t++) {
-        const double *a = hull + 2 * t, *b = hull + 2 * ((t + 1) % hv);
-        double dd = seg_dist64(pr, pc, a[0], a[1], b[0], b[1]);
-        dmin = fmin(dmin, dd);
-        double cr = (b[0] - a[0]) * (pc - a[1]) - (b[1] - a[1]) * (pr - a[0]);
-        if (cr < 0.0) inside = false;
-        if (hv == 2) break;
+    __shared__ double tile[TILE + 2][TILE + 3];
+    const int i0 = blockIdx.y * TILE, j0 = blockIdx.x * TILE;
+    for (int t = threadIdx.x; t < (TILE + 2) * (TILE + 2); t += blockDim.x) {
+        const int ti = t / (TILE + 2), tj = t % (TILE + 2);
+        const int i = mg_mirror(i0 + ti - 1, n), j = mg_mirror(j0 + tj - 1, m);   // halo past the tile's cells unused
+        tile[ti][tj] = zb[(long long)i * m + j];
     }
-    return inside ? dmin : -dmin;
+    __syncthreads();
+    for (int t = threadIdx.x; t < TILE * TILE; t += blockDim.x) {
+        const int ti = t / TILE, tj = t % TILE, i = i0 + ti, j = j0 + tj;
+        if (i >= n || j >= m) continue;
+        const double hx = 0.5 * (tile[ti + 1][tj + 2] - tile[ti + 1][tj]);
+        const double hy = 0.5 * (tile[ti + 2][tj + 1] - tile[ti][tj + 1]);
+        g64[(long long)i * m + j] = 1.0 / fma(beta, fma(hx, hx, hy * hy), 1.0);
+    }
 }
 
-__global__ void k_setup_maps(SetupArgs S)
+// marker distance function, curvature weight and the initial level set
+__global__ void k_marker_maps(MarkerArgs A)
 {
-    int j = blockIdx.x * blockDim.x + threadIdx.x, i = blockIdx.y;
-    if (j >= S.m || i >= S.n) return;
-    const int n = S.n, m = S.m;
-    long long q = (long long)i * m + j;
-    int jp = mg_mirror(j + 1, m), jm = mg_mirror(j - 1, m), ip = mg_mirror(i + 1, n), im = mg_mirror(i - 1, n);
-    double gx = (S.zb[(long long)i * m + jp] - S.zb[(long long)i * m + jm]) / 2.0;
-    double gy = (S.zb[(long long)ip * m + j] - S.zb[(long long)im * m + j]) / 2.0;
-    double g = 1.0 / (1.0 + S.beta * (gx * gx + gy * gy));
-    double prod = 1.0;
-    for (int t = 0; t < S.k; t++) {
-        double dy = (S.mk[2 * t] - (i + 0.5)) * S.h0;
-        double dx = (S.mk[2 * t + 1] - (j + 0.5)) * S.h0;
-        prod *= 1.0 - exp(-(dx * dx + dy * dy) / (2.0 * S.sigma_d * S.sigma_d));
+    const int j = blockIdx.x * blockDim.x + threadIdx.x, i = blockIdx.y;
+    if (j >= A.m || i >= A.n) return;
+    const double yc = i + 0.5, xc = j + 0.5;
+    const double inv2s2 = 0.5 / (A.sigma_d * A.sigma_d);
+    double d = 1.0;
+    for (int t = 0; t < A.k; t++) {
+        const double dy = (yc - A.mk[2 * t]) * A.h0, dx = (xc - A.mk[2 * t + 1]) * A.h0;
+        d *= -expm1(-fma(dx, dx, dy * dy) * inv2s2);
     }
-    double w = (S.model == 1) ? prod * g : g;
-    double ph = hull_sd(S.hull, S.hv, i + 0.5, j + 0.5);
-    ph = ph < -S.M ? -S.M : (ph > S.M ? S.M : ph);
-    S.g64[q] = g; S.d64[q] = prod; S.w64[q] = w; S.phi64[q] = ph;
-    long long q32 = (long long)i * S.p32 + j;
-    S.w32[q32] = (float)w; S.d32[q32] = (float)prod;
-    S.z32[q32] = S.z[(long long)i * S.pz + j];
-    S.phi32[q32] = (float)ph;
+    const long long q = (long long)i * A.m + j, q32 = (long long)i * A.p32 + j;
+    const double g = A.g64[q];
+    const double w = A.model == 1 ? d * g : g;
+    const double phi = fmin(A.M, fmax(-A.M, hull_signed_distance(A, yc, xc)));
+    A.d64[q] = d; A.w64[q] = w; A.phi64[q] = phi;
+    A.d32[q32] = (float)d; A.w32[q32] = (float)w; A.phi32[q32] = (float)phi;
+    A.z32[q32] = A.z[(long long)i * A.pz + j];
 }
 
 // ==========================================================================
@@ -545,66 +580,6 @@ __global__ void k_eta(const double *phi64, const double *prev, long long N, doub
     if (tid == 0) { partial[2 * blockIdx.x] = r0[0]; partial[2 * blockIdx.x + 1] = r1[0]; }
 }
 
-// ==========================================================================
-// 1x1 coarsest grid: N = -delta(phi)(fit + s(phi)) has no stencil (S = 0);
-// the box-constrained scalar equation N(phi) = F is solved directly: among
-// its solutions (interior roots, or a bound where the residual pushes
-// outward) the one nearest the current value (FP64, one thread).  In the
-// deviation form phi = b + e, F = N(b) + G, the bounds are those of e shifted
-// by b, and e = phi - b is stored.
-struct ScalarArgs {
-    float *phi; const float *F, *fit, *lo, *hi;
-    const float *base;              // deviation form: base (phi then holds e); null otherwise
-    double h2, A1, nu, eps, M;
-    int model, scaled;
-};
-__device__ double scalar_N(const ScalarArgs &S, double phi)
-{
-    double s = 0.0;
-    if (S.model == 1) s = 2.0 * S.nu * (S.h2 * mg_heav64(phi, S.eps) - S.A1);
-    double dl = S.scaled ? 1.0 : mg_delta64(phi, S.eps);
-    return -dl * ((double)S.fit[0] + s);
-}
-__global__ void k_scalar_solve(ScalarArgs S)
-{
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const double b = S.base ? (double)S.base[0] : 0.0;
-    const double Fv = S.base ? (double)S.F[0] + scalar_N(S, b) : (double)S.F[0];
-    auto R = [&](double x) { return Fv - scalar_N(S, x); };
-    double lo = S.lo ? b + (double)S.lo[0] : -S.M, hi = S.hi ? b + (double)S.hi[0] : S.M;
-    double cur = b + (double)S.phi[0], best = cur, bestd = 1e300;
-    const int NS = 4096;
-    if (R(lo) >= 0.0) { best = lo; bestd = fabs(cur - lo); }
-    if (R(hi) <= 0.0 && fabs(hi - cur) < bestd) { best = hi; bestd = fabs(hi - cur); }
-    double a = lo, ra = R(a);
-    for (int t = 1; t <= NS && hi > lo; t++) {
-        double bb = lo + (hi - lo) * t / NS, rb = R(bb);
-        double root = 0.0;
-        bool found = false;
-        if (ra == 0.0) { root = a; found = true; }
-        else if (rb != 0.0 && ((ra < 0.0) != (rb < 0.0))) {
-            double x0 = a, x1 = bb, r0 = ra;
-            for (int it = 0; it < 200; it++) {
-                double mid = 0.5 * (x0 + x1);
-                if (mid <= x0 || mid >= x1) break;
-                double rm = R(mid);
-                if (rm == 0.0) { x0 = x1 = mid; break; }
-                if ((rm < 0.0) == (r0 < 0.0)) { x0 = mid; r0 = rm; } else x1 = mid;
-            }
-            root = 0.5 * (x0 + x1); found = true;
-        }
-        if (found && fabs(root - cur) < bestd) { bestd = fabs(root - cur); best = root; }
-        a = bb; ra = rb;
-    }
-    if (ra == 0.0 && fabs(a - cur) < bestd) best = a;
-    if (S.base) {
-        float e = (float)(best - b);
-        e = fminf(fmaxf(e, S.lo[0]), S.hi[0]);
-        S.phi[0] = e;
-    } else {
-        S.phi[0] = (float)best;
-    }
-}
 
 // ==========================================================================
 // Deviation form (mixed-precision mode).  On every level the state is
@@ -1212,37 +1187,55 @@ struct EnergyArgs {
     double h, mu, lambda1, lambda2, theta, eps;
     double *partial;
 };
+// The model's discrete energy (eq. scfunc / rcfunc) at the FP64 finest phi:
+// per cell, the length term mu w delta(phi) |grad phi| (|grad H(phi)| by the
+// chain rule, central differences in domain units, mirrored edges) plus the
+// region terms H (lambda1 (z - c1)^2 [+ theta d]) + (1 - H) lambda2 (z - c2)^2,
+// times the cell area h^2 (applied in k_energy_final with the Rada-Chen area
+// penalty).  One 32 x 32 tile per block with its mirrored halo of phi in LDS;
+// each block writes the sums of its tile (energy, sum of H) as one partial.
 __global__ void __launch_bounds__(256) k_energy(EnergyArgs A)
 {
-    __shared__ double r0[256], r1[256];
-    const int tid = threadIdx.x;
-    const long long N = (long long)A.n * A.m;
-    const double c1 = A.dsc[0], c2 = A.dsc[1];
-    double e = 0.0, sh = 0.0;
-    for (long long t = (long long)blockIdx.x * blockDim.x + tid; t < N; t += (long long)gridDim.x * blockDim.x) {
-        const int i = (int)(t / A.m), j = (int)(t % A.m);
-        const double ph = A.phi[t];
-        const double gx = (A.phi[(long long)i * A.m + mg_mirror(j + 1, A.m)] - A.phi[(long long)i * A.m + mg_mirror(j - 1, A.m)]) /
-                          (2.0 * A.h);
-        const double gy = (A.phi[(long long)mg_mirror(i + 1, A.n) * A.m + j] - A.phi[(long long)mg_mirror(i - 1, A.n) * A.m + j]) /
-                          (2.0 * A.h);
-        const double H = mg_heav64(ph, A.eps);
-        const double zz = (double)A.z[(long long)i * A.pz + j];
-        const double a = zz - c1, b = zz - c2;
-        const double w = A.model == 1 ? A.g[t] * A.d[t] : A.g[t];
-        double v = A.mu * w * mg_delta64(ph, A.eps) * sqrt(gx * gx + gy * gy) + A.lambda1 * a * a * H +
-                   A.lambda2 * b * b * (1.0 - H);
-        if (A.model == 0) v += A.theta * A.d[t] * H;
-        e += v;
-        sh += H;
+    __shared__ double ph[TILE + 2][TILE + 3];
+    __shared__ double wsum[2][256 / 64];
+    const int i0 = blockIdx.y * TILE, j0 = blockIdx.x * TILE, n = A.n, m = A.m;
+    for (int t = threadIdx.x; t < (TILE + 2) * (TILE + 2); t += blockDim.x) {
+        const int ti = t / (TILE + 2), tj = t % (TILE + 2);
+        ph[ti][tj] = A.phi[(long long)mg_mirror(i0 + ti - 1, n) * m + mg_mirror(j0 + tj - 1, m)];
     }
-    r0[tid] = e; r1[tid] = sh;
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (tid < s) { r0[tid] += r0[tid + s]; r1[tid] += r1[tid + s]; }
-        __syncthreads();
+    const double c1 = A.dsc[0], c2 = A.dsc[1], inv2h = 0.5 / A.h;
+    double en = 0.0, hs = 0.0;
+    for (int t = threadIdx.x; t < TILE * TILE; t += blockDim.x) {
+        const int ti = t / TILE, tj = t % TILE, i = i0 + ti, j = j0 + tj;
+        if (i >= n || j >= m) continue;
+        const long long q = (long long)i * m + j;
+        const double p0 = ph[ti + 1][tj + 1];
+        const double px = (ph[ti + 1][tj + 2] - ph[ti + 1][tj]) * inv2h;
+        const double py = (ph[ti + 2][tj + 1] - ph[ti][tj + 1]) * inv2h;
+        const double heav = mg_heav64(p0, A.eps);
+        const double zv = (double)A.z[(long long)i * A.pz + j];
+        const double in_term = A.lambda1 * (zv - c1) * (zv - c1) + (A.model == 0 ? A.theta * A.d[q] : 0.0);
+        const double out_term = A.lambda2 * (zv - c2) * (zv - c2);
+        const double weight = A.model == 1 ? A.g[q] * A.d[q] : A.g[q];
+        en += A.mu * weight * mg_delta64(p0, A.eps) * sqrt(px * px + py * py) + heav * in_term + (1.0 - heav) * out_term;
+        hs += heav;
     }
-    if (tid == 0) { A.partial[2 * blockIdx.x] = r0[0]; A.partial[2 * blockIdx.x + 1] = r1[0]; }
+    // wave sums by lane exchange, then the block's four waves in order
+    for (int o = 32; o > 0; o >>= 1) {
+        en += __shfl_down(en, o, 64);
+        hs += __shfl_down(hs, o, 64);
+    }
+    const int wv = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) { wsum[0][wv] = en; wsum[1][wv] = hs; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double e = 0.0, s = 0.0;
+        for (int k = 0; k < (int)(blockDim.x >> 6); k++) { e += wsum[0][k]; s += wsum[1][k]; }
+        const int b = blockIdx.y * gridDim.x + blockIdx.x;
+        A.partial[2 * b] = e;
+        A.partial[2 * b + 1] = s;
+    }
 }
 
 // adds the nb partials of k_energy in a fixed order: out = h^2 sum + (Rada-Chen) nu (a1^2 + a2^2),
