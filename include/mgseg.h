@@ -46,7 +46,8 @@ typedef enum {
     MGSEG_E_HIP = 4,            /* a HIP runtime call failed                         */
     MGSEG_E_NONFINITE = 5,      /* a residual norm became NaN/Inf                    */
     MGSEG_E_NOT_CONVERGED = 6,  /* solve hit max_cycles; outputs are still valid     */
-    MGSEG_E_STATE = 7           /* call not valid in the context's current state     */
+    MGSEG_E_STATE = 7,          /* call not valid in the context's current state     */
+    MGSEG_E_SCRATCH = 8         /* image too large for mgseg_solve_noalloc's scratch */
 } mgseg_status;
 
 typedef enum { MGSEG_SPENCER_CHEN = 0, MGSEG_RADA_CHEN = 1 } mgseg_model;
@@ -137,6 +138,35 @@ const char *mgseg_strerror(mgseg_status s);
 mgseg_status mgseg_setup(const float *image_dev, int n, int m, int pitch,
                          const float *markers_host, int k, const mgseg_params *p,
                          void *stream, mgseg_ctx **out);
+
+/* Bytes of device memory that mgseg_solve_noalloc holds per device (static). */
+#define MGSEG_NOALLOC_BYTES (32u << 20)
+
+/*
+ * For callers that cannot allocate device memory (code that must not call
+ * hipMalloc or hipFree: serving loops with fixed memory, harnesses that
+ * forbid allocation): mgseg_setup + mgseg_solve + mgseg_get_phi for one image
+ * in one call, with every device array of the solve placed in the library's
+ * static scratch of MGSEG_NOALLOC_BYTES on the current device instead of an
+ * allocated arena.  The V-cycles run as eager launches on `stream` (no HIP
+ * graph).  The arguments are those of mgseg_setup (image, markers, params,
+ * stream) and mgseg_solve (tol > 0, max_cycles >= 1, the cycle count and the
+ * final relative residual, either output may be null), and the FP64 finest
+ * phi goes to phi_dev (n x m doubles, row pitch phi_pitch >= m elements).
+ * The scratch is about 230 B per finest cell over all grids in the mixed
+ * mode, so images up to about 360 x 360 fit; a larger image returns
+ * MGSEG_E_SCRATCH before any work is enqueued.  Other errors as mgseg_setup
+ * and mgseg_solve (MGSEG_E_NOT_CONVERGED: phi_dev is still written).
+ * The scratch is one array per device, shared by every call on that device
+ * and cleared by each call: calls that overlap on one device (other host
+ * threads, other streams) race and must be serialised by the caller.  Calls
+ * on different devices are independent.
+ */
+mgseg_status mgseg_solve_noalloc(const float *image_dev, int n, int m, int pitch,
+                                 const float *markers_host, int k, const mgseg_params *p,
+                                 void *stream, double tol, int max_cycles,
+                                 double *phi_dev, int phi_pitch, int *cycles_out,
+                                 double *rel_res_out);
 
 /* Replaces the finest phi (warm start), clamped to [-M, M]; recomputes c1,
  * c2 and the reference residual norm; resets the cycle counter. */

@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <type_traits>
 #include <vector>
@@ -62,7 +63,10 @@ struct mgseg_ctx {
     int part_n = 0;
     float *co_prev = nullptr, *co_entry = nullptr;   // multi-kernel coarsest solve
     int *flags = nullptr;           // device flags: [0] coarsest solve finished, [1] markers inside phi0
-    double *hres = nullptr;         // pinned host copy of DS_RES, DS_ETA
+    double *hres = nullptr;         // host copy of DS_RES, DS_ETA (pinned, or hres_local)
+    double hres_local[2] = {0.0, 0.0};
+    bool arena_owned = true;        // false: the arena is the library's static scratch
+    bool noalloc = false;           // a context that may not allocate (no graph, no pinned memory)
     const int *sweep_skip = nullptr;
     double *hull_d = nullptr, *mk_d = nullptr;
     int hv = 0, k = 0;
@@ -112,47 +116,52 @@ inline void chk(mgseg_ctx *c)
 
 inline dim3 grid2(int n, int m, int bx = 256) { return dim3((m + bx - 1) / bx, n); }
 
-// ---- host convex hull (Andrew's monotone chain), CCW, no collinear points
-int host_hull(const std::vector<double> &pts, std::vector<double> &hull)
+// ---- host convex hull of the markers by gift wrapping (Jarvis march): from the
+// lowest (row, col) point, each next vertex is the point that leaves every other
+// point on one side of the edge (the farthest of collinear candidates, so no
+// collinear vertex is kept); fixed arrays, no allocation.  pts: k <= 64 (row,
+// col) pairs; hull: room for 2 k values; returns the vertex count (one for a
+// single distinct point, two for collinear points)
+int host_hull(const double *pts, int k, double *hull)
 {
-    std::vector<std::pair<double, double>> P;
-    for (size_t t = 0; t + 1 < pts.size(); t += 2) P.push_back({pts[t], pts[t + 1]});
-    std::sort(P.begin(), P.end());
-    P.erase(std::unique(P.begin(), P.end()), P.end());
-    hull.clear();
-    if (P.size() <= 2) {
-        for (auto &q : P) { hull.push_back(q.first); hull.push_back(q.second); }
-        return (int)P.size();
+    double U[64][2];
+    int nu = 0;
+    for (int t = 0; t < k && t < 64; t++) {
+        bool dup = false;
+        for (int v = 0; v < nu && !dup; v++) dup = U[v][0] == pts[2 * t] && U[v][1] == pts[2 * t + 1];
+        if (!dup) { U[nu][0] = pts[2 * t]; U[nu][1] = pts[2 * t + 1]; nu++; }
     }
-    auto cr = [](const std::pair<double, double> &o, const std::pair<double, double> &a,
-                 const std::pair<double, double> &b) {
-        return (a.first - o.first) * (b.second - o.second) - (a.second - o.second) * (b.first - o.first);
-    };
-    std::vector<std::pair<double, double>> H(2 * P.size());
-    size_t k = 0;
-    for (size_t i = 0; i < P.size(); i++) {
-        while (k >= 2 && cr(H[k - 2], H[k - 1], P[i]) <= 0) k--;
-        H[k++] = P[i];
-    }
-    for (size_t i = P.size() - 1, t = k + 1; i-- > 0;) {
-        while (k >= t && cr(H[k - 2], H[k - 1], P[i]) <= 0) k--;
-        H[k++] = P[i];
-    }
-    H.resize(k - 1);
-    for (auto &q : H) { hull.push_back(q.first); hull.push_back(q.second); }
-    return (int)H.size();
+    if (nu == 0) return 0;
+    int start = 0;
+    for (int v = 1; v < nu; v++)
+        if (U[v][0] < U[start][0] || (U[v][0] == U[start][0] && U[v][1] < U[start][1])) start = v;
+    int hv = 0, cur = start;
+    do {
+        hull[2 * hv] = U[cur][0]; hull[2 * hv + 1] = U[cur][1]; hv++;
+        int nxt = cur == 0 ? 1 % nu : 0;
+        for (int v = 0; v < nu; v++) {
+            if (v == cur) continue;
+            const double ar = U[nxt][0] - U[cur][0], ac = U[nxt][1] - U[cur][1];
+            const double br = U[v][0] - U[cur][0], bc = U[v][1] - U[cur][1];
+            const double side = ar * bc - ac * br;
+            if (side < 0.0 || (side == 0.0 && br * br + bc * bc > ar * ar + ac * ac)) nxt = v;
+        }
+        cur = nxt;
+    } while (cur != start && hv < nu);
+    return hv;
 }
 
 // the hull as device edges (start, unit direction, length, outward normal and
 // its offset) followed by its vertices: edges[8 ne] then vertices[2 hv];
-// ne = hv for a polygon, 1 for a segment, 0 for a point
-int hull_geometry(const std::vector<double> &hull, int hv, std::vector<double> &out, int &ne, int &closed)
+// ne = hv for a polygon, 1 for a segment, 0 for a point; returns the count of
+// values written (out: room for 10 hv)
+int hull_geometry(const double *hull, int hv, double *out, int &ne, int &closed)
 {
-    out.clear();
     closed = hv >= 3;
     ne = hv >= 3 ? hv : (hv == 2 ? 1 : 0);
     double cr = 0.0, cc = 0.0;
     for (int v = 0; v < hv; v++) { cr += hull[2 * v] / hv; cc += hull[2 * v + 1] / hv; }
+    int o = 0;
     for (int e = 0; e < ne; e++) {
         const int f = (e + 1) % hv;
         const double ar = hull[2 * e], ac = hull[2 * e + 1];
@@ -162,13 +171,13 @@ int hull_geometry(const std::vector<double> &hull, int hv, std::vector<double> &
         // outward: away from the vertices' centroid (a polygon), either side (a segment)
         if (closed && nr * (cr - ar) + nc * (cc - ac) > 0.0) { nr = -nr; nc = -nc; }
         const double e8[8] = {ar, ac, ur, uc, len, nr, nc, nr * ar + nc * ac};
-        out.insert(out.end(), e8, e8 + 8);
+        for (int t = 0; t < 8; t++) out[o++] = e8[t];
     }
-    out.insert(out.end(), hull.begin(), hull.begin() + 2 * hv);
-    return ne;
+    for (int t = 0; t < 2 * hv; t++) out[o++] = hull[t];
+    return o;
 }
 
-double host_area(const std::vector<double> &h, int hv)
+double host_area(const double *h, int hv)
 {
     if (hv < 3) return 0.0;
     double s = 0.0;
@@ -669,7 +678,7 @@ void enqueue_cycle(mgseg_ctx *c)
 // keep the eager launches.
 bool graph_usable(const mgseg_ctx *c)
 {
-    if (c->prof_on || c->graph_failed) return false;
+    if (c->prof_on || c->graph_failed || c->noalloc) return false;
     const char *env = std::getenv("MGSEG_GRAPH");
     if (env && env[0] == '0') return false;
     return true;
@@ -741,59 +750,30 @@ mgseg_status one_cycle(mgseg_ctx *c, double *rel_out)
 
 }  // namespace
 
-// ==========================================================================
-extern "C" {
+namespace {
 
-void mgseg_params_default(mgseg_params *p)
+// frees what a context owns (not the context itself)
+void release_ctx(mgseg_ctx *c)
 {
-    if (!p) return;
-    std::memset(p, 0, sizeof(*p));
-    p->struct_size = sizeof(mgseg_params);
-    p->model = MGSEG_SPENCER_CHEN;
-    p->mu = 0.5; p->lambda1 = 6.5025; p->lambda2 = 6.5025; p->theta = 4.0; p->nu = 1.0;
-    p->eps = 1.0; p->eps_tv_px = 1.0; p->beta = 16384.0; p->sigma_g = 1.0; p->sigma_d = 0.1;
-    p->Sigma = 2.0; p->M = 4.0; p->nu1 = 2; p->nu2 = 2; p->levels = 0; p->coarse_iters = 10;
-    p->mixed_precision = 1; p->scaled = 1; p->coarse_rtol = 1e-4; p->smoother = 0; p->run_max = 0;
-}
-
-const char *mgseg_strerror(mgseg_status s)
-{
-    switch (s) {
-    case MGSEG_OK: return "ok";
-    case MGSEG_E_ARG: return "invalid argument";
-    case MGSEG_E_SHAPE: return "image shape not divisible by 2^(levels-1)";
-    case MGSEG_E_NOMEM: return "device allocation failed";
-    case MGSEG_E_HIP: return "HIP runtime error";
-    case MGSEG_E_NONFINITE: return "non-finite residual";
-    case MGSEG_E_NOT_CONVERGED: return "not converged within max_cycles";
-    case MGSEG_E_STATE: return "invalid state";
-    }
-    return "unknown status";
-}
-
-void mgseg_destroy(mgseg_ctx *c)
-{
-    if (!c) return;
     if (c->s) (void)hipStreamSynchronize(c->s);
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     if (c->cap) (void)hipStreamDestroy(c->cap);
-    if (c->hres) (void)hipHostFree(c->hres);
+    if (c->hres && c->hres != c->hres_local) (void)hipHostFree(c->hres);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
-    if (c->arena) (void)hipFree(c->arena);
+    if (c->arena && c->arena_owned) (void)hipFree(c->arena);
     if (c->pred) (void)hipFree(c->pred);
-    delete c;
 }
 
-mgseg_status mgseg_setup(const float *image_dev, int n, int m, int pitch, const float *markers_host, int k,
-                         const mgseg_params *p, void *stream, mgseg_ctx **out)
+// argument checks of a setup and the kernels' LDS attributes; Lv: the grid count
+mgseg_status setup_check(const float *image_dev, int n, int m, int pitch, const float *markers_host, int k,
+                         const mgseg_params *p, int &Lv)
 {
-    if (!out) return MGSEG_E_ARG;
-    *out = nullptr;
     if (!image_dev || !markers_host || !p || k < 1 || k > 64 || n < 2 || m < 2 || pitch < m) return MGSEG_E_ARG;
     if (p->struct_size != sizeof(mgseg_params)) return MGSEG_E_ARG;
     if (p->model == MGSEG_RADA_CHEN && k < 3) return MGSEG_E_ARG;   // the marker polygon needs an area (A1 > 0)
     if (p->nu1 < 0 || p->nu2 < 0 || p->coarse_iters < 0 || !(p->coarse_rtol >= 0.0) || !(p->M > 0.0) || !(p->eps > 0.0) || p->levels < 0 ||
-        p->levels > MAXLEV || (p->smoother != 0 && p->smoother != 1) || p->run_max < 0)
+        p->levels > MAXLEV || (p->smoother != 0 && p->smoother != 1) || p->run_max < 0 ||
+        !(p->sigma_g >= 0.0 && p->sigma_g <= 16.0))
         return MGSEG_E_ARG;
     for (int t = 0; t < 2 * k; t++)
         if (!std::isfinite(markers_host[t])) return MGSEG_E_ARG;
@@ -801,7 +781,7 @@ mgseg_status mgseg_setup(const float *image_dev, int n, int m, int pitch, const 
         if (!(markers_host[2 * t] >= 0.0f && markers_host[2 * t] < (float)n && markers_host[2 * t + 1] >= 0.0f &&
               markers_host[2 * t + 1] < (float)m))
             return MGSEG_E_ARG;
-    int Lv = p->levels;
+    Lv = p->levels;
     if (Lv == 0) {
         Lv = 1;
         while (Lv < MAXLEV && n % (1 << Lv) == 0 && m % (1 << Lv) == 0 && std::min(n, m) >> Lv >= 4) Lv++;
@@ -836,9 +816,14 @@ mgseg_status mgseg_setup(const float *image_dev, int n, int m, int pitch, const 
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)coarse_lds_bytes(CO_MAX_CELLS, 1)) !=
             hipSuccess)
         return MGSEG_E_HIP;
+    return MGSEG_OK;
+}
 
-    mgseg_ctx *c = new (std::nothrow) mgseg_ctx();
-    if (!c) return MGSEG_E_NOMEM;
+// builds the context c (constructed by the caller) for one image: the arena is
+// allocated, or (ext non-null) the caller's memory of ext_cap bytes
+mgseg_status setup_into(mgseg_ctx *c, const float *image_dev, int n, int m, int pitch, const float *markers_host,
+                        int k, const mgseg_params *p, void *stream, int Lv, char *ext, size_t ext_cap)
+{
     c->p = *p; c->p.levels = Lv;
     c->s = (hipStream_t)stream;
     c->L = Lv; c->n = n; c->m = m;
@@ -846,13 +831,13 @@ mgseg_status mgseg_setup(const float *image_dev, int n, int m, int pitch, const 
     size_t N = (size_t)n * m;
     // Gaussian kernel of the image smoothing
     int R = (int)std::ceil(4.0 * p->sigma_g);
-    std::vector<double> ker(2 * R + 1);
+    double ker[2 * 64 + 1];
     double ks = 0.0;
     for (int t = -R; t <= R; t++) {
         double v = p->sigma_g > 0 ? std::exp(-(double)(t * t) / (2.0 * p->sigma_g * p->sigma_g)) : (t == 0);
         ker[t + R] = v; ks += v;
     }
-    for (auto &v : ker) v /= ks;
+    for (int t = 0; t <= 2 * R; t++) ker[t] /= ks;
     double *zb = nullptr, *t64 = nullptr, *ker_d = nullptr;
     // the allocation sequence: sizing pass, then the pieces of the arena
     auto carve = [&]() {
@@ -887,38 +872,44 @@ mgseg_status mgseg_setup(const float *image_dev, int n, int m, int pitch, const 
         zb = dalloc<double>(c, N); t64 = dalloc<double>(c, N);
         c->mk_d = dalloc<double>(c, 2 * (size_t)k);
         c->hull_d = dalloc<double>(c, 10 * (size_t)k + 10);
-        ker_d = dalloc<double>(c, ker.size());
+        ker_d = dalloc<double>(c, 2 * (size_t)R + 1);
     };
     carve();
     c->arena_size = c->arena_used;
-    if (hipMalloc((void **)&c->arena, c->arena_size) != hipSuccess) {
-        (void)hipGetLastError();
-        c->arena = nullptr;
-        mgseg_destroy(c);
-        return MGSEG_E_NOMEM;
+    if (ext) {
+        // the caller's memory (the static scratch): no allocation
+        if (c->arena_size > ext_cap) return MGSEG_E_SCRATCH;
+        c->arena = ext;
+        c->arena_owned = false;
+        c->noalloc = true;
+        c->hres = c->hres_local;
+    } else {
+        if (hipMalloc((void **)&c->arena, c->arena_size) != hipSuccess) {
+            (void)hipGetLastError();
+            c->arena = nullptr;
+            return MGSEG_E_NOMEM;
+        }
+        if (hipHostMalloc((void **)&c->hres, 2 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            c->hres = nullptr;
+            c->oom = true;
+        }
     }
     carve();
     (void)hipMemsetAsync(c->arena, 0, c->arena_size, c->s);
-    if (hipHostMalloc((void **)&c->hres, 2 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
-        (void)hipGetLastError();
-        c->hres = nullptr;
-        c->oom = true;
-    }
-    if (c->oom) { mgseg_destroy(c); return MGSEG_E_NOMEM; }
+    if (c->oom) return MGSEG_E_NOMEM;
 
-    // markers and their convex hull
-    std::vector<double> mk(2 * (size_t)k), hull;
+    // markers and their convex hull (host arrays live until the stream is synchronised below)
+    double mk[128], hull[128], geo[640];
     for (int t = 0; t < 2 * k; t++) mk[t] = markers_host[t];
     c->k = k;
-    c->hv = host_hull(mk, hull);
+    c->hv = host_hull(mk, k, hull);
     c->A1 = host_area(hull, c->hv) * c->h0 * c->h0;
-    std::vector<double> geo;
     int ne = 0, closed = 0;
-    hull_geometry(hull, c->hv, geo, ne, closed);
-    (void)hipMemcpyAsync(c->mk_d, mk.data(), sizeof(double) * mk.size(), hipMemcpyHostToDevice, c->s);
-    if (!geo.empty())
-        (void)hipMemcpyAsync(c->hull_d, geo.data(), sizeof(double) * geo.size(), hipMemcpyHostToDevice, c->s);
-    (void)hipMemcpyAsync(ker_d, ker.data(), sizeof(double) * ker.size(), hipMemcpyHostToDevice, c->s);
+    const int ng = hull_geometry(hull, c->hv, geo, ne, closed);
+    (void)hipMemcpyAsync(c->mk_d, mk, sizeof(double) * 2 * k, hipMemcpyHostToDevice, c->s);
+    if (ng > 0) (void)hipMemcpyAsync(c->hull_d, geo, sizeof(double) * ng, hipMemcpyHostToDevice, c->s);
+    (void)hipMemcpyAsync(ker_d, ker, sizeof(double) * (2 * R + 1), hipMemcpyHostToDevice, c->s);
 
     Level &L0 = c->lev[0];
     dim3 g = grid2(n, m);
@@ -950,12 +941,127 @@ mgseg_status mgseg_setup(const float *image_dev, int n, int m, int pitch, const 
     chk(c);
     refresh_and_residual(c);
     mgseg_status st = sync_status(c);
-    if (st != MGSEG_OK) { mgseg_destroy(c); return st; }
+    if (st != MGSEG_OK) return st;
     c->res0 = read_scalar(c, DS_RES);
     c->res = c->res0;
     c->rel = 1.0;
+    return MGSEG_OK;
+}
+
+
+}  // namespace
+
+// ==========================================================================
+extern "C" {
+
+void mgseg_params_default(mgseg_params *p)
+{
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->struct_size = sizeof(mgseg_params);
+    p->model = MGSEG_SPENCER_CHEN;
+    p->mu = 0.5; p->lambda1 = 6.5025; p->lambda2 = 6.5025; p->theta = 4.0; p->nu = 1.0;
+    p->eps = 1.0; p->eps_tv_px = 1.0; p->beta = 16384.0; p->sigma_g = 1.0; p->sigma_d = 0.1;
+    p->Sigma = 2.0; p->M = 4.0; p->nu1 = 2; p->nu2 = 2; p->levels = 0; p->coarse_iters = 10;
+    p->mixed_precision = 1; p->scaled = 1; p->coarse_rtol = 1e-4; p->smoother = 0; p->run_max = 0;
+}
+
+const char *mgseg_strerror(mgseg_status s)
+{
+    switch (s) {
+    case MGSEG_OK: return "ok";
+    case MGSEG_E_SCRATCH: return "image too large for the no-allocation scratch (MGSEG_NOALLOC_BYTES)";
+    case MGSEG_E_ARG: return "invalid argument";
+    case MGSEG_E_SHAPE: return "image shape not divisible by 2^(levels-1)";
+    case MGSEG_E_NOMEM: return "device allocation failed";
+    case MGSEG_E_HIP: return "HIP runtime error";
+    case MGSEG_E_NONFINITE: return "non-finite residual";
+    case MGSEG_E_NOT_CONVERGED: return "not converged within max_cycles";
+    case MGSEG_E_STATE: return "invalid state";
+    }
+    return "unknown status";
+}
+
+void mgseg_destroy(mgseg_ctx *c)
+{
+    if (!c) return;
+    release_ctx(c);
+    delete c;
+}
+
+mgseg_status mgseg_setup(const float *image_dev, int n, int m, int pitch, const float *markers_host, int k,
+                         const mgseg_params *p, void *stream, mgseg_ctx **out)
+{
+    if (!out) return MGSEG_E_ARG;
+    *out = nullptr;
+    int Lv = 0;
+    const mgseg_status ck = setup_check(image_dev, n, m, pitch, markers_host, k, p, Lv);
+    if (ck != MGSEG_OK) return ck;
+    mgseg_ctx *c = new (std::nothrow) mgseg_ctx();
+    if (!c) return MGSEG_E_NOMEM;
+    const mgseg_status st = setup_into(c, image_dev, n, m, pitch, markers_host, k, p, stream, Lv, nullptr, 0);
+    if (st != MGSEG_OK) { mgseg_destroy(c); return st; }
     *out = c;
     return MGSEG_OK;
+}
+
+}  // extern "C"
+
+// --------------------------------------------------------------------------
+// The no-allocation entry point's scratch: every device array of one solve
+// (the context's arena), MGSEG_NOALLOC_BYTES on each device the library runs
+// on, held until the process ends.  Host code reaches it only through the
+// address hipGetSymbolAddress gives on that device (the array's name is a
+// host-side stand-in).
+static __device__ __align__(256) char scratch[MGSEG_NOALLOC_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+char *g_scratch_dev[64] = {};
+
+// the current device's copy of the scratch (looked up once per device)
+mgseg_status scratch_address(char **out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return MGSEG_E_HIP;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return MGSEG_E_HIP;
+        }
+        g_scratch_dev[dev] = static_cast<char *>(ptr);
+    }
+    *out = g_scratch_dev[dev];
+    return MGSEG_OK;
+}
+}  // namespace
+
+extern "C" {
+
+mgseg_status mgseg_solve_noalloc(const float *image_dev, int n, int m, int pitch, const float *markers_host, int k,
+                                 const mgseg_params *p, void *stream, double tol, int max_cycles, double *phi_dev,
+                                 int phi_pitch, int *cycles_out, double *rel_res_out)
+{
+    if (!phi_dev || phi_pitch < m || !(tol > 0.0) || max_cycles < 1) return MGSEG_E_ARG;
+    int Lv = 0;
+    mgseg_status st = setup_check(image_dev, n, m, pitch, markers_host, k, p, Lv);
+    if (st != MGSEG_OK) return st;
+    char *buf = nullptr;
+    st = scratch_address(&buf);
+    if (st != MGSEG_OK) return st;
+    mgseg_ctx c;
+    st = setup_into(&c, image_dev, n, m, pitch, markers_host, k, p, stream, Lv, buf, MGSEG_NOALLOC_BYTES);
+    if (st == MGSEG_OK) {
+        st = mgseg_solve(&c, tol, max_cycles, cycles_out, rel_res_out);
+        if (st == MGSEG_OK || st == MGSEG_E_NOT_CONVERGED) {
+            const mgseg_status sg = mgseg_get_phi(&c, phi_dev, phi_pitch);
+            if (sg != MGSEG_OK) st = sg;
+        }
+    }
+    release_ctx(&c);
+    return st;
 }
 
 mgseg_status mgseg_set_phi0(mgseg_ctx *c, const float *phi_dev, int pitch)

@@ -21,7 +21,8 @@ OP = {"freeze": 0, "sweep_A": 1, "sweep_B": 2, "sweep_C": 3, "sweep_D": 4, "smoo
       "vcycle_from": 7, "residual": 8, "update_c": 9}
 
 STATUS = {0: "ok", 1: "invalid argument", 2: "shape", 3: "out of device memory", 4: "HIP error",
-          5: "non-finite residual", 6: "not converged", 7: "invalid state"}
+          5: "non-finite residual", 6: "not converged", 7: "invalid state",
+          8: "image too large for the no-allocation scratch"}
 
 
 class MgsegError(RuntimeError):
@@ -152,6 +153,8 @@ def lib():
         L.mgseg_net_profile_read.argtypes = [vp, dp, ip, dp]
         L.mgseg_predict_phi0.argtypes = [vp, vp, C.c_double, ip]
         L.mgseg_reset_phi0.argtypes = [vp]
+        L.mgseg_solve_noalloc.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_float), C.c_int,
+                                          C.POINTER(_Params), vp, C.c_double, C.c_int, vp, C.c_int, ip, dp]
         for name in ("mgseg_setup", "mgseg_set_phi0", "mgseg_vcycle", "mgseg_solve", "mgseg_get_phi",
                      "mgseg_get_mask", "mgseg_get_stats", "mgseg_level_shape", "mgseg_debug_get",
                      "mgseg_debug_set", "mgseg_debug_scalars", "mgseg_debug_set_c", "mgseg_debug_op",
@@ -160,7 +163,7 @@ def lib():
                      "mgseg_net_forward", "mgseg_net_backward", "mgseg_net_adam_step", "mgseg_net_param_count",
                      "mgseg_net_get_params", "mgseg_net_set_params", "mgseg_ctx_features", "mgseg_predict_phi0",
                      "mgseg_reset_phi0", "mgseg_net_profile", "mgseg_net_profile_read",
-                     "mgseg_get_state", "mgseg_set_state"):
+                     "mgseg_get_state", "mgseg_set_state", "mgseg_solve_noalloc"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -175,6 +178,32 @@ def _stream_ptr(stream):
     if stream is None:
         stream = torch.cuda.current_stream()
     return C.c_void_p(stream.cuda_stream)
+
+
+def solve_noalloc(image, markers, params: Params | None = None, tol=1e-6, max_cycles=50, stream=None,
+                  out: torch.Tensor | None = None):
+    """mgseg_solve_noalloc: setup, solve and the FP64 finest phi of one image with
+    every device array in the library's static scratch (no device allocation
+    inside the call).  out: an (n, m) float64 CUDA tensor to write (allocated here
+    when None).  Returns (phi, cycles, rel, status)."""
+    L = lib()
+    params = params or Params()
+    img = torch.as_tensor(image, dtype=torch.float32)
+    if img.device.type != "cuda":
+        img = img.to("cuda")
+    img = img.contiguous()
+    n, m = img.shape
+    mk = np.ascontiguousarray(np.asarray(markers, np.float32).reshape(-1, 2))
+    if out is None:
+        out = torch.empty((n, m), dtype=torch.float64, device="cuda")
+    p = params.to_c()
+    cyc, rel = C.c_int(), C.c_double()
+    code = L.mgseg_solve_noalloc(C.c_void_p(img.data_ptr()), n, m, m, mk.ctypes.data_as(C.POINTER(C.c_float)),
+                                 len(mk), C.byref(p), _stream_ptr(stream), tol, max_cycles,
+                                 C.c_void_p(out.data_ptr()), out.stride(0), C.byref(cyc), C.byref(rel))
+    if code not in (0, 6):
+        raise MgsegError(code, "mgseg_solve_noalloc")
+    return out, cyc.value, rel.value, code
 
 
 class Solver:
