@@ -16,7 +16,7 @@ _SRC = os.path.join(_HERE, "mgseg_oracle.c")
 _LIB = os.path.join(_HERE, "libmgseg_oracle.so")
 
 FIELDS = {"z": 0, "d": 1, "w": 2, "fit": 3, "phi": 4, "F": 5, "A": 6, "B": 7, "C": 8,
-          "D": 9, "S": 10, "f": 11, "g": 12}
+          "D": 9, "S": 10, "f": 11, "g": 12, "lo": 13, "hi": 14, "phic": 15}
 
 
 def build_oracle(force: bool = False) -> str:
@@ -104,7 +104,7 @@ def _load():
         _lib.or_set.argtypes = [C.c_void_p, C.c_int, C.c_int, dp]
         _lib.or_get_labels.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_uint8)]
         _lib.or_set_labels.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_uint8)]
-        for name in ("or_step_freeze", "or_step_coarsest", "or_step_vcycle_level"):
+        for name in ("or_step_freeze", "or_step_coarsest", "or_step_vcycle_level", "or_step_to_coarse"):
             getattr(_lib, name).argtypes = [C.c_void_p, C.c_int]
         _lib.or_step_sweep.argtypes = [C.c_void_p, C.c_int, C.c_int]
         _lib.or_step_smooth.argtypes = [C.c_void_p, C.c_int, C.c_int]
@@ -287,6 +287,10 @@ class Oracle:
 
     def vcycle_level(self, l):
         self.lib.or_step_vcycle_level(self.ctx, l)
+
+    def to_coarse(self, l):
+        """The coarse problem of level l + 1 from level l's state (restriction, bounds, FAS right-hand side)."""
+        self.lib.or_step_to_coarse(self.ctx, l)
 
     def residual(self, l=0, project=True) -> np.ndarray:
         n, m, _ = self.shape(l)

@@ -852,13 +852,13 @@ static void coarse_bounds(or_ctx *c, int l)
         }
 }
 
-static void vcycle_level(or_ctx *c, int l)
+/* the coarse problem of level l + 1 from the state of level l: projected    */
+/* residual, restriction of phi and of the residual, coarse bounds, coarse    */
+/* right-hand side N(R phi) + R r (FAS)                                       */
+static void to_coarse(or_ctx *c, int l)
 {
-    or_level *L = &c->lev[l];
-    if (l == c->L - 1) { coarsest(c, l); return; }
-    smooth(c, l, c->p.nu1);
-    or_level *Lc = &c->lev[l + 1];
-    size_t Nc = (size_t)Lc->n * Lc->m, N = (size_t)L->n * L->m;
+    or_level *L = &c->lev[l], *Lc = &c->lev[l + 1];
+    size_t Nc = (size_t)Lc->n * Lc->m;
     residual(c, l, L->phi, L->F, L->tmp, 1);
     or_restrict(L->phi, L->n, L->m, Lc->phic);
     or_restrict(L->tmp, L->n, L->m, Lc->tmp2);
@@ -866,6 +866,16 @@ static void vcycle_level(or_ctx *c, int l)
     memcpy(Lc->phi, Lc->phic, sizeof(double) * Nc);
     apply_N(c, l + 1, Lc->phic, Lc->F);
     for (size_t q = 0; q < Nc; q++) Lc->F[q] += Lc->tmp2[q];
+}
+
+static void vcycle_level(or_ctx *c, int l)
+{
+    or_level *L = &c->lev[l];
+    if (l == c->L - 1) { coarsest(c, l); return; }
+    smooth(c, l, c->p.nu1);
+    or_level *Lc = &c->lev[l + 1];
+    size_t Nc = (size_t)Lc->n * Lc->m, N = (size_t)L->n * L->m;
+    to_coarse(c, l);
     vcycle_level(c, l + 1);
     for (size_t q = 0; q < Nc; q++) Lc->tmp2[q] = Lc->phi[q] - Lc->phic[q];
     or_prolong(Lc->tmp2, Lc->n, Lc->m, L->tmp);
@@ -1073,7 +1083,8 @@ void or_scalars(or_ctx *c, double *out)
 void or_set_c(or_ctx *c, double c1, double c2) { c->c1 = c1; c->c2 = c2; update_fit(c); }
 void or_set_res0(or_ctx *c, double r0) { c->res0 = r0; }
 
-/* field ids: 0 z, 1 d, 2 w, 3 fit, 4 phi, 5 F, 6 A, 7 B, 8 C, 9 D, 10 S, 11 f, 12 g (level 0 only) */
+/* field ids: 0 z, 1 d, 2 w, 3 fit, 4 phi, 5 F, 6 A, 7 B, 8 C, 9 D, 10 S, 11 f, 12 g (level 0 only), */
+/* 13 lo, 14 hi, 15 phic (the restricted state of the last coarse problem) */
 static double *field(or_ctx *c, int l, int id)
 {
     or_level *L = &c->lev[l];
@@ -1082,6 +1093,7 @@ static double *field(or_ctx *c, int l, int id)
     case 4: return L->phi; case 5: return L->F; case 6: return L->A; case 7: return L->B;
     case 8: return L->C; case 9: return L->D; case 10: return L->S; case 11: return L->f;
     case 12: return l == 0 ? c->g0 : NULL;
+    case 13: return L->lo; case 14: return L->hi; case 15: return L->phic;
     default: return NULL;
     }
 }
@@ -1108,6 +1120,7 @@ void or_step_sweep(or_ctx *c, int l, int s) { if (s < 4) hs2_sweep(c, l, s); els
 void or_step_smooth(or_ctx *c, int l, int iters) { smooth(c, l, iters); }
 void or_step_coarsest(or_ctx *c, int l) { coarsest(c, l); }
 void or_step_vcycle_level(or_ctx *c, int l) { vcycle_level(c, l); }
+void or_step_to_coarse(or_ctx *c, int l) { if (l + 1 < c->L) to_coarse(c, l); }
 void or_step_residual(or_ctx *c, int l, double *r, int project) { residual(c, l, c->lev[l].phi, c->lev[l].F, r, project); }
 void or_step_operator(or_ctx *c, int l, double *out) { apply_N(c, l, c->lev[l].phi, out); }
 void or_step_update_c(or_ctx *c) { update_c(c); update_fit(c); }
