@@ -92,8 +92,11 @@ typedef struct {
 
 typedef struct {
     double c1, c2;          /* region means (eq. c1c2)                               */
-    double rel_res;         /* |r~_k| / |r~_0| on the finest grid                    */
-    double res;             /* |r~_k| (FP64, projected residual)                     */
+    double rel_res;         /* |r~_k| / |r~_0| on the finest grid: the projected     */
+                            /* residual of the paper's equations (eq. abcdrc, every  */
+                            /* row with its factor delta_eps(phi_ij)); mgseg_solve   */
+                            /* stops on it                                           */
+    double res;             /* |r~_k| (FP64)                                         */
     double res0;            /* |r~_0|                                                */
     double eta;             /* paper's relative change |phi_k - phi_k-1|/|phi_k-1|   */
     int32_t cycles;         /* V-cycles done since setup / last set_phi0             */
@@ -104,6 +107,9 @@ typedef struct {
                             /* Rada-Chen functional; central differences, h^2 cells) */
     double frac_D;          /* fraction of finest cells in the jump set at the last  */
                             /* freeze (Sec. 4.3)                                     */
+    double res_rows;        /* |r~_k| of the rows as the smoother holds them (each   */
+    double res0_rows;       /* divided by delta_eps(phi_ij) when params.scaled), and */
+    double rel_res_rows;    /* its |r~_0| and ratio                                  */
 } mgseg_stats;
 
 /* Fills *p with the defaults. */

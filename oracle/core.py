@@ -88,6 +88,11 @@ def _load():
         _lib.or_solve.argtypes = [C.c_void_p, C.c_double, C.c_int, dp]
         _lib.or_res_norm.restype = C.c_double
         _lib.or_res_norm.argtypes = [C.c_void_p]
+        _lib.or_res_norm_rows.restype = C.c_double
+        _lib.or_res_norm_rows.argtypes = [C.c_void_p]
+        _lib.or_rel_rows.restype = C.c_double
+        _lib.or_rel_rows.argtypes = [C.c_void_p]
+        _lib.or_set_res0_rows.argtypes = [C.c_void_p, C.c_double]
         _lib.or_energy.restype = C.c_double
         _lib.or_energy.argtypes = [C.c_void_p]
         _lib.or_timemarch.restype = C.c_double
@@ -264,7 +269,19 @@ class Oracle:
         return k, hist[: abs(k)]
 
     def res_norm(self) -> float:
+        """Projected residual norm of the paper's rows (eq. abcdrc, each with its delta factor)."""
         return self.lib.or_res_norm(self.ctx)
+
+    def res_norm_rows(self) -> float:
+        """Projected residual norm of the rows the smoother holds (divided by delta if scaled)."""
+        return self.lib.or_res_norm_rows(self.ctx)
+
+    def rel_rows(self) -> float:
+        """The last cycle's relative residual of the smoother's rows."""
+        return self.lib.or_rel_rows(self.ctx)
+
+    def set_res0_rows(self, r0: float):
+        self.lib.or_set_res0_rows(self.ctx, r0)
 
     def energy(self) -> float:
         return self.lib.or_energy(self.ctx)

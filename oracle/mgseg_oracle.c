@@ -66,7 +66,9 @@ typedef struct {
     or_params p;
     int L;
     double h0, A1, c1, c2;
-    double res0;
+    double res0;        /* |r~_0| of the paper's rows (eq. abcdrc, each row with its delta factor) */
+    double res0_rows;   /* |r~_0| of the rows as the smoother holds them (divided by delta if scaled) */
+    double rel_rows;    /* the last cycle's relative residual of the latter */
     or_level lev[OR_MAXLEV];
     double *g0, *phi_prev;
 } or_ctx;
@@ -912,11 +914,37 @@ static void update_fit(or_ctx *c)
 }
 
 
-double or_res_norm(or_ctx *c)
+/* projected residual norms on level 0: of the paper's discrete equations    */
+/* (eq. abcdrc: every row carries its factor delta_eps(phi_ij)), and of the  */
+/* rows as the smoother holds them (divided by delta_eps(phi_ij) when the    */
+/* rows are scaled; the same rows otherwise)                                 */
+static void res_norms(or_ctx *c, double *paper, double *rows)
 {
     or_level *L = &c->lev[0];
+    size_t N = (size_t)L->n * L->m;
     residual(c, 0, L->phi, NULL, L->tmp, 1);
-    return l2(L->tmp, (size_t)L->n * L->m);
+    double sp = 0.0, sr = 0.0;
+    for (size_t q = 0; q < N; q++) {
+        double v = L->tmp[q];
+        double vp = c->p.scaled ? deps(L->phi[q], c->p.eps) * v : v;
+        sr += v * v; sp += vp * vp;
+    }
+    *paper = sqrt(sp);
+    *rows = sqrt(sr);
+}
+
+double or_res_norm(or_ctx *c)
+{
+    double p, r;
+    res_norms(c, &p, &r);
+    return p;
+}
+
+double or_res_norm_rows(or_ctx *c)
+{
+    double p, r;
+    res_norms(c, &p, &r);
+    return r;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -961,7 +989,8 @@ or_ctx *or_create(const double *z, int n, int m, const double *markers, int k, c
     }
     update_c(c);
     update_fit(c);
-    c->res0 = or_res_norm(c);
+    res_norms(c, &c->res0, &c->res0_rows);
+    c->rel_rows = 1.0;
     return c;
 }
 
@@ -978,8 +1007,10 @@ void or_destroy(or_ctx *c)
 }
 
 /* one cycle followed by the c1, c2 refresh (Sec. 5: updated at the end of  */
-/* each multigrid iteration); returns |r~|/|r~_0| on level 0 and the paper's */
-/* relative change eta = |phi_new - phi_old| / |phi_old| (Sec. 5.1)          */
+/* each multigrid iteration); returns |r~|/|r~_0| of the paper's rows on     */
+/* level 0 (the stopping measure), keeps that of the smoother's rows, and    */
+/* gives the paper's relative change eta = |phi_new - phi_old| / |phi_old|   */
+/* (Sec. 5.1)                                                                */
 double or_vcycle(or_ctx *c, double *eta)
 {
     or_level *L = &c->lev[0];
@@ -997,9 +1028,12 @@ double or_vcycle(or_ctx *c, double *eta)
         }
         *eta = pn > 0.0 ? sqrt(dn / pn) : 0.0;
     }
-    double r = or_res_norm(c);
-    return c->res0 > 0.0 ? r / c->res0 : 0.0;
+    double rp, rr;
+    res_norms(c, &rp, &rr);
+    c->rel_rows = c->res0_rows > 0.0 ? rr / c->res0_rows : 0.0;
+    return c->res0 > 0.0 ? rp / c->res0 : 0.0;
 }
+double or_rel_rows(or_ctx *c) { return c->rel_rows; }
 
 int or_solve(or_ctx *c, double tol, int max_cycles, double *hist)
 {
@@ -1082,6 +1116,7 @@ void or_scalars(or_ctx *c, double *out)
 }
 void or_set_c(or_ctx *c, double c1, double c2) { c->c1 = c1; c->c2 = c2; update_fit(c); }
 void or_set_res0(or_ctx *c, double r0) { c->res0 = r0; }
+void or_set_res0_rows(or_ctx *c, double r0) { c->res0_rows = r0; }
 
 /* field ids: 0 z, 1 d, 2 w, 3 fit, 4 phi, 5 F, 6 A, 7 B, 8 C, 9 D, 10 S, 11 f, 12 g (level 0 only), */
 /* 13 lo, 14 hi, 15 phic (the restricted state of the last coarse problem) */

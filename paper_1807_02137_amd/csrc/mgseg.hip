@@ -24,8 +24,9 @@ enum {
     DS_AREA_FRZ = 2,          // area term of the current freeze
     DS_AREA_EVAL = 3,         // area term for operator evaluations
     DS_AREA64 = 4,            // area term at the FP64 finest phi
-    DS_RES = 5,               // last residual norm
+    DS_RES = 5,               // last residual norm of the paper's rows (the stopping measure)
     DS_ETA = 6,               // last relative change of phi (right after DS_RES)
+    DS_RESR = 7,              // last residual norm of the smoother's rows (right after DS_ETA)
     DS_AREAB0 = 8,            // deviation form: area term at the base of level l is slot DS_AREAB0 + l
     DS_CO = 8 + MAXLEV,       // coarsest-solve changes (2 slots)
     DS_ENERGY = 8 + MAXLEV + 2,   // the model's energy (mgseg_get_stats)
@@ -54,6 +55,7 @@ struct mgseg_ctx {
     hipStream_t s = nullptr;
     int L = 0, n = 0, m = 0;
     double h0 = 0.0, A1 = 0.0, res0 = 0.0, res = 0.0, eta = 0.0, rel = 0.0;
+    double res0_rows = 0.0, res_rows = 0.0;   // the same for the rows as the smoother holds them
     int cycles = 0;
     Level lev[MAXLEV];
     double *phi64 = nullptr, *w64 = nullptr, *d64 = nullptr, *g64 = nullptr, *prev64 = nullptr;
@@ -63,8 +65,8 @@ struct mgseg_ctx {
     int part_n = 0;
     float *co_prev = nullptr, *co_entry = nullptr;   // multi-kernel coarsest solve
     int *flags = nullptr;           // device flags: [0] coarsest solve finished, [1] markers inside phi0
-    double *hres = nullptr;         // host copy of DS_RES, DS_ETA (pinned, or hres_local)
-    double hres_local[2] = {0.0, 0.0};
+    double *hres = nullptr;         // host copy of DS_RES, DS_ETA, DS_RESR (pinned, or hres_local)
+    double hres_local[3] = {0.0, 0.0, 0.0};
     bool arena_owned = true;        // false: the arena is the library's static scratch
     bool noalloc = false;           // a context that may not allocate (no graph, no pinned memory)
     const int *sweep_skip = nullptr;
@@ -273,7 +275,7 @@ void res64(mgseg_ctx *c)
     A.partial = c->part;
     dim3 g = grid2(c->n, c->m);
     hipLaunchKernelGGL(k_res64, g, dim3(256), 0, c->s, A);
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FIN_NT), 0, c->s, c->part, (int)(g.x * g.y), 2, 0.0, 0.0, 0.0, 0.0,
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FIN_NT), 0, c->s, c->part, (int)(g.x * g.y), 4, 0.0, 0.0, 0.0, 0.0,
                        c->dsc + DS_RES);
 }
 
@@ -723,7 +725,7 @@ void cycle_begin(mgseg_ctx *c)
         }
     }
     if (!launched) enqueue_cycle(c);
-    (void)hipMemcpyAsync(c->hres, c->dsc + DS_RES, 2 * sizeof(double), hipMemcpyDeviceToHost, c->s);
+    (void)hipMemcpyAsync(c->hres, c->dsc + DS_RES, 3 * sizeof(double), hipMemcpyDeviceToHost, c->s);
     chk(c);
 }
 
@@ -733,6 +735,7 @@ mgseg_status cycle_end(mgseg_ctx *c, double *rel_out)
     const double res = c->hres[0];
     c->eta = c->hres[1];
     c->res = res;
+    c->res_rows = c->hres[2];
     c->cycles++;
     c->rel = c->res0 > 0.0 ? res / c->res0 : 0.0;
     if (rel_out) *rel_out = c->rel;
@@ -861,7 +864,7 @@ mgseg_status setup_into(mgseg_ctx *c, const float *image_dev, int n, int m, int 
         c->phi64 = dalloc<double>(c, N); c->w64 = dalloc<double>(c, N); c->d64 = dalloc<double>(c, N);
         c->g64 = dalloc<double>(c, N); c->prev64 = dalloc<double>(c, N); c->phi0m = dalloc<double>(c, N);
         c->dsc = dalloc<double>(c, DS_COUNT);
-        c->part_n = 8 * RED_BLOCKS + (int)((N + 255) / 256) + n + 16;
+        c->part_n = 8 * RED_BLOCKS + 2 * (int)((N + 255) / 256) + n + 16;
         c->part = dalloc<double>(c, (size_t)c->part_n);
         {
             const Level &Lc = c->lev[Lv - 1];
@@ -889,7 +892,7 @@ mgseg_status setup_into(mgseg_ctx *c, const float *image_dev, int n, int m, int 
             c->arena = nullptr;
             return MGSEG_E_NOMEM;
         }
-        if (hipHostMalloc((void **)&c->hres, 2 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        if (hipHostMalloc((void **)&c->hres, 3 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
             (void)hipGetLastError();
             c->hres = nullptr;
             c->oom = true;
@@ -943,6 +946,8 @@ mgseg_status setup_into(mgseg_ctx *c, const float *image_dev, int n, int m, int 
     mgseg_status st = sync_status(c);
     if (st != MGSEG_OK) return st;
     c->res0 = read_scalar(c, DS_RES);
+    c->res0_rows = read_scalar(c, DS_RESR);
+    c->res_rows = c->res0_rows;
     c->res = c->res0;
     c->rel = 1.0;
     return MGSEG_OK;
@@ -1074,6 +1079,8 @@ mgseg_status mgseg_set_phi0(mgseg_ctx *c, const float *phi_dev, int pitch)
     mgseg_status st = sync_status(c);
     if (st != MGSEG_OK) return st;
     c->res0 = read_scalar(c, DS_RES);
+    c->res0_rows = read_scalar(c, DS_RESR);
+    c->res_rows = c->res0_rows;
     c->res = c->res0; c->rel = 1.0; c->cycles = 0;
     return MGSEG_OK;
 }
@@ -1148,6 +1155,8 @@ mgseg_status mgseg_get_stats(mgseg_ctx *c, mgseg_stats *s)
     double nd = 0.0;
     for (double v : cnt) nd += v;
     s->c1 = c12[0]; s->c2 = c12[1]; s->rel_res = c->rel; s->res = c->res; s->res0 = c->res0;
+    s->res_rows = c->res_rows; s->res0_rows = c->res0_rows;
+    s->rel_res_rows = c->res0_rows > 0.0 ? c->res_rows / c->res0_rows : 0.0;
     s->eta = c->eta; s->cycles = c->cycles; s->levels = c->L;
     s->frac_fg = ph.empty() ? 0.0 : (double)fg / (double)ph.size();
     s->energy = en;
@@ -1160,10 +1169,10 @@ struct StateHeader {
     uint64_t magic;
     int32_t n, m, levels, cycles;
     double res0, res, rel, eta;
-    uint64_t reserved;
+    double res0_rows;
 };
 static_assert(sizeof(StateHeader) == 64, "state header is 64 bytes");
-constexpr uint64_t STATE_MAGIC = 0x3154535347534d47ull;   // "GMSGSST1"
+constexpr uint64_t STATE_MAGIC = 0x3254535347534d47ull;   // "GMSGSST2"
 }  // namespace
 
 mgseg_status mgseg_get_state(mgseg_ctx *c, void *blob, size_t *bytes)
@@ -1172,7 +1181,7 @@ mgseg_status mgseg_get_state(mgseg_ctx *c, void *blob, size_t *bytes)
     const size_t N = (size_t)c->n * c->m, need = sizeof(StateHeader) + sizeof(double) * N;
     if (!blob) { *bytes = need; return MGSEG_OK; }
     if (*bytes < need) { *bytes = need; return MGSEG_E_ARG; }
-    StateHeader h{STATE_MAGIC, c->n, c->m, c->L, c->cycles, c->res0, c->res, c->rel, c->eta, 0};
+    StateHeader h{STATE_MAGIC, c->n, c->m, c->L, c->cycles, c->res0, c->res, c->rel, c->eta, c->res0_rows};
     std::memcpy(blob, &h, sizeof(h));
     (void)hipMemcpyAsync(static_cast<char *>(blob) + sizeof(h), c->phi64, sizeof(double) * N, hipMemcpyDeviceToHost,
                          c->s);
@@ -1199,6 +1208,7 @@ mgseg_status mgseg_set_state(mgseg_ctx *c, const void *blob, size_t bytes)
     mgseg_status st = sync_status(c);
     if (st != MGSEG_OK) return st;
     c->res0 = h.res0; c->res = h.res; c->rel = h.rel; c->eta = h.eta; c->cycles = h.cycles;
+    c->res0_rows = h.res0_rows; c->res_rows = read_scalar(c, DS_RESR);
     return MGSEG_OK;
 }
 
@@ -1573,6 +1583,8 @@ mgseg_status mgseg_reset_phi0(mgseg_ctx *c)
     mgseg_status st = sync_status(c);
     if (st != MGSEG_OK) return st;
     c->res0 = read_scalar(c, DS_RES);
+    c->res0_rows = read_scalar(c, DS_RESR);
+    c->res_rows = c->res0_rows;
     c->res = c->res0; c->rel = 1.0; c->cycles = 0;
     return MGSEG_OK;
 }

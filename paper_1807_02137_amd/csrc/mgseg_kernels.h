@@ -434,7 +434,7 @@ __global__ void __launch_bounds__(FIN_NT) k_finalize(const double *partial, int 
     double a0 = 0.0, a1 = 0.0, a2 = 0.0;
     if (mode == 2) {
         for (int b = t; b < nb; b += FIN_NT) a0 += partial[b];
-    } else if (mode == 3) {
+    } else if (mode == 3 || mode == 4) {
         for (int b = t; b < nb; b += FIN_NT) { a0 += partial[2 * b]; a1 += partial[2 * b + 1]; }
     } else {
         for (int b = t; b < nb; b += FIN_NT) {
@@ -451,6 +451,10 @@ __global__ void __launch_bounds__(FIN_NT) k_finalize(const double *partial, int 
     const double sH = r0[0], sHz = r1[0], sz = r2[0];
     if (mode == 2) {
         out[0] = sqrt(sH);
+    } else if (mode == 4) {
+        // the two residual norms: out[0] and out[2] (the slots around the one between)
+        out[0] = sqrt(sH);
+        out[2] = sqrt(sHz);
     } else if (mode == 3) {
         out[0] = sHz > 0.0 ? sqrt(sH / sHz) : 0.0;
     } else if (mode == 0) {
@@ -497,11 +501,15 @@ __device__ double cell_N64(const Res64Args &A, int i, int j, double c1, double c
     return v;
 }
 
+// the squares of the projected residual of the paper's rows (eq. abcdrc, each
+// with its delta(phi) factor: the stopping measure) and of the rows as the
+// smoother holds them (divided by delta(phi) when scaled) go to two partials
+// per block
 __global__ void k_res64(Res64Args A)
 {
-    __shared__ double red[256];
+    __shared__ double red[256], red2[256];
     int j = blockIdx.x * blockDim.x + threadIdx.x, i = blockIdx.y, tid = threadIdx.x;
-    double acc = 0.0;
+    double acc = 0.0, acc_rows = 0.0;
     if (j < A.m && i < A.n) {
         double c1 = A.c12[0], c2 = A.c12[1];
         double area = A.area ? *A.area : 0.0;
@@ -510,18 +518,25 @@ __global__ void k_res64(Res64Args A)
         double ph = A.phi64[(long long)i * A.m + j];
         double rp = r;
         if ((ph >= A.M && rp < 0.0) || (ph <= -A.M && rp > 0.0)) rp = 0.0;
-        acc = rp * rp;
+        acc_rows = rp * rp;
+        const double rpp = A.scaled ? mg_delta64(ph, A.eps) * rp : rp;
+        acc = rpp * rpp;
         long long q = (long long)i * A.p32 + j;
         if (A.phi32) A.phi32[q] = (float)ph;
         if (A.G) A.G[q] = (float)r;
     }
     red[tid] = acc;
+    red2[tid] = acc_rows;
     __syncthreads();
     for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-        if (tid < s) red[tid] += red[tid + s];
+        if (tid < s) { red[tid] += red[tid + s]; red2[tid] += red2[tid + s]; }
         __syncthreads();
     }
-    if (tid == 0) A.partial[(long long)blockIdx.y * gridDim.x + blockIdx.x] = red[0];
+    if (tid == 0) {
+        const long long b = (long long)blockIdx.y * gridDim.x + blockIdx.x;
+        A.partial[2 * b] = red[0];
+        A.partial[2 * b + 1] = red2[0];
+    }
 }
 
 __global__ void k_copy32to64(const float *phi32, int p32, double *phi64, int n, int m)

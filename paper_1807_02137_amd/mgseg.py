@@ -45,7 +45,8 @@ class _Params(C.Structure):
 class _Stats(C.Structure):
     _fields_ = [("c1", C.c_double), ("c2", C.c_double), ("rel_res", C.c_double), ("res", C.c_double),
                 ("res0", C.c_double), ("eta", C.c_double), ("cycles", C.c_int32), ("levels", C.c_int32),
-                ("frac_fg", C.c_double), ("energy", C.c_double), ("frac_D", C.c_double)]
+                ("frac_fg", C.c_double), ("energy", C.c_double), ("frac_D", C.c_double),
+                ("res_rows", C.c_double), ("res0_rows", C.c_double), ("rel_res_rows", C.c_double)]
 
 
 @dataclass
