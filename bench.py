@@ -1,15 +1,25 @@
-"""Benchmark: solve of one 1024x1024 selective-segmentation image to a relative
-projected residual of 1e-6 with the FAS V(2,2) cycle and Hybrid Smoother 2
-(9 grids, FP32 cycles + FP64 finest-grid defect correction) on one GPU.
+"""Benchmark: time to a relative residual of 1e-6 and grid points per second
+per V-cycle of the FAS V(2,2) cycle with Hybrid Smoother 2 on one GPU.
 
-One step = setup (edge detector, distance map, initial level set, coarse
-maps) + V-cycles until |r~|/|r~_0| <= 1e-6, for the 12-ellipse synthetic
-image (seed 2000).  The image is resident in HBM before the timed region.
+Default (the largest single-GPU configuration): one 8192 x 8192 image of 200
+star polygons (seed 4000), 14 grids down to 1 x 1, FP32 cycles with the FP64
+finest-grid defect correction.  One step = setup (edge detector, distance
+map, initial level set, coarse maps) + V-cycles until the projected residual
+of the paper's rows is at most 1e-6 of its initial value; the image is
+resident in HBM before the timed region.  --workload c2 runs the 1024 x 1024
+twelve-ellipse image (seed 2000, 9 grids) the same way; c3 the batch of 64
+uneven images; c5 the learned warm start.
 
-Prints one JSON line: value = grid points per second per V-cycle
-(finest-grid points x cycles / wall time), with the roofline of the
-finest-grid sweep kernel (HIP events around its launches) and the CPU
-oracle timed on a bounded sample of the same workload.
+Prints one JSON line: value = grid points per second per V-cycle (finest
+points x cycles / wall time), the time to tolerance, the roofline of the
+finest-grid sweep kernel and the CPU oracle timed on a bounded sample.
+
+Roofline: one directional sweep must move at least 21 B per cell (read the
+state, psi, w, the fit map and F, 4 B each, and the label byte; write the
+state, 4 B): algorithmic bytes = 21 x cells per launch, over the average
+launch time from HIP events on the solver's stream.  (The design's own
+traffic, with stored face coefficients and bounds, is 37 B per cell; it is
+reported beside as design_bytes_per_launch.)
 """
 from __future__ import annotations
 
@@ -26,7 +36,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 MFMA_BF16_PEAK_TFLOPS = 2500.0          # dense bf16 matrix-core peak
 WEIGHTS = os.path.join(ROOT, "paper_1807_02137_amd", "weights", "warmstart_512_b32_d4.npz")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_1024_traffic.json")
+TRAFFIC_FILES = {"c2": os.path.join(ROOT, "profiles", "k_sweep_1024x1024_traffic.json"),
+                 "c4": os.path.join(ROOT, "profiles", "k_sweep_long_8192x8192_traffic.json")}
 MODEL_NAMES = {"sc": "Spencer-Chen", "rc": "Rada-Chen", "cv": "global Chan-Vese (w = 1, no selection term)"}
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1807_02137_amd", "csrc", f)
                   for f in ("mgseg_device.h", "mgseg_kernels.h", "mgseg.hip")]
@@ -40,12 +51,12 @@ def kernel_source_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
+def measured_traffic(workload="c2"):
     """HBM bytes per finest-grid sweep launch from the recorded FETCH_SIZE /
     WRITE_SIZE counters (scaled by a plain copy of known size), or None when
     the kernel sources have changed since they were taken."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(TRAFFIC_FILES[workload]) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
@@ -145,7 +156,7 @@ def warmstart_bench(steps: int, warmup: int, count: int):
     from paper_1807_02137_amd import build, mgseg, synth, warmstart
     if not os.path.exists(build.LIB):
         build.build()
-    inst = warmstart.generate(warmstart.HELDOUT_SEEDS[:count], 512, workers=8)
+    inst = warmstart.generate(warmstart.HELDOUT_SEEDS[:count], 512, workers=1)   # no fork from this process
     print(f"c5: {count} held-out images drawn", file=sys.stderr, flush=True)
     torch.cuda.set_device(0)
     net, scale = warmstart.load(WEIGHTS)
@@ -235,56 +246,113 @@ def warmstart_bench(steps: int, warmup: int, count: int):
     }))
 
 
-def large_bench(steps: int, max_cycles: int = MAX_CYCLES):
-    """The 8192x8192 solve: 200 star polygons (seed 4000), 12 grids down to 4x4
-    (carried down to 1x1 the cycle does not converge on this content, in the
-    oracle either), FP32 cycles + FP64 finest residual, to rel. residual 1e-6
-    (at most max_cycles).  Lines of 8192 cells run 8 cells per thread."""
+SWEEP_BYTES_PER_PX = 21.0      # compulsory FP32 bytes per cell of one directional sweep (see module doc)
+C4_SEED, C4_N, C4_LEVELS, C4_MAX_CYCLES = 4000, 8192, 14, 300
+
+
+def host_cpu() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            return next(l.split(":", 1)[1].strip() for l in fh if l.startswith("model name"))
+    except (OSError, StopIteration):
+        return "unknown CPU"
+
+
+def oracle_sample(image, markers, levels, seconds, **kw):
+    """The FP64 oracle (single-threaded C) timed on the host: setup, then whole
+    V-cycles until `seconds` have passed.  Returns grid-pts/s per V-cycle (setup
+    included in the time) and a description."""
+    from oracle import Oracle, OracleParams
+    from oracle.core import OPT_FLAGS
+    t0 = time.perf_counter()
+    o = Oracle(image, markers, OracleParams(levels=levels, **kw))
+    k = 0
+    while True:
+        o.vcycle()
+        k += 1
+        if time.perf_counter() - t0 >= seconds:
+            break
+    tc = time.perf_counter() - t0
+    n, m = image.shape
+    return n * m * k / tc, k, tc, f"single-threaded FP64 C, gcc {' '.join(OPT_FLAGS)}, {host_cpu()}"
+
+
+def large_bench(steps: int, warmup: int, max_cycles: int, cpu_seconds: float, no_cpu: bool):
+    """The 8192 x 8192 solve (the largest single-GPU configuration): 200 star
+    polygons (seed 4000), 8 markers, 14 grids down to 1 x 1, FP32 cycles with
+    the FP64 finest residual, to a relative residual of 1e-6 of the paper's
+    rows.  One step = setup + solve, the image resident in HBM."""
     import torch
     from paper_1807_02137_amd import build, mgseg, synth
     if not os.path.exists(build.LIB):
         build.build()
     t0 = time.perf_counter()
-    inst = synth.config4(4000)
+    inst = synth.config4(C4_SEED, C4_N)
     print(f"c4: image drawn in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     torch.cuda.set_device(0)
     n = inst.image.shape[0]
     img = torch.from_numpy(inst.image).to("cuda")
-    params = mgseg.Params(levels=12)
+    params = mgseg.Params(levels=C4_LEVELS)
     stream = torch.cuda.current_stream()
-    cycles, rels, oks = [], [], []
+
+    def step():
+        s = mgseg.Solver(img, inst.markers, params, stream=stream)
+        cyc, rel, ok = s.solve(TOL, max_cycles)
+        st = s.stats()
+        s.close()
+        return cyc, rel, ok, st
+
+    for _ in range(warmup):
+        step()
+    cycles, rels, oks, sts = [], [], [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        s = mgseg.Solver(img, inst.markers, params, stream=stream)
-        cyc, rel, ok = s.solve(TOL, max_cycles)
-        s.close()
-        cycles.append(cyc); rels.append(rel); oks.append(ok)
+        cyc, rel, ok, st = step()
+        cycles.append(cyc); rels.append(rel); oks.append(ok); sts.append(st)
         print(f"c4: solve {len(cycles)}: {cyc} cycles, rel {rel:.2e}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    # finest-sweep timing: 3 event-profiled cycles
+    # finest-sweep timing: HIP events around every finest-grid sweep launch on
+    # the solver's stream over one more whole solve (eager launches, outside the
+    # timed region), so that the average covers the same launches as a kernel
+    # trace of one solve
     s = mgseg.Solver(img, inst.markers, params, stream=stream)
     s.profile(True)
-    for _ in range(3):
-        s.vcycle()
-    prof_ms, prof_n, prof_bytes = s.profile_read()
+    s.solve(TOL, max_cycles)
+    prof_ms, prof_n, design_bytes = s.profile_read()
     s.close()
     avg_ms = prof_ms / max(prof_n, 1)
-    achieved = prof_bytes / (avg_ms * 1e-3) / 1e9 if prof_n else 0.0
+    alg_bytes = SWEEP_BYTES_PER_PX * n * n
+    achieved = alg_bytes / (avg_ms * 1e-3) / 1e9 if prof_n else 0.0
     copy = copy_bandwidth()
+    cpu = None
+    if not no_cpu:
+        sample = synth.config4(C4_SEED, 2048)
+        v, k, tc, how = oracle_sample(sample.image, sample.markers, 12, cpu_seconds)
+        cpu = {"value": v, "unit": "grid-pts/s per V-cycle", "cores": 1, "kind": "oracle",
+               "sample": f"oracle setup + {k} V-cycles ({tc:.1f} s) of the same recipe drawn at 2048 x 2048 "
+                         f"(12 grids), {how}"}
+    st = sts[-1]
     print(json.dumps({
-        "metric": "grid-pts/s per V-cycle (solve to rel. residual 1e-6)",
+        "metric": "time to rel. residual 1e-6 + grid-pts/s per V-cycle (%HBM peak)",
         "value": n * n * sum(cycles) / wall, "unit": "grid-pts/s per V-cycle", "n_gpus": 1, "steps": steps,
-        "warmup": 0, "ms_per_step": wall / steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "warmup": warmup, "ms_per_step": wall / steps * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
-        "config": {"workload": "8192x8192 image of 200 star polygons, 8 markers, Spencer-Chen, FAS V(2,2), "
-                               "12 grids (4x4 coarsest), Hybrid Smoother 2, tol 1e-6", "seed": 4000},
-        "cycles_per_solve": cycles, "rel_res": rels, "converged": all(oks),
+        "config": {"workload": "8192x8192 image of 200 star polygons (blur 1.5, noise 0.05), 8 markers, "
+                               "Spencer-Chen, FAS V(2,2), 14 grids (1x1 coarsest), Hybrid Smoother 2, "
+                               "FP32 cycles + FP64 finest residual, tol 1e-6", "seed": C4_SEED},
+        "time_to_tol_ms": wall / steps * 1e3,
+        "cycles_per_solve": cycles, "rel_res": rels, "rel_res_rows": st["rel_res_rows"], "converged": all(oks),
+        "ms_per_cycle": wall / max(sum(cycles), 1) * 1e3,
+        "segmentation": {"foreground_share": st["frac_fg"], "jump_set_share": st["frac_D"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "copy_gbs": copy,
-                     "frac_of_copy": achieved / copy, "kernel": "k_sweep (finest-grid directional sweep, 8192-cell lines)",
-                     "launches": prof_n, "avg_us": avg_ms * 1e3, "bytes_per_launch": prof_bytes},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic("c4"),
+                     "copy_gbs": copy, "frac_of_copy": achieved / copy,
+                     "kernel": "k_sweep_long (finest-grid directional sweep, 8192-cell lines)",
+                     "launches": prof_n, "avg_us": avg_ms * 1e3, "bytes_per_launch": alg_bytes,
+                     "bytes_per_px": SWEEP_BYTES_PER_PX, "design_bytes_per_launch": design_bytes},
+        "cpu_baseline": cpu,
     }))
 
 
@@ -297,9 +365,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain copy of known size (counter calibration) and exit")
-    ap.add_argument("--workload", default="c2", choices=("c2", "c3", "c4", "c5"),
-                    help="c2: the 1024x1024 solve (default); c3: the 64-image batch of uneven sizes; "
-                         "c4: the 8192x8192 solve; c5: the learned warm start on 512x512 held-out images")
+    ap.add_argument("--workload", default="c4", choices=("c2", "c3", "c4", "c5"),
+                    help="c4: the 8192x8192 solve (default, the largest single-GPU configuration); c2: the "
+                         "1024x1024 solve; c3: the 64-image batch of uneven sizes; c5: the learned warm start "
+                         "on 512x512 held-out images")
     ap.add_argument("--model", default="sc", choices=("sc", "rc", "cv"),
                     help="c2 only: Spencer-Chen (default), Rada-Chen or the global Chan-Vese workload")
     ap.add_argument("--smoother", default="hs2", choices=("hs2", "gslex"),
@@ -307,7 +376,7 @@ def main():
                          "(its Algorithm 1 with a standard smoother)")
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--c5-images", type=int, default=16)
-    ap.add_argument("--max-cycles", type=int, default=MAX_CYCLES, help="c4 only: cycle cap of a solve")
+    ap.add_argument("--max-cycles", type=int, default=C4_MAX_CYCLES, help="c4 only: cycle cap of a solve")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: libmgseg runs on one GPU (asked for --gpus {args.gpus}); "
@@ -324,7 +393,7 @@ def main():
         warmstart_bench(args.steps, args.warmup, args.c5_images)
         return
     if args.workload == "c4":
-        large_bench(args.steps, args.max_cycles)
+        large_bench(args.steps, args.warmup, args.max_cycles, args.cpu_seconds, args.no_cpu_baseline)
         return
     import torch
 
@@ -363,39 +432,24 @@ def main():
     # kernel timing: one more solve outside the timed region, launched eagerly
     # with HIP events around every finest-grid sweep on the solver's stream
     _, _, _, prof = step(profile=True)
-    prof_ms, prof_n, prof_bytes = prof
+    prof_ms, prof_n, design_bytes = prof
     npts = N * N
     value = npts * sum(cycles) / wall
     avg_ms = prof_ms / max(prof_n, 1)
+    prof_bytes = SWEEP_BYTES_PER_PX * npts
     achieved = prof_bytes / (avg_ms * 1e-3) / 1e9 if prof_n else 0.0
     copy = copy_bandwidth()
 
     cpu = None
     if not args.no_cpu_baseline:
-        from oracle import Oracle, OracleParams
-        tc0 = time.perf_counter()
         okw = dict(mgseg.CHAN_VESE) if args.model == "cv" else {"model": model}
         okw["smoother"] = smoother
-        o = Oracle(inst.image, inst.markers, OracleParams(levels=LEVELS, **okw))
-        k = 0
-        while True:
-            o.vcycle()
-            k += 1
-            if time.perf_counter() - tc0 >= args.cpu_seconds:
-                break
-        tc = time.perf_counter() - tc0
-        model_name = "unknown CPU"
-        try:
-            with open("/proc/cpuinfo") as fh:
-                model_name = next(l.split(":", 1)[1].strip() for l in fh if l.startswith("model name"))
-        except (OSError, StopIteration):
-            pass
-        cpu = {"value": npts * k / tc, "unit": "grid-pts/s per V-cycle", "cores": 1, "kind": "oracle",
-               "sample": f"oracle setup + {k} V-cycles of the same 1024x1024 image ({tc:.1f} s, "
-                         f"single-threaded FP64 C, gcc -O2, {model_name}, {os.cpu_count()} host threads visible)"}
+        v, k, tc, how = oracle_sample(inst.image, inst.markers, LEVELS, args.cpu_seconds, **okw)
+        cpu = {"value": v, "unit": "grid-pts/s per V-cycle", "cores": 1, "kind": "oracle",
+               "sample": f"oracle setup + {k} V-cycles of the same 1024x1024 image ({tc:.1f} s), {how}"}
 
     out = {
-        "metric": "grid-pts/s per V-cycle (solve to rel. residual 1e-6)",
+        "metric": "time to rel. residual 1e-6 + grid-pts/s per V-cycle (%HBM peak)",
         "value": value,
         "unit": "grid-pts/s per V-cycle",
         "n_gpus": 1,
@@ -418,10 +472,11 @@ def main():
         "time_to_tol_ms": wall / args.steps * 1e3,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic() if args.model == "sc" and not smoother else None,
+                     "traffic": measured_traffic("c2") if args.model == "sc" and not smoother else None,
                      "copy_gbs": copy, "frac_of_copy": achieved / copy,
                      "kernel": "k_sweep (finest-grid directional sweep)",
-                     "launches": prof_n, "avg_us": avg_ms * 1e3, "bytes_per_launch": prof_bytes},
+                     "launches": prof_n, "avg_us": avg_ms * 1e3, "bytes_per_launch": prof_bytes,
+                     "bytes_per_px": SWEEP_BYTES_PER_PX, "design_bytes_per_launch": design_bytes},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

@@ -19,11 +19,16 @@ FIELDS = {"z": 0, "d": 1, "w": 2, "fit": 3, "phi": 4, "F": 5, "A": 6, "B": 7, "C
           "D": 9, "S": 10, "f": 11, "g": 12, "lo": 13, "hi": 14, "phic": 15}
 
 
+# -O3 without -march=native: the library may be built on another host than the
+# one that runs it; no fast-math (the oracle's arithmetic is plain IEEE FP64)
+OPT_FLAGS = ("-O3",)
+
+
 def build_oracle(force: bool = False) -> str:
-    """Compile the oracle with the host compiler (plain -O2, no fast-math)."""
+    """Compile the oracle with the host compiler (-O3, no fast-math)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + f".tmp{os.getpid()}"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-shared", "-fPIC", _SRC, "-o", tmp, "-lm"])
+        subprocess.check_call(["gcc", *OPT_FLAGS, "-std=c11", "-shared", "-fPIC", _SRC, "-o", tmp, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 

@@ -26,18 +26,36 @@ TRAIN_SEEDS = range(500000, 520000)
 HELDOUT_SEEDS = range(600000, 601000)
 
 
+def gpu_runtime_loaded() -> bool:
+    """True when this process has the HIP / HSA runtime mapped (the library or
+    torch initialised the GPU, or a profiler preloaded its runtime): such a
+    process must not fork workers."""
+    if torch.cuda.is_initialized():
+        return True
+    try:
+        with open("/proc/self/maps") as fh:
+            maps = fh.read()
+    except OSError:
+        return True
+    return "libhsa-runtime64" in maps or "libamdhip64" in maps
+
+
 def generate(seeds, n=512, workers=16):
-    """Seeded 4-20-shape instances (images, markers, seeds), drawn on `workers`
-    host processes that never touch the GPU: forked while this process has
-    not initialised the GPU yet, else spawned (which re-imports the caller's
-    main module, so that module must guard its script code)."""
+    """Seeded 4-20-shape instances (images, markers, seeds).  Drawn on `workers`
+    forked host processes that never touch the GPU, but only while this process
+    has no GPU runtime loaded; otherwise (or for few seeds) in this process.
+    The pool is closed and joined, never terminated."""
     seeds = list(seeds)
-    if workers <= 1 or len(seeds) < 4:
+    if workers <= 1 or len(seeds) < 4 or gpu_runtime_loaded():
         return [synth.config5_arrays((s, n)) for s in seeds]
-    method = "spawn" if torch.cuda.is_initialized() else "fork"
-    with mp.get_context(method).Pool(min(workers, len(seeds))) as pool:
-        return pool.map(synth.config5_arrays, [(s, n) for s in seeds],
-                        chunksize=max(1, len(seeds) // (4 * workers)))
+    pool = mp.get_context("fork").Pool(min(workers, len(seeds)))
+    try:
+        out = pool.map(synth.config5_arrays, [(s, n) for s in seeds],
+                       chunksize=max(1, len(seeds) // (4 * workers)))
+    finally:
+        pool.close()
+        pool.join()
+    return out
 
 
 @dataclass
