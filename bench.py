@@ -371,9 +371,9 @@ def main():
                          "on 512x512 held-out images")
     ap.add_argument("--model", default="sc", choices=("sc", "rc", "cv"),
                     help="c2 only: Spencer-Chen (default), Rada-Chen or the global Chan-Vese workload")
-    ap.add_argument("--smoother", default="hs2", choices=("hs2", "gslex"),
-                    help="c2 only: Hybrid Smoother 2 (default, the paper's Algorithm 3) or GSLEX-I "
-                         "(its Algorithm 1 with a standard smoother)")
+    ap.add_argument("--smoother", default="hs2", choices=("hs2", "gslex", "hs1"),
+                    help="c2 only: Hybrid Smoother 2 (default, the paper's Algorithm 3), GSLEX-I (its "
+                         "Algorithm 1 with a standard smoother) or Hybrid Smoother 1 (its Algorithm 2)")
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--c5-images", type=int, default=16)
     ap.add_argument("--max-cycles", type=int, default=C4_MAX_CYCLES, help="c4 only: cycle cap of a solve")
@@ -404,7 +404,7 @@ def main():
     inst = synth.config2(SEED, N)
     img = torch.from_numpy(inst.image).to("cuda")
     model = 1 if args.model == "rc" else 0
-    smoother = 1 if args.smoother == "gslex" else 0
+    smoother = {"hs2": 0, "gslex": 1, "hs1": 2}[args.smoother]
     params = (mgseg.chan_vese_params(levels=LEVELS, smoother=smoother) if args.model == "cv"
               else mgseg.Params(levels=LEVELS, model=model, smoother=smoother))
     stream = torch.cuda.current_stream()
@@ -463,7 +463,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "1024x1024 12-ellipse image, 6 markers, "
                                f"{MODEL_NAMES[args.model]}, FAS V(2,2), "
-                               f"9 grids, {'GSLEX-I' if smoother else 'Hybrid Smoother 2'}, tol 1e-6",
+                               f"9 grids, {['Hybrid Smoother 2', 'GSLEX-I', 'Hybrid Smoother 1'][smoother]}, tol 1e-6",
                    "seed": SEED,
                    "parallelism": "single GPU"},
         "cycles_per_solve": cycles,

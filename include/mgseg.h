@@ -81,7 +81,12 @@ typedef struct {
                             /* 3); 1: GSLEX-I (Sec. 3.2), one point Gauss-Seidel     */
                             /* pass per outer iteration in the rows' four-class      */
                             /* order, the standard smoother of the paper's Algorithm */
-                            /* 1; default 0                                          */
+                            /* 1; 2: Hybrid Smoother 1 (Sec. 4.2, Algorithm 2):      */
+                            /* GSLINE-I on every column (four column classes), then  */
+                            /* the collective update at every jump-set cell of the   */
+                            /* cell and its neighbours except the one behind its     */
+                            /* smallest coefficient (eight cell classes); needs      */
+                            /* mixed_precision = 1; default 0                        */
     int32_t run_max;        /* superpixels of Hybrid Smoother 2 (Sec. 4.3, Fig. 3):  */
                             /* 0 (default) solves every maximal run of starred cells */
                             /* on a line as one unit, as the paper does (lines       */

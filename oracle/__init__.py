@@ -5,5 +5,5 @@ CPU-baseline leg of the benchmark.  The product library never imports,
 links or executes anything from this package, and this package imports
 nothing from the product package.
 """
-from .core import (Oracle, OracleParams, box_tridiag, build_oracle, hull, line_units, prolong,  # noqa: F401
+from .core import (Oracle, OracleParams, box_dense, box_tridiag, build_oracle, hull, line_units, prolong,  # noqa: F401
                    restrict, setup_maps, visit_order)

@@ -64,7 +64,7 @@ class OracleParams:
     coarse_iters: int = 10
     coarse_rtol: float = 1e-4  # coarsest solve stops when an iteration moves nothing by more than this share
     order: int = 1            # 0 paper lexicographic lines, 1 four-class line order
-    smoother: int = 0         # 0 Hybrid Smoother 2, 1 GSLEX-I
+    smoother: int = 0         # 0 Hybrid Smoother 2, 1 GSLEX-I, 2 Hybrid Smoother 1
     obstacle: int = 1         # 1 coarse corrections bounded by the fine slack
     scaled: int = 1           # 1 each row divided by delta_eps(psi_ij) > 0
     run_max: int = 0          # 0 maximal runs (Sec. 4.3), else runs cut into near-equal pieces of at most run_max
@@ -127,6 +127,8 @@ def _load():
         _lib.or_prolong.argtypes = [dp, C.c_int, C.c_int, dp]
         _lib.or_hull.restype = C.c_int
         _lib.or_hull.argtypes = [dp, C.c_int, dp]
+        _lib.or_box_dense.restype = C.c_int
+        _lib.or_box_dense.argtypes = [C.c_int, dp, dp, dp, dp, dp]
         _lib.or_box_tridiag.restype = C.c_int
         _lib.or_box_tridiag.argtypes = [C.c_int, dp, dp, dp, dp, dp, dp, dp]
         _lib.or_line_units.argtypes = [C.POINTER(C.c_uint8), C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int)]
@@ -168,6 +170,15 @@ def box_tridiag(lo, di, up, rh, bl, bh):
     arrs = [np.ascontiguousarray(a, np.float64) for a in (lo, di, up, rh, bl, bh)]
     x = np.zeros(len(di))
     ok = _load().or_box_tridiag(len(di), *[_dp(a) for a in arrs], _dp(x))
+    return x if ok else None
+
+
+def box_dense(M, b, bl, bh):
+    """Box-constrained solve of a small dense system (None on a zero pivot)."""
+    M = np.ascontiguousarray(M, np.float64)
+    arrs = [np.ascontiguousarray(a, np.float64) for a in (b, bl, bh)]
+    x = np.zeros(len(b))
+    ok = _load().or_box_dense(len(b), _dp(M), *[_dp(a) for a in arrs], _dp(x))
     return x if ok else None
 
 

@@ -45,7 +45,7 @@ typedef struct {
                         /* value by more than coarse_rtol times the largest total  */
                         /* change since the solve began                            */
     int order;          /* 0 = paper lexicographic line order, 1 = 4-colour line order */
-    int smoother;       /* 0 = Hybrid Smoother 2, 1 = GSLEX-I                      */
+    int smoother;       /* 0 = Hybrid Smoother 2, 1 = GSLEX-I, 2 = Hybrid Smoother 1 */
     int obstacle;       /* 1 = coarse corrections bounded by the fine slack        */
     int scaled;         /* 1 = each row divided by its factor delta_eps(psi_ij)    */
     int run_max;        /* 0 = maximal runs; else longer runs are cut into pieces  */
@@ -773,11 +773,159 @@ static void gslex_sweep(or_ctx *c, int l)
             for (int j = 0; j < m; j++) point_update(c, L, (size_t)i * m + j);
 }
 
+/* ------------------------------------------------------------------------ */
+/* Hybrid Smoother 1 (Sec. 4.2, "Implementing Hybrid Smoother 1"): step I,   */
+/* GSLINE-I on every column (each column one line system, the paper's       */
+/* column-by-column line Gauss-Seidel); step II, at every pixel of the jump  */
+/* set the collective update of the pixel and its three neighbours other     */
+/* than the one behind its smallest coefficient, which is lagged             */
+/* (eqs. caseAlagged .. caseDlagged).  Each neighbour's row is its own       */
+/* discrete equation (eq. abcd), its coupling to the centre being its own    */
+/* coefficient towards the centre (with delta-scaled rows this is the        */
+/* centre's coefficient towards it, as the paper's arrow matrices write it); */
+/* all other pixels enter at their current values.  With the box reading the */
+/* block is solved as its box-constrained system.                            */
+/* Order: 0 = the paper's (columns left to right; jump pixels row by row);   */
+/* 1 = the parallel one (columns in four classes as sweep C; jump pixels in  */
+/* eight classes (i + 3 j) mod 8, row by row within a class: two pixels of    */
+/* one class are at least four cells apart, so their blocks neither share    */
+/* nor read each other's pixels).                                            */
+
+/* Box-constrained small dense system M x = b (M diagonally dominant with a   */
+/* negative diagonal), bl <= x <= bh: active-set iteration (free unknowns    */
+/* solved by Gaussian elimination with the held ones at their bounds; free   */
+/* unknowns outside the box are held, held unknowns whose row residual turns */
+/* inward are released).  Returns 0 on a zero pivot.                         */
+int or_box_dense(int k, const double *M, const double *b, const double *bl, const double *bh, double *x)
+{
+    int held[8] = {0}, idx[8];
+    double A[64], r[8], y[8];
+    if (k > 8) return 0;
+    for (int it = 0; it < 2 * k + 4; it++) {
+        int nf = 0;
+        for (int a = 0; a < k; a++) {
+            if (held[a]) x[a] = held[a] > 0 ? bh[a] : bl[a];
+            else idx[nf++] = a;
+        }
+        for (int a = 0; a < nf; a++) {
+            double v = b[idx[a]];
+            for (int t = 0; t < k; t++)
+                if (held[t]) v -= M[idx[a] * k + t] * x[t];
+            r[a] = v;
+            for (int c2 = 0; c2 < nf; c2++) A[a * nf + c2] = M[idx[a] * k + idx[c2]];
+        }
+        for (int p2 = 0; p2 < nf; p2++) {         /* elimination without pivoting */
+            if (A[p2 * nf + p2] == 0.0) return 0;
+            for (int q2 = p2 + 1; q2 < nf; q2++) {
+                double fct = A[q2 * nf + p2] / A[p2 * nf + p2];
+                for (int c2 = p2; c2 < nf; c2++) A[q2 * nf + c2] -= fct * A[p2 * nf + c2];
+                r[q2] -= fct * r[p2];
+            }
+        }
+        for (int p2 = nf - 1; p2 >= 0; p2--) {
+            double v = r[p2];
+            for (int c2 = p2 + 1; c2 < nf; c2++) v -= A[p2 * nf + c2] * y[c2];
+            y[p2] = v / A[p2 * nf + p2];
+        }
+        for (int a = 0; a < nf; a++) x[idx[a]] = y[a];
+        int changed = 0;
+        for (int a = 0; a < k; a++) {
+            if (!held[a]) {
+                if (x[a] > bh[a]) { held[a] = 1; changed = 1; }
+                else if (x[a] < bl[a]) { held[a] = -1; changed = 1; }
+            } else {
+                double v = -b[a], mag = fabs(b[a]);
+                for (int t = 0; t < k; t++) { v += M[a * k + t] * x[t]; mag += fabs(M[a * k + t] * x[t]); }
+                /* the row's update moves x_a by -v / M_aa = v / |M_aa|: a unknown held at its upper  */
+                /* bound is released where that move is downward (v < 0), at its lower bound where   */
+                /* it is upward, beyond rounding                                                       */
+                if ((held[a] == 1 && v < -1e-12 * mag) || (held[a] == -1 && v > 1e-12 * mag)) { held[a] = 0; changed = 1; }
+            }
+        }
+        if (!changed) break;
+    }
+    for (int a = 0; a < k; a++) x[a] = clampB(x[a], bl[a], bh[a]);
+    return 1;
+}
+
+/* neighbour of (i, j) behind coefficient s (0 A: i+1, 1 B: i-1, 2 C: j+1, 3 D: j-1), -1 outside */
+static long nb_of(const or_level *L, int i, int j, int s)
+{
+    int ii = i + (s == 0) - (s == 1), jj = j + (s == 2) - (s == 3);
+    if (ii < 0 || ii >= L->n || jj < 0 || jj >= L->m) return -1;
+    return (long)ii * L->m + jj;
+}
+static double coef_s(const or_level *L, size_t q, int s)
+{
+    return s == 0 ? L->A[q] : (s == 1 ? L->B[q] : (s == 2 ? L->C[q] : L->D[q]));
+}
+
+/* the collective update at jump pixel (i, j) lagging its coefficient lag */
+static void hs1_block(or_ctx *c, or_level *L, int i, int j, int lag)
+{
+    (void)c;
+    size_t q0 = (size_t)i * L->m + j;
+    long cell[4];
+    int k = 0;
+    cell[k++] = (long)q0;
+    for (int s = 0; s < 4; s++) {
+        if (s == lag) continue;
+        long nq = nb_of(L, i, j, s);
+        if (nq >= 0) cell[k++] = nq;
+    }
+    double M[16] = {0}, b[4], bl[4], bh[4], x[4];
+    for (int a = 0; a < k; a++) {
+        size_t q = (size_t)cell[a];
+        if (L->S[q] == 0.0) return;
+        int qi = (int)(q / L->m), qj = (int)(q % L->m);
+        M[a * k + a] = -L->S[q];
+        double rhs = L->f[q] + L->F[q];
+        for (int s = 0; s < 4; s++) {
+            long nq = nb_of(L, qi, qj, s);
+            if (nq < 0) continue;
+            int inblock = -1;
+            for (int t = 0; t < k; t++) if (cell[t] == nq) inblock = t;
+            /* the leaves couple only to the centre (the arrow): a leaf's other block */
+            /* neighbours, and the centre's lagged one, enter at their current values */
+            if (inblock >= 0 && (a == 0 || inblock == 0)) M[a * k + inblock] += coef_s(L, q, s);
+            else rhs -= coef_s(L, q, s) * L->phi[nq];
+        }
+        b[a] = rhs; bl[a] = L->lo[q]; bh[a] = L->hi[q];
+    }
+    if (or_box_dense(k, M, b, bl, bh, x))
+        for (int a = 0; a < k; a++) L->phi[cell[a]] = x[a];
+}
+
+static void hs1_outer(or_ctx *c, int l)
+{
+    or_level *L = &c->lev[l];
+    int n = L->n, m = L->m;
+    size_t *px = (size_t *)malloc(sizeof(size_t) * (size_t)(n + 1));
+    /* step I: GSLINE-I, every column one line system (the order of sweep C) */
+    for (int k = 0; k < (c->p.order == 0 ? 1 : 4); k++)
+        for (int j = (c->p.order == 0 ? 0 : k); j < m; j += (c->p.order == 0 ? 1 : 4)) {
+            for (int i = 0; i < n; i++) px[i] = (size_t)i * m + j;
+            run_update(c, L, px, n);
+        }
+    free(px);
+    /* step II: the blocks at the jump pixels */
+    for (int cls = 0; cls < (c->p.order == 0 ? 1 : 8); cls++)
+        for (int i = 0; i < n; i++)
+            for (int j = 0; j < m; j++) {
+                if (c->p.order != 0 && ((i + 3 * j) % 8) != cls) continue;
+                uint8_t b = L->lab[(size_t)i * m + j];
+                if (!b) continue;
+                int lag = b & 1 ? 0 : (b & 2 ? 1 : (b & 4 ? 2 : 3));
+                hs1_block(c, L, i, j, lag);
+            }
+}
+
 static void smooth(or_ctx *c, int l, int iters)
 {
     for (int it = 0; it < iters; it++) {
         freeze(c, l);
         if (c->p.smoother == 1) { gslex_sweep(c, l); continue; }
+        if (c->p.smoother == 2) { hs1_outer(c, l); continue; }
         for (int s = 0; s < 4; s++) hs2_sweep(c, l, s);
     }
 }
@@ -1151,7 +1299,7 @@ void or_set_labels(or_ctx *c, int l, const uint8_t *in) { memcpy(c->lev[l].lab, 
 
 /* single steps on level l */
 void or_step_freeze(or_ctx *c, int l) { freeze(c, l); }
-void or_step_sweep(or_ctx *c, int l, int s) { if (s < 4) hs2_sweep(c, l, s); else gslex_sweep(c, l); }
+void or_step_sweep(or_ctx *c, int l, int s) { if (s < 4) hs2_sweep(c, l, s); else if (s == 4) gslex_sweep(c, l); else hs1_outer(c, l); }
 void or_step_smooth(or_ctx *c, int l, int iters) { smooth(c, l, iters); }
 void or_step_coarsest(or_ctx *c, int l) { coarsest(c, l); }
 void or_step_vcycle_level(or_ctx *c, int l) { vcycle_level(c, l); }

@@ -316,6 +316,12 @@ void launch_sweep(mgseg_ctx *c, int l, int s, const float *phi_old, float *phi_n
         if (c->err == hipSuccess) c->err = hipErrorInvalidValue;
         return;
     }
+    // whole-line systems (every cell starred) exist for the forward sweep on the stored coefficients
+    const bool whl = A.bit == LAB_ALL && ml <= 1024;
+    if (whl && (rev || !cfm)) {
+        if (c->err == hipSuccess) c->err = hipErrorInvalidValue;
+        return;
+    }
     const size_t lds = sweep_lds_bytes(ml), llds = long_lds_bytes<1024>(ml), lds2 = sweep2_lds_bytes(ml);
 #define MG_SWEEP_CF(NT, CF)                                                                       \
     do {                                                                                              \
@@ -364,7 +370,16 @@ void launch_sweep(mgseg_ctx *c, int l, int s, const float *phi_old, float *phi_n
     // one thread per cell up to 1024-cell lines; longer lines take rounds.  Up
     // to 512 cells the workgroup has a second half that computes the
     // recomputed neighbour line beside the band's first line.
-    if (ml <= 64) MG_SWEEP2(64);
+    // A whole-line system (every cell starred: the line relaxation of Hybrid
+    // Smoother 1, forward, on the stored coefficients) has kernels of its own
+    // that eliminate the line by a scan.
+    if (whl) {
+        if (ml <= 64) hipLaunchKernelGGL((k_sweep2<64, false, true, true>), dim3(bands), dim3(128), lds2, c->s, A);
+        else if (ml <= 128) hipLaunchKernelGGL((k_sweep2<128, false, true, true>), dim3(bands), dim3(256), lds2, c->s, A);
+        else if (ml <= 256) hipLaunchKernelGGL((k_sweep2<256, false, true, true>), dim3(bands), dim3(512), lds2, c->s, A);
+        else if (ml <= 512) hipLaunchKernelGGL((k_sweep2<512, false, true, true>), dim3(bands), dim3(1024), lds2, c->s, A);
+        else hipLaunchKernelGGL((k_sweep<1024, false, true, true>), dim3(bands), dim3(1024), lds, c->s, A);
+    } else if (ml <= 64) MG_SWEEP2(64);
     else if (ml <= 128) MG_SWEEP2(128);
     else if (ml <= 256) MG_SWEEP2(256);
     else if (ml <= 512) MG_SWEEP2(512);
@@ -465,6 +480,22 @@ void outer(mgseg_ctx *c, int l)
         chk(c);
         return;
     }
+    if (c->p.smoother == 2) {
+        // Hybrid Smoother 1 (Algorithm 2): GSLINE-I on every column (sweep C's order and
+        // layout, every cell starred, the result written row-major), then the blocks at
+        // the jump-set cells in eight classes
+        transpose_f(c, L.P[0], L.prm, L.T[1], L.pcm, L.n, L.m);
+        launch_sweep(c, l, 2, L.T[1], nullptr, L.P[0], L.prm, LAB_ALL);
+        BlockArgs B;
+        B.e = L.P[0]; B.cf = L.cf; B.T = L.F; B.lo = L.lo; B.hi = L.hi; B.lab = L.lab; B.skip = c->sweep_skip;
+        B.p = L.prm; B.n = L.n; B.m = L.m;
+        for (int cls = 0; cls < 8; cls++) {
+            B.cls = cls;
+            hipLaunchKernelGGL(k_hs1_blocks, grid2(L.n, L.m), dim3(256), 0, c->s, B);
+        }
+        chk(c);
+        return;
+    }
     launch_sweep(c, l, 0, L.P[0], L.P[1]);
     launch_sweep(c, l, 1, L.P[1], nullptr, L.T[1], L.pcm);     // written column-major
     launch_sweep(c, l, 2, L.T[1], L.T[2]);
@@ -501,7 +532,7 @@ bool lds_level(mgseg_ctx *c, int l)
 void smooth(mgseg_ctx *c, int l, int iters)
 {
     // grids of at most 8 bands each way: all outer iterations in one workgroup, one band per wave
-    if (iters > 0 && lds_level(c, l) && c->lev[l].n <= 32 && c->lev[l].m <= 32) {
+    if (iters > 0 && lds_level(c, l) && c->lev[l].n <= 32 && c->lev[l].m <= 32 && c->p.smoother != 2) {
         hipLaunchKernelGGL((k_coarse_smooth<512>), dim3(1), dim3(512), coarse_lds_bytes(c->lev[l].n, c->lev[l].m),
                            c->s, coarse_args(c, l, iters, 0.0));
         chk(c);
@@ -518,7 +549,7 @@ void coarsest(mgseg_ctx *c, int l)
     // smooth error a coarse grid corrects) vanishes there: it returns the state it
     // received, a zero coarse correction
     if (L.n * L.m == 1) return;
-    if (lds_level(c, l)) {
+    if (lds_level(c, l) && c->p.smoother != 2) {
         // one wave for a grid of one band, else one band per wave of 512 threads
         const CoarseArgs C = coarse_args(c, l, c->p.coarse_iters, c->p.coarse_rtol);
         if (L.n <= 4 && L.m <= 4)
@@ -775,7 +806,8 @@ mgseg_status setup_check(const float *image_dev, int n, int m, int pitch, const 
     if (p->struct_size != sizeof(mgseg_params)) return MGSEG_E_ARG;
     if (p->model == MGSEG_RADA_CHEN && k < 3) return MGSEG_E_ARG;   // the marker polygon needs an area (A1 > 0)
     if (p->nu1 < 0 || p->nu2 < 0 || p->coarse_iters < 0 || !(p->coarse_rtol >= 0.0) || !(p->M > 0.0) || !(p->eps > 0.0) || p->levels < 0 ||
-        p->levels > MAXLEV || (p->smoother != 0 && p->smoother != 1) || p->run_max < 0 ||
+        p->levels > MAXLEV || p->smoother < 0 || p->smoother > 2 || (p->smoother == 2 && !p->mixed_precision) ||
+        p->run_max < 0 ||
         !(p->sigma_g >= 0.0 && p->sigma_g <= 16.0))
         return MGSEG_E_ARG;
     for (int t = 0; t < 2 * k; t++)

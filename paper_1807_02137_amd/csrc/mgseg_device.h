@@ -90,6 +90,9 @@ __device__ __forceinline__ Ramp ramp_comp(const Ramp &g, const Ramp &f)
 // a label bit no cell carries (the labels use bits 0-3, one per sweep): a
 // sweep with it has no starred cell, every cell a point update
 #define LAB_NONE 4
+// every cell starred: each line is one system (line Gauss-Seidel, GSLINE-I of
+// Sec. 3.2), solved with the box; no cut of the run other than the kernel's
+#define LAB_ALL 5
 
 // --------------------------------------------------------------------------
 // Line-sweep arguments.  All arrays are in the layout of the sweep; `lab`
@@ -364,7 +367,13 @@ __device__ __forceinline__ bool has_run4(uint64_t w0, uint64_t w1)
 // runs are cut into pieces of at most three
 __device__ __forceinline__ bool long_units_possible(const LineArgs &A)
 {
-    return A.bit != LAB_NONE && !(A.run_max >= 1 && A.run_max <= 3);
+    return A.bit == LAB_ALL || (A.bit != LAB_NONE && !(A.run_max >= 1 && A.run_max <= 3));
+}
+// the cut of the runs of a sweep (0: none); whole-line systems are never cut
+__device__ __forceinline__ int run_cut(const LineArgs &A) { return A.bit == LAB_ALL ? 0 : A.run_max; }
+__device__ __forceinline__ bool starred(const LineArgs &A, unsigned lab)
+{
+    return A.bit == LAB_ALL || ((lab >> A.bit) & 1) != 0;
 }
 
 // Units of more than three cells.  Rows k = 0..L-1 of the unit (positions
@@ -641,6 +650,100 @@ __device__ __forceinline__ Ramp block_scan_excl(Ramp mine, Ramp *wtot, int parit
     return ex;
 }
 
+// --------------------------------------------------------------------------
+// The backward elimination of a whole line as a scan.  The step
+//   P_k = a_k / (1 - c_k P_{k+1}),  Q_k = (c_k Q_{k+1} - r_k) / (1 - c_k P_{k+1})
+// is linear-fractional in (P, Q): on the homogeneous vector (Q, P, 1) it acts
+// as the block upper-triangular matrix [[c, 0, -r], [0, 0, a], [0, -c, 1]],
+// and products of such matrices keep the form [[al, b0, b1], [0, B]] (B 2x2):
+// seven numbers.  A scan over the positions from the line's end composes them;
+// position k's prefix applied to the end vector (0, 0, 1) (no successor beyond
+// the line end, where c = 0) gives (Q_k, P_k, 1) up to a common factor.  Each
+// composition is rescaled by its denominator entry B11 (positive: a product of
+// the pivots 1 - c P), which leaves the ratios unchanged and keeps long lines
+// in range; B11 = 1 is then implicit and six numbers are kept, and the
+// prefix's P_k = m01, Q_k = b1.  The compositions run in FP64: composing
+// near-singular steps (strong coupling along the line) in FP32 loses several
+// bits against the sequential elimination, while FP64 leaves P, Q correct to
+// their FP32 rounding.
+struct Elim {
+    double al, b0, b1, m00, m01, m10;
+};
+__device__ __forceinline__ Elim elim_id() { return Elim{1.0, 0.0, 0.0, 1.0, 0.0, 0.0}; }
+__device__ __forceinline__ Elim elim_step(float a, float c, float r)
+{
+    return Elim{(double)c, 0.0, -(double)r, 0.0, (double)a, -(double)c};
+}
+// a fixed value y (P = 0, Q = y)
+__device__ __forceinline__ Elim elim_fixed(float y) { return Elim{0.0, 0.0, (double)y, 0.0, 0.0, 0.0}; }
+// g o f (f applied first), rescaled to B11 = 1
+__device__ __forceinline__ Elim elim_comp(const Elim &g, const Elim &f)
+{
+    // the denominator lies in (0, 2]: the hardware reciprocal and one Newton step
+    const double den = fma(g.m10, f.m01, 1.0);
+    double sc = __builtin_amdgcn_rcp(den);
+    sc = fma(sc, fma(-den, sc, 1.0), sc);
+    Elim o;
+    o.al = g.al * f.al * sc;
+    o.b0 = fma(g.al, f.b0, fma(g.b0, f.m00, g.b1 * f.m10)) * sc;
+    o.b1 = fma(g.al, f.b1, fma(g.b0, f.m01, g.b1)) * sc;
+    o.m00 = fma(g.m00, f.m00, g.m01 * f.m10) * sc;
+    o.m01 = fma(g.m00, f.m01, g.m01) * sc;
+    o.m10 = fma(g.m10, f.m00, f.m10) * sc;
+    return o;
+}
+template <int CTRL, int ROWM = 0xf>
+__device__ __forceinline__ double dpp_d(double old, double src)
+{
+    const long long o = __double_as_longlong(old), v = __double_as_longlong(src);
+    const int lo = __builtin_amdgcn_update_dpp((int)o, (int)v, CTRL, ROWM, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(v >> 32), CTRL, ROWM, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+template <int CTRL, int ROWM = 0xf>
+__device__ __forceinline__ Elim dpp_elim(const Elim &e)
+{
+    return Elim{dpp_d<CTRL, ROWM>(1.0, e.al), dpp_d<CTRL, ROWM>(0.0, e.b0), dpp_d<CTRL, ROWM>(0.0, e.b1),
+                dpp_d<CTRL, ROWM>(1.0, e.m00), dpp_d<CTRL, ROWM>(0.0, e.m01), dpp_d<CTRL, ROWM>(0.0, e.m10)};
+}
+template <int LANES = 64>
+__device__ __forceinline__ Elim wave_scan_elim(Elim v)
+{
+    if (LANES > 1) v = elim_comp(v, dpp_elim<0x111>(v));
+    if (LANES > 2) v = elim_comp(v, dpp_elim<0x112>(v));
+    if (LANES > 4) v = elim_comp(v, dpp_elim<0x114>(v));
+    if (LANES > 8) v = elim_comp(v, dpp_elim<0x118>(v));
+    if (LANES > 16) v = elim_comp(v, dpp_elim<0x142, 0xa>(v));
+    if (LANES > 32) v = elim_comp(v, dpp_elim<0x143, 0xc>(v));
+    return v;
+}
+__device__ __forceinline__ Elim readlane_elim(const Elim &e, int lane)
+{
+    auto rl = [&](double x) {
+        const long long b = __double_as_longlong(x);
+        const int lo = __builtin_amdgcn_readlane((int)b, lane), hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+        return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+    };
+    return Elim{rl(e.al), rl(e.b0), rl(e.b1), rl(e.m00), rl(e.m01), rl(e.m10)};
+}
+// inclusive scan in thread order over the NT threads of the group (t: index in
+// the group); several waves: one barrier (wave totals through LDS)
+template <int NT>
+__device__ __forceinline__ Elim block_scan_elim(Elim mine, Elim *etot, int t)
+{
+    const int lane = t & 63, wave = t >> 6;
+    constexpr int NW = NT / 64;
+    Elim inc = wave_scan_elim<64>(mine);
+    if (NW > 1) {
+        if (lane == 63) etot[wave] = inc;
+        __syncthreads();
+        const Elim ws = wave_scan_elim<NW>(lane < NW ? etot[lane] : elim_id());
+        const int wv = __builtin_amdgcn_readfirstlane(wave);
+        if (wv > 0) inc = elim_comp(inc, readlane_elim(ws, wv - 1));
+    }
+    return inc;
+}
+
 // Global inputs of one cell of a line (the frozen state of the sweep and the
 // old values): everything phase 1 of a line step reads from memory, so that
 // the next line's reads can be issued before the current line is computed
@@ -782,6 +885,22 @@ __device__ __forceinline__ void row_store(const Buf &B, int p, const CellRow &w)
     B.at(RF_HI, p) = w.hi;
     B.at(RF_X, p) = w.x;
 }
+// the row back from LDS (as row_store left it; pb is not kept, the cell being a unit cell)
+template <class Buf>
+__device__ __forceinline__ CellRow row_load(const Buf &B, int p)
+{
+    CellRow w;
+    const float a = B.at(RF_A, p);
+    w.ok = !isnan(a);
+    w.a = w.ok ? a : 0.0f;
+    w.c = B.at(RF_C, p);
+    w.rr = B.at(RF_R, p);
+    w.pb = 0.0f;
+    w.lo = B.at(RF_LO, p);
+    w.hi = B.at(RF_HI, p);
+    w.x = B.at(RF_X, p);
+    return w;
+}
 
 // --------------------------------------------------------------------------
 // One line of one directional sweep, one thread per cell (visit position
@@ -815,10 +934,10 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
-template <int NT, bool REV, bool CF = false, bool WS = false>
+template <int NT, bool REV, bool CF = false, bool WS = false, bool WH = false>
 __device__ __forceinline__ float sweep_line(const LineArgs &A, int r, const RunBuf &B, uint64_t *msk, bool write,
                                             float upv, bool up_fresh, float dnv, bool dn_fresh, Ramp *wtot,
-                                            unsigned *wbad, const CellIn &c, int t, bool act)
+                                            unsigned *wbad, Elim *etot, const CellIn &c, int t, bool act)
 {
     static_assert(!WS || NT == 64, "a wave-synchronous line is one wave");
     if (WS) wave_lds_sync();
@@ -837,7 +956,7 @@ __device__ __forceinline__ float sweep_line(const LineArgs &A, int r, const RunB
     w.ok = false; w.x = 0.0f;
     bool s0 = false;
     if (in) {
-        s0 = ((c.lab >> A.bit) & 1) != 0;
+        s0 = starred(A, c.lab);
         float vu = 0.0f, vd = 0.0f;
         if (has_up) vu = up_fresh ? upv : c.vu;
         if (has_dn) vd = dn_fresh ? dnv : c.vd;
@@ -862,6 +981,28 @@ __device__ __forceinline__ float sweep_line(const LineArgs &A, int r, const RunB
         if (lmode) any_long = __ballot(has_run4(w0, lane + 1 < nw ? msk[lane + 1] : 0ull)) != 0ull;
     }
 
+    // phase 1b: a whole-line system (every cell starred, more than three cells) is eliminated by
+    // one scan from the line's end: the thread of index t takes position ml - 1 - t and leaves
+    // that position's P, Q in RF_P, RF_Q
+    const bool whole = WH && ml > 3;
+    if (whole) {
+        const int pr = ml - 1 - t;
+        Elim e = elim_id();
+        if (act && pr >= 0) {
+            const float a = B.at(RF_A, pr);
+            e = isnan(a) ? elim_fixed(B.at(RF_X, pr)) : elim_step(a, B.at(RF_C, pr), B.at(RF_R, pr));
+        }
+        const Elim pre = block_scan_elim<NT>(e, etot, t);
+        if (act && pr >= 0) {
+            B.at(RF_P, pr) = (float)pre.m01;
+            B.at(RF_Q, pr) = (float)pre.b1;
+        }
+        if (NT == 64 && WS) wave_lds_sync();
+        else __syncthreads();
+        // the row is taken again from LDS, so that no register holds it across the scan
+        if (in) w = row_load(B, p);
+    }
+
     // phase 2: the cell's unit (ps, L; L = 0: a point); the chain ramp of a unit of at most three
     // cells at its last cell; every cell of a longer unit its own Z_k
     int ps = p, Lu = 0;
@@ -870,12 +1011,12 @@ __device__ __forceinline__ float sweep_line(const LineArgs &A, int r, const RunB
     if (in) {
         if (any_star) {
             if (NT == 64) {
-                if (s0) unit_of1(bm, ml, p, A.run_max, ps, Lu);
+                if (s0) unit_of1(bm, ml, p, run_cut(A), ps, Lu);
                 else if (p >= 1 && ((bm >> (p - 1)) & 1ull) && (p < 2 || !((bm >> (p - 2)) & 1ull))) {
                     ps = p - 1; Lu = 2;
                 }
             } else {
-                if (s0) unit_of(msk, nw, ml, p, A.run_max, ps, Lu);
+                if (s0) unit_of(msk, nw, ml, p, run_cut(A), ps, Lu);
                 else if (p >= 1 && mask_bit(msk, p - 1) && (p < 2 || !mask_bit(msk, p - 2))) { ps = p - 1; Lu = 2; }
             }
         }
@@ -884,7 +1025,13 @@ __device__ __forceinline__ float sweep_line(const LineArgs &A, int r, const RunB
         } else if (Lu > 3) {
             const int last = ps + Lu - 1;
             float P, Q;
-            long_elim(B, p, last, B.sig_after(last, ml), P, Q, lP1, lQ1);
+            if (whole) {
+                P = B.at(RF_P, p); Q = B.at(RF_Q, p);
+                if (p < last) { lP1 = B.at(RF_P, p + 1); lQ1 = B.at(RF_Q, p + 1); }
+                else { lP1 = 0.0f; lQ1 = B.sig_after(last, ml); }
+            } else {
+                long_elim(B, p, last, B.sig_after(last, ml), P, Q, lP1, lQ1);
+            }
             u = Ramp{P, Q, w.lo, w.hi};
             if (p == ps) B.at(RF_P, ps) = 0.0f;      // the unit's failed-check flag
         } else if (ps + Lu - 1 == p) {
@@ -961,7 +1108,43 @@ __device__ __forceinline__ float sweep_line(const LineArgs &A, int r, const RunB
         for (int pass = 0;; pass++) {
             Ramp u2 = ramp_id();
             float st = 0.0f;
-            if (fu) {
+            if (whole) {
+                // the free chains of the whole line eliminated by one scan (held cells fixed at
+                // their bounds); P into RF_P, Q into RF_O (the values are not read again before
+                // the substitution writes them)
+                const int pr = ml - 1 - t;
+                Elim e = elim_id();
+                if (act && pr >= 0) {
+                    // a cell of S = 0 keeps its old value, a held cell its bound
+                    const float sq = B.at(RF_Q, pr), a = B.at(RF_A, pr);
+                    if (isnan(a) || sq < 0.0f) {
+                        const float y = isnan(a) ? B.at(RF_X, pr) : (sq == -1.0f ? B.at(RF_LO, pr) : B.at(RF_HI, pr));
+                        e = elim_fixed(y);
+                    } else {
+                        e = elim_step(a, B.at(RF_C, pr), B.at(RF_R, pr));
+                    }
+                }
+                const Elim pre = block_scan_elim<NT>(e, etot, t);
+                if (act && pr >= 0) {
+                    B.at(RF_P, pr) = (float)pre.m01;
+                    B.at(RF_O, pr) = (float)pre.b1;
+                }
+                if (NT == 64 && WS) wave_lds_sync();
+                else __syncthreads();
+                if (in) w = row_load(B, p);
+            }
+            if (fu && whole) {
+                st = B.at(RF_Q, p);
+                const float P2 = B.at(RF_P, p), Q2 = B.at(RF_O, p);
+                if (st < 0.0f) {
+                    u2 = Ramp{0.0f, Q2, Q2, Q2};
+                } else if (p == ps) {
+                    const float y0 = fmaf(P2, x, Q2);
+                    u2 = Ramp{0.0f, y0, y0, y0};
+                } else {
+                    u2 = Ramp{P2, Q2, -MG_BIG, MG_BIG};
+                }
+            } else if (fu) {
                 st = B.at(RF_Q, p);
                 float P2 = 0.0f, Q2 = su;
 #pragma nounroll
@@ -998,8 +1181,10 @@ __device__ __forceinline__ float sweep_line(const LineArgs &A, int r, const RunB
             // its row points back into the box (beyond rounding)
             bool chg = false;
             if (fu) {
-                float ns = 0.0f;
-                if (st == 0.0f) {
+                float ns = st;
+                if (!w.ok) {
+                    // a cell of S = 0 (whole lines only) stays at its old value
+                } else if (st == 0.0f) {
                     ns = yv < w.lo ? -1.0f : (yv > w.hi ? -2.0f : 0.0f);
                 } else {
                     const float yp = p == ps ? x : B.at(RF_O, p - 1);
@@ -1084,9 +1269,9 @@ __device__ __forceinline__ void band_step(int r0, int nl, int st, int &r, bool &
 // CellIn).  B: the first of two row buffers; lpar: the caller's running line
 // count, whose parity picks the buffer of each line (it continues across
 // bands that one workgroup takes one after another).
-template <int NT, bool REV, bool PF = false, bool CF = false, bool WS = false>
+template <int NT, bool REV, bool PF = false, bool CF = false, bool WS = false, bool WH = false>
 __device__ __forceinline__ void sweep_band(const LineArgs &A, int b, const RunBuf &B, uint64_t *msk, Ramp *wtot,
-                                           unsigned *wbad, int &lpar)
+                                           unsigned *wbad, Elim *etot, int &lpar)
 {
     // transposed output of a full band: the band's 4 lines are 4 consecutive
     // floats of the output layout, written as one 16-byte store per cell
@@ -1122,8 +1307,8 @@ __device__ __forceinline__ void sweep_band(const LineArgs &A, int b, const RunBu
         } else {
             load(r, up_fresh, dn_fresh, la);
         }
-        const float cur = sweep_line<NT, REV, CF, WS>(A, r, B.other(lpar & 1), msk, !redundant && !pack, prev,
-                                                      up_fresh, red, dn_fresh, wtot, wbad, la, t, true);
+        const float cur = sweep_line<NT, REV, CF, WS, WH>(A, r, B.other(lpar & 1), msk, !redundant && !pack, prev,
+                                                      up_fresh, red, dn_fresh, wtot, wbad, etot, la, t, true);
         lpar++;
         const int li = r - r0;
         if (redundant) red = cur;
@@ -1154,10 +1339,10 @@ __device__ __forceinline__ void sweep_band(const LineArgs &A, int b, const RunBu
 // buffers and scan totals.  Lines of one wave (NT = 64) take no block barrier
 // inside a step: each half runs its own steps, and one block barrier before
 // the last step publishes the recomputed line.
-template <int NT, bool REV, bool PF, bool CF>
+template <int NT, bool REV, bool PF, bool CF, bool WH>
 __device__ __forceinline__ void sweep_band2(const LineArgs &A, int b, const RunBuf &B0, const RunBuf &B1,
                                             uint64_t *msk0, uint64_t *msk1, Ramp *wtot0, Ramp *wtot1, float *redl,
-                                            unsigned *wbad)
+                                            unsigned *wbad, Elim *etot0, Elim *etot1)
 {
     constexpr bool WS = NT == 64;
     // read all four steps' inputs at the start where the registers allow it
@@ -1170,6 +1355,7 @@ __device__ __forceinline__ void sweep_band2(const LineArgs &A, int b, const RunB
     const RunBuf B = half ? B1 : B0;
     uint64_t *msk = half ? msk1 : msk0;
     Ramp *wtot = half ? wtot1 : wtot0;
+    Elim *etot = half ? etot1 : etot0;
     auto valid = [&](int st) { const int r = band_line<REV>(r0, st); return r >= 0 && r < nl; };
     // the band step of this half's k-th call (-1: none): lower 0, 1, 2, 4; upper 3
     auto step_of = [&](int k) { return half == 0 ? (k < 3 ? k : 4) : (k == 0 ? 3 : -1); };
@@ -1204,21 +1390,31 @@ __device__ __forceinline__ void sweep_band2(const LineArgs &A, int b, const RunB
         const float dnv = act && dn_fresh && t < ml ? redl[t] : 0.0f;
         float cur = 0.0f;
         if (act) {
-            cur = sweep_line<NT, REV, CF, WS>(A, r, B.other(k & 1), msk, !redundant && !pack, prev, up_fresh, dnv,
-                                              dn_fresh, wtot, wbad, la, t, true);
+            cur = sweep_line<NT, REV, CF, WS, WH>(A, r, B.other(k & 1), msk, !redundant && !pack, prev, up_fresh, dnv,
+                                              dn_fresh, wtot, wbad, etot, la, t, true);
         } else if (!WS) {
             // a half with no line takes the line step's barriers only: the one after the rows and
             // masks, the scan's (several waves), and those of the long-unit check (its waves
             // publish no failure)
+            const bool whole = WH && ml > 3;
             __syncthreads();
+            if (whole) {
+                if (NT > 64) __syncthreads();
+                __syncthreads();
+            }
             if (NT > 64) __syncthreads();
             if (long_units_possible(A)) {
                 const bool l0 = (threadIdx.x & 63) == 0;
                 if (l0) wbad[threadIdx.x >> 6] = 0u;
                 __syncthreads();
                 if (block_flag(wbad)) {
-                    // the repair's passes: scan, values, flags (and the serial finish after eight)
+                    // the repair's passes: [whole lines: elimination scan and its publication,]
+                    // scan, values, flags (and the serial finish after eight)
                     for (int pass = 0;; pass++) {
+                        if (whole) {
+                            if (NT > 64) __syncthreads();
+                            __syncthreads();
+                        }
                         if (NT > 64) __syncthreads();
                         __syncthreads();
                         if (l0) wbad[threadIdx.x >> 6] = 0u;
@@ -1312,7 +1508,7 @@ __device__ __forceinline__ void long_band(const LineArgs &A, int b, float *ring,
 #pragma nounroll
         for (int k = 0; k < K; k++) {
             const int p = k * NT + t;
-            const bool s0 = p < ml && ((R.lab[cell(p)] >> A.bit) & 1) != 0;
+            const bool s0 = p < ml && starred(A, R.lab[cell(p)]);
             const unsigned long long bm = __ballot(s0);
             if (lane == 0 && k * NT + wave * 64 < ml) msk[((k * NT) >> 6) + wave] = bm;
         }
@@ -1338,7 +1534,7 @@ __device__ __forceinline__ void long_band(const LineArgs &A, int b, float *ring,
                 const float vd = has_dn ? (dn_fresh ? red[p] : c.vd) : 0.0f;
                 w = cell_row<REV, CF>(A, c, r, cell(p), vu, vd, area);
                 if (mask_bit(msk, p)) {
-                    unit_of(msk, nw, ml, p, A.run_max > 0 && A.run_max < NT ? A.run_max : NT, ps, L);
+                    unit_of(msk, nw, ml, p, run_cut(A) > 0 && run_cut(A) < NT ? run_cut(A) : NT, ps, L);
                     inu = true;
                 } else if (p >= 1 && mask_bit(msk, p - 1) && (p < 2 || !mask_bit(msk, p - 2))) {
                     ps = p - 1; L = 2;               // the cell after a single starred cell
@@ -1440,13 +1636,14 @@ __host__ __device__ inline size_t sweep2_lds_bytes(int ml)
     return 2 * sweep_lds_bytes(ml) + (size_t)ml * sizeof(float);
 }
 
-template <int NT, bool REV, bool CF>
+template <int NT, bool REV, bool CF, bool WH = false>
 __global__ void __launch_bounds__(2 * NT) k_sweep2(LineArgs A)
 {
     if (A.skip && *A.skip) return;
     extern __shared__ uint64_t smem64[];
     __shared__ Ramp wtot[2][2 * (NT / 64)];
     __shared__ unsigned wbad[2 * (NT / 64)];
+    __shared__ Elim etot[2][NT / 64];
     const int nw = sweep_mask_words(A.ml);
     RunBuf B0, B1;
     B0.fs = A.ml;
@@ -1454,18 +1651,20 @@ __global__ void __launch_bounds__(2 * NT) k_sweep2(LineArgs A)
     B1.fs = A.ml;
     B1.p = B0.p + 2 * RB_FIELDS * A.ml;
     float *redl = B1.p + 2 * RB_FIELDS * A.ml;
-    // read-ahead of the next line where the registers allow it (1024 threads: only with the stored coefficients)
-    sweep_band2<NT, REV, (NT <= 256 || CF), CF>(A, blockIdx.x, B0, B1, smem64, smem64 + nw, wtot[0], wtot[1], redl,
-                                                wbad);
+    // read-ahead of the next line where the registers allow it (1024 threads: only with the stored
+    // coefficients, and not beside the whole-line elimination)
+    sweep_band2<NT, REV, (NT <= 256 || (CF && !WH)), CF, WH>(A, blockIdx.x, B0, B1, smem64, smem64 + nw, wtot[0], wtot[1], redl,
+                                                wbad, etot[0], etot[1]);
 }
 
-template <int NT, bool REV, bool CF>
+template <int NT, bool REV, bool CF, bool WH = false>
 __global__ void __launch_bounds__(NT) k_sweep(LineArgs A)
 {
     if (A.skip && *A.skip) return;
     extern __shared__ uint64_t smem64[];
     __shared__ Ramp wtot[2 * (NT / 64 > 0 ? NT / 64 : 1)];
     __shared__ unsigned wbad[NT / 64 > 0 ? NT / 64 : 1];
+    __shared__ Elim etot[NT / 64 > 0 ? NT / 64 : 1];
     uint64_t *msk = smem64;
     RunBuf B;
     B.fs = A.ml;
@@ -1473,5 +1672,5 @@ __global__ void __launch_bounds__(NT) k_sweep(LineArgs A)
     // read-ahead of the next line where the registers allow it (at 1024 threads, 128 registers per
     // lane: only with the stored coefficients)
     int lpar = 0;
-    sweep_band<NT, REV, (NT <= 512 || CF), CF>(A, blockIdx.x, B, msk, wtot, wbad, lpar);
+    sweep_band<NT, REV, (NT <= 512 || CF) && !WH, CF, false, WH>(A, blockIdx.x, B, msk, wtot, wbad, etot, lpar);
 }

@@ -975,6 +975,121 @@ __global__ void __launch_bounds__(256) k_coarse_delta(const float *x, const floa
     if (t == 0 && (double)r0[0] <= rtol * (double)r1[0]) stop[0] = 1;
 }
 
+// ==========================================================================
+// Hybrid Smoother 1, step II (Sec. 4.2, eqs. caseAlagged .. caseDlagged): at
+// a jump-set cell whose smallest coefficient is s, the cell and its three
+// neighbours other than the one behind s are updated collectively (the
+// neighbour behind s is lagged).  Each neighbour's row is its own equation
+// (its coefficient towards the centre; with delta-scaled rows the centre's
+// towards it, as the paper's arrow matrices write it), every other cell at its
+// current value.  In the deviation form the rows are those of the freeze:
+//   sum_f a_f e_nb - S e = T   (a_f the stored scaled face coefficients).
+// The box-constrained block is solved exactly: a leaf k is the clipped ramp
+// x_k = clip(al_k y + be_k, lo_k, hi_k) of the centre value y, so the centre
+// solves y = clip(g(y), lo, hi) with g monotone piecewise linear of slope
+// below one (diagonal dominance); y - clip(g(y)) increases, and its root lies
+// on the linear piece between the largest candidate (the leaves' kinks and
+// the centre's bounds) where it is <= 0 and the smallest where it is >= 0.
+// Cells of class (i + 3 j) mod 8 = cls only: two of them are at least four
+// cells apart, so the blocks of one launch share no cell and read none that
+// another writes.
+struct BlockArgs {
+    float *e;                    // row-major state (pitch p)
+    const float4 *cf;            // frozen scaled face coefficients: to i+1, i-1, j+1, j-1
+    const float *T, *lo, *hi;    // right-hand side and bounds of the rows
+    const uint8_t *lab;          // labels: bit s = jump set with smallest coefficient s
+    const int *skip;             // non-null and set: the launch does nothing
+    int p, n, m, cls;
+};
+__device__ __forceinline__ float blk_coef(const float4 &g, int s)
+{
+    return s == 0 ? g.x : (s == 1 ? g.y : (s == 2 ? g.z : g.w));
+}
+__global__ void __launch_bounds__(256) k_hs1_blocks(BlockArgs B)
+{
+    if (B.skip && *B.skip) return;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x, i = blockIdx.y;
+    if (i >= B.n || j >= B.m || ((i + 3 * j) & 7) != B.cls) return;
+    const long long q0 = (long long)i * B.p + j;
+    const unsigned lb = B.lab[q0];
+    if (!lb) return;
+    const int lag = (lb & 1) ? 0 : ((lb & 2) ? 1 : ((lb & 4) ? 2 : 3));
+    const int di[4] = {1, -1, 0, 0}, dj[4] = {0, 0, 1, -1}, back[4] = {1, 0, 3, 2};
+    auto inside = [&](int a, int b) { return a >= 0 && a < B.n && b >= 0 && b < B.m; };
+    const float4 g0 = B.cf[q0];
+    const float S0 = g0.x + g0.y + g0.z + g0.w;
+    if (!(S0 > 0.0f)) return;
+    // centre row: sum over leaves a_k x_k - S0 y = T0 - a_lag e_lag
+    float rhs0 = B.T[q0];
+    if (inside(i + di[lag], j + dj[lag]))
+        rhs0 -= blk_coef(g0, lag) * B.e[(long long)(i + di[lag]) * B.p + j + dj[lag]];
+    float gam[3], al[3], be[3], llo[3], lhi[3];
+    long long lq[3];
+    int nl = 0;
+    for (int s = 0; s < 4; s++) {
+        if (s == lag) continue;
+        const int a = i + di[s], b = j + dj[s];
+        if (!inside(a, b)) continue;
+        const long long q = (long long)a * B.p + b;
+        const float4 g = B.cf[q];
+        const float S = g.x + g.y + g.z + g.w;
+        if (!(S > 0.0f)) return;
+        // leaf row: a_(leaf -> centre) y - S x = T - (its other neighbours at their values)
+        float r = B.T[q];
+        for (int t = 0; t < 4; t++) {
+            if (t == back[s]) continue;
+            const int c2 = a + di[t], d2 = b + dj[t];
+            if (inside(c2, d2)) r -= blk_coef(g, t) * B.e[(long long)c2 * B.p + d2];
+        }
+        const float inv = 1.0f / S;
+        gam[nl] = blk_coef(g0, s) / S0;
+        al[nl] = blk_coef(g, back[s]) * inv;
+        be[nl] = -r * inv;
+        llo[nl] = B.lo[q]; lhi[nl] = B.hi[q];
+        lq[nl] = q;
+        nl++;
+    }
+    const float be0 = -rhs0 / S0, lo0 = B.lo[q0], hi0 = B.hi[q0];
+    auto leaf = [&](int k, float y) { return mg_clip(fmaf(al[k], y, be[k]), llo[k], lhi[k]); };
+    auto g_of = [&](float y) {
+        float v = be0;
+        for (int k = 0; k < nl; k++) v = fmaf(gam[k], leaf(k, y), v);
+        return v;
+    };
+    auto psi = [&](float y) { return y - mg_clip(g_of(y), lo0, hi0); };
+    // candidates: the leaves' kinks and the centre's bounds
+    float plo = lo0, phi = hi0;
+    for (int k = 0; k < nl; k++) {
+        if (!(al[k] > 0.0f)) continue;
+        const float ia = 1.0f / al[k];
+        const float c2[2] = {(llo[k] - be[k]) * ia, (lhi[k] - be[k]) * ia};
+        for (int t = 0; t < 2; t++) {
+            const float pc = mg_clip(c2[t], lo0, hi0);
+            const float v = psi(pc);
+            if (v <= 0.0f && pc > plo) plo = pc;
+            if (v >= 0.0f && pc < phi) phi = pc;
+        }
+    }
+    float y;
+    if (psi(lo0) >= 0.0f) y = lo0;
+    else if (psi(hi0) <= 0.0f) y = hi0;
+    else if (!(phi > plo)) y = plo;
+    else {
+        // g on (plo, phi): each leaf either at a bound or on its ramp
+        const float mid = 0.5f * (plo + phi);
+        float sl = 0.0f, c0 = be0;
+        for (int k = 0; k < nl; k++) {
+            const float v = fmaf(al[k], mid, be[k]);
+            if (v <= llo[k]) c0 = fmaf(gam[k], llo[k], c0);
+            else if (v >= lhi[k]) c0 = fmaf(gam[k], lhi[k], c0);
+            else { sl = fmaf(gam[k], al[k], sl); c0 = fmaf(gam[k], be[k], c0); }
+        }
+        y = mg_clip(mg_clip(c0 / (1.0f - sl), lo0, hi0), plo, phi);
+    }
+    B.e[q0] = y;
+    for (int k = 0; k < nl; k++) B.e[lq[k]] = leaf(k, y);
+}
+
 __global__ void k_set_int(int *p, int v)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) p[0] = v;
@@ -1111,7 +1226,7 @@ __global__ void __launch_bounds__(NT) k_coarse_smooth(CoarseArgs G)
         int lpar = 0;
         R.phi_old = P0; R.phi_new = P1; R.bit = G.smoother == 1 ? LAB_NONE : 0;
         for (int b = wave; b < (n + 3) / 4; b += NWV)
-            sweep_band<64, false, true, true, true>(R, b, RBr, mskw, shw, nullptr, lpar);
+            sweep_band<64, false, true, true, true>(R, b, RBr, mskw, shw, nullptr, nullptr, lpar);
         __syncthreads();
         if (G.smoother == 1) {
             // GSLEX-I: the pass of sweep A is the whole outer iteration
@@ -1120,18 +1235,18 @@ __global__ void __launch_bounds__(NT) k_coarse_smooth(CoarseArgs G)
         } else {
             R.phi_old = P1; R.phi_new = P2; R.bit = 1;
             for (int b = wave; b < (n + 3) / 4; b += NWV)
-                sweep_band<64, true, true, true, true>(R, b, RBr, mskw, shw, nullptr, lpar);
+                sweep_band<64, true, true, true, true>(R, b, RBr, mskw, shw, nullptr, nullptr, lpar);
             __syncthreads();
             block_transpose<NT>(P2, m, T1, n, n, m);
             __syncthreads();
             // sweeps C and D (columns)
             T.phi_old = T1; T.phi_new = T2; T.bit = 2;
             for (int b = wave; b < (m + 3) / 4; b += NWV)
-                sweep_band<64, false, true, true, true>(T, b, RBc, mskw, shw, nullptr, lpar);
+                sweep_band<64, false, true, true, true>(T, b, RBc, mskw, shw, nullptr, nullptr, lpar);
             __syncthreads();
             T.phi_old = T2; T.phi_new = T1; T.bit = 3;
             for (int b = wave; b < (m + 3) / 4; b += NWV)
-                sweep_band<64, true, true, true, true>(T, b, RBc, mskw, shw, nullptr, lpar);
+                sweep_band<64, true, true, true, true>(T, b, RBc, mskw, shw, nullptr, nullptr, lpar);
             __syncthreads();
         }
         float dmax = 0.0f, tot = 0.0f;

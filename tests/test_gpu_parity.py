@@ -363,6 +363,29 @@ def test_single_sweep_units_across_rounds(shape, sweep):
     s.close()
 
 
+@pytest.mark.parametrize("seed", [1000, 1001, 1002])
+def test_solve_parity_hybrid1(seed):
+    """Algorithm 2 (Hybrid Smoother 1: GSLINE-I on every column, then the arrow
+    blocks at the jump-set cells in eight classes) against the oracle's Hybrid
+    Smoother 1 in the same order: the cycle histories and the final segmentation."""
+    say("case Hybrid Smoother 1 seed", seed)
+    inst, s, o = make(seed, smoother=2)
+    hg, ho = [], []
+    for _ in range(40):
+        hg.append(s.vcycle())
+        if hg[-1] <= 1e-6:
+            break
+    k, hist = o.solve(1e-6, 40)
+    pg, po = s.phi().cpu().numpy(), o.get("phi")
+    agree = (pg > 0) == (po > 0)
+    flips = int((~agree).sum())
+    dmax = float(np.abs(pg - po)[agree].max()) if agree.any() else 0.0
+    say(f"gpu {len(hg)} cycles {np.round(hg, 4)}; oracle {k} cycles {np.round(hist, 4)}; flips {flips} max|dphi| {dmax:.3e}")
+    assert hg[-1] <= 1e-6 and k > 0 and abs(len(hg) - k) <= 1
+    assert flips <= 1 and dmax <= 1e-4
+    s.close()
+
+
 def plant_long_runs(lab, sweep, lengths, seed=0):
     """Sets the sweep's starred bit on runs of the given lengths along every
     line (visit order), separated by at least one unstarred cell: the first

@@ -314,3 +314,80 @@ def test_lfa_hybrid2_rate_matches_the_oracles_own_sweep():
         want = lfa.rate_hybrid2(np.array(coef))
         got = _measured_sweep_rate(coef, s)
         assert abs(got - want) <= 0.015, (coef, got, want)
+
+
+# ------------------------------------------------- Hybrid Smoother 1 (Sec. 4.2, Algorithm 2)
+from oracle import box_dense  # noqa: E402
+
+
+def _arrow(rng, k):
+    """A random arrow matrix (centre coupled to k - 1 leaves, leaves to the centre
+    only) with a negative, strictly dominant diagonal, as eqs. caseAlagged-caseDlagged."""
+    M = np.zeros((k, k))
+    for a in range(1, k):
+        M[0, a] = rng.uniform(0.1, 1.0)
+        M[a, 0] = rng.uniform(0.1, 1.0)
+    for a in range(k):
+        M[a, a] = -(np.abs(M[a]).sum() + rng.uniform(0.05, 1.0))
+    return M
+
+
+def test_box_dense_unconstrained_matches_linalg():
+    rng = np.random.default_rng(5)
+    for _ in range(50):
+        k = int(rng.integers(2, 5))
+        M, b = _arrow(rng, k), rng.normal(0, 2, k)
+        x = box_dense(M, b, np.full(k, -1e9), np.full(k, 1e9))
+        assert np.abs(x - np.linalg.solve(M, b)).max() <= 1e-12 * (1 + np.abs(x).max())
+
+
+def test_box_dense_matches_projected_gauss_seidel():
+    """Against brute force: projected Gauss-Seidel iterated to a fixed point (the
+    unique solution of the box-constrained M-matrix problem)."""
+    rng = np.random.default_rng(6)
+    for _ in range(200):
+        k = int(rng.integers(2, 5))
+        M, b = _arrow(rng, k), rng.normal(0, 3, k)
+        lo, hi = rng.uniform(-2, 0, k), rng.uniform(0, 2, k)
+        x = box_dense(M, b, lo, hi)
+        y = np.zeros(k)
+        for _ in range(5000):
+            for a in range(k):
+                v = (b[a] - M[a] @ y + M[a, a] * y[a]) / M[a, a]
+                y[a] = min(hi[a], max(lo[a], v))
+        assert np.abs(x - y).max() <= 1e-10
+
+
+def test_eight_class_order_keeps_blocks_apart():
+    """Two jump pixels of one class (i + 3 j) mod 8 are at least four cells apart
+    (L1), so their blocks (the pixel and its neighbours) share no pixel and neither
+    reads a pixel the other writes (a block reads up to two cells from its centre)."""
+    for di in range(-4, 5):
+        for dj in range(-4, 5):
+            if (di, dj) != (0, 0) and (di + 3 * dj) % 8 == 0:
+                assert abs(di) + abs(dj) >= 4
+
+
+def test_hybrid1_fixed_point_is_projected_solution():
+    """Iterated on one grid, Hybrid Smoother 1 (GSLINE-I on every column, then the
+    blocks at the jump pixels) stops at a point where the projected residual of
+    the discrete equations vanishes."""
+    inst = synth.tiny_instance(8, 20, 24)
+    o = Oracle(inst.image, inst.markers, OracleParams(levels=1, smoother=2))
+    o.smooth(400, 0)
+    r = o.residual(0, True)
+    assert np.abs(r).max() <= 1e-9
+
+
+@pytest.mark.parametrize("seed", [1000, 1001, 1002])
+def test_hybrid1_paper_order_and_parallel_order_agree(seed):
+    """Algorithm 2 with the paper's order and with the parallel order (four column
+    classes, eight block classes) reach 1e-6 and the same segmentation."""
+    inst = synth.config1(seed)
+    out = []
+    for order in (0, 1):
+        o = Oracle(inst.image, inst.markers, OracleParams(levels=6, smoother=2, order=order))
+        k, hist = o.solve(1e-6, 40)
+        assert k > 0
+        out.append(o.get("phi") > 0)
+    assert np.array_equal(out[0], out[1])
