@@ -6,4 +6,4 @@ links or executes anything from this package, and this package imports
 nothing from the product package.
 """
 from .core import (Oracle, OracleParams, box_dense, box_tridiag, build_oracle, hull, line_units, prolong,  # noqa: F401
-                   restrict, setup_maps, visit_order)
+                   restrict, setup_maps, tridiag_solve, visit_order)

@@ -102,6 +102,12 @@ def _load():
         _lib.or_energy.argtypes = [C.c_void_p]
         _lib.or_timemarch.restype = C.c_double
         _lib.or_timemarch.argtypes = [C.c_void_p, C.c_long, C.c_double, C.c_int, C.c_double]
+        _lib.or_aos_step.restype = C.c_double
+        _lib.or_aos_step.argtypes = [C.c_void_p, C.c_double]
+        _lib.or_aos.restype = C.c_int
+        _lib.or_aos.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_int, dp]
+        _lib.or_tridiag_solve.restype = None
+        _lib.or_tridiag_solve.argtypes = [C.c_int, dp, dp, dp, dp]
         _lib.or_levels.restype = C.c_int
         _lib.or_levels.argtypes = [C.c_void_p]
         _lib.or_level_shape.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), dp]
@@ -180,6 +186,14 @@ def box_dense(M, b, bl, bh):
     x = np.zeros(len(b))
     ok = _load().or_box_dense(len(b), _dp(M), *[_dp(a) for a in arrs], _dp(x))
     return x if ok else None
+
+
+def tridiag_solve(lo, di, up, rhs):
+    """The oracle's Thomas solve of lo_k x_{k-1} + di_k x_k + up_k x_{k+1} = rhs_k."""
+    arrs = [np.ascontiguousarray(a, np.float64) for a in (lo, di, up)]
+    x = np.array(rhs, np.float64)
+    _load().or_tridiag_solve(len(x), *[_dp(a) for a in arrs], _dp(x))
+    return x
 
 
 def line_units(labels_line, bit, run_max=0):
@@ -304,6 +318,18 @@ class Oracle:
 
     def timemarch(self, steps, cfl=0.2, crefresh=100, tol=0.0) -> float:
         return self.lib.or_timemarch(self.ctx, steps, cfl, crefresh, tol)
+
+    def aos_step(self, tau: float) -> float:
+        """One AOS step of the finest grid (time step tau in units of h/mu), then
+        the region means refreshed; returns the relative change of phi."""
+        return self.lib.or_aos_step(self.ctx, tau)
+
+    def aos(self, tau: float, eta_tol: float = 1e-4, max_iters: int = 200):
+        """AOS steps until the relative change falls below eta_tol: (steps, changes);
+        steps is negative when the tolerance was not reached."""
+        hist = np.zeros(max_iters)
+        k = self.lib.or_aos(self.ctx, tau, eta_tol, max_iters, _dp(hist))
+        return k, hist[: abs(k)]
 
     # --- single steps
     def freeze(self, l=0):

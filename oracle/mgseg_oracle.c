@@ -1255,6 +1255,117 @@ double or_timemarch(or_ctx *c, long steps, double cfl, int crefresh, double tol)
 }
 
 /* ------------------------------------------------------------------------ */
+/* AOS: additive operator splitting, the semi-implicit time stepper of the  */
+/* comparison in Sec. 5 (Table 4) and one of the "exact" solvers Algorithm 1 */
+/* names for the coarsest grid.  The paper gives no formula of its own; this */
+/* is the standard scheme (Weickert, ter Haar Romeny & Viergever 1998) for   */
+/* phi_t = N(phi) - F on level l with the coefficients of eq. abcdrc frozen  */
+/* at phi^k:                                                                  */
+/*   y_1 = (I - 2 tau A_1)^{-1} (phi^k - tau (f + F))   (A_1: the couplings  */
+/*         A, B to i+1, i-1, one tridiagonal system per column),              */
+/*   y_2 = (I - 2 tau A_2)^{-1} (phi^k - tau (f + F))   (A_2: C, D to j+-1,  */
+/*         one system per row),                                               */
+/*   phi^{k+1} = clamp((y_1 + y_2) / 2, lo, hi).                              */
+/* A_1 and A_2 have zero row sums, so each factor keeps constants.  tau_hat  */
+/* is the step in units of h / mu, so that 2 tau A = 2 tau_hat G with G the  */
+/* face values.                                                               */
+
+/* Thomas algorithm for lo_k x_{k-1} + di_k x_k + up_k x_{k+1} = x_k (the    */
+/* right-hand side in x, the solution returned there); the rows are strictly */
+/* diagonally dominant, so no pivoting is needed.  cp: n doubles of scratch. */
+static void tridiag_solve(int n, const double *lo, const double *di, const double *up, double *x, double *cp)
+{
+    double den = di[0];
+    cp[0] = up[0] / den;
+    x[0] = x[0] / den;
+    for (int k = 1; k < n; k++) {
+        den = di[k] - lo[k] * cp[k - 1];
+        cp[k] = up[k] / den;
+        x[k] = (x[k] - lo[k] * x[k - 1]) / den;
+    }
+    for (int k = n - 2; k >= 0; k--) x[k] -= cp[k] * x[k + 1];
+}
+void or_tridiag_solve(int n, const double *lo, const double *di, const double *up, double *x)
+{
+    double *cp = dalloc((size_t)n);
+    tridiag_solve(n, lo, di, up, x, cp);
+    free(cp);
+}
+
+/* one AOS step on level l; returns |phi^{k+1} - phi^k| / |phi^k| */
+static double aos_step(or_ctx *c, int l, double tau_hat)
+{
+    or_level *L = &c->lev[l];
+    int n = L->n, m = L->m;
+    size_t N = (size_t)n * m;
+    double tau = tau_hat * L->h / c->p.mu;
+    double *A = dalloc(N), *B = dalloc(N), *C = dalloc(N), *D = dalloc(N), *S = dalloc(N), *f = dalloc(N);
+    double *rhs = dalloc(N), *y1 = dalloc(N), *y2 = dalloc(N);
+    int K = n > m ? n : m;
+    double *lo = dalloc((size_t)K), *di = dalloc((size_t)K), *up = dalloc((size_t)K), *x = dalloc((size_t)K),
+           *cp = dalloc((size_t)K);
+    coeffs_at(c, l, L->phi, A, B, C, D, S, f);
+    for (size_t q = 0; q < N; q++) rhs[q] = L->phi[q] - tau * (f[q] + L->F[q]);
+    for (int j = 0; j < m; j++) {          /* columns: i varies */
+        for (int i = 0; i < n; i++) {
+            size_t q = (size_t)i * m + j;
+            lo[i] = -2.0 * tau * B[q];
+            up[i] = -2.0 * tau * A[q];
+            di[i] = 1.0 + 2.0 * tau * (A[q] + B[q]);
+            x[i] = rhs[q];
+        }
+        tridiag_solve(n, lo, di, up, x, cp);
+        for (int i = 0; i < n; i++) y1[(size_t)i * m + j] = x[i];
+    }
+    for (int i = 0; i < n; i++) {          /* rows: j varies */
+        for (int j = 0; j < m; j++) {
+            size_t q = (size_t)i * m + j;
+            lo[j] = -2.0 * tau * D[q];
+            up[j] = -2.0 * tau * C[q];
+            di[j] = 1.0 + 2.0 * tau * (C[q] + D[q]);
+            x[j] = rhs[q];
+        }
+        tridiag_solve(m, lo, di, up, x, cp);
+        for (int j = 0; j < m; j++) y2[(size_t)i * m + j] = x[j];
+    }
+    double dn = 0.0, pn = 0.0;
+    for (size_t q = 0; q < N; q++) {
+        double v = clampB(0.5 * (y1[q] + y2[q]), L->lo[q], L->hi[q]);
+        dn += (v - L->phi[q]) * (v - L->phi[q]);
+        pn += L->phi[q] * L->phi[q];
+        L->phi[q] = v;
+    }
+    free(A); free(B); free(C); free(D); free(S); free(f);
+    free(rhs); free(y1); free(y2); free(lo); free(di); free(up); free(x); free(cp);
+    return pn > 0.0 ? sqrt(dn / pn) : 0.0;
+}
+
+/* one AOS step of the finest grid (F = 0), then c1, c2 refreshed */
+double or_aos_step(or_ctx *c, double tau_hat)
+{
+    or_level *L = &c->lev[0];
+    memset(L->F, 0, sizeof(double) * (size_t)L->n * L->m);
+    double eta = aos_step(c, 0, tau_hat);
+    update_c(c);
+    update_fit(c);
+    return eta;
+}
+
+/* AOS solve of the finest grid: steps until the relative change falls     */
+/* below eta_tol (the stopping rule of the comparison in Sec. 5); returns   */
+/* the number of steps (negative: not reached), the changes in hist.        */
+int or_aos(or_ctx *c, double tau_hat, double eta_tol, int max_iters, double *hist)
+{
+    int k;
+    for (k = 0; k < max_iters; k++) {
+        double eta = or_aos_step(c, tau_hat);
+        if (hist) hist[k] = eta;
+        if (eta < eta_tol) return k + 1;
+    }
+    return -k;
+}
+
+/* ------------------------------------------------------------------------ */
 /* accessors and single-step entry points for the tests                     */
 int or_levels(or_ctx *c) { return c->L; }
 void or_level_shape(or_ctx *c, int l, int *n, int *m, double *h) { *n = c->lev[l].n; *m = c->lev[l].m; *h = c->lev[l].h; }
