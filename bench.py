@@ -75,6 +75,8 @@ def calibrate_copy(mib: int = 1024):
     b.copy_(a)
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes": a.numel() * 4}))
+
+
 def copy_bandwidth(mib: int = 1024, reps: int = 5) -> float:
     """GB/s of a plain device-to-device copy of `mib` MiB (read + write counted),
     best of `reps`: the bandwidth a streaming kernel reaches on this GPU."""
@@ -356,6 +358,67 @@ def large_bench(steps: int, warmup: int, max_cycles: int, cpu_seconds: float, no
     }))
 
 
+# compulsory bytes of one AOS step per pixel: read phi (FP64), w and d (FP64), the
+# image (FP32); write phi (FP64)
+AOS_BYTES_PER_PX = 8 + 16 + 4 + 8
+
+
+def aos_bench(args, img, inst, params, stream):
+    """The AOS time stepper on the 1024x1024 image, run to the paper's relative-change
+    stop; its segmentation is compared with the multigrid solve of the same image."""
+    import torch
+
+    from paper_1807_02137_amd import mgseg
+    s = mgseg.Solver(img, inst.markers, params, stream=stream)
+    s.solve(TOL, MAX_CYCLES)
+    ref = s.get("phi64") > 0
+    s.close()
+
+    def step():
+        s = mgseg.Solver(img, inst.markers, params, stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        it, eta, rel, ok = s.aos(args.aos_tau, args.aos_eta, 5000)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        seg = s.get("phi64") > 0
+        s.close()
+        return it, eta, rel, ok, t1 - t0, seg
+
+    for _ in range(args.warmup):
+        step()
+    runs = [step() for _ in range(args.steps)]
+    wall = sum(r[4] for r in runs)
+    iters = [r[0] for r in runs]
+    seg = runs[-1][5]
+    iou = float((seg & ref).sum() / max((seg | ref).sum(), 1))
+    npts = N * N
+    ms_step = wall / max(sum(iters), 1) * 1e3
+    achieved = AOS_BYTES_PER_PX * npts / (ms_step * 1e-3) / 1e9
+    out = {
+        "metric": "time to relative change 1e-4 (AOS) + grid-pts/s per AOS step",
+        "value": npts * sum(iters) / wall,
+        "unit": "grid-pts/s per AOS step",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"1024x1024 12-ellipse image, 6 markers, {MODEL_NAMES[args.model]}, AOS "
+                               f"tau {args.aos_tau} h/mu, stop at relative change {args.aos_eta}",
+                   "seed": SEED, "parallelism": "single GPU"},
+        "aos_steps": iters, "eta": [r[1] for r in runs], "rel_res_paper": [r[2] for r in runs],
+        "converged": all(r[3] for r in runs),
+        "iou_vs_multigrid": iou,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "one whole AOS step (coefficients, column and row Thomas solves, combine, "
+                               "region means, change)",
+                     "bytes_per_px": AOS_BYTES_PER_PX, "avg_us": ms_step * 1e3},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -374,6 +437,11 @@ def main():
     ap.add_argument("--smoother", default="hs2", choices=("hs2", "gslex", "hs1"),
                     help="c2 only: Hybrid Smoother 2 (default, the paper's Algorithm 3), GSLEX-I (its "
                          "Algorithm 1 with a standard smoother) or Hybrid Smoother 1 (its Algorithm 2)")
+    ap.add_argument("--solver", default="mg", choices=("mg", "aos"),
+                    help="c2 only: the FAS multigrid (default) or the AOS time stepper the paper compares "
+                         "against (Sec. 5), run to the relative change --aos-eta")
+    ap.add_argument("--aos-tau", type=float, default=200.0, help="AOS time step in units of h/mu")
+    ap.add_argument("--aos-eta", type=float, default=1e-4, help="AOS stop: relative change of phi")
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--c5-images", type=int, default=16)
     ap.add_argument("--max-cycles", type=int, default=C4_MAX_CYCLES, help="c4 only: cycle cap of a solve")
@@ -408,6 +476,10 @@ def main():
     params = (mgseg.chan_vese_params(levels=LEVELS, smoother=smoother) if args.model == "cv"
               else mgseg.Params(levels=LEVELS, model=model, smoother=smoother))
     stream = torch.cuda.current_stream()
+
+    if args.solver == "aos":
+        aos_bench(args, img, inst, params, stream)
+        return
 
     def step(profile=False):
         s = mgseg.Solver(img, inst.markers, params, stream=stream)

@@ -197,6 +197,27 @@ mgseg_status mgseg_vcycle(mgseg_ctx *c, double *rel_res_out);
 mgseg_status mgseg_solve(mgseg_ctx *c, double tol, int max_cycles, int *cycles_out,
                          double *rel_res_out);
 
+/* AOS solver (additive operator splitting), the semi-implicit time stepper
+ * of the timing comparison in Sec. 5 (Table 4) and an "exact" solver named
+ * for the coarsest grid in Algorithm 1.  From the context's current finest
+ * phi (FP64), each step freezes the coefficients of eq. abcdrc at phi^k,
+ * solves one tridiagonal system per column (couplings A, B) and per row
+ * (C, D) for y_l = (I - 2 tau A_l)^{-1} (phi^k - tau f), sets
+ * phi^{k+1} = clamp((y_1 + y_2) / 2, -M, M), and refreshes c1, c2 (eq. c1c2).
+ * tau: the step in units of h / mu (> 0).  Stops once the paper's relative
+ * change |phi^{k+1} - phi^k| / |phi^k| falls below eta_tol (Sec. 5), or
+ * after max_iters steps.  Outputs (each may be null): steps taken, the last
+ * relative change, and the projected relative residual of the paper's rows
+ * at the result (the stopping measure of mgseg_solve).  The next mgseg_vcycle
+ * continues from the AOS result.  The first call allocates 48 bytes per
+ * pixel of device memory, held until mgseg_destroy.  Errors: MGSEG_E_ARG
+ * (null context, tau <= 0, eta_tol < 0, max_iters < 0), MGSEG_E_NOMEM,
+ * MGSEG_E_HIP, MGSEG_E_NONFINITE;
+ * MGSEG_E_NOT_CONVERGED when max_iters steps did not reach eta_tol (outputs
+ * valid). */
+mgseg_status mgseg_aos(mgseg_ctx *c, double tau, double eta_tol, int max_iters, int *iters_out,
+                       double *eta_out, double *rel_res_out);
+
 /* Finest phi in FP64 (n x m, pitch in elements). */
 mgseg_status mgseg_get_phi(mgseg_ctx *c, double *phi_dev, int pitch);
 

@@ -13,6 +13,7 @@
 
 #include "../../include/mgseg.h"
 #include "mgseg_kernels.h"
+#include "mgseg_aos.h"
 
 #define MAXLEV 16
 
@@ -75,6 +76,7 @@ struct mgseg_ctx {
     char *arena = nullptr;          // every device array of the context (dalloc)
     size_t arena_size = 0, arena_used = 0;
     float *pred = nullptr;          // network input and output of mgseg_predict_phi0 (first call)
+    double *aos = nullptr;          // six n x m FP64 planes of the AOS solver (first call)
     hipError_t err = hipSuccess;
     bool oom = false;
     // one V-cycle captured as a HIP graph (replayed on s); cap: private capture stream
@@ -796,6 +798,7 @@ void release_ctx(mgseg_ctx *c)
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     if (c->arena && c->arena_owned) (void)hipFree(c->arena);
     if (c->pred) (void)hipFree(c->pred);
+    if (c->aos) (void)hipFree(c->aos);
 }
 
 // argument checks of a setup and the kernels' LDS attributes; Lv: the grid count
@@ -1154,6 +1157,85 @@ mgseg_status mgseg_get_mask(mgseg_ctx *c, uint8_t *mask_dev, int pitch)
     hipLaunchKernelGGL(k_out_mask, grid2(c->n, c->m), dim3(256), 0, c->s, c->phi64, c->n, c->m, mask_dev, pitch);
     chk(c);
     return sync_status(c);
+}
+
+namespace {
+
+// one AOS step of the finest FP64 phi (time step tau_hat h / mu), then c1, c2
+// and the relative change of phi (DS_ETA)
+void aos_step(mgseg_ctx *c, double tau_hat)
+{
+    Level &L = c->lev[0];
+    const long long N = (long long)c->n * c->m;
+    double *uA = c->aos, *uB = uA + N, *uC = uB + N, *uD = uC + N, *r = uD + N, *y1 = r + N;
+    (void)hipMemcpyAsync(c->prev64, c->phi64, sizeof(double) * N, hipMemcpyDeviceToDevice, c->s);
+    const int nb = std::min(RED_BLOCKS, std::max(1, (int)((N + 255) / 256)));
+    if (c->p.model == 1) {
+        hipLaunchKernelGGL(k_sums<double>, dim3(nb), dim3(256), 0, c->s, c->phi64, c->m, (const float *)nullptr, 0,
+                           c->n, c->m, c->p.eps, c->part);
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FIN_NT), 0, c->s, c->part, nb, 0, (double)N, L.h * L.h, c->A1,
+                           c->p.nu, c->dsc + DS_AREA64);
+    }
+    AosArgs A;
+    A.phi64 = c->phi64; A.w64 = c->w64; A.d64 = c->d64; A.z32 = L.z; A.p32 = L.prm;
+    A.c12 = c->dsc + DS_C1; A.area = c->p.model == 1 ? c->dsc + DS_AREA64 : nullptr;
+    A.kap = c->p.mu / L.h; A.e2 = lev_e2(c, 0); A.eps = c->p.eps;
+    A.l1 = c->p.lambda1; A.l2 = c->p.lambda2; A.theta = c->p.theta; A.tau = tau_hat * L.h / c->p.mu;
+    A.model = c->p.model; A.scaled = c->p.scaled; A.n = c->n; A.m = c->m;
+    A.uA = uA; A.uB = uB; A.uC = uC; A.uD = uD; A.r = r;
+    hipLaunchKernelGGL(k_aos_coef, grid2(c->n, c->m), dim3(256), 0, c->s, A);
+    hipLaunchKernelGGL(k_aos_cols, dim3((c->m + 63) / 64), dim3(64), 0, c->s, uA, uB, r, y1, c->n, c->m);
+    hipLaunchKernelGGL(k_aos_rows, dim3((c->n + 63) / 64), dim3(64), 0, c->s, uC, uD, r, c->n, c->m);
+    hipLaunchKernelGGL(k_aos_combine, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, c->s, c->phi64, y1, uD, N,
+                       c->p.M);
+    update_c(c);
+    hipLaunchKernelGGL(k_eta, dim3(nb), dim3(256), 0, c->s, c->phi64, c->prev64, N, c->part + 4 * RED_BLOCKS);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FIN_NT), 0, c->s, c->part + 4 * RED_BLOCKS, nb, 3, 0.0, 0.0, 0.0, 0.0,
+                       c->dsc + DS_ETA);
+    chk(c);
+}
+
+}  // namespace
+
+mgseg_status mgseg_aos(mgseg_ctx *c, double tau, double eta_tol, int max_iters, int *iters_out, double *eta_out,
+                       double *rel_res_out)
+{
+    if (!c || !(tau > 0.0) || !(eta_tol >= 0.0) || max_iters < 0) return MGSEG_E_ARG;
+    if (c->noalloc) return MGSEG_E_ARG;
+    mgseg_status st = sync_status(c);
+    if (st != MGSEG_OK) return st;
+    const size_t N = (size_t)c->n * c->m;
+    if (!c->aos && hipMalloc(&c->aos, 6 * N * sizeof(double)) != hipSuccess) {
+        c->aos = nullptr;
+        (void)hipGetLastError();
+        return MGSEG_E_NOMEM;
+    }
+    int done = 0;
+    double eta = 0.0;
+    while (done < max_iters) {
+        aos_step(c, tau);
+        (void)hipMemcpyAsync(c->hres, c->dsc + DS_RES, 3 * sizeof(double), hipMemcpyDeviceToHost, c->s);
+        st = sync_status(c);
+        if (st != MGSEG_OK) return st;
+        eta = c->hres[1];
+        done++;
+        if (!std::isfinite(eta)) return MGSEG_E_NONFINITE;
+        if (eta < eta_tol) break;
+    }
+    // the paper's residual at the result, and the FP32 / deviation-form state of the multigrid
+    refresh_and_residual(c);
+    (void)hipMemcpyAsync(c->hres, c->dsc + DS_RES, 3 * sizeof(double), hipMemcpyDeviceToHost, c->s);
+    st = sync_status(c);
+    if (st != MGSEG_OK) return st;
+    c->res = c->hres[0];
+    c->res_rows = c->hres[2];
+    c->eta = eta;
+    c->rel = c->res0 > 0.0 ? c->res / c->res0 : 0.0;
+    if (iters_out) *iters_out = done;
+    if (eta_out) *eta_out = eta;
+    if (rel_res_out) *rel_res_out = c->rel;
+    if (!std::isfinite(c->res)) return MGSEG_E_NONFINITE;
+    return done > 0 && eta < eta_tol ? MGSEG_OK : MGSEG_E_NOT_CONVERGED;
 }
 
 mgseg_status mgseg_get_stats(mgseg_ctx *c, mgseg_stats *s)

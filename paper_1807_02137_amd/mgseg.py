@@ -117,6 +117,7 @@ def lib():
         L.mgseg_set_phi0.argtypes = [vp, vp, C.c_int]
         L.mgseg_vcycle.argtypes = [vp, dp]
         L.mgseg_solve.argtypes = [vp, C.c_double, C.c_int, ip, dp]
+        L.mgseg_aos.argtypes = [vp, C.c_double, C.c_double, C.c_int, ip, dp, dp]
         L.mgseg_get_phi.argtypes = [vp, vp, C.c_int]
         L.mgseg_get_mask.argtypes = [vp, vp, C.c_int]
         L.mgseg_get_stats.argtypes = [vp, C.POINTER(_Stats)]
@@ -164,7 +165,7 @@ def lib():
                      "mgseg_net_forward", "mgseg_net_backward", "mgseg_net_adam_step", "mgseg_net_param_count",
                      "mgseg_net_get_params", "mgseg_net_set_params", "mgseg_ctx_features", "mgseg_predict_phi0",
                      "mgseg_reset_phi0", "mgseg_net_profile", "mgseg_net_profile_read",
-                     "mgseg_get_state", "mgseg_set_state", "mgseg_solve_noalloc"):
+                     "mgseg_get_state", "mgseg_set_state", "mgseg_solve_noalloc", "mgseg_aos"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -251,6 +252,16 @@ class Solver:
         if code not in (0, 6) or (code == 6 and raise_on_nonconv):
             raise MgsegError(code, "mgseg_solve")
         return cyc.value, rel.value, code == 0
+
+    def aos(self, tau, eta_tol=1e-4, max_iters=200, raise_on_nonconv=False):
+        """AOS steps (time step tau in units of h/mu) from the current phi until the
+        relative change falls below eta_tol: (steps, last change, relative residual,
+        reached)."""
+        it, eta, rel = C.c_int(), C.c_double(), C.c_double()
+        code = self.L.mgseg_aos(self.ctx, tau, eta_tol, max_iters, C.byref(it), C.byref(eta), C.byref(rel))
+        if code not in (0, 6) or (code == 6 and raise_on_nonconv):
+            raise MgsegError(code, "mgseg_aos")
+        return it.value, eta.value, rel.value, code == 0
 
     def set_phi0(self, phi):
         t = torch.as_tensor(phi, dtype=torch.float32, device="cuda").contiguous()
