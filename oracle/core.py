@@ -64,7 +64,8 @@ class OracleParams:
     coarse_iters: int = 10
     coarse_rtol: float = 1e-4  # coarsest solve stops when an iteration moves nothing by more than this share
     order: int = 1            # 0 paper lexicographic lines, 1 four-class line order
-    smoother: int = 0         # 0 Hybrid Smoother 2, 1 GSLEX-I, 2 Hybrid Smoother 1
+    smoother: int = 0         # 0 Hybrid Smoother 2, 1 GSLEX-I, 2 Hybrid Smoother 1, 3 GSLINE-I, 4 NEWT-I,
+                              # 5 GSLEX-II, 6 GSLINE-II, 7 NEWT-II
     obstacle: int = 1         # 1 coarse corrections bounded by the fine slack
     scaled: int = 1           # 1 each row divided by delta_eps(psi_ij) > 0
     run_max: int = 0          # 0 maximal runs (Sec. 4.3), else runs cut into near-equal pieces of at most run_max

@@ -896,18 +896,28 @@ static void hs1_block(or_ctx *c, or_level *L, int i, int j, int lag)
         for (int a = 0; a < k; a++) L->phi[cell[a]] = x[a];
 }
 
-static void hs1_outer(or_ctx *c, int l)
+/* GSLINE-I (Sec. 3.2, Smoothers 3-4, eq. system): every column one         */
+/* tridiagonal line system with the frozen coefficients, columns left to    */
+/* right (order = 0) or in the four classes of sweep C (order = 1).          */
+static void gsline_sweep(or_ctx *c, int l)
 {
     or_level *L = &c->lev[l];
     int n = L->n, m = L->m;
     size_t *px = (size_t *)malloc(sizeof(size_t) * (size_t)(n + 1));
-    /* step I: GSLINE-I, every column one line system (the order of sweep C) */
     for (int k = 0; k < (c->p.order == 0 ? 1 : 4); k++)
         for (int j = (c->p.order == 0 ? 0 : k); j < m; j += (c->p.order == 0 ? 1 : 4)) {
             for (int i = 0; i < n; i++) px[i] = (size_t)i * m + j;
             run_update(c, L, px, n);
         }
     free(px);
+}
+
+static void hs1_outer(or_ctx *c, int l)
+{
+    or_level *L = &c->lev[l];
+    int n = L->n, m = L->m;
+    /* step I: GSLINE-I, every column one line system (the order of sweep C) */
+    gsline_sweep(c, l);
     /* step II: the blocks at the jump pixels */
     for (int cls = 0; cls < (c->p.order == 0 ? 1 : 8); cls++)
         for (int i = 0; i < n; i++)
@@ -920,13 +930,137 @@ static void hs1_outer(or_ctx *c, int l)
             }
 }
 
+/* ------------------------------------------------------------------------ */
+/* The other standard smoothers of Sec. 3.2.                                 */
+/*                                                                            */
+/* NEWT (Smoothers 5-6, eq. newtrc): a point Newton step on the pixel's own  */
+/* equation, whose only nonlinearity in phi_ij beyond the frozen stencil is  */
+/* the Rada-Chen area term Q (eq. rcabcd).  With the rows as the solver      */
+/* holds them: scaled (divided by delta_eps), the row carries Q = 2 nu       */
+/* (h^2 sum H - A1) with dQ/dphi_ij = 2 nu h^2 delta_eps(phi_ij); unscaled,  */
+/* Q = delta_eps(phi_ij) 2 nu (h^2 sum H - A1) with derivative               */
+/* 2 nu delta_eps^2 h^2 + delta_eps' 2 nu (h^2 sum H - A1).  The update is   */
+/*   phi_ij <- (P - Q + Q' phi_ij) / (S + Q'),                                */
+/* P the neighbour sum minus the fit part of f; for Spencer-Chen Q = 0 and   */
+/* NEWT is GSLEX.  NEWT-I takes Q' at the frozen state.                      */
+static double newton_qprime(const or_ctx *c, const or_level *L, double phi, double area)
+{
+    if (c->p.model != 1) return 0.0;
+    double d = deps(phi, c->p.eps);
+    double a = 2.0 * c->p.nu * L->h * L->h * d;
+    if (c->p.scaled) return a;
+    double dd = -2.0 * phi * d * d * M_PI / c->p.eps;     /* delta_eps'(phi) */
+    return a * d + dd * area;
+}
+
+static void newt_sweep(or_ctx *c, int l)
+{
+    or_level *L = &c->lev[l];
+    const int n = L->n, m = L->m;
+    double area = area_term(c, l, L->tmp);                /* at the frozen state */
+    for (int k = 0; k < (c->p.order == 0 ? 1 : 4); k++)
+        for (int i = (c->p.order == 0 ? 0 : k); i < n; i += (c->p.order == 0 ? 1 : 4))
+            for (int j = 0; j < m; j++) {
+                size_t q = (size_t)i * m + j;
+                if (L->S[q] == 0.0) continue;
+                double qp = newton_qprime(c, L, L->tmp[q], area);
+                double v = -L->f[q] - L->F[q] + qp * L->phi[q];
+                if (i < n - 1) v += L->A[q] * L->phi[q + m];
+                if (i > 0) v += L->B[q] * L->phi[q - m];
+                if (j < m - 1) v += L->C[q] * L->phi[q + 1];
+                if (j > 0) v += L->D[q] * L->phi[q - 1];
+                L->phi[q] = clampB(v / (L->S[q] + qp), L->lo[q], L->hi[q]);
+            }
+}
+
+/* The local ("-II") variants refresh a pixel's coefficients from the       */
+/* current phi right before they are used (Sec. 3.2: GSLEX-II, GSLINE-II,   */
+/* NEWT-II), the area term's sum of H included (kept current after every    */
+/* update).  coeffs_cell: A..D, S, f of eq. abcdrc at pixel q from phi.      */
+static void coeffs_cell(or_ctx *c, int l, const double *phi, size_t q, double area)
+{
+    or_level *L = &c->lev[l];
+    int n = L->n, m = L->m, i = (int)(q / m), j = (int)(q % m);
+    double G[4]; int in[4];
+    cell_faces(phi, L->w, n, m, i, j, lev_e2(c, l), G, in);
+    double kap = c->p.mu / L->h;
+    double dl = c->p.scaled ? 1.0 : deps(phi[q], c->p.eps);
+    L->A[q] = kap * dl * G[0]; L->B[q] = kap * dl * G[1];
+    L->C[q] = kap * dl * G[2]; L->D[q] = kap * dl * G[3];
+    L->S[q] = L->A[q] + L->B[q] + L->C[q] + L->D[q];
+    L->f[q] = dl * (L->fit[q] + area);
+}
+
+static double area_delta(const or_ctx *c, const or_level *L, double before, double after)
+{
+    if (c->p.model != 1) return 0.0;
+    return 2.0 * c->p.nu * L->h * L->h * (Heps(after, c->p.eps) - Heps(before, c->p.eps));
+}
+
+/* GSLEX-II (newton = 0) and NEWT-II (newton = 1): lexicographic point      */
+/* updates, each with its pixel's coefficients (and Q') at the current phi. */
+static void point_local_sweep(or_ctx *c, int l, int newton)
+{
+    or_level *L = &c->lev[l];
+    const int n = L->n, m = L->m;
+    double area = area_term(c, l, L->phi);
+    for (int k = 0; k < (c->p.order == 0 ? 1 : 4); k++)
+        for (int i = (c->p.order == 0 ? 0 : k); i < n; i += (c->p.order == 0 ? 1 : 4))
+            for (int j = 0; j < m; j++) {
+                size_t q = (size_t)i * m + j;
+                coeffs_cell(c, l, L->phi, q, area);
+                if (L->S[q] == 0.0) continue;
+                double qp = newton ? newton_qprime(c, L, L->phi[q], area) : 0.0;
+                double old = L->phi[q];
+                double v = -L->f[q] - L->F[q] + qp * old;
+                if (i < n - 1) v += L->A[q] * L->phi[q + m];
+                if (i > 0) v += L->B[q] * L->phi[q - m];
+                if (j < m - 1) v += L->C[q] * L->phi[q + 1];
+                if (j > 0) v += L->D[q] * L->phi[q - 1];
+                L->phi[q] = clampB(v / (L->S[q] + qp), L->lo[q], L->hi[q]);
+                area += area_delta(c, L, old, L->phi[q]);
+            }
+}
+
+/* GSLINE-II: column line solves, each with its column's coefficients at   */
+/* the current phi.                                                          */
+static void gsline_local_sweep(or_ctx *c, int l)
+{
+    or_level *L = &c->lev[l];
+    int n = L->n, m = L->m;
+    size_t *px = (size_t *)malloc(sizeof(size_t) * (size_t)(n + 1));
+    double *old = dalloc((size_t)n);
+    double area = area_term(c, l, L->phi);
+    for (int k = 0; k < (c->p.order == 0 ? 1 : 4); k++)
+        for (int j = (c->p.order == 0 ? 0 : k); j < m; j += (c->p.order == 0 ? 1 : 4)) {
+            for (int i = 0; i < n; i++) {
+                px[i] = (size_t)i * m + j;
+                coeffs_cell(c, l, L->phi, px[i], area);
+                old[i] = L->phi[px[i]];
+            }
+            run_update(c, L, px, n);
+            for (int i = 0; i < n; i++) area += area_delta(c, L, old[i], L->phi[px[i]]);
+        }
+    free(px); free(old);
+}
+
+/* smoother: 0 Hybrid Smoother 2, 1 GSLEX-I, 2 Hybrid Smoother 1, 3 GSLINE-I, */
+/* 4 NEWT-I, 5 GSLEX-II, 6 GSLINE-II, 7 NEWT-II                              */
 static void smooth(or_ctx *c, int l, int iters)
 {
     for (int it = 0; it < iters; it++) {
         freeze(c, l);
-        if (c->p.smoother == 1) { gslex_sweep(c, l); continue; }
-        if (c->p.smoother == 2) { hs1_outer(c, l); continue; }
-        for (int s = 0; s < 4; s++) hs2_sweep(c, l, s);
+        switch (c->p.smoother) {
+        case 1: gslex_sweep(c, l); break;
+        case 2: hs1_outer(c, l); break;
+        case 3: gsline_sweep(c, l); break;
+        case 4: newt_sweep(c, l); break;
+        case 5: point_local_sweep(c, l, 0); break;
+        case 6: gsline_local_sweep(c, l); break;
+        case 7: point_local_sweep(c, l, 1); break;
+        default:
+            for (int s = 0; s < 4; s++) hs2_sweep(c, l, s);
+        }
     }
 }
 
@@ -1410,7 +1544,21 @@ void or_set_labels(or_ctx *c, int l, const uint8_t *in) { memcpy(c->lev[l].lab, 
 
 /* single steps on level l */
 void or_step_freeze(or_ctx *c, int l) { freeze(c, l); }
-void or_step_sweep(or_ctx *c, int l, int s) { if (s < 4) hs2_sweep(c, l, s); else if (s == 4) gslex_sweep(c, l); else hs1_outer(c, l); }
+/* s: 0-3 the sweeps of Hybrid Smoother 2, 4 GSLEX-I, 5 Hybrid Smoother 1, 6 GSLINE-I, 7 NEWT-I, */
+/* 8 GSLEX-II, 9 GSLINE-II, 10 NEWT-II (after a freeze)                                         */
+void or_step_sweep(or_ctx *c, int l, int s)
+{
+    switch (s) {
+    case 4: gslex_sweep(c, l); break;
+    case 5: hs1_outer(c, l); break;
+    case 6: gsline_sweep(c, l); break;
+    case 7: newt_sweep(c, l); break;
+    case 8: point_local_sweep(c, l, 0); break;
+    case 9: gsline_local_sweep(c, l); break;
+    case 10: point_local_sweep(c, l, 1); break;
+    default: hs2_sweep(c, l, s);
+    }
+}
 void or_step_smooth(or_ctx *c, int l, int iters) { smooth(c, l, iters); }
 void or_step_coarsest(or_ctx *c, int l) { coarsest(c, l); }
 void or_step_vcycle_level(or_ctx *c, int l) { vcycle_level(c, l); }
