@@ -86,7 +86,14 @@ typedef struct {
                             /* the collective update at every jump-set cell of the   */
                             /* cell and its neighbours except the one behind its     */
                             /* smallest coefficient (eight cell classes); needs      */
-                            /* mixed_precision = 1; default 0                        */
+                            /* mixed_precision = 1; 3: GSLINE-I (Sec. 3.2, eq.       */
+                            /* system), one line system per column per outer         */
+                            /* iteration (four column classes; needs                 */
+                            /* mixed_precision = 1); 4: NEWT-I (Sec. 3.2, eq.        */
+                            /* newtrc), GSLEX-I's pass with the derivative of the    */
+                            /* Rada-Chen area term on each diagonal (Spencer-Chen:   */
+                            /* the same as 1).  The local -II variants are not       */
+                            /* offered (MGSEG_E_ARG); default 0                      */
     int32_t run_max;        /* superpixels of Hybrid Smoother 2 (Sec. 4.3, Fig. 3):  */
                             /* 0 (default) solves every maximal run of starred cells */
                             /* on a line as one unit, as the paper does (lines       */

@@ -287,7 +287,7 @@ void res64(mgseg_ctx *c)
 // bit: the label bit of the starred cells (default: the sweep's own; a bit no
 // label carries makes every cell a point)
 void launch_sweep(mgseg_ctx *c, int l, int s, const float *phi_old, float *phi_new, float *tout = nullptr,
-                  int tpitch = 0, int bit = -1)
+                  int tpitch = 0, int bit = -1, const float *qd = nullptr)
 {
     Level &L = c->lev[l];
     bool cm = s >= 2;
@@ -305,6 +305,7 @@ void launch_sweep(mgseg_ctx *c, int l, int s, const float *phi_old, float *phi_n
     // deviation form: the freeze stored the scaled face coefficients (and the fit term is in T)
     const bool cfm = devm(c) && L.cf != nullptr;
     A.cf = cfm ? (cm ? L.cf_cm : L.cf) : nullptr;
+    A.qd = qd;
     A.pitch = cm ? L.pcm : L.prm;
     A.lpitch = A.pitch;
     A.nl = cm ? L.m : L.n;
@@ -475,19 +476,44 @@ void outer(mgseg_ctx *c, int l)
 {
     Level &L = c->lev[l];
     freeze(c, l);
-    if (c->p.smoother == 1) {
-        // GSLEX-I: one pass of point updates in the order of sweep A (no cell starred)
-        launch_sweep(c, l, 0, L.P[0], L.P[1], nullptr, 0, LAB_NONE);
+    if (c->p.smoother == 1 || c->p.smoother == 4) {
+        // GSLEX-I: one pass of point updates in the order of sweep A (no cell starred).
+        // NEWT-I (eq. newtrc) is the same pass with the derivative Q' of the Rada-Chen
+        // area term added to every diagonal (Spencer-Chen: Q = 0, and NEWT is GSLEX)
+        const float *qd = nullptr;
+        if (c->p.smoother == 4 && c->p.model == 1) {
+            const double h2nu2 = 2.0 * c->p.nu * L.h * L.h;
+            if (devm(c)) {
+                if (l == 0)
+                    hipLaunchKernelGGL(k_newton_diag<double>, grid2(L.n, L.m), dim3(256), 0, c->s, c->phi64, c->m,
+                                       L.P[0], L.prm, L.n, L.m, h2nu2, c->p.eps, c->p.scaled,
+                                       c->dsc + DS_AREA_FRZ, L.r);
+                else
+                    hipLaunchKernelGGL(k_newton_diag<float>, grid2(L.n, L.m), dim3(256), 0, c->s, L.phic, L.prm,
+                                       L.P[0], L.prm, L.n, L.m, h2nu2, c->p.eps, c->p.scaled,
+                                       c->dsc + DS_AREA_FRZ, L.r);
+            } else {
+                hipLaunchKernelGGL(k_newton_diag<float>, grid2(L.n, L.m), dim3(256), 0, c->s, (const float *)nullptr,
+                                   0, L.psi, L.prm, L.n, L.m, h2nu2, c->p.eps, c->p.scaled, c->dsc + DS_AREA_FRZ,
+                                   L.r);
+            }
+            qd = L.r;       // the residual plane is free while the level smooths
+        }
+        launch_sweep(c, l, 0, L.P[0], L.P[1], nullptr, 0, LAB_NONE, qd);
         (void)hipMemcpyAsync(L.P[0], L.P[1], sizeof(float) * (size_t)L.n * L.prm, hipMemcpyDeviceToDevice, c->s);
         chk(c);
         return;
     }
-    if (c->p.smoother == 2) {
-        // Hybrid Smoother 1 (Algorithm 2): GSLINE-I on every column (sweep C's order and
-        // layout, every cell starred, the result written row-major), then the blocks at
-        // the jump-set cells in eight classes
+    if (c->p.smoother == 2 || c->p.smoother == 3) {
+        // GSLINE-I (eq. system): every column one line system, in sweep C's order and
+        // layout, every cell starred, the result written row-major.  Hybrid Smoother 1
+        // (Algorithm 2) follows it with the blocks at the jump-set cells in eight classes.
         transpose_f(c, L.P[0], L.prm, L.T[1], L.pcm, L.n, L.m);
         launch_sweep(c, l, 2, L.T[1], nullptr, L.P[0], L.prm, LAB_ALL);
+        if (c->p.smoother == 3) {
+            chk(c);
+            return;
+        }
         BlockArgs B;
         B.e = L.P[0]; B.cf = L.cf; B.T = L.F; B.lo = L.lo; B.hi = L.hi; B.lab = L.lab; B.skip = c->sweep_skip;
         B.p = L.prm; B.n = L.n; B.m = L.m;
@@ -534,7 +560,7 @@ bool lds_level(mgseg_ctx *c, int l)
 void smooth(mgseg_ctx *c, int l, int iters)
 {
     // grids of at most 8 bands each way: all outer iterations in one workgroup, one band per wave
-    if (iters > 0 && lds_level(c, l) && c->lev[l].n <= 32 && c->lev[l].m <= 32 && c->p.smoother != 2) {
+    if (iters > 0 && lds_level(c, l) && c->lev[l].n <= 32 && c->lev[l].m <= 32 && c->p.smoother <= 1) {
         hipLaunchKernelGGL((k_coarse_smooth<512>), dim3(1), dim3(512), coarse_lds_bytes(c->lev[l].n, c->lev[l].m),
                            c->s, coarse_args(c, l, iters, 0.0));
         chk(c);
@@ -551,7 +577,7 @@ void coarsest(mgseg_ctx *c, int l)
     // smooth error a coarse grid corrects) vanishes there: it returns the state it
     // received, a zero coarse correction
     if (L.n * L.m == 1) return;
-    if (lds_level(c, l) && c->p.smoother != 2) {
+    if (lds_level(c, l) && c->p.smoother <= 1) {
         // one wave for a grid of one band, else one band per wave of 512 threads
         const CoarseArgs C = coarse_args(c, l, c->p.coarse_iters, c->p.coarse_rtol);
         if (L.n <= 4 && L.m <= 4)
@@ -809,7 +835,7 @@ mgseg_status setup_check(const float *image_dev, int n, int m, int pitch, const 
     if (p->struct_size != sizeof(mgseg_params)) return MGSEG_E_ARG;
     if (p->model == MGSEG_RADA_CHEN && k < 3) return MGSEG_E_ARG;   // the marker polygon needs an area (A1 > 0)
     if (p->nu1 < 0 || p->nu2 < 0 || p->coarse_iters < 0 || !(p->coarse_rtol >= 0.0) || !(p->M > 0.0) || !(p->eps > 0.0) || p->levels < 0 ||
-        p->levels > MAXLEV || p->smoother < 0 || p->smoother > 2 || (p->smoother == 2 && !p->mixed_precision) ||
+        p->levels > MAXLEV || p->smoother < 0 || p->smoother > 4 || ((p->smoother == 2 || p->smoother == 3) && !p->mixed_precision) ||
         p->run_max < 0 ||
         !(p->sigma_g >= 0.0 && p->sigma_g <= 16.0))
         return MGSEG_E_ARG;

@@ -109,6 +109,7 @@ struct LineArgs {
     int tpitch;                         //   cell q of line r at tout[q * tpitch + r]
     const double *area;                 // Rada-Chen area term (null: 0)
     const float4 *cf;                   // frozen scaled face coefficients (sweeps with CF; fit null)
+    const float *qd;                    // NEWT: the Newton term Q' added to each cell's diagonal (null: none)
     int pitch, lpitch, nl, ml;
     float kap, e2, M, eps;
     int bit, scaled;
@@ -751,7 +752,7 @@ __device__ __forceinline__ Elim block_scan_elim(Elim mine, Elim *etot, int t)
 struct CellIn {
     float p0, pp, pm, p0p, p0m, ppp, ppm, pmp, pmm;   // psi at (r,q), (r+1,q), (r-1,q), (r,q+), (r,q-), (r+1,q+), (r+1,q-), (r-1,q+), (r-1,q-)
     float w00, wp, wm, w0p, w0m;                      // w at (r,q), (r+1,q), (r-1,q), (r,q+), (r,q-)
-    float fit, F, vu, vd, sig, pold, lo, hi;
+    float fit, F, vu, vd, sig, pold, lo, hi, qd;
     float4 g;                                         // stored coefficients (CF): to r+1, r-1, q+1, q-1
     unsigned lab;
 };
@@ -762,6 +763,7 @@ struct CellIn {
 struct LineRows {
     const float *ps0, *psm, *psp, *w0, *wm, *wp, *old, *fit, *F, *lo, *hi, *vu, *vd;
     const float4 *cf;
+    const float *qd;
     const uint8_t *lab;
     float M;
 };
@@ -783,6 +785,7 @@ __device__ __forceinline__ LineRows line_rows(const LineArgs &A, int r, bool up_
     R.vu = ru >= 0 && ru < nl && !up_fresh ? A.phi_old + (long long)ru * P : nullptr;
     R.vd = rd >= 0 && rd < nl && !dn_fresh ? A.phi_old + (long long)rd * P : nullptr;
     R.cf = A.cf ? A.cf + ro : nullptr;
+    R.qd = A.qd ? A.qd + ro : nullptr;
     R.lab = A.lab + (long long)r * A.lpitch;
     R.M = A.M;
     return R;
@@ -811,6 +814,7 @@ __device__ __forceinline__ void cell_load(const LineRows &R, int ml, int p, Cell
     c.lo = R.lo ? R.lo[q] : -R.M;
     c.hi = R.lo ? R.hi[q] : R.M;
     c.pold = R.old[q];
+    c.qd = R.qd ? R.qd[q] : 0.0f;
 }
 
 // The frozen coefficients of cell (r, q) (eq. abcdrc) as the row
@@ -853,10 +857,12 @@ __device__ __forceinline__ CellRow cell_row(const LineArgs &A, const CellIn &c, 
 {
     float xp, xm, lp, lm, f;
     cell_coef<CF>(A, c, r, q, area, xp, xm, lp, lm, f);
-    const float S = xp + xm + lp + lm;
+    // NEWT (eq. newtrc): the Newton term Q' joins the diagonal, and Q' times the old value the
+    // right-hand side (zero for the other smoothers)
+    const float S = xp + xm + lp + lm + c.qd;
     const float Xu = REV ? xp : xm, Xd = REV ? xm : xp;
     const float Lp = REV ? lp : lm, Ls = REV ? lm : lp;
-    const float rhs = f + c.F - Xu * vu - Xd * vd;
+    const float rhs = f + c.F - Xu * vu - Xd * vd - c.qd * c.pold;
     CellRow w;
     w.ok = S > 0.0f;
     const float inv = w.ok ? __builtin_amdgcn_rcpf(S) : 0.0f;

@@ -993,6 +993,23 @@ __global__ void __launch_bounds__(256) k_coarse_delta(const float *x, const floa
 // Cells of class (i + 3 j) mod 8 = cls only: two of them are at least four
 // cells apart, so the blocks of one launch share no cell and read none that
 // another writes.
+// NEWT (eq. newtrc): the derivative Q' in phi_ij of the Rada-Chen area term at the
+// frozen state psi = b + e (b null: psi = e): rows scaled by delta_eps, the row's
+// area term 2 nu (h^2 sum H - A1) gives Q' = 2 nu h^2 delta_eps(psi); unscaled rows
+// carry delta_eps(psi) times it, Q' = 2 nu h^2 delta_eps^2 + delta_eps'(psi) area.
+template <typename BT>
+__global__ void k_newton_diag(const BT *b, int pb, const float *e, int p, int n, int m, double h2nu2, double eps,
+                              int scaled, const double *area, float *qd)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x, i = blockIdx.y;
+    if (j >= m || i >= n) return;
+    const double psi = (b ? (double)b[(long long)i * pb + j] : 0.0) + (double)e[(long long)i * p + j];
+    const double d = mg_delta64(psi, eps);
+    double v = h2nu2 * d;
+    if (!scaled) v = v * d - 2.0 * psi * d * d * MG_PI / eps * (*area);
+    qd[(long long)i * p + j] = (float)v;
+}
+
 struct BlockArgs {
     float *e;                    // row-major state (pitch p)
     const float4 *cf;            // frozen scaled face coefficients: to i+1, i-1, j+1, j-1
@@ -1151,6 +1168,7 @@ __global__ void __launch_bounds__(NT) k_coarse_smooth(CoarseArgs G)
     LineArgs C, R, T;
     C.psi = psi; C.w = w; C.fit = dev ? nullptr : fit; C.F = F; C.lab = lab; C.lo = lo; C.hi = hi;
     C.skip = nullptr; C.tout = nullptr; C.tpitch = 0; C.area = G.area; C.pitch = m; C.lpitch = m; C.cf = nullptr;
+    C.qd = nullptr;
     C.nl = n; C.ml = m; C.kap = G.kap; C.e2 = G.e2; C.M = G.M; C.eps = (float)G.eps; C.scaled = G.scaled;
     C.run_max = G.run_max;
     C.phi_old = P0; C.phi_new = nullptr; C.bit = 0;

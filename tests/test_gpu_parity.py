@@ -386,6 +386,30 @@ def test_solve_parity_hybrid1(seed):
     s.close()
 
 
+@pytest.mark.parametrize("smoother,model", [(3, 0), (3, 1), (4, 1), (4, 0)])
+def test_solve_parity_standard_smoothers(smoother, model):
+    """Algorithm 1 with GSLINE-I (3: one line system per column) and NEWT-I (4: the
+    point Newton step of eq. newtrc) against the oracle's same smoother, both
+    models: the cycle histories and the final segmentation."""
+    say("case smoother", smoother, "model", model)
+    inst, s, o = make(1001, smoother=smoother, model=model)
+    hg = []
+    for _ in range(60):
+        hg.append(s.vcycle())
+        if hg[-1] <= 1e-6:
+            break
+    k, hist = o.solve(1e-6, 60)
+    pg, po = s.phi().cpu().numpy(), o.get("phi")
+    agree = (pg > 0) == (po > 0)
+    flips = int((~agree).sum())
+    dmax = float(np.abs(pg - po)[agree].max())
+    say(f"gpu {len(hg)} cycles {np.round(hg[:8], 4)}; oracle {k} cycles {np.round(hist[:8], 4)}; "
+        f"flips {flips} max|dphi| {dmax:.3e}")
+    assert hg[-1] <= 1e-6 and k > 0 and abs(len(hg) - k) <= 1
+    assert flips <= 1 and dmax <= 1e-4
+    s.close()
+
+
 def plant_long_runs(lab, sweep, lengths, seed=0):
     """Sets the sweep's starred bit on runs of the given lengths along every
     line (visit order), separated by at least one unstarred cell: the first
