@@ -511,6 +511,7 @@ def main():
     prof_bytes = SWEEP_BYTES_PER_PX * npts
     achieved = prof_bytes / (avg_ms * 1e-3) / 1e9 if prof_n else 0.0
     copy = copy_bandwidth()
+    rates = smoothing_rate_table(img, inst, params, stream) if args.model != "cv" else None
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -550,8 +551,30 @@ def main():
                      "launches": prof_n, "avg_us": avg_ms * 1e3, "bytes_per_launch": prof_bytes,
                      "bytes_per_px": SWEEP_BYTES_PER_PX, "design_bytes_per_launch": design_bytes},
         "cpu_baseline": cpu,
+        "smoothing_rates": rates,
     }
     print(json.dumps(out))
+
+
+def smoothing_rate_table(img, inst, params, stream):
+    """Table 1's measurement on this image: the local Fourier analysis of each
+    smoother over every pixel at the solved phi (mu~_max, mu~_avg, and the same
+    over the jump set), with the analysis kernel's time."""
+    import torch
+
+    from paper_1807_02137_amd import mgseg
+    s = mgseg.Solver(img, inst.markers, params, stream=stream)
+    s.solve(TOL, MAX_CYCLES)
+    out = {}
+    for name, k in (("GSLEX-I", 1), ("GSLINE-I", 3), ("NEWT-I", 4), ("Hybrid Smoother 2", 0)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        agg, _ = s.smoothing_rates(k)
+        torch.cuda.synchronize()
+        agg["ms"] = (time.perf_counter() - t0) * 1e3
+        out[name] = agg
+    s.close()
+    return out
 
 
 if __name__ == "__main__":

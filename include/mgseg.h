@@ -225,6 +225,23 @@ mgseg_status mgseg_solve(mgseg_ctx *c, double tol, int max_cycles, int *cycles_o
 mgseg_status mgseg_aos(mgseg_ctx *c, double tau, double eta_tol, int max_iters, int *iters_out,
                        double *eta_out, double *rel_res_out);
 
+/* Local Fourier analysis of a smoother over the whole finest grid (Sec. 3.3,
+ * Table 1): the coefficients of eq. abcdrc are frozen at the current finest
+ * phi, and each pixel's smoothing rate is the largest amplification of the
+ * frozen-coefficient smoother over the high frequencies
+ * (a = 2 pi t / 128, t = -64 .. 64, max(|a1|, |a2|) > pi / 2).
+ * smoother: 1 GSLEX-I (couplings B, D new), 3 GSLINE-I (column lines:
+ * A, B, D new), 4 NEWT-I (GSLEX with the Rada-Chen Newton term on the
+ * diagonal), 0 Hybrid Smoother 2 (at a jump-set pixel the sweep that lags
+ * its smallest coupling, elsewhere GSLEX).  out5 (host): mu~_max and mu~_avg
+ * over all pixels, the same two over the jump set, and the jump-set share.
+ * mu_dev (optional, device, pitch mu_pitch >= m): each pixel's rate.  Needs
+ * mixed_precision = 1 (MGSEG_E_STATE otherwise).  The first call allocates
+ * 5 doubles per 256 pixels of device memory, held until mgseg_destroy.
+ * Errors: MGSEG_E_ARG (null context or out5, another smoother, a short
+ * pitch), MGSEG_E_STATE, MGSEG_E_NOMEM, MGSEG_E_HIP. */
+mgseg_status mgseg_smoothing_rates(mgseg_ctx *c, int smoother, double *out5, float *mu_dev, int mu_pitch);
+
 /* Finest phi in FP64 (n x m, pitch in elements). */
 mgseg_status mgseg_get_phi(mgseg_ctx *c, double *phi_dev, int pitch);
 

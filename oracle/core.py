@@ -107,6 +107,8 @@ def _load():
         _lib.or_aos_step.argtypes = [C.c_void_p, C.c_double]
         _lib.or_aos.restype = C.c_int
         _lib.or_aos.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_int, dp]
+        _lib.or_newton_qprime.restype = None
+        _lib.or_newton_qprime.argtypes = [C.c_void_p, C.c_int, dp]
         _lib.or_tridiag_solve.restype = None
         _lib.or_tridiag_solve.argtypes = [C.c_int, dp, dp, dp, dp]
         _lib.or_levels.restype = C.c_int
@@ -362,6 +364,13 @@ class Oracle:
         n, m, _ = self.shape(l)
         out = np.zeros((n, m))
         self.lib.or_step_operator(self.ctx, l, _dp(out))
+        return out
+
+    def newton_qprime(self, l=0) -> np.ndarray:
+        """NEWT's diagonal term Q' of every cell at the current phi (Sec. 3.2, eq. newtrc)."""
+        n, m, _ = self.shape(l)
+        out = np.zeros((n, m))
+        self.lib.or_newton_qprime(self.ctx, l, _dp(out))
         return out
 
     def update_c(self):

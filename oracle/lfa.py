@@ -41,10 +41,11 @@ def freq_grid(n: int = 128, strict: bool = True):
     return a1, a2, hf
 
 
-def symbol(coef, new, a1, a2):
-    """Amplification of each Fourier mode for frozen ``coef`` = (A, B, C, D)."""
+def symbol(coef, new, a1, a2, q=0.0):
+    """Amplification of each Fourier mode for frozen ``coef`` = (A, B, C, D);
+    q: a term added to the diagonal (NEWT's derivative of the area term)."""
     A, B, C, D = (float(c) for c in coef)
-    S = A + B + C + D
+    S = A + B + C + D + float(q)
     E = {"A": np.exp(1j * a1), "B": np.exp(-1j * a1), "C": np.exp(1j * a2), "D": np.exp(-1j * a2)}
     cf = {"A": A, "B": B, "C": C, "D": D}
     num = sum(cf[k] * E[k] for k in COUPLINGS if k not in new)
@@ -53,10 +54,10 @@ def symbol(coef, new, a1, a2):
     return num / np.abs(den)
 
 
-def rate(coef, new, n: int = 128, strict: bool = True) -> float:
+def rate(coef, new, n: int = 128, strict: bool = True, q: float = 0.0) -> float:
     """Smoothing rate mu-hat: maximum of the symbol over high frequencies."""
     a1, a2, hf = freq_grid(n, strict)
-    return float(symbol(coef, set(new), a1, a2)[hf].max())
+    return float(symbol(coef, set(new), a1, a2, q)[hf].max())
 
 
 def rate_gslex(coef, n=128, strict=True):

@@ -1560,6 +1560,13 @@ void or_step_sweep(or_ctx *c, int l, int s)
     }
 }
 void or_step_smooth(or_ctx *c, int l, int iters) { smooth(c, l, iters); }
+/* NEWT's diagonal term Q' of every cell of level l at its current phi */
+void or_newton_qprime(or_ctx *c, int l, double *out)
+{
+    or_level *L = &c->lev[l];
+    double area = area_term(c, l, L->phi);
+    for (size_t q = 0; q < (size_t)L->n * L->m; q++) out[q] = newton_qprime(c, L, L->phi[q], area);
+}
 void or_step_coarsest(or_ctx *c, int l) { coarsest(c, l); }
 void or_step_vcycle_level(or_ctx *c, int l) { vcycle_level(c, l); }
 void or_step_to_coarse(or_ctx *c, int l) { if (l + 1 < c->L) to_coarse(c, l); }

@@ -14,6 +14,7 @@
 #include "../../include/mgseg.h"
 #include "mgseg_kernels.h"
 #include "mgseg_aos.h"
+#include "mgseg_lfa.h"
 
 #define MAXLEV 16
 
@@ -77,6 +78,7 @@ struct mgseg_ctx {
     size_t arena_size = 0, arena_used = 0;
     float *pred = nullptr;          // network input and output of mgseg_predict_phi0 (first call)
     double *aos = nullptr;          // six n x m FP64 planes of the AOS solver (first call)
+    double *lfa = nullptr;          // partials of mgseg_smoothing_rates (first call)
     hipError_t err = hipSuccess;
     bool oom = false;
     // one V-cycle captured as a HIP graph (replayed on s); cap: private capture stream
@@ -825,6 +827,7 @@ void release_ctx(mgseg_ctx *c)
     if (c->arena && c->arena_owned) (void)hipFree(c->arena);
     if (c->pred) (void)hipFree(c->pred);
     if (c->aos) (void)hipFree(c->aos);
+    if (c->lfa) (void)hipFree(c->lfa);
 }
 
 // argument checks of a setup and the kernels' LDS attributes; Lv: the grid count
@@ -1262,6 +1265,53 @@ mgseg_status mgseg_aos(mgseg_ctx *c, double tau, double eta_tol, int max_iters, 
     if (rel_res_out) *rel_res_out = c->rel;
     if (!std::isfinite(c->res)) return MGSEG_E_NONFINITE;
     return done > 0 && eta < eta_tol ? MGSEG_OK : MGSEG_E_NOT_CONVERGED;
+}
+
+mgseg_status mgseg_smoothing_rates(mgseg_ctx *c, int smoother, double *out5, float *mu_dev, int mu_pitch)
+{
+    if (!c || !out5 || (smoother != 0 && smoother != 1 && smoother != 3 && smoother != 4)) return MGSEG_E_ARG;
+    if (mu_dev && mu_pitch < c->m) return MGSEG_E_ARG;
+    if (c->noalloc) return MGSEG_E_ARG;
+    Level &L0 = c->lev[0];
+    if (!devm(c) || !L0.cf) return MGSEG_E_STATE;
+    mgseg_status st = sync_status(c);
+    if (st != MGSEG_OK) return st;
+    const long long N = (long long)c->n * c->m;
+    const int nb = (int)((N + LFA_NB - 1) / LFA_NB);
+    if (!c->lfa && hipMalloc(&c->lfa, (5 * (size_t)nb + 5) * sizeof(double)) != hipSuccess) {
+        c->lfa = nullptr;
+        (void)hipGetLastError();
+        return MGSEG_E_NOMEM;
+    }
+    // the frozen couplings at the current finest phi (the deviation restarted from it)
+    const dim3 gt((c->m + TILE - 1) / TILE, (c->n + TILE - 1) / TILE);
+    const dim3 tb(TILE, tile_rows((long long)gt.x * gt.y));
+    hipLaunchKernelGGL(k_start0, gt, tb, 0, c->s, c->phi64, c->n, c->m, c->p.M, L0.P[0], L0.lo, L0.hi, L0.prm,
+                       L0.lo_cm, L0.hi_cm, L0.pcm);
+    freeze(c, 0);
+    const float *qd = nullptr;
+    if (smoother == 4 && c->p.model == 1) {
+        hipLaunchKernelGGL(k_newton_diag<double>, grid2(L0.n, L0.m), dim3(256), 0, c->s, c->phi64, c->m, L0.P[0],
+                           L0.prm, L0.n, L0.m, 2.0 * c->p.nu * L0.h * L0.h, c->p.eps, c->p.scaled,
+                           c->dsc + DS_AREA_FRZ, L0.r);
+        qd = L0.r;
+    }
+    LfaArgs A;
+    A.cf = L0.cf; A.qd = qd; A.lab = L0.lab; A.p = L0.prm; A.n = c->n; A.m = c->m;
+    A.mode = smoother == 0 ? 2 : (smoother == 3 ? 1 : 0);
+    A.mu = mu_dev; A.mp = mu_pitch; A.partial = c->lfa;
+    hipLaunchKernelGGL(k_lfa_rates, dim3(nb), dim3(LFA_NB), 0, c->s, A);
+    hipLaunchKernelGGL(k_lfa_final, dim3(1), dim3(64), 0, c->s, c->lfa, nb, c->lfa + 5 * (size_t)nb);
+    double r[5];
+    (void)hipMemcpyAsync(r, c->lfa + 5 * (size_t)nb, sizeof(r), hipMemcpyDeviceToHost, c->s);
+    st = sync_status(c);
+    if (st != MGSEG_OK) return st;
+    out5[0] = r[0];
+    out5[1] = r[1] / (double)N;
+    out5[2] = r[2];
+    out5[3] = r[4] > 0.0 ? r[3] / r[4] : 0.0;
+    out5[4] = r[4] / (double)N;
+    return MGSEG_OK;
 }
 
 mgseg_status mgseg_get_stats(mgseg_ctx *c, mgseg_stats *s)

@@ -118,6 +118,7 @@ def lib():
         L.mgseg_vcycle.argtypes = [vp, dp]
         L.mgseg_solve.argtypes = [vp, C.c_double, C.c_int, ip, dp]
         L.mgseg_aos.argtypes = [vp, C.c_double, C.c_double, C.c_int, ip, dp, dp]
+        L.mgseg_smoothing_rates.argtypes = [vp, C.c_int, dp, vp, C.c_int]
         L.mgseg_get_phi.argtypes = [vp, vp, C.c_int]
         L.mgseg_get_mask.argtypes = [vp, vp, C.c_int]
         L.mgseg_get_stats.argtypes = [vp, C.POINTER(_Stats)]
@@ -165,7 +166,8 @@ def lib():
                      "mgseg_net_forward", "mgseg_net_backward", "mgseg_net_adam_step", "mgseg_net_param_count",
                      "mgseg_net_get_params", "mgseg_net_set_params", "mgseg_ctx_features", "mgseg_predict_phi0",
                      "mgseg_reset_phi0", "mgseg_net_profile", "mgseg_net_profile_read",
-                     "mgseg_get_state", "mgseg_set_state", "mgseg_solve_noalloc", "mgseg_aos"):
+                     "mgseg_get_state", "mgseg_set_state", "mgseg_solve_noalloc", "mgseg_aos",
+                     "mgseg_smoothing_rates"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -262,6 +264,17 @@ class Solver:
         if code not in (0, 6) or (code == 6 and raise_on_nonconv):
             raise MgsegError(code, "mgseg_aos")
         return it.value, eta.value, rel.value, code == 0
+
+    def smoothing_rates(self, smoother, per_pixel=False):
+        """Local Fourier analysis of a smoother at the current phi: (dict of mu~_max,
+        mu~_avg, their values over the jump set and its share, per-pixel rates or None)."""
+        out = (C.c_double * 5)()
+        mu = torch.empty((self.n, self.m), dtype=torch.float32, device="cuda") if per_pixel else None
+        _check(self.L.mgseg_smoothing_rates(self.ctx, smoother, out,
+                                            C.c_void_p(mu.data_ptr()) if mu is not None else None, self.m),
+               "mgseg_smoothing_rates")
+        keys = ("mu_max", "mu_avg", "mu_max_D", "mu_avg_D", "share_D")
+        return dict(zip(keys, list(out))), (mu.cpu().numpy() if mu is not None else None)
 
     def set_phi0(self, phi):
         t = torch.as_tensor(phi, dtype=torch.float32, device="cuda").contiguous()
