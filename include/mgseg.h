@@ -92,8 +92,13 @@ typedef struct {
                             /* mixed_precision = 1); 4: NEWT-I (Sec. 3.2, eq.        */
                             /* newtrc), GSLEX-I's pass with the derivative of the    */
                             /* Rada-Chen area term on each diagonal (Spencer-Chen:   */
-                            /* the same as 1).  The local -II variants are not       */
-                            /* offered (MGSEG_E_ARG); default 0                      */
+                            /* the same as 1); 5 GSLEX-II, 6 GSLINE-II, 7 NEWT-II:   */
+                            /* the local variants, each pixel's (column's)           */
+                            /* coefficients refreshed from the current iterate where */
+                            /* they are used, rows (columns) in four classes;        */
+                            /* Spencer-Chen only (NEWT-II is then GSLEX-II),         */
+                            /* mixed_precision = 1, GSLINE-II columns of at most     */
+                            /* 1024 cells (MGSEG_E_ARG otherwise); default 0         */
     int32_t run_max;        /* superpixels of Hybrid Smoother 2 (Sec. 4.3, Fig. 3):  */
                             /* 0 (default) solves every maximal run of starred cells */
                             /* on a line as one unit, as the paper does (lines       */

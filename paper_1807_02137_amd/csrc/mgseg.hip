@@ -15,6 +15,7 @@
 #include "mgseg_kernels.h"
 #include "mgseg_aos.h"
 #include "mgseg_lfa.h"
+#include "mgseg_local.h"
 
 #define MAXLEV 16
 
@@ -473,10 +474,49 @@ void freeze(mgseg_ctx *c, int l)
     chk(c);
 }
 
+// one pass of a local ("-II") smoother (Sec. 3.2): 5 GSLEX-II, 6 GSLINE-II, 7 NEWT-II
+// (Spencer-Chen rows: the same as GSLEX-II); the rows of each class, or its columns,
+// at once, the coefficients refreshed from the current iterate where they are used
+void outer_local(mgseg_ctx *c, int l)
+{
+    Level &L = c->lev[l];
+    with_dev(c, l, [&](auto A) {
+        using BT = std::remove_const_t<std::remove_pointer_t<decltype(A.b)>>;
+        if (c->p.smoother != 6) {
+            for (int cls = 0; cls < 4; cls++) {
+                const int rows = (L.n - cls + 3) / 4;
+                if (rows > 0)
+                    hipLaunchKernelGGL(k_gslex_local<BT>, dim3((rows + 63) / 64), dim3(64), 0, c->s, A, cls);
+            }
+            return;
+        }
+        LineArgs S;
+        std::memset(&S, 0, sizeof(S));
+        S.tout = L.P[0]; S.tpitch = L.prm; S.pitch = L.pcm; S.lpitch = L.pcm;
+        S.nl = L.m; S.ml = L.n; S.kap = (float)(c->p.mu / L.h); S.e2 = lev_e2(c, l); S.M = (float)c->p.M;
+        S.eps = (float)c->p.eps; S.bit = LAB_ALL; S.scaled = c->p.scaled; S.run_max = c->p.run_max;
+        const size_t lds = gsline_local_lds(L.n);
+        for (int cls = 0; cls < 4; cls++) {
+            const int cols = (L.m - cls + 3) / 4;
+            if (cols <= 0) continue;
+            if (L.n <= 64) hipLaunchKernelGGL((k_gsline_local<64, BT>), dim3(cols), dim3(64), lds, c->s, A, S, cls);
+            else if (L.n <= 128) hipLaunchKernelGGL((k_gsline_local<128, BT>), dim3(cols), dim3(128), lds, c->s, A, S, cls);
+            else if (L.n <= 256) hipLaunchKernelGGL((k_gsline_local<256, BT>), dim3(cols), dim3(256), lds, c->s, A, S, cls);
+            else if (L.n <= 512) hipLaunchKernelGGL((k_gsline_local<512, BT>), dim3(cols), dim3(512), lds, c->s, A, S, cls);
+            else hipLaunchKernelGGL((k_gsline_local<1024, BT>), dim3(cols), dim3(1024), lds, c->s, A, S, cls);
+        }
+    });
+    chk(c);
+}
+
 // one outer iteration of Hybrid Smoother 2: freeze, sweeps A, B, C, D
 void outer(mgseg_ctx *c, int l)
 {
     Level &L = c->lev[l];
+    if (c->p.smoother >= 5) {
+        outer_local(c, l);
+        return;
+    }
     freeze(c, l);
     if (c->p.smoother == 1 || c->p.smoother == 4) {
         // GSLEX-I: one pass of point updates in the order of sweep A (no cell starred).
@@ -838,7 +878,8 @@ mgseg_status setup_check(const float *image_dev, int n, int m, int pitch, const 
     if (p->struct_size != sizeof(mgseg_params)) return MGSEG_E_ARG;
     if (p->model == MGSEG_RADA_CHEN && k < 3) return MGSEG_E_ARG;   // the marker polygon needs an area (A1 > 0)
     if (p->nu1 < 0 || p->nu2 < 0 || p->coarse_iters < 0 || !(p->coarse_rtol >= 0.0) || !(p->M > 0.0) || !(p->eps > 0.0) || p->levels < 0 ||
-        p->levels > MAXLEV || p->smoother < 0 || p->smoother > 4 || ((p->smoother == 2 || p->smoother == 3) && !p->mixed_precision) ||
+        p->levels > MAXLEV || p->smoother < 0 || p->smoother > 7 || (p->smoother >= 2 && p->smoother != 4 && !p->mixed_precision) ||
+        (p->smoother >= 5 && (p->model != MGSEG_SPENCER_CHEN || (p->smoother == 6 && n > 1024))) ||
         p->run_max < 0 ||
         !(p->sigma_g >= 0.0 && p->sigma_g <= 16.0))
         return MGSEG_E_ARG;

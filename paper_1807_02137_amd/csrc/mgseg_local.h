@@ -1,0 +1,93 @@
+// The local ("-II") smoothers of Sec. 3.2: a pixel's (GSLEX-II) or a
+// column's (GSLINE-II) coefficients of eq. abcdrc are refreshed from the
+// current iterate right before they are used, instead of once per outer
+// iteration.  Deviation form (psi = b + e), Spencer-Chen rows (no global
+// area sum, whose running refresh would order every pixel after every other).
+//
+// Order: the lines of the four classes (index mod 4) of the parallel sweeps,
+// class after class.  The lines of one class share no stencil cell (a
+// pixel's coefficients and update read its 3 x 3 neighbourhood), so every
+// line of a class is updated at once and the result equals the sequential
+// order line by line.
+//
+// GSLEX-II: one thread per row of the class, walking its row left to right:
+// at each pixel the refreshed row (dev_cell: the face coefficients au and the
+// right-hand side T at the current b + e) and the point update
+//   e_ij <- clip((sum au e_nb - T) / sum au, lo, hi),
+// the left neighbour already updated.  A row is inherently sequential (the
+// next pixel's coefficients depend on this pixel's new value), so the pass
+// costs one pixel-step per column of every class, latency-bound.
+//
+// GSLINE-II: one workgroup per column of the class, one thread per cell: the
+// column's refreshed rows, then the column's box-constrained tridiagonal
+// system through the whole-line path of the directional sweep (every cell
+// starred), written in place.
+#pragma once
+#include "mgseg_kernels.h"
+
+template <typename BT>
+__global__ void __launch_bounds__(64) k_gslex_local(DevArgs<BT> A, int cls)
+{
+    const int i = cls + 4 * (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i >= A.n) return;
+    float *e = const_cast<float *>(A.e);
+    const long long row = (long long)i * A.p;
+    for (int j = 0; j < A.m; j++) {
+        double Le;
+        float u0, au[4];
+        uint8_t lab;
+        const double t = dev_cell(A, i, j, false, Le, u0, lab, au);
+        const float S = au[0] + au[1] + au[2] + au[3];
+        if (!(S > 0.0f)) continue;
+        float v = -(float)t;
+        if (i + 1 < A.n) v = fmaf(au[0], e[row + A.p + j], v);
+        if (i > 0) v = fmaf(au[1], e[row - A.p + j], v);
+        if (j + 1 < A.m) v = fmaf(au[2], e[row + j + 1], v);
+        if (j > 0) v = fmaf(au[3], e[row + j - 1], v);
+        e[row + j] = mg_clip(v / S, A.lo[row + j], A.hi[row + j]);
+    }
+}
+
+// L: the column sweep's arguments (nl = m lines of ml = n cells, bit LAB_ALL,
+// tout = e row-major); one workgroup of NT >= n threads per column
+template <int NT, typename BT>
+__global__ void __launch_bounds__(NT) k_gsline_local(DevArgs<BT> A, LineArgs L, int cls)
+{
+    extern __shared__ uint64_t smem64[];
+    __shared__ Ramp wtot[2 * (NT / 64)];
+    __shared__ unsigned wbad[NT / 64];
+    __shared__ Elim etot[NT / 64];
+    const int j = cls + 4 * (int)blockIdx.x;
+    if (j >= A.m) return;
+    const int i = threadIdx.x;
+    uint64_t *msk = smem64;
+    RunBuf B;
+    B.fs = A.n;
+    B.p = reinterpret_cast<float *>(smem64 + sweep_mask_words(A.n));
+    CellIn c{};
+    if (i < A.n) {
+        double Le;
+        float u0, au[4];
+        uint8_t lab;
+        const double t = dev_cell(A, i, j, false, Le, u0, lab, au);
+        const long long q = (long long)i * A.p + j;
+        // (to the next line j+1, the previous line j-1, the next cell i+1, the previous cell i-1)
+        c.g = make_float4(au[2], au[3], au[0], au[1]);
+        c.F = (float)t;
+        c.vu = j > 0 ? A.e[q - 1] : 0.0f;
+        c.vd = j + 1 < A.m ? A.e[q + 1] : 0.0f;
+        c.sig = i + 1 < A.n ? A.e[q + A.p] : 0.0f;
+        c.pold = A.e[q];
+        c.lo = A.lo[q];
+        c.hi = A.hi[q];
+        c.lab = 0;
+        c.qd = 0.0f;
+    }
+    sweep_line<NT, false, true, NT == 64, true>(L, j, B, msk, true, 0.0f, false, 0.0f, false, wtot, wbad, etot, c,
+                                                i, true);
+}
+
+inline size_t gsline_local_lds(int n)
+{
+    return sizeof(uint64_t) * (size_t)sweep_mask_words(n) + sizeof(float) * (size_t)RB_FIELDS * n;
+}

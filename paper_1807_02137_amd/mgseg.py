@@ -71,7 +71,8 @@ class Params:
     mixed_precision: int = 1
     scaled: int = 1
     coarse_rtol: float = 1e-4
-    smoother: int = 0           # 0 Hybrid Smoother 2, 1 GSLEX-I, 2 Hybrid Smoother 1, 3 GSLINE-I, 4 NEWT-I
+    smoother: int = 0           # 0 Hybrid Smoother 2, 1 GSLEX-I, 2 Hybrid Smoother 1, 3 GSLINE-I, 4 NEWT-I,
+                                # 5 GSLEX-II, 6 GSLINE-II, 7 NEWT-II (Spencer-Chen)
     run_max: int = 0            # 0 maximal superpixel runs (the paper's); k > 0 runs cut into pieces of <= k
 
     def to_c(self) -> _Params:

@@ -386,11 +386,12 @@ def test_solve_parity_hybrid1(seed):
     s.close()
 
 
-@pytest.mark.parametrize("smoother,model", [(3, 0), (3, 1), (4, 1), (4, 0)])
+@pytest.mark.parametrize("smoother,model", [(3, 0), (3, 1), (4, 1), (4, 0), (5, 0), (6, 0), (7, 0)])
 def test_solve_parity_standard_smoothers(smoother, model):
-    """Algorithm 1 with GSLINE-I (3: one line system per column) and NEWT-I (4: the
-    point Newton step of eq. newtrc) against the oracle's same smoother, both
-    models: the cycle histories and the final segmentation."""
+    """Algorithm 1 with GSLINE-I (3: one line system per column), NEWT-I (4: the
+    point Newton step of eq. newtrc) and the local variants GSLEX-II, GSLINE-II,
+    NEWT-II (5-7, coefficients refreshed where used; Spencer-Chen) against the
+    oracle's same smoother: the cycle histories and the final segmentation."""
     say("case smoother", smoother, "model", model)
     inst, s, o = make(1001, smoother=smoother, model=model)
     hg = []
