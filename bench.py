@@ -97,6 +97,9 @@ def copy_bandwidth(mib: int = 1024, reps: int = 5) -> float:
 
 SEED = 2000
 N = 1024
+SMOOTHERS = {"hs2": (0, "Hybrid Smoother 2"), "gslex": (1, "GSLEX-I"), "hs1": (2, "Hybrid Smoother 1"),
+             "gsline": (3, "GSLINE-I"), "newt": (4, "NEWT-I"), "gslex2": (5, "GSLEX-II"),
+             "gsline2": (6, "GSLINE-II"), "newt2": (7, "NEWT-II")}
 LEVELS = 9
 TOL = 1e-6
 MAX_CYCLES = 80
@@ -434,9 +437,10 @@ def main():
                          "on 512x512 held-out images")
     ap.add_argument("--model", default="sc", choices=("sc", "rc", "cv"),
                     help="c2 only: Spencer-Chen (default), Rada-Chen or the global Chan-Vese workload")
-    ap.add_argument("--smoother", default="hs2", choices=("hs2", "gslex", "hs1"),
-                    help="c2 only: Hybrid Smoother 2 (default, the paper's Algorithm 3), GSLEX-I (its "
-                         "Algorithm 1 with a standard smoother) or Hybrid Smoother 1 (its Algorithm 2)")
+    ap.add_argument("--smoother", default="hs2", choices=tuple(SMOOTHERS),
+                    help="c2 only: Hybrid Smoother 2 (default, the paper's Algorithm 3), Hybrid Smoother 1 "
+                         "(its Algorithm 2) or a standard smoother of its Algorithm 1 (gslex, gsline, newt: "
+                         "the -I variants; gslex2, gsline2, newt2: the local -II variants)")
     ap.add_argument("--solver", default="mg", choices=("mg", "aos"),
                     help="c2 only: the FAS multigrid (default) or the AOS time stepper the paper compares "
                          "against (Sec. 5), run to the relative change --aos-eta")
@@ -472,7 +476,7 @@ def main():
     inst = synth.config2(SEED, N)
     img = torch.from_numpy(inst.image).to("cuda")
     model = 1 if args.model == "rc" else 0
-    smoother = {"hs2": 0, "gslex": 1, "hs1": 2}[args.smoother]
+    smoother = SMOOTHERS[args.smoother][0]
     params = (mgseg.chan_vese_params(levels=LEVELS, smoother=smoother) if args.model == "cv"
               else mgseg.Params(levels=LEVELS, model=model, smoother=smoother))
     stream = torch.cuda.current_stream()
@@ -536,7 +540,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "1024x1024 12-ellipse image, 6 markers, "
                                f"{MODEL_NAMES[args.model]}, FAS V(2,2), "
-                               f"9 grids, {['Hybrid Smoother 2', 'GSLEX-I', 'Hybrid Smoother 1'][smoother]}, tol 1e-6",
+                               f"9 grids, {SMOOTHERS[args.smoother][1]}, tol 1e-6",
                    "seed": SEED,
                    "parallelism": "single GPU"},
         "cycles_per_solve": cycles,

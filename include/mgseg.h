@@ -247,6 +247,37 @@ mgseg_status mgseg_aos(mgseg_ctx *c, double tau, double eta_tol, int max_iters, 
  * pitch), MGSEG_E_STATE, MGSEG_E_NOMEM, MGSEG_E_HIP. */
 mgseg_status mgseg_smoothing_rates(mgseg_ctx *c, int smoother, double *out5, float *mu_dev, int mu_pitch);
 
+/* Launch schedule of a context.  Every schedule computes the same bits
+ * (each kernel choice below evaluates the same arithmetic in the same
+ * order); they differ only in speed.
+ *   lds_side      grids below the finest with both sides at most lds_side
+ *                 (and at most 64) run in one LDS-resident workgroup: the
+ *                 coarsest solve, and the smoothing of grids of at most 32 x 32
+ *                 (0: every grid through the global-memory kernels); default 64
+ *   line_threads  0: each line of a sweep takes the smallest workgroup half
+ *                 that holds it (default); 1: the next wider one (lines of at
+ *                 most 512 cells)
+ *   graph         1: each cycle is replayed from a captured HIP graph
+ *                 (default); 0: launched eagerly */
+typedef struct {
+    int32_t lds_side;
+    int32_t line_threads;
+    int32_t graph;
+} mgseg_schedule;
+
+mgseg_status mgseg_get_schedule(mgseg_ctx *c, mgseg_schedule *out);
+/* MGSEG_E_ARG on a value out of range. */
+mgseg_status mgseg_set_schedule(mgseg_ctx *c, const mgseg_schedule *s);
+
+/* Autotuner: times trial_cycles V-cycles (after one untimed) of every
+ * schedule of lds_side in {0, 16, 32, 64} x line_threads in {0, 1} x graph
+ * in {0, 1} from the context's current state, keeps the fastest, and
+ * restores the state (the solve continues where it stood; the cycle count
+ * is unchanged).  Outputs (each may be null): the chosen schedule and its
+ * milliseconds per cycle.  Errors: MGSEG_E_ARG (trial_cycles < 1),
+ * MGSEG_E_HIP. */
+mgseg_status mgseg_tune(mgseg_ctx *c, int trial_cycles, mgseg_schedule *best_out, double *ms_per_cycle_out);
+
 /* Finest phi in FP64 (n x m, pitch in elements). */
 mgseg_status mgseg_get_phi(mgseg_ctx *c, double *phi_dev, int pitch);
 

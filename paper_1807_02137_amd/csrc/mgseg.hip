@@ -80,6 +80,7 @@ struct mgseg_ctx {
     float *pred = nullptr;          // network input and output of mgseg_predict_phi0 (first call)
     double *aos = nullptr;          // six n x m FP64 planes of the AOS solver (first call)
     double *lfa = nullptr;          // partials of mgseg_smoothing_rates (first call)
+    mgseg_schedule sched{64, 0, 1}; // launch schedule (mgseg_set_schedule, mgseg_tune)
     hipError_t err = hipSuccess;
     bool oom = false;
     // one V-cycle captured as a HIP graph (replayed on s); cap: private capture stream
@@ -379,17 +380,19 @@ void launch_sweep(mgseg_ctx *c, int l, int s, const float *phi_old, float *phi_n
     // A whole-line system (every cell starred: the line relaxation of Hybrid
     // Smoother 1, forward, on the stored coefficients) has kernels of its own
     // that eliminate the line by a scan.
+    // the schedule's line_threads = 1 gives each line the next wider group (lines of at most 512 cells)
+    const int mls = c->sched.line_threads && ml <= 512 ? 2 * ml : ml;
     if (whl) {
-        if (ml <= 64) hipLaunchKernelGGL((k_sweep2<64, false, true, true>), dim3(bands), dim3(128), lds2, c->s, A);
-        else if (ml <= 128) hipLaunchKernelGGL((k_sweep2<128, false, true, true>), dim3(bands), dim3(256), lds2, c->s, A);
-        else if (ml <= 256) hipLaunchKernelGGL((k_sweep2<256, false, true, true>), dim3(bands), dim3(512), lds2, c->s, A);
-        else if (ml <= 512) hipLaunchKernelGGL((k_sweep2<512, false, true, true>), dim3(bands), dim3(1024), lds2, c->s, A);
+        if (mls <= 64) hipLaunchKernelGGL((k_sweep2<64, false, true, true>), dim3(bands), dim3(128), lds2, c->s, A);
+        else if (mls <= 128) hipLaunchKernelGGL((k_sweep2<128, false, true, true>), dim3(bands), dim3(256), lds2, c->s, A);
+        else if (mls <= 256) hipLaunchKernelGGL((k_sweep2<256, false, true, true>), dim3(bands), dim3(512), lds2, c->s, A);
+        else if (mls <= 512) hipLaunchKernelGGL((k_sweep2<512, false, true, true>), dim3(bands), dim3(1024), lds2, c->s, A);
         else hipLaunchKernelGGL((k_sweep<1024, false, true, true>), dim3(bands), dim3(1024), lds, c->s, A);
-    } else if (ml <= 64) MG_SWEEP2(64);
-    else if (ml <= 128) MG_SWEEP2(128);
-    else if (ml <= 256) MG_SWEEP2(256);
-    else if (ml <= 512) MG_SWEEP2(512);
-    else if (ml <= 1024) MG_SWEEP(1024);
+    } else if (mls <= 64) MG_SWEEP2(64);
+    else if (mls <= 128) MG_SWEEP2(128);
+    else if (mls <= 256) MG_SWEEP2(256);
+    else if (mls <= 512) MG_SWEEP2(512);
+    else if (mls <= 1024) MG_SWEEP(1024);
     else MG_SWEEP_LONG();
 #undef MG_SWEEP
 #undef MG_SWEEP_CF
@@ -486,13 +489,14 @@ void outer_local(mgseg_ctx *c, int l)
             for (int cls = 0; cls < 4; cls++) {
                 const int rows = (L.n - cls + 3) / 4;
                 if (rows > 0)
-                    hipLaunchKernelGGL(k_gslex_local<BT>, dim3((rows + 63) / 64), dim3(64), 0, c->s, A, cls);
+                    hipLaunchKernelGGL(k_gslex_local<BT>, dim3((rows + 63) / 64), dim3(64), 0, c->s, A, cls,
+                                       c->sweep_skip);
             }
             return;
         }
         LineArgs S;
         std::memset(&S, 0, sizeof(S));
-        S.tout = L.P[0]; S.tpitch = L.prm; S.pitch = L.pcm; S.lpitch = L.pcm;
+        S.tout = L.P[0]; S.tpitch = L.prm; S.pitch = L.pcm; S.lpitch = L.pcm; S.skip = c->sweep_skip;
         S.nl = L.m; S.ml = L.n; S.kap = (float)(c->p.mu / L.h); S.e2 = lev_e2(c, l); S.M = (float)c->p.M;
         S.eps = (float)c->p.eps; S.bit = LAB_ALL; S.scaled = c->p.scaled; S.run_max = c->p.run_max;
         const size_t lds = gsline_local_lds(L.n);
@@ -596,7 +600,8 @@ CoarseArgs coarse_args(mgseg_ctx *c, int l, int iters, double rtol)
 bool lds_level(mgseg_ctx *c, int l)
 {
     const Level &L = c->lev[l];
-    return l > 0 && L.n <= 64 && L.m <= 64 && L.n * L.m <= CO_MAX_CELLS;
+    const int side = std::min(64, c->sched.lds_side);
+    return l > 0 && L.n <= side && L.m <= side && L.n * L.m <= CO_MAX_CELLS;
 }
 
 void smooth(mgseg_ctx *c, int l, int iters)
@@ -781,7 +786,7 @@ void enqueue_cycle(mgseg_ctx *c)
 // keep the eager launches.
 bool graph_usable(const mgseg_ctx *c)
 {
-    if (c->prof_on || c->graph_failed || c->noalloc) return false;
+    if (c->prof_on || c->graph_failed || c->noalloc || !c->sched.graph) return false;
     const char *env = std::getenv("MGSEG_GRAPH");
     if (env && env[0] == '0') return false;
     return true;
@@ -1441,6 +1446,67 @@ mgseg_status mgseg_set_state(mgseg_ctx *c, const void *blob, size_t bytes)
     c->res0 = h.res0; c->res = h.res; c->rel = h.rel; c->eta = h.eta; c->cycles = h.cycles;
     c->res0_rows = h.res0_rows; c->res_rows = read_scalar(c, DS_RESR);
     return MGSEG_OK;
+}
+
+mgseg_status mgseg_get_schedule(mgseg_ctx *c, mgseg_schedule *out)
+{
+    if (!c || !out) return MGSEG_E_ARG;
+    *out = c->sched;
+    return MGSEG_OK;
+}
+
+mgseg_status mgseg_set_schedule(mgseg_ctx *c, const mgseg_schedule *sc)
+{
+    if (!c || !sc || sc->lds_side < 0 || sc->line_threads < 0 || sc->line_threads > 1 || sc->graph < 0 ||
+        sc->graph > 1)
+        return MGSEG_E_ARG;
+    mgseg_status st = sync_status(c);
+    if (st != MGSEG_OK) return st;
+    const bool relaunch = sc->lds_side != c->sched.lds_side || sc->line_threads != c->sched.line_threads;
+    c->sched = *sc;
+    // a captured cycle holds the old launches
+    if (relaunch && c->gexec) {
+        (void)hipGraphExecDestroy(c->gexec);
+        c->gexec = nullptr;
+    }
+    return MGSEG_OK;
+}
+
+mgseg_status mgseg_tune(mgseg_ctx *c, int trial_cycles, mgseg_schedule *best_out, double *ms_per_cycle_out)
+{
+    if (!c || trial_cycles < 1) return MGSEG_E_ARG;
+    size_t bytes = 0;
+    mgseg_status st = mgseg_get_state(c, nullptr, &bytes);
+    if (st != MGSEG_OK) return st;
+    std::vector<char> saved(bytes);
+    st = mgseg_get_state(c, saved.data(), &bytes);
+    if (st != MGSEG_OK) return st;
+    const mgseg_schedule start = c->sched;
+    mgseg_schedule best = start;
+    double best_ms = 1e300;
+    const int sides[] = {0, 16, 32, 64};
+    for (int side : sides)
+        for (int lt = 0; lt <= 1; lt++)
+            for (int g = 0; g <= 1; g++) {
+                const mgseg_schedule cand{side, lt, g};
+                st = mgseg_set_schedule(c, &cand);
+                if (st == MGSEG_OK) st = mgseg_set_state(c, saved.data(), bytes);
+                double rel = 0.0;
+                if (st == MGSEG_OK) st = one_cycle(c, &rel);    // untimed: the capture of a graph
+                if (st != MGSEG_OK && st != MGSEG_E_NONFINITE) break;
+                auto t0 = std::chrono::steady_clock::now();
+                for (int k = 0; k < trial_cycles && st == MGSEG_OK; k++) st = one_cycle(c, &rel);
+                const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0)
+                                      .count() / trial_cycles;
+                if (st == MGSEG_OK && ms < best_ms) { best_ms = ms; best = cand; }
+            }
+    // the solve continues from where it stood, with the fastest schedule
+    mgseg_status st2 = mgseg_set_schedule(c, best_ms < 1e300 ? &best : &start);
+    if (st2 == MGSEG_OK) st2 = mgseg_set_state(c, saved.data(), bytes);
+    if (best_out) *best_out = c->sched;
+    if (ms_per_cycle_out) *ms_per_cycle_out = best_ms;
+    if (st != MGSEG_OK && st != MGSEG_E_NONFINITE) return st;
+    return st2;
 }
 
 mgseg_status mgseg_level_shape(mgseg_ctx *c, int level, int *n, int *m, double *h)

@@ -25,9 +25,11 @@
 #pragma once
 #include "mgseg_kernels.h"
 
+// skip: non-null and set, the launch does nothing (the coarsest solve's stop)
 template <typename BT>
-__global__ void __launch_bounds__(64) k_gslex_local(DevArgs<BT> A, int cls)
+__global__ void __launch_bounds__(64) k_gslex_local(DevArgs<BT> A, int cls, const int *skip)
 {
+    if (skip && *skip) return;
     const int i = cls + 4 * (int)(blockIdx.x * blockDim.x + threadIdx.x);
     if (i >= A.n) return;
     float *e = const_cast<float *>(A.e);
@@ -53,6 +55,7 @@ __global__ void __launch_bounds__(64) k_gslex_local(DevArgs<BT> A, int cls)
 template <int NT, typename BT>
 __global__ void __launch_bounds__(NT) k_gsline_local(DevArgs<BT> A, LineArgs L, int cls)
 {
+    if (L.skip && *L.skip) return;
     extern __shared__ uint64_t smem64[];
     __shared__ Ramp wtot[2 * (NT / 64)];
     __shared__ unsigned wbad[NT / 64];

@@ -42,6 +42,10 @@ class _Params(C.Structure):
                 ("run_max", C.c_int32)]
 
 
+class _Schedule(C.Structure):
+    _fields_ = [("lds_side", C.c_int32), ("line_threads", C.c_int32), ("graph", C.c_int32)]
+
+
 class _Stats(C.Structure):
     _fields_ = [("c1", C.c_double), ("c2", C.c_double), ("rel_res", C.c_double), ("res", C.c_double),
                 ("res0", C.c_double), ("eta", C.c_double), ("cycles", C.c_int32), ("levels", C.c_int32),
@@ -120,6 +124,9 @@ def lib():
         L.mgseg_solve.argtypes = [vp, C.c_double, C.c_int, ip, dp]
         L.mgseg_aos.argtypes = [vp, C.c_double, C.c_double, C.c_int, ip, dp, dp]
         L.mgseg_smoothing_rates.argtypes = [vp, C.c_int, dp, vp, C.c_int]
+        L.mgseg_get_schedule.argtypes = [vp, C.POINTER(_Schedule)]
+        L.mgseg_set_schedule.argtypes = [vp, C.POINTER(_Schedule)]
+        L.mgseg_tune.argtypes = [vp, C.c_int, C.POINTER(_Schedule), dp]
         L.mgseg_get_phi.argtypes = [vp, vp, C.c_int]
         L.mgseg_get_mask.argtypes = [vp, vp, C.c_int]
         L.mgseg_get_stats.argtypes = [vp, C.POINTER(_Stats)]
@@ -168,7 +175,7 @@ def lib():
                      "mgseg_net_get_params", "mgseg_net_set_params", "mgseg_ctx_features", "mgseg_predict_phi0",
                      "mgseg_reset_phi0", "mgseg_net_profile", "mgseg_net_profile_read",
                      "mgseg_get_state", "mgseg_set_state", "mgseg_solve_noalloc", "mgseg_aos",
-                     "mgseg_smoothing_rates"):
+                     "mgseg_smoothing_rates", "mgseg_get_schedule", "mgseg_set_schedule", "mgseg_tune"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -276,6 +283,22 @@ class Solver:
                "mgseg_smoothing_rates")
         keys = ("mu_max", "mu_avg", "mu_max_D", "mu_avg_D", "share_D")
         return dict(zip(keys, list(out))), (mu.cpu().numpy() if mu is not None else None)
+
+    def schedule(self) -> dict:
+        sc = _Schedule()
+        _check(self.L.mgseg_get_schedule(self.ctx, C.byref(sc)), "mgseg_get_schedule")
+        return {k: getattr(sc, k) for k, _ in _Schedule._fields_}
+
+    def set_schedule(self, lds_side=64, line_threads=0, graph=1):
+        sc = _Schedule(lds_side, line_threads, graph)
+        _check(self.L.mgseg_set_schedule(self.ctx, C.byref(sc)), "mgseg_set_schedule")
+
+    def tune(self, trial_cycles=2):
+        """Times every launch schedule from the current state and keeps the fastest
+        (the state is restored): (schedule dict, ms per cycle)."""
+        sc, ms = _Schedule(), C.c_double()
+        _check(self.L.mgseg_tune(self.ctx, trial_cycles, C.byref(sc), C.byref(ms)), "mgseg_tune")
+        return {k: getattr(sc, k) for k, _ in _Schedule._fields_}, ms.value
 
     def set_phi0(self, phi):
         t = torch.as_tensor(phi, dtype=torch.float32, device="cuda").contiguous()

@@ -3,6 +3,7 @@
 Every test drives the HIP library through its C ABI (Python ctypes binding)
 and the oracle on the same seeded synthetic input.
 """
+import os
 import sys
 
 import numpy as np
@@ -52,14 +53,28 @@ def test_setup_maps():
 
 
 def test_labels_match():
+    """Labels of the jump set (Sec. 4.1, Sec. 5.2) from the GPU's FP32 face values
+    against the oracle's FP64 ones: every mismatch must be a near-tie of the
+    oracle's own faces, the ratio test within 1e-6 of Sigma or the two smallest
+    interior faces within 1e-6 of each other."""
     say("case labels seed 1000")
     inst, s, o = make(mixed=0)
     s.op("freeze", 0)
     o.freeze(0)
     lg, lo = s.get("labels"), o.labels()
-    mism = int((lg != lo).sum())
-    say("label mismatches", mism, "of", lg.size, "jump-set fraction", float((lo > 0).mean()))
-    assert mism <= 2
+    n, m = lg.shape
+    faces = np.stack([o.get(k) for k in "ABCD"], axis=-1)
+    bad = np.argwhere(lg != lo)
+    say("label mismatches", len(bad), "of", lg.size, "jump-set fraction", float((lo > 0).mean()))
+    sigma = OracleParams().Sigma
+    for i, j in bad:
+        inside = [i + 1 < n, i > 0, j + 1 < m, j > 0]
+        g = np.array([faces[i, j, k] for k in range(4) if inside[k]])
+        srt = np.sort(g)
+        ratio_tie = abs(srt[-1] - sigma * srt[0]) <= 1e-6 * srt[-1]
+        argmin_tie = abs(srt[1] - srt[0]) <= 1e-6 * srt[1]
+        say(f"  ({i}, {j}) gpu {lg[i, j]} oracle {lo[i, j]} faces {g} ratio tie {ratio_tie} argmin tie {argmin_tie}")
+        assert ratio_tie or argmin_tie
     s.close()
 
 
@@ -78,8 +93,9 @@ def test_single_sweep(sweep):
     s.op(["sweep_A", "sweep_B", "sweep_C", "sweep_D"][sweep], 0)
     o.sweep(sweep, 0)
     d = np.abs(s.get("phi").astype(np.float64) - o.get("phi"))
-    say("max |dphi|", d.max(), "runs in sweep", int(((o.labels() >> sweep) & 1).sum()))
-    assert d.max() <= 2e-4
+    scale = np.abs(o.get("phi")).max()
+    say("max |dphi|", d.max(), "relative", d.max() / scale, "runs in sweep", int(((o.labels() >> sweep) & 1).sum()))
+    assert d.max() <= 1e-5 * scale
     s.close()
 
 
@@ -103,6 +119,8 @@ def test_vcycle_trajectory():
         pg, po = s.get("phi64"), o.get("phi")
         flips = int(((pg > 0) != (po > 0)).sum())
         say(f"cycle {k}: rel gpu {rg:.3e} oracle {ro:.3e} max|dphi| {np.abs(pg - po).max():.3e} flips {flips}")
+        assert abs(rg - ro) <= 1e-3 * ro
+        assert np.abs(pg - po)[(pg > 0) == (po > 0)].max() <= 1e-4
     assert flips <= 2
     s.close()
 
@@ -549,6 +567,58 @@ def test_full_size_solution_has_oracle_residual():
     assert ok and rel <= 1e-6
     assert rel_or <= 1.1e-6
     assert iou >= 0.9
+    s.close()
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def test_c2_full_size_matches_the_oracle_solve():
+    """The 1024x1024 benchmark image (seed 2000, 9 grids) solved to 1e-6 on the
+    GPU against the oracle's own solve of it (tests/golden/make_fullsize.py):
+    the cycle count, the segmentation (at most 0.01 % of pixels differ) and phi
+    at 4096 seeded pixels (|dphi| <= 1e-4 where the masks agree)."""
+    say("case full size 1024x1024 against the oracle's solve")
+    ref = np.load(os.path.join(GOLDEN, "c2_oracle_1024.npz"))
+    inst = synth.config2(2000, 1024)
+    s = mgseg.Solver(inst.image, inst.markers, mgseg.Params(levels=9))
+    cyc, rel, ok = s.solve(1e-6, 80)
+    phi = s.phi().cpu().numpy()
+    mask_o = np.unpackbits(ref["mask"])[: phi.size].reshape(phi.shape).astype(bool)
+    flips = int(((phi > 0) != mask_o).sum())
+    si, sj = ref["si"], ref["sj"]
+    agree = (phi[si, sj] > 0) == mask_o[si, sj]
+    d = np.abs(phi[si, sj] - ref["phi_s"])[agree].max()
+    say(f"gpu {cyc} cycles rel {rel:.3e}; oracle {int(ref['cycles'])} cycles; flips {flips}; max|dphi| {d:.3e}")
+    assert ok and abs(cyc - int(ref["cycles"])) <= 1
+    assert flips <= 1e-4 * phi.size
+    assert d <= 1e-4
+    s.close()
+
+
+def test_c4_first_two_cycles_match_the_oracle():
+    """The 8192x8192 star-polygon image (seed 4000, 14 grids): the relative
+    residuals of the first two cycles, the segmentation after them (at most
+    0.01 % of pixels differ) and phi at 16384 seeded pixels against the oracle's
+    first two cycles (tests/golden/make_fullsize.py)."""
+    say("case 8192x8192 first two cycles")
+    path = os.path.join(GOLDEN, "c4_oracle_8192_2cycles.npz")
+    if not os.path.exists(path):
+        pytest.skip("oracle fixture not written")
+    ref = np.load(path)
+    inst = synth.config4(4000, 8192)
+    s = mgseg.Solver(inst.image, inst.markers, mgseg.Params(levels=14))
+    hist = [s.vcycle() for _ in range(2)]
+    phi = s.phi().cpu().numpy()
+    mask_o = np.unpackbits(ref["mask"])[: phi.size].reshape(phi.shape).astype(bool)
+    flips = int(((phi > 0) != mask_o).sum())
+    si, sj = ref["si"], ref["sj"]
+    agree = (phi[si, sj] > 0) == mask_o[si, sj]
+    d = np.abs(phi[si, sj] - ref["phi_s"])[agree].max()
+    say(f"gpu {np.round(hist, 5)} oracle {np.round(ref['hist'], 5)} flips {flips} max|dphi| {d:.3e}")
+    assert np.all(np.abs(np.array(hist) - ref["hist"]) <= 1e-3 * ref["hist"])
+    assert flips <= 1e-4 * phi.size
+    assert d <= 1e-4
     s.close()
 
 
