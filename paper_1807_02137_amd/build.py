@@ -7,7 +7,8 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRCS = [os.path.join(HERE, "csrc", "mgseg.hip"), os.path.join(HERE, "csrc", "mgseg_net.hip")]
-DEPS = [*SRCS, os.path.join(HERE, "csrc", "mgseg_device.h"), os.path.join(HERE, "csrc", "mgseg_kernels.h"),
+DEPS = [*SRCS, *(os.path.join(HERE, "csrc", f) for f in ("mgseg_device.h", "mgseg_kernels.h", "mgseg_aos.h",
+                                                           "mgseg_lfa.h", "mgseg_local.h")),
         os.path.join(ROOT, "include", "mgseg.h")]
 LIB_DIR = os.path.join(HERE, "lib")
 LIB = os.path.join(LIB_DIR, "libmgseg.so")
