@@ -12,12 +12,9 @@
 //
 // Data: five dense n x m FP64 planes hold 2 tau s g for the faces to i+1,
 // i-1, j+1, j-1 (s = kappa delta, or kappa for the scaled rows) and r; the
-// column solves put y_1 in a sixth.  A column is one thread (consecutive
-// threads take consecutive columns, so every row step is one coalesced
-// access); a row is one thread walking along its row (the accesses of a wave
-// are one element of each of 64 rows; each 128-byte line serves 16 steps
-// from the cache).  Both are Thomas eliminations (the rows are strictly
-// diagonally dominant M-matrix rows: positive pivots, no pivoting).
+// column solves put y_1 in a sixth, the row solves y_2 over a coupling
+// plane.  Every line (column or row) is one wave (k_aos_lines); the rows are
+// strictly diagonally dominant M-matrix rows (positive pivots, no pivoting).
 #pragma once
 #include "mgseg_device.h"
 
@@ -67,45 +64,107 @@ __global__ void __launch_bounds__(256) k_aos_coef(AosArgs A)
     A.r[q] = p0 - A.tau * f;
 }
 
-// Thomas elimination of one line of len cells at base + k * step:
-//   -lo_k y_{k-1} + (1 + up_k + lo_k) y_k - up_k y_{k+1} = r_k.
-// Forward: y_k = e_k y_{k+1} + t_k with e_k = up_k / d_k, t_k = (r_k + lo_k t_{k-1}) / d_k,
-// d_k = 1 + up_k + lo_k (1 - e_{k-1}); e goes over up, t over y; back substitution in y.
-__device__ __forceinline__ void aos_line(double *up, const double *lo, const double *r, double *y, long long base,
-                                         long long step, int len)
+// One line of len cells per wave, chunks of C = ceil(len / 64) consecutive
+// cells per lane, for the rows
+//   -lo_k y_{k-1} + (1 + up_k + lo_k) y_k - up_k y_{k+1} = r_k
+// (lo_0 = up_{len-1} = 0: the couplings across the grid edge vanish), cell k
+// of line L at L * ls + k * cs.  The backward elimination y_k = P_k y_{k-1} +
+// Q_k is the linear-fractional map of the elimination scan (Elim, FP64):
+//  1. each lane composes its chunk's steps into one map;
+//  2. a wave scan of the chunk maps from the line's end gives each lane the
+//     state (P, Q) just after its chunk;
+//  3. each lane runs the plain backward recursion over its own cells from
+//     that state, and stores P_k, Q_k over up_k, lo_k;
+//  4. the forward substitution: each lane composes its cells' affine maps
+//     y -> P_k y + Q_k, a wave scan in line order gives the value entering
+//     its chunk, and the lane writes its cells' y.
+// The recursions inside a chunk are the sequential elimination; only the 6
+// scan levels compose maps.  A workgroup of 16 waves takes 16 neighbouring
+// lines, so that strided lines (columns of a row-major plane) share each
+// cache line between its waves.
+__device__ __forceinline__ Elim elim_step_d(double a, double c, double r) { return Elim{c, 0.0, -r, 0.0, a, -c}; }
+
+struct Aff {
+    double a, b;               // y -> a y + b
+};
+__device__ __forceinline__ Aff aff_comp(const Aff &g, const Aff &f) { return Aff{g.a * f.a, fma(g.a, f.b, g.b)}; }
+template <int CTRL, int ROWM = 0xf>
+__device__ __forceinline__ Aff dpp_aff(const Aff &v)
 {
-    double e = 0.0, t = 0.0;
-    for (int k = 0; k < len; k++) {
-        const long long q = base + k * step;
+    return Aff{dpp_d<CTRL, ROWM>(1.0, v.a), dpp_d<CTRL, ROWM>(0.0, v.b)};
+}
+__device__ __forceinline__ Aff wave_scan_aff(Aff v)
+{
+    v = aff_comp(v, dpp_aff<0x111>(v));
+    v = aff_comp(v, dpp_aff<0x112>(v));
+    v = aff_comp(v, dpp_aff<0x114>(v));
+    v = aff_comp(v, dpp_aff<0x118>(v));
+    v = aff_comp(v, dpp_aff<0x142, 0xa>(v));
+    v = aff_comp(v, dpp_aff<0x143, 0xc>(v));
+    return v;
+}
+__device__ __forceinline__ double shfl_d(double x, int src)
+{
+    return __shfl(x, src, 64);
+}
+__device__ __forceinline__ Elim shfl_elim(const Elim &e, int src)
+{
+    return Elim{shfl_d(e.al, src), shfl_d(e.b0, src), shfl_d(e.b1, src), shfl_d(e.m00, src), shfl_d(e.m01, src),
+                shfl_d(e.m10, src)};
+}
+
+__global__ void __launch_bounds__(1024) k_aos_lines(double *up, double *lo, const double *r, double *y, int nlines,
+                                                    int len, long long ls, long long cs)
+{
+    const int lane = threadIdx.x & 63;
+    const int line = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (line >= nlines) return;                        // whole waves
+    const long long base = (long long)line * ls;
+    const int C = (len + 63) / 64;
+    const int k0 = min(lane * C, len), k1 = min(k0 + C, len);
+    auto at = [&](int k) { return base + (long long)k * cs; };
+    // 1. the chunk's elimination map, from its last cell to its first
+    Elim E = elim_id();
+    for (int k = k1 - 1; k >= k0; k--) {
+        const long long q = at(k);
         const double a = up[q], b = lo[q];
-        const double inv = 1.0 / (1.0 + a + b * (1.0 - e));
-        e = a * inv;
-        t = (r[q] + b * t) * inv;
-        up[q] = e;
-        y[q] = t;
+        const double inv = 1.0 / (1.0 + a + b);
+        E = elim_comp(elim_step_d(b * inv, a * inv, -r[q] * inv), E);
     }
-    for (int k = len - 2; k >= 0; k--) {
-        const long long q = base + k * step;
-        t = fma(up[q], t, y[q]);
-        y[q] = t;
+    // 2. the maps of the chunks after this one, composed (lanes reversed, so that a later
+    //    chunk sits on a lower lane and is applied first), exclusive
+    Elim R = shfl_elim(E, 63 - lane);
+    R = wave_scan_elim<64>(R);
+    const Elim id = elim_id();
+    R = Elim{dpp_d<0x138>(id.al, R.al), dpp_d<0x138>(id.b0, R.b0), dpp_d<0x138>(id.b1, R.b1),
+             dpp_d<0x138>(id.m00, R.m00), dpp_d<0x138>(id.m01, R.m01), dpp_d<0x138>(id.m10, R.m10)};
+    const Elim S = shfl_elim(R, 63 - lane);
+    // 3. the backward recursion over the chunk from the state after it (beyond the line's end: P = Q = 0)
+    double P = S.m01, Q = S.b1;
+    for (int k = k1 - 1; k >= k0; k--) {
+        const long long q = at(k);
+        const double a = up[q], b = lo[q];
+        const double d = 1.0 + a + b;
+        const double inv = 1.0 / (d - a * P);
+        P = b * inv;
+        Q = fma(a, Q, r[q]) * inv;
+        up[q] = P;
+        lo[q] = Q;
     }
-}
-
-// one thread per column: couplings to i+1 (uA) and i-1 (uB); y_1 -> y
-__global__ void __launch_bounds__(64) k_aos_cols(double *uA, const double *uB, const double *r, double *y, int n, int m)
-{
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= m) return;
-    aos_line(uA, uB, r, y, j, m, n);
-}
-
-// one thread per row: couplings to j+1 (uC) and j-1 (uD); y_2 -> uD (each
-// element is read before it is overwritten, by the same thread)
-__global__ void __launch_bounds__(64) k_aos_rows(double *uC, double *uD, const double *r, int n, int m)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    aos_line(uC, uD, r, uD, (long long)i * m, 1, m);
+    // 4. forward substitution: the chunk's affine map, the value entering it, the cells
+    Aff F{1.0, 0.0};
+    for (int k = k0; k < k1; k++) {
+        const long long q = at(k);
+        F = aff_comp(Aff{up[q], lo[q]}, F);
+    }
+    const Aff inc = wave_scan_aff(F);
+    const Aff ex = Aff{dpp_d<0x138>(1.0, inc.a), dpp_d<0x138>(0.0, inc.b)};
+    double v = ex.b;                                   // y_{-1} = 0
+    for (int k = k0; k < k1; k++) {
+        const long long q = at(k);
+        v = fma(up[q], v, lo[q]);
+        y[q] = v;
+    }
 }
 
 // phi = clamp((y_1 + y_2) / 2, -M, M)
