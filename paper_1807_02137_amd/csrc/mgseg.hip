@@ -1259,12 +1259,13 @@ void aos_step(mgseg_ctx *c, double tau_hat)
     A.model = c->p.model; A.scaled = c->p.scaled; A.n = c->n; A.m = c->m;
     A.uA = uA; A.uB = uB; A.uC = uC; A.uD = uD; A.r = r;
     hipLaunchKernelGGL(k_aos_coef, grid2(c->n, c->m), dim3(256), 0, c->s, A);
-    // columns: m lines of n cells (stride m); rows: n lines of m cells (contiguous), y_2 over uD
-    hipLaunchKernelGGL(k_aos_lines, dim3((c->m + 15) / 16), dim3(1024), 0, c->s, uA, uB, r, y1, c->m, c->n, 1LL,
+    // columns: m lines of n cells (stride m), y_1 to its own plane; rows: n lines of m cells
+    // (contiguous), y_2 over uA (free once the columns are done)
+    hipLaunchKernelGGL(k_aos_lines<8>, dim3((c->m + 3) / 4), dim3(256), 0, c->s, uA, uB, r, y1, c->m, c->n, 1LL,
                        (long long)c->m);
-    hipLaunchKernelGGL(k_aos_lines, dim3((c->n + 15) / 16), dim3(1024), 0, c->s, uC, uD, r, uD, c->n, c->m,
+    hipLaunchKernelGGL(k_aos_lines<8>, dim3((c->n + 3) / 4), dim3(256), 0, c->s, uC, uD, r, uA, c->n, c->m,
                        (long long)c->m, 1LL);
-    hipLaunchKernelGGL(k_aos_combine, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, c->s, c->phi64, y1, uD, N,
+    hipLaunchKernelGGL(k_aos_combine, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, c->s, c->phi64, y1, uA, N,
                        c->p.M);
     update_c(c);
     hipLaunchKernelGGL(k_eta, dim3(nb), dim3(256), 0, c->s, c->phi64, c->prev64, N, c->part + 4 * RED_BLOCKS);

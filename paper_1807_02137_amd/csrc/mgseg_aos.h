@@ -79,9 +79,8 @@ __global__ void __launch_bounds__(256) k_aos_coef(AosArgs A)
 //     y -> P_k y + Q_k, a wave scan in line order gives the value entering
 //     its chunk, and the lane writes its cells' y.
 // The recursions inside a chunk are the sequential elimination; only the 6
-// scan levels compose maps.  A workgroup of 16 waves takes 16 neighbouring
-// lines, so that strided lines (columns of a row-major plane) share each
-// cache line between its waves.
+// scan levels compose maps.  A workgroup of 4 waves takes 4 neighbouring
+// lines.
 __device__ __forceinline__ Elim elim_step_d(double a, double c, double r) { return Elim{c, 0.0, -r, 0.0, a, -c}; }
 
 struct Aff {
@@ -113,8 +112,38 @@ __device__ __forceinline__ Elim shfl_elim(const Elim &e, int src)
                 shfl_d(e.m10, src)};
 }
 
-__global__ void __launch_bounds__(1024) k_aos_lines(double *up, double *lo, const double *r, double *y, int nlines,
-                                                    int len, long long ls, long long cs)
+// the elimination map of the chunk's steps (each row normalised by its diagonal)
+__device__ __forceinline__ Elim aos_step_map(double a, double b, double r)
+{
+    const double inv = 1.0 / (1.0 + a + b);
+    return elim_step_d(b * inv, a * inv, -r * inv);
+}
+// the chunk maps of the chunks after this one (lanes reversed, so that a later chunk sits on a
+// lower lane and is applied first; exclusive), applied to the end state: (P, Q) after the chunk
+__device__ __forceinline__ void aos_after(const Elim &E, int lane, double &P, double &Q)
+{
+    Elim R = shfl_elim(E, 63 - lane);
+    R = wave_scan_elim<64>(R);
+    const Elim id = elim_id();
+    R = Elim{dpp_d<0x138>(id.al, R.al), dpp_d<0x138>(id.b0, R.b0), dpp_d<0x138>(id.b1, R.b1),
+             dpp_d<0x138>(id.m00, R.m00), dpp_d<0x138>(id.m01, R.m01), dpp_d<0x138>(id.m10, R.m10)};
+    const Elim S = shfl_elim(R, 63 - lane);
+    P = S.m01;
+    Q = S.b1;
+}
+// the value entering each lane's chunk from the chunks' affine maps (exclusive, line order)
+__device__ __forceinline__ double aos_entering(const Aff &F)
+{
+    const Aff inc = wave_scan_aff(F);
+    return dpp_d<0x138>(0.0, inc.b);                  // y_{-1} = 0
+}
+
+// Each pass over a chunk reads its cells in blocks of G whose loads are issued
+// together before any of the block's stores (the recursion itself is a chain
+// in registers), so that one memory latency is paid per block, not per cell.
+template <int G>
+__global__ void __launch_bounds__(256) k_aos_lines(double *up, double *lo, const double *r, double *y, int nlines,
+                                                   int len, long long ls, long long cs)
 {
     const int lane = threadIdx.x & 63;
     const int line = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
@@ -123,47 +152,71 @@ __global__ void __launch_bounds__(1024) k_aos_lines(double *up, double *lo, cons
     const int C = (len + 63) / 64;
     const int k0 = min(lane * C, len), k1 = min(k0 + C, len);
     auto at = [&](int k) { return base + (long long)k * cs; };
+    double a[G], b[G], rv[G];
+    // backward over the chunk in blocks: k = kb, kb - 1, ..., kb - G + 1
+    auto load_back = [&](int kb, bool with_r) {
+#pragma unroll
+        for (int j = 0; j < G; j++) {
+            const int k = kb - j;
+            if (k >= k0) {
+                const long long q = at(k);
+                a[j] = up[q]; b[j] = lo[q];
+                if (with_r) rv[j] = r[q];
+            }
+        }
+    };
     // 1. the chunk's elimination map, from its last cell to its first
     Elim E = elim_id();
-    for (int k = k1 - 1; k >= k0; k--) {
-        const long long q = at(k);
-        const double a = up[q], b = lo[q];
-        const double inv = 1.0 / (1.0 + a + b);
-        E = elim_comp(elim_step_d(b * inv, a * inv, -r[q] * inv), E);
+    for (int kb = k1 - 1; kb >= k0; kb -= G) {
+        load_back(kb, true);
+#pragma unroll
+        for (int j = 0; j < G; j++)
+            if (kb - j >= k0) E = elim_comp(aos_step_map(a[j], b[j], rv[j]), E);
     }
-    // 2. the maps of the chunks after this one, composed (lanes reversed, so that a later
-    //    chunk sits on a lower lane and is applied first), exclusive
-    Elim R = shfl_elim(E, 63 - lane);
-    R = wave_scan_elim<64>(R);
-    const Elim id = elim_id();
-    R = Elim{dpp_d<0x138>(id.al, R.al), dpp_d<0x138>(id.b0, R.b0), dpp_d<0x138>(id.b1, R.b1),
-             dpp_d<0x138>(id.m00, R.m00), dpp_d<0x138>(id.m01, R.m01), dpp_d<0x138>(id.m10, R.m10)};
-    const Elim S = shfl_elim(R, 63 - lane);
-    // 3. the backward recursion over the chunk from the state after it (beyond the line's end: P = Q = 0)
-    double P = S.m01, Q = S.b1;
-    for (int k = k1 - 1; k >= k0; k--) {
-        const long long q = at(k);
-        const double a = up[q], b = lo[q];
-        const double d = 1.0 + a + b;
-        const double inv = 1.0 / (d - a * P);
-        P = b * inv;
-        Q = fma(a, Q, r[q]) * inv;
-        up[q] = P;
-        lo[q] = Q;
+    // 2. the state after the chunk; 3. the backward recursion, P over up and Q over lo
+    double P, Q;
+    aos_after(E, lane, P, Q);
+    for (int kb = k1 - 1; kb >= k0; kb -= G) {
+        load_back(kb, true);
+#pragma unroll
+        for (int j = 0; j < G; j++) {
+            const int k = kb - j;
+            if (k < k0) continue;
+            const double inv = 1.0 / (1.0 + a[j] + b[j] - a[j] * P);
+            Q = fma(a[j], Q, rv[j]) * inv;
+            P = b[j] * inv;
+            const long long q = at(k);
+            up[q] = P;
+            lo[q] = Q;
+        }
     }
     // 4. forward substitution: the chunk's affine map, the value entering it, the cells
+    auto load_fwd = [&](int kb) {
+#pragma unroll
+        for (int j = 0; j < G; j++) {
+            const int k = kb + j;
+            if (k < k1) {
+                const long long q = at(k);
+                a[j] = up[q]; b[j] = lo[q];
+            }
+        }
+    };
     Aff F{1.0, 0.0};
-    for (int k = k0; k < k1; k++) {
-        const long long q = at(k);
-        F = aff_comp(Aff{up[q], lo[q]}, F);
+    for (int kb = k0; kb < k1; kb += G) {
+        load_fwd(kb);
+#pragma unroll
+        for (int j = 0; j < G; j++)
+            if (kb + j < k1) F = aff_comp(Aff{a[j], b[j]}, F);
     }
-    const Aff inc = wave_scan_aff(F);
-    const Aff ex = Aff{dpp_d<0x138>(1.0, inc.a), dpp_d<0x138>(0.0, inc.b)};
-    double v = ex.b;                                   // y_{-1} = 0
-    for (int k = k0; k < k1; k++) {
-        const long long q = at(k);
-        v = fma(up[q], v, lo[q]);
-        y[q] = v;
+    double v = aos_entering(F);
+    for (int kb = k0; kb < k1; kb += G) {
+        load_fwd(kb);
+#pragma unroll
+        for (int j = 0; j < G; j++) {
+            if (kb + j >= k1) continue;
+            v = fma(a[j], v, b[j]);
+            y[at(kb + j)] = v;
+        }
     }
 }
 
