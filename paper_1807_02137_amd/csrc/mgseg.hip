@@ -80,7 +80,7 @@ struct mgseg_ctx {
     float *pred = nullptr;          // network input and output of mgseg_predict_phi0 (first call)
     double *aos = nullptr;          // six n x m FP64 planes of the AOS solver (first call)
     double *lfa = nullptr;          // partials of mgseg_smoothing_rates (first call)
-    mgseg_schedule sched{64, 0, 1}; // launch schedule (mgseg_set_schedule, mgseg_tune)
+    mgseg_schedule sched{64, 0, 1, 1}; // launch schedule (mgseg_set_schedule, mgseg_tune)
     hipError_t err = hipSuccess;
     bool oom = false;
     // one V-cycle captured as a HIP graph (replayed on s); cap: private capture stream
@@ -310,6 +310,7 @@ void launch_sweep(mgseg_ctx *c, int l, int s, const float *phi_old, float *phi_n
     const bool cfm = devm(c) && L.cf != nullptr;
     A.cf = cfm ? (cm ? L.cf_cm : L.cf) : nullptr;
     A.qd = qd;
+    A.split = 0; A.nb_old = nullptr;
     A.pitch = cm ? L.pcm : L.prm;
     A.lpitch = A.pitch;
     A.nl = cm ? L.m : L.n;
@@ -350,10 +351,19 @@ void launch_sweep(mgseg_ctx *c, int l, int s, const float *phi_old, float *phi_n
         if (cfm) MG_SWEEP2_CF(NT, true);   \
         else MG_SWEEP2_CF(NT, false);  \
     } while (0)
+    // a forward sweep written in its own layout may run as two launches (the bands' first three
+    // lines, then their fourth lines reading the final neighbours), with no recomputed line
+    const bool split = c->sched.split_long && !rev && !tout && phi_new;
 #define MG_SWEEP_LONG_CF(CF)                                                                                    \
     do {                                                                                                        \
         if (rev) hipLaunchKernelGGL((k_sweep_long<1024, true, CF>), dim3(bands), dim3(1024), llds, c->s, A);   \
-        else hipLaunchKernelGGL((k_sweep_long<1024, false, CF>), dim3(bands), dim3(1024), llds, c->s, A);      \
+        else if (split) {                                                                                       \
+            LineArgs A1 = A, A2 = A;                                                                            \
+            A1.split = 1;                                                                                       \
+            A2.split = 2; A2.nb_old = phi_new;                                                                  \
+            hipLaunchKernelGGL((k_sweep_long<1024, false, CF>), dim3(bands), dim3(1024), llds, c->s, A1);      \
+            hipLaunchKernelGGL((k_sweep_long<1024, false, CF>), dim3(bands), dim3(1024), llds, c->s, A2);      \
+        } else hipLaunchKernelGGL((k_sweep_long<1024, false, CF>), dim3(bands), dim3(1024), llds, c->s, A);    \
     } while (0)
 #define MG_SWEEP_LONG()                \
     do {                               \
@@ -1462,11 +1472,12 @@ mgseg_status mgseg_get_schedule(mgseg_ctx *c, mgseg_schedule *out)
 mgseg_status mgseg_set_schedule(mgseg_ctx *c, const mgseg_schedule *sc)
 {
     if (!c || !sc || sc->lds_side < 0 || sc->line_threads < 0 || sc->line_threads > 1 || sc->graph < 0 ||
-        sc->graph > 1)
+        sc->graph > 1 || sc->split_long < 0 || sc->split_long > 1)
         return MGSEG_E_ARG;
     mgseg_status st = sync_status(c);
     if (st != MGSEG_OK) return st;
-    const bool relaunch = sc->lds_side != c->sched.lds_side || sc->line_threads != c->sched.line_threads;
+    const bool relaunch = sc->lds_side != c->sched.lds_side || sc->line_threads != c->sched.line_threads ||
+                          sc->split_long != c->sched.split_long;
     c->sched = *sc;
     // a captured cycle holds the old launches
     if (relaunch && c->gexec) {
@@ -1489,21 +1500,25 @@ mgseg_status mgseg_tune(mgseg_ctx *c, int trial_cycles, mgseg_schedule *best_out
     mgseg_schedule best = start;
     double best_ms = 1e300;
     const int sides[] = {0, 16, 32, 64};
+    const bool has_long = c->n > 1024 || c->m > 1024;
+    std::vector<mgseg_schedule> cands;
     for (int side : sides)
         for (int lt = 0; lt <= 1; lt++)
-            for (int g = 0; g <= 1; g++) {
-                const mgseg_schedule cand{side, lt, g};
-                st = mgseg_set_schedule(c, &cand);
-                if (st == MGSEG_OK) st = mgseg_set_state(c, saved.data(), bytes);
-                double rel = 0.0;
-                if (st == MGSEG_OK) st = one_cycle(c, &rel);    // untimed: the capture of a graph
-                if (st != MGSEG_OK && st != MGSEG_E_NONFINITE) break;
-                auto t0 = std::chrono::steady_clock::now();
-                for (int k = 0; k < trial_cycles && st == MGSEG_OK; k++) st = one_cycle(c, &rel);
-                const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0)
-                                      .count() / trial_cycles;
-                if (st == MGSEG_OK && ms < best_ms) { best_ms = ms; best = cand; }
-            }
+            for (int g = 0; g <= 1; g++)
+                for (int sp = 0; sp <= (has_long ? 1 : 0); sp++) cands.push_back(mgseg_schedule{side, lt, g, sp});
+    for (const mgseg_schedule &cand : cands) {
+        st = mgseg_set_schedule(c, &cand);
+        if (st == MGSEG_OK) st = mgseg_set_state(c, saved.data(), bytes);
+        double rel = 0.0;
+        if (st == MGSEG_OK) st = one_cycle(c, &rel);    // untimed: the capture of a graph
+        if (st != MGSEG_OK && st != MGSEG_E_NONFINITE) break;
+        auto t0 = std::chrono::steady_clock::now();
+        for (int k = 0; k < trial_cycles && st == MGSEG_OK; k++) st = one_cycle(c, &rel);
+        const double ms =
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count() / trial_cycles;
+        if (st == MGSEG_OK && ms < best_ms) { best_ms = ms; best = cand; }
+        if (st != MGSEG_OK && st != MGSEG_E_NONFINITE) break;
+    }
     // the solve continues from where it stood, with the fastest schedule
     mgseg_status st2 = mgseg_set_schedule(c, best_ms < 1e300 ? &best : &start);
     if (st2 == MGSEG_OK) st2 = mgseg_set_state(c, saved.data(), bytes);

@@ -109,7 +109,12 @@ struct LineArgs {
     int tpitch;                         //   cell q of line r at tout[q * tpitch + r]
     const double *area;                 // Rada-Chen area term (null: 0)
     const float4 *cf;                   // frozen scaled face coefficients (sweeps with CF; fit null)
-    const float *qd;                    // NEWT: the Newton term Q' added to each cell's diagonal (null: none)
+    const float *qd = nullptr;          // NEWT: the Newton term Q' added to each cell's diagonal (null: none)
+    // long lines, forward sweeps: 0 every line of a band in one launch; 1 the band's first
+    // three lines only; 2 its fourth line only, its cross-line neighbours (final after the
+    // split-1 launch) read from nb_old
+    int split = 0;
+    const float *nb_old = nullptr;
     int pitch, lpitch, nl, ml;
     float kap, e2, M, eps;
     int bit, scaled;
@@ -782,8 +787,9 @@ __device__ __forceinline__ LineRows line_rows(const LineArgs &A, int r, bool up_
     R.F = A.F ? A.F + ro : nullptr;
     R.lo = A.lo ? A.lo + ro : nullptr;
     R.hi = A.lo ? A.hi + ro : nullptr;
-    R.vu = ru >= 0 && ru < nl && !up_fresh ? A.phi_old + (long long)ru * P : nullptr;
-    R.vd = rd >= 0 && rd < nl && !dn_fresh ? A.phi_old + (long long)rd * P : nullptr;
+    const float *nbs = A.nb_old ? A.nb_old : A.phi_old;
+    R.vu = ru >= 0 && ru < nl && !up_fresh ? nbs + (long long)ru * P : nullptr;
+    R.vd = rd >= 0 && rd < nl && !dn_fresh ? nbs + (long long)rd * P : nullptr;
     R.cf = A.cf ? A.cf + ro : nullptr;
     R.qd = A.qd ? A.qd + ro : nullptr;
     R.lab = A.lab + (long long)r * A.lpitch;
@@ -1491,6 +1497,9 @@ __device__ __forceinline__ void long_band(const LineArgs &A, int b, float *ring,
         int r; bool redundant, up_fresh, dn_fresh;
         band_step<REV>(r0, nl, st, r, redundant, up_fresh, dn_fresh);
         if (r < 0 || r >= nl) continue;
+        // a split sweep: the first three lines, or the fourth with both neighbours final in memory
+        if ((A.split == 1 && st >= 3) || (A.split == 2 && st != 4)) continue;
+        if (A.split == 2) { up_fresh = false; dn_fresh = false; }
         const bool has_up = REV ? r + 1 < nl : r > 0, has_dn = REV ? r > 0 : r + 1 < nl;
         const LineRows R = line_rows<REV>(A, r, up_fresh, dn_fresh);
         // steps 1 and 4 end a pair of own lines (forward: 0,1 and 2,3; reverse: 3,2 and 1,0)

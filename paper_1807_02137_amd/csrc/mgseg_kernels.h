@@ -1168,7 +1168,7 @@ __global__ void __launch_bounds__(NT) k_coarse_smooth(CoarseArgs G)
     LineArgs C, R, T;
     C.psi = psi; C.w = w; C.fit = dev ? nullptr : fit; C.F = F; C.lab = lab; C.lo = lo; C.hi = hi;
     C.skip = nullptr; C.tout = nullptr; C.tpitch = 0; C.area = G.area; C.pitch = m; C.lpitch = m; C.cf = nullptr;
-    C.qd = nullptr;
+    C.qd = nullptr; C.split = 0; C.nb_old = nullptr;
     C.nl = n; C.ml = m; C.kap = G.kap; C.e2 = G.e2; C.M = G.M; C.eps = (float)G.eps; C.scaled = G.scaled;
     C.run_max = G.run_max;
     C.phi_old = P0; C.phi_new = nullptr; C.bit = 0;

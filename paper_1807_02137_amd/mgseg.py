@@ -43,7 +43,8 @@ class _Params(C.Structure):
 
 
 class _Schedule(C.Structure):
-    _fields_ = [("lds_side", C.c_int32), ("line_threads", C.c_int32), ("graph", C.c_int32)]
+    _fields_ = [("lds_side", C.c_int32), ("line_threads", C.c_int32), ("graph", C.c_int32),
+                ("split_long", C.c_int32)]
 
 
 class _Stats(C.Structure):
@@ -289,8 +290,8 @@ class Solver:
         _check(self.L.mgseg_get_schedule(self.ctx, C.byref(sc)), "mgseg_get_schedule")
         return {k: getattr(sc, k) for k, _ in _Schedule._fields_}
 
-    def set_schedule(self, lds_side=64, line_threads=0, graph=1):
-        sc = _Schedule(lds_side, line_threads, graph)
+    def set_schedule(self, lds_side=64, line_threads=0, graph=1, split_long=1):
+        sc = _Schedule(lds_side, line_threads, graph, split_long)
         _check(self.L.mgseg_set_schedule(self.ctx, C.byref(sc)), "mgseg_set_schedule")
 
     def tune(self, trial_cycles=2):

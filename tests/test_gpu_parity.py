@@ -120,7 +120,7 @@ def test_vcycle_trajectory():
         flips = int(((pg > 0) != (po > 0)).sum())
         say(f"cycle {k}: rel gpu {rg:.3e} oracle {ro:.3e} max|dphi| {np.abs(pg - po).max():.3e} flips {flips}")
         assert abs(rg - ro) <= 1e-3 * ro
-        assert np.abs(pg - po)[(pg > 0) == (po > 0)].max() <= 1e-4
+        assert np.abs(pg - po).max() <= 1e-4
     assert flips <= 2
     s.close()
 
@@ -141,7 +141,7 @@ def test_solve_parity(seed):
     pg, po = s.phi().cpu().numpy(), o.get("phi")
     agree = (pg > 0) == (po > 0)
     flips = int((~agree).sum())
-    dmax = float(np.abs(pg - po)[agree].max())
+    dmax = float(np.abs(pg - po).max())
     say(f"seed {seed}: gpu {cyc} cycles rel {rel:.2e}; oracle {k} cycles; flips {flips} max|dphi| {dmax:.3e}")
     assert ok and k > 0
     assert flips <= max(1, int(1e-4 * pg.size))
@@ -163,7 +163,7 @@ def test_solve_parity_rada_chen(seed):
     pg, po = s.phi().cpu().numpy(), o.get("phi")
     agree = (pg > 0) == (po > 0)
     flips = int((~agree).sum())
-    dmax = float(np.abs(pg - po)[agree].max())
+    dmax = float(np.abs(pg - po).max())
     say(f"gpu {len(hg)} cycles rel {hg[-1]:.2e}; oracle {k} cycles; flips {flips} max|dphi| {dmax:.3e}")
     assert hg[-1] <= 1e-6 and k > 0
     assert flips <= max(1, int(1e-4 * pg.size))
@@ -188,7 +188,7 @@ def test_solve_parity_chan_vese(seed):
     pg, po = s.phi().cpu().numpy(), o.get("phi")
     agree = (pg > 0) == (po > 0)
     flips = int((~agree).sum())
-    dmax = float(np.abs(pg - po)[agree].max())
+    dmax = float(np.abs(pg - po).max())
     say(f"gpu {len(hg)} cycles rel {hg[-1]:.2e}; oracle {k} cycles; flips {flips} max|dphi| {dmax:.3e}; "
         f"foreground {(pg > 0).mean():.3f}")
     assert hg[-1] <= 1e-6 and k > 0
@@ -216,7 +216,7 @@ def test_solve_parity_gslex(seed):
     pg, po = s.phi().cpu().numpy(), o.get("phi")
     agree = (pg > 0) == (po > 0)
     flips = int((~agree).sum())
-    dmax = float(np.abs(pg - po)[agree].max())
+    dmax = float(np.abs(pg - po).max())
     h2 = mgseg.Solver(inst.image, inst.markers, mgseg.Params(levels=6))
     c2, _, _ = h2.solve(1e-6, 60)
     say(f"gpu {len(hg)} cycles rel {hg[-1]:.2e}; oracle {k} cycles; flips {flips} max|dphi| {dmax:.3e}; "
@@ -246,7 +246,7 @@ def test_solve_parity_ragged_shapes(shape):
     pg, po = s.phi().cpu().numpy(), o.get("phi")
     agree = (pg > 0) == (po > 0)
     flips = int((~agree).sum())
-    dmax = float(np.abs(pg - po)[agree].max()) if agree.any() else 0.0
+    dmax = float(np.abs(pg - po).max())
     say(f"gpu {len(hg)} cycles rel {hg[-1]:.2e}; oracle {k} cycles; flips {flips} max|dphi| {dmax:.3e}")
     assert hg[-1] <= 1e-6 and k > 0
     assert flips <= 1
@@ -319,7 +319,7 @@ def test_solve_parity_1024_thread_lines(shape):
     pg, po = s.phi().cpu().numpy(), o.get("phi")
     agree = (pg > 0) == (po > 0)
     flips = int((~agree).sum())
-    dmax = float(np.abs(pg - po)[agree].max())
+    dmax = float(np.abs(pg - po).max())
     say(f"gpu {len(hg)} cycles rel {hg[-1]:.2e}; oracle {k} cycles; flips {flips} max|dphi| {dmax:.3e}")
     assert hg[-1] <= 1e-6 and k > 0
     assert flips <= 1
@@ -397,7 +397,7 @@ def test_solve_parity_hybrid1(seed):
     pg, po = s.phi().cpu().numpy(), o.get("phi")
     agree = (pg > 0) == (po > 0)
     flips = int((~agree).sum())
-    dmax = float(np.abs(pg - po)[agree].max()) if agree.any() else 0.0
+    dmax = float(np.abs(pg - po).max())
     say(f"gpu {len(hg)} cycles {np.round(hg, 4)}; oracle {k} cycles {np.round(hist, 4)}; flips {flips} max|dphi| {dmax:.3e}")
     assert hg[-1] <= 1e-6 and k > 0 and abs(len(hg) - k) <= 1
     assert flips <= 1 and dmax <= 1e-4
@@ -421,7 +421,7 @@ def test_solve_parity_standard_smoothers(smoother, model):
     pg, po = s.phi().cpu().numpy(), o.get("phi")
     agree = (pg > 0) == (po > 0)
     flips = int((~agree).sum())
-    dmax = float(np.abs(pg - po)[agree].max())
+    dmax = float(np.abs(pg - po).max())
     say(f"gpu {len(hg)} cycles {np.round(hg[:8], 4)}; oracle {k} cycles {np.round(hist[:8], 4)}; "
         f"flips {flips} max|dphi| {dmax:.3e}")
     assert hg[-1] <= 1e-6 and k > 0 and abs(len(hg) - k) <= 1
@@ -515,9 +515,9 @@ def test_solve_parity_three_cell_cut(seed):
     pg, po = s.phi().cpu().numpy(), o.get("phi")
     agree = (pg > 0) == (po > 0)
     flips = int((~agree).sum())
-    say(f"gpu {len(hg)} cycles; oracle {k}; flips {flips} max|dphi| {np.abs(pg - po)[agree].max():.3e}")
+    say(f"gpu {len(hg)} cycles; oracle {k}; flips {flips} max|dphi| {np.abs(pg - po).max():.3e}")
     assert hg[-1] <= 1e-6 and k > 0 and flips <= 1
-    assert np.abs(pg - po)[agree].max() <= 1e-4
+    assert np.abs(pg - po).max() <= 1e-4
     s.close()
 
 
@@ -577,7 +577,7 @@ def test_c2_full_size_matches_the_oracle_solve():
     """The 1024x1024 benchmark image (seed 2000, 9 grids) solved to 1e-6 on the
     GPU against the oracle's own solve of it (tests/golden/make_fullsize.py):
     the cycle count, the segmentation (at most 0.01 % of pixels differ) and phi
-    at 4096 seeded pixels (|dphi| <= 1e-4 where the masks agree)."""
+    at 4096 seeded pixels (|dphi| <= 1e-4 at every sample)."""
     say("case full size 1024x1024 against the oracle's solve")
     ref = np.load(os.path.join(GOLDEN, "c2_oracle_1024.npz"))
     inst = synth.config2(2000, 1024)
@@ -587,8 +587,7 @@ def test_c2_full_size_matches_the_oracle_solve():
     mask_o = np.unpackbits(ref["mask"])[: phi.size].reshape(phi.shape).astype(bool)
     flips = int(((phi > 0) != mask_o).sum())
     si, sj = ref["si"], ref["sj"]
-    agree = (phi[si, sj] > 0) == mask_o[si, sj]
-    d = np.abs(phi[si, sj] - ref["phi_s"])[agree].max()
+    d = np.abs(phi[si, sj] - ref["phi_s"]).max()
     say(f"gpu {cyc} cycles rel {rel:.3e}; oracle {int(ref['cycles'])} cycles; flips {flips}; max|dphi| {d:.3e}")
     assert ok and abs(cyc - int(ref["cycles"])) <= 1
     assert flips <= 1e-4 * phi.size
@@ -613,8 +612,7 @@ def test_c4_first_two_cycles_match_the_oracle():
     mask_o = np.unpackbits(ref["mask"])[: phi.size].reshape(phi.shape).astype(bool)
     flips = int(((phi > 0) != mask_o).sum())
     si, sj = ref["si"], ref["sj"]
-    agree = (phi[si, sj] > 0) == mask_o[si, sj]
-    d = np.abs(phi[si, sj] - ref["phi_s"])[agree].max()
+    d = np.abs(phi[si, sj] - ref["phi_s"]).max()
     say(f"gpu {np.round(hist, 5)} oracle {np.round(ref['hist'], 5)} flips {flips} max|dphi| {d:.3e}")
     assert np.all(np.abs(np.array(hist) - ref["hist"]) <= 1e-3 * ref["hist"])
     assert flips <= 1e-4 * phi.size
@@ -687,7 +685,7 @@ def test_batch_large_coarsest_matches_oracle():
     pg, po = s.phi().cpu().numpy(), o.get("phi")
     agree = (pg > 0) == (po > 0)
     flips = int((~agree).sum())
-    dmax = float(np.abs(pg - po)[agree].max())
+    dmax = float(np.abs(pg - po).max())
     say(f"gpu {cg} cycles rel {rg:.2e}; oracle {k} cycles; flips {flips} max|dphi| {dmax:.3e}")
     assert okg and k > 0 and flips <= 1 and dmax <= 1e-4
     s.close()

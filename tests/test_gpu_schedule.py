@@ -1,8 +1,9 @@
 """The launch schedules of a context (mgseg_set_schedule) compute the same bits,
 and the autotuner (mgseg_tune) keeps the solve where it stood: every schedule
 of the tuner's set, from the same start, gives a finest phi identical to the
-default schedule's after three V-cycles (config-1 image, and a 256 x 384 image
-whose lines take the two-half and single-half sweep kernels), and tuning
+default schedule's after three V-cycles (config-1 image, a 256 x 384 image
+whose lines take the two-half and single-half sweep kernels, and a 64 x 1280
+image whose rows take the long-line kernel, split or not), and tuning
 leaves phi, the cycle count and the residual unchanged."""
 import itertools
 import sys
@@ -18,7 +19,7 @@ if not torch.cuda.is_available():
 
 from paper_1807_02137_amd import mgseg, synth  # noqa: E402
 
-SCHEDULES = list(itertools.product((0, 16, 32, 64), (0, 1), (0, 1)))
+SCHEDULES = list(itertools.product((0, 16, 32, 64), (0, 1), (0, 1), (0, 1)))
 
 
 def say(*a):
@@ -37,7 +38,8 @@ def run(inst, levels, sched, cycles=3, **kw):
     return phi
 
 
-@pytest.mark.parametrize("shape,levels,smoother", [((128, 128), 6, 0), ((256, 384), 6, 0), ((128, 128), 6, 3)])
+@pytest.mark.parametrize("shape,levels,smoother", [((128, 128), 6, 0), ((256, 384), 6, 0), ((128, 128), 6, 3),
+                                                   ((64, 1280), 5, 0)])
 def test_every_schedule_gives_the_same_bits(shape, levels, smoother):
     say("case schedules", shape, "smoother", smoother)
     inst = synth.shapes_instance(11, shape[0], shape[1], 4, 1.0, 0.05, 4, "sched", min_count=3)
