@@ -259,7 +259,7 @@ mgseg_status mgseg_smoothing_rates(mgseg_ctx *c, int smoother, double *out5, flo
  *                 most 512 cells)
  *   graph         1: each cycle is replayed from a captured HIP graph
  *                 (default); 0: launched eagerly
- *   split_long    lines longer than 1024 cells, forward sweeps written in
+ *   split_long    lines longer than 512 cells, forward sweeps written in
  *                 their own layout: 1 (default) two launches, the first
  *                 three lines of every band of four, then the fourth lines
  *                 reading their final neighbours; 0 one launch that
@@ -277,7 +277,7 @@ mgseg_status mgseg_set_schedule(mgseg_ctx *c, const mgseg_schedule *s);
 
 /* Autotuner: times trial_cycles V-cycles (after one untimed) of every
  * schedule of lds_side in {0, 16, 32, 64} x line_threads in {0, 1} x graph
- * in {0, 1} (x split_long in {0, 1} where a side exceeds 1024 cells) from
+ * in {0, 1} (x split_long in {0, 1} where a side exceeds 512 cells) from
  * the context's current state, keeps the fastest, and
  * restores the state (the solve continues where it stood; the cycle count
  * is unchanged).  Outputs (each may be null): the chosen schedule and its

@@ -51,7 +51,11 @@ def symbol(coef, new, a1, a2, q=0.0):
     num = sum(cf[k] * E[k] for k in COUPLINGS if k not in new)
     den = S - sum(cf[k] * E[k] for k in COUPLINGS if k in new)
     num = np.abs(num) if not np.isscalar(num) else abs(num) * np.ones_like(a1)
-    return num / np.abs(den)
+    den = np.abs(den) * np.ones_like(a1)
+    # a mode with no coupling at all (both sums empty: a pixel without faces) is not amplified
+    out = np.zeros_like(num)
+    np.divide(num, den, out=out, where=den > 0)
+    return np.where((den == 0) & (num > 0), np.inf, out)
 
 
 def rate(coef, new, n: int = 128, strict: bool = True, q: float = 0.0) -> float:

@@ -331,10 +331,19 @@ void launch_sweep(mgseg_ctx *c, int l, int s, const float *phi_old, float *phi_n
         return;
     }
     const size_t lds = sweep_lds_bytes(ml), llds = long_lds_bytes<1024>(ml), lds2 = sweep2_lds_bytes(ml);
+    // a forward sweep written in its own layout may run as two launches (the bands' first three
+    // lines, then their fourth lines reading the final neighbours), with no recomputed line
+    const bool split = c->sched.split_long && !rev && !tout && phi_new;
 #define MG_SWEEP_CF(NT, CF)                                                                       \
     do {                                                                                              \
         if (rev) hipLaunchKernelGGL((k_sweep<NT, true, CF>), dim3(bands), dim3(NT), lds, c->s, A); \
-        else hipLaunchKernelGGL((k_sweep<NT, false, CF>), dim3(bands), dim3(NT), lds, c->s, A);    \
+        else if (split) {                                                                             \
+            LineArgs A1 = A, A2 = A;                                                                  \
+            A1.split = 1;                                                                             \
+            A2.split = 2; A2.nb_old = phi_new;                                                        \
+            hipLaunchKernelGGL((k_sweep<NT, false, CF>), dim3(bands), dim3(NT), lds, c->s, A1);      \
+            hipLaunchKernelGGL((k_sweep<NT, false, CF>), dim3(bands), dim3(NT), lds, c->s, A2);      \
+        } else hipLaunchKernelGGL((k_sweep<NT, false, CF>), dim3(bands), dim3(NT), lds, c->s, A);    \
     } while (0)
 #define MG_SWEEP(NT)                   \
     do {                               \
@@ -351,9 +360,6 @@ void launch_sweep(mgseg_ctx *c, int l, int s, const float *phi_old, float *phi_n
         if (cfm) MG_SWEEP2_CF(NT, true);   \
         else MG_SWEEP2_CF(NT, false);  \
     } while (0)
-    // a forward sweep written in its own layout may run as two launches (the bands' first three
-    // lines, then their fourth lines reading the final neighbours), with no recomputed line
-    const bool split = c->sched.split_long && !rev && !tout && phi_new;
 #define MG_SWEEP_LONG_CF(CF)                                                                                    \
     do {                                                                                                        \
         if (rev) hipLaunchKernelGGL((k_sweep_long<1024, true, CF>), dim3(bands), dim3(1024), llds, c->s, A);   \
@@ -1500,7 +1506,7 @@ mgseg_status mgseg_tune(mgseg_ctx *c, int trial_cycles, mgseg_schedule *best_out
     mgseg_schedule best = start;
     double best_ms = 1e300;
     const int sides[] = {0, 16, 32, 64};
-    const bool has_long = c->n > 1024 || c->m > 1024;
+    const bool has_long = c->n > 512 || c->m > 512;
     std::vector<mgseg_schedule> cands;
     for (int side : sides)
         for (int lt = 0; lt <= 1; lt++)

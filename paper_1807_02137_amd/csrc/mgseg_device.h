@@ -1292,7 +1292,11 @@ __device__ __forceinline__ void sweep_band(const LineArgs &A, int b, const RunBu
     const int nl = A.nl, ml = A.ml, t = threadIdx.x % NT;
     const int r0 = 4 * b;
     const bool pack = A.tout != nullptr && r0 + 3 < nl;
-    auto valid = [&](int st) { const int r = band_line<REV>(r0, st); return r >= 0 && r < nl; };
+    // a split sweep takes the band's first three lines, or its fourth with both neighbours in memory
+    auto valid = [&](int st) {
+        const int r = band_line<REV>(r0, st);
+        return r >= 0 && r < nl && !((A.split == 1 && st >= 3) || (A.split == 2 && st != 4));
+    };
     auto load = [&](int r, bool uf, bool df, CellIn &c) {
         if (t < ml) cell_load<REV, CF>(line_rows<REV>(A, r, uf, df), ml, t, c);
     };
@@ -1302,18 +1306,21 @@ __device__ __forceinline__ void sweep_band(const LineArgs &A, int b, const RunBu
     if (PF && st < 5) {
         int r; bool rdd, uf, df;
         band_step<REV>(r0, nl, st, r, rdd, uf, df);
+        if (A.split == 2) { uf = false; df = false; }
         load(r, uf, df, la);
     }
 #pragma nounroll
     while (st < 5) {
         int r; bool redundant, up_fresh, dn_fresh;
         band_step<REV>(r0, nl, st, r, redundant, up_fresh, dn_fresh);
+        if (A.split == 2) { up_fresh = false; dn_fresh = false; }
         int nx = st + 1;
         while (nx < 5 && !valid(nx)) nx++;
         if (PF) {
             if (nx < 5) {
                 int r2; bool rd2, uf2, df2;
                 band_step<REV>(r0, nl, nx, r2, rd2, uf2, df2);
+                if (A.split == 2) { uf2 = false; df2 = false; }
                 load(r2, uf2, df2, lb);
             }
         } else {
