@@ -290,8 +290,10 @@ void res64(mgseg_ctx *c)
 // column-major; phi_old -> phi_new in the layout of the sweep
 // bit: the label bit of the starred cells (default: the sweep's own; a bit no
 // label carries makes every cell a point)
+// scratch (reverse sweeps): a free plane in the sweep's line layout, which lets a long-line
+// sweep run split
 void launch_sweep(mgseg_ctx *c, int l, int s, const float *phi_old, float *phi_new, float *tout = nullptr,
-                  int tpitch = 0, int bit = -1, const float *qd = nullptr)
+                  int tpitch = 0, int bit = -1, const float *qd = nullptr, float *scratch = nullptr)
 {
     Level &L = c->lev[l];
     bool cm = s >= 2;
@@ -360,9 +362,16 @@ void launch_sweep(mgseg_ctx *c, int l, int s, const float *phi_old, float *phi_n
         if (cfm) MG_SWEEP2_CF(NT, true);   \
         else MG_SWEEP2_CF(NT, false);  \
     } while (0)
+    const bool split_rev = c->sched.split_long && rev && tout && scratch;
 #define MG_SWEEP_LONG_CF(CF)                                                                                    \
     do {                                                                                                        \
-        if (rev) hipLaunchKernelGGL((k_sweep_long<1024, true, CF>), dim3(bands), dim3(1024), llds, c->s, A);   \
+        if (rev && split_rev) {                                                                                 \
+            LineArgs A1 = A, A2 = A;                                                                            \
+            A1.split = 1; A1.nb_out = scratch;                                                                  \
+            A2.split = 2; A2.nb_old = scratch;                                                                  \
+            hipLaunchKernelGGL((k_sweep_long<1024, true, CF>), dim3(bands), dim3(1024), llds, c->s, A1);       \
+            hipLaunchKernelGGL((k_sweep_long<1024, true, CF>), dim3(bands), dim3(1024), llds, c->s, A2);       \
+        } else if (rev) hipLaunchKernelGGL((k_sweep_long<1024, true, CF>), dim3(bands), dim3(1024), llds, c->s, A);  \
         else if (split) {                                                                                       \
             LineArgs A1 = A, A2 = A;                                                                            \
             A1.split = 1;                                                                                       \
@@ -587,9 +596,9 @@ void outer(mgseg_ctx *c, int l)
         return;
     }
     launch_sweep(c, l, 0, L.P[0], L.P[1]);
-    launch_sweep(c, l, 1, L.P[1], nullptr, L.T[1], L.pcm);     // written column-major
+    launch_sweep(c, l, 1, L.P[1], nullptr, L.T[1], L.pcm, -1, nullptr, L.P[0]);   // written column-major
     launch_sweep(c, l, 2, L.T[1], L.T[2]);
-    launch_sweep(c, l, 3, L.T[2], nullptr, L.P[0], L.prm);     // written row-major
+    launch_sweep(c, l, 3, L.T[2], nullptr, L.P[0], L.prm, -1, nullptr, L.T[1]);   // written row-major
     chk(c);
 }
 

@@ -115,6 +115,7 @@ struct LineArgs {
     // split-1 launch) read from nb_old
     int split = 0;
     const float *nb_old = nullptr;
+    float *nb_out = nullptr;            // split 1 of a reverse sweep: its first and third lines, line layout
     int pitch, lpitch, nl, ml;
     float kap, e2, M, eps;
     int bit, scaled;
@@ -1525,7 +1526,16 @@ __device__ __forceinline__ void long_band(const LineArgs &A, int b, float *ring,
             }
             if (redundant) red[p] = v;
             else prev[p] = v;
+            if (A.nb_out && (st == 0 || st == 2)) A.nb_out[(long long)r * A.pitch + q] = v;
         };
+        // split 2 of a reverse sweep: the partner of the band's last pair from split 1
+        if (REV && A.split == 2 && pair_w) {
+#pragma nounroll
+            for (int k = 0; k < K; k++) {
+                const int p = k * NT + t;
+                if (p < ml) prev[p] = A.nb_old[(long long)(r0 + 1) * A.pitch + cell(p)];
+            }
+        }
         // starred masks of the whole line
 #pragma nounroll
         for (int k = 0; k < K; k++) {

@@ -3,8 +3,9 @@ and the autotuner (mgseg_tune) keeps the solve where it stood: every schedule
 of the tuner's set, from the same start, gives a finest phi identical to the
 default schedule's after three V-cycles (config-1 image, a 256 x 384 image
 whose lines take the two-half and single-half sweep kernels, and a 64 x 1280
-image whose rows take the long-line kernel and a 768 x 64 image whose
-columns take the 1024-thread kernel, split or not), and tuning
+image whose rows take the long-line kernel, a 1152 x 64 image whose columns
+do, and a 768 x 64 image whose columns take the 1024-thread kernel, split or
+not), and tuning
 leaves phi, the cycle count and the residual unchanged."""
 import itertools
 import sys
@@ -40,7 +41,7 @@ def run(inst, levels, sched, cycles=3, **kw):
 
 
 @pytest.mark.parametrize("shape,levels,smoother", [((128, 128), 6, 0), ((256, 384), 6, 0), ((128, 128), 6, 3),
-                                                   ((64, 1280), 5, 0), ((768, 64), 5, 0)])
+                                                   ((64, 1280), 5, 0), ((1152, 64), 5, 0), ((768, 64), 5, 0)])
 def test_every_schedule_gives_the_same_bits(shape, levels, smoother):
     say("case schedules", shape, "smoother", smoother)
     inst = synth.shapes_instance(11, shape[0], shape[1], 4, 1.0, 0.05, 4, "sched", min_count=3)
