@@ -86,14 +86,15 @@ typedef struct {
                             /* the collective update at every jump-set cell of the   */
                             /* cell and its neighbours except the one behind its     */
                             /* smallest coefficient (eight cell classes); needs      */
-                            /* mixed_precision = 1; 3: GSLINE-I (Sec. 3.2, eq.       */
+                            /* mixed_precision = 1 and columns of at most 1024       */
+                            /* cells (n <= 1024); 3: GSLINE-I (Sec. 3.2, eq.         */
                             /* system), one line system per column per outer         */
                             /* iteration (four column classes; needs                 */
-                            /* mixed_precision = 1); 4: NEWT-I (Sec. 3.2, eq.        */
-                            /* newtrc), GSLEX-I's pass with the derivative of the    */
-                            /* Rada-Chen area term on each diagonal (Spencer-Chen:   */
-                            /* the same as 1); 5 GSLEX-II, 6 GSLINE-II, 7 NEWT-II:   */
-                            /* the local variants, each pixel's (column's)           */
+                            /* mixed_precision = 1 and n <= 1024); 4: NEWT-I (Sec.   */
+                            /* 3.2, eq. newtrc), GSLEX-I's pass with the derivative  */
+                            /* of the Rada-Chen area term on each diagonal (Spencer- */
+                            /* Chen: the same as 1); 5 GSLEX-II, 6 GSLINE-II, 7      */
+                            /* NEWT-II: the local variants, each pixel's (column's)  */
                             /* coefficients refreshed from the current iterate where */
                             /* they are used, rows (columns) in four classes;        */
                             /* Spencer-Chen only (NEWT-II is then GSLEX-II),         */

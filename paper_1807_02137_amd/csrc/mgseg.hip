@@ -332,7 +332,8 @@ void launch_sweep(mgseg_ctx *c, int l, int s, const float *phi_old, float *phi_n
         if (c->err == hipSuccess) c->err = hipErrorInvalidValue;
         return;
     }
-    const size_t lds = sweep_lds_bytes(ml), llds = long_lds_bytes<1024>(ml), lds2 = sweep2_lds_bytes(ml);
+    const size_t lds = sweep_lds_bytes(ml), llds = long_lds_bytes<LONG_NT>(ml), lds2 = sweep2_lds_bytes(ml);
+    const size_t llds_s = long_lds_bytes<LONG_NT>(ml, false);   // a split long sweep: no line in LDS
     // a forward sweep written in its own layout may run as two launches (the bands' first three
     // lines, then their fourth lines reading the final neighbours), with no recomputed line
     const bool split = c->sched.split_long && !rev && !tout && phi_new;
@@ -367,18 +368,18 @@ void launch_sweep(mgseg_ctx *c, int l, int s, const float *phi_old, float *phi_n
     do {                                                                                                        \
         if (rev && split_rev) {                                                                                 \
             LineArgs A1 = A, A2 = A;                                                                            \
-            A1.split = 1; A1.nb_out = scratch;                                                                  \
-            A2.split = 2; A2.nb_old = scratch;                                                                  \
-            hipLaunchKernelGGL((k_sweep_long<1024, true, CF>), dim3(bands), dim3(1024), llds, c->s, A1);       \
-            hipLaunchKernelGGL((k_sweep_long<1024, true, CF>), dim3(bands), dim3(1024), llds, c->s, A2);       \
-        } else if (rev) hipLaunchKernelGGL((k_sweep_long<1024, true, CF>), dim3(bands), dim3(1024), llds, c->s, A);  \
+            A1.split = 1; A1.nb_out = scratch; A1.fresh = scratch;                                              \
+            A2.split = 2; A2.nb_old = scratch; A2.fresh = scratch;                                              \
+            hipLaunchKernelGGL((k_sweep_long<LONG_NT, true, CF>), dim3(bands), dim3(LONG_NT), llds_s, c->s, A1);       \
+            hipLaunchKernelGGL((k_sweep_long<LONG_NT, true, CF>), dim3(bands), dim3(LONG_NT), llds_s, c->s, A2);       \
+        } else if (rev) hipLaunchKernelGGL((k_sweep_long<LONG_NT, true, CF>), dim3(bands), dim3(LONG_NT), llds, c->s, A);  \
         else if (split) {                                                                                       \
             LineArgs A1 = A, A2 = A;                                                                            \
-            A1.split = 1;                                                                                       \
-            A2.split = 2; A2.nb_old = phi_new;                                                                  \
-            hipLaunchKernelGGL((k_sweep_long<1024, false, CF>), dim3(bands), dim3(1024), llds, c->s, A1);      \
-            hipLaunchKernelGGL((k_sweep_long<1024, false, CF>), dim3(bands), dim3(1024), llds, c->s, A2);      \
-        } else hipLaunchKernelGGL((k_sweep_long<1024, false, CF>), dim3(bands), dim3(1024), llds, c->s, A);    \
+            A1.split = 1; A1.fresh = phi_new;                                                                   \
+            A2.split = 2; A2.nb_old = phi_new; A2.fresh = phi_new;                                              \
+            hipLaunchKernelGGL((k_sweep_long<LONG_NT, false, CF>), dim3(bands), dim3(LONG_NT), llds_s, c->s, A1);      \
+            hipLaunchKernelGGL((k_sweep_long<LONG_NT, false, CF>), dim3(bands), dim3(LONG_NT), llds_s, c->s, A2);      \
+        } else hipLaunchKernelGGL((k_sweep_long<LONG_NT, false, CF>), dim3(bands), dim3(LONG_NT), llds, c->s, A);    \
     } while (0)
 #define MG_SWEEP_LONG()                \
     do {                               \
@@ -909,7 +910,8 @@ mgseg_status setup_check(const float *image_dev, int n, int m, int pitch, const 
     if (p->model == MGSEG_RADA_CHEN && k < 3) return MGSEG_E_ARG;   // the marker polygon needs an area (A1 > 0)
     if (p->nu1 < 0 || p->nu2 < 0 || p->coarse_iters < 0 || !(p->coarse_rtol >= 0.0) || !(p->M > 0.0) || !(p->eps > 0.0) || p->levels < 0 ||
         p->levels > MAXLEV || p->smoother < 0 || p->smoother > 7 || (p->smoother >= 2 && p->smoother != 4 && !p->mixed_precision) ||
-        (p->smoother >= 5 && (p->model != MGSEG_SPENCER_CHEN || (p->smoother == 6 && n > 1024))) ||
+        (p->smoother >= 5 && p->model != MGSEG_SPENCER_CHEN) ||
+        ((p->smoother == 2 || p->smoother == 3 || p->smoother == 6) && n > 1024) ||   // one workgroup per column system
         p->run_max < 0 ||
         !(p->sigma_g >= 0.0 && p->sigma_g <= 16.0))
         return MGSEG_E_ARG;
@@ -930,16 +932,16 @@ mgseg_status setup_check(const float *image_dev, int n, int m, int pitch, const 
     // lines longer than one workgroup keep the band's previous and recomputed
     // lines in LDS: the device must allow that much per workgroup
     if (std::max(n, m) > 1024) {
-        const size_t need = long_lds_bytes<1024>(std::max(n, m));   // dynamic; the wave totals are static
+        const size_t need = long_lds_bytes<LONG_NT>(std::max(n, m));   // dynamic; the wave totals are static
         int dev = 0, lds_max = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
             return MGSEG_E_HIP;
-        if (need + 2 * (1024 / 64) * sizeof(Ramp) > (size_t)lds_max) return MGSEG_E_SHAPE;
-        const void *fns[4] = {reinterpret_cast<const void *>(&k_sweep_long<1024, false, false>),
-                              reinterpret_cast<const void *>(&k_sweep_long<1024, true, false>),
-                              reinterpret_cast<const void *>(&k_sweep_long<1024, false, true>),
-                              reinterpret_cast<const void *>(&k_sweep_long<1024, true, true>)};
+        if (need + 2 * (LONG_NT / 64) * sizeof(Ramp) > (size_t)lds_max) return MGSEG_E_SHAPE;
+        const void *fns[4] = {reinterpret_cast<const void *>(&k_sweep_long<LONG_NT, false, false>),
+                              reinterpret_cast<const void *>(&k_sweep_long<LONG_NT, true, false>),
+                              reinterpret_cast<const void *>(&k_sweep_long<LONG_NT, false, true>),
+                              reinterpret_cast<const void *>(&k_sweep_long<LONG_NT, true, true>)};
         for (const void *fn : fns)
             if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)need) != hipSuccess)
                 return MGSEG_E_HIP;

@@ -115,7 +115,10 @@ struct LineArgs {
     // split-1 launch) read from nb_old
     int split = 0;
     const float *nb_old = nullptr;
-    float *nb_out = nullptr;            // split 1 of a reverse sweep: its first and third lines, line layout
+    float *nb_out = nullptr;            // split 1 of a reverse sweep: its three lines, line layout
+    // split long-line sweeps: the plane (line layout, pitch) holding the previous own line's final
+    // values, read in place of a copy in LDS (forward split 1: phi_new; reverse: nb_out / nb_old)
+    const float *fresh = nullptr;
     int pitch, lpitch, nl, ml;
     float kap, e2, M, eps;
     int bit, scaled;
@@ -158,12 +161,20 @@ __host__ __device__ inline int sweep_mask_words(int ml) { return (ml + 63) / 64;
 
 // Row buffer of lines longer than one workgroup: a ring of SLOTS positions
 // (two rounds of the line).  Only unit cells are stored; the successor's old
-// value sits beside each cell (RG_S), and a unit's new values go to RF_O.
+// value sits beside each cell (RG_S), and a unit's new values go to RF_O,
+// which shares the storage of RF_X: a unit's new values are written only by
+// its own solve, after that solve has read the unit's rows, and the one later
+// read of RF_X inside the solve (a cell of S = 0, held at its old value) finds
+// that value there, as the substitution leaves it (such cells occur in units
+// of more than three cells only in whole-line systems, which these lines do
+// not take).  Nine fields instead of ten let two workgroups share a CU.
 enum { RG_S = RB_FIELDS, RF_COUNT };
+constexpr int RING_FIELDS = RF_COUNT - 1;
 template <int SLOTS>
 struct RingBuf {
     float *p;
-    __device__ __forceinline__ float &at(int f, int q) const { return p[f * SLOTS + (q & (SLOTS - 1))]; }
+    __device__ __forceinline__ static constexpr int slot(int f) { return f == RF_O ? RF_X : (f == RG_S ? RF_O : f); }
+    __device__ __forceinline__ float &at(int f, int q) const { return p[slot(f) * SLOTS + (q & (SLOTS - 1))]; }
     __device__ __forceinline__ float sig_after(int last, int) const { return at(RG_S, last); }
     __device__ __forceinline__ float &y(int q) const { return at(RF_O, q); }
 };
@@ -1483,7 +1494,10 @@ __device__ __forceinline__ void sweep_band2(const LineArgs &A, int b, const RunB
 // it is final (cells of a unit that ends in the next round: one round
 // later).  LDS holds the previous own line (the fresh upstream neighbour,
 // prev) and the recomputed neighbour line (red), each cell at its visit
-// position, read and written only by the thread that owns the position.
+// position, read and written only by the thread that owns the position.  A
+// split sweep recomputes no line and reads the previous own line from the
+// plane it was written to (A.fresh; visible after the barrier that opens the
+// next line), so its LDS is the masks and the ring alone.
 // The transposed output of a full band goes out as float2 pairs of lines
 // (0, 1) and (2, 3), written when the pair's second line is done.  The
 // rounds are a loop, not unrolled: one copy of the round's code, and no
@@ -1500,6 +1514,7 @@ __device__ __forceinline__ void long_band(const LineArgs &A, int b, float *ring,
     const int K = (ml + NT - 1) / NT;
     const int r0 = 4 * b;
     const bool pack = A.tout != nullptr && r0 + 3 < nl;
+    const bool gfresh = A.split != 0;      // no line in LDS: prev and red are not there
 #pragma nounroll
     for (int st = 0; st < 5; st++) {
         int r; bool redundant, up_fresh, dn_fresh;
@@ -1509,33 +1524,31 @@ __device__ __forceinline__ void long_band(const LineArgs &A, int b, float *ring,
         if ((A.split == 1 && st >= 3) || (A.split == 2 && st != 4)) continue;
         if (A.split == 2) { up_fresh = false; dn_fresh = false; }
         const bool has_up = REV ? r + 1 < nl : r > 0, has_dn = REV ? r > 0 : r + 1 < nl;
-        const LineRows R = line_rows<REV>(A, r, up_fresh, dn_fresh);
+        // a split sweep reads the fresh upstream line from memory with the cell's other inputs
+        const bool upg = gfresh && up_fresh;
+        LineRows R = line_rows<REV>(A, r, up_fresh && !upg, dn_fresh);
+        if (upg) R.vu = A.fresh + (long long)(REV ? r + 1 : r - 1) * A.pitch;
         // steps 1 and 4 end a pair of own lines (forward: 0,1 and 2,3; reverse: 3,2 and 1,0)
         const bool pair_w = pack && (st == 1 || st == 4);
         const bool single_w = !redundant && !pack;
         const int rp = r0 + ((r - r0) & 2);
-        // the final value v of position p: write it, keep it
-        auto fin = [&](int p, float v) {
+        // the final value v of position p: write it, keep it.  og: the pair partner's value at p in
+        // a split sweep (the upstream line, in memory: its cell input vu)
+        auto fin = [&](int p, float v, float og) {
             const long long q = cell(p);
             if (single_w) {
                 if (A.tout) A.tout[q * A.tpitch + r] = v;
                 else A.phi_new[(long long)r * A.pitch + q] = v;
             } else if (pair_w) {
-                const float o = prev[p];
+                const float o = gfresh ? og : prev[p];
                 *reinterpret_cast<float2 *>(A.tout + q * A.tpitch + rp) = REV ? make_float2(v, o) : make_float2(o, v);
             }
-            if (redundant) red[p] = v;
-            else prev[p] = v;
-            if (A.nb_out && (st == 0 || st == 2)) A.nb_out[(long long)r * A.pitch + q] = v;
-        };
-        // split 2 of a reverse sweep: the partner of the band's last pair from split 1
-        if (REV && A.split == 2 && pair_w) {
-#pragma nounroll
-            for (int k = 0; k < K; k++) {
-                const int p = k * NT + t;
-                if (p < ml) prev[p] = A.nb_old[(long long)(r0 + 1) * A.pitch + cell(p)];
+            if (!gfresh) {
+                if (redundant) red[p] = v;
+                else prev[p] = v;
             }
-        }
+            if (A.nb_out) A.nb_out[(long long)r * A.pitch + q] = v;
+        };
         // starred masks of the whole line
 #pragma nounroll
         for (int k = 0; k < K; k++) {
@@ -1547,6 +1560,7 @@ __device__ __forceinline__ void long_band(const LineArgs &A, int b, float *ring,
         __syncthreads();
         float carry = 0.0f;
         bool pend = false;                       // the last round's cell waits for a unit ending in this one
+        float pvu = 0.0f;                        // the last round's cell input vu (its pair partner)
         // the next round's inputs are read at the start of a round (round 0: here),
         // so that their latency overlaps the round's computation
         CellIn cn;
@@ -1562,7 +1576,7 @@ __device__ __forceinline__ void long_band(const LineArgs &A, int b, float *ring,
             bool inu = false, last = false;
             int ps = p, L = 1;
             if (in) {
-                const float vu = has_up ? (up_fresh ? prev[p] : c.vu) : 0.0f;
+                const float vu = has_up ? (up_fresh && !upg ? prev[p] : c.vu) : 0.0f;
                 const float vd = has_dn ? (dn_fresh ? red[p] : c.vd) : 0.0f;
                 w = cell_row<REV, CF>(A, c, r, cell(p), vu, vd, area);
                 if (mask_bit(msk, p)) {
@@ -1627,23 +1641,34 @@ __device__ __forceinline__ void long_band(const LineArgs &A, int b, float *ring,
                 }
                 __syncthreads();
                 if (inu && ps + L - 1 < (k + 1) * NT) v = B.y(p);
-                if (k > 0 && pend) fin(p - NT, B.y(p - NT));
+                if (k > 0 && pend) fin(p - NT, B.y(p - NT), pvu);
             }
             pend = inu && ps + L - 1 >= (k + 1) * NT;
-            if (in && !pend) fin(p, v);
+            pvu = c.vu;
+            if (in && !pend) fin(p, v, c.vu);
         }
     }
 }
 
-// dynamic LDS of the long-line kernel: [starred masks][RF_COUNT fields x 2 NT
-// ring][prev: ml floats][red: ml floats]
+// Workgroup of the long-line kernel: 1024 threads; rounds of 1024 cells, so
+// units of up to 1024 cells fit the ring of two rounds.  A split sweep keeps
+// no line in LDS (masks and ring: about 73 KB at 8192 cells), so two
+// workgroups share a CU.
+constexpr int LONG_NT = 1024;
+// dynamic LDS of the long-line kernel: [starred masks][RING_FIELDS fields x 2 NT
+// ring][prev: ml floats][red: ml floats]; lines = false (a split sweep): no prev, no red
 template <int NT>
-__host__ __device__ inline size_t long_lds_bytes(int ml)
+__host__ __device__ inline size_t long_lds_bytes(int ml, bool lines = true)
 {
-    return (size_t)sweep_mask_words(ml) * 8 + ((size_t)RF_COUNT * 2 * NT + 2 * (size_t)ml) * sizeof(float);
+    return (size_t)sweep_mask_words(ml) * 8 +
+           ((size_t)RING_FIELDS * 2 * NT + (lines ? 2 * (size_t)ml : 0)) * sizeof(float);
 }
+// Eight waves per SIMD (two 1024-thread workgroups per CU): at most 64
+// registers per lane; the few values the compiler then keeps in scratch cost
+// less than the second workgroup gains, which runs its rounds while the other
+// waits at a barrier behind a long unit's serial solve.
 template <int NT, bool REV, bool CF>
-__global__ void __launch_bounds__(NT) k_sweep_long(LineArgs A)
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8 * NT / 1024))) k_sweep_long(LineArgs A)
 {
     if (A.skip && *A.skip) return;
     extern __shared__ uint64_t smem64[];
@@ -1651,7 +1676,8 @@ __global__ void __launch_bounds__(NT) k_sweep_long(LineArgs A)
     __shared__ unsigned wlast[NT / 64];
     uint64_t *msk = smem64;
     float *ring = reinterpret_cast<float *>(smem64 + sweep_mask_words(A.ml));
-    float *prev = ring + RF_COUNT * 2 * NT;
+    float *prev = ring + RING_FIELDS * 2 * NT;
+    // (a split sweep touches neither prev nor red; its launch leaves out their room)
     long_band<NT, REV, CF>(A, blockIdx.x, ring, prev, prev + A.ml, msk, wtot, wlast);
 }
 

@@ -78,6 +78,11 @@ def test_setup_rejects_bad_arguments_before_any_device_work(lib):
     # Rada-Chen needs a marker polygon of positive area: at least 3 markers
     rc = mgseg.Params(model=1).to_c()
     assert lib.mgseg_setup(img, 64, 64, 64, mk, 2, C.byref(rc), None, C.byref(out)) == 1
+    # the column-system smoothers (Hybrid Smoother 1, GSLINE-I, GSLINE-II) take one workgroup per
+    # column: columns of more than 1024 cells are refused (rows may be longer)
+    for sm in (2, 3, 6):
+        q = mgseg.Params(smoother=sm, levels=3).to_c()
+        assert lib.mgseg_setup(img, 2048, 64, 64, mk, 3, C.byref(q), None, C.byref(out)) == 1
     assert not out.value
     # network sizes
     net = C.c_void_p()
