@@ -291,7 +291,7 @@ void res64(mgseg_ctx *c)
 // bit: the label bit of the starred cells (default: the sweep's own; a bit no
 // label carries makes every cell a point)
 // scratch (reverse sweeps): a free plane in the sweep's line layout, which lets a long-line
-// sweep run split
+// sweep run split, written there in its own layout and then transposed to tout
 void launch_sweep(mgseg_ctx *c, int l, int s, const float *phi_old, float *phi_new, float *tout = nullptr,
                   int tpitch = 0, int bit = -1, const float *qd = nullptr, float *scratch = nullptr)
 {
@@ -363,15 +363,21 @@ void launch_sweep(mgseg_ctx *c, int l, int s, const float *phi_old, float *phi_n
         if (cfm) MG_SWEEP2_CF(NT, true);   \
         else MG_SWEEP2_CF(NT, false);  \
     } while (0)
+    // a reverse sweep with a transposed output and a free plane runs split as the forward sweep
+    // does, written in its own layout to the free plane, which one tiled transpose then copies
+    // to the output (coalesced on both sides, where the sweep's own transposed stores hit a new
+    // page every few cells)
     const bool split_rev = c->sched.split_long && rev && tout && scratch;
 #define MG_SWEEP_LONG_CF(CF)                                                                                    \
     do {                                                                                                        \
         if (rev && split_rev) {                                                                                 \
             LineArgs A1 = A, A2 = A;                                                                            \
-            A1.split = 1; A1.nb_out = scratch; A1.fresh = scratch;                                              \
+            A1.tout = A2.tout = nullptr; A1.phi_new = A2.phi_new = scratch;                                     \
+            A1.split = 1; A1.fresh = scratch;                                                                   \
             A2.split = 2; A2.nb_old = scratch; A2.fresh = scratch;                                              \
             hipLaunchKernelGGL((k_sweep_long<LONG_NT, true, CF>), dim3(bands), dim3(LONG_NT), llds_s, c->s, A1);       \
             hipLaunchKernelGGL((k_sweep_long<LONG_NT, true, CF>), dim3(bands), dim3(LONG_NT), llds_s, c->s, A2);       \
+            transpose_f(c, scratch, A.pitch, tout, tpitch, A.nl, A.ml);                                       \
         } else if (rev) hipLaunchKernelGGL((k_sweep_long<LONG_NT, true, CF>), dim3(bands), dim3(LONG_NT), llds, c->s, A);  \
         else if (split) {                                                                                       \
             LineArgs A1 = A, A2 = A;                                                                            \

@@ -110,14 +110,13 @@ struct LineArgs {
     const double *area;                 // Rada-Chen area term (null: 0)
     const float4 *cf;                   // frozen scaled face coefficients (sweeps with CF; fit null)
     const float *qd = nullptr;          // NEWT: the Newton term Q' added to each cell's diagonal (null: none)
-    // long lines, forward sweeps: 0 every line of a band in one launch; 1 the band's first
-    // three lines only; 2 its fourth line only, its cross-line neighbours (final after the
-    // split-1 launch) read from nb_old
+    // sweeps written in their own layout: 0 every line of a band in one launch; 1 the band's
+    // first three lines only; 2 its fourth line only, its cross-line neighbours (final after
+    // the split-1 launch) read from nb_old
     int split = 0;
     const float *nb_old = nullptr;
-    float *nb_out = nullptr;            // split 1 of a reverse sweep: its three lines, line layout
     // split long-line sweeps: the plane (line layout, pitch) holding the previous own line's final
-    // values, read in place of a copy in LDS (forward split 1: phi_new; reverse: nb_out / nb_old)
+    // values (phi_new), read in place of a copy in LDS
     const float *fresh = nullptr;
     int pitch, lpitch, nl, ml;
     float kap, e2, M, eps;
@@ -1495,9 +1494,10 @@ __device__ __forceinline__ void sweep_band2(const LineArgs &A, int b, const RunB
 // later).  LDS holds the previous own line (the fresh upstream neighbour,
 // prev) and the recomputed neighbour line (red), each cell at its visit
 // position, read and written only by the thread that owns the position.  A
-// split sweep recomputes no line and reads the previous own line from the
-// plane it was written to (A.fresh; visible after the barrier that opens the
-// next line), so its LDS is the masks and the ring alone.
+// split sweep (written in its own layout) recomputes no line and reads the
+// previous own line from the plane it was written to (A.fresh; visible after
+// the barrier that opens the next line), so its LDS is the masks and the
+// ring alone.
 // The transposed output of a full band goes out as float2 pairs of lines
 // (0, 1) and (2, 3), written when the pair's second line is done.  The
 // rounds are a loop, not unrolled: one copy of the round's code, and no
@@ -1532,22 +1532,21 @@ __device__ __forceinline__ void long_band(const LineArgs &A, int b, float *ring,
         const bool pair_w = pack && (st == 1 || st == 4);
         const bool single_w = !redundant && !pack;
         const int rp = r0 + ((r - r0) & 2);
-        // the final value v of position p: write it, keep it.  og: the pair partner's value at p in
-        // a split sweep (the upstream line, in memory: its cell input vu)
-        auto fin = [&](int p, float v, float og) {
+        // the final value v of position p: write it, keep it (a split sweep writes its own
+        // layout, never pairs)
+        auto fin = [&](int p, float v) {
             const long long q = cell(p);
             if (single_w) {
                 if (A.tout) A.tout[q * A.tpitch + r] = v;
                 else A.phi_new[(long long)r * A.pitch + q] = v;
             } else if (pair_w) {
-                const float o = gfresh ? og : prev[p];
+                const float o = prev[p];
                 *reinterpret_cast<float2 *>(A.tout + q * A.tpitch + rp) = REV ? make_float2(v, o) : make_float2(o, v);
             }
             if (!gfresh) {
                 if (redundant) red[p] = v;
                 else prev[p] = v;
             }
-            if (A.nb_out) A.nb_out[(long long)r * A.pitch + q] = v;
         };
         // starred masks of the whole line
 #pragma nounroll
@@ -1560,7 +1559,6 @@ __device__ __forceinline__ void long_band(const LineArgs &A, int b, float *ring,
         __syncthreads();
         float carry = 0.0f;
         bool pend = false;                       // the last round's cell waits for a unit ending in this one
-        float pvu = 0.0f;                        // the last round's cell input vu (its pair partner)
         // the next round's inputs are read at the start of a round (round 0: here),
         // so that their latency overlaps the round's computation
         CellIn cn;
@@ -1641,11 +1639,10 @@ __device__ __forceinline__ void long_band(const LineArgs &A, int b, float *ring,
                 }
                 __syncthreads();
                 if (inu && ps + L - 1 < (k + 1) * NT) v = B.y(p);
-                if (k > 0 && pend) fin(p - NT, B.y(p - NT), pvu);
+                if (k > 0 && pend) fin(p - NT, B.y(p - NT));
             }
             pend = inu && ps + L - 1 >= (k + 1) * NT;
-            pvu = c.vu;
-            if (in && !pend) fin(p, v, c.vu);
+            if (in && !pend) fin(p, v);
         }
     }
 }

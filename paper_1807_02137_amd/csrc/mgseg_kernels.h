@@ -6,7 +6,10 @@
 // rows of a 32 x 32-tile block: 8 (four rows per thread) on grids of many
 // tiles, where several blocks per CU overlap each other's barriers; 32 (one
 // row per thread, the shortest chain) on small grids
-__host__ __device__ inline int tile_rows(long long tiles) { return tiles >= 4096 ? 8 : TILE; }
+// rows of a 32 x 32 tile's block: 16 on large grids (two rows per thread; 512
+// threads, three blocks per CU beside the stencil and transpose staging in
+// LDS), 32 on small ones (one row per thread)
+__host__ __device__ inline int tile_rows(long long tiles) { return tiles >= 4096 ? 16 : TILE; }
 
 // ==========================================================================
 // Setup maps (Sec. 2.2).  Level-0 maps are computed in FP64.
@@ -612,7 +615,7 @@ __global__ void k_eta(const double *phi64, const double *prev, long long N, doub
 // grids: e = 0 with bounds from the finer grid's slack.
 
 // finest-grid cycle start: e = 0, bounds of e = [-M - b, M - b]
-// (32 x 32 tiles, block (32, 8) or (32, 32) as tile_rows picks; the
+// (32 x 32 tiles, block (32, 16) or (32, 32) as tile_rows picks; the
 // column-major bounds through LDS so that both layouts are written coalesced)
 __global__ void __launch_bounds__(1024) k_start0(const double *b, int n, int m, double M, float *e, float *lo,
                                                 float *hi, int p, float *lo_cm, float *hi_cm, int pc)
@@ -752,7 +755,7 @@ __device__ __forceinline__ void stage_halo(const DevArgs<BT> &A, int by, int bx,
 // line, to the next cell, to the previous cell) of each layout: row-major
 // (i+1, i-1, j+1, j-1), column-major (j+1, j-1, i+1, i-1).  32 x 32 tiles:
 // row-major outputs written directly, column-major copies through LDS so that
-// both layouts are written coalesced.  Block (32, 32) or (32, 8): one or four
+// both layouts are written coalesced.  Block (32, 32) or (32, 16): one or two
 // rows per thread; the stencil inputs are staged in LDS (stage_halo).
 template <typename BT>
 __global__ void __launch_bounds__(1024) k_freeze_dev(DevArgs<BT> A)
