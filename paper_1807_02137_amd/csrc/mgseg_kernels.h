@@ -3,12 +3,10 @@
 #include "mgseg_device.h"
 
 #define TILE 32
-// rows of a 32 x 32-tile block: 8 (four rows per thread) on grids of many
-// tiles, where several blocks per CU overlap each other's barriers; 32 (one
-// row per thread, the shortest chain) on small grids
-// rows of a 32 x 32 tile's block: 16 on large grids (two rows per thread; 512
-// threads, three blocks per CU beside the stencil and transpose staging in
-// LDS), 32 on small ones (one row per thread)
+// rows of a 32 x 32-tile block: 16 (two rows per thread; 512 threads, three
+// blocks per CU beside the stencil and transpose staging in LDS) on grids of
+// many tiles, where several blocks per CU overlap each other's barriers; 32
+// (one row per thread, the shortest chain) on small grids
 __host__ __device__ inline int tile_rows(long long tiles) { return tiles >= 4096 ? 16 : TILE; }
 
 // ==========================================================================
@@ -507,23 +505,25 @@ __device__ double cell_N64(const Res64Args &A, int i, int j, double c1, double c
 // the squares of the projected residual of the paper's rows (eq. abcdrc, each
 // with its delta(phi) factor: the stopping measure) and of the rows as the
 // smoother holds them (divided by delta(phi) when scaled) go to two partials
-// per block
+// per block.  Block (x, y) takes columns 256 x .. 256 x + 255 of the rows
+// y, y + gridDim.y, ..., so that a grid of at most 256 block rows leaves few
+// partials for the final sum.
 __global__ void k_res64(Res64Args A)
 {
     __shared__ double red[256], red2[256];
-    int j = blockIdx.x * blockDim.x + threadIdx.x, i = blockIdx.y, tid = threadIdx.x;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x, tid = threadIdx.x;
     double acc = 0.0, acc_rows = 0.0;
-    if (j < A.m && i < A.n) {
-        double c1 = A.c12[0], c2 = A.c12[1];
-        double area = A.area ? *A.area : 0.0;
+    const double c1 = A.c12[0], c2 = A.c12[1];
+    const double area = A.area ? *A.area : 0.0;
+    for (int i = blockIdx.y; i < A.n && j < A.m; i += gridDim.y) {
         double N = cell_N64(A, i, j, c1, c2, area);
         double r = -N;
         double ph = A.phi64[(long long)i * A.m + j];
         double rp = r;
         if ((ph >= A.M && rp < 0.0) || (ph <= -A.M && rp > 0.0)) rp = 0.0;
-        acc_rows = rp * rp;
+        acc_rows += rp * rp;
         const double rpp = A.scaled ? mg_delta64(ph, A.eps) * rp : rp;
-        acc = rpp * rpp;
+        acc += rpp * rpp;
         long long q = (long long)i * A.p32 + j;
         if (A.phi32) A.phi32[q] = (float)ph;
         if (A.G) A.G[q] = (float)r;
