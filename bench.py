@@ -355,8 +355,10 @@ def large_bench(steps: int, warmup: int, max_cycles: int, cpu_seconds: float, no
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic("c4"),
                      "copy_gbs": copy, "frac_of_copy": achieved / copy,
-                     "kernel": "k_sweep_long (finest-grid directional sweep, 8192-cell lines)",
-                     "launches": prof_n, "avg_us": avg_ms * 1e3, "bytes_per_launch": alg_bytes,
+                     "kernel": "k_sweep_long (finest-grid directional sweep, 8192-cell lines; one sweep is two "
+                               "launches, and a reverse sweep's output one tiled transpose more)",
+                     "launches": prof_n, "unit_of_launch": "one sweep", "avg_us": avg_ms * 1e3,
+                     "bytes_per_launch": alg_bytes,
                      "bytes_per_px": SWEEP_BYTES_PER_PX, "design_bytes_per_launch": design_bytes},
         "cpu_baseline": cpu,
     }))
@@ -552,8 +554,9 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic("c2") if args.model == "sc" and not smoother else None,
                      "copy_gbs": copy, "frac_of_copy": achieved / copy,
-                     "kernel": "k_sweep (finest-grid directional sweep)",
-                     "launches": prof_n, "avg_us": avg_ms * 1e3, "bytes_per_launch": prof_bytes,
+                     "kernel": "k_sweep (finest-grid directional sweep; a forward sweep is two launches)",
+                     "launches": prof_n, "unit_of_launch": "one sweep", "avg_us": avg_ms * 1e3,
+                     "bytes_per_launch": prof_bytes,
                      "bytes_per_px": SWEEP_BYTES_PER_PX, "design_bytes_per_launch": design_bytes},
         "cpu_baseline": cpu,
         "smoothing_rates": rates,
