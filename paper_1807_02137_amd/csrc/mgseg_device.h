@@ -1484,11 +1484,16 @@ __device__ __forceinline__ void sweep_band2(const LineArgs &A, int b, const RunB
 // --------------------------------------------------------------------------
 // Lines longer than one workgroup: NT threads take K rounds of NT cells, one
 // round after another, so that only one round's inputs are held at a time.
-// A unit's chain ramp sits at its LAST position (its other cells take the
+// A unit of at most three cells, or one that crosses into the next round,
+// has its chain ramp at its LAST position (its other cells take the
 // identity): the scan's exclusive prefix there is the value entering the
 // unit, and a unit that begins in one round and ends in the next is solved
 // in the next round, where all of its rows are known (units are at most one
-// round long, so the ring of two rounds holds every row of a unit).  The unit rows live in
+// round long, so the ring of two rounds holds every row of a unit).  A unit
+// of more than three cells inside one round is solved as on shorter lines:
+// every cell eliminates from the unit's end down to itself, takes its Z_k
+// into the scan and checks its own row; the first cell's thread finishes a
+// unit whose check failed with the active-set iteration.  The unit rows live in
 // a ring of two rounds (RingBuf).  A cell's new value is written as soon as
 // it is final (cells of a unit that ends in the next round: one round
 // later).  LDS holds the previous own line (the fresh upstream neighbour,
@@ -1504,7 +1509,7 @@ __device__ __forceinline__ void sweep_band2(const LineArgs &A, int b, const RunB
 // per-round addresses held across rounds.
 template <int NT, bool REV, bool CF>
 __device__ __forceinline__ void long_band(const LineArgs &A, int b, float *ring, float *prev, float *red,
-                                          uint64_t *msk, Ramp *wtot, unsigned *wlast)
+                                          uint64_t *msk, Ramp *wtot, unsigned *wlast, unsigned *wfail)
 {
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int nl = A.nl, ml = A.ml, nw = (ml + 63) >> 6;
@@ -1590,6 +1595,9 @@ __device__ __forceinline__ void long_band(const LineArgs &A, int b, float *ring,
                     B.at(RG_S, p) = c.sig;
                 }
             }
+            // a unit of more than three cells inside this round: every cell eliminates from the
+            // unit's last cell down to itself and takes its Z_k into the scan (as on shorter lines)
+            const bool inr = inu && L > 3 && ps >= k * NT && ps + L - 1 < (k + 1) * NT;
             // rows of the round visible; uk: a unit of the block ends in this round
             const unsigned long long lm = __ballot(last);
             if (lane == 0) wlast[wave] = lm != 0ull ? 1u : 0u;
@@ -1597,7 +1605,14 @@ __device__ __forceinline__ void long_band(const LineArgs &A, int b, float *ring,
             const bool uk = __ballot(lane < NT / 64 && wlast[lane] != 0u) != 0ull;
             Ramp u = ramp_id();
             if (in && !inu) u = cell_ramp(w);
-            if (last) {
+            float lP1 = 0.0f, lQ1 = 0.0f;
+            if (inr) {
+                const int lp = ps + L - 1;
+                float P, Q;
+                long_elim(B, p, lp, B.sig_after(lp, ml), P, Q, lP1, lQ1);
+                u = Ramp{P, Q, w.lo, w.hi};
+                if (p == ps) B.at(RF_P, ps) = 0.0f;      // the unit's failed-check flag
+            } else if (last) {
                 if (L <= 2) {
                     PairRows Q;
                     pair_load(B, ps, L, ml, Q);
@@ -1614,10 +1629,23 @@ __device__ __forceinline__ void long_band(const LineArgs &A, int b, float *ring,
             const Ramp ex = block_scan_excl<NT>(u, wtot, k & 1, tot, t);
             const float x = ramp_eval(ex, carry);
             float v = 0.0f;
-            if (in && !inu) v = ramp_eval(u, x);
+            if (in && (!inu || inr)) v = ramp_eval(u, x);
             carry = ramp_eval(tot, carry);
+            // the row check of an in-round unit's cell at its predecessor's value x and its
+            // successor's Z_{k+1}(v)
+            bool bad = false;
+            if (inr) {
+                const int lp = ps + L - 1;
+                const float yn = p == lp ? lQ1 : mg_clip(fmaf(lP1, v, lQ1), B.at(RF_LO, p + 1), B.at(RF_HI, p + 1));
+                const float ta = w.a * x, tc = w.c * yn;
+                bad = w.ok && !long_row_ok(v, (ta + tc) - w.rr, fabsf(ta) + fabsf(tc) + fabsf(w.rr), w.lo, w.hi);
+                B.y(p) = v;
+                if (bad) B.at(RF_P, ps) = 1.0f;
+            }
             if (uk) {
-                if (last) {
+                const unsigned long long fb = __ballot(bad);
+                if (lane == 0) wfail[wave] = fb != 0ull ? 1u : 0u;
+                if (last && !inr) {
                     if (L <= 2) {
                         PairRows Q;
                         pair_load(B, ps, L, ml, Q);
@@ -1638,6 +1666,12 @@ __device__ __forceinline__ void long_band(const LineArgs &A, int b, float *ring,
                     }
                 }
                 __syncthreads();
+                // an in-round unit whose check failed: its first cell's thread finishes it with the
+                // active-set iteration from the scan's values
+                if (__ballot(lane < NT / 64 && wfail[lane] != 0u) != 0ull) {
+                    if (inr && p == ps && B.at(RF_P, ps) != 0.0f) long_active_set(B, ps, L, ml, x);
+                    __syncthreads();
+                }
                 if (inu && ps + L - 1 < (k + 1) * NT) v = B.y(p);
                 if (k > 0 && pend) fin(p - NT, B.y(p - NT));
             }
@@ -1670,12 +1704,12 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8 * NT 
     if (A.skip && *A.skip) return;
     extern __shared__ uint64_t smem64[];
     __shared__ Ramp wtot[2 * (NT / 64)];
-    __shared__ unsigned wlast[NT / 64];
+    __shared__ unsigned wlast[NT / 64], wfail[NT / 64];
     uint64_t *msk = smem64;
     float *ring = reinterpret_cast<float *>(smem64 + sweep_mask_words(A.ml));
     float *prev = ring + RING_FIELDS * 2 * NT;
     // (a split sweep touches neither prev nor red; its launch leaves out their room)
-    long_band<NT, REV, CF>(A, blockIdx.x, ring, prev, prev + A.ml, msk, wtot, wlast);
+    long_band<NT, REV, CF>(A, blockIdx.x, ring, prev, prev + A.ml, msk, wtot, wlast, wfail);
 }
 
 // dynamic LDS: [starred masks, 8 B per 64 cells][2 x RB_FIELDS * ml floats of rows]
