@@ -279,8 +279,8 @@ void res64(mgseg_ctx *c)
     A.phi32 = devm(c) ? nullptr : L.P[0];
     A.G = devm(c) ? L.G : nullptr;
     A.partial = c->part;
-    const dim3 g((c->m + 255) / 256, std::min(c->n, 256));
-    hipLaunchKernelGGL(k_res64, g, dim3(256), 0, c->s, A);
+    const dim3 g((c->m + TILE - 1) / TILE, std::min((c->n + TILE - 1) / TILE, 32));
+    hipLaunchKernelGGL(k_res64, g, dim3(TILE, R64_ROWS), 0, c->s, A);
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FIN_NT), 0, c->s, c->part, (int)(g.x * g.y), 4, 0.0, 0.0, 0.0, 0.0,
                        c->dsc + DS_RES);
 }

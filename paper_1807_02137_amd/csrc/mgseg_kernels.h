@@ -481,58 +481,77 @@ struct Res64Args {
     double *partial;
 };
 
-__device__ double cell_N64(const Res64Args &A, int i, int j, double c1, double c2, double area)
-{
-    const int n = A.n, m = A.m;
-    int im = mg_mirror(i - 1, n), ip = mg_mirror(i + 1, n), jm = mg_mirror(j - 1, m), jp = mg_mirror(j + 1, m);
-    auto P = [&](int a, int b) { return A.phi64[(long long)a * m + b]; };
-    auto W = [&](int a, int b) { return A.w64[(long long)a * m + b]; };
-    double p0 = P(i, j);
-    double dl = A.scaled ? 1.0 : mg_delta64(p0, A.eps);
-    double s = A.kap * dl;
-    double z = (double)A.z32[(long long)i * A.p32 + j];
-    double fa = z - c1, fb = z - c2;
-    double fit = A.l1 * fa * fa - A.l2 * fb * fb;
-    if (A.model == 0) fit += A.theta * A.d64[(long long)i * m + j];
-    double v = -dl * (fit + area);
-    if (i + 1 < n) v += s * mg_face64(p0, P(i + 1, j), P(i, jp), P(i + 1, jp), P(i, jm), P(i + 1, jm), W(i, j), W(i + 1, j), A.e2) * (P(i + 1, j) - p0);
-    if (i > 0) v += s * mg_face64(P(i - 1, j), p0, P(i - 1, jp), P(i, jp), P(i - 1, jm), P(i, jm), W(i - 1, j), W(i, j), A.e2) * (P(i - 1, j) - p0);
-    if (j + 1 < m) v += s * mg_face64(p0, P(i, j + 1), P(ip, j), P(ip, j + 1), P(im, j), P(im, j + 1), W(i, j), W(i, j + 1), A.e2) * (P(i, j + 1) - p0);
-    if (j > 0) v += s * mg_face64(P(i, j - 1), p0, P(ip, j - 1), P(ip, j), P(im, j - 1), P(im, j), W(i, j - 1), W(i, j), A.e2) * (P(i, j - 1) - p0);
-    return v;
-}
-
 // the squares of the projected residual of the paper's rows (eq. abcdrc, each
 // with its delta(phi) factor: the stopping measure) and of the rows as the
 // smoother holds them (divided by delta(phi) when scaled) go to two partials
-// per block.  Block (x, y) takes columns 256 x .. 256 x + 255 of the rows
-// y, y + gridDim.y, ..., so that a grid of at most 256 block rows leaves few
-// partials for the final sum.
-__global__ void k_res64(Res64Args A)
+// per block.  A block (32, 16) takes the 32 x 32 tiles of one tile column at
+// tile rows y, y + gridDim.y, ...: phi and w of a tile and its one-cell halo
+// (mirrored at the grid edge as the stencil mirrors) are staged in LDS, and
+// every face value of the tile (33 x 32 between rows, 32 x 33 between
+// columns) is computed once, for the two cells it separates.
+#define R64_ROWS 16
+__global__ void __launch_bounds__(TILE * R64_ROWS) k_res64(Res64Args A)
 {
-    __shared__ double red[256], red2[256];
-    const int j = blockIdx.x * blockDim.x + threadIdx.x, tid = threadIdx.x;
-    double acc = 0.0, acc_rows = 0.0;
+    __shared__ double ph[TILE + 2][TILE + 2], ww[TILE + 2][TILE + 2];
+    __shared__ double fv[TILE + 1][TILE], fh[TILE][TILE + 1];
+    __shared__ double red[TILE * R64_ROWS], red2[TILE * R64_ROWS];
+    const int n = A.n, m = A.m, tx = threadIdx.x, ty = threadIdx.y, tid = ty * TILE + tx;
+    constexpr int NTH = TILE * R64_ROWS;
+    const int bx = blockIdx.x * TILE;
     const double c1 = A.c12[0], c2 = A.c12[1];
     const double area = A.area ? *A.area : 0.0;
-    for (int i = blockIdx.y; i < A.n && j < A.m; i += gridDim.y) {
-        double N = cell_N64(A, i, j, c1, c2, area);
-        double r = -N;
-        double ph = A.phi64[(long long)i * A.m + j];
-        double rp = r;
-        if ((ph >= A.M && rp < 0.0) || (ph <= -A.M && rp > 0.0)) rp = 0.0;
-        acc_rows += rp * rp;
-        const double rpp = A.scaled ? mg_delta64(ph, A.eps) * rp : rp;
-        acc += rpp * rpp;
-        long long q = (long long)i * A.p32 + j;
-        if (A.phi32) A.phi32[q] = (float)ph;
-        if (A.G) A.G[q] = (float)r;
+    double acc = 0.0, acc_rows = 0.0;
+    for (int by = blockIdx.y * TILE; by < n; by += gridDim.y * TILE) {
+        __syncthreads();                  // the previous tile's LDS reads are done
+        for (int t = tid; t < (TILE + 2) * (TILE + 2); t += NTH) {
+            const int yy = t / (TILE + 2), xx = t % (TILE + 2);
+            const long long q = (long long)mg_mirror(by - 1 + yy, n) * m + mg_mirror(bx - 1 + xx, m);
+            ph[yy][xx] = A.phi64[q];
+            ww[yy][xx] = A.w64[q];
+        }
+        __syncthreads();
+        // fv[yy][x]: the face between tile rows yy - 1 and yy (grid rows by - 1 + yy, by + yy);
+        // fh[y][xx]: between tile columns xx - 1 and xx; faces on the grid edge are not used
+        for (int t = tid; t < (TILE + 1) * TILE; t += NTH) {
+            const int yy = t / TILE, x = t % TILE;
+            fv[yy][x] = mg_face64(ph[yy][x + 1], ph[yy + 1][x + 1], ph[yy][x + 2], ph[yy + 1][x + 2], ph[yy][x],
+                                  ph[yy + 1][x], ww[yy][x + 1], ww[yy + 1][x + 1], A.e2);
+            const int y = t / (TILE + 1), xx = t % (TILE + 1);
+            fh[y][xx] = mg_face64(ph[y + 1][xx], ph[y + 1][xx + 1], ph[y + 2][xx], ph[y + 2][xx + 1], ph[y][xx],
+                                  ph[y][xx + 1], ww[y + 1][xx], ww[y + 1][xx + 1], A.e2);
+        }
+        __syncthreads();
+        for (int y = ty; y < TILE; y += R64_ROWS) {
+            const int i = by + y, j = bx + tx;
+            if (i >= n || j >= m) continue;
+            const double p0 = ph[y + 1][tx + 1];
+            const double dl = A.scaled ? 1.0 : mg_delta64(p0, A.eps);
+            const double s = A.kap * dl;
+            const double z = (double)A.z32[(long long)i * A.p32 + j];
+            const double fa = z - c1, fb = z - c2;
+            double fit = A.l1 * fa * fa - A.l2 * fb * fb;
+            if (A.model == 0) fit += A.theta * A.d64[(long long)i * m + j];
+            double v = -dl * (fit + area);
+            if (i + 1 < n) v += s * fv[y + 1][tx] * (ph[y + 2][tx + 1] - p0);
+            if (i > 0) v += s * fv[y][tx] * (ph[y][tx + 1] - p0);
+            if (j + 1 < m) v += s * fh[y][tx + 1] * (ph[y + 1][tx + 2] - p0);
+            if (j > 0) v += s * fh[y][tx] * (ph[y + 1][tx] - p0);
+            const double r = -v;
+            double rp = r;
+            if ((p0 >= A.M && rp < 0.0) || (p0 <= -A.M && rp > 0.0)) rp = 0.0;
+            acc_rows += rp * rp;
+            const double rpp = A.scaled ? mg_delta64(p0, A.eps) * rp : rp;
+            acc += rpp * rpp;
+            const long long q = (long long)i * A.p32 + j;
+            if (A.phi32) A.phi32[q] = (float)p0;
+            if (A.G) A.G[q] = (float)r;
+        }
     }
     red[tid] = acc;
     red2[tid] = acc_rows;
     __syncthreads();
-    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-        if (tid < s) { red[tid] += red[tid + s]; red2[tid] += red2[tid + s]; }
+    for (int st = NTH / 2; st > 0; st >>= 1) {
+        if (tid < st) { red[tid] += red[tid + st]; red2[tid] += red2[tid + st]; }
         __syncthreads();
     }
     if (tid == 0) {
