@@ -697,19 +697,17 @@ struct DevArgs {
 // au = the four face coefficients at psi scaled by kap dl(psi) (to i+1, i-1,
 // j+1, j-1; 0 across the grid edge): the sweeps' frozen A, B, C, D.
 // Bv, Ev, Wv: b, e, w at a cell (global memory or a staged tile).
-template <typename BT, class BV, class EV, class WV>
-__device__ __forceinline__ double dev_cell_at(const DevArgs<BT> &A, int i, int j, bool want_Le, double &Le, float &u0,
-                                              uint8_t &lab, float (&au)[4], const BV &Bv, const EV &Ev, const WV &Wv)
+// (dev_cell_faces: the same with the cell's face values at b and at psi given)
+template <typename BT, class BV, class EV>
+__device__ __forceinline__ double dev_cell_faces(const DevArgs<BT> &A, int i, int j, bool want_Le, double &Le,
+                                                 float &u0, uint8_t &lab, float (&au)[4], const BV &Bv, const EV &Ev,
+                                                 const float (&gb)[4], const float (&gu)[4])
 {
     const int n = A.n, m = A.m;
     auto B64 = [&](int a, int c) { return (double)Bv(a, c); };
     auto E64 = [&](int a, int c) { return (double)Ev(a, c); };
     auto Bf = [&](int a, int c) { return (float)Bv(a, c); };
     auto Uf = [&](int a, int c) { return (float)(B64(a, c) + E64(a, c)); };
-    auto W = [&](int a, int c) { return Wv(a, c); };
-    float gb[4], gu[4];
-    faces4(Bf, W, n, m, i, j, A.e2, gb);
-    faces4(Uf, W, n, m, i, j, A.e2, gu);
     const float ub = Bf(i, j);
     u0 = Uf(i, j);
     const float dlb = A.scaled ? 1.0f : mg_delta(ub, A.eps), dlu = A.scaled ? 1.0f : mg_delta(u0, A.eps);
@@ -734,6 +732,17 @@ __device__ __forceinline__ double dev_cell_at(const DevArgs<BT> &A, int i, int j
     t -= (double)dlb * (fit + sb) - (double)dlu * (fit + su);
     lab = label_of(gu, n, m, i, j, A.Sigma);
     return t;
+}
+template <typename BT, class BV, class EV, class WV>
+__device__ __forceinline__ double dev_cell_at(const DevArgs<BT> &A, int i, int j, bool want_Le, double &Le, float &u0,
+                                              uint8_t &lab, float (&au)[4], const BV &Bv, const EV &Ev, const WV &Wv)
+{
+    auto Bf = [&](int a, int c) { return (float)Bv(a, c); };
+    auto Uf = [&](int a, int c) { return (float)((double)Bv(a, c) + (double)Ev(a, c)); };
+    float gb[4], gu[4];
+    faces4(Bf, Wv, A.n, A.m, i, j, A.e2, gb);
+    faces4(Uf, Wv, A.n, A.m, i, j, A.e2, gu);
+    return dev_cell_faces(A, i, j, want_Le, Le, u0, lab, au, Bv, Ev, gb, gu);
 }
 template <typename BT>
 __device__ __forceinline__ double dev_cell(const DevArgs<BT> &A, int i, int j, bool want_Le, double &Le, float &u0,
@@ -769,55 +778,124 @@ __device__ __forceinline__ void stage_halo(const DevArgs<BT> &A, int by, int bx,
     }
 }
 
+// The face values of a staged tile at b and at psi = fl32(b + e), each face
+// computed once for the two cells it separates, with the arguments faces4
+// gives it (so the same values): fv[yy][x] is the face between tile rows
+// yy - 1 and yy, fh[y][xx] the face between tile columns xx - 1 and xx (a face
+// on the grid edge comes from the mirrored halo and is not used).  bf, uf: b
+// and psi of the tile and its halo in FP32.
+struct TileFaces {
+    float bf[TILE + 2][TILE + 2], uf[TILE + 2][TILE + 2];
+    float fvb[TILE + 1][TILE], fvu[TILE + 1][TILE], fhb[TILE][TILE + 1], fhu[TILE][TILE + 1];
+};
+template <typename BT>
+__device__ __forceinline__ void tile_faces(const BT (&hb)[TILE + 2][TILE + 2], const float (&he)[TILE + 2][TILE + 2],
+                                           const float (&hw)[TILE + 2][TILE + 2], float e2, TileFaces &F)
+{
+    const int nt = blockDim.x * blockDim.y, tid = threadIdx.y * blockDim.x + threadIdx.x;
+    for (int t = tid; t < (TILE + 2) * (TILE + 2); t += nt) {
+        const int yy = t / (TILE + 2), xx = t % (TILE + 2);
+        F.bf[yy][xx] = (float)hb[yy][xx];
+        F.uf[yy][xx] = (float)((double)hb[yy][xx] + (double)he[yy][xx]);
+    }
+    __syncthreads();
+    for (int t = tid; t < (TILE + 1) * TILE; t += nt) {
+        const int yy = t / TILE, x = t % TILE, y = t / (TILE + 1), xx = t % (TILE + 1);
+        F.fvb[yy][x] = mg_face(F.bf[yy][x + 1], F.bf[yy + 1][x + 1], F.bf[yy][x + 2], F.bf[yy + 1][x + 2], F.bf[yy][x],
+                               F.bf[yy + 1][x], hw[yy][x + 1], hw[yy + 1][x + 1], e2);
+        F.fvu[yy][x] = mg_face(F.uf[yy][x + 1], F.uf[yy + 1][x + 1], F.uf[yy][x + 2], F.uf[yy + 1][x + 2], F.uf[yy][x],
+                               F.uf[yy + 1][x], hw[yy][x + 1], hw[yy + 1][x + 1], e2);
+        F.fhb[y][xx] = mg_face(F.bf[y + 1][xx], F.bf[y + 1][xx + 1], F.bf[y + 2][xx], F.bf[y + 2][xx + 1], F.bf[y][xx],
+                               F.bf[y][xx + 1], hw[y + 1][xx], hw[y + 1][xx + 1], e2);
+        F.fhu[y][xx] = mg_face(F.uf[y + 1][xx], F.uf[y + 1][xx + 1], F.uf[y + 2][xx], F.uf[y + 2][xx + 1], F.uf[y][xx],
+                               F.uf[y][xx + 1], hw[y + 1][xx], hw[y + 1][xx + 1], e2);
+    }
+    __syncthreads();
+}
+// the four faces (faces4's order, zero across the grid edge) of tile cell (y, x), grid cell (i, j)
+__device__ __forceinline__ void tile_cell_faces(const TileFaces &F, int y, int x, int i, int j, int n, int m,
+                                                float (&gb)[4], float (&gu)[4])
+{
+    gb[0] = i + 1 < n ? F.fvb[y + 1][x] : 0.0f;
+    gu[0] = i + 1 < n ? F.fvu[y + 1][x] : 0.0f;
+    gb[1] = i > 0 ? F.fvb[y][x] : 0.0f;
+    gu[1] = i > 0 ? F.fvu[y][x] : 0.0f;
+    gb[2] = j + 1 < m ? F.fhb[y][x + 1] : 0.0f;
+    gu[2] = j + 1 < m ? F.fhu[y][x + 1] : 0.0f;
+    gb[3] = j > 0 ? F.fhb[y][x] : 0.0f;
+    gu[3] = j > 0 ? F.fhu[y][x] : 0.0f;
+}
+
 // freeze in deviation form: psi = fl32(b + e), T, labels and (cf non-null)
 // the sweeps' scaled face coefficients, as (to the next line, to the previous
 // line, to the next cell, to the previous cell) of each layout: row-major
 // (i+1, i-1, j+1, j-1), column-major (j+1, j-1, i+1, i-1).  32 x 32 tiles:
-// row-major outputs written directly, column-major copies through LDS so that
-// both layouts are written coalesced.  Block (32, 32) or (32, 16): one or two
-// rows per thread; the stencil inputs are staged in LDS (stage_halo).
+// the stencil inputs staged in LDS (stage_halo), the tile's faces computed
+// once (tile_faces), row-major outputs written directly, column-major copies
+// through LDS (over the face arrays, once every cell has read its faces) so
+// that both layouts are written coalesced.  Block (32, 32) or (32, 16): one
+// or two rows per thread.
 template <typename BT>
 __global__ void __launch_bounds__(1024) k_freeze_dev(DevArgs<BT> A)
 {
-    __shared__ float tp[TILE][TILE + 1], tt[TILE][TILE + 1];
-    __shared__ uint8_t tl[TILE][TILE + 1];
-    __shared__ float4 tc[TILE][TILE + 1];
+    struct Staging {
+        float tp[TILE][TILE + 1], tt[TILE][TILE + 1];
+        float4 tc[TILE][TILE + 1];
+        uint8_t tl[TILE][TILE + 1];
+    };
+    constexpr size_t UNI = sizeof(TileFaces) > sizeof(Staging) ? sizeof(TileFaces) : sizeof(Staging);
+    __shared__ __align__(16) unsigned char uni[UNI];
     __shared__ BT hb[TILE + 2][TILE + 2];
     __shared__ float he[TILE + 2][TILE + 2], hw[TILE + 2][TILE + 2];
+    TileFaces &F = *reinterpret_cast<TileFaces *>(uni);
+    Staging &S = *reinterpret_cast<Staging *>(uni);
     const int bx = blockIdx.x * TILE, by = blockIdx.y * TILE;
     stage_halo(A, by, bx, hb, he, hw);
     __syncthreads();
+    tile_faces(hb, he, hw, A.e2, F);
     // grid cell (a, c) of the stencil of a tile cell lies in the staged halo
     auto Bv = [&](int a, int c) { return hb[a - by + 1][c - bx + 1]; };
     auto Ev = [&](int a, int c) { return he[a - by + 1][c - bx + 1]; };
-    auto Wv = [&](int a, int c) { return hw[a - by + 1][c - bx + 1]; };
-    for (int y = threadIdx.y; y < TILE; y += blockDim.y) {
+    constexpr int RPT = 2;   // rows per thread (block (32, 16); (32, 32) uses one)
+    float r_u0[RPT], r_t[RPT], r_au[RPT][4];
+    uint8_t r_lab[RPT];
+#pragma unroll
+    for (int k = 0; k < RPT; k++) {
+        const int y = threadIdx.y + k * blockDim.y;
         const int i = by + y, j = bx + threadIdx.x;
-        if (i < A.n && j < A.m) {
+        r_u0[k] = 0.0f; r_t[k] = 0.0f; r_lab[k] = 0;
+        r_au[k][0] = r_au[k][1] = r_au[k][2] = r_au[k][3] = 0.0f;
+        if (y < TILE && i < A.n && j < A.m) {
             double Le;
-            float u0;
-            uint8_t lab;
-            float au[4];
-            const double t = dev_cell_at(A, i, j, false, Le, u0, lab, au, Bv, Ev, Wv);
+            float gb[4], gu[4];
+            tile_cell_faces(F, y, threadIdx.x, i, j, A.n, A.m, gb, gu);
+            const double t = dev_cell_faces(A, i, j, false, Le, r_u0[k], r_lab[k], r_au[k], Bv, Ev, gb, gu);
+            r_t[k] = (float)t;
             const long long q = (long long)i * A.p + j;
-            if (A.psi) A.psi[q] = u0;
-            A.T[q] = (float)t;
-            A.lab[q] = lab;
-            if (A.cf) A.cf[q] = make_float4(au[0], au[1], au[2], au[3]);
-            tp[y][threadIdx.x] = u0; tt[y][threadIdx.x] = (float)t; tl[y][threadIdx.x] = lab;
-            tc[y][threadIdx.x] = make_float4(au[2], au[3], au[0], au[1]);
+            if (A.psi) A.psi[q] = r_u0[k];
+            A.T[q] = r_t[k];
+            A.lab[q] = r_lab[k];
+            if (A.cf) A.cf[q] = make_float4(r_au[k][0], r_au[k][1], r_au[k][2], r_au[k][3]);
         }
     }
     if (!A.T_cm) return;
+    __syncthreads();                 // every cell has read its faces: the staging takes their place
+#pragma unroll
+    for (int k = 0; k < RPT; k++) {
+        const int y = threadIdx.y + k * blockDim.y;
+        if (y >= TILE) continue;
+        S.tp[y][threadIdx.x] = r_u0[k]; S.tt[y][threadIdx.x] = r_t[k]; S.tl[y][threadIdx.x] = r_lab[k];
+        S.tc[y][threadIdx.x] = make_float4(r_au[k][2], r_au[k][3], r_au[k][0], r_au[k][1]);
+    }
     __syncthreads();
     for (int y = threadIdx.y; y < TILE; y += blockDim.y) {
         const int j = bx + y, i = by + threadIdx.x;
         if (i < A.n && j < A.m) {
             const long long qc = (long long)j * A.pc + i;
-            if (A.psi_cm) A.psi_cm[qc] = tp[threadIdx.x][y];
-            A.T_cm[qc] = tt[threadIdx.x][y];
-            A.lab_cm[qc] = tl[threadIdx.x][y];
-            if (A.cf_cm) A.cf_cm[qc] = tc[threadIdx.x][y];
+            if (A.psi_cm) A.psi_cm[qc] = S.tp[threadIdx.x][y];
+            A.T_cm[qc] = S.tt[threadIdx.x][y];
+            A.lab_cm[qc] = S.tl[threadIdx.x][y];
+            if (A.cf_cm) A.cf_cm[qc] = S.tc[threadIdx.x][y];
         }
     }
 }
@@ -825,6 +903,8 @@ __global__ void __launch_bounds__(1024) k_freeze_dev(DevArgs<BT> A)
 // residual in deviation form: r = F - N(b + e) = T(b + e) - L_{b+e} e, projected
 // on the bounds of e (zero where the correction would leave them).  32 x 32
 // tiles, block (32, tile_rows), the stencil inputs staged in LDS (stage_halo).
+// (Each cell forms its own four faces here: the shared-face staging of the
+// freeze costs this kernel more in occupancy than it saves.)
 template <typename BT>
 __global__ void __launch_bounds__(1024) k_res_dev(DevArgs<BT> A)
 {
