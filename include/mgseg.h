@@ -260,11 +260,14 @@ mgseg_status mgseg_smoothing_rates(mgseg_ctx *c, int smoother, double *out5, flo
  *                 most 512 cells)
  *   graph         1: each cycle is replayed from a captured HIP graph
  *                 (default); 0: launched eagerly
- *   split_long    lines longer than 512 cells, forward sweeps written in
- *                 their own layout: 1 (default) two launches, the first
- *                 three lines of every band of four, then the fourth lines
- *                 reading their final neighbours; 0 one launch that
- *                 recomputes the next band's first line */
+ *   split_long    lines longer than 512 cells: 1 (default) two launches
+ *                 per sweep, the first three lines of every band of four,
+ *                 then the fourth lines reading their final neighbours
+ *                 (forward sweeps written in their own layout; on lines
+ *                 longer than 1024 cells also the reverse sweeps, written
+ *                 to a free plane in their own layout and then transposed
+ *                 to the next sweep's); 0 one launch that recomputes the
+ *                 next band's first line */
 typedef struct {
     int32_t lds_side;
     int32_t line_threads;
