@@ -15,11 +15,12 @@
 // [IC][tap][OC]); FP32 master weights with Adam.  Every channel count is a
 // multiple of 16 (the input's 3 channels are padded with zeros to 16).
 //
-// Convolutions are implicit GEMMs on the matrix cores
-// (mfma_f32_16x16x16bf16, FP32 accumulation):
+// Convolutions are implicit GEMMs on the matrix cores (FP32 accumulation;
+// k_conv on mfma_f32_16x16x32_bf16, a 16-channel remainder and k_wgrad on
+// mfma_f32_16x16x16bf16_1k):
 //   forward / data gradient (k_conv): M = output channels, N = pixels,
 //     K = 9 taps x input channels.  A block computes 32 channels x an 8 x 32
-//     pixel tile; per 16-channel chunk the tile's input halo (10 x 34
+//     pixel tile; per 32-channel chunk the tile's input halo (10 x 34
 //     pixels) is staged in LDS and each wave keeps the weights of all 9
 //     taps in registers.
 //   weight gradient (k_wgrad): M = output channels, N = 9 taps x input
@@ -45,7 +46,7 @@ namespace {
 constexpr int CIN0 = 16;                       // input channels after padding
 constexpr int TY = 8, TX = 32;                 // pixel tile of a block
 constexpr int HY = TY + 2, HX = TX + 2;        // its halo
-constexpr int HP = 24;                         // LDS elements per halo pixel in k_conv (16 used; 48 B keeps lanes apart)
+constexpr int HP = 40;                         // LDS elements per halo pixel in k_conv (32 used; 80 B keeps lanes apart)
 constexpr int OCB = 32;                        // output channels per block
 constexpr int GTS = TY * TX + 8;               // k_wgrad: LDS row of the transposed output gradient
 constexpr int XRS = 36;                        // k_wgrad: LDS halo row (34 used)
@@ -76,11 +77,67 @@ struct ConvArgs {
     int IC, OC, H, W, relu;
 };
 
-__global__ void __launch_bounds__(256) k_conv(ConvArgs A)
+// One chunk of KC input channels (32: mfma_f32_16x16x32_bf16, 8 channels per
+// lane and operand; 16: mfma_f32_16x16x16bf16_1k, 4 per lane).  Lane group
+// g = lane / 16 brings the same channels c0 + V g .. c0 + V g + V - 1 to the
+// weight operand (row l16 = output channel) and to the pixel operand (column
+// l16 = pixel), so each product pairs one channel of both whatever order the
+// instruction sums its K terms in.
+template <int KC>
+__device__ __forceinline__ void conv_chunk(const ConvArgs &A, uint16_t *halo, int c0, const uint16_t *w0,
+                                           const uint16_t *w1, bool two, int ty0, int tx0, long long img, int wave,
+                                           int l16, int g, f32x4 (&acc)[2][4])
+{
+    constexpr int V = KC / 4;
+    typedef short vec __attribute__((ext_vector_type(V)));
+    vec wa[2][9];
+#pragma unroll
+    for (int r = 0; r < 9; r++) {
+        wa[0][r] = *(const vec *)(w0 + r * A.IC + c0 + V * g);
+        wa[1][r] = two ? *(const vec *)(w1 + r * A.IC + c0 + V * g) : vec{};
+    }
+    __syncthreads();                                // the previous chunk's halo is no longer read
+    constexpr int Q = KC / 8;                       // 16-byte pieces per halo pixel
+    for (int u = threadIdx.x; u < HY * HX * Q; u += 256) {
+        const int hp = u / Q, part = u - hp * Q;
+        const int hy = hp / HX, hx = hp - hy * HX;
+        const int y = ty0 + hy - 1, x = tx0 + hx - 1;
+        uint4 v = {0u, 0u, 0u, 0u};
+        if (y >= 0 && y < A.H && x >= 0 && x < A.W)
+            v = *(const uint4 *)(A.in + (img + (long long)y * A.W + x) * A.ips + A.ioff + c0 + 8 * part);
+        *(uint4 *)(halo + hp * HP + 8 * part) = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 9; r++) {
+        const int dy = r / 3, dx = r % 3;
+#pragma unroll
+        for (int p = 0; p < 4; p++) {
+            const int yr = 2 * wave + (p >> 1), xo = 16 * (p & 1);
+            const vec bv = *(const vec *)(halo + ((yr + dy) * HX + xo + l16 + dx) * HP + V * g);
+            if constexpr (KC == 32) {
+                typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+                const bf8 b = __builtin_bit_cast(bf8, bv);
+                acc[0][p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, wa[0][r]), b, acc[0][p], 0,
+                                                                   0, 0);
+                if (two)
+                    acc[1][p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, wa[1][r]), b,
+                                                                       acc[1][p], 0, 0, 0);
+            } else {
+                acc[0][p] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wa[0][r], bv, acc[0][p], 0, 0, 0);
+                if (two) acc[1][p] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wa[1][r], bv, acc[1][p], 0, 0, 0);
+            }
+        }
+    }
+}
+
+// At most 168 registers per lane (three waves per SIMD): the 9 taps' weights
+// of two 16-channel tiles take 72 of them.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_conv(ConvArgs A)
 {
     __shared__ __attribute__((aligned(16))) uint16_t halo[HY * HX * HP];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int l16 = lane & 15, g4 = (lane >> 4) * 4;
+    const int l16 = lane & 15, g = lane >> 4, g4 = 4 * g;
     const int tilesx = (A.W + TX - 1) / TX;
     const int ty0 = (int)(blockIdx.x / tilesx) * TY, tx0 = (int)(blockIdx.x % tilesx) * TX;
     const int oc0 = blockIdx.y * OCB;
@@ -91,38 +148,11 @@ __global__ void __launch_bounds__(256) k_conv(ConvArgs A)
     for (int t = 0; t < 2; t++)
 #pragma unroll
         for (int p = 0; p < 4; p++) acc[t][p] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    const uint16_t *w0 = A.Wk + (long long)(oc0 + l16) * 9 * A.IC + g4;
-    const uint16_t *w1 = A.Wk + (long long)(oc0 + 16 + (two ? l16 : 0)) * 9 * A.IC + g4;
-    for (int c0 = 0; c0 < A.IC; c0 += 16) {
-        bf16x4 wa[2][9];
-#pragma unroll
-        for (int r = 0; r < 9; r++) {
-            wa[0][r] = *(const bf16x4 *)(w0 + r * A.IC + c0);
-            wa[1][r] = two ? *(const bf16x4 *)(w1 + r * A.IC + c0) : bf16x4{0, 0, 0, 0};
-        }
-        __syncthreads();                            // the previous chunk's halo is no longer read
-        for (int u = threadIdx.x; u < HY * HX * 2; u += 256) {
-            const int hp = u >> 1, half = u & 1;
-            const int hy = hp / HX, hx = hp - hy * HX;
-            const int y = ty0 + hy - 1, x = tx0 + hx - 1;
-            uint4 v = {0u, 0u, 0u, 0u};
-            if (y >= 0 && y < A.H && x >= 0 && x < A.W)
-                v = *(const uint4 *)(A.in + (img + (long long)y * A.W + x) * A.ips + A.ioff + c0 + 8 * half);
-            *(uint4 *)(halo + hp * HP + 8 * half) = v;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < 9; r++) {
-            const int dy = r / 3, dx = r % 3;
-#pragma unroll
-            for (int p = 0; p < 4; p++) {
-                const int yr = 2 * wave + (p >> 1), xo = 16 * (p & 1);
-                const bf16x4 bv = *(const bf16x4 *)(halo + ((yr + dy) * HX + xo + l16 + dx) * HP + g4);
-                acc[0][p] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wa[0][r], bv, acc[0][p], 0, 0, 0);
-                if (two) acc[1][p] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wa[1][r], bv, acc[1][p], 0, 0, 0);
-            }
-        }
-    }
+    const uint16_t *w0 = A.Wk + (long long)(oc0 + l16) * 9 * A.IC;
+    const uint16_t *w1 = A.Wk + (long long)(oc0 + 16 + (two ? l16 : 0)) * 9 * A.IC;
+    int c0 = 0;
+    for (; c0 + 32 <= A.IC; c0 += 32) conv_chunk<32>(A, halo, c0, w0, w1, two, ty0, tx0, img, wave, l16, g, acc);
+    if (c0 < A.IC) conv_chunk<16>(A, halo, c0, w0, w1, two, ty0, tx0, img, wave, l16, g, acc);
     // D[row = 4 (lane / 16) + i][col = lane % 16]: 4 consecutive channels of one pixel
 #pragma unroll
     for (int p = 0; p < 4; p++) {
