@@ -444,6 +444,14 @@ mgseg_status mgseg_net_adam_step(mgseg_net *n, double lr, double b1, double b2, 
 mgseg_status mgseg_net_param_count(mgseg_net *n, long long *count);
 mgseg_status mgseg_net_get_params(mgseg_net *n, float *host, float *grad_host);
 mgseg_status mgseg_net_set_params(mgseg_net *n, const float *host);
+/* The Adam state in the same order: first moments m and second moments v
+ * (host buffers of `count` floats; either may be null on _get, both are
+ * required on _set) and the number of steps taken, which sets the bias
+ * correction of the next step.  Restoring them after set_params resumes an
+ * interrupted training run with the same updates it would have made.
+ * _set: steps outside 0..2^31-1 or a null buffer give MGSEG_E_ARG. */
+mgseg_status mgseg_net_get_adam(mgseg_net *n, float *m_host, float *v_host, long long *steps);
+mgseg_status mgseg_net_set_adam(mgseg_net *n, const float *m_host, const float *v_host, long long steps);
 void mgseg_net_destroy(mgseg_net *n);
 
 /* Convolution timing.  While enabled, every k_conv launch (forward and data

@@ -1028,6 +1028,36 @@ mgseg_status mgseg_net_get_params(mgseg_net *n, float *host, float *grad_host)
     return ok ? MGSEG_OK : MGSEG_E_HIP;
 }
 
+mgseg_status mgseg_net_get_adam(mgseg_net *n, float *m_host, float *v_host, long long *steps)
+{
+    if (!n) return MGSEG_E_ARG;
+    if (hipDeviceSynchronize() != hipSuccess) return MGSEG_E_HIP;
+    long long off = 0;
+    bool ok = true;
+    for_params(n, [&](float *, float *, float *m, float *v, long long k) {
+        if (m_host) ok &= hipMemcpy(m_host + off, m, k * sizeof(float), hipMemcpyDeviceToHost) == hipSuccess;
+        if (v_host) ok &= hipMemcpy(v_host + off, v, k * sizeof(float), hipMemcpyDeviceToHost) == hipSuccess;
+        off += k;
+    });
+    if (steps) *steps = n->steps;
+    return ok ? MGSEG_OK : MGSEG_E_HIP;
+}
+
+mgseg_status mgseg_net_set_adam(mgseg_net *n, const float *m_host, const float *v_host, long long steps)
+{
+    if (!n || !m_host || !v_host || steps < 0 || steps > 0x7fffffffLL) return MGSEG_E_ARG;
+    if (hipDeviceSynchronize() != hipSuccess) return MGSEG_E_HIP;
+    long long off = 0;
+    bool ok = true;
+    for_params(n, [&](float *, float *, float *m, float *v, long long k) {
+        ok &= hipMemcpy(m, m_host + off, k * sizeof(float), hipMemcpyHostToDevice) == hipSuccess;
+        ok &= hipMemcpy(v, v_host + off, k * sizeof(float), hipMemcpyHostToDevice) == hipSuccess;
+        off += k;
+    });
+    n->steps = (int)steps;
+    return ok ? MGSEG_OK : MGSEG_E_HIP;
+}
+
 mgseg_status mgseg_net_set_params(mgseg_net *n, const float *host)
 {
     if (!n || !host) return MGSEG_E_ARG;

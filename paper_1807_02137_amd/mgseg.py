@@ -158,6 +158,8 @@ def lib():
         L.mgseg_net_param_count.argtypes = [vp, C.POINTER(C.c_longlong)]
         L.mgseg_net_get_params.argtypes = [vp, vp, vp]
         L.mgseg_net_set_params.argtypes = [vp, vp]
+        L.mgseg_net_get_adam.argtypes = [vp, vp, vp, C.POINTER(C.c_longlong)]
+        L.mgseg_net_set_adam.argtypes = [vp, vp, vp, C.c_longlong]
         L.mgseg_net_destroy.argtypes = [vp]
         L.mgseg_net_destroy.restype = None
         L.mgseg_ctx_features.argtypes = [vp, vp]
@@ -173,7 +175,8 @@ def lib():
                      "mgseg_profile", "mgseg_profile_read", "mgseg_setup_batch", "mgseg_batch_tune",
                      "mgseg_batch_set_streams", "mgseg_solve_batch", "mgseg_batch_ctx", "mgseg_net_create",
                      "mgseg_net_forward", "mgseg_net_backward", "mgseg_net_adam_step", "mgseg_net_param_count",
-                     "mgseg_net_get_params", "mgseg_net_set_params", "mgseg_ctx_features", "mgseg_predict_phi0",
+                     "mgseg_net_get_params", "mgseg_net_set_params", "mgseg_net_get_adam", "mgseg_net_set_adam",
+                     "mgseg_ctx_features", "mgseg_predict_phi0",
                      "mgseg_reset_phi0", "mgseg_net_profile", "mgseg_net_profile_read",
                      "mgseg_get_state", "mgseg_set_state", "mgseg_solve_noalloc", "mgseg_aos",
                      "mgseg_smoothing_rates", "mgseg_get_schedule", "mgseg_set_schedule", "mgseg_tune"):
@@ -511,6 +514,20 @@ class Net:
         if v.size != self.count:
             raise ValueError(f"expected {self.count} parameters, got {v.size}")
         _check(self.L.mgseg_net_set_params(self.h, v.ctypes.data_as(C.c_void_p)), "mgseg_net_set_params")
+
+    def adam_state(self):
+        """(first moments, second moments, steps taken) of Adam, host arrays in the parameter order."""
+        m, v, t = np.zeros(self.count, np.float32), np.zeros(self.count, np.float32), C.c_longlong()
+        _check(self.L.mgseg_net_get_adam(self.h, m.ctypes.data_as(C.c_void_p), v.ctypes.data_as(C.c_void_p),
+                                         C.byref(t)), "mgseg_net_get_adam")
+        return m, v, t.value
+
+    def set_adam_state(self, m, v, steps):
+        m, v = np.ascontiguousarray(m, np.float32), np.ascontiguousarray(v, np.float32)
+        if m.size != self.count or v.size != self.count:
+            raise ValueError(f"expected {self.count} moments each, got {m.size} and {v.size}")
+        _check(self.L.mgseg_net_set_adam(self.h, m.ctypes.data_as(C.c_void_p), v.ctypes.data_as(C.c_void_p),
+                                         int(steps)), "mgseg_net_set_adam")
 
     def profile(self, enable=True):
         """Time every convolution launch with HIP events (clears the record)."""

@@ -207,18 +207,25 @@ def choose_scale(net: mgseg.Net, instances, params: mgseg.Params, scales=(1.0, 0
     return min(ok, key=lambda sc: stats[sc]["cycles"])
 
 
-def save(net: mgseg.Net, path, scale=1.0):
+def save(net: mgseg.Net, path, scale=1.0, optimizer=True):
     """The network's parameters (library order), its shape and the amplitude
-    of its phi0, as .npz."""
+    of its phi0, as .npz; with optimizer, also Adam's moments and step count,
+    so that training can resume where it stopped."""
     p, _ = net.params()
-    np.savez(path, params=p, base=net.base, depth=net.depth, scale=scale)
+    extra = {}
+    if optimizer:
+        m, v, t = net.adam_state()
+        extra = dict(adam_m=m, adam_v=v, adam_steps=t)
+    np.savez(path, params=p, base=net.base, depth=net.depth, scale=scale, **extra)
 
 
 def load(path):
-    """(network, amplitude) saved by save()."""
+    """(network, amplitude) saved by save(), with Adam's state where saved."""
     d = np.load(path)
     net = mgseg.Net(int(d["base"]), int(d["depth"]))
     net.set_params(d["params"])
+    if "adam_m" in d:
+        net.set_adam_state(d["adam_m"], d["adam_v"], int(d["adam_steps"]))
     return net, float(d["scale"]) if "scale" in d else 1.0
 
 

@@ -151,6 +151,51 @@ def test_adam_steps_follow_the_update_rule():
     net.close()
 
 
+def test_adam_state_round_trip_resumes_training(tmp_path):
+    """A network given another's parameters and Adam state (moments, step
+    count) takes the same next step, bit for bit; with the parameters alone
+    (moments cleared, bias correction restarted) it does not.  The checkpoint
+    of warmstart.save / load carries the same state."""
+    say("case net adam state")
+    from paper_1807_02137_amd import warmstart
+    base, depth = 16, 3
+    rng = np.random.default_rng(19)
+    x = torch.tensor(features(rng, 2, 24, 40), dtype=torch.float32)
+    tgt = torch.tensor(rng.uniform(-6, 6, (2, 24, 40)), dtype=torch.float32)
+
+    def step(n):
+        n.forward(x, M)
+        n.backward(tgt, M)
+        n.adam_step(1e-2)
+
+    a = mgseg.Net(base, depth, 9)
+    step(a)
+    step(a)
+    p, _ = a.params()
+    m, v, t = a.adam_state()
+    assert t == 2 and np.abs(m).max() > 0 and np.abs(v).max() > 0
+    path = str(tmp_path / "ckpt.npz")
+    warmstart.save(a, path)
+    b = mgseg.Net(base, depth, 123)
+    b.set_params(p)
+    b.set_adam_state(m, v, t)
+    c, _ = warmstart.load(path)
+    fresh = mgseg.Net(base, depth, 5)
+    fresh.set_params(p)
+    assert fresh.adam_state()[2] == 0 and not np.abs(fresh.adam_state()[0]).any()
+    for n in (a, b, c, fresh):
+        step(n)
+    pa = a.params()[0]
+    assert np.array_equal(b.params()[0], pa)
+    assert np.array_equal(c.params()[0], pa)
+    mc, vc, tc = c.adam_state()
+    ma, va, ta = a.adam_state()
+    assert tc == ta == 3 and np.array_equal(mc, ma) and np.array_equal(vc, va)
+    assert not np.array_equal(fresh.params()[0], pa)
+    for n in (a, b, c, fresh):
+        n.close()
+
+
 def test_training_lowers_the_loss_on_a_fixed_batch():
     """The loss is a cross-entropy against soft targets q = (1 + t / M) / 2,
     whose minimum over all outputs is the mean binary entropy of q; Adam on
