@@ -245,13 +245,15 @@ void update_fit(mgseg_ctx *c)
                        (float)c->p.theta, c->p.model);
 }
 
-// c1, c2 (eq. c1c2) from the FP64 finest phi
-void update_c(mgseg_ctx *c)
+// c1, c2 (eq. c1c2) from the FP64 finest phi; sums_done: the partial sums are
+// already in c->part (k_finish0_sums)
+void update_c(mgseg_ctx *c, bool sums_done = false)
 {
     Level &L = c->lev[0];
     int nb = std::min(RED_BLOCKS, std::max(1, (c->n * c->m + 255) / 256));
-    hipLaunchKernelGGL(k_sums<double>, dim3(nb), dim3(256), 0, c->s, c->phi64, c->m, L.z, L.prm, c->n, c->m,
-                       c->p.eps, c->part);
+    if (!sums_done)
+        hipLaunchKernelGGL(k_sums<double>, dim3(nb), dim3(256), 0, c->s, c->phi64, c->m, L.z, L.prm, c->n, c->m,
+                           c->p.eps, c->part);
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FIN_NT), 0, c->s, c->part, nb, 1, (double)c->n * c->m, 0.0, 0.0, 0.0,
                        c->dsc + DS_C1);
     update_fit(c);
@@ -791,22 +793,30 @@ void enqueue_cycle(mgseg_ctx *c)
 {
     Level &L0 = c->lev[0];
     size_t N = (size_t)c->n * c->m;
-    (void)hipMemcpyAsync(c->prev64, c->phi64, sizeof(double) * N, hipMemcpyDeviceToDevice, c->s);
+    const int nb = std::min(RED_BLOCKS, std::max(1, (int)((N + 255) / 256)));
     dim3 g = grid2(c->n, c->m);
     if (c->p.mixed_precision) {
+        // the base phi64 stays fixed through the V-cycle, so the cycle's end takes the
+        // change and the c1, c2 sums in the pass that updates it
         const dim3 gt((c->m + TILE - 1) / TILE, (c->n + TILE - 1) / TILE);
         const dim3 tb(TILE, tile_rows((long long)gt.x * gt.y));
         hipLaunchKernelGGL(k_start0, gt, tb, 0, c->s, c->phi64, c->n, c->m, c->p.M, L0.P[0], L0.lo, L0.hi, L0.prm,
                            L0.lo_cm, L0.hi_cm, L0.pcm);
+        vcycle_from(c, 0);
+        hipLaunchKernelGGL(k_finish0_sums, dim3(nb), dim3(256), 0, c->s, c->phi64, L0.P[0], L0.lo, L0.hi, L0.prm,
+                           L0.z, L0.prm, c->n, c->m, c->p.M, c->p.eps, c->part, c->part + 4 * RED_BLOCKS);
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FIN_NT), 0, c->s, c->part + 4 * RED_BLOCKS, nb, 3, 0.0, 0.0, 0.0,
+                           0.0, c->dsc + DS_ETA);
+        update_c(c, true);
+        res64(c);
+        c->lev[0].has_F = false;
+        chk(c);
+        return;
     }
+    (void)hipMemcpyAsync(c->prev64, c->phi64, sizeof(double) * N, hipMemcpyDeviceToDevice, c->s);
     vcycle_from(c, 0);
-    if (c->p.mixed_precision)
-        hipLaunchKernelGGL(k_finish0, g, dim3(256), 0, c->s, c->phi64, L0.P[0], L0.lo, L0.hi, L0.prm, c->n, c->m,
-                           c->p.M);
-    else
-        hipLaunchKernelGGL(k_copy32to64, g, dim3(256), 0, c->s, L0.P[0], L0.prm, c->phi64, c->n, c->m);
+    hipLaunchKernelGGL(k_copy32to64, g, dim3(256), 0, c->s, L0.P[0], L0.prm, c->phi64, c->n, c->m);
     refresh_and_residual(c);
-    int nb = std::min(RED_BLOCKS, std::max(1, (int)((N + 255) / 256)));
     hipLaunchKernelGGL(k_eta, dim3(nb), dim3(256), 0, c->s, c->phi64, c->prev64, (long long)N, c->part + 4 * RED_BLOCKS);
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FIN_NT), 0, c->s, c->part + 4 * RED_BLOCKS, nb, 3, 0.0, 0.0, 0.0, 0.0,
                        c->dsc + DS_ETA);

@@ -663,17 +663,55 @@ __global__ void __launch_bounds__(1024) k_start0(const double *b, int n, int m, 
     }
 }
 
-// finest-grid cycle end: phi64 = clip(b + e); a deviation at its bound lands
-// exactly on the bound
-__global__ void k_finish0(double *b, const float *e, const float *lo, const float *hi, int p, int n, int m, double M)
+// finest-grid cycle end: phi64 = clip(b + e) (a deviation at its bound lands
+// exactly on the bound), with the sums the cycle's end needs taken in the same
+// pass: sum H(phi), sum H(phi) z, sum z at the new phi (c1, c2) into pc, and
+// sum (phi - b)^2, sum b^2 (the relative change eta, b being the value the
+// cycle started from) into pe.  Cells go to threads as in k_sums and k_eta
+// (grid-stride over the row-major index, gridDim.x x 256 threads) and the
+// block sums take the same tree, so with the same grid every sum has the bits
+// of those kernels run after the update.
+__global__ void __launch_bounds__(256) k_finish0_sums(double *b, const float *e, const float *lo, const float *hi,
+                                                      int p, const float *z, int pz, int n, int m, double M,
+                                                      double eps, double *pc, double *pe)
 {
-    int j = blockIdx.x * blockDim.x + threadIdx.x, i = blockIdx.y;
-    if (j >= m || i >= n) return;
-    long long q = (long long)i * p + j;
-    double v = b[(long long)i * m + j] + (double)e[q];
-    if (e[q] >= hi[q]) v = M;
-    if (e[q] <= lo[q]) v = -M;
-    b[(long long)i * m + j] = v < -M ? -M : (v > M ? M : v);
+    __shared__ double r0[256], r1[256], r2[256], r3[256], r4[256];
+    const int tid = threadIdx.x;
+    const long long N = (long long)n * m, stride = (long long)gridDim.x * blockDim.x;
+    long long t = (long long)blockIdx.x * blockDim.x + tid;
+    int i = (int)(t / m), j = (int)(t % m);
+    const int di = (int)(stride / m), dj = (int)(stride % m);
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, d0 = 0.0, d1 = 0.0;
+    for (; t < N; t += stride) {
+        const long long q = (long long)i * p + j, qb = (long long)i * m + j;
+        const double old = b[qb];
+        const float ev = e[q];
+        double v = old + (double)ev;
+        if (ev >= hi[q]) v = M;
+        if (ev <= lo[q]) v = -M;
+        v = v < -M ? -M : (v > M ? M : v);
+        b[qb] = v;
+        const double H = mg_heav64(v, eps);
+        const double zz = (double)z[(long long)i * pz + j];
+        a0 += H; a1 += H * zz; a2 += zz;
+        const double d = v - old;
+        d0 += d * d; d1 += old * old;
+        j += dj; i += di;
+        if (j >= m) { j -= m; i++; }
+    }
+    r0[tid] = a0; r1[tid] = a1; r2[tid] = a2; r3[tid] = d0; r4[tid] = d1;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (tid < s) {
+            r0[tid] += r0[tid + s]; r1[tid] += r1[tid + s]; r2[tid] += r2[tid + s];
+            r3[tid] += r3[tid + s]; r4[tid] += r4[tid + s];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        pc[3 * blockIdx.x] = r0[0]; pc[3 * blockIdx.x + 1] = r1[0]; pc[3 * blockIdx.x + 2] = r2[0];
+        pe[2 * blockIdx.x] = r3[0]; pe[2 * blockIdx.x + 1] = r4[0];
+    }
 }
 
 template <typename BT>

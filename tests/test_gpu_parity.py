@@ -52,6 +52,28 @@ def test_setup_maps():
     s.close()
 
 
+@pytest.mark.parametrize("mixed,kw", [(1, {}), (1, {"model": 1}), (0, {})])
+def test_cycle_end_sums(mixed, kw):
+    """The sums a cycle ends with: c1, c2 (eq. c1c2) equal the oracle's at the
+    cycle's new FP64 phi, and eta equals the relative change of phi over the
+    cycle summed on the host (the mixed mode takes them in the pass that
+    updates phi)."""
+    say("case cycle-end sums mixed", mixed, kw)
+    inst, s, o = make(mixed=mixed, **kw)
+    s.vcycle()
+    p0 = s.get("phi64")
+    s.vcycle()
+    p1, st = s.get("phi64"), s.stats()
+    eta = float(np.sqrt(((p1 - p0) ** 2).sum() / (p0 ** 2).sum()))
+    o.set("phi", p1)
+    o.update_c()
+    sc = o.scalars()
+    say(f"  eta {st['eta']:.12e} host {eta:.12e}; c1 {st['c1']:.15f} oracle {sc['c1']:.15f}")
+    assert eta > 0 and abs(st["eta"] - eta) <= 1e-12 * eta
+    assert abs(st["c1"] - sc["c1"]) <= 1e-12 and abs(st["c2"] - sc["c2"]) <= 1e-12
+    s.close()
+
+
 def test_labels_match():
     """Labels of the jump set (Sec. 4.1, Sec. 5.2) from the GPU's FP32 face values
     against the oracle's FP64 ones: every mismatch must be a near-tie of the
