@@ -235,7 +235,8 @@ void update_fit(mgseg_ctx *c)
     F.trow0[0] = 0;
     for (int l = 0; l < c->L; l++) {
         const Level &L = c->lev[l];
-        F.z[l] = L.z; F.d[l] = L.d; F.fit[l] = L.fit; F.fit_cm[l] = L.fit_cm;
+        // the mixed mode's column sweeps take the fit term inside T: no column-major copy
+        F.z[l] = L.z; F.d[l] = L.d; F.fit[l] = L.fit; F.fit_cm[l] = devm(c) ? nullptr : L.fit_cm;
         F.p[l] = L.prm; F.pc[l] = L.pcm; F.n[l] = L.n; F.m[l] = L.m;
         F.trow0[l + 1] = F.trow0[l] + (L.n + TILE - 1) / TILE;
     }

@@ -357,7 +357,7 @@ __global__ void k_coarse_rhs(const float *phic, const float *w, const float *fit
 // fit maps of every level with the current c1, c2 (Spencer-Chen adds theta d),
 // one launch of 32 x 32 tiles, block (32, tile_rows): block row y covers tile row
 // y - trow0[l] of the level l whose tile rows [trow0[l], trow0[l+1]) contain
-// y; the column-major copy goes through LDS
+// y; the column-major copy goes through LDS (fit_cm[l] null: not written)
 #define FIT_MAXLEV 16
 struct FitLevels {
     const float *z[FIT_MAXLEV], *d[FIT_MAXLEV];
@@ -375,6 +375,7 @@ __global__ void __launch_bounds__(1024) k_fit(FitLevels F, const double *c12, fl
     const int by = ((int)blockIdx.y - F.trow0[l]) * TILE, bx = blockIdx.x * TILE;
     if (bx >= m) return;                   // the whole block: narrower level
     const float c1 = (float)c12[0], c2 = (float)c12[1];
+    const bool cm = F.fit_cm[l] != nullptr;          // the same for the whole block
     for (int y = threadIdx.y; y < TILE; y += blockDim.y) {
         const int i = by + y, j = bx + threadIdx.x;
         if (i >= n || j >= m) continue;
@@ -383,8 +384,9 @@ __global__ void __launch_bounds__(1024) k_fit(FitLevels F, const double *c12, fl
         float v = l1 * a * a - l2 * b * b;
         if (model == 0) v += theta * F.d[l][q];
         F.fit[l][q] = v;
-        tf[y][threadIdx.x] = v;
+        if (cm) tf[y][threadIdx.x] = v;
     }
+    if (!cm) return;
     __syncthreads();
     for (int y = threadIdx.y; y < TILE; y += blockDim.y) {
         const int j = bx + y, i = by + threadIdx.x;
