@@ -11,7 +11,7 @@
 // order line by line.
 //
 // GSLEX-II: one thread per row of the class, walking its row left to right:
-// at each pixel the refreshed row (dev_cell: the face coefficients au and the
+// at each pixel the refreshed row (the face coefficients au and the
 // right-hand side T at the current b + e) and the point update
 //   e_ij <- clip((sum au e_nb - T) / sum au, lo, hi),
 // the left neighbour already updated.  A row is inherently sequential (the
@@ -26,6 +26,34 @@
 #include "mgseg_kernels.h"
 
 // skip: non-null and set, the launch does nothing (the coarsest solve's stop)
+//
+// The thread keeps b, e and w of its 3 x 3 stencil in registers (columns
+// j-1, j, j+1 of rows i-1, i, i+1; the half-sample mirror at the grid edge
+// names the cell itself, so an edge never needs the slot beyond it) and
+// reads column j+2 one step ahead, so a step waits on no memory: its own
+// row's left neighbour is the value it has just written.  The values are
+// those of global memory at that point of the walk, so the result is the
+// same bit for bit as reading them there.
+// (named scalars rather than arrays, so that no select between them turns
+// into an indexed load from scratch memory)
+template <typename T>
+struct Win3 {
+    T u0, u1, u2, c0, c1, c2, d0, d1, d2;    // rows i-1, i, i+1 (mirrored) x columns j-1, j, j+1
+    __device__ __forceinline__ T at(int a, int c, int i, int j) const
+    {
+        const T vu = c < j ? u0 : (c == j ? u1 : u2);
+        const T vc = c < j ? c0 : (c == j ? c1 : c2);
+        const T vd = c < j ? d0 : (c == j ? d1 : d2);
+        return a < i ? vu : (a == i ? vc : vd);
+    }
+    __device__ __forceinline__ void shift(T nu, T nc, T nd)
+    {
+        u0 = u1; u1 = u2; u2 = nu;
+        c0 = c1; c1 = c2; c2 = nc;
+        d0 = d1; d1 = d2; d2 = nd;
+    }
+};
+
 template <typename BT>
 __global__ void __launch_bounds__(64) k_gslex_local(DevArgs<BT> A, int cls, const int *skip)
 {
@@ -33,20 +61,47 @@ __global__ void __launch_bounds__(64) k_gslex_local(DevArgs<BT> A, int cls, cons
     const int i = cls + 4 * (int)(blockIdx.x * blockDim.x + threadIdx.x);
     if (i >= A.n) return;
     float *e = const_cast<float *>(A.e);
+    const int n = A.n, m = A.m;
     const long long row = (long long)i * A.p;
-    for (int j = 0; j < A.m; j++) {
+    const long long ru = (long long)mg_mirror(i - 1, n), rd = (long long)mg_mirror(i + 1, n);
+    const long long pu = ru * A.p, pd = rd * A.p, bu = ru * A.pb, bc = (long long)i * A.pb, bd = rd * A.pb;
+    Win3<BT> wb;
+    Win3<float> we, ww;
+    // column c of the three rows (past the edge: a column that is never read)
+    BT nbu, nbc, nbd;
+    float neu, nec, ned, nwu, nwc, nwd;
+    auto fetch = [&](int c) {
+        const int cc = c < m ? c : m - 1;
+        nbu = A.b[bu + cc]; nbc = A.b[bc + cc]; nbd = A.b[bd + cc];
+        neu = e[pu + cc]; nec = e[row + cc]; ned = e[pd + cc];
+        nwu = A.w[pu + cc]; nwc = A.w[row + cc]; nwd = A.w[pd + cc];
+    };
+    fetch(0);
+    wb.shift(nbu, nbc, nbd); we.shift(neu, nec, ned); ww.shift(nwu, nwc, nwd);
+    wb.shift(nbu, nbc, nbd); we.shift(neu, nec, ned); ww.shift(nwu, nwc, nwd);
+    fetch(1);
+    wb.shift(nbu, nbc, nbd); we.shift(neu, nec, ned); ww.shift(nwu, nwc, nwd);
+    for (int j = 0; j < m; j++) {
+        fetch(j + 2);
+        // stencil cell (a, c): after mirroring one of (i - 1 | i | i + 1) x (j - 1 | j | j + 1)
+        auto Bv = [&](int a, int c) { return wb.at(a, c, i, j); };
+        auto Ev = [&](int a, int c) { return we.at(a, c, i, j); };
+        auto Wv = [&](int a, int c) { return ww.at(a, c, i, j); };
         double Le;
         float u0, au[4];
         uint8_t lab;
-        const double t = dev_cell(A, i, j, false, Le, u0, lab, au);
+        const double t = dev_cell_at(A, i, j, false, Le, u0, lab, au, Bv, Ev, Wv);
         const float S = au[0] + au[1] + au[2] + au[3];
-        if (!(S > 0.0f)) continue;
-        float v = -(float)t;
-        if (i + 1 < A.n) v = fmaf(au[0], e[row + A.p + j], v);
-        if (i > 0) v = fmaf(au[1], e[row - A.p + j], v);
-        if (j + 1 < A.m) v = fmaf(au[2], e[row + j + 1], v);
-        if (j > 0) v = fmaf(au[3], e[row + j - 1], v);
-        e[row + j] = mg_clip(v / S, A.lo[row + j], A.hi[row + j]);
+        if (S > 0.0f) {
+            float v = -(float)t;
+            if (i + 1 < n) v = fmaf(au[0], we.d1, v);
+            if (i > 0) v = fmaf(au[1], we.u1, v);
+            if (j + 1 < m) v = fmaf(au[2], we.c2, v);
+            if (j > 0) v = fmaf(au[3], we.c0, v);
+            we.c1 = mg_clip(v / S, A.lo[row + j], A.hi[row + j]);
+            e[row + j] = we.c1;
+        }
+        wb.shift(nbu, nbc, nbd); we.shift(neu, nec, ned); ww.shift(nwu, nwc, nwd);
     }
 }
 
