@@ -946,6 +946,12 @@ __device__ __forceinline__ CellRow row_load(const Buf &B, int p)
 // other while this one's cells still read theirs after the scan; the masks
 // are read before the scan only.
 // OR of the per-wave flags of the workgroup (after the barrier that published them)
+// Passes of the parallel active-set repair before a failed unit is finished by
+// its first cell's serial iteration.  The held set of a whole-line system can
+// move along the line a few cells per pass, and its serial finish costs
+// milliseconds on a line of hundreds of cells, so whole lines take more passes.
+// (Both halves of a two-half workgroup count the passes with this.)
+__device__ __forceinline__ constexpr int repair_passes(bool whole) { return whole ? 256 : 8; }
 __device__ __forceinline__ bool block_flag(const unsigned *wflag)
 {
     const int ln = threadIdx.x & 63;
@@ -1108,8 +1114,8 @@ __device__ __forceinline__ float sweep_line(const LineArgs &A, int r, const RunB
     // iteration run in parallel: the held state of every cell of such a unit lives in RF_Q (-1 at
     // lo, -2 at hi, 0 free; at first the state of z), every cell eliminates its free chain up to
     // the next held cell, a second scan substitutes, and the cells update their held states, until
-    // none changes.  After eight such passes the thread of the unit's first cell (which holds the
-    // entering value) would finish the unit with the serial iteration.  One-wave lines synchronise
+    // none changes.  After repair_passes such passes the thread of the unit's first cell (which
+    // holds the entering value) finishes the unit with the serial iteration.  One-wave lines synchronise
     // only where a unit failed; wider lines publish one flag per wave and take one barrier (the
     // other half of a two-half workgroup takes it too), and the repair's barriers only where a
     // unit failed.
@@ -1231,7 +1237,7 @@ __device__ __forceinline__ float sweep_line(const LineArgs &A, int r, const RunB
                 more = block_flag(wbad);
             }
             if (!more) break;
-            if (pass == 7) {
+            if (pass + 1 == repair_passes(whole)) {
                 if (fu && p == ps) long_active_set(B, ps, Lu, ml, x);
                 if (NT == 64 && WS) wave_lds_sync();
                 else __syncthreads();
@@ -1439,7 +1445,7 @@ __device__ __forceinline__ void sweep_band2(const LineArgs &A, int b, const RunB
                 __syncthreads();
                 if (block_flag(wbad)) {
                     // the repair's passes: [whole lines: elimination scan and its publication,]
-                    // scan, values, flags (and the serial finish after eight)
+                    // scan, values, flags (and the serial finish after repair_passes)
                     for (int pass = 0;; pass++) {
                         if (whole) {
                             if (NT > 64) __syncthreads();
@@ -1450,7 +1456,7 @@ __device__ __forceinline__ void sweep_band2(const LineArgs &A, int b, const RunB
                         if (l0) wbad[threadIdx.x >> 6] = 0u;
                         __syncthreads();
                         if (!block_flag(wbad)) break;
-                        if (pass == 7) {
+                        if (pass + 1 == repair_passes(whole)) {
                             __syncthreads();
                             break;
                         }
