@@ -104,6 +104,7 @@ SMOOTHERS = {"hs2": (0, "Hybrid Smoother 2"), "gslex": (1, "GSLEX-I"), "hs1": (2
 LEVELS = 9
 TOL = 1e-6
 MAX_CYCLES = 80
+BATCH_MAX_CYCLES = 150      # the batch's slowest images need about 100 cycles (the oracle: 93 and 99)
 
 
 def batch_bench(count: int):
@@ -128,7 +129,7 @@ def batch_bench(count: int):
             S, ms = 1, None
         before = [b.image(k).stats()["cycles"] for k in range(count)]
         t0 = time.perf_counter()
-        cyc, rel, ok = b.solve(1e-6, 80)
+        cyc, rel, ok = b.solve(1e-6, BATCH_MAX_CYCLES)
         wall = time.perf_counter() - t0
         done = [c - c0 for c, c0 in zip(cyc, before)]
         out[mode] = {"streams": S, "tune_ms_per_round": ms, "wall_s": wall, "converged": ok,
@@ -140,7 +141,7 @@ def batch_bench(count: int):
         "value": out["tuned"]["value"], "unit": "grid-pts/s per V-cycle", "n_gpus": 1,
         "higher_is_better": True, "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": f"{count} images, sides 256-2048 (multiples of 32), 3 shapes each, "
-                               "Spencer-Chen, FAS V(2,2), Hybrid Smoother 2, tol 1e-6",
+                               f"Spencer-Chen, FAS V(2,2), Hybrid Smoother 2, tol 1e-6, at most {BATCH_MAX_CYCLES} cycles",
                    "total_px": sum(px)},
         "tuned": out["tuned"], "one_stream": out["one_stream"],
         "speedup_vs_one_stream": out["tuned"]["value"] / out["one_stream"]["value"]}))
