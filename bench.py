@@ -163,7 +163,8 @@ def warmstart_bench(steps: int, warmup: int, count: int):
     from paper_1807_02137_amd import build, mgseg, synth, warmstart
     if not os.path.exists(build.LIB):
         build.build()
-    inst = warmstart.generate(warmstart.HELDOUT_SEEDS[:count], 512, workers=1)   # no fork from this process
+    inst = warmstart.generate(warmstart.HELDOUT_SEEDS[:count], 512, workers=1,   # no fork from this process
+                              log=lambda k: print(f"c5: {k} held-out images drawn", file=sys.stderr, flush=True))
     print(f"c5: {count} held-out images drawn", file=sys.stderr, flush=True)
     torch.cuda.set_device(0)
     net, scale = warmstart.load(WEIGHTS)

@@ -40,14 +40,20 @@ def gpu_runtime_loaded() -> bool:
     return "libhsa-runtime64" in maps or "libamdhip64" in maps
 
 
-def generate(seeds, n=512, workers=16):
+def generate(seeds, n=512, workers=16, log=None):
     """Seeded 4-20-shape instances (images, markers, seeds).  Drawn on `workers`
     forked host processes that never touch the GPU, but only while this process
-    has no GPU runtime loaded; otherwise (or for few seeds) in this process.
+    has no GPU runtime loaded; otherwise (or for few seeds) in this process,
+    calling log(done) every 50 instances if given.
     The pool is closed and joined, never terminated."""
     seeds = list(seeds)
     if workers <= 1 or len(seeds) < 4 or gpu_runtime_loaded():
-        return [synth.config5_arrays((s, n)) for s in seeds]
+        out = []
+        for s in seeds:
+            out.append(synth.config5_arrays((s, n)))
+            if log is not None and len(out) % 50 == 0:
+                log(len(out))
+        return out
     pool = mp.get_context("fork").Pool(min(workers, len(seeds)))
     try:
         out = pool.map(synth.config5_arrays, [(s, n) for s in seeds],
