@@ -295,7 +295,8 @@ def test_single_sweep_long_lines(shape, sweep):
     """Lines longer than one 1024-thread workgroup, taken in rounds of 1024
     cells (1600 and 2304 cells: 2 and 3 rounds; 8192: 8 rounds), along the rows
     and along the columns; one sweep from the same frozen state and labels
-    against the oracle."""
+    against the oracle, within 1e-5 of the largest |phi| (measured: at most
+    1.2e-6 absolute, |phi| <= 4)."""
     n, m = shape
     say("case long-line sweep", "ABCD"[sweep], n, m)
     img, mk = long_line_instance(n, m)
@@ -317,7 +318,7 @@ def test_single_sweep_long_lines(shape, sweep):
     beyond = np.nonzero(starred.any(axis=1 - long_axis))[0]
     say("max |dphi|", d.max(), "starred", int(starred.sum()), "last starred position", int(beyond.max()) if beyond.size else -1)
     assert beyond.size and beyond.max() > 1024        # units beyond the first workgroup's cells
-    assert d.max() <= 2e-4
+    assert d.max() <= 1e-5 * np.abs(o.get("phi")).max()
     s.close()
 
 
@@ -379,7 +380,8 @@ def test_single_sweep_units_across_rounds(shape, sweep):
     """Units that begin in one 1024-cell round of a long line and end in the
     next (planted starred runs of 1-5 cells on every round boundary; runs of 4
     and 5 cells are cut into two units, single cells take their successor):
-    one sweep against the oracle from the same state and the same labels."""
+    one sweep against the oracle from the same state and the same labels,
+    within 1e-5 of the largest |phi| (measured: at most 1.1e-6 absolute)."""
     n, m = shape
     say("case units across rounds", "ABCD"[sweep], n, m)
     img, mk = long_line_instance(n, m)
@@ -399,7 +401,7 @@ def test_single_sweep_units_across_rounds(shape, sweep):
     o.sweep(sweep, 0)
     d = np.abs(s.get("phi").astype(np.float64) - o.get("phi"))
     say("max |dphi|", d.max(), "units across a boundary", planted)
-    assert d.max() <= 2e-4
+    assert d.max() <= 1e-5 * np.abs(o.get("phi")).max()
     s.close()
 
 
@@ -495,7 +497,11 @@ def test_single_sweep_long_units(shape, sweep, lengths):
     lines of every sweep kernel (one wave, two-half, 1024 threads, rounds of
     1024 cells with units across the round boundaries): one sweep from the same
     state against the oracle, which solves each run by its own active-set
-    method.  The state has cells at both bounds inside the runs."""
+    method.  The state has cells at both bounds inside the runs.  The bar is
+    2e-4 absolute (5e-5 of |phi| <= 4): the FP32 elimination through a unit of
+    hundreds of cells against the oracle's FP64 solve grows with the unit's
+    length (measured: up to 6e-6 for units of at most 512 cells, 4.9e-5 for
+    planted units of 1000 cells)."""
     n, m = shape
     say("case long units", "ABCD"[sweep], n, m, lengths)
     img, mk = long_line_instance(n, m) if max(n, m) > 64 else (synth.tiny_instance(7, n, m).image,
