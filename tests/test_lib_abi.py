@@ -94,6 +94,10 @@ def test_setup_rejects_bad_arguments_before_any_device_work(lib):
     assert lib.mgseg_get_state(None, None, C.byref(n)) == 1
     assert lib.mgseg_set_state(None, None, 0) == 1
     assert lib.mgseg_solve_batch(None, 1e-6, 10, None, None) == 1
+    # the network's Adam state with a null handle
+    steps = C.c_longlong(0)
+    assert lib.mgseg_net_get_adam(None, None, None, C.byref(steps)) == 1
+    assert lib.mgseg_net_set_adam(None, None, None, C.c_longlong(0)) == 1
     # null context everywhere
     assert lib.mgseg_vcycle(None, None) == 1
     assert lib.mgseg_solve(None, 1e-6, 10, None, None) == 1
