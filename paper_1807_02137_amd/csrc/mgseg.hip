@@ -720,20 +720,23 @@ void vcycle_from(mgseg_ctx *c, int l0)
     for (int l = l0; l < c->L - 1; l++) {
         Level &L = c->lev[l], &Lc = c->lev[l + 1];
         smooth(c, l, c->p.nu1);
-        residual(c, l, L.r, nullptr);
         dim3 gc = grid2(Lc.n, Lc.m);
         if (dev) {
-            // the residual (to G) and the state (base, deviation, bounds) in one launch
+            // the fine residual and its restriction (to G) and the state (base, deviation,
+            // bounds) in one launch; the fine residual stays in LDS
+            const bool rc = c->p.model == 1;
+            if (rc) dev_area(c, l, DS_AREA_EVAL);
             with_dev(c, l, [&](auto A) {
                 using BT = std::remove_const_t<std::remove_pointer_t<decltype(A.b)>>;
-                const dim3 gct((Lc.m + TILE - 1) / TILE, (Lc.n + TILE - 1) / TILE);
-                const dim3 tb(TILE, tile_rows((long long)gct.x * gct.y));
-                hipLaunchKernelGGL(k_restrict_dev<BT>, gct, tb, 0, c->s, A.b, A.pb, L.P[0], L.lo, L.hi,
-                                   L.prm, L.n, L.m, Lc.phic, Lc.P[0], Lc.lo, Lc.hi, Lc.prm, Lc.n, Lc.m, Lc.lo_cm,
-                                   Lc.hi_cm, Lc.pcm, L.r, Lc.G);
+                A.area_u = rc ? c->dsc + DS_AREA_EVAL : nullptr;
+                A.r = nullptr;
+                const dim3 g((Lc.m + RR_CT - 1) / RR_CT, (Lc.n + RR_CT - 1) / RR_CT);
+                hipLaunchKernelGGL(k_res_restrict_dev<BT>, g, dim3(RR_CT, RR_CT), 0, c->s, A, Lc.phic, Lc.P[0],
+                                   Lc.lo, Lc.hi, Lc.prm, Lc.n, Lc.m, Lc.lo_cm, Lc.hi_cm, Lc.pcm, Lc.G);
             });
-            if (c->p.model == 1) area_term(c, l + 1, Lc.phic, Lc.prm, DS_AREAB0 + l + 1);
+            if (rc) area_term(c, l + 1, Lc.phic, Lc.prm, DS_AREAB0 + l + 1);
         } else {
+            residual(c, l, L.r, nullptr);
             hipLaunchKernelGGL(k_restrict, gc, dim3(256), 0, c->s, L.r, L.prm, Lc.r, Lc.prm, Lc.n, Lc.m);
             hipLaunchKernelGGL(k_restrict, gc, dim3(256), 0, c->s, L.P[0], L.prm, Lc.phic, Lc.prm, Lc.n, Lc.m);
             hipLaunchKernelGGL(k_coarse_bounds, gc, dim3(256), 0, c->s, L.P[0], l > 0 ? L.lo : nullptr,
