@@ -1,4 +1,4 @@
-"""What the trained warm-start network gains over the method without it.
+"""The trained warm-start network inside the solve, at equal accuracy.
 
 The shipped network (paper_1807_02137_amd/weights/warmstart_512_b32_d4.npz:
 base 32, depth 4, trained by the library's own kernels on 2048 seeded
@@ -9,6 +9,14 @@ marker-based start's), so the comparison is at equal accuracy; a start that
 reaches that residual at another fixed point (another segmentation) is
 counted as such.  The quantities are cycle counts, deterministic for given
 seeds; wall times are printed, not asserted.
+
+No gain is asserted: on these 12 images the network's start needs fewer
+cycles on average, but on 1000 held-out images it needs more (33.7 against
+31.3 cycles, `bench.py --workload c5 --c5-images 1000`), so a mean over a
+dozen images says nothing either way.  What holds is checked: the network's
+output is taken (it keeps every marker inside) on most images, the solve
+from it reaches the tolerance wherever the marker start does, and it ends
+at the same segmentation on most.
 """
 import os
 import sys
@@ -32,7 +40,7 @@ def say(*a):
     sys.stdout.flush()
 
 
-def test_learned_start_needs_fewer_cycles_at_equal_accuracy():
+def test_learned_start_reaches_the_same_accuracy():
     seeds = warmstart.HELDOUT_SEEDS[:12]
     say(f"case warm-start gain, held-out seeds {seeds.start}..{seeds.stop - 1}")
     net, scale = warmstart.load(WEIGHTS)
@@ -52,5 +60,4 @@ def test_learned_start_needs_fewer_cycles_at_equal_accuracy():
         assert r["learned"]["converged"] or not r["marker"]["converged"], r["seed"]
     assert s["learned"]["accepted"] >= 9
     assert s["learned"]["same_fixed_point"] >= 9
-    assert s["learned"]["cycles"] < s["marker"]["cycles"]
     net.close()
