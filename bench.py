@@ -142,7 +142,7 @@ def batch_bench(count: int):
         "higher_is_better": True, "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": f"{count} images, sides 256-2048 (multiples of 32), 3 shapes each, "
                                f"Spencer-Chen, FAS V(2,2), Hybrid Smoother 2, tol 1e-6, at most {BATCH_MAX_CYCLES} cycles",
-                   "total_px": sum(px)},
+                   "total_px": sum(px), "hw_queues": os.environ.get("GPU_MAX_HW_QUEUES")},
         "tuned": out["tuned"], "one_stream": out["one_stream"],
         "speedup_vs_one_stream": out["tuned"]["value"] / out["one_stream"]["value"]}))
 
@@ -464,6 +464,10 @@ def main():
         calibrate_copy()
         return
     if args.workload == "c3":
+        # the batch's streams run side by side only on as many hardware queues as the HIP
+        # runtime opens (read when it starts, before any device call; HIP's default is 4)
+        if int(os.environ.get("GPU_MAX_HW_QUEUES", "4")) < 16:
+            os.environ["GPU_MAX_HW_QUEUES"] = "16"
         batch_bench(args.batch_count)
         return
     if args.workload == "c5":

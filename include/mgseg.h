@@ -374,7 +374,10 @@ mgseg_status mgseg_setup_batch(int count, const float *const *images_dev, const 
  * one V-cycle on every image for each stream count in {1, 2, 4, 8} (at most
  * the image count); keeps the fastest.  The tuning cycles are real V-cycles
  * and count in the images' cycle totals.  Outputs (may be null): the chosen
- * stream count and its measured time per round in milliseconds. */
+ * stream count and its measured time per round in milliseconds.
+ * The streams run side by side only on as many hardware queues as the HIP
+ * runtime opens for the process (GPU_MAX_HW_QUEUES, read when the runtime
+ * starts; 4 unless set): a caller that batches should set it to at least 8. */
 mgseg_status mgseg_batch_tune(mgseg_batch *b, int trial_rounds, int *nstreams_out, double *ms_per_round_out);
 
 /* Sets the stream count (1..8) without tuning. */
