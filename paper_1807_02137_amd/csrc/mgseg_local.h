@@ -34,8 +34,10 @@
 // row's left neighbour is the value it has just written.  The values are
 // those of global memory at that point of the walk, so the result is the
 // same bit for bit as reading them there.
-// (named scalars rather than arrays, so that no select between them turns
-// into an indexed load from scratch memory)
+// (Named scalars rather than arrays, whose selects the compiler turned into
+// indexed loads from scratch memory; the FP32 build keeps the window in
+// registers, the FP64 one of the finest grid still holds 40 bytes of it in
+// scratch.)
 template <typename T>
 struct Win3 {
     T u0, u1, u2, c0, c1, c2, d0, d1, d2;    // rows i-1, i, i+1 (mirrored) x columns j-1, j, j+1
